@@ -1,0 +1,25 @@
+import os
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+
+def pytest_configure(config):
+    config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU and the built HIP library")
+    config.addinivalue_line("markers", "slow: CPU test that takes more than a few seconds")
+
+
+@pytest.fixture(scope="session")
+def small_db():
+    import synth
+    return synth.gen_db(10_000, 1000)
+
+
+@pytest.fixture(scope="session")
+def small_queries(small_db):
+    import synth
+    return synth.gen_queries(small_db, 100, 2000, 0.1, 0.5)
