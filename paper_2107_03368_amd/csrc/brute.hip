@@ -1,0 +1,286 @@
+// Sequential-search k-NN under the Weighted Hamming distance (Eq. 1) and the
+// per-row popcount, for gfx950.
+//
+// Scan kernel: a block of 4 waves serves one tile of QT queries over a slice of
+// the database.  Each wave streams its own contiguous run of rows; a row
+// (512 B) is spread over 8 lanes, lane j of a group holding the 16-byte
+// chunks j, j+8, j+16, j+24, so one load instruction reads 8 whole 128-byte
+// lines.  The query tile sits in registers as the same slices.  Per pair only
+// the overlap C = popcount(q AND t) is counted (AND + BCNT per dword); with
+// |q| and |t| it gives A = |q| - C, B = |t| - C and the key
+// K = A*wB + B*wA.  Each wave keeps, per query, its k best (K, row) keys in
+// one register across the 64 lanes and inserts only candidates below the
+// current k-th key.  A merge kernel then reduces the per-wave lists of every
+// query to the exact top k and writes the results.
+#include "qd_device.h"
+#include "qd_internal.h"
+
+namespace qd {
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kWavesPerBlock = kBlock / 64;
+constexpr int kRowsPerStep = 8;  // rows per wave per step (8 lanes per row)
+constexpr uint32_t kMaxParts = 4096;
+constexpr uint32_t kMaxCand = QD_MAX_K * QD_MAX_K;
+
+template <int QT>
+__global__ __launch_bounds__(kBlock) void scan_topk_kernel(const uint4 *__restrict__ db, uint64_t n,
+                                                           const uint4 *__restrict__ q, uint32_t nq, uint32_t k,
+                                                           uint32_t n_qtiles, uint32_t n_parts,
+                                                           uint64_t rows_per_part, u64 *__restrict__ part) {
+    const int lane = lane_id();
+    const int g = lane >> 3, j = lane & 7;
+    const uint32_t qtile = blockIdx.x % n_qtiles;
+    const uint32_t p = (blockIdx.x / n_qtiles) * kWavesPerBlock + (threadIdx.x >> 6);
+    if (p >= n_parts) return;  // whole wave
+    const uint64_t r0 = (uint64_t)p * rows_per_part;
+    const uint64_t r1 = r0 + rows_per_part < n ? r0 + rows_per_part : n;
+
+    uint4 qv[QT][4];
+    uint32_t wa[QT], wb[QT], pq[QT];
+    u64 list[QT], thr[QT];
+#pragma unroll
+    for (int t = 0; t < QT; t++) {
+        const uint32_t qi = qtile * QT + t;
+        uint32_t s = 0;
+#pragma unroll
+        for (int i = 0; i < 4; i++) {
+            qv[t][i] = qi < nq ? q[(uint64_t)qi * 32 + j + 8 * i] : make_uint4(0, 0, 0, 0);
+            s += popc4(qv[t][i]);
+        }
+        pq[t] = readfirst(sum8(s));
+        wa[t] = pq[t] > 1 ? pq[t] : 1;
+        wb[t] = (QD_BITS - pq[t]) > 1 ? QD_BITS - pq[t] : 1;
+        list[t] = KEY_NONE;
+        thr[t] = qi < nq ? KEY_NONE : 0;  // padding queries never insert
+    }
+
+    for (uint64_t base = r0; base < r1; base += kRowsPerStep) {
+        const uint64_t row = base + g;
+        const bool valid = row < r1;
+        uint4 tv[4];
+        const uint4 *src = db + row * 32 + j;
+#pragma unroll
+        for (int i = 0; i < 4; i++) tv[i] = valid ? src[8 * i] : make_uint4(0, 0, 0, 0);
+        const uint32_t tp = sum8(popc4(tv[0]) + popc4(tv[1]) + popc4(tv[2]) + popc4(tv[3]));
+#pragma unroll
+        for (int t = 0; t < QT; t++) {
+            uint32_t c = popc_and4(tv[0], qv[t][0]) + popc_and4(tv[1], qv[t][1]) + popc_and4(tv[2], qv[t][2]) +
+                         popc_and4(tv[3], qv[t][3]);
+            c = sum8(c);
+            const uint32_t K = (pq[t] - c) * wb[t] + (tp - c) * wa[t];
+            const u64 key = valid ? ((u64)K << 32) | (uint32_t)row : KEY_NONE;
+            u64 m = ballot(j == 0 && key < thr[t]);
+            while (m) {
+                const int L = __builtin_ctzll(m);
+                m &= m - 1;
+                const u64 c2 = readlane64(key, L);
+                if (c2 < thr[t]) {
+                    list[t] = list_insert(list[t], c2, k);
+                    thr[t] = readlane64(list[t], (int)k - 1);
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < QT; t++) {
+        const uint32_t qi = qtile * QT + t;
+        if (qi < nq && lane < (int)k) part[((uint64_t)qi * n_parts + p) * k + lane] = list[t];
+    }
+}
+
+// One block per query: exact top k from n_parts sorted lists of k keys, then
+// the result rows.  U = the k-th smallest list head bounds the k-th key from
+// above (those k heads are k distinct candidates), and only lists whose head
+// is <= U (at most k of them) can hold keys <= U, so at most k*k candidates
+// are gathered and sorted.
+__global__ __launch_bounds__(kBlock) void merge_emit_kernel(const u64 *__restrict__ part, uint32_t n_parts,
+                                                            uint32_t k, const uint64_t *__restrict__ q,
+                                                            const uint64_t *__restrict__ db, uint32_t *idx,
+                                                            int32_t *missed, int32_t *extra, float *dist) {
+    __shared__ u64 heads[kMaxParts];
+    __shared__ u64 cand[kMaxCand];
+    __shared__ uint32_t ncand;
+    const uint32_t qi = blockIdx.x;
+    const u64 *lists = part + (uint64_t)qi * n_parts * k;
+    const uint32_t hp = next_pow2(n_parts < 2 ? 2 : n_parts);
+    for (uint32_t i = threadIdx.x; i < hp; i += blockDim.x) heads[i] = i < n_parts ? lists[(uint64_t)i * k] : KEY_NONE;
+    if (threadIdx.x == 0) ncand = 0;
+    __syncthreads();
+    block_bitonic_sort(heads, hp);
+    const u64 U = k <= n_parts ? heads[k - 1] : KEY_NONE;
+    for (uint32_t p = threadIdx.x; p < n_parts; p += blockDim.x) {
+        const u64 *L = lists + (uint64_t)p * k;
+        for (uint32_t r = 0; r < k; r++) {
+            const u64 e = L[r];
+            if (e == KEY_NONE || e > U) break;
+            cand[atomicAdd(&ncand, 1u)] = e;
+        }
+    }
+    __syncthreads();
+    const uint32_t nc = ncand;
+    const uint32_t cp = next_pow2(nc < 2 ? 2 : nc);
+    for (uint32_t i = nc + threadIdx.x; i < cp; i += blockDim.x) cand[i] = KEY_NONE;
+    __syncthreads();
+    block_bitonic_sort(cand, cp);
+    if (threadIdx.x < k) {
+        const uint32_t r = threadIdx.x;
+        const uint64_t o = (uint64_t)qi * k + r;
+        const u64 e = r < nc ? cand[r] : KEY_NONE;
+        if (e == KEY_NONE) {
+            idx[o] = QD_PAD_IDX;
+            missed[o] = -1;
+            extra[o] = -1;
+            dist[o] = __builtin_inff();
+        } else {
+            const uint32_t row = (uint32_t)e;
+            const uint64_t *qq = q + (uint64_t)qi * QD_WORDS;
+            const uint64_t *tt = db + (uint64_t)row * QD_WORDS;
+            uint32_t a = 0, b = 0, pqv = 0;
+            for (int w = 0; w < QD_WORDS; w++) {
+                const uint64_t x = qq[w], y = tt[w];
+                a += __popcll(x & ~y);
+                b += __popcll(~x & y);
+                pqv += __popcll(x);
+            }
+            const uint32_t wav = pqv > 1 ? pqv : 1;
+            const uint32_t wbv = (QD_BITS - pqv) > 1 ? QD_BITS - pqv : 1;
+            const uint32_t K = a * wbv + b * wav;
+            idx[o] = row;
+            missed[o] = (int32_t)a;
+            extra[o] = (int32_t)b;
+            dist[o] = (float)((double)K / ((double)wav * (double)wbv));
+        }
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void popcount_rows_kernel(const uint4 *__restrict__ db, uint64_t n,
+                                                               uint16_t *__restrict__ pop) {
+    const int lane = lane_id();
+    const int g = lane >> 3, j = lane & 7;
+    const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
+    for (uint64_t base = wave * kRowsPerStep; base < n; base += nwaves * kRowsPerStep) {
+        const uint64_t row = base + g;
+        const bool valid = row < n;
+        uint32_t s = 0;
+#pragma unroll
+        for (int i = 0; i < 4; i++) s += valid ? popc4(db[row * 32 + j + 8 * i]) : 0;
+        s = sum8(s);
+        if (valid && j == 0) pop[row] = (uint16_t)s;
+    }
+}
+
+template <int QT>
+void launch_scan(dim3 grid, hipStream_t s, const uint4 *db, uint64_t n, const uint4 *q, uint32_t nq, uint32_t k,
+                 uint32_t n_qtiles, uint32_t n_parts, uint64_t rpp, u64 *part) {
+    hipLaunchKernelGGL(scan_topk_kernel<QT>, grid, dim3(kBlock), 0, s, db, n, q, nq, k, n_qtiles, n_parts, rpp, part);
+}
+
+}  // namespace
+
+// Launch shape of one brute-force call (exposed for tests and the autotuner).
+struct BruteShape {
+    uint32_t qt, n_qtiles, n_parts;
+    uint64_t rows_per_part;
+};
+
+static BruteShape brute_shape(uint64_t n, uint32_t nq, uint32_t qt_force, uint32_t parts_force) {
+    BruteShape sh;
+    uint32_t qt = qt_force;
+    if (qt == 0) qt = nq <= 1 ? 1 : nq <= 2 ? 2 : nq <= 4 ? 4 : nq <= 8 ? 8 : 16;
+    sh.qt = qt;
+    sh.n_qtiles = (nq + qt - 1) / qt;
+    uint64_t parts = parts_force;
+    if (parts == 0) {
+        const uint64_t want_waves = (uint64_t)device_cus() * 16;
+        parts = (want_waves + sh.n_qtiles - 1) / sh.n_qtiles;
+    }
+    const uint64_t max_by_rows = (n + 255) / 256;  // at least 256 rows per wave
+    if (parts > max_by_rows) parts = max_by_rows;
+    if (parts > kMaxParts) parts = kMaxParts;
+    if (parts < 1) parts = 1;
+    uint64_t rpp = (n + parts - 1) / parts;
+    rpp = (rpp + kRowsPerStep - 1) / kRowsPerStep * kRowsPerStep;
+    sh.rows_per_part = rpp;
+    sh.n_parts = (uint32_t)((n + rpp - 1) / rpp);
+    return sh;
+}
+
+int knn_bruteforce_impl(const uint64_t *d_db, uint64_t n, const uint64_t *d_q, uint32_t nq, uint32_t k,
+                        uint32_t *d_idx, int32_t *d_missed, int32_t *d_extra, float *d_dist, void *stream,
+                        uint32_t qt_force, uint32_t parts_force) {
+    if (k < 1 || k > QD_MAX_K) return fail(QD_ERR_INVALID, "k=%u outside 1..%d", k, QD_MAX_K);
+    if (n < 1 || n > QD_MAX_ROWS) return fail(QD_ERR_INVALID, "n=%llu outside 1..%llu", (u64)n, (u64)QD_MAX_ROWS);
+    if (nq == 0) return QD_OK;
+    if (!d_db || !d_q || !d_idx || !d_missed || !d_extra || !d_dist) return fail(QD_ERR_INVALID, "null pointer");
+    if (!aligned16(d_db) || !aligned16(d_q)) return fail(QD_ERR_INVALID, "descriptor arrays must be 16-byte aligned");
+    if (qt_force && qt_force != 1 && qt_force != 2 && qt_force != 4 && qt_force != 8 && qt_force != 16)
+        return fail(QD_ERR_INVALID, "query tile %u not in {1,2,4,8,16}", qt_force);
+    hipStream_t s = (hipStream_t)stream;
+    const BruteShape sh = brute_shape(n, nq, qt_force, parts_force);
+    const uint64_t blocks_per_tile = (sh.n_parts + kWavesPerBlock - 1) / kWavesPerBlock;
+    const uint64_t blocks = blocks_per_tile * sh.n_qtiles;
+    if (blocks > 0x7FFFFFFFull) return fail(QD_ERR_INVALID, "launch too large");
+    u64 *part = nullptr;
+    const size_t part_bytes = (size_t)nq * sh.n_parts * k * sizeof(u64);
+    QD_HIP_CHECK(hipMallocAsync((void **)&part, part_bytes, s));
+    const uint4 *db4 = reinterpret_cast<const uint4 *>(d_db);
+    const uint4 *q4 = reinterpret_cast<const uint4 *>(d_q);
+    dim3 grid((uint32_t)blocks);
+    {
+    KernelTimer timer("wh_scan_topk", s);
+    switch (sh.qt) {
+        case 1: launch_scan<1>(grid, s, db4, n, q4, nq, k, sh.n_qtiles, sh.n_parts, sh.rows_per_part, part); break;
+        case 2: launch_scan<2>(grid, s, db4, n, q4, nq, k, sh.n_qtiles, sh.n_parts, sh.rows_per_part, part); break;
+        case 4: launch_scan<4>(grid, s, db4, n, q4, nq, k, sh.n_qtiles, sh.n_parts, sh.rows_per_part, part); break;
+        case 8: launch_scan<8>(grid, s, db4, n, q4, nq, k, sh.n_qtiles, sh.n_parts, sh.rows_per_part, part); break;
+        default: launch_scan<16>(grid, s, db4, n, q4, nq, k, sh.n_qtiles, sh.n_parts, sh.rows_per_part, part); break;
+    }
+    }
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) {
+        KernelTimer timer("topk_merge", s);
+        hipLaunchKernelGGL(merge_emit_kernel, dim3(nq), dim3(kBlock), 0, s, part, sh.n_parts, k, d_q, d_db, d_idx,
+                           d_missed, d_extra, d_dist);
+        e = hipGetLastError();
+    }
+    hipError_t e2 = hipFreeAsync(part, s);
+    if (e != hipSuccess) return fail(QD_ERR_DEVICE, "brute-force launch: %s", hipGetErrorString(e));
+    if (e2 != hipSuccess) return fail(QD_ERR_DEVICE, "hipFreeAsync: %s", hipGetErrorString(e2));
+    return QD_OK;
+}
+
+}  // namespace qd
+
+extern "C" int qd_popcount_rows(const uint64_t *d_db, uint64_t n, uint16_t *d_pop, void *stream) {
+    using namespace qd;
+    if (n == 0) return QD_OK;
+    if (!d_db || !d_pop) return fail(QD_ERR_INVALID, "null pointer");
+    if (!aligned16(d_db)) return fail(QD_ERR_INVALID, "descriptor array must be 16-byte aligned");
+    uint64_t waves = (n + kRowsPerStep - 1) / kRowsPerStep;
+    uint64_t blocks = (waves + kWavesPerBlock - 1) / kWavesPerBlock;
+    const uint64_t cap = (uint64_t)device_cus() * 32;
+    if (blocks > cap) blocks = cap;
+    hipLaunchKernelGGL(popcount_rows_kernel, dim3((uint32_t)blocks), dim3(kBlock), 0, (hipStream_t)stream,
+                       reinterpret_cast<const uint4 *>(d_db), n, d_pop);
+    QD_HIP_CHECK(hipGetLastError());
+    return QD_OK;
+}
+
+extern "C" int qd_knn_bruteforce(const uint64_t *d_db, uint64_t n, const uint64_t *d_q, uint32_t nq, uint32_t k,
+                                 uint32_t *d_idx, int32_t *d_missed, int32_t *d_extra, float *d_dist,
+                                 void *stream) {
+    return qd::knn_bruteforce_impl(d_db, n, d_q, nq, k, d_idx, d_missed, d_extra, d_dist, stream, 0, 0);
+}
+
+// Same search with an explicit launch shape: query tile (1,2,4,8,16; 0 =
+// automatic) and number of row slices per tile (0 = automatic).  Used by the
+// autotuner and by tests that check results do not depend on the shape.
+extern "C" int qd_knn_bruteforce_shaped(const uint64_t *d_db, uint64_t n, const uint64_t *d_q, uint32_t nq,
+                                        uint32_t k, uint32_t query_tile, uint32_t row_parts, uint32_t *d_idx,
+                                        int32_t *d_missed, int32_t *d_extra, float *d_dist, void *stream) {
+    return qd::knn_bruteforce_impl(d_db, n, d_q, nq, k, d_idx, d_missed, d_extra, d_dist, stream, query_tile,
+                                   row_parts);
+}

@@ -1,0 +1,61 @@
+"""The C-ABI library loads and exports every entry point include/qd.h declares.
+
+CPU-only: nothing is called that needs a GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+LIB = os.path.join(ROOT, "paper_2107_03368_amd", "libqd.so")
+
+
+def _declared():
+    names = set()
+    for f in os.listdir(os.path.join(ROOT, "include")):
+        if f.endswith(".h"):
+            text = open(os.path.join(ROOT, "include", f)).read()
+            text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+            names |= set(re.findall(r"\b(qd_[a-z0-9_]+)\s*\(", text))
+    return sorted(names)
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for required in ("qd_knn_bruteforce", "qd_popcount_rows", "qd_last_error"):
+        assert required in names
+
+
+@pytest.mark.parametrize("name", _declared())
+def test_library_exports(name):
+    if not os.path.exists(LIB):
+        from paper_2107_03368_amd import build
+        build.build(verbose=False)
+    lib = ctypes.CDLL(LIB)
+    assert hasattr(lib, name), f"{name} declared in include/ but not exported by libqd.so"
+
+
+def test_version_and_error_string_without_gpu():
+    lib = ctypes.CDLL(LIB)
+    lib.qd_last_error.restype = ctypes.c_char_p
+    assert lib.qd_version() >= 100
+    assert isinstance(lib.qd_last_error(), bytes)
+
+
+def test_argument_errors_are_reported_before_any_device_work():
+    # Fake, never-dereferenced pointers: the checks must reject these calls
+    # before touching the device (none is present here).
+    lib = ctypes.CDLL(LIB)
+    lib.qd_last_error.restype = ctypes.c_char_p
+    f = lib.qd_knn_bruteforce
+    P, U64, U32 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32
+    f.argtypes = [P, U64, P, U32, U32, P, P, P, P, P]
+    a = P(0x10000)
+    assert f(a, 100, a, 5, 0, a, a, a, a, None) == -1          # k = 0
+    assert b"k=0" in lib.qd_last_error()
+    assert f(a, 100, a, 5, 65, a, a, a, a, None) == -1         # k > QD_MAX_K
+    assert f(a, 0, a, 5, 10, a, a, a, a, None) == -1           # empty database
+    assert f(None, 100, a, 5, 10, a, a, a, a, None) == -1      # null database
+    assert f(P(0x10008), 100, a, 5, 10, a, a, a, a, None) == -1  # misaligned rows
+    assert f(a, 100, a, 0, 10, a, a, a, a, None) == 0          # nq = 0 is a no-op

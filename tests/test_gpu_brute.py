@@ -1,0 +1,95 @@
+"""GPU sequential-search k-NN against the CPU oracle, through the C ABI.
+
+Bit-exact on idx, missed, extra and dist (the float is the same correctly
+rounded double quotient on both sides)."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def qd():
+    import paper_2107_03368_amd as qd
+    return qd
+
+
+def _t(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a).view(np.int64)).to("cuda:0")
+
+
+def _np(res):
+    idx, missed, extra, dist = (x.cpu().numpy() for x in res)
+    return idx.view(np.uint32), missed, extra, dist
+
+
+def _same(res, ref, rows=None):
+    idx, missed, extra, dist = _np(res)
+    if rows is not None:
+        idx, missed, extra, dist = idx[rows], missed[rows], extra[rows], dist[rows]
+    assert np.array_equal(idx, ref.idx)
+    assert np.array_equal(missed, ref.missed)
+    assert np.array_equal(extra, ref.extra)
+    assert np.array_equal(dist, ref.dist)
+
+
+@pytest.mark.parametrize("k", [1, 10])
+def test_small_workload_matches_oracle(qd, small_db, small_queries, k):
+    q, _ = small_queries
+    ref = oracle.knn_brute(small_db, q, k)
+    _same(qd.knn_bruteforce(_t(small_db), _t(q), k), ref)
+
+
+@pytest.mark.parametrize("tile,parts", [(1, 1), (2, 3), (4, 7), (8, 64), (16, 4096), (16, 1), (1, 4096)])
+def test_result_independent_of_launch_shape(qd, small_db, small_queries, tile, parts):
+    q, _ = small_queries
+    q = q[:37]  # ragged against every query tile
+    db = small_db[:9_999]  # ragged against the 8-row step
+    ref = oracle.knn_brute(db, q, 13)
+    _same(qd.knn_bruteforce(_t(db), _t(q), 13, query_tile=tile, row_parts=parts), ref)
+
+
+def test_ties_duplicates_and_degenerate_queries(qd):
+    rng = np.random.default_rng(3)
+    base = synth.gen_db(200, 51)
+    db = np.concatenate([base, base[:50], base[:50], np.zeros((7, 64), np.uint64),
+                         np.full((3, 64), np.uint64(0xFFFFFFFFFFFFFFFF))])
+    db = db[rng.permutation(len(db))]
+    q = np.concatenate([base[:20], np.zeros((2, 64), np.uint64), np.full((2, 64), np.uint64(0xFFFFFFFFFFFFFFFF)),
+                        synth.gen_queries(base, 10, 52, 0.3, 0.6)[0]])
+    for k in (1, 5, 64):
+        ref = oracle.knn_brute(db, q, k)
+        _same(qd.knn_bruteforce(_t(db), _t(q), k), ref)
+
+
+def test_fewer_rows_than_k_and_single_row(qd, small_db, small_queries):
+    q, _ = small_queries
+    for n, k in ((3, 5), (1, 1), (1, 64), (63, 64)):
+        ref = oracle.knn_brute(small_db[:n], q[:9], k)
+        _same(qd.knn_bruteforce(_t(small_db[:n]), _t(q[:9]), k), ref)
+
+
+def test_popcount_rows(qd, small_db):
+    pop = qd.popcount_rows(_t(small_db)).cpu().numpy().astype(np.int64)
+    ref = np.unpackbits(small_db.view(np.uint8), axis=1).sum(1)
+    assert np.array_equal(pop, ref)
+
+
+@pytest.fixture(scope="module")
+def db_1m():
+    return synth.gen_db(1_000_000, 1001)
+
+
+@pytest.mark.parametrize("k", [1, 10, 50])
+def test_1m_workload_sampled_queries(qd, db_1m, k):
+    # the full 4,096-query batch runs on the GPU in the launch shape the
+    # benchmark uses; the oracle scores a sample of the queries
+    q, _ = synth.gen_queries(db_1m, 4096, 2001, 0.1, 0.6)
+    res = qd.knn_bruteforce(_t(db_1m), _t(q), k)
+    rows = np.array([0, 1, 777, 2048, 4095])
+    ref = oracle.knn_brute(db_1m, q[rows], k)
+    _same(res, ref, rows)
