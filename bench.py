@@ -83,12 +83,13 @@ def main():
         log(f"tree built in {build_s:.2f}s")
         if "tree" in wanted:
             paths["tree"] = lambda: qd.knn_tree(tree, qt, k)
+            paths["tree_dfs"] = lambda: qd.knn_tree(tree, qt, k, order=qd.ORDER_DEPTH_FIRST)
 
     # reference result for the cross-path exactness check (outside timing)
     ref = [x.cpu() for x in paths["brute"]()]
     for name, fn in paths.items():
         if name != "brute":
-            out = [x.cpu() for x in fn()]
+            out = [x.cpu() for x in fn()[:4]]
             if not all(torch.equal(a, b) for a, b in zip(ref, out)):
                 raise SystemExit(f"{name} results differ from sequential search")
     recall = float((ref[0][:, 0].numpy().view(np.uint32) == src).mean())

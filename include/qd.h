@@ -103,6 +103,90 @@ int qd_knn_bruteforce_shaped(const uint64_t *d_db, uint64_t n, const uint64_t *d
                              uint32_t query_tile, uint32_t row_parts, uint32_t *d_idx, int32_t *d_missed,
                              int32_t *d_extra, float *d_dist, void *stream);
 
+/* ---------------------------------------------------------------------------
+ * Dissimilarity Tree (Section 4).
+ *
+ * qd_tree_build indexes a fixed set of n descriptors (Section 4.1, Listing 1):
+ * each node holding more than max_leaf descriptors is split in two; bit
+ * positions are taken in ascending popularity over the node (ties: ascending
+ * bit index) and every descriptor still in the "similar" set that has the
+ * bit set moves to the "dissimilar" set, until the dissimilar set holds at
+ * least half of the node; a move that would empty the similar set is not
+ * applied, and a node that cannot be split stays a leaf.  Every node, leaves
+ * included, stores the OR ("sum") image of its descriptors, and the AND
+ * ("product") image if store_and_image is set.
+ * Numbering: nodes are numbered breadth first from the root (0), the similar
+ * child before the dissimilar one.  Node i covers leaf-order positions
+ * begin[i] .. begin[i]+count[i]-1; perm maps a leaf-order position to the
+ * database row.  Within a leaf, rows keep ascending database order.
+ * Ownership: the tree copies the rows into leaf order, so the caller may free
+ * d_db after the call.  The call is synchronous (it returns once the tree is
+ * complete) and uses `stream` for its device work.  Free with qd_tree_free.
+ * ------------------------------------------------------------------------- */
+typedef struct qd_tree_s *qd_tree_t;
+
+typedef struct {
+    uint32_t max_leaf;        /* leaf when a node holds <= max_leaf rows; 0 = 32 (Section 4.1) */
+    uint32_t store_and_image; /* 0 = sum images only (the paper's choice for sparse QUICCI) */
+} qd_build_params;
+
+typedef struct {
+    uint64_t n, n_nodes, n_leaves;
+    uint32_t depth, max_leaf, has_and_image;
+} qd_tree_info_t;
+
+int qd_tree_build(const uint64_t *d_db, uint64_t n, const qd_build_params *params, void *stream, qd_tree_t *out);
+int qd_tree_free(qd_tree_t t);
+int qd_tree_info(qd_tree_t t, qd_tree_info_t *info);
+
+/* Copy the tree's arrays to caller-owned HOST buffers (any may be NULL):
+ * h_child n_nodes x 2 (similar, dissimilar; -1 for leaves), h_begin and
+ * h_count n_nodes, h_or / h_and n_nodes x 64 words, h_perm n.  Synchronous. */
+int qd_tree_export(qd_tree_t t, int32_t *h_child, uint32_t *h_begin, uint32_t *h_count, uint64_t *h_or,
+                   uint64_t *h_and, uint32_t *h_perm);
+
+/* ---------------------------------------------------------------------------
+ * Exact k-NN through the tree (Section 4.2, Listing 2).
+ *
+ * A node's lower bound (minWHDist): every query 1-bit that is 0 in the
+ * node's sum image is a type A error for all its rows, and every query 0-bit
+ * that is 1 in its product image (when stored) a type B error, so all rows
+ * under the node have key K >= Kb = A_lb*wB + B_lb*wA.  A child is queued
+ * when fewer than k results exist or Kb <= the current k-th key; a popped
+ * node with Kb above the k-th key is not expanded.  The result equals
+ * qd_knn_bruteforce's exactly, whatever the order.
+ * Orders:
+ *   QD_ORDER_BEST_FIRST (default, the paper's priority queue): nodes leave
+ *     the frontier in ascending floor(Kb / wB), which is the exact bound
+ *     order when no product images are stored; the search stops at the first
+ *     popped node whose bound exceeds the k-th key.
+ *   QD_ORDER_DEPTH_FIRST: a stack; each expansion visits the preferred child
+ *     first: the higher score in d_scores when given (nq x n_scored floats,
+ *     query-major, nodes 0..n_scored-1; e.g. a learned model's output), else
+ *     the lower bound (ties: the similar child).  Runs until the stack is
+ *     empty, skipping popped nodes that cannot improve the result.
+ * d_query_stats (nullable): nq x 4 uint32 per query: nodes visited
+ * (expanded pops, leaves and inner nodes), leaves visited, bounds evaluated,
+ * distances evaluated.  h_stats (nullable): totals; filling it waits for the
+ * stream.  waves_per_cu = 0 picks a default occupancy.
+ * ------------------------------------------------------------------------- */
+typedef enum { QD_ORDER_BEST_FIRST = 0, QD_ORDER_DEPTH_FIRST = 1 } qd_order;
+
+typedef struct {
+    qd_order order;
+    const float *d_scores; /* depth-first only; nullable */
+    uint32_t n_scored;
+    uint32_t waves_per_cu;
+} qd_search_params;
+
+typedef struct {
+    uint64_t nodes_visited, leaves_visited, bounds_evaluated, dists_evaluated;
+} qd_stats;
+
+int qd_knn_tree(qd_tree_t t, const uint64_t *d_q, uint32_t nq, uint32_t k, const qd_search_params *params,
+                uint32_t *d_idx, int32_t *d_missed, int32_t *d_extra, float *d_dist, uint32_t *d_query_stats,
+                qd_stats *h_stats, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

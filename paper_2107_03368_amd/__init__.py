@@ -119,3 +119,112 @@ def profile_read(kernel):
     n = ctypes.c_uint64()
     _check(_lib.qd_profile_read(kernel.encode(), ctypes.byref(ms), ctypes.byref(n)), "qd_profile_read")
     return ms.value, n.value
+
+
+# ---------------------------------------------------------------------------
+# Dissimilarity Tree
+# ---------------------------------------------------------------------------
+class _BuildParams(ctypes.Structure):
+    _fields_ = [("max_leaf", ctypes.c_uint32), ("store_and_image", ctypes.c_uint32)]
+
+
+class _TreeInfo(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_uint64), ("n_nodes", ctypes.c_uint64), ("n_leaves", ctypes.c_uint64),
+                ("depth", ctypes.c_uint32), ("max_leaf", ctypes.c_uint32), ("has_and_image", ctypes.c_uint32)]
+
+
+class _SearchParams(ctypes.Structure):
+    _fields_ = [("order", ctypes.c_int), ("d_scores", ctypes.c_void_p), ("n_scored", ctypes.c_uint32),
+                ("waves_per_cu", ctypes.c_uint32)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("nodes_visited", ctypes.c_uint64), ("leaves_visited", ctypes.c_uint64),
+                ("bounds_evaluated", ctypes.c_uint64), ("dists_evaluated", ctypes.c_uint64)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+ORDER_BEST_FIRST = 0
+ORDER_DEPTH_FIRST = 1
+
+_sig("qd_tree_build", [_P, _U64, ctypes.POINTER(_BuildParams), _P, ctypes.POINTER(ctypes.c_void_p)])
+_sig("qd_tree_free", [_P])
+_sig("qd_tree_info", [_P, ctypes.POINTER(_TreeInfo)])
+_sig("qd_tree_export", [_P, _P, _P, _P, _P, _P, _P])
+_sig("qd_knn_tree", [_P, _P, _U32, _U32, ctypes.POINTER(_SearchParams), _P, _P, _P, _P, _P,
+                     ctypes.POINTER(Stats), _P])
+
+
+class Tree:
+    """A library-owned Dissimilarity Tree (freed with the object)."""
+
+    def __init__(self, handle):
+        self._h = ctypes.c_void_p(handle)
+        info = _TreeInfo()
+        _check(_lib.qd_tree_info(self._h, ctypes.byref(info)), "qd_tree_info")
+        self.n, self.n_nodes, self.n_leaves = info.n, info.n_nodes, info.n_leaves
+        self.depth, self.max_leaf, self.has_and_image = info.depth, info.max_leaf, bool(info.has_and_image)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def free(self):
+        if self._h is not None and self._h.value:
+            _lib.qd_tree_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+    def export(self):
+        """Host copies: child (n_nodes, 2), begin, count, or_img (n_nodes, 64), [and_img], perm."""
+        import numpy as np
+        child = np.empty((self.n_nodes, 2), np.int32)
+        begin = np.empty(self.n_nodes, np.uint32)
+        count = np.empty(self.n_nodes, np.uint32)
+        or_img = np.empty((self.n_nodes, 64), np.uint64)
+        and_img = np.empty((self.n_nodes, 64), np.uint64) if self.has_and_image else None
+        perm = np.empty(self.n, np.uint32)
+        p = lambda a: None if a is None else ctypes.c_void_p(a.ctypes.data)
+        _check(_lib.qd_tree_export(self._h, p(child), p(begin), p(count), p(or_img), p(and_img), p(perm)),
+               "qd_tree_export")
+        return dict(child=child, begin=begin, count=count, or_img=or_img, and_img=and_img, perm=perm)
+
+
+def tree_build(db, max_leaf=32, store_and_image=False):
+    _desc(db, "db")
+    prm = _BuildParams(max_leaf, 1 if store_and_image else 0)
+    h = ctypes.c_void_p()
+    _check(_lib.qd_tree_build(_ptr(db), db.shape[0], ctypes.byref(prm), _stream(), ctypes.byref(h)),
+           "qd_tree_build")
+    return Tree(h.value)
+
+
+def knn_tree(tree, q, k, order=ORDER_BEST_FIRST, scores=None, query_stats=False, totals=False, waves_per_cu=0):
+    """Exact k-NN through the tree.  Returns (idx, missed, extra, dist[, qstats][, totals])."""
+    _desc(q, "q")
+    nq = q.shape[0]
+    idx, missed, extra, dist = _results(nq, k, q.device)
+    qs = torch.empty((nq, 4), dtype=torch.int32, device=q.device) if query_stats else None
+    prm = _SearchParams(order, None, 0, waves_per_cu)
+    if scores is not None:
+        if not (scores.is_cuda and scores.dtype == torch.float32 and scores.dim() == 2 and scores.shape[0] == nq
+                and scores.is_contiguous()):
+            raise ValueError("scores must be a contiguous cuda float32 tensor (nq, n_scored)")
+        prm.d_scores = scores.data_ptr()
+        prm.n_scored = scores.shape[1]
+    st = Stats()
+    _check(_lib.qd_knn_tree(tree.handle, _ptr(q), nq, k, ctypes.byref(prm), _ptr(idx), _ptr(missed), _ptr(extra),
+                            _ptr(dist), _ptr(qs), ctypes.byref(st) if totals else None, _stream()), "qd_knn_tree")
+    out = [idx, missed, extra, dist]
+    if query_stats:
+        out.append(qs)
+    if totals:
+        out.append(st.as_dict())
+    return tuple(out)

@@ -1,0 +1,26 @@
+// Library-owned Dissimilarity Tree (opaque to callers as qd_tree_t).
+#pragma once
+
+#include "qd_internal.h"
+
+struct qd_tree_s {
+    int device = 0;
+    uint64_t n = 0;         // database rows
+    uint64_t n_nodes = 0;   // breadth-first numbered, root 0
+    uint64_t n_leaves = 0;
+    uint32_t depth = 0;     // number of levels
+    uint32_t max_leaf = 32;
+    bool has_and = false;
+    uint64_t *d_sorted = nullptr;  // n x 64 words: rows in leaf order
+    uint32_t *d_perm = nullptr;    // n: database row of each leaf-order position
+    uint64_t *d_or = nullptr;      // n_nodes x 64 words: sum (OR) image
+    uint64_t *d_and = nullptr;     // n_nodes x 64 words: product (AND) image, optional
+    int32_t *d_child = nullptr;    // n_nodes x 2: similar, dissimilar (-1 for a leaf)
+    uint32_t *d_begin = nullptr;   // n_nodes: first leaf-order position
+    uint32_t *d_count = nullptr;   // n_nodes: rows under the node
+    uint16_t *d_pop = nullptr;     // n: popcount of each leaf-order row
+};
+
+namespace qd {
+void tree_release(qd_tree_s *t);
+}

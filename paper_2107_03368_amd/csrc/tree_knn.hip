@@ -1,0 +1,408 @@
+// Dissimilarity Tree k-NN search (Section 4.2, Listing 2) as a persistent
+// kernel: each wave takes queries from a global counter until none are left,
+// and searches one query at a time.
+//
+// Node bound (minWHDist): a query 1-bit that is 0 in a node's sum image is a
+// type A error for every row under the node, so with
+//   A_lb = |q| - popcount(q AND OR)   (and, with product images,
+//   B_lb = popcount(NOT q AND AND))
+// every row under the node has key K >= Kb = A_lb*wB + B_lb*wA.  Children are
+// bounded when their parent is expanded; a child is queued when fewer than k
+// results exist or Kb <= the current k-th key; a popped node whose Kb exceeds
+// the k-th key is not expanded.
+//
+// Frontier orders:
+//  best-first (the paper's priority queue): a bucket queue on
+//    floor(Kb / wB) (= A_lb without product images, so nodes come out in
+//    exact bound order); the search stops at the first popped node whose
+//    bound exceeds the k-th key.  Each bucket is a stack of 16-entry chunks in
+//    the wave's global workspace, its (chunk, fill) word in LDS, and a
+//    4096-bit occupancy map spread over the 64 lanes finds the lowest
+//    non-empty bucket with one ballot.  Only lane 0 touches the chunk memory.
+//  depth-first: a stack in LDS; at every expansion the preferred child is
+//    visited first (lower bound, or higher learned score where scores are
+//    given); popped nodes are re-checked against the k-th key and skipped
+//    when they cannot improve the result; the search ends with an empty stack.
+// Both orders return exactly the sequential-search result.
+#include "qd_device.h"
+#include "qd_internal.h"
+#include "qd_tree.h"
+
+namespace qd {
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kWaves = kBlock / 64;
+constexpr int kBuckets = 4096;
+constexpr uint32_t kChunk = 16;
+constexpr uint32_t kNone = 0xFFFFFFFFu;
+constexpr int kMaxStack = 256;
+
+struct TreeView {
+    const uint4 *sorted;
+    const uint32_t *perm;
+    const uint4 *orimg;
+    const uint4 *andimg;  // nullable
+    const int32_t *child;
+    const uint32_t *begin;
+    const uint32_t *count;
+    const uint16_t *pop;
+};
+
+struct Scores {
+    const float *s;       // nq x n_scored (nullable): learned preference, higher = visit first
+    uint32_t n_scored;    // nodes 0 .. n_scored-1 carry a score
+};
+
+// Sum over the 32-lane half of the wave; every lane gets its half's sum.
+__device__ __forceinline__ uint32_t sum32(uint32_t v) {
+    v = sum8(v);
+    v += (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x140, 0xF, 0xF, false);  // row_mirror (16 lanes)
+    v += (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, 0x401F);             // xor 16 within 32
+    return v;
+}
+
+template <bool kBest>
+__global__ __launch_bounds__(kBlock) void tree_knn_kernel(TreeView T, const uint4 *__restrict__ q, uint32_t nq,
+                                                          uint32_t k, uint32_t *__restrict__ next_query,
+                                                          u64 *__restrict__ pool, uint32_t *__restrict__ chunk_prev,
+                                                          uint64_t pool_chunks, Scores S, uint32_t *idx,
+                                                          int32_t *missed, int32_t *extra, float *dist,
+                                                          uint32_t *qstats, unsigned long long *gstats) {
+    __shared__ uint32_t bstate_all[kBest ? kWaves * kBuckets : 1];
+    __shared__ u64 stack_all[kBest ? 1 : kWaves * kMaxStack];
+    const int lane = lane_id();
+    const int wave = threadIdx.x >> 6;
+    const int g = lane >> 3, j = lane & 7;
+    const uint64_t slot = (uint64_t)blockIdx.x * kWaves + wave;
+    u64 *mypool = pool + slot * pool_chunks * kChunk;
+    uint32_t *myprev = chunk_prev + slot * pool_chunks * 2;
+    uint32_t *myfree = myprev + pool_chunks;
+    uint32_t *bstate = bstate_all + (kBest ? wave * kBuckets : 0);
+    u64 *stack = stack_all + (kBest ? 0 : wave * kMaxStack);
+    const bool has_and = T.andimg != nullptr;
+
+    for (;;) {
+        uint32_t qi = 0;
+        if (lane == 0) qi = atomicAdd(next_query, 1u);
+        qi = readfirst(qi);
+        if (qi >= nq) break;
+
+        // query in two layouts: row slices (chunks j, j+8, j+16, j+24) for the
+        // leaf scan, and chunk (lane & 31) for bounding two children at once
+        uint4 qv[4];
+        uint32_t s = 0;
+#pragma unroll
+        for (int i = 0; i < 4; i++) {
+            qv[i] = q[(uint64_t)qi * 32 + j + 8 * i];
+            s += popc4(qv[i]);
+        }
+        const uint32_t pq = readfirst(sum8(s));
+        const uint4 qn = q[(uint64_t)qi * 32 + (lane & 31)];
+        const uint4 nqn = make_uint4(~qn.x, ~qn.y, ~qn.z, ~qn.w);
+        const uint32_t wa = pq > 1 ? pq : 1;
+        const uint32_t wb = (QD_BITS - pq) > 1 ? QD_BITS - pq : 1;
+        const float *qs = S.s ? S.s + (uint64_t)qi * S.n_scored : nullptr;
+
+        u64 list = KEY_NONE;      // k best (K << 32 | row), lane r = r-th best
+        uint32_t payload = 0;     // A | B << 16 of the entry in `list`
+        uint32_t kworst = kNone;  // K of the k-th entry (kNone until k entries)
+        uint32_t visited = 0, leaves = 0, bounds = 0, dists = 0;
+
+        // frontier
+        u64 occ = 0;        // best-first: bucket occupancy bits 64*lane .. 64*lane+63
+        u64 touched = 0;    // best-first: buckets whose state word is valid for this query
+        uint32_t alloc = 0; // best-first: chunks handed out so far
+        uint32_t nfree = 0; // best-first: chunks on the free list
+        int sp = 0;         // depth-first: stack depth
+
+        auto bound_pair = [&](int32_t c0, int32_t c1, uint32_t &kb0, uint32_t &kb1) {
+            const int32_t c = lane < 32 ? c0 : c1;
+            const uint4 o = T.orimg[(uint64_t)c * 32 + (lane & 31)];
+            uint32_t ov = sum32(popc_and4(qn, o));
+            uint32_t bl = 0;
+            if (has_and) bl = sum32(popc_and4(nqn, T.andimg[(uint64_t)c * 32 + (lane & 31)]));
+            const uint32_t kb = (pq - ov) * wb + bl * wa;
+            kb0 = readlane(kb, 0);
+            kb1 = readlane(kb, 32);
+        };
+        auto take_chunk = [&]() -> uint32_t {  // lane 0 only; capacity is sized so it never runs out
+            const uint32_t c = nfree > 0 ? myfree[nfree - 1] : alloc;
+            return c < pool_chunks ? c : (uint32_t)(pool_chunks - 1);
+        };
+        auto push = [&](uint32_t kb, uint32_t node) {
+            const u64 e = ((u64)kb << 32) | node;
+            if (kBest) {
+                uint32_t b = kb / wb;
+                b = b < kBuckets ? b : kBuckets - 1;
+                const bool tb = (readlane64(touched, (int)(b >> 6)) >> (b & 63)) & 1ull;
+                uint32_t took = 0;
+                if (lane == 0) {
+                    if (!tb) {
+                        const uint32_t c = take_chunk();
+                        took = 1;
+                        myprev[c] = kNone;
+                        mypool[(uint64_t)c * kChunk] = e;
+                        bstate[b] = (c << 5) | 1u;
+                    } else {
+                        const uint32_t st = bstate[b];
+                        const uint32_t c = st >> 5, f = st & 31u;
+                        if (f == kChunk) {
+                            const uint32_t c2 = take_chunk();
+                            took = 1;
+                            myprev[c2] = c;
+                            mypool[(uint64_t)c2 * kChunk] = e;
+                            bstate[b] = (c2 << 5) | 1u;
+                        } else {
+                            mypool[(uint64_t)c * kChunk + f] = e;
+                            bstate[b] = (c << 5) | (f + 1);
+                        }
+                    }
+                }
+                if (readfirst(took)) {
+                    if (nfree > 0)
+                        nfree--;
+                    else
+                        alloc++;
+                }
+                if (lane == (int)(b >> 6)) {
+                    occ |= 1ull << (b & 63);
+                    touched |= 1ull << (b & 63);
+                }
+            } else {
+                if (sp < kMaxStack) {
+                    if (lane == 0) stack[sp] = e;
+                    sp++;
+                }
+            }
+        };
+
+        // root
+        {
+            const uint4 o = T.orimg[lane & 31];
+            uint32_t ov = sum32(popc_and4(qn, o));
+            uint32_t bl = 0;
+            if (has_and) bl = sum32(popc_and4(nqn, T.andimg[lane & 31]));
+            const uint32_t kb = readlane((pq - ov) * wb + bl * wa, 0);
+            bounds++;
+            push(kb, 0);
+        }
+
+        for (;;) {
+            u64 e;
+            if (kBest) {
+                const u64 nz = ballot(occ != 0);
+                if (!nz) break;
+                const int L = __builtin_ctzll(nz);
+                const uint32_t b = 64u * (uint32_t)L + (uint32_t)__builtin_ctzll(readlane64(occ, L));
+                u64 got = 0;
+                uint32_t emptied = 0, freed = kNone;
+                if (lane == 0) {
+                    const uint32_t st = bstate[b];
+                    const uint32_t c = st >> 5, f = (st & 31u) - 1;
+                    got = mypool[(uint64_t)c * kChunk + f];
+                    if (f == 0) {
+                        const uint32_t pc = myprev[c];
+                        if (pc == kNone) {
+                            bstate[b] = c << 5;  // keep the emptied chunk for this bucket
+                            emptied = 1;
+                        } else {
+                            bstate[b] = (pc << 5) | kChunk;
+                            myfree[nfree] = c;
+                            freed = c;
+                        }
+                    } else {
+                        bstate[b] = (c << 5) | f;
+                    }
+                }
+                e = readlane64(got, 0);
+                if (readfirst(freed) != kNone) nfree++;
+                if (readfirst(emptied) && lane == L) occ &= ~(1ull << (b & 63));
+            } else {
+                if (sp == 0) break;
+                sp--;
+                e = readlane64(lane == 0 ? stack[sp] : 0ull, 0);
+            }
+            const uint32_t kb = (uint32_t)(e >> 32), node = (uint32_t)e;
+            if (kworst != kNone && kb > kworst) {
+                if (kBest) break;  // every open node is at least this far
+                continue;          // depth-first: this entry cannot improve the result
+            }
+            visited++;
+            const int32_t c0 = T.child[2 * node], c1 = T.child[2 * node + 1];
+            if (c0 < 0) {
+                leaves++;
+                const uint32_t b0 = T.begin[node], m = T.count[node];
+                dists += m;
+                for (uint32_t base = 0; base < m; base += 8) {
+                    const uint32_t r = base + (uint32_t)g;
+                    const bool valid = r < m;
+                    const uint64_t pos = (uint64_t)b0 + (valid ? r : 0);
+                    uint4 tv[4];
+#pragma unroll
+                    for (int i = 0; i < 4; i++) tv[i] = T.sorted[pos * 32 + j + 8 * i];
+                    const uint32_t c = sum8(popc_and4(tv[0], qv[0]) + popc_and4(tv[1], qv[1]) +
+                                            popc_and4(tv[2], qv[2]) + popc_and4(tv[3], qv[3]));
+                    const uint32_t tp = T.pop[pos];
+                    const uint32_t A = pq - c, B = tp - c;
+                    const uint32_t K = A * wb + B * wa;
+                    const uint32_t row = T.perm[pos];
+                    const u64 key = valid ? ((u64)K << 32) | row : KEY_NONE;
+                    const u64 thr = kworst == kNone ? KEY_NONE : readlane64(list, (int)k - 1);
+                    u64 mk = ballot(j == 0 && key < thr);
+                    while (mk) {
+                        const int L = __builtin_ctzll(mk);
+                        mk &= mk - 1;
+                        const u64 cand = readlane64(key, L);
+                        const uint32_t cpay = readlane(A | (B << 16), L);
+                        const u64 t2 = readlane64(list, (int)k - 1);
+                        if (cand < t2) {
+                            const int pos2 = __popcll(ballot(list < cand));
+                            const u64 up = shift_up64(list);
+                            const uint32_t pup =
+                                (uint32_t)__builtin_amdgcn_ds_bpermute((lane > 0 ? lane - 1 : 0) << 2, (int)payload);
+                            const u64 nl = lane < pos2 ? list : (lane == pos2 ? cand : up);
+                            const uint32_t np = lane < pos2 ? payload : (lane == pos2 ? cpay : pup);
+                            list = lane < (int)k ? nl : KEY_NONE;
+                            payload = lane < (int)k ? np : 0;
+                        }
+                    }
+                    const u64 last = readlane64(list, (int)k - 1);
+                    kworst = last == KEY_NONE ? kNone : (uint32_t)(last >> 32);
+                }
+            } else {
+                uint32_t kb0, kb1;
+                bound_pair(c0, c1, kb0, kb1);
+                bounds += 2;
+                const bool ok0 = kworst == kNone || kb0 <= kworst;
+                const bool ok1 = kworst == kNone || kb1 <= kworst;
+                if (kBest) {
+                    if (ok0) push(kb0, (uint32_t)c0);
+                    if (ok1) push(kb1, (uint32_t)c1);
+                } else {
+                    // preferred child last, so it is popped first
+                    bool first1 = kb1 < kb0;  // lower bound first; ties: similar child
+                    if (qs && (uint32_t)c0 < S.n_scored && (uint32_t)c1 < S.n_scored) first1 = qs[c1] > qs[c0];
+                    if (first1) {
+                        if (ok0) push(kb0, (uint32_t)c0);
+                        if (ok1) push(kb1, (uint32_t)c1);
+                    } else {
+                        if (ok1) push(kb1, (uint32_t)c1);
+                        if (ok0) push(kb0, (uint32_t)c0);
+                    }
+                }
+            }
+        }
+
+        // results
+        if (lane < (int)k) {
+            const uint64_t o = (uint64_t)qi * k + lane;
+            if (list == KEY_NONE) {
+                idx[o] = QD_PAD_IDX;
+                missed[o] = -1;
+                extra[o] = -1;
+                dist[o] = __builtin_inff();
+            } else {
+                const uint32_t A = payload & 0xFFFF, B = payload >> 16;
+                idx[o] = (uint32_t)list;
+                missed[o] = (int32_t)A;
+                extra[o] = (int32_t)B;
+                dist[o] = (float)((double)(list >> 32) / ((double)wa * (double)wb));
+            }
+        }
+        if (lane == 0) {
+            if (qstats) {
+                qstats[(uint64_t)qi * 4 + 0] = visited;
+                qstats[(uint64_t)qi * 4 + 1] = leaves;
+                qstats[(uint64_t)qi * 4 + 2] = bounds;
+                qstats[(uint64_t)qi * 4 + 3] = dists;
+            }
+            if (gstats) {
+                atomicAdd(&gstats[0], (unsigned long long)visited);
+                atomicAdd(&gstats[1], (unsigned long long)leaves);
+                atomicAdd(&gstats[2], (unsigned long long)bounds);
+                atomicAdd(&gstats[3], (unsigned long long)dists);
+            }
+        }
+    }
+}
+
+}  // namespace
+
+int knn_tree_impl(qd_tree_t t, const uint64_t *d_q, uint32_t nq, uint32_t k, int order, const float *d_scores,
+                  uint32_t n_scored, uint32_t *d_idx, int32_t *d_missed, int32_t *d_extra, float *d_dist,
+                  uint32_t *d_qstats, qd_stats *h_stats, void *stream, uint32_t waves_per_cu) {
+    if (!t) return fail(QD_ERR_INVALID, "null tree");
+    if (k < 1 || k > QD_MAX_K) return fail(QD_ERR_INVALID, "k=%u outside 1..%d", k, QD_MAX_K);
+    if (order != QD_ORDER_BEST_FIRST && order != QD_ORDER_DEPTH_FIRST)
+        return fail(QD_ERR_INVALID, "unknown frontier order %d", order);
+    if (h_stats) *h_stats = qd_stats{0, 0, 0, 0};
+    if (nq == 0) return QD_OK;
+    if (!d_q || !d_idx || !d_missed || !d_extra || !d_dist) return fail(QD_ERR_INVALID, "null pointer");
+    if (!aligned16(d_q)) return fail(QD_ERR_INVALID, "queries must be 16-byte aligned");
+    if (order == QD_ORDER_DEPTH_FIRST && t->depth + 2 > (uint32_t)kMaxStack)
+        return fail(QD_ERR_UNSUPPORTED, "tree depth %u exceeds the depth-first stack (%d)", t->depth, kMaxStack);
+    hipStream_t s = (hipStream_t)stream;
+    const int cus = device_cus();
+    if (waves_per_cu == 0) waves_per_cu = order == QD_ORDER_BEST_FIRST ? 8 : 16;
+    uint64_t blocks = ((uint64_t)cus * waves_per_cu + kWaves - 1) / kWaves;
+    const uint64_t need = (nq + kWaves - 1) / kWaves;
+    if (blocks > need) blocks = need;
+    const uint64_t slots = blocks * kWaves;
+    // Each node is queued at most once.  Live chunks: a bucket holds at most
+    // one partly filled chunk (or one kept empty chunk) besides full ones, and
+    // emptied chunks go to a free list, so n_nodes/kChunk + 2 per bucket
+    // chunks never run out.
+    const uint64_t pool_chunks = order == QD_ORDER_BEST_FIRST ? t->n_nodes / kChunk + 2 * kBuckets + 2 : 1;
+    // workspace: [counter | stats x4 | pad] [chunk_prev] [pool]
+    const size_t head = 256;
+    const size_t prev_bytes = (size_t)(slots * pool_chunks * 8 + 255) / 256 * 256;  // prev + free list
+    const size_t pool_bytes = (size_t)slots * pool_chunks * kChunk * 8;
+    char *ws = nullptr;
+    QD_HIP_CHECK(hipMallocAsync((void **)&ws, head + prev_bytes + pool_bytes, s));
+    QD_HIP_CHECK(hipMemsetAsync(ws, 0, head, s));
+    uint32_t *counter = reinterpret_cast<uint32_t *>(ws);
+    unsigned long long *gstats = reinterpret_cast<unsigned long long *>(ws + 64);
+    uint32_t *chunk_prev = reinterpret_cast<uint32_t *>(ws + head);
+    u64 *pool = reinterpret_cast<u64 *>(ws + head + prev_bytes);
+    TreeView T{reinterpret_cast<const uint4 *>(t->d_sorted), t->d_perm, reinterpret_cast<const uint4 *>(t->d_or),
+               reinterpret_cast<const uint4 *>(t->d_and), t->d_child, t->d_begin, t->d_count, t->d_pop};
+    Scores S{d_scores, d_scores ? n_scored : 0};
+    {
+        KernelTimer timer("tree_knn", s);
+        if (order == QD_ORDER_BEST_FIRST)
+            hipLaunchKernelGGL(tree_knn_kernel<true>, dim3((uint32_t)blocks), dim3(kBlock), 0, s, T,
+                               reinterpret_cast<const uint4 *>(d_q), nq, k, counter, pool, chunk_prev, pool_chunks, S,
+                               d_idx, d_missed, d_extra, d_dist, d_qstats, gstats);
+        else
+            hipLaunchKernelGGL(tree_knn_kernel<false>, dim3((uint32_t)blocks), dim3(kBlock), 0, s, T,
+                               reinterpret_cast<const uint4 *>(d_q), nq, k, counter, pool, chunk_prev, pool_chunks, S,
+                               d_idx, d_missed, d_extra, d_dist, d_qstats, gstats);
+    }
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess && h_stats) {
+        unsigned long long hs[4];
+        e = hipMemcpyAsync(hs, gstats, sizeof hs, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e == hipSuccess) *h_stats = qd_stats{hs[0], hs[1], hs[2], hs[3]};
+    }
+    hipError_t e2 = hipFreeAsync(ws, s);
+    if (e != hipSuccess) return fail(QD_ERR_DEVICE, "tree search: %s", hipGetErrorString(e));
+    if (e2 != hipSuccess) return fail(QD_ERR_DEVICE, "hipFreeAsync: %s", hipGetErrorString(e2));
+    return QD_OK;
+}
+
+}  // namespace qd
+
+extern "C" int qd_knn_tree(qd_tree_t t, const uint64_t *d_q, uint32_t nq, uint32_t k, const qd_search_params *p,
+                           uint32_t *d_idx, int32_t *d_missed, int32_t *d_extra, float *d_dist,
+                           uint32_t *d_query_stats, qd_stats *h_stats, void *stream) {
+    const int order = p ? (int)p->order : QD_ORDER_BEST_FIRST;
+    const float *sc = p ? p->d_scores : nullptr;
+    const uint32_t ns = p ? p->n_scored : 0;
+    const uint32_t wpc = p ? p->waves_per_cu : 0;
+    if (sc && order != QD_ORDER_DEPTH_FIRST)
+        return qd::fail(QD_ERR_INVALID, "node scores order the depth-first frontier only");
+    return qd::knn_tree_impl(t, d_q, nq, k, order, sc, ns, d_idx, d_missed, d_extra, d_dist, d_query_stats, h_stats,
+                             stream, wpc);
+}

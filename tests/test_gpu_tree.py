@@ -1,0 +1,156 @@
+"""GPU Dissimilarity Tree build and search against the CPU oracle.
+
+Build: the whole tree (numbering, split membership, leaf order, images) must
+equal the oracle's literal Listing-1 build; at 1M rows the oracle re-splits
+sampled nodes from the GPU tree's own membership.  Search: results equal the
+oracle's sequential search bit for bit, in both frontier orders."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def qd():
+    import paper_2107_03368_amd as qd
+    return qd
+
+
+def _t(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a).view(np.int64)).to("cuda:0")
+
+
+def _same(res, ref, rows=None):
+    idx, missed, extra, dist = (x.cpu().numpy() for x in res[:4])
+    idx = idx.view(np.uint32)
+    if rows is not None:
+        idx, missed, extra, dist = idx[rows], missed[rows], extra[rows], dist[rows]
+    assert np.array_equal(idx, ref.idx)
+    assert np.array_equal(missed, ref.missed)
+    assert np.array_equal(extra, ref.extra)
+    assert np.array_equal(dist, ref.dist)
+
+
+def _same_tree(gt, ot):
+    assert gt["child"].shape[0] == ot.n_nodes
+    assert np.array_equal(gt["child"], ot.child)
+    assert np.array_equal(gt["begin"].astype(np.int64), ot.begin)
+    assert np.array_equal(gt["count"].astype(np.int64), ot.count)
+    assert np.array_equal(gt["perm"], ot.perm)
+    assert np.array_equal(gt["or_img"], ot.or_img)
+    if gt["and_img"] is not None:
+        assert np.array_equal(gt["and_img"], ot.and_img)
+
+
+@pytest.mark.parametrize("max_leaf", [32, 8])
+def test_build_equals_oracle_10k(qd, small_db, max_leaf):
+    gt = qd.tree_build(_t(small_db), max_leaf=max_leaf, store_and_image=True).export()
+    _same_tree(gt, oracle.tree_build(small_db, max_leaf=max_leaf))
+
+
+def test_build_equals_oracle_30k_large_nodes(qd):
+    db = synth.gen_db(30_000, 1009)  # nodes above 2048 rows take the multi-block path
+    _same_tree(qd.tree_build(_t(db)).export(), oracle.tree_build(db))
+
+
+def test_build_degenerate_inputs(qd):
+    cases = [
+        synth.from_bits(40, [[1, 2, 3]] * 40),                           # identical rows
+        np.zeros((50, 64), np.uint64),                                   # no set bit
+        synth.from_bits(40, [[] for _ in range(30)] + [[5]] * 10),       # zeros + one bit
+        synth.from_bits(34, [[10, 20] if i < 2 else [10] for i in range(34)]),
+        np.concatenate([synth.gen_db(3000, 5), synth.gen_db(3000, 5)]),  # every row twice
+        synth.gen_db(1, 6),
+    ]
+    for db in cases:
+        _same_tree(qd.tree_build(_t(db), store_and_image=True).export(), oracle.tree_build(db))
+
+
+@pytest.mark.parametrize("k", [1, 10, 50])
+def test_search_matches_oracle_10k(qd, small_db, small_queries, k):
+    q, _ = small_queries
+    tree = qd.tree_build(_t(small_db))
+    ref = oracle.knn_brute(small_db, q, k)
+    best = qd.knn_tree(tree, _t(q), k, query_stats=True)
+    _same(best, ref)
+    _same(qd.knn_tree(tree, _t(q), k, order=qd.ORDER_DEPTH_FIRST), ref)
+    # traversal statistics follow the oracle's best-first search (ties may pop
+    # in another order, so allow a small difference)
+    ot = oracle.tree_build(small_db)
+    ostats = oracle.tree_knn(small_db, ot, q, k).stats
+    g = best[4].cpu().numpy()
+    assert abs(g[:, 0].sum() - ostats[:, 0].sum()) <= 0.02 * ostats[:, 0].sum()
+    assert (g[:, 3] <= small_db.shape[0]).all()
+
+
+def test_search_with_product_images_and_scores(qd, small_db, small_queries):
+    import torch
+    q, _ = small_queries
+    tree = qd.tree_build(_t(small_db), store_and_image=True)
+    ref = oracle.knn_brute(small_db, q, 10)
+    _same(qd.knn_tree(tree, _t(q), 10), ref)
+    for seed in (1, 2):
+        sc = torch.from_numpy(np.random.default_rng(seed).random((len(q), tree.n_nodes), dtype=np.float32))
+        _same(qd.knn_tree(tree, _t(q), 10, order=qd.ORDER_DEPTH_FIRST, scores=sc.cuda()), ref)
+
+
+def test_search_edge_cases(qd):
+    base = synth.gen_db(500, 71)
+    db = np.concatenate([base, base[:100], np.zeros((5, 64), np.uint64)])
+    q = np.concatenate([base[:10], np.zeros((1, 64), np.uint64), np.full((1, 64), np.uint64(0xFFFFFFFFFFFFFFFF)),
+                        synth.gen_queries(base, 8, 72, 0.2, 0.6)[0]])
+    tree = qd.tree_build(_t(db))
+    for k in (1, 7, 64):
+        ref = oracle.knn_brute(db, q, k)
+        for order in (qd.ORDER_BEST_FIRST, qd.ORDER_DEPTH_FIRST):
+            _same(qd.knn_tree(tree, _t(q), k, order=order), ref)
+    small = synth.gen_db(3, 73)
+    t3 = qd.tree_build(_t(small))
+    ref = oracle.knn_brute(small, q, 5)
+    _same(qd.knn_tree(t3, _t(q), 5), ref)
+
+
+@pytest.fixture(scope="module")
+def tree_1m(qd):
+    db = synth.gen_db(1_000_000, 1001)
+    return db, qd.tree_build(_t(db))
+
+
+def test_build_1m_sampled_nodes(tree_1m):
+    db, tree = tree_1m
+    gt = tree.export()
+    n = db.shape[0]
+    assert np.array_equal(np.sort(gt["perm"]), np.arange(n, dtype=np.uint32))
+    child, begin, count = gt["child"], gt["begin"].astype(np.int64), gt["count"].astype(np.int64)
+    leaves = child[:, 0] < 0
+    assert count[leaves].sum() == n
+    rng = np.random.default_rng(9)
+    inner = np.flatnonzero(~leaves)
+    sizes = count[inner]
+    picks = list(rng.choice(inner[sizes <= 20_000], 24, replace=False)) + [int(inner[np.argmax(sizes <= 60_000)])]
+    for i in picks:
+        mem = gt["perm"][begin[i]:begin[i] + count[i]]
+        side = oracle.split_node(db, np.sort(mem))  # the node's rows in database order
+        s, d = child[i]
+        sim = np.sort(gt["perm"][begin[s]:begin[s] + count[s]])
+        dis = np.sort(gt["perm"][begin[d]:begin[d] + count[d]])
+        assert np.array_equal(np.sort(mem)[~side], sim) and np.array_equal(np.sort(mem)[side], dis)
+        assert np.array_equal(np.bitwise_or.reduce(db[mem], axis=0), gt["or_img"][i])
+    for i in rng.choice(np.flatnonzero(leaves), 200, replace=False):
+        mem = gt["perm"][begin[i]:begin[i] + count[i]]
+        assert count[i] <= 32 or (db[mem] == db[mem[0]]).all()
+        assert np.array_equal(np.bitwise_or.reduce(db[mem], axis=0), gt["or_img"][i])
+
+
+@pytest.mark.parametrize("k", [1, 10, 50])
+def test_search_1m_sampled_queries(qd, tree_1m, k):
+    db, tree = tree_1m
+    q, _ = synth.gen_queries(db, 4096, 2001, 0.1, 0.6)
+    rows = np.array([0, 5, 1000, 3333, 4095])
+    ref = oracle.knn_brute(db, q[rows], k)
+    _same(qd.knn_tree(tree, _t(q), k), ref, rows)
+    _same(qd.knn_tree(tree, _t(q), k, order=qd.ORDER_DEPTH_FIRST), ref, rows)
