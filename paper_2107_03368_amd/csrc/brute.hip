@@ -32,7 +32,8 @@ __global__ __launch_bounds__(kBlock) void scan_topk_kernel(const uint4 *__restri
     const int lane = lane_id();
     const int g = lane >> 3, j = lane & 7;
     const uint32_t qtile = blockIdx.x % n_qtiles;
-    const uint32_t p = (blockIdx.x / n_qtiles) * kWavesPerBlock + (threadIdx.x >> 6);
+    // wave-uniform (readfirstlane) so the row loop compiles as a uniform loop
+    const uint32_t p = readfirst((blockIdx.x / n_qtiles) * kWavesPerBlock + (threadIdx.x >> 6));
     if (p >= n_parts) return;  // whole wave
     const uint64_t r0 = (uint64_t)p * rows_per_part;
     const uint64_t r1 = r0 + rows_per_part < n ? r0 + rows_per_part : n;
@@ -159,7 +160,7 @@ __global__ __launch_bounds__(kBlock) void popcount_rows_kernel(const uint4 *__re
                                                                uint16_t *__restrict__ pop) {
     const int lane = lane_id();
     const int g = lane >> 3, j = lane & 7;
-    const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const uint64_t wave = readfirst((uint32_t)(((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6));
     const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
     for (uint64_t base = wave * kRowsPerStep; base < n; base += nwaves * kRowsPerStep) {
         const uint64_t row = base + g;

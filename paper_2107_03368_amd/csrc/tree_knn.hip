@@ -83,9 +83,11 @@ __global__ __launch_bounds__(kBlock) void tree_knn_kernel(TreeView T, const uint
     const bool has_and = T.andimg != nullptr;
 
     for (;;) {
-        uint32_t qi = 0;
-        if (lane == 0) qi = atomicAdd(next_query, 1u);
-        qi = readfirst(qi);
+        // every lane takes part in the atomic (lane 0 adds 1, the others 0) so
+        // that no lane-dependent branch guards the loop head; control values
+        // below are passed through readfirstlane so the compiler keeps the
+        // whole traversal wave-uniform
+        const uint32_t qi = readfirst(atomicAdd(next_query, lane == 0 ? 1u : 0u));
         if (qi >= nq) break;
 
         // query in two layouts: row slices (chunks j, j+8, j+16, j+24) for the
@@ -170,9 +172,9 @@ __global__ __launch_bounds__(kBlock) void tree_knn_kernel(TreeView T, const uint
                     touched |= 1ull << (b & 63);
                 }
             } else {
-                if (sp < kMaxStack) {
+                if (readfirst((uint32_t)sp) < (uint32_t)kMaxStack) {
                     if (lane == 0) stack[sp] = e;
-                    sp++;
+                    sp = (int)readfirst((uint32_t)sp + 1);
                 }
             }
         };
@@ -219,20 +221,21 @@ __global__ __launch_bounds__(kBlock) void tree_knn_kernel(TreeView T, const uint
                 if (readfirst(freed) != kNone) nfree++;
                 if (readfirst(emptied) && lane == L) occ &= ~(1ull << (b & 63));
             } else {
-                if (sp == 0) break;
-                sp--;
+                if (readfirst((uint32_t)sp) == 0) break;
+                sp = (int)readfirst((uint32_t)sp - 1);
                 e = readlane64(lane == 0 ? stack[sp] : 0ull, 0);
             }
-            const uint32_t kb = (uint32_t)(e >> 32), node = (uint32_t)e;
+            const uint32_t kb = readfirst((uint32_t)(e >> 32)), node = readfirst((uint32_t)e);
             if (kworst != kNone && kb > kworst) {
                 if (kBest) break;  // every open node is at least this far
                 continue;          // depth-first: this entry cannot improve the result
             }
             visited++;
-            const int32_t c0 = T.child[2 * node], c1 = T.child[2 * node + 1];
+            const int32_t c0 = (int32_t)readfirst((uint32_t)T.child[2 * node]);
+            const int32_t c1 = (int32_t)readfirst((uint32_t)T.child[2 * node + 1]);
             if (c0 < 0) {
                 leaves++;
-                const uint32_t b0 = T.begin[node], m = T.count[node];
+                const uint32_t b0 = readfirst(T.begin[node]), m = readfirst(T.count[node]);
                 dists += m;
                 for (uint32_t base = 0; base < m; base += 8) {
                     const uint32_t r = base + (uint32_t)g;
@@ -267,8 +270,7 @@ __global__ __launch_bounds__(kBlock) void tree_knn_kernel(TreeView T, const uint
                             payload = lane < (int)k ? np : 0;
                         }
                     }
-                    const u64 last = readlane64(list, (int)k - 1);
-                    kworst = last == KEY_NONE ? kNone : (uint32_t)(last >> 32);
+                    kworst = readfirst(readlane((uint32_t)(readlane64(list, (int)k - 1) >> 32), 0));
                 }
             } else {
                 uint32_t kb0, kb1;
