@@ -187,6 +187,31 @@ int qd_knn_tree(qd_tree_t t, const uint64_t *d_q, uint32_t nq, uint32_t k, const
                 uint32_t *d_idx, int32_t *d_missed, int32_t *d_extra, float *d_dist, uint32_t *d_query_stats,
                 qd_stats *h_stats, void *stream);
 
+/* ---------------------------------------------------------------------------
+ * Partial-object retrieval by voting (Section 3).
+ *
+ * nqo query objects; query object g owns the query descriptors
+ * d_qoff[g] .. d_qoff[g+1]-1 of d_qdesc (d_qoff: nqo+1 uint64 on the device,
+ * d_qoff[0] = 0, d_qoff[nqo] = n_qdesc), in the order they are processed (the
+ * paper draws them at random; the caller supplies that order).  Every
+ * descriptor's k nearest database descriptors are found exactly (through tree
+ * t, or by sequential search over d_db when t is NULL), all in one batched
+ * launch; each neighbour casts one vote for its object d_obj_of[row]
+ * (uint16, n rows; object ids < n_obj <= 65536; a row whose id is >= n_obj
+ * casts no vote).
+ * Outputs: d_votes nqo x n_obj uint32 (all votes), d_winner[g] = the first
+ * object whose count reaches vote_threshold (1..255; the paper uses 10),
+ * counting votes in descriptor order and, within a descriptor, in neighbour
+ * rank order, or -1 if none does; d_used[g] = descriptors processed when the
+ * winner was decided (all of them if none).  d_nn_idx (nullable, n_qdesc x k
+ * uint32) receives the neighbour rows.  params (nullable) picks the tree
+ * frontier order and occupancy; d_scores must be NULL.
+ * ------------------------------------------------------------------------- */
+int qd_retrieve_objects(qd_tree_t t, const uint64_t *d_db, uint64_t n, const uint16_t *d_obj_of, uint32_t n_obj,
+                        const uint64_t *d_qdesc, uint64_t n_qdesc, const uint64_t *d_qoff, uint32_t nqo, uint32_t k,
+                        uint32_t vote_threshold, const qd_search_params *params, uint32_t *d_votes,
+                        int32_t *d_winner, uint32_t *d_used, uint32_t *d_nn_idx, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

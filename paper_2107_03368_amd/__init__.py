@@ -228,3 +228,32 @@ def knn_tree(tree, q, k, order=ORDER_BEST_FIRST, scores=None, query_stats=False,
     if totals:
         out.append(st.as_dict())
     return tuple(out)
+
+
+# ---------------------------------------------------------------------------
+# Retrieval by voting
+# ---------------------------------------------------------------------------
+_sig("qd_retrieve_objects", [_P, _P, _U64, _P, _U32, _P, _U64, _P, _U32, _U32, _U32, ctypes.POINTER(_SearchParams),
+                             _P, _P, _P, _P, _P])
+
+
+def retrieve_objects(qdesc, qoff, obj_of, n_obj, k, threshold=10, tree=None, db=None, order=ORDER_BEST_FIRST,
+                     return_nn=False):
+    """Vote histogram (nqo, n_obj), winner (nqo,), descriptors used (nqo,)[, neighbour rows].
+
+    qoff: cuda int64 (nqo+1) CSR offsets into qdesc; obj_of: cuda int16 object id per database row."""
+    _desc(qdesc, "qdesc")
+    if tree is None:
+        _desc(db, "db")
+    nqo = qoff.shape[0] - 1
+    dev = qdesc.device
+    votes = torch.empty((nqo, n_obj), dtype=torch.int32, device=dev)
+    winner = torch.empty(nqo, dtype=torch.int32, device=dev)
+    used = torch.empty(nqo, dtype=torch.int32, device=dev)
+    nn = torch.empty((qdesc.shape[0], k), dtype=torch.int32, device=dev) if return_nn else None
+    prm = _SearchParams(order, None, 0, 0)
+    rc = _lib.qd_retrieve_objects(tree.handle if tree is not None else None, _ptr(db), 0 if db is None else db.shape[0],
+                                  _ptr(obj_of), n_obj, _ptr(qdesc), qdesc.shape[0], _ptr(qoff), nqo, k, threshold,
+                                  ctypes.byref(prm), _ptr(votes), _ptr(winner), _ptr(used), _ptr(nn), _stream())
+    _check(rc, "qd_retrieve_objects")
+    return (votes, winner, used, nn) if return_nn else (votes, winner, used)
