@@ -168,7 +168,8 @@ int qd_tree_export(qd_tree_t t, int32_t *h_child, uint32_t *h_begin, uint32_t *h
  * d_query_stats (nullable): nq x 4 uint32 per query: nodes visited
  * (expanded pops, leaves and inner nodes), leaves visited, bounds evaluated,
  * distances evaluated.  h_stats (nullable): totals; filling it waits for the
- * stream.  waves_per_cu = 0 picks a default occupancy.
+ * stream.  waves_per_cu = 0 picks a default occupancy.  d_visited records
+ * which of the first n_traced nodes each query expanded (traversal traces).
  * ------------------------------------------------------------------------- */
 typedef enum { QD_ORDER_BEST_FIRST = 0, QD_ORDER_DEPTH_FIRST = 1 } qd_order;
 
@@ -177,6 +178,10 @@ typedef struct {
     const float *d_scores; /* depth-first only; nullable */
     uint32_t n_scored;
     uint32_t waves_per_cu;
+    uint32_t *d_visited;   /* nullable: trace bitmap, nq x ceil(n_traced/32) uint32; bit (node % 32) of word
+                              node / 32 of query j's row is set when the search expands node (< n_traced).
+                              The library clears it first. */
+    uint32_t n_traced;
 } qd_search_params;
 
 typedef struct {
@@ -211,6 +216,81 @@ int qd_retrieve_objects(qd_tree_t t, const uint64_t *d_db, uint64_t n, const uin
                         const uint64_t *d_qdesc, uint64_t n_qdesc, const uint64_t *d_qoff, uint32_t nqo, uint32_t k,
                         uint32_t vote_threshold, const qd_search_params *params, uint32_t *d_votes,
                         int32_t *d_winner, uint32_t *d_used, uint32_t *d_nn_idx, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Learned frontier order (an extension: the paper orders the frontier by the
+ * bound only).  A multilayer perceptron scores (query, node) pairs; the
+ * depth-first search visits the higher-scoring child first.  Pruning keeps
+ * using the exact bounds, so the k-NN result is the same for any scores.
+ *   x = [query bits (4096, 0/1), node features (32)]
+ *   h1 = ReLU(x W1 + b1), h2 = ReLU(h1 W2 + b2), score = h2 . w3 + b3
+ * Parameters (fp32, QD_MLP_NPARAMS floats, this order, matrices stored
+ * [input][output] row-major): W1q 4096 x 256 (query-bit rows of W1),
+ * W1f 32 x 256 (feature rows), b1 256, W2 256 x 256, b2 256, w3 256, b3 1.
+ * Inference and training run BF16 weights with FP32 accumulation; the model
+ * keeps FP32 masters and Adam moments.
+ * Features of pair (q, node), |q| read as max(|q|,1), a_lb =
+ * popcount(q AND NOT OR(node)), ov = popcount(q AND OR(node)), bands =
+ * image rows 0-5, 6-11, ..., 54-59, 60-63:
+ *   0 a_lb/|q|  1 ov/|q|  2 popcount(OR)/4096  3 the sibling's a_lb/|q| (0 for
+ *   the root)  4 depth/32  5 log2(rows under the node)/24  6 is a leaf
+ *   7 is the similar child  8 |q|/512  9 popcount(OR AND NOT q)/4096
+ *   10..20 a_lb per band / |q|   21..31 ov per band / |q|
+ * ------------------------------------------------------------------------- */
+#define QD_MLP_HIDDEN 256
+#define QD_MLP_FEATURES 32
+#define QD_MLP_NPARAMS 1123073
+
+typedef struct qd_model_s *qd_model_t;
+
+/* New model from device fp32 parameters (copied); synchronous. */
+int qd_model_create(const float *d_params, void *stream, qd_model_t *out);
+int qd_model_free(qd_model_t m);
+/* Copy the fp32 master parameters to d_params (QD_MLP_NPARAMS floats). */
+int qd_model_params(qd_model_t m, float *d_params, void *stream);
+/* Features (n_pairs x 32 fp32) of pairs (d_q[d_pair_q[p]], d_pair_node[p]). */
+int qd_model_features(qd_tree_t t, const uint64_t *d_q, const uint32_t *d_pair_q, const uint32_t *d_pair_node,
+                      uint64_t n_pairs, float *d_feat, void *stream);
+/* Scores (logits) of pairs with given features; pair p uses query d_pair_q[p] < nq. */
+int qd_model_forward(qd_model_t m, const uint64_t *d_q, uint32_t nq, const uint32_t *d_pair_q, const float *d_feat,
+                     uint64_t n_pairs, float *d_scores, void *stream);
+/* Gradient of the mean binary cross-entropy (labels 0/1 against the logit)
+ * over the pairs, which must be grouped by query: query j owns pairs
+ * d_qoff[j] .. d_qoff[j+1]-1 (device, nq+1).  d_grads: QD_MLP_NPARAMS floats
+ * in the parameter layout; d_loss (nullable): the mean loss.  Reductions run
+ * in a fixed order, so the gradient is reproducible. */
+int qd_model_gradients(qd_model_t m, const uint64_t *d_q, uint32_t nq, const uint64_t *d_qoff,
+                       const uint32_t *d_pair_q, const float *d_feat, const float *d_labels, uint64_t n_pairs,
+                       float *d_grads, float *d_loss, void *stream);
+/* One Adam step (beta 0.9 / 0.999, eps 1e-8) with the given gradient. */
+int qd_model_adam_step(qd_model_t m, const float *d_grads, float lr, void *stream);
+/* Scores of nodes 0 .. n_scored-1 for every query: d_scores is nq x n_scored,
+ * ready for qd_search_params.d_scores. */
+int qd_model_score_tree(qd_model_t m, qd_tree_t t, const uint64_t *d_q, uint32_t nq, uint32_t n_scored,
+                        float *d_scores, void *stream);
+/* Training pairs from a traced search: for each query j and node 1 <=
+ * node < n_traced whose parent the search expanded (d_visited, as written by
+ * qd_knn_tree), a pair (j, node) with label 1 if one of the query's k result
+ * rows (d_result_idx, nq x k) lies under the node, else 0.  Pairs come grouped
+ * by query in ascending node order; d_qoff (nq+1 uint64) gets the groups.
+ * Writes at most `capacity` pairs and returns the total in *h_n_pairs (if it
+ * exceeds capacity nothing is written: call again with enough room).
+ * Synchronous. */
+int qd_trace_pairs(qd_tree_t t, uint32_t nq, uint32_t k, const uint32_t *d_result_idx, const uint32_t *d_visited,
+                   uint32_t n_traced, uint32_t *d_pair_q, uint32_t *d_pair_node, float *d_labels, uint64_t capacity,
+                   uint64_t *d_qoff, uint64_t *h_n_pairs, void *stream);
+
+/* Train on traversal traces: trace the exact best-first search of the nq
+ * training queries (k results, nodes < n_traced), form the labelled pairs as
+ * qd_trace_pairs does, then run `epochs` passes of Adam (learning rate lr)
+ * over batches of batch_queries consecutive queries, taken in the order
+ * h_batch_order gives (host array of ceil(nq / batch_queries) batch indices;
+ * NULL = ascending).  h_losses (nullable, host, epochs x batches floats):
+ * mean loss of every step (NaN for a batch without pairs).  *h_n_pairs: the
+ * number of training pairs.  Synchronous. */
+int qd_model_train(qd_model_t m, qd_tree_t t, const uint64_t *d_q, uint32_t nq, uint32_t k, uint32_t n_traced,
+                   uint32_t epochs, uint32_t batch_queries, float lr, const uint32_t *h_batch_order,
+                   float *h_losses, uint64_t *h_n_pairs, void *stream);
 
 #ifdef __cplusplus
 }

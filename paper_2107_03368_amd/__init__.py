@@ -135,7 +135,7 @@ class _TreeInfo(ctypes.Structure):
 
 class _SearchParams(ctypes.Structure):
     _fields_ = [("order", ctypes.c_int), ("d_scores", ctypes.c_void_p), ("n_scored", ctypes.c_uint32),
-                ("waves_per_cu", ctypes.c_uint32)]
+                ("waves_per_cu", ctypes.c_uint32), ("d_visited", ctypes.c_void_p), ("n_traced", ctypes.c_uint32)]
 
 
 class Stats(ctypes.Structure):
@@ -212,7 +212,7 @@ def knn_tree(tree, q, k, order=ORDER_BEST_FIRST, scores=None, query_stats=False,
     nq = q.shape[0]
     idx, missed, extra, dist = _results(nq, k, q.device)
     qs = torch.empty((nq, 4), dtype=torch.int32, device=q.device) if query_stats else None
-    prm = _SearchParams(order, None, 0, waves_per_cu)
+    prm = _SearchParams(order, None, 0, waves_per_cu, None, 0)
     if scores is not None:
         if not (scores.is_cuda and scores.dtype == torch.float32 and scores.dim() == 2 and scores.shape[0] == nq
                 and scores.is_contiguous()):
@@ -251,9 +251,151 @@ def retrieve_objects(qdesc, qoff, obj_of, n_obj, k, threshold=10, tree=None, db=
     winner = torch.empty(nqo, dtype=torch.int32, device=dev)
     used = torch.empty(nqo, dtype=torch.int32, device=dev)
     nn = torch.empty((qdesc.shape[0], k), dtype=torch.int32, device=dev) if return_nn else None
-    prm = _SearchParams(order, None, 0, 0)
+    prm = _SearchParams(order, None, 0, 0, None, 0)
     rc = _lib.qd_retrieve_objects(tree.handle if tree is not None else None, _ptr(db), 0 if db is None else db.shape[0],
                                   _ptr(obj_of), n_obj, _ptr(qdesc), qdesc.shape[0], _ptr(qoff), nqo, k, threshold,
                                   ctypes.byref(prm), _ptr(votes), _ptr(winner), _ptr(used), _ptr(nn), _stream())
     _check(rc, "qd_retrieve_objects")
     return (votes, winner, used, nn) if return_nn else (votes, winner, used)
+
+
+# ---------------------------------------------------------------------------
+# Learned frontier order (MLP)
+# ---------------------------------------------------------------------------
+MLP_HIDDEN = 256
+MLP_FEATURES = 32
+MLP_NPARAMS = 1123073
+
+_sig("qd_model_create", [_P, _P, ctypes.POINTER(ctypes.c_void_p)])
+_sig("qd_model_free", [_P])
+_sig("qd_model_params", [_P, _P, _P])
+_sig("qd_model_features", [_P, _P, _P, _P, _U64, _P, _P])
+_sig("qd_model_forward", [_P, _P, _U32, _P, _P, _U64, _P, _P])
+_sig("qd_model_gradients", [_P, _P, _U32, _P, _P, _P, _P, _U64, _P, _P, _P])
+_sig("qd_model_adam_step", [_P, _P, ctypes.c_float, _P])
+_sig("qd_model_score_tree", [_P, _P, _P, _U32, _U32, _P, _P])
+_sig("qd_trace_pairs", [_P, _U32, _U32, _P, _P, _U32, _P, _P, _P, _U64, _P, ctypes.POINTER(ctypes.c_uint64), _P])
+_sig("qd_model_train", [_P, _P, _P, _U32, _U32, _U32, _U32, _U32, ctypes.c_float, _P, _P,
+                        ctypes.POINTER(ctypes.c_uint64), _P])
+
+
+class Model:
+    """Library-owned frontier-order model (fp32 masters + bf16 copies)."""
+
+    def __init__(self, params):
+        if not (params.is_cuda and params.dtype == torch.float32 and params.numel() == MLP_NPARAMS):
+            raise ValueError(f"params must be a cuda float32 tensor of {MLP_NPARAMS} values")
+        h = ctypes.c_void_p()
+        _check(_lib.qd_model_create(_ptr(params.contiguous()), _stream(), ctypes.byref(h)), "qd_model_create")
+        self._h = h
+
+    @property
+    def handle(self):
+        return self._h
+
+    def params(self):
+        out = torch.empty(MLP_NPARAMS, dtype=torch.float32, device="cuda")
+        _check(_lib.qd_model_params(self._h, _ptr(out), _stream()), "qd_model_params")
+        return out
+
+    def free(self):
+        if self._h is not None and self._h.value:
+            _lib.qd_model_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def _u32(t, name):
+    if not (t.is_cuda and t.dtype == torch.int32 and t.is_contiguous()):
+        raise ValueError(f"{name} must be a contiguous cuda int32 tensor")
+    return t
+
+
+def model_features(tree, q, pair_q, pair_node):
+    _desc(q, "q")
+    _u32(pair_q, "pair_q")
+    _u32(pair_node, "pair_node")
+    feat = torch.empty((pair_q.shape[0], MLP_FEATURES), dtype=torch.float32, device=q.device)
+    _check(_lib.qd_model_features(tree.handle, _ptr(q), _ptr(pair_q), _ptr(pair_node), pair_q.shape[0], _ptr(feat),
+                                  _stream()), "qd_model_features")
+    return feat
+
+
+def model_forward(model, q, pair_q, feat):
+    _desc(q, "q")
+    _u32(pair_q, "pair_q")
+    s = torch.empty(pair_q.shape[0], dtype=torch.float32, device=q.device)
+    _check(_lib.qd_model_forward(model.handle, _ptr(q), q.shape[0], _ptr(pair_q), _ptr(feat.contiguous()),
+                                 pair_q.shape[0], _ptr(s), _stream()), "qd_model_forward")
+    return s
+
+
+def model_gradients(model, q, qoff, pair_q, feat, labels):
+    """(gradient vector, mean loss); pairs grouped by query as qoff (int64, nq+1) says."""
+    _desc(q, "q")
+    _u32(pair_q, "pair_q")
+    g = torch.empty(MLP_NPARAMS, dtype=torch.float32, device=q.device)
+    loss = torch.empty(1, dtype=torch.float32, device=q.device)
+    _check(_lib.qd_model_gradients(model.handle, _ptr(q), q.shape[0], _ptr(qoff), _ptr(pair_q),
+                                   _ptr(feat.contiguous()), _ptr(labels.contiguous()), pair_q.shape[0], _ptr(g),
+                                   _ptr(loss), _stream()), "qd_model_gradients")
+    return g, loss
+
+
+def model_adam_step(model, grads, lr):
+    _check(_lib.qd_model_adam_step(model.handle, _ptr(grads), lr, _stream()), "qd_model_adam_step")
+
+
+def model_score_tree(model, tree, q, n_scored):
+    _desc(q, "q")
+    s = torch.empty((q.shape[0], n_scored), dtype=torch.float32, device=q.device)
+    _check(_lib.qd_model_score_tree(model.handle, tree.handle, _ptr(q), q.shape[0], n_scored, _ptr(s), _stream()),
+           "qd_model_score_tree")
+    return s
+
+
+def knn_tree_traced(tree, q, k, n_traced):
+    """Best-first search that also returns the visited bitmap (nq, ceil(n_traced/32)) int32."""
+    _desc(q, "q")
+    nq = q.shape[0]
+    idx, missed, extra, dist = _results(nq, k, q.device)
+    vis = torch.empty((nq, (n_traced + 31) // 32), dtype=torch.int32, device=q.device)
+    prm = _SearchParams(ORDER_BEST_FIRST, None, 0, 0, vis.data_ptr(), n_traced)
+    _check(_lib.qd_knn_tree(tree.handle, _ptr(q), nq, k, ctypes.byref(prm), _ptr(idx), _ptr(missed), _ptr(extra),
+                            _ptr(dist), None, None, _stream()), "qd_knn_tree")
+    return idx, missed, extra, dist, vis
+
+
+def trace_pairs(tree, result_idx, visited, n_traced):
+    """(pair_q, pair_node, labels, qoff) from a traced search."""
+    nq, k = result_idx.shape
+    qoff = torch.empty(nq + 1, dtype=torch.int64, device=result_idx.device)
+    n = ctypes.c_uint64()
+    _check(_lib.qd_trace_pairs(tree.handle, nq, k, _ptr(result_idx), _ptr(visited), n_traced, None, None, None, 0,
+                               _ptr(qoff), ctypes.byref(n), _stream()), "qd_trace_pairs")
+    npairs = n.value
+    pq = torch.empty(npairs, dtype=torch.int32, device=result_idx.device)
+    pn = torch.empty(npairs, dtype=torch.int32, device=result_idx.device)
+    lab = torch.empty(npairs, dtype=torch.float32, device=result_idx.device)
+    _check(_lib.qd_trace_pairs(tree.handle, nq, k, _ptr(result_idx), _ptr(visited), n_traced, _ptr(pq), _ptr(pn),
+                               _ptr(lab), npairs, _ptr(qoff), ctypes.byref(n), _stream()), "qd_trace_pairs")
+    return pq, pn, lab, qoff
+
+
+def model_train(model, tree, q, k, n_traced, epochs, batch_queries, lr, batch_order=None):
+    """Train on traces of the exact search; returns (per-step losses, number of pairs)."""
+    import numpy as np
+    _desc(q, "q")
+    nb = (q.shape[0] + batch_queries - 1) // batch_queries
+    losses = np.zeros(epochs * nb, dtype=np.float32)
+    order = None if batch_order is None else np.ascontiguousarray(batch_order, dtype=np.uint32)
+    n = ctypes.c_uint64()
+    _check(_lib.qd_model_train(model.handle, tree.handle, _ptr(q), q.shape[0], k, n_traced, epochs, batch_queries,
+                               lr, None if order is None else ctypes.c_void_p(order.ctypes.data),
+                               ctypes.c_void_p(losses.ctypes.data), ctypes.byref(n), _stream()), "qd_model_train")
+    return losses, n.value

@@ -39,6 +39,21 @@ __device__ __forceinline__ uint32_t sum8(uint32_t v) {
     return v;
 }
 
+// Sum over each 32-lane half of the wave; every lane gets its half's sum.
+__device__ __forceinline__ uint32_t sum32_half(uint32_t v) {
+    v = sum8(v);
+    v += (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x140, 0xF, 0xF, false);  // row_mirror (16 lanes)
+    v += (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, 0x401F);             // xor 16 within 32
+    return v;
+}
+
+// Float sum over the wave in a fixed butterfly order (every lane gets it).
+__device__ __forceinline__ float wave_sum_f(float v) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m);
+    return v;
+}
+
 __device__ __forceinline__ uint32_t popc4(uint4 a) {
     return __popc(a.x) + __popc(a.y) + __popc(a.z) + __popc(a.w);
 }

@@ -19,6 +19,9 @@ struct qd_tree_s {
     uint32_t *d_begin = nullptr;   // n_nodes: first leaf-order position
     uint32_t *d_count = nullptr;   // n_nodes: rows under the node
     uint16_t *d_pop = nullptr;     // n: popcount of each leaf-order row
+    int32_t *d_parent = nullptr;   // n_nodes: parent node (-1 for the root)
+    uint8_t *d_depth = nullptr;    // n_nodes: level of the node (root 0)
+    uint32_t *d_iperm = nullptr;   // n: leaf-order position of each database row
 };
 
 namespace qd {

@@ -23,7 +23,8 @@ int knn_bruteforce_impl(const uint64_t *d_db, uint64_t n, const uint64_t *d_q, u
                         uint32_t qt_force, uint32_t parts_force);
 int knn_tree_impl(qd_tree_t t, const uint64_t *d_q, uint32_t nq, uint32_t k, int order, const float *d_scores,
                   uint32_t n_scored, uint32_t *d_idx, int32_t *d_missed, int32_t *d_extra, float *d_dist,
-                  uint32_t *d_qstats, qd_stats *h_stats, void *stream, uint32_t waves_per_cu);
+                  uint32_t *d_qstats, qd_stats *h_stats, void *stream, uint32_t waves_per_cu, uint32_t *d_trace,
+                  uint32_t n_traced);
 
 namespace {
 
@@ -119,7 +120,8 @@ extern "C" int qd_retrieve_objects(qd_tree_t t, const uint64_t *d_db, uint64_t n
     if (n_qdesc > 0xFFFFFFFFull) return fail(QD_ERR_INVALID, "too many query descriptors");
     const uint64_t n_db = t ? t->n : n;
     if (!t && (!d_db || n < 1)) return fail(QD_ERR_INVALID, "no tree and no database");
-    if (params && params->d_scores) return fail(QD_ERR_INVALID, "scores are per call of qd_knn_tree only");
+    if (params && (params->d_scores || params->d_visited))
+        return fail(QD_ERR_INVALID, "scores and traces are per call of qd_knn_tree only");
     hipStream_t s = (hipStream_t)stream;
     const size_t m = (size_t)n_qdesc * k;
     uint32_t *nn = d_nn_idx;
@@ -140,7 +142,7 @@ extern "C" int qd_retrieve_objects(qd_tree_t t, const uint64_t *d_db, uint64_t n
         if (t)
             rc = knn_tree_impl(t, d_qdesc, (uint32_t)n_qdesc, k, params ? (int)params->order : QD_ORDER_BEST_FIRST,
                                nullptr, 0, nn, missed, extra, dist, nullptr, nullptr, stream,
-                               params ? params->waves_per_cu : 0);
+                               params ? params->waves_per_cu : 0, nullptr, 0);
         else
             rc = knn_bruteforce_impl(d_db, n, d_qdesc, (uint32_t)n_qdesc, k, nn, missed, extra, dist, stream, 0, 0);
         if (rc != QD_OK) {

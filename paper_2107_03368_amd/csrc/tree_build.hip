@@ -454,6 +454,12 @@ __global__ __launch_bounds__(kBlock) void inner_images_kernel(const uint32_t *__
     }
 }
 
+__global__ __launch_bounds__(kBlock) void invert_perm_kernel(const uint32_t *__restrict__ perm, uint64_t n,
+                                                             uint32_t *__restrict__ iperm) {
+    for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (uint64_t)gridDim.x * kBlock)
+        iperm[perm[i]] = (uint32_t)i;
+}
+
 template <class T>
 struct DevBuf {
     T *p = nullptr;
@@ -467,7 +473,8 @@ struct DevBuf {
 
 void tree_release(qd_tree_s *t) {
     if (!t) return;
-    void *ptrs[] = {t->d_sorted, t->d_perm, t->d_or, t->d_and, t->d_child, t->d_begin, t->d_count, t->d_pop};
+    void *ptrs[] = {t->d_sorted, t->d_perm,  t->d_or,    t->d_and,   t->d_child, t->d_begin,
+                    t->d_count,  t->d_pop,   t->d_parent, t->d_depth, t->d_iperm};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     delete t;
@@ -634,7 +641,8 @@ int tree_build_impl(const uint64_t *d_db, uint64_t n, const qd_build_params *par
     if (hipMalloc((void **)&t->d_sorted, n * 512) != hipSuccess || hipMalloc((void **)&t->d_perm, n * 4) != hipSuccess ||
         hipMalloc((void **)&t->d_or, nn * 512) != hipSuccess || hipMalloc((void **)&t->d_child, nn * 8) != hipSuccess ||
         hipMalloc((void **)&t->d_begin, nn * 4) != hipSuccess || hipMalloc((void **)&t->d_count, nn * 4) != hipSuccess ||
-        hipMalloc((void **)&t->d_pop, n * 2) != hipSuccess ||
+        hipMalloc((void **)&t->d_pop, n * 2) != hipSuccess || hipMalloc((void **)&t->d_parent, nn * 4) != hipSuccess ||
+        hipMalloc((void **)&t->d_depth, nn) != hipSuccess || hipMalloc((void **)&t->d_iperm, n * 4) != hipSuccess ||
         (want_and && hipMalloc((void **)&t->d_and, nn * 512) != hipSuccess))
         return cleanup(fail(QD_ERR_OOM, "tree allocation failed"));
     std::vector<uint32_t> hb32(nn);
@@ -646,6 +654,16 @@ int tree_build_impl(const uint64_t *d_db, uint64_t n, const qd_build_params *par
     }
     n_leaves = (uint32_t)leaf_ids.size();
     t->n_leaves = n_leaves;
+    std::vector<int32_t> parent(nn, -1);
+    std::vector<uint8_t> depth(nn, 0);
+    for (uint64_t i = 0; i < nn; i++)
+        if (child[2 * i] >= 0) {
+            parent[child[2 * i]] = parent[child[2 * i + 1]] = (int32_t)i;
+            depth[child[2 * i]] = depth[child[2 * i + 1]] = (uint8_t)std::min(255, depth[i] + 1);
+        }
+    if (hipMemcpyAsync(t->d_parent, parent.data(), nn * 4, hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(t->d_depth, depth.data(), nn, hipMemcpyHostToDevice, s) != hipSuccess)
+        return cleanup(fail(QD_ERR_DEVICE, "tree upload failed"));
     if (hipMemcpyAsync(t->d_perm, pin, n * 4, hipMemcpyDeviceToDevice, s) != hipSuccess ||
         hipMemcpyAsync(t->d_child, child.data(), nn * 8, hipMemcpyHostToDevice, s) != hipSuccess ||
         hipMemcpyAsync(t->d_begin, hb32.data(), nn * 4, hipMemcpyHostToDevice, s) != hipSuccess ||
@@ -678,6 +696,8 @@ int tree_build_impl(const uint64_t *d_db, uint64_t n, const qd_build_params *par
                            reinterpret_cast<uint4 *>(t->d_and));
         if (hipStreamSynchronize(s) != hipSuccess) return cleanup(fail(QD_ERR_DEVICE, "inner images"));
     }
+    hipLaunchKernelGGL(invert_perm_kernel, dim3((uint32_t)std::min<uint64_t>((n + kBlock - 1) / kBlock, 65535)),
+                       dim3(kBlock), 0, s, t->d_perm, n, t->d_iperm);
     int rc = qd_popcount_rows(t->d_sorted, n, t->d_pop, stream);
     if (rc != QD_OK) return cleanup(rc);
     if (hipStreamSynchronize(s) != hipSuccess || hipGetLastError() != hipSuccess)

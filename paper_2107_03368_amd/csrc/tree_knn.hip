@@ -54,13 +54,7 @@ struct Scores {
     uint32_t n_scored;    // nodes 0 .. n_scored-1 carry a score
 };
 
-// Sum over the 32-lane half of the wave; every lane gets its half's sum.
-__device__ __forceinline__ uint32_t sum32(uint32_t v) {
-    v = sum8(v);
-    v += (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x140, 0xF, 0xF, false);  // row_mirror (16 lanes)
-    v += (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, 0x401F);             // xor 16 within 32
-    return v;
-}
+__device__ __forceinline__ uint32_t sum32(uint32_t v) { return sum32_half(v); }
 
 template <bool kBest>
 __global__ __launch_bounds__(kBlock) void tree_knn_kernel(TreeView T, const uint4 *__restrict__ q, uint32_t nq,
@@ -68,7 +62,8 @@ __global__ __launch_bounds__(kBlock) void tree_knn_kernel(TreeView T, const uint
                                                           u64 *__restrict__ pool, uint32_t *__restrict__ chunk_prev,
                                                           uint64_t pool_chunks, Scores S, uint32_t *idx,
                                                           int32_t *missed, int32_t *extra, float *dist,
-                                                          uint32_t *qstats, unsigned long long *gstats) {
+                                                          uint32_t *qstats, unsigned long long *gstats,
+                                                          uint32_t *trace, uint32_t n_traced) {
     __shared__ uint32_t bstate_all[kBest ? kWaves * kBuckets : 1];
     __shared__ u64 stack_all[kBest ? 1 : kWaves * kMaxStack];
     const int lane = lane_id();
@@ -231,6 +226,8 @@ __global__ __launch_bounds__(kBlock) void tree_knn_kernel(TreeView T, const uint
                 continue;          // depth-first: this entry cannot improve the result
             }
             visited++;
+            if (trace && node < n_traced && lane == 0)
+                atomicOr(&trace[(uint64_t)qi * ((n_traced + 31) / 32) + node / 32], 1u << (node & 31));
             const int32_t c0 = (int32_t)readfirst((uint32_t)T.child[2 * node]);
             const int32_t c1 = (int32_t)readfirst((uint32_t)T.child[2 * node + 1]);
             if (c0 < 0) {
@@ -333,7 +330,8 @@ __global__ __launch_bounds__(kBlock) void tree_knn_kernel(TreeView T, const uint
 
 int knn_tree_impl(qd_tree_t t, const uint64_t *d_q, uint32_t nq, uint32_t k, int order, const float *d_scores,
                   uint32_t n_scored, uint32_t *d_idx, int32_t *d_missed, int32_t *d_extra, float *d_dist,
-                  uint32_t *d_qstats, qd_stats *h_stats, void *stream, uint32_t waves_per_cu) {
+                  uint32_t *d_qstats, qd_stats *h_stats, void *stream, uint32_t waves_per_cu, uint32_t *d_trace,
+                  uint32_t n_traced) {
     if (!t) return fail(QD_ERR_INVALID, "null tree");
     if (k < 1 || k > QD_MAX_K) return fail(QD_ERR_INVALID, "k=%u outside 1..%d", k, QD_MAX_K);
     if (order != QD_ORDER_BEST_FIRST && order != QD_ORDER_DEPTH_FIRST)
@@ -363,6 +361,8 @@ int knn_tree_impl(qd_tree_t t, const uint64_t *d_q, uint32_t nq, uint32_t k, int
     char *ws = nullptr;
     QD_HIP_CHECK(hipMallocAsync((void **)&ws, head + prev_bytes + pool_bytes, s));
     QD_HIP_CHECK(hipMemsetAsync(ws, 0, head, s));
+    if (d_trace && n_traced)
+        QD_HIP_CHECK(hipMemsetAsync(d_trace, 0, (size_t)nq * ((n_traced + 31) / 32) * 4, s));
     uint32_t *counter = reinterpret_cast<uint32_t *>(ws);
     unsigned long long *gstats = reinterpret_cast<unsigned long long *>(ws + 64);
     uint32_t *chunk_prev = reinterpret_cast<uint32_t *>(ws + head);
@@ -375,11 +375,11 @@ int knn_tree_impl(qd_tree_t t, const uint64_t *d_q, uint32_t nq, uint32_t k, int
         if (order == QD_ORDER_BEST_FIRST)
             hipLaunchKernelGGL(tree_knn_kernel<true>, dim3((uint32_t)blocks), dim3(kBlock), 0, s, T,
                                reinterpret_cast<const uint4 *>(d_q), nq, k, counter, pool, chunk_prev, pool_chunks, S,
-                               d_idx, d_missed, d_extra, d_dist, d_qstats, gstats);
+                               d_idx, d_missed, d_extra, d_dist, d_qstats, gstats, d_trace, n_traced);
         else
             hipLaunchKernelGGL(tree_knn_kernel<false>, dim3((uint32_t)blocks), dim3(kBlock), 0, s, T,
                                reinterpret_cast<const uint4 *>(d_q), nq, k, counter, pool, chunk_prev, pool_chunks, S,
-                               d_idx, d_missed, d_extra, d_dist, d_qstats, gstats);
+                               d_idx, d_missed, d_extra, d_dist, d_qstats, gstats, d_trace, n_traced);
     }
     hipError_t e = hipGetLastError();
     if (e == hipSuccess && h_stats) {
@@ -406,5 +406,5 @@ extern "C" int qd_knn_tree(qd_tree_t t, const uint64_t *d_q, uint32_t nq, uint32
     if (sc && order != QD_ORDER_DEPTH_FIRST)
         return qd::fail(QD_ERR_INVALID, "node scores order the depth-first frontier only");
     return qd::knn_tree_impl(t, d_q, nq, k, order, sc, ns, d_idx, d_missed, d_extra, d_dist, d_query_stats, h_stats,
-                             stream, wpc);
+                             stream, wpc, p ? p->d_visited : nullptr, p ? p->n_traced : 0);
 }
