@@ -11,7 +11,10 @@
 // x is binary and shared by every node scored for that query, u_q = b1 +
 // sum over the query's set bits of the W1q rows is formed once per query (a
 // gather-add); a pair then costs u_q + f W1f (32 x 256), the 256 x 256 layer
-// as a BF16 MFMA GEMM over a batch of pairs, and the 256-wide head.
+// as a BF16 MFMA GEMM over a batch of pairs, and the 256-wide head.  The
+// layer-1 activations enter that GEMM as two BF16 terms (hi + lo, with lo the
+// rounding residual), i.e. one GEMM of depth 512 against W2 stacked twice, so
+// only the weights are rounded to BF16.
 // Training (binary cross-entropy on the logit, mean over pairs) runs the same
 // kernels backwards; every reduction has a fixed order, so gradients are
 // reproducible bit for bit.  Parameters are FP32 masters with Adam moments;
@@ -31,6 +34,7 @@ struct qd_model_s {
     float *m = nullptr;      // Adam first moments
     float *v = nullptr;      // Adam second moments
     uint16_t *w = nullptr;   // bf16 copy of p (same layout)
+    uint16_t *w2x2 = nullptr;  // bf16 W2 stacked twice (512 x 256): the layer-2 operand for hi/lo activations
     uint64_t step = 0;
 };
 
@@ -71,7 +75,7 @@ __device__ __forceinline__ uint16_t f2bf(float f) {
 template <bool TA, bool TB>
 __global__ __launch_bounds__(kBlock) void gemm_bf16_kernel(const uint16_t *__restrict__ A,
                                                            const uint16_t *__restrict__ B, float *__restrict__ C,
-                                                           int K, int lda, int ldb, int ldc) {
+                                                           int K, int lda, int ldb, int ldc, int accumulate) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int m0 = blockIdx.y * 64 + (w >> 1) * 32, n0 = blockIdx.x * 64 + (w & 1) * 32;
     const int li = lane & 15, lk = (lane >> 4) * 8;
@@ -116,7 +120,10 @@ __global__ __launch_bounds__(kBlock) void gemm_bf16_kernel(const uint16_t *__res
         for (int b = 0; b < 2; b++)
 #pragma unroll
             for (int r = 0; r < 4; r++)
-                C[(size_t)(m0 + 16 * a + 4 * (lane >> 4) + r) * ldc + n0 + 16 * b + li] = acc[a][b][r];
+            {
+                float *c = C + (size_t)(m0 + 16 * a + 4 * (lane >> 4) + r) * ldc + n0 + 16 * b + li;
+                *c = accumulate ? *c + acc[a][b][r] : acc[a][b][r];
+            }
 }
 
 // ---------------------------------------------------------------------------
@@ -226,7 +233,8 @@ __global__ __launch_bounds__(kBlock) void uq_kernel(const uint64_t *__restrict__
     u[(size_t)blockIdx.x * H + t] = acc;
 }
 
-// h1[p][j] = bf16(ReLU(u[q(p) - q0][j] + sum_f feat[p][f] W1f[f][j])); rows
+// h = ReLU(u[q(p) - q0][j] + sum_f feat[p][f] W1f[f][j]) stored as two bf16
+// terms: h1[p][j] = bf16(h), h1[p][256 + j] = bf16(h - bf16(h)).  Rows
 // p >= n_pairs (padding up to the GEMM tile) are zero.
 __global__ __launch_bounds__(kBlock) void layer1_kernel(const float *__restrict__ u, PairIdx P, uint32_t q0,
                                                         const float *__restrict__ feat, uint64_t n_pairs,
@@ -234,14 +242,18 @@ __global__ __launch_bounds__(kBlock) void layer1_kernel(const float *__restrict_
     const uint64_t p = blockIdx.x;
     const int j = threadIdx.x;
     if (p >= n_pairs) {
-        h1[p * H + j] = 0;
+        h1[p * 2 * H + j] = 0;
+        h1[p * 2 * H + H + j] = 0;
         return;
     }
     const float *f = feat + p * NF;
     float z = u[(size_t)(P.q(p) - q0) * H + j];
 #pragma unroll 8
     for (int i = 0; i < NF; i++) z += f[i] * bf2f(w[OFF_W1F + (size_t)i * H + j]);
-    h1[p * H + j] = f2bf(z > 0.f ? z : 0.f);
+    const float h = z > 0.f ? z : 0.f;
+    const uint16_t hi = f2bf(h);
+    h1[p * 2 * H + j] = hi;
+    h1[p * 2 * H + H + j] = f2bf(h - bf2f(hi));
 }
 
 // s[p] = b3 + sum_j w3[j] ReLU(z2[p][j] + b2[j]); one wave per pair.  With
@@ -332,7 +344,7 @@ __global__ __launch_bounds__(kBlock) void layer1_grad_kernel(const float *__rest
     for (uint32_t qi = 0; qi < nq; qi++) {
         float su = 0.f;
         for (uint64_t p = qoff[qi] - qoff_base; p < qoff[qi + 1] - qoff_base; p++) {
-            const float dz = bf2f(h1[p * H + j]) > 0.f ? dh1[p * H + j] : 0.f;
+            const float dz = bf2f(h1[p * 2 * H + j]) > 0.f ? dh1[p * H + j] : 0.f;
             su += dz;
 #pragma unroll
             for (int i = 0; i < NF; i++) gf[i] += feat[p * NF + i] * dz;
@@ -393,19 +405,32 @@ __global__ __launch_bounds__(kBlock) void scatter_scores_kernel(const float *__r
 inline uint64_t pad64(uint64_t x) { return (x + 63) / 64 * 64; }
 
 void gemm(hipStream_t s, bool ta, bool tb, const uint16_t *A, const uint16_t *B, float *C, int M, int N, int K,
-          int lda, int ldb, int ldc) {
+          int lda, int ldb, int ldc, int accumulate = 0) {
     dim3 grid(N / 64, M / 64);
-    if (!ta && !tb) hipLaunchKernelGGL((gemm_bf16_kernel<false, false>), grid, dim3(kBlock), 0, s, A, B, C, K, lda, ldb, ldc);
-    if (!ta && tb) hipLaunchKernelGGL((gemm_bf16_kernel<false, true>), grid, dim3(kBlock), 0, s, A, B, C, K, lda, ldb, ldc);
-    if (ta && !tb) hipLaunchKernelGGL((gemm_bf16_kernel<true, false>), grid, dim3(kBlock), 0, s, A, B, C, K, lda, ldb, ldc);
-    if (ta && tb) hipLaunchKernelGGL((gemm_bf16_kernel<true, true>), grid, dim3(kBlock), 0, s, A, B, C, K, lda, ldb, ldc);
+    if (!ta && !tb)
+        hipLaunchKernelGGL((gemm_bf16_kernel<false, false>), grid, dim3(kBlock), 0, s, A, B, C, K, lda, ldb, ldc, accumulate);
+    if (!ta && tb)
+        hipLaunchKernelGGL((gemm_bf16_kernel<false, true>), grid, dim3(kBlock), 0, s, A, B, C, K, lda, ldb, ldc, accumulate);
+    if (ta && !tb)
+        hipLaunchKernelGGL((gemm_bf16_kernel<true, false>), grid, dim3(kBlock), 0, s, A, B, C, K, lda, ldb, ldc, accumulate);
+    if (ta && tb)
+        hipLaunchKernelGGL((gemm_bf16_kernel<true, true>), grid, dim3(kBlock), 0, s, A, B, C, K, lda, ldb, ldc, accumulate);
+}
+
+// w2x2 = [W2; W2] in bf16
+__global__ __launch_bounds__(kBlock) void stack_w2_kernel(const uint16_t *__restrict__ w, uint16_t *__restrict__ w2x2) {
+    const size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < (size_t)H * H) {
+        w2x2[i] = w[OFF_W2 + i];
+        w2x2[(size_t)H * H + i] = w[OFF_W2 + i];
+    }
 }
 
 // Forward of one chunk of pairs (and, with labels, the gradients).
 // Scratch layout per chunk of P (padded to 64) pairs is allocated by the caller.
 struct Scratch {
     float *u = nullptr;     // nq_chunk x H
-    uint16_t *h1 = nullptr; // P x H
+    uint16_t *h1 = nullptr; // P x 2H (hi, lo)
     float *z2 = nullptr;    // P x H   (also dh1 in the backward pass)
     float *s = nullptr;     // P
     float *h2 = nullptr;    // P x H   (training)
@@ -432,7 +457,8 @@ extern "C" int qd_model_create(const float *d_params, void *stream, qd_model_t *
     qd_model_s *m = new qd_model_s();
     const size_t n = QD_MLP_NPARAMS;
     if (hipMalloc((void **)&m->p, n * 4) != hipSuccess || hipMalloc((void **)&m->m, n * 4) != hipSuccess ||
-        hipMalloc((void **)&m->v, n * 4) != hipSuccess || hipMalloc((void **)&m->w, n * 2) != hipSuccess) {
+        hipMalloc((void **)&m->v, n * 4) != hipSuccess || hipMalloc((void **)&m->w, n * 2) != hipSuccess ||
+        hipMalloc((void **)&m->w2x2, (size_t)2 * H * H * 2) != hipSuccess) {
         qd_model_free(m);
         return fail(QD_ERR_OOM, "model allocation failed");
     }
@@ -441,6 +467,7 @@ extern "C" int qd_model_create(const float *d_params, void *stream, qd_model_t *
     QD_HIP_CHECK(hipMemsetAsync(m->m, 0, n * 4, s));
     QD_HIP_CHECK(hipMemsetAsync(m->v, 0, n * 4, s));
     hipLaunchKernelGGL(to_bf16_kernel, dim3(1024), dim3(kBlock), 0, s, m->p, m->w, n);
+    hipLaunchKernelGGL(stack_w2_kernel, dim3(H * H / kBlock), dim3(kBlock), 0, s, m->w, m->w2x2);
     QD_HIP_CHECK(hipGetLastError());
     QD_HIP_CHECK(hipStreamSynchronize(s));
     *out = m;
@@ -449,7 +476,7 @@ extern "C" int qd_model_create(const float *d_params, void *stream, qd_model_t *
 
 extern "C" int qd_model_free(qd_model_t m) {
     if (!m) return QD_OK;
-    void *ptrs[] = {m->p, m->m, m->v, m->w};
+    void *ptrs[] = {m->p, m->m, m->v, m->w, m->w2x2};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     delete m;
@@ -493,7 +520,7 @@ static int mlp_run(qd_model_t m, const uint64_t *d_q, uint32_t q0, uint32_t nq, 
     using namespace qd;
     const uint64_t np = pad64(n_pairs ? n_pairs : 1);
     const bool train = y != nullptr;
-    size_t bytes = (size_t)nq * H * 4 + np * H * 2 + np * H * 4 + np * 4;
+    size_t bytes = (size_t)nq * H * 4 + np * H * 4 + np * H * 4 + np * 4;
     if (train) bytes += np * H * 4 + np * 4 + np * 4 + np * H * 2 + (size_t)H * H * 4 + (size_t)nq * H * 4;
     char *ws = nullptr;
     QD_HIP_CHECK(hipMallocAsync((void **)&ws, bytes + 64 * 16, s));
@@ -505,7 +532,7 @@ static int mlp_run(qd_model_t m, const uint64_t *d_q, uint32_t q0, uint32_t nq, 
     };
     Scratch S;
     S.u = (float *)take((size_t)nq * H * 4);
-    S.h1 = (uint16_t *)take(np * H * 2);
+    S.h1 = (uint16_t *)take(np * H * 4);
     S.z2 = (float *)take(np * H * 4);
     S.s = (float *)take(np * 4);
     if (train) {
@@ -521,7 +548,7 @@ static int mlp_run(qd_model_t m, const uint64_t *d_q, uint32_t q0, uint32_t nq, 
         hipLaunchKernelGGL(uq_kernel, dim3(nq), dim3(kBlock), 0, s, d_q, q0, m->w, S.u);
         hipLaunchKernelGGL(layer1_kernel, dim3((uint32_t)np), dim3(kBlock), 0, s, S.u, P, q0, d_feat, n_pairs, m->w,
                            S.h1);
-        gemm(s, false, false, S.h1, m->w + OFF_W2, S.z2, (int)np, H, H, H, H, H);
+        gemm(s, false, false, S.h1, m->w2x2, S.z2, (int)np, H, 2 * H, 2 * H, H, H);
         hipLaunchKernelGGL(head_kernel, dim3((uint32_t)(np / 4)), dim3(kBlock), 0, s, S.z2, n_pairs, m->w, y,
                            d_scores ? d_scores : S.s, S.h2, S.ds, S.lossv, S.d2, np);
     }
@@ -530,8 +557,9 @@ static int mlp_run(qd_model_t m, const uint64_t *d_q, uint32_t q0, uint32_t nq, 
         KernelTimer timer("mlp_backward", s);
         hipLaunchKernelGGL(head_grad_kernel, dim3(1), dim3(kBlock), 0, s, S.h2, S.ds, S.lossv, n_pairs, m->w, d_grads,
                            d_loss);
-        // dW2 = h1^T d2 ; dh1 = d2 W2^T (into z2's buffer)
-        gemm(s, true, false, S.h1, S.d2, S.dw2, H, H, (int)np, H, H, H);
+        // dW2 = (h1_hi + h1_lo)^T d2 ; dh1 = d2 W2^T (into z2's buffer)
+        gemm(s, true, false, S.h1, S.d2, S.dw2, H, H, (int)np, 2 * H, H, H);
+        gemm(s, true, false, S.h1 + H, S.d2, S.dw2, H, H, (int)np, 2 * H, H, H, 1);
         gemm(s, false, true, S.d2, m->w + OFF_W2, S.z2, (int)np, H, H, H, H, H);
         hipLaunchKernelGGL(copy_grad_w2_kernel, dim3(H * H / kBlock), dim3(kBlock), 0, s, S.dw2, d_grads);
         hipLaunchKernelGGL(layer1_grad_kernel, dim3(1), dim3(kBlock), 0, s, S.z2, S.h1, d_feat, d_qoff, qoff_base, nq,
@@ -574,6 +602,7 @@ extern "C" int qd_model_adam_step(qd_model_t m, const float *d_grads, float lr, 
     const float c1 = 1.f - powf(b1, (float)m->step), c2 = 1.f - powf(b2, (float)m->step);
     hipLaunchKernelGGL(adam_kernel, dim3(1024), dim3(kBlock), 0, (hipStream_t)stream, m->p, m->m, m->v, m->w,
                        d_grads, (size_t)QD_MLP_NPARAMS, lr, b1, b2, 1e-8f, c1, c2);
+    hipLaunchKernelGGL(stack_w2_kernel, dim3(H * H / kBlock), dim3(kBlock), 0, (hipStream_t)stream, m->w, m->w2x2);
     QD_HIP_CHECK(hipGetLastError());
     return QD_OK;
 }
