@@ -36,6 +36,9 @@ CUS, SIMDS, LANES, CLOCK_GHZ = 256, 4, 16, 2.4
 VALU_PEAK_TOPS = CUS * SIMDS * LANES * CLOCK_GHZ / 1000.0  # 32-bit lane ops: 39.3 T/s
 OPS_PER_PAIR = 256  # 128 x (AND + BCNT) over 4096 bits
 ROW_BYTES = 512
+# frontier-order model: trained on the 1M database's traces, scores the top
+# N_SCORED nodes (depth <= 10) of the searched tree
+TRAIN_QUERIES, TRAIN_BATCH, TRAIN_EPOCHS, TRAIN_LR, N_SCORED = 1024, 16, 4, 1e-3, 2047
 
 
 def log(*a):
@@ -75,6 +78,8 @@ def main():
     wanted = args.paths.split(",")
     paths["brute"] = lambda: qd.knn_bruteforce(dbt, qt, k)
     tree = None
+    train = None
+    build_s = None
     if ("tree" in wanted or "learned" in wanted) and hasattr(qd, "tree_build"):
         t0 = time.time()
         tree = qd.tree_build(dbt)
@@ -84,6 +89,29 @@ def main():
         if "tree" in wanted:
             paths["tree"] = lambda: qd.knn_tree(tree, qt, k)
             paths["tree_dfs"] = lambda: qd.knn_tree(tree, qt, k, order=qd.ORDER_DEPTH_FIRST)
+        if "learned" in wanted:
+            # offline: train the frontier-order model on traces of the exact search over
+            # the 1M-descriptor database (seed 1001) with its own queries
+            t0 = time.time()
+            tdb = synth.gen_db(1_000_000, 1001)
+            tq, _ = synth.gen_queries(tdb, TRAIN_QUERIES, 2001, 0.1, 0.6)
+            ttree = qd.tree_build(torch.from_numpy(tdb.view(np.int64)).to(dev))
+            model = qd.Model(torch.from_numpy(synth.uniform_f32(qd.MLP_NPARAMS, 3003, -0.05, 0.05)).to(dev))
+            nb = (TRAIN_QUERIES + TRAIN_BATCH - 1) // TRAIN_BATCH
+            order = synth.permutation(nb, 3004)
+            losses, npairs = qd.model_train(model, ttree, torch.from_numpy(tq.view(np.int64)).to(dev), k, N_SCORED,
+                                            TRAIN_EPOCHS, TRAIN_BATCH, TRAIN_LR, batch_order=order)
+            train = {"seconds": time.time() - t0, "pairs": npairs, "epochs": TRAIN_EPOCHS,
+                     "loss_first": float(np.nanmean(losses[:nb])), "loss_last": float(np.nanmean(losses[-nb:]))}
+            del ttree, tdb
+            log(f"order model trained on {npairs} traced pairs in {train['seconds']:.1f}s, loss "
+                f"{train['loss_first']:.4f} -> {train['loss_last']:.4f}")
+            n_scored = min(N_SCORED, tree.n_nodes)
+
+            def learned():
+                sc = qd.model_score_tree(model, tree, qt, n_scored)
+                return qd.knn_tree(tree, qt, k, order=qd.ORDER_DEPTH_FIRST, scores=sc)
+            paths["tree_learned"] = learned
 
     # reference result for the cross-path exactness check (outside timing)
     ref = [x.cpu() for x in paths["brute"]()]
@@ -106,12 +134,18 @@ def main():
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / args.steps
         kernels = {}
-        for kname in ("wh_scan_topk", "topk_merge", "tree_knn"):
+        for kname in ("wh_scan_topk", "topk_merge", "tree_knn", "mlp_features", "mlp_forward"):
             ms, cnt = qd.profile_read(kname)
             if cnt:
                 kernels[kname] = {"avg_ms": ms / cnt, "launches": cnt}
         qd.profile_enable(False)
         per_path[name] = {"ms": dt * 1e3, "queries_per_s": nq / dt, "kernels": kernels}
+        if name.startswith("tree"):
+            st = (qd.knn_tree(tree, qt, k, totals=True) if name == "tree" else
+                  qd.knn_tree(tree, qt, k, order=qd.ORDER_DEPTH_FIRST, totals=True,
+                              scores=qd.model_score_tree(model, tree, qt, n_scored) if name == "tree_learned"
+                              else None))[-1]
+            per_path[name]["per_query"] = {kk: v / nq for kk, v in st.items()}
         log(f"{name}: {dt * 1e3:.2f} ms/batch, {nq / dt:.0f} q/s, kernels {kernels}")
 
     # small-batch scan: HBM-bound regime (one pass over the rows serves <= 8 queries)
@@ -162,6 +196,8 @@ def main():
         "config": {"workload": f"{args.workload}: {n} descriptors x {nq} queries, k={k}", "n": n, "queries": nq,
                    "k": k, "value_path": best},
         "paths": per_path,
+        "tree_build_s": build_s,
+        "order_model_training": train,
         "brute_small_batch_hbm": hbm,
         "recall_source_row_at_1": recall,
         "roofline": roofline,
