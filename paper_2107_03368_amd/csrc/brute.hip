@@ -209,6 +209,26 @@ static BruteShape brute_shape(uint64_t n, uint32_t nq, uint32_t qt_force, uint32
     return sh;
 }
 
+int knn_bruteforce_mfma(const uint64_t *d_db, uint64_t n, const uint64_t *d_q, uint32_t nq, uint32_t k,
+                        uint32_t *d_idx, int32_t *d_missed, int32_t *d_extra, float *d_dist, void *stream);
+
+int popcount_rows_launch(const uint64_t *d_db, uint64_t n, uint16_t *d_pop, hipStream_t s) {
+    if (n == 0) return QD_OK;
+    uint64_t waves = (n + kRowsPerStep - 1) / kRowsPerStep;
+    uint64_t blocks = (waves + kWavesPerBlock - 1) / kWavesPerBlock;
+    const uint64_t cap = (uint64_t)device_cus() * 32;
+    if (blocks > cap) blocks = cap;
+    hipLaunchKernelGGL(popcount_rows_kernel, dim3((uint32_t)blocks), dim3(kBlock), 0, s,
+                       reinterpret_cast<const uint4 *>(d_db), n, d_pop);
+    QD_HIP_CHECK(hipGetLastError());
+    return QD_OK;
+}
+
+// Batches of at least this many queries over at least kMfmaMinRows rows use
+// the matrix-core path (the overlap counts are then a dense contraction).
+constexpr uint32_t kMfmaMinQueries = 512;
+constexpr uint64_t kMfmaMinRows = 1u << 16;
+
 int knn_bruteforce_impl(const uint64_t *d_db, uint64_t n, const uint64_t *d_q, uint32_t nq, uint32_t k,
                         uint32_t *d_idx, int32_t *d_missed, int32_t *d_extra, float *d_dist, void *stream,
                         uint32_t qt_force, uint32_t parts_force) {
@@ -219,6 +239,11 @@ int knn_bruteforce_impl(const uint64_t *d_db, uint64_t n, const uint64_t *d_q, u
     if (!aligned16(d_db) || !aligned16(d_q)) return fail(QD_ERR_INVALID, "descriptor arrays must be 16-byte aligned");
     if (qt_force && qt_force != 1 && qt_force != 2 && qt_force != 4 && qt_force != 8 && qt_force != 16)
         return fail(QD_ERR_INVALID, "query tile %u not in {1,2,4,8,16}", qt_force);
+    if (qt_force == 0 && parts_force == 0 && nq >= kMfmaMinQueries && n >= kMfmaMinRows) {
+        const int rc = knn_bruteforce_mfma(d_db, n, d_q, nq, k, d_idx, d_missed, d_extra, d_dist, stream);
+        if (rc != QD_ERR_UNSUPPORTED) return rc;
+        clear_error();
+    }
     hipStream_t s = (hipStream_t)stream;
     const BruteShape sh = brute_shape(n, nq, qt_force, parts_force);
     const uint64_t blocks_per_tile = (sh.n_parts + kWavesPerBlock - 1) / kWavesPerBlock;
@@ -260,14 +285,7 @@ extern "C" int qd_popcount_rows(const uint64_t *d_db, uint64_t n, uint16_t *d_po
     if (n == 0) return QD_OK;
     if (!d_db || !d_pop) return fail(QD_ERR_INVALID, "null pointer");
     if (!aligned16(d_db)) return fail(QD_ERR_INVALID, "descriptor array must be 16-byte aligned");
-    uint64_t waves = (n + kRowsPerStep - 1) / kRowsPerStep;
-    uint64_t blocks = (waves + kWavesPerBlock - 1) / kWavesPerBlock;
-    const uint64_t cap = (uint64_t)device_cus() * 32;
-    if (blocks > cap) blocks = cap;
-    hipLaunchKernelGGL(popcount_rows_kernel, dim3((uint32_t)blocks), dim3(kBlock), 0, (hipStream_t)stream,
-                       reinterpret_cast<const uint4 *>(d_db), n, d_pop);
-    QD_HIP_CHECK(hipGetLastError());
-    return QD_OK;
+    return popcount_rows_launch(d_db, n, d_pop, (hipStream_t)stream);
 }
 
 extern "C" int qd_knn_bruteforce(const uint64_t *d_db, uint64_t n, const uint64_t *d_q, uint32_t nq, uint32_t k,

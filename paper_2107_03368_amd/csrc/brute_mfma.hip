@@ -1,0 +1,306 @@
+// Large-batch sequential search on the matrix cores.
+//
+// For many queries the overlap counts C[q][t] = popcount(q AND t) of Eq. 1
+// form a dense {0,1} matrix product C = Q T^T over the 4096 bit positions, so
+// they are computed with v_mfma_i32_16x16x64_i8 on bits unpacked to bytes.
+// A block of 4 waves owns 128 queries x 256 rows.  The K dimension is
+// streamed in chunks of 512 bits: packed chunks go global -> LDS, then for
+// each 64-bit step the whole block unpacks the step to bytes in LDS (one bit
+// per byte), and every wave multiplies its 64 x 128 quarter as 4 x 8 MFMA
+// tiles.  Lane l supplies A rows (l % 16) at k = 16*(l/16) .. +15 (16 bytes)
+// and B columns likewise, and receives C rows 4*(l/16) .. +3 of column l % 16.
+//
+// Selection: a first sequential search over a sample of the rows gives each
+// query an upper bound U_q on its k-th key (the sample's k-th key: those k
+// rows are candidates too).  The matrix pass keeps every (row, key) with
+// key <= U_q in a per-query candidate buffer; the exact top k are all among
+// them.  A final kernel sorts each query's candidates and writes the
+// results; queries whose buffer overflowed are searched again by the
+// register-tiled scan, so the result is exact in every case.
+#include <algorithm>
+#include <vector>
+
+#include "qd_device.h"
+#include "qd_internal.h"
+
+namespace qd {
+
+int knn_bruteforce_impl(const uint64_t *d_db, uint64_t n, const uint64_t *d_q, uint32_t nq, uint32_t k,
+                        uint32_t *d_idx, int32_t *d_missed, int32_t *d_extra, float *d_dist, void *stream,
+                        uint32_t qt_force, uint32_t parts_force);
+int popcount_rows_launch(const uint64_t *d_db, uint64_t n, uint16_t *d_pop, hipStream_t s);
+
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int MQ = 128;           // queries per block
+constexpr int MR = 256;           // rows per block
+constexpr int KCH = 512;          // bits per packed chunk (8 steps of 64)
+constexpr int CHB = KCH / 8;      // bytes per row per chunk (64)
+constexpr int UST = 80;           // unpacked row stride in LDS (64 bytes + 16 pad)
+constexpr uint32_t kCap = 8192;   // candidate slots per query
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+
+// 4 bits -> 4 bytes of 0/1 (bit e -> byte e): the multiplier places bit e at
+// bit 8e with no two terms overlapping, so no carries occur.
+__device__ __forceinline__ uint32_t spread4(uint32_t x) { return ((x & 0xFu) * 0x00204081u) & 0x01010101u; }
+
+__global__ __launch_bounds__(kBlock) void scan_mfma_kernel(const uint4 *__restrict__ db, uint64_t n,
+                                                           const uint4 *__restrict__ q, uint32_t nq,
+                                                           const uint16_t *__restrict__ tpop,
+                                                           const uint16_t *__restrict__ qpop,
+                                                           const u64 *__restrict__ thr, uint32_t n_qtiles,
+                                                           uint32_t *__restrict__ cnt, u64 *__restrict__ cand) {
+    __shared__ uint8_t pa[MQ * CHB];    // packed query chunk
+    __shared__ uint8_t pb[MR * CHB];    // packed row chunk
+    __shared__ uint8_t ua[MQ * UST];    // unpacked query step
+    __shared__ uint8_t ub[MR * UST];    // unpacked row step
+    const uint32_t qt = blockIdx.x % n_qtiles;
+    const uint64_t rt = blockIdx.x / n_qtiles;
+    const uint32_t q0 = qt * MQ;
+    const uint64_t t0 = rt * MR;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int wq = w >> 1, wr = w & 1;
+    const int li = lane & 15, lg = lane >> 4;
+
+    v4i acc[4][8];
+#pragma unroll
+    for (int a = 0; a < 4; a++)
+#pragma unroll
+        for (int b = 0; b < 8; b++) acc[a][b] = v4i{0, 0, 0, 0};
+
+    for (int c = 0; c < QD_BITS / KCH; c++) {
+        __syncthreads();  // previous chunk fully consumed
+        // packed chunk c: 64 bytes = 4 uint4 per row
+        for (int i = tid; i < (MQ + MR) * 4; i += kBlock) {
+            const int r = i >> 2, j = i & 3;
+            uint4 v = make_uint4(0, 0, 0, 0);
+            if (r < MQ) {
+                if (q0 + r < nq) v = q[(uint64_t)(q0 + r) * 32 + c * 4 + j];
+                *reinterpret_cast<uint4 *>(pa + r * CHB + j * 16) = v;
+            } else {
+                const uint64_t t = t0 + (r - MQ);
+                if (t < n) v = db[t * 32 + c * 4 + j];
+                *reinterpret_cast<uint4 *>(pb + (r - MQ) * CHB + j * 16) = v;
+            }
+        }
+        for (int s = 0; s < KCH / 64; s++) {
+            __syncthreads();  // packed chunk ready; previous step's MFMAs done
+            // unpack 64-bit step s: item = (row, 16-bit segment)
+            for (int i = tid; i < (MQ + MR) * 4; i += kBlock) {
+                const int r = i >> 2, g = i & 3;
+                const uint8_t *src = r < MQ ? pa + r * CHB : pb + (r - MQ) * CHB;
+                const uint32_t bits = *reinterpret_cast<const uint16_t *>(src + s * 8 + g * 2);
+                uint4 o = make_uint4(spread4(bits), spread4(bits >> 4), spread4(bits >> 8), spread4(bits >> 12));
+                uint8_t *dst = r < MQ ? ua + r * UST : ub + (r - MQ) * UST;
+                *reinterpret_cast<uint4 *>(dst + g * 16) = o;
+            }
+            __syncthreads();
+            v4i af[4], bf[8];
+#pragma unroll
+            for (int a = 0; a < 4; a++)
+                af[a] = *reinterpret_cast<const v4i *>(ua + (wq * 64 + a * 16 + li) * UST + lg * 16);
+#pragma unroll
+            for (int b = 0; b < 8; b++)
+                bf[b] = *reinterpret_cast<const v4i *>(ub + (wr * 128 + b * 16 + li) * UST + lg * 16);
+#pragma unroll
+            for (int a = 0; a < 4; a++)
+#pragma unroll
+                for (int b = 0; b < 8; b++)
+                    acc[a][b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(af[a], bf[b], acc[a][b], 0, 0, 0);
+        }
+    }
+
+    // epilogue: keys of this lane's 16 queries x 8 rows
+#pragma unroll
+    for (int a = 0; a < 4; a++)
+#pragma unroll
+        for (int r = 0; r < 4; r++) {
+            const uint32_t qi = q0 + wq * 64 + a * 16 + lg * 4 + r;
+            if (qi >= nq) continue;
+            const uint32_t pq = qpop[qi];
+            const uint32_t wa = pq > 1 ? pq : 1, wb = (QD_BITS - pq) > 1 ? QD_BITS - pq : 1;
+            const u64 th = thr[qi];
+#pragma unroll
+            for (int b = 0; b < 8; b++) {
+                const uint64_t t = t0 + wr * 128 + b * 16 + li;
+                if (t >= n) continue;
+                const uint32_t C = (uint32_t)acc[a][b][r];
+                const uint32_t K = (pq - C) * wb + ((uint32_t)tpop[t] - C) * wa;
+                const u64 key = ((u64)K << 32) | (uint32_t)t;
+                if (key <= th) {
+                    const uint32_t pos = atomicAdd(&cnt[qi], 1u);
+                    if (pos < kCap) cand[(uint64_t)qi * kCap + pos] = key;
+                }
+            }
+        }
+}
+
+// One block per query: sort the candidates (<= kCap), write the first k.
+// Overflowed queries are left for the fallback and flagged in `redo`.
+__global__ __launch_bounds__(kBlock) void select_emit_kernel(const uint32_t *__restrict__ cnt,
+                                                             const u64 *__restrict__ cand, uint32_t k,
+                                                             const uint64_t *__restrict__ q,
+                                                             const uint64_t *__restrict__ db, uint32_t *idx,
+                                                             int32_t *missed, int32_t *extra, float *dist,
+                                                             uint32_t *redo, uint32_t *n_redo) {
+    __shared__ u64 keys[kCap];
+    const uint32_t qi = blockIdx.x;
+    const uint32_t m = cnt[qi];
+    if (m > kCap) {
+        if (threadIdx.x == 0) redo[atomicAdd(n_redo, 1u)] = qi;
+        return;
+    }
+    const uint32_t np = next_pow2(m < 2 ? 2 : m);
+    for (uint32_t i = threadIdx.x; i < np; i += kBlock) keys[i] = i < m ? cand[(uint64_t)qi * kCap + i] : KEY_NONE;
+    __syncthreads();
+    block_bitonic_sort(keys, np);
+    if (threadIdx.x < k) {
+        const uint32_t r = threadIdx.x;
+        const uint64_t o = (uint64_t)qi * k + r;
+        const u64 e = r < m ? keys[r] : KEY_NONE;
+        if (e == KEY_NONE) {
+            idx[o] = QD_PAD_IDX;
+            missed[o] = -1;
+            extra[o] = -1;
+            dist[o] = __builtin_inff();
+        } else {
+            const uint32_t row = (uint32_t)e;
+            const uint64_t *qq = q + (uint64_t)qi * QD_WORDS;
+            const uint64_t *tt = db + (uint64_t)row * QD_WORDS;
+            uint32_t a = 0, b = 0, pqv = 0;
+            for (int w = 0; w < QD_WORDS; w++) {
+                const uint64_t x = qq[w], y = tt[w];
+                a += __popcll(x & ~y);
+                b += __popcll(~x & y);
+                pqv += __popcll(x);
+            }
+            const uint32_t wav = pqv > 1 ? pqv : 1;
+            const uint32_t wbv = (QD_BITS - pqv) > 1 ? QD_BITS - pqv : 1;
+            idx[o] = row;
+            missed[o] = (int32_t)a;
+            extra[o] = (int32_t)b;
+            dist[o] = (float)((double)(a * wbv + b * wav) / ((double)wav * (double)wbv));
+        }
+    }
+}
+
+// thr[q] = the k-th sample key, from the sample search's outputs
+__global__ void sample_threshold_kernel(const uint32_t *__restrict__ idx, const int32_t *__restrict__ missed,
+                                        const int32_t *__restrict__ extra, const uint16_t *__restrict__ qpop,
+                                        uint32_t nq, uint32_t k, u64 *__restrict__ thr) {
+    const uint32_t qi = blockIdx.x * blockDim.x + threadIdx.x;
+    if (qi >= nq) return;
+    const uint64_t o = (uint64_t)qi * k + (k - 1);
+    const uint32_t pq = qpop[qi];
+    const uint32_t wa = pq > 1 ? pq : 1, wb = (QD_BITS - pq) > 1 ? QD_BITS - pq : 1;
+    thr[qi] = idx[o] == QD_PAD_IDX ? KEY_NONE
+                                   : ((u64)((uint32_t)missed[o] * wb + (uint32_t)extra[o] * wa) << 32) | idx[o];
+}
+
+__global__ void gather_queries_kernel(const uint4 *__restrict__ q, const uint32_t *__restrict__ list, uint32_t m,
+                                      uint4 *__restrict__ out) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < m * 32) out[i] = q[(uint64_t)list[i >> 5] * 32 + (i & 31)];
+}
+
+template <class T>
+__global__ void scatter_rows_kernel(const T *__restrict__ src, const uint32_t *__restrict__ list, uint32_t m,
+                                    uint32_t k, T *__restrict__ dst) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < m * k) dst[(uint64_t)list[i / k] * k + (i % k)] = src[i];
+}
+
+}  // namespace
+
+// Matrix-core path for large batches; returns QD_ERR_UNSUPPORTED when the
+// shape is not worth it (the caller then uses the register-tiled scan).
+int knn_bruteforce_mfma(const uint64_t *d_db, uint64_t n, const uint64_t *d_q, uint32_t nq, uint32_t k,
+                        uint32_t *d_idx, int32_t *d_missed, int32_t *d_extra, float *d_dist, void *stream) {
+    hipStream_t s = (hipStream_t)stream;
+    // sample: about k*n/1024 rows, so about 1,024 candidates per query are expected
+    uint64_t sample = std::max<uint64_t>((uint64_t)k * 64, (n * k + 1023) / 1024);
+    if (sample * 4 > n) return QD_ERR_UNSUPPORTED;
+    const uint32_t n_qtiles = (nq + MQ - 1) / MQ;
+    const uint64_t n_rtiles = (n + MR - 1) / MR;
+    if ((uint64_t)n_qtiles * n_rtiles > 0x7FFFFFFFull) return QD_ERR_UNSUPPORTED;
+    // scratch: tpop n*2 | qpop nq*2 | thr nq*8 | cnt nq*4 | cand nq*cap*8 | sample outputs nq*k*16 | redo nq*4+4
+    const size_t a_tpop = 0, a_qpop = a_tpop + (n * 2 + 255) / 256 * 256;
+    const size_t a_thr = a_qpop + ((size_t)nq * 2 + 255) / 256 * 256;
+    const size_t a_cnt = a_thr + (size_t)nq * 8;
+    const size_t a_cand = a_cnt + ((size_t)nq * 4 + 255) / 256 * 256;
+    const size_t a_smp = a_cand + (size_t)nq * kCap * 8;
+    const size_t a_redo = a_smp + (size_t)nq * k * 16;
+    const size_t bytes = a_redo + (size_t)nq * 4 + 256;
+    char *ws = nullptr;
+    QD_HIP_CHECK(hipMallocAsync((void **)&ws, bytes, s));
+    uint16_t *tpop = (uint16_t *)(ws + a_tpop), *qpop = (uint16_t *)(ws + a_qpop);
+    u64 *thr = (u64 *)(ws + a_thr);
+    uint32_t *cnt = (uint32_t *)(ws + a_cnt);
+    u64 *cand = (u64 *)(ws + a_cand);
+    uint32_t *sidx = (uint32_t *)(ws + a_smp);
+    int32_t *smis = (int32_t *)(sidx + (size_t)nq * k), *sext = smis + (size_t)nq * k;
+    float *sdist = (float *)(sext + (size_t)nq * k);
+    uint32_t *redo = (uint32_t *)(ws + a_redo);
+    uint32_t *n_redo = redo + nq;
+    auto done = [&](int rc) {
+        (void)hipFreeAsync(ws, s);
+        return rc;
+    };
+    int rc = popcount_rows_launch(d_db, n, tpop, s);
+    if (rc == QD_OK) rc = popcount_rows_launch(d_q, nq, qpop, s);
+    if (rc != QD_OK) return done(rc);
+    // thresholds from the first `sample` rows
+    rc = knn_bruteforce_impl(d_db, sample, d_q, nq, k, sidx, smis, sext, sdist, stream, 16, 0);  // register-tiled scan
+    if (rc != QD_OK) return done(rc);
+    hipLaunchKernelGGL(sample_threshold_kernel, dim3((nq + 255) / 256), dim3(256), 0, s, sidx, smis, sext, qpop, nq, k,
+                       thr);
+    if (hipMemsetAsync(cnt, 0, (size_t)nq * 4, s) != hipSuccess || hipMemsetAsync(n_redo, 0, 4, s) != hipSuccess)
+        return done(fail(QD_ERR_DEVICE, "memset"));
+    {
+        KernelTimer timer("wh_scan_mfma", s);
+        hipLaunchKernelGGL(scan_mfma_kernel, dim3((uint32_t)(n_qtiles * n_rtiles)), dim3(kBlock), 0, s,
+                           reinterpret_cast<const uint4 *>(d_db), n, reinterpret_cast<const uint4 *>(d_q), nq, tpop,
+                           qpop, thr, n_qtiles, cnt, cand);
+    }
+    {
+        KernelTimer timer("topk_select", s);
+        hipLaunchKernelGGL(select_emit_kernel, dim3(nq), dim3(kBlock), 0, s, cnt, cand, k, d_q, d_db, d_idx, d_missed,
+                           d_extra, d_dist, redo, n_redo);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return done(fail(QD_ERR_DEVICE, "matrix-core scan: %s", hipGetErrorString(e)));
+    // queries whose candidate buffer overflowed: search them again with the scan
+    uint32_t h_redo = 0;
+    e = hipMemcpyAsync(&h_redo, n_redo, 4, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return done(fail(QD_ERR_DEVICE, "overflow check: %s", hipGetErrorString(e)));
+    if (h_redo > 0) {
+        uint4 *gq = nullptr;
+        char *ro = nullptr;
+        if (hipMallocAsync((void **)&gq, (size_t)h_redo * 512, s) != hipSuccess ||
+            hipMallocAsync((void **)&ro, (size_t)h_redo * k * 16, s) != hipSuccess)
+            return done(fail(QD_ERR_OOM, "fallback scratch"));
+        hipLaunchKernelGGL(gather_queries_kernel, dim3((h_redo * 32 + 255) / 256), dim3(256), 0, s,
+                           reinterpret_cast<const uint4 *>(d_q), redo, h_redo, gq);
+        uint32_t *ri = (uint32_t *)ro;
+        int32_t *rm = (int32_t *)(ri + (size_t)h_redo * k), *rx = rm + (size_t)h_redo * k;
+        float *rd = (float *)(rx + (size_t)h_redo * k);
+        rc = knn_bruteforce_impl(d_db, n, reinterpret_cast<const uint64_t *>(gq), h_redo, k, ri, rm, rx, rd, stream, 16,
+                                 0);
+        if (rc == QD_OK) {
+            const dim3 g((h_redo * k + 255) / 256);
+            hipLaunchKernelGGL(scatter_rows_kernel<uint32_t>, g, dim3(256), 0, s, ri, redo, h_redo, k, d_idx);
+            hipLaunchKernelGGL(scatter_rows_kernel<int32_t>, g, dim3(256), 0, s, rm, redo, h_redo, k, d_missed);
+            hipLaunchKernelGGL(scatter_rows_kernel<int32_t>, g, dim3(256), 0, s, rx, redo, h_redo, k, d_extra);
+            hipLaunchKernelGGL(scatter_rows_kernel<float>, g, dim3(256), 0, s, rd, redo, h_redo, k, d_dist);
+            if (hipGetLastError() != hipSuccess) rc = fail(QD_ERR_DEVICE, "fallback scatter");
+        }
+        (void)hipFreeAsync(gq, s);
+        (void)hipFreeAsync(ro, s);
+    }
+    return done(rc);
+}
+
+}  // namespace qd

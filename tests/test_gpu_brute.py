@@ -93,3 +93,36 @@ def test_1m_workload_sampled_queries(qd, db_1m, k):
     rows = np.array([0, 1, 777, 2048, 4095])
     ref = oracle.knn_brute(db_1m, q[rows], k)
     _same(res, ref, rows)
+
+
+def test_matrix_core_path_equals_register_scan_and_oracle(qd):
+    # >= 512 queries over >= 65,536 rows take the int8-MFMA path by default;
+    # the register-tiled scan (an explicit query tile) must agree bit for bit
+    db = synth.gen_db(100_003, 1011)  # ragged against the 256-row tile
+    q, _ = synth.gen_queries(db, 600, 2011, 0.1, 0.6)  # ragged against the 128-query tile
+    for k in (1, 10, 50):
+        a = qd.knn_bruteforce(_t(db), _t(q), k)
+        b = qd.knn_bruteforce(_t(db), _t(q), k, query_tile=16)
+        for x, y in zip(a, b):
+            assert np.array_equal(x.cpu().numpy(), y.cpu().numpy())
+        rows = np.array([0, 127, 128, 599])
+        _same(a, oracle.knn_brute(db, q[rows], k), rows)
+
+
+def test_matrix_core_path_overflow_falls_back_exactly(qd):
+    # the sample rows (the first rows) hold only the image corners, which no ring
+    # arc reaches: every query misses all of its bits there and pays for ~900
+    # extra bits, so the sample's k-th key admits nearly every other row; every
+    # query overflows its candidate buffer and is searched again by the
+    # register-tiled scan
+    db = synth.gen_db(70_000, 1012)
+    rr, cc = np.meshgrid(np.arange(64), np.arange(64), indexing="ij")
+    corner = ((rr - 31.5) ** 2 + (cc - 31.5) ** 2 > 32.5 ** 2)
+    db[:8000] = synth.from_bits(1, [list(np.flatnonzero(corner.reshape(-1)))])[0]
+    q, _ = synth.gen_queries(db[8000:], 520, 2012, 0.1, 0.6)
+    a = qd.knn_bruteforce(_t(db), _t(q), 10)
+    b = qd.knn_bruteforce(_t(db), _t(q), 10, query_tile=16)
+    for x, y in zip(a, b):
+        assert np.array_equal(x.cpu().numpy(), y.cpu().numpy())
+    rows = np.array([0, 519])
+    _same(a, oracle.knn_brute(db, q[rows], 10), rows)
