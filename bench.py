@@ -134,7 +134,8 @@ def main():
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / args.steps
         kernels = {}
-        for kname in ("wh_scan_topk", "topk_merge", "tree_knn", "mlp_features", "mlp_forward"):
+        for kname in ("wh_scan_mfma", "wh_scan_topk", "topk_merge", "topk_select", "tree_knn", "mlp_features",
+                      "mlp_forward"):
             ms, cnt = qd.profile_read(kname)
             if cnt:
                 kernels[kname] = {"avg_ms": ms / cnt, "launches": cnt}
