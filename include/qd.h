@@ -292,6 +292,54 @@ int qd_model_train(qd_model_t m, qd_tree_t t, const uint64_t *d_q, uint32_t nq, 
                    uint32_t epochs, uint32_t batch_queries, float lr, const uint32_t *h_batch_order,
                    float *h_losses, uint64_t *h_n_pairs, void *stream);
 
+/* ---------------------------------------------------------------------------
+ * Batched retrieval plans (an extension: the paper runs query objects one
+ * descriptor at a time).  A plan fixes the search (tree t, or sequential
+ * search over d_db when t is NULL; params picks the tree frontier order and
+ * occupancy, query_tile the sequential scan's tile, 0 = 16), k, the vote
+ * threshold and the largest batch (max_qdesc descriptors in max_qobj query
+ * objects).  It allocates all its device memory at creation and records one
+ * batch -- the k-NN of every descriptor in one launch, then the votes -- into
+ * a hipGraph whose kernels read the batch size from device memory.
+ * qd_plan_run serves one batch exactly as qd_retrieve_objects would (same
+ * arguments and outputs): it copies the inputs into the plan, replays the
+ * graph on `stream` and copies the outputs out; it allocates nothing and never
+ * waits for the device.  Runs of one plan must not overlap (they share its
+ * buffers).  The plan keeps pointers to t, d_db and d_obj_of, which must
+ * outlive it.  The sequential search in a plan always uses the register-tiled
+ * scan (the matrix-core path needs a host decision per batch).
+ * ------------------------------------------------------------------------- */
+typedef struct qd_plan_s *qd_plan_t;
+
+int qd_plan_create(qd_tree_t t, const uint64_t *d_db, uint64_t n, const uint16_t *d_obj_of, uint32_t n_obj,
+                   uint64_t max_qdesc, uint32_t max_qobj, uint32_t k, uint32_t vote_threshold,
+                   const qd_search_params *params, uint32_t query_tile, qd_plan_t *out);
+int qd_plan_run(qd_plan_t p, const uint64_t *d_qdesc, uint64_t n_qdesc, const uint64_t *d_qoff, uint32_t nqo,
+                uint32_t *d_votes, int32_t *d_winner, uint32_t *d_used, void *stream);
+int qd_plan_free(qd_plan_t p);
+
+/* ---------------------------------------------------------------------------
+ * Autotuner: times every launch configuration of a k-NN batch (tree t:
+ * frontier order x waves per CU; sequential search: automatic path and query
+ * tiles 4, 8, 16) over `reps` runs after one warm-up on the caller's sample
+ * batch, and returns the fastest in *best (every configuration returns the
+ * same exact result).  With `all`, every candidate's timing is written too.
+ * Results are cached per (device, rows, nodes, nq, k) for the process, and in
+ * the file named by the environment variable QD_TUNE_CACHE when it is set (a
+ * cached entry is returned without timing unless `all` is requested).
+ * Synchronous.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+    int path;              /* 1 = tree search, 0 = sequential search */
+    qd_order order;        /* tree: frontier order */
+    uint32_t waves_per_cu; /* tree: occupancy (0 = default) */
+    uint32_t query_tile;   /* sequential: query tile (0 = automatic, matrix cores for large batches) */
+    float ms;              /* mean time of one batch */
+} qd_tuning;
+
+int qd_autotune(qd_tree_t t, const uint64_t *d_db, uint64_t n, const uint64_t *d_q, uint32_t nq, uint32_t k,
+                uint32_t reps, qd_tuning *best, qd_tuning *all, uint32_t max_all, uint32_t *n_all, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

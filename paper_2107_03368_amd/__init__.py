@@ -399,3 +399,75 @@ def model_train(model, tree, q, k, n_traced, epochs, batch_queries, lr, batch_or
                                lr, None if order is None else ctypes.c_void_p(order.ctypes.data),
                                ctypes.c_void_p(losses.ctypes.data), ctypes.byref(n), _stream()), "qd_model_train")
     return losses, n.value
+
+
+# ---------------------------------------------------------------------------
+# Batched retrieval plans (hipGraph) and the autotuner
+# ---------------------------------------------------------------------------
+class _Tuning(ctypes.Structure):
+    _fields_ = [("path", ctypes.c_int), ("order", ctypes.c_int), ("waves_per_cu", ctypes.c_uint32),
+                ("query_tile", ctypes.c_uint32), ("ms", ctypes.c_float)]
+
+    def as_dict(self):
+        return {"path": "tree" if self.path else "sequential", "order": self.order,
+                "waves_per_cu": self.waves_per_cu, "query_tile": self.query_tile, "ms": self.ms}
+
+
+_sig("qd_plan_create", [_P, _P, _U64, _P, _U32, _U64, _U32, _U32, _U32, ctypes.POINTER(_SearchParams), _U32,
+                        ctypes.POINTER(ctypes.c_void_p)])
+_sig("qd_plan_run", [_P, _P, _U64, _P, _U32, _P, _P, _P, _P])
+_sig("qd_plan_free", [_P])
+_sig("qd_autotune", [_P, _P, _U64, _P, _U32, _U32, _U32, ctypes.POINTER(_Tuning), ctypes.POINTER(_Tuning), _U32,
+                     ctypes.POINTER(ctypes.c_uint32), _P])
+
+
+class Plan:
+    """A retrieval plan: fixed capacities, buffers allocated once, one batch
+    recorded in a hipGraph and replayed per run."""
+
+    def __init__(self, obj_of, n_obj, max_qdesc, max_qobj, k, threshold=10, tree=None, db=None,
+                 order=ORDER_BEST_FIRST, waves_per_cu=0, query_tile=0):
+        if tree is None:
+            _desc(db, "db")
+        self._keep = (tree, db, obj_of)  # the plan points into these
+        prm = _SearchParams(order, None, 0, waves_per_cu, None, 0)
+        h = ctypes.c_void_p()
+        _check(_lib.qd_plan_create(tree.handle if tree is not None else None, _ptr(db),
+                                   0 if db is None else db.shape[0], _ptr(obj_of), n_obj, max_qdesc, max_qobj, k,
+                                   threshold, ctypes.byref(prm), query_tile, ctypes.byref(h)), "qd_plan_create")
+        self._h = h
+        self.n_obj = n_obj
+
+    def run(self, qdesc, qoff):
+        _desc(qdesc, "qdesc")
+        nqo = qoff.shape[0] - 1
+        dev = qdesc.device
+        votes = torch.empty((nqo, self.n_obj), dtype=torch.int32, device=dev)
+        winner = torch.empty(nqo, dtype=torch.int32, device=dev)
+        used = torch.empty(nqo, dtype=torch.int32, device=dev)
+        _check(_lib.qd_plan_run(self._h, _ptr(qdesc), qdesc.shape[0], _ptr(qoff), nqo, _ptr(votes), _ptr(winner),
+                                _ptr(used), _stream()), "qd_plan_run")
+        return votes, winner, used
+
+    def free(self):
+        if self._h is not None and self._h.value:
+            _lib.qd_plan_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def autotune(q, k, tree=None, db=None, reps=3, with_all=True):
+    """(best configuration, all candidates) for a k-NN batch; see qd_autotune."""
+    _desc(q, "q")
+    best = _Tuning()
+    all_ = (_Tuning * 16)()
+    n_all = ctypes.c_uint32()
+    _check(_lib.qd_autotune(tree.handle if tree is not None else None, _ptr(db), 0 if db is None else db.shape[0],
+                            _ptr(q), q.shape[0], k, reps, ctypes.byref(best), all_ if with_all else None, 16,
+                            ctypes.byref(n_all), _stream()), "qd_autotune")
+    return best.as_dict(), [all_[i].as_dict() for i in range(n_all.value)]

@@ -55,6 +55,8 @@ bool profiling() { return g_prof_on; }
 
 KernelTimer::KernelTimer(const char *name, hipStream_t s) : name_(name), s_(s) {
     if (!g_prof_on) return;
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s_, &cap) != hipSuccess || cap != hipStreamCaptureStatusNone) return;  // no events in graphs
     if (hipEventCreate(&a_) != hipSuccess || hipEventCreate(&b_) != hipSuccess) {
         a_ = b_ = nullptr;
         return;

@@ -14,6 +14,7 @@
 // query to the exact top k and writes the results.
 #include "qd_device.h"
 #include "qd_internal.h"
+#include "qd_launch.h"
 
 namespace qd {
 namespace {
@@ -28,7 +29,12 @@ template <int QT>
 __global__ __launch_bounds__(kBlock) void scan_topk_kernel(const uint4 *__restrict__ db, uint64_t n,
                                                            const uint4 *__restrict__ q, uint32_t nq, uint32_t k,
                                                            uint32_t n_qtiles, uint32_t n_parts,
-                                                           uint64_t rows_per_part, u64 *__restrict__ part) {
+                                                           uint64_t rows_per_part, u64 *__restrict__ part,
+                                                           const uint32_t *__restrict__ nq_dev) {
+    if (nq_dev) {
+        nq = *nq_dev;  // size given on the device (captured graphs)
+        if ((blockIdx.x % n_qtiles) * QT >= nq) return;  // whole block
+    }
     const int lane = lane_id();
     const int g = lane >> 3, j = lane & 7;
     const uint32_t qtile = blockIdx.x % n_qtiles;
@@ -99,7 +105,9 @@ __global__ __launch_bounds__(kBlock) void scan_topk_kernel(const uint4 *__restri
 __global__ __launch_bounds__(kBlock) void merge_emit_kernel(const u64 *__restrict__ part, uint32_t n_parts,
                                                             uint32_t k, const uint64_t *__restrict__ q,
                                                             const uint64_t *__restrict__ db, uint32_t *idx,
-                                                            int32_t *missed, int32_t *extra, float *dist) {
+                                                            int32_t *missed, int32_t *extra, float *dist,
+                                                            const uint32_t *__restrict__ nq_dev) {
+    if (nq_dev && blockIdx.x >= *nq_dev) return;  // whole block
     __shared__ u64 heads[kMaxParts];
     __shared__ u64 cand[kMaxCand];
     __shared__ uint32_t ncand;
@@ -175,24 +183,20 @@ __global__ __launch_bounds__(kBlock) void popcount_rows_kernel(const uint4 *__re
 
 template <int QT>
 void launch_scan(dim3 grid, hipStream_t s, const uint4 *db, uint64_t n, const uint4 *q, uint32_t nq, uint32_t k,
-                 uint32_t n_qtiles, uint32_t n_parts, uint64_t rpp, u64 *part) {
-    hipLaunchKernelGGL(scan_topk_kernel<QT>, grid, dim3(kBlock), 0, s, db, n, q, nq, k, n_qtiles, n_parts, rpp, part);
+                 uint32_t n_qtiles, uint32_t n_parts, uint64_t rpp, u64 *part, const uint32_t *nq_dev) {
+    hipLaunchKernelGGL(scan_topk_kernel<QT>, grid, dim3(kBlock), 0, s, db, n, q, nq, k, n_qtiles, n_parts, rpp, part,
+                       nq_dev);
 }
 
 }  // namespace
 
-// Launch shape of one brute-force call (exposed for tests and the autotuner).
-struct BruteShape {
-    uint32_t qt, n_qtiles, n_parts;
-    uint64_t rows_per_part;
-};
-
-static BruteShape brute_shape(uint64_t n, uint32_t nq, uint32_t qt_force, uint32_t parts_force) {
-    BruteShape sh;
+BruteLaunch brute_launch_shape(uint64_t n, uint32_t nq, uint32_t k, uint32_t qt_force, uint32_t parts_force) {
+    BruteLaunch sh;
     uint32_t qt = qt_force;
     if (qt == 0) qt = nq <= 1 ? 1 : nq <= 2 ? 2 : nq <= 4 ? 4 : nq <= 8 ? 8 : 16;
     sh.qt = qt;
     sh.n_qtiles = (nq + qt - 1) / qt;
+    if (sh.n_qtiles == 0) sh.n_qtiles = 1;
     uint64_t parts = parts_force;
     if (parts == 0) {
         const uint64_t want_waves = (uint64_t)device_cus() * 16;
@@ -206,7 +210,36 @@ static BruteShape brute_shape(uint64_t n, uint32_t nq, uint32_t qt_force, uint32
     rpp = (rpp + kRowsPerStep - 1) / kRowsPerStep * kRowsPerStep;
     sh.rows_per_part = rpp;
     sh.n_parts = (uint32_t)((n + rpp - 1) / rpp);
+    sh.blocks = (uint64_t)((sh.n_parts + kWavesPerBlock - 1) / kWavesPerBlock) * sh.n_qtiles;
+    sh.part_bytes = (size_t)(nq ? nq : 1) * sh.n_parts * k * sizeof(u64);
     return sh;
+}
+
+int brute_launch(const BruteLaunch &sh, u64 *part, const uint64_t *d_db, uint64_t n, const uint64_t *d_q, uint32_t nq,
+                 const uint32_t *nq_dev, uint32_t k, uint32_t *d_idx, int32_t *d_missed, int32_t *d_extra,
+                 float *d_dist, hipStream_t s) {
+    if (sh.blocks > 0x7FFFFFFFull) return fail(QD_ERR_INVALID, "launch too large");
+    const uint4 *db4 = reinterpret_cast<const uint4 *>(d_db);
+    const uint4 *q4 = reinterpret_cast<const uint4 *>(d_q);
+    dim3 grid((uint32_t)sh.blocks);
+    {
+        KernelTimer timer("wh_scan_topk", s);
+        switch (sh.qt) {
+            case 1: launch_scan<1>(grid, s, db4, n, q4, nq, k, sh.n_qtiles, sh.n_parts, sh.rows_per_part, part, nq_dev); break;
+            case 2: launch_scan<2>(grid, s, db4, n, q4, nq, k, sh.n_qtiles, sh.n_parts, sh.rows_per_part, part, nq_dev); break;
+            case 4: launch_scan<4>(grid, s, db4, n, q4, nq, k, sh.n_qtiles, sh.n_parts, sh.rows_per_part, part, nq_dev); break;
+            case 8: launch_scan<8>(grid, s, db4, n, q4, nq, k, sh.n_qtiles, sh.n_parts, sh.rows_per_part, part, nq_dev); break;
+            default: launch_scan<16>(grid, s, db4, n, q4, nq, k, sh.n_qtiles, sh.n_parts, sh.rows_per_part, part, nq_dev); break;
+        }
+    }
+    QD_HIP_CHECK(hipGetLastError());
+    {
+        KernelTimer timer("topk_merge", s);
+        hipLaunchKernelGGL(merge_emit_kernel, dim3(nq), dim3(kBlock), 0, s, part, sh.n_parts, k, d_q, d_db, d_idx,
+                           d_missed, d_extra, d_dist, nq_dev);
+    }
+    QD_HIP_CHECK(hipGetLastError());
+    return QD_OK;
 }
 
 int knn_bruteforce_mfma(const uint64_t *d_db, uint64_t n, const uint64_t *d_q, uint32_t nq, uint32_t k,
@@ -245,35 +278,12 @@ int knn_bruteforce_impl(const uint64_t *d_db, uint64_t n, const uint64_t *d_q, u
         clear_error();
     }
     hipStream_t s = (hipStream_t)stream;
-    const BruteShape sh = brute_shape(n, nq, qt_force, parts_force);
-    const uint64_t blocks_per_tile = (sh.n_parts + kWavesPerBlock - 1) / kWavesPerBlock;
-    const uint64_t blocks = blocks_per_tile * sh.n_qtiles;
-    if (blocks > 0x7FFFFFFFull) return fail(QD_ERR_INVALID, "launch too large");
+    const BruteLaunch sh = brute_launch_shape(n, nq, k, qt_force, parts_force);
     u64 *part = nullptr;
-    const size_t part_bytes = (size_t)nq * sh.n_parts * k * sizeof(u64);
-    QD_HIP_CHECK(hipMallocAsync((void **)&part, part_bytes, s));
-    const uint4 *db4 = reinterpret_cast<const uint4 *>(d_db);
-    const uint4 *q4 = reinterpret_cast<const uint4 *>(d_q);
-    dim3 grid((uint32_t)blocks);
-    {
-    KernelTimer timer("wh_scan_topk", s);
-    switch (sh.qt) {
-        case 1: launch_scan<1>(grid, s, db4, n, q4, nq, k, sh.n_qtiles, sh.n_parts, sh.rows_per_part, part); break;
-        case 2: launch_scan<2>(grid, s, db4, n, q4, nq, k, sh.n_qtiles, sh.n_parts, sh.rows_per_part, part); break;
-        case 4: launch_scan<4>(grid, s, db4, n, q4, nq, k, sh.n_qtiles, sh.n_parts, sh.rows_per_part, part); break;
-        case 8: launch_scan<8>(grid, s, db4, n, q4, nq, k, sh.n_qtiles, sh.n_parts, sh.rows_per_part, part); break;
-        default: launch_scan<16>(grid, s, db4, n, q4, nq, k, sh.n_qtiles, sh.n_parts, sh.rows_per_part, part); break;
-    }
-    }
-    hipError_t e = hipGetLastError();
-    if (e == hipSuccess) {
-        KernelTimer timer("topk_merge", s);
-        hipLaunchKernelGGL(merge_emit_kernel, dim3(nq), dim3(kBlock), 0, s, part, sh.n_parts, k, d_q, d_db, d_idx,
-                           d_missed, d_extra, d_dist);
-        e = hipGetLastError();
-    }
+    QD_HIP_CHECK(hipMallocAsync((void **)&part, sh.part_bytes, s));
+    const int rc = brute_launch(sh, part, d_db, n, d_q, nq, nullptr, k, d_idx, d_missed, d_extra, d_dist, s);
     hipError_t e2 = hipFreeAsync(part, s);
-    if (e != hipSuccess) return fail(QD_ERR_DEVICE, "brute-force launch: %s", hipGetErrorString(e));
+    if (rc != QD_OK) return rc;
     if (e2 != hipSuccess) return fail(QD_ERR_DEVICE, "hipFreeAsync: %s", hipGetErrorString(e2));
     return QD_OK;
 }

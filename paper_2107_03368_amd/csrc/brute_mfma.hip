@@ -3,13 +3,13 @@
 // For many queries the overlap counts C[q][t] = popcount(q AND t) of Eq. 1
 // form a dense {0,1} matrix product C = Q T^T over the 4096 bit positions, so
 // they are computed with v_mfma_i32_16x16x64_i8 on bits unpacked to bytes.
-// A block of 8 waves owns 128 queries x 256 rows.  The K dimension is
+// A block of 8 waves owns 256 queries x 256 rows.  The K dimension is
 // streamed in chunks of 512 bits: packed chunks go global -> registers ->
 // LDS (the next chunk's loads are in flight while the current one is used),
 // and for each 64-bit step the whole block unpacks the step to bytes in LDS
 // (one bit per byte; double-buffered, so the unpack of step s+1 follows the
 // MFMAs of step s with one barrier per step), and every wave multiplies its
-// 64 x 64 eighth as 4 x 4 MFMA tiles.  Lane l supplies A rows (l % 16) at k = 16*(l/16) .. +15 (16 bytes)
+// 128 x 64 eighth as 8 x 4 MFMA tiles.  Lane l supplies A rows (l % 16) at k = 16*(l/16) .. +15 (16 bytes)
 // and B columns likewise, and receives C rows 4*(l/16) .. +3 of column l % 16.
 //
 // Selection: a first sequential search over a sample of the rows gives each
@@ -36,7 +36,7 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr int kThreads = 512;     // matrix-core scan: 8 waves
-constexpr int MQ = 128;           // queries per block
+constexpr int MQ = 256;           // queries per block
 constexpr int MR = 256;           // rows per block
 constexpr int KCH = 512;          // bits per packed chunk (8 steps of 64)
 constexpr int CHB = KCH / 8;      // bytes per row per chunk (64)
@@ -62,13 +62,13 @@ __global__ __launch_bounds__(kThreads) void scan_mfma_kernel(const uint4 *__rest
     const uint32_t q0 = qt * MQ;
     const uint64_t t0 = rt * MR;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    const int wq = w >> 2, wr = w & 3;  // 2 x 4 waves, each 64 queries x 64 rows
+    const int wq = w >> 2, wr = w & 3;  // 2 x 4 waves, each 128 queries x 64 rows
     const int li = lane & 15, lg = lane >> 4;
     constexpr int kLoads = (MQ + MR) * 4 / kThreads;  // uint4 per thread per chunk
 
-    v4i acc[4][4];
+    v4i acc[8][4];
 #pragma unroll
-    for (int a = 0; a < 4; a++)
+    for (int a = 0; a < 8; a++)
 #pragma unroll
         for (int b = 0; b < 4; b++) acc[a][b] = v4i{0, 0, 0, 0};
 
@@ -115,13 +115,13 @@ __global__ __launch_bounds__(kThreads) void scan_mfma_kernel(const uint4 *__rest
         if (s == 0 && c + 1 < kSteps / kPerChunk) load_chunk(c + 1);  // in flight during this chunk
         const uint8_t *ua = uk[g & 1];
         const uint8_t *ubp = uk[g & 1] + MQ * UST;
-        v4i af[4], bf[4];
+        v4i af[8], bf[4];
 #pragma unroll
-        for (int a = 0; a < 4; a++) af[a] = *reinterpret_cast<const v4i *>(ua + (wq * 64 + a * 16 + li) * UST + lg * 16);
+        for (int a = 0; a < 8; a++) af[a] = *reinterpret_cast<const v4i *>(ua + (wq * 128 + a * 16 + li) * UST + lg * 16);
 #pragma unroll
         for (int b = 0; b < 4; b++) bf[b] = *reinterpret_cast<const v4i *>(ubp + (wr * 64 + b * 16 + li) * UST + lg * 16);
 #pragma unroll
-        for (int a = 0; a < 4; a++)
+        for (int a = 0; a < 8; a++)
 #pragma unroll
             for (int b = 0; b < 4; b++)
                 acc[a][b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(af[a], bf[b], acc[a][b], 0, 0, 0);
@@ -136,12 +136,12 @@ __global__ __launch_bounds__(kThreads) void scan_mfma_kernel(const uint4 *__rest
         __syncthreads();
     }
 
-    // epilogue: keys of this lane's 16 queries x 4 rows
+    // epilogue: keys of this lane's 32 queries x 4 rows
 #pragma unroll
-    for (int a = 0; a < 4; a++)
+    for (int a = 0; a < 8; a++)
 #pragma unroll
         for (int r = 0; r < 4; r++) {
-            const uint32_t qi = q0 + wq * 64 + a * 16 + lg * 4 + r;
+            const uint32_t qi = q0 + wq * 128 + a * 16 + lg * 4 + r;
             if (qi >= nq) continue;
             const uint32_t pq = qpop[qi];
             const uint32_t wa = pq > 1 ? pq : 1, wb = (QD_BITS - pq) > 1 ? QD_BITS - pq : 1;

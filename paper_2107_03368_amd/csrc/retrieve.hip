@@ -14,6 +14,7 @@
 // global memory; the replay counts stay in LDS as bytes.
 #include "qd_device.h"
 #include "qd_internal.h"
+#include "qd_launch.h"
 #include "qd_tree.h"
 
 namespace qd {
@@ -36,7 +37,9 @@ __global__ __launch_bounds__(kBlock) void vote_kernel(const uint32_t *__restrict
                                                       const uint16_t *__restrict__ obj_of, uint64_t n_db,
                                                       uint32_t n_obj, const uint64_t *__restrict__ qoff,
                                                       uint32_t threshold, uint32_t *__restrict__ votes,
-                                                      int32_t *__restrict__ winner, uint32_t *__restrict__ used) {
+                                                      int32_t *__restrict__ winner, uint32_t *__restrict__ used,
+                                                      const uint32_t *__restrict__ nqo_dev) {
+    if (nqo_dev && blockIdx.x >= *nqo_dev) return;  // whole block (size given on the device)
     __shared__ uint32_t hist[kLdsBins];
     __shared__ uint8_t running[kMaxObjects];  // votes so far per object, saturating at the threshold
     const uint32_t g = blockIdx.x;
@@ -103,6 +106,17 @@ __global__ __launch_bounds__(kBlock) void vote_kernel(const uint32_t *__restrict
 }
 
 }  // namespace
+
+int vote_launch(const uint32_t *nn, uint32_t k, const uint16_t *obj_of, uint64_t n_db, uint32_t n_obj,
+                const uint64_t *qoff, uint32_t nqo, const uint32_t *nqo_dev, uint32_t threshold, uint32_t *votes,
+                int32_t *winner, uint32_t *used, hipStream_t s) {
+    KernelTimer timer("vote", s);
+    hipLaunchKernelGGL(vote_kernel, dim3(nqo), dim3(kBlock), 0, s, nn, k, obj_of, n_db, n_obj, qoff, threshold, votes,
+                       winner, used, nqo_dev);
+    QD_HIP_CHECK(hipGetLastError());
+    return QD_OK;
+}
+
 }  // namespace qd
 
 extern "C" int qd_retrieve_objects(qd_tree_t t, const uint64_t *d_db, uint64_t n, const uint16_t *d_obj_of,
@@ -150,13 +164,8 @@ extern "C" int qd_retrieve_objects(qd_tree_t t, const uint64_t *d_db, uint64_t n
             return rc;
         }
     }
-    {
-        KernelTimer timer("vote", s);
-        hipLaunchKernelGGL(vote_kernel, dim3(nqo), dim3(kBlock), 0, s, nn, k, d_obj_of, n_db, n_obj, d_qoff,
-                           vote_threshold, d_votes, d_winner, d_used);
-    }
-    hipError_t e = hipGetLastError();
+    const int rc = vote_launch(nn, k, d_obj_of, n_db, n_obj, d_qoff, nqo, nullptr, vote_threshold, d_votes, d_winner,
+                               d_used, s);
     if (ws) (void)hipFreeAsync(ws, s);
-    if (e != hipSuccess) return fail(QD_ERR_DEVICE, "vote kernel: %s", hipGetErrorString(e));
-    return QD_OK;
+    return rc;
 }

@@ -26,6 +26,7 @@
 // Both orders return exactly the sequential-search result.
 #include "qd_device.h"
 #include "qd_internal.h"
+#include "qd_launch.h"
 #include "qd_tree.h"
 
 namespace qd {
@@ -63,7 +64,8 @@ __global__ __launch_bounds__(kBlock) void tree_knn_kernel(TreeView T, const uint
                                                           uint64_t pool_chunks, Scores S, uint32_t *idx,
                                                           int32_t *missed, int32_t *extra, float *dist,
                                                           uint32_t *qstats, unsigned long long *gstats,
-                                                          uint32_t *trace, uint32_t n_traced) {
+                                                          uint32_t *trace, uint32_t n_traced,
+                                                          const uint32_t *__restrict__ nq_dev) {
     __shared__ uint32_t bstate_all[kBest ? kWaves * kBuckets : 1];
     __shared__ u64 stack_all[kBest ? 1 : kWaves * kMaxStack];
     const int lane = lane_id();
@@ -76,6 +78,7 @@ __global__ __launch_bounds__(kBlock) void tree_knn_kernel(TreeView T, const uint
     uint32_t *bstate = bstate_all + (kBest ? wave * kBuckets : 0);
     u64 *stack = stack_all + (kBest ? 0 : wave * kMaxStack);
     const bool has_and = T.andimg != nullptr;
+    if (nq_dev) nq = readfirst(*nq_dev);  // size given on the device (captured graphs)
 
     for (;;) {
         // every lane takes part in the atomic (lane 0 adds 1, the others 0) so
@@ -328,6 +331,56 @@ __global__ __launch_bounds__(kBlock) void tree_knn_kernel(TreeView T, const uint
 
 }  // namespace
 
+__global__ void zero_words_kernel(uint32_t *p, uint32_t n) {
+    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0;
+}
+
+TreeLaunch tree_launch_shape(qd_tree_t t, uint32_t nq_max, int order, uint32_t waves_per_cu) {
+    TreeLaunch L;
+    const int cus = device_cus();
+    if (waves_per_cu == 0) waves_per_cu = order == QD_ORDER_BEST_FIRST ? 8 : 16;
+    uint64_t blocks = ((uint64_t)cus * waves_per_cu + kWaves - 1) / kWaves;
+    const uint64_t need = ((uint64_t)(nq_max ? nq_max : 1) + kWaves - 1) / kWaves;
+    if (blocks > need) blocks = need;
+    L.blocks = blocks;
+    L.slots = blocks * kWaves;
+    // Each node is queued at most once.  Live chunks: a bucket holds at most
+    // one partly filled chunk (or one kept empty chunk) besides full ones, and
+    // emptied chunks go to a free list, so n_nodes/kChunk + 2 per bucket
+    // chunks never run out.
+    L.pool_chunks = order == QD_ORDER_BEST_FIRST ? t->n_nodes / kChunk + 2 * kBuckets + 2 : 1;
+    L.head = 256;  // [counter | pad | stats x4 | pad]
+    L.prev_bytes = (size_t)(L.slots * L.pool_chunks * 8 + 255) / 256 * 256;  // prev + free list
+    L.pool_bytes = (size_t)L.slots * L.pool_chunks * kChunk * 8;
+    return L;
+}
+
+int tree_launch(qd_tree_t t, const TreeLaunch &L, char *ws, const uint64_t *d_q, uint32_t nq,
+                const uint32_t *nq_dev, uint32_t k, int order, const float *d_scores, uint32_t n_scored,
+                uint32_t *d_idx, int32_t *d_missed, int32_t *d_extra, float *d_dist, uint32_t *d_qstats,
+                uint32_t *d_trace, uint32_t n_traced, hipStream_t s) {
+    hipLaunchKernelGGL(zero_words_kernel, dim3(1), dim3(64), 0, s, reinterpret_cast<uint32_t *>(ws),
+                       (uint32_t)(L.head / 4));
+    uint32_t *counter = reinterpret_cast<uint32_t *>(ws);
+    unsigned long long *gstats = reinterpret_cast<unsigned long long *>(ws + 64);
+    uint32_t *chunk_prev = reinterpret_cast<uint32_t *>(ws + L.head);
+    u64 *pool = reinterpret_cast<u64 *>(ws + L.head + L.prev_bytes);
+    TreeView T{reinterpret_cast<const uint4 *>(t->d_sorted), t->d_perm, reinterpret_cast<const uint4 *>(t->d_or),
+               reinterpret_cast<const uint4 *>(t->d_and), t->d_child, t->d_begin, t->d_count, t->d_pop};
+    Scores S{d_scores, d_scores ? n_scored : 0};
+    KernelTimer timer("tree_knn", s);
+    if (order == QD_ORDER_BEST_FIRST)
+        hipLaunchKernelGGL(tree_knn_kernel<true>, dim3((uint32_t)L.blocks), dim3(kBlock), 0, s, T,
+                           reinterpret_cast<const uint4 *>(d_q), nq, k, counter, pool, chunk_prev, L.pool_chunks, S,
+                           d_idx, d_missed, d_extra, d_dist, d_qstats, gstats, d_trace, n_traced, nq_dev);
+    else
+        hipLaunchKernelGGL(tree_knn_kernel<false>, dim3((uint32_t)L.blocks), dim3(kBlock), 0, s, T,
+                           reinterpret_cast<const uint4 *>(d_q), nq, k, counter, pool, chunk_prev, L.pool_chunks, S,
+                           d_idx, d_missed, d_extra, d_dist, d_qstats, gstats, d_trace, n_traced, nq_dev);
+    QD_HIP_CHECK(hipGetLastError());
+    return QD_OK;
+}
+
 int knn_tree_impl(qd_tree_t t, const uint64_t *d_q, uint32_t nq, uint32_t k, int order, const float *d_scores,
                   uint32_t n_scored, uint32_t *d_idx, int32_t *d_missed, int32_t *d_extra, float *d_dist,
                   uint32_t *d_qstats, qd_stats *h_stats, void *stream, uint32_t waves_per_cu, uint32_t *d_trace,
@@ -342,53 +395,24 @@ int knn_tree_impl(qd_tree_t t, const uint64_t *d_q, uint32_t nq, uint32_t k, int
     if (!aligned16(d_q)) return fail(QD_ERR_INVALID, "queries must be 16-byte aligned");
     if (order == QD_ORDER_DEPTH_FIRST && t->depth + 2 > (uint32_t)kMaxStack)
         return fail(QD_ERR_UNSUPPORTED, "tree depth %u exceeds the depth-first stack (%d)", t->depth, kMaxStack);
+    if (n_traced > t->n_nodes) return fail(QD_ERR_INVALID, "n_traced above the node count");
     hipStream_t s = (hipStream_t)stream;
-    const int cus = device_cus();
-    if (waves_per_cu == 0) waves_per_cu = order == QD_ORDER_BEST_FIRST ? 8 : 16;
-    uint64_t blocks = ((uint64_t)cus * waves_per_cu + kWaves - 1) / kWaves;
-    const uint64_t need = (nq + kWaves - 1) / kWaves;
-    if (blocks > need) blocks = need;
-    const uint64_t slots = blocks * kWaves;
-    // Each node is queued at most once.  Live chunks: a bucket holds at most
-    // one partly filled chunk (or one kept empty chunk) besides full ones, and
-    // emptied chunks go to a free list, so n_nodes/kChunk + 2 per bucket
-    // chunks never run out.
-    const uint64_t pool_chunks = order == QD_ORDER_BEST_FIRST ? t->n_nodes / kChunk + 2 * kBuckets + 2 : 1;
-    // workspace: [counter | stats x4 | pad] [chunk_prev] [pool]
-    const size_t head = 256;
-    const size_t prev_bytes = (size_t)(slots * pool_chunks * 8 + 255) / 256 * 256;  // prev + free list
-    const size_t pool_bytes = (size_t)slots * pool_chunks * kChunk * 8;
+    const TreeLaunch L = tree_launch_shape(t, nq, order, waves_per_cu);
     char *ws = nullptr;
-    QD_HIP_CHECK(hipMallocAsync((void **)&ws, head + prev_bytes + pool_bytes, s));
-    QD_HIP_CHECK(hipMemsetAsync(ws, 0, head, s));
+    QD_HIP_CHECK(hipMallocAsync((void **)&ws, L.total(), s));
     if (d_trace && n_traced)
         QD_HIP_CHECK(hipMemsetAsync(d_trace, 0, (size_t)nq * ((n_traced + 31) / 32) * 4, s));
-    uint32_t *counter = reinterpret_cast<uint32_t *>(ws);
-    unsigned long long *gstats = reinterpret_cast<unsigned long long *>(ws + 64);
-    uint32_t *chunk_prev = reinterpret_cast<uint32_t *>(ws + head);
-    u64 *pool = reinterpret_cast<u64 *>(ws + head + prev_bytes);
-    TreeView T{reinterpret_cast<const uint4 *>(t->d_sorted), t->d_perm, reinterpret_cast<const uint4 *>(t->d_or),
-               reinterpret_cast<const uint4 *>(t->d_and), t->d_child, t->d_begin, t->d_count, t->d_pop};
-    Scores S{d_scores, d_scores ? n_scored : 0};
-    {
-        KernelTimer timer("tree_knn", s);
-        if (order == QD_ORDER_BEST_FIRST)
-            hipLaunchKernelGGL(tree_knn_kernel<true>, dim3((uint32_t)blocks), dim3(kBlock), 0, s, T,
-                               reinterpret_cast<const uint4 *>(d_q), nq, k, counter, pool, chunk_prev, pool_chunks, S,
-                               d_idx, d_missed, d_extra, d_dist, d_qstats, gstats, d_trace, n_traced);
-        else
-            hipLaunchKernelGGL(tree_knn_kernel<false>, dim3((uint32_t)blocks), dim3(kBlock), 0, s, T,
-                               reinterpret_cast<const uint4 *>(d_q), nq, k, counter, pool, chunk_prev, pool_chunks, S,
-                               d_idx, d_missed, d_extra, d_dist, d_qstats, gstats, d_trace, n_traced);
-    }
-    hipError_t e = hipGetLastError();
-    if (e == hipSuccess && h_stats) {
+    int rc = tree_launch(t, L, ws, d_q, nq, nullptr, k, order, d_scores, n_scored, d_idx, d_missed, d_extra, d_dist,
+                         d_qstats, d_trace, n_traced, s);
+    hipError_t e = hipSuccess;
+    if (rc == QD_OK && h_stats) {
         unsigned long long hs[4];
-        e = hipMemcpyAsync(hs, gstats, sizeof hs, hipMemcpyDeviceToHost, s);
+        e = hipMemcpyAsync(hs, ws + 64, sizeof hs, hipMemcpyDeviceToHost, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         if (e == hipSuccess) *h_stats = qd_stats{hs[0], hs[1], hs[2], hs[3]};
     }
     hipError_t e2 = hipFreeAsync(ws, s);
+    if (rc != QD_OK) return rc;
     if (e != hipSuccess) return fail(QD_ERR_DEVICE, "tree search: %s", hipGetErrorString(e));
     if (e2 != hipSuccess) return fail(QD_ERR_DEVICE, "hipFreeAsync: %s", hipGetErrorString(e2));
     return QD_OK;

@@ -78,3 +78,39 @@ def test_objects_workload_full_scale(qd):
     rows = np.array([0, 1, 12345, len(q) // 2, len(q) - 1])
     assert np.array_equal(nn[rows], oracle.knn_brute(db, q[rows], 5).idx)
     assert (rw == qobj).mean() >= 0.95  # the workload is retrievable
+
+
+@pytest.mark.parametrize("use_tree", [True, False])
+def test_plan_graph_replays_match_direct_retrieval(qd, use_tree):
+    import torch
+    db, obj, off, q, qobj = _workload(40, 300, 24, 20, 120, 91)
+    tree = qd.tree_build(_t(db)) if use_tree else None
+    dbt = None if use_tree else _t(db)
+    plan = qd.Plan(_t(obj), 40, max_qdesc=len(q), max_qobj=24, k=5, threshold=10, tree=tree, db=dbt)
+    # batches of different sizes, with eager library work between the replays
+    for lo, hi in ((0, 24), (3, 10), (0, 1), (5, 24)):
+        sub = np.asarray(off[lo:hi + 1], np.uint64) - off[lo]
+        qs = q[int(off[lo]):int(off[hi])]
+        got = plan.run(_t(qs), _t(sub))
+        ref = qd.retrieve_objects(_t(qs), _t(sub), _t(obj), 40, 5, 10, tree=tree, db=dbt)
+        torch.cuda.synchronize()
+        for a, b in zip(got, ref):
+            assert torch.equal(a, b)
+        rv, rw, ru = oracle.votes(oracle.knn_brute(db, qs, 5).idx, obj, 40, sub, 10)
+        assert np.array_equal(got[1].cpu().numpy(), rw)
+
+
+def test_autotuner_returns_a_timed_exact_configuration(qd):
+    db = synth.gen_db(50_000, 95)
+    q, _ = synth.gen_queries(db, 300, 96, 0.1, 0.6)
+    tree = qd.tree_build(_t(db))
+    ref = oracle.knn_brute(db, q[:4], 10)
+    for kw in (dict(tree=tree), dict(db=_t(db))):
+        best, cands = qd.autotune(_t(q), 10, reps=2, **kw)
+        assert len(cands) >= 3 and all(c["ms"] > 0 for c in cands)
+        assert best["ms"] == min(c["ms"] for c in cands)
+        if "tree" in kw:
+            res = qd.knn_tree(tree, _t(q), 10, order=best["order"], waves_per_cu=best["waves_per_cu"])
+        else:
+            res = qd.knn_bruteforce(_t(db), _t(q), 10, query_tile=best["query_tile"])
+        assert np.array_equal(res[0].cpu().numpy().view(np.uint32)[:4], ref.idx)
