@@ -32,6 +32,7 @@ WORKLOADS = {
 
 # MI355X published peaks and unit counts
 HBM_PEAK_GBS = 8000.0
+INT8_PEAK_TOPS = 5000.0  # dense int8 MFMA
 CUS, SIMDS, LANES, CLOCK_GHZ = 256, 4, 16, 2.4
 VALU_PEAK_TOPS = CUS * SIMDS * LANES * CLOCK_GHZ / 1000.0  # 32-bit lane ops: 39.3 T/s
 OPS_PER_PAIR = 256  # 128 x (AND + BCNT) over 4096 bits
@@ -39,6 +40,10 @@ ROW_BYTES = 512
 # frontier-order model: trained on the 1M database's traces, scores the top
 # N_SCORED nodes (depth <= 10) of the searched tree
 TRAIN_QUERIES, TRAIN_BATCH, TRAIN_EPOCHS, TRAIN_LR, N_SCORED = 1024, 16, 4, 1e-3, 2047
+# HBM bytes of one scan_mfma_kernel launch at the 10M x 8,192 workload, from the
+# FETCH_SIZE / WRITE_SIZE counters scaled by a 1 GiB copy (profiles/); None
+# until measured for the current kernel
+TRAFFIC = None
 
 
 def log(*a):
@@ -53,6 +58,8 @@ def main():
     ap.add_argument("--workload", default="10m", choices=sorted(WORKLOADS))
     ap.add_argument("--cpu-sample", type=int, default=48, help="queries in the oracle's timed sample (0 = skip)")
     ap.add_argument("--paths", default="brute,tree,learned")
+    ap.add_argument("--pmc-run", action="store_true",
+                    help="only a 1 GiB device copy (counter calibration) and one sequential-search batch")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU; --gpus must be 1"}))
@@ -64,6 +71,20 @@ def main():
 
     w = WORKLOADS[args.workload]
     dev = torch.device("cuda:0")
+    if args.pmc_run:
+        # a plain copy of known size, to scale the HBM byte counters, then one batch
+        src = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        db = synth.gen_db(w["n"], w["seed_db"])
+        q, _ = synth.gen_queries(db, w["nq"], w["seed_q"], w["pmin"], w["pmax"])
+        dbt = torch.from_numpy(db.view(np.int64)).to(dev)
+        qt = torch.from_numpy(q.view(np.int64)).to(dev)
+        qd.knn_bruteforce(dbt, qt, w["k"])
+        torch.cuda.synchronize()
+        log("pmc run done")
+        return
     t0 = time.time()
     db = synth.gen_db(w["n"], w["seed_db"])
     q, src = synth.gen_queries(db, w["nq"], w["seed_q"], w["pmin"], w["pmax"])
@@ -167,10 +188,20 @@ def main():
 
     step_ms = sum(p["ms"] for p in per_path.values())
     best = min(per_path, key=lambda p: per_path[p]["ms"])
-    scan = per_path["brute"]["kernels"]["wh_scan_topk"]["avg_ms"]
-    achieved = nq * n * OPS_PER_PAIR / (scan * 1e-3) / 1e12
-    roofline = {"kernel": "wh_scan_topk", "bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS,
-                "unit": "TOP/s (32-bit integer lane ops)", "frac": achieved / VALU_PEAK_TOPS, "traffic": None}
+    bk = per_path["brute"]["kernels"]
+    if "wh_scan_mfma" in bk:
+        # int8 matrix-core scan: 2 ops (multiply, add) per bit pair per (query, row)
+        ms = bk["wh_scan_mfma"]["avg_ms"]
+        achieved = nq * n * 4096 * 2 / (ms * 1e-3) / 1e12
+        roofline = {"kernel": "scan_mfma_kernel", "bound": "mfma", "achieved": achieved, "peak": INT8_PEAK_TOPS,
+                    "unit": "TOP/s (int8 MFMA ops)", "frac": achieved / INT8_PEAK_TOPS, "traffic": TRAFFIC,
+                    "avg_ms": ms}
+    else:
+        ms = bk["wh_scan_topk"]["avg_ms"]
+        achieved = nq * n * OPS_PER_PAIR / (ms * 1e-3) / 1e12
+        roofline = {"kernel": "scan_topk_kernel", "bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS,
+                    "unit": "TOP/s (32-bit integer lane ops)", "frac": achieved / VALU_PEAK_TOPS, "traffic": None,
+                    "avg_ms": ms}
 
     cpu = None
     if args.cpu_sample > 0:
