@@ -43,7 +43,9 @@ TRAIN_QUERIES, TRAIN_BATCH, TRAIN_EPOCHS, TRAIN_LR, N_SCORED = 1024, 16, 4, 1e-3
 # HBM bytes of one scan_mfma_kernel launch at the 10M x 8,192 workload, from the
 # FETCH_SIZE / WRITE_SIZE counters scaled by a 1 GiB copy (profiles/); None
 # until measured for the current kernel
-TRAFFIC = None
+TRAFFIC = 41.12e9 + 0.521e9
+TRAFFIC_DETAIL = {"read_bytes": 41.12e9, "write_bytes": 0.521e9, "algorithmic_read_bytes": 5.124e9,
+                  "counter_scale": {"FETCH_SIZE": 2.0, "WRITE_SIZE": 1.0}}
 
 
 def log(*a):
@@ -195,7 +197,7 @@ def main():
         achieved = nq * n * 4096 * 2 / (ms * 1e-3) / 1e12
         roofline = {"kernel": "scan_mfma_kernel", "bound": "mfma", "achieved": achieved, "peak": INT8_PEAK_TOPS,
                     "unit": "TOP/s (int8 MFMA ops)", "frac": achieved / INT8_PEAK_TOPS, "traffic": TRAFFIC,
-                    "avg_ms": ms}
+                    "traffic_detail": TRAFFIC_DETAIL if TRAFFIC is not None else None, "avg_ms": ms}
     else:
         ms = bk["wh_scan_topk"]["avg_ms"]
         achieved = nq * n * OPS_PER_PAIR / (ms * 1e-3) / 1e12
