@@ -112,6 +112,7 @@ def main():
         if "tree" in wanted:
             paths["tree"] = lambda: qd.knn_tree(tree, qt, k)
             paths["tree_dfs"] = lambda: qd.knn_tree(tree, qt, k, order=qd.ORDER_DEPTH_FIRST)
+            paths["tree_blocked"] = lambda: qd.knn_tree(tree, qt, k, order=qd.ORDER_BLOCKED)
         if "learned" in wanted:
             # offline: train the frontier-order model on traces of the exact search over
             # the 1M-descriptor database (seed 1001) with its own queries
@@ -158,7 +159,8 @@ def main():
         dt = (time.perf_counter() - t0) / args.steps
         kernels = {}
         for kname in ("wh_scan_mfma", "wh_scan_topk", "topk_merge", "topk_select", "tree_knn", "mlp_features",
-                      "mlp_forward"):
+                      "mlp_forward", "tree_block_bounds", "tree_block_round1", "tree_block_lists", "tree_block_eval",
+                      "tree_block_select"):
             ms, cnt = qd.profile_read(kname)
             if cnt:
                 kernels[kname] = {"avg_ms": ms / cnt, "launches": cnt}
@@ -166,6 +168,7 @@ def main():
         per_path[name] = {"ms": dt * 1e3, "queries_per_s": nq / dt, "kernels": kernels}
         if name.startswith("tree"):
             st = (qd.knn_tree(tree, qt, k, totals=True) if name == "tree" else
+                  qd.knn_tree(tree, qt, k, order=qd.ORDER_BLOCKED, totals=True) if name == "tree_blocked" else
                   qd.knn_tree(tree, qt, k, order=qd.ORDER_DEPTH_FIRST, totals=True,
                               scores=qd.model_score_tree(model, tree, qt, n_scored) if name == "tree_learned"
                               else None))[-1]

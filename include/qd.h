@@ -165,13 +165,23 @@ int qd_tree_export(qd_tree_t t, int32_t *h_child, uint32_t *h_begin, uint32_t *h
  *     query-major, nodes 0..n_scored-1; e.g. a learned model's output), else
  *     the lower bound (ties: the similar child).  Runs until the stack is
  *     empty, skipping popped nodes that cannot improve the result.
+ *   QD_ORDER_BLOCKED: the whole batch at once on the matrix cores.  The leaf
+ *     order is cut into blocks of 256 rows, each with the sum image of its
+ *     rows; the same bound is computed for every (query, block) pair, and
+ *     each query evaluates its blocks in rounds of ascending bound (a first
+ *     round of 16 blocks, then about doubling), keeping only blocks whose
+ *     bound is <= its current k-th key, until no block is left that could
+ *     hold a better key.  Queries whose candidate buffer overflows are
+ *     searched again best-first.  Waits for the stream between rounds (not
+ *     capturable); takes no scores or traces.  Per-query stats mean: blocks
+ *     evaluated, rounds taken part in, blocks bounded, distances evaluated.
  * d_query_stats (nullable): nq x 4 uint32 per query: nodes visited
  * (expanded pops, leaves and inner nodes), leaves visited, bounds evaluated,
  * distances evaluated.  h_stats (nullable): totals; filling it waits for the
  * stream.  waves_per_cu = 0 picks a default occupancy.  d_visited records
  * which of the first n_traced nodes each query expanded (traversal traces).
  * ------------------------------------------------------------------------- */
-typedef enum { QD_ORDER_BEST_FIRST = 0, QD_ORDER_DEPTH_FIRST = 1 } qd_order;
+typedef enum { QD_ORDER_BEST_FIRST = 0, QD_ORDER_DEPTH_FIRST = 1, QD_ORDER_BLOCKED = 2 } qd_order;
 
 typedef struct {
     qd_order order;

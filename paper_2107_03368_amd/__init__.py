@@ -148,6 +148,7 @@ class Stats(ctypes.Structure):
 
 ORDER_BEST_FIRST = 0
 ORDER_DEPTH_FIRST = 1
+ORDER_BLOCKED = 2
 
 _sig("qd_tree_build", [_P, _U64, ctypes.POINTER(_BuildParams), _P, ctypes.POINTER(ctypes.c_void_p)])
 _sig("qd_tree_free", [_P])

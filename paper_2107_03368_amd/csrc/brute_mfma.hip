@@ -1,16 +1,9 @@
 // Large-batch sequential search on the matrix cores.
 //
 // For many queries the overlap counts C[q][t] = popcount(q AND t) of Eq. 1
-// form a dense {0,1} matrix product C = Q T^T over the 4096 bit positions, so
-// they are computed with v_mfma_i32_16x16x64_i8 on bits unpacked to bytes.
-// A block of 8 waves owns 256 queries x 256 rows.  The K dimension is
-// streamed in chunks of 512 bits: packed chunks go global -> registers ->
-// LDS (the next chunk's loads are in flight while the current one is used),
-// and for each 64-bit step the whole block unpacks the step to bytes in LDS
-// (one bit per byte; double-buffered, so the unpack of step s+1 follows the
-// MFMAs of step s with one barrier per step), and every wave multiplies its
-// 128 x 64 eighth as 8 x 4 MFMA tiles.  Lane l supplies A rows (l % 16) at k = 16*(l/16) .. +15 (16 bytes)
-// and B columns likewise, and receives C rows 4*(l/16) .. +3 of column l % 16.
+// form a dense {0,1} matrix product C = Q T^T over the 4096 bit positions;
+// they are computed by the shared 256 x 256 tile (mfma_tile.h), one block per
+// (query tile, row tile).
 //
 // Selection: a first sequential search over a sample of the rows gives each
 // query an upper bound U_q on its k-th key (the sample's k-th key: those k
@@ -22,6 +15,7 @@
 #include <algorithm>
 #include <vector>
 
+#include "mfma_tile.h"
 #include "qd_device.h"
 #include "qd_internal.h"
 
@@ -35,120 +29,46 @@ int popcount_rows_launch(const uint64_t *d_db, uint64_t n, uint16_t *d_pop, hipS
 namespace {
 
 constexpr int kBlock = 256;
-constexpr int kThreads = 512;     // matrix-core scan: 8 waves
-constexpr int MQ = 256;           // queries per block
-constexpr int MR = 256;           // rows per block
-constexpr int KCH = 512;          // bits per packed chunk (8 steps of 64)
-constexpr int CHB = KCH / 8;      // bytes per row per chunk (64)
-constexpr int UST = 80;           // unpacked row stride in LDS (64 bytes + 16 pad)
+constexpr int MQ = mt::MA;        // queries per block
+constexpr int MR = mt::MB;        // rows per block
 constexpr uint32_t kCap = 8192;   // candidate slots per query
 
-typedef int v4i __attribute__((ext_vector_type(4)));
-
-// 4 bits -> 4 bytes of 0/1 (bit e -> byte e): the multiplier places bit e at
-// bit 8e with no two terms overlapping, so no carries occur.
-__device__ __forceinline__ uint32_t spread4(uint32_t x) { return ((x & 0xFu) * 0x00204081u) & 0x01010101u; }
-
-__global__ __launch_bounds__(kThreads) void scan_mfma_kernel(const uint4 *__restrict__ db, uint64_t n,
-                                                             const uint4 *__restrict__ q, uint32_t nq,
-                                                             const uint16_t *__restrict__ tpop,
-                                                             const uint16_t *__restrict__ qpop,
-                                                             const u64 *__restrict__ thr, uint32_t n_qtiles,
-                                                             uint32_t *__restrict__ cnt, u64 *__restrict__ cand) {
-    __shared__ uint8_t pk[2][(MQ + MR) * CHB];  // packed chunk (queries then rows), double-buffered
-    __shared__ uint8_t uk[2][(MQ + MR) * UST];  // unpacked 64-bit step, double-buffered
+__global__ __launch_bounds__(mt::kThreads) void scan_mfma_kernel(const uint4 *__restrict__ db, uint64_t n,
+                                                                 const uint4 *__restrict__ q, uint32_t nq,
+                                                                 const uint16_t *__restrict__ tpop,
+                                                                 const uint16_t *__restrict__ qpop,
+                                                                 const u64 *__restrict__ thr, uint32_t n_qtiles,
+                                                                 uint32_t *__restrict__ cnt, u64 *__restrict__ cand) {
+    __shared__ mt::Smem sm;
     const uint32_t qt = blockIdx.x % n_qtiles;
     const uint64_t rt = blockIdx.x / n_qtiles;
     const uint32_t q0 = qt * MQ;
     const uint64_t t0 = rt * MR;
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    const int wq = w >> 2, wr = w & 3;  // 2 x 4 waves, each 128 queries x 64 rows
-    const int li = lane & 15, lg = lane >> 4;
-    constexpr int kLoads = (MQ + MR) * 4 / kThreads;  // uint4 per thread per chunk
-
-    v4i acc[8][4];
+    const uint4 *src[mt::kLoads];
 #pragma unroll
-    for (int a = 0; a < 8; a++)
-#pragma unroll
-        for (int b = 0; b < 4; b++) acc[a][b] = v4i{0, 0, 0, 0};
-
-    uint4 pre[kLoads];
-    auto load_chunk = [&](int c) {
-#pragma unroll
-        for (int u = 0; u < kLoads; u++) {
-            const int i = tid + u * kThreads, r = i >> 2, j = i & 3;
-            uint4 v = make_uint4(0, 0, 0, 0);
-            if (r < MQ) {
-                if (q0 + r < nq) v = q[(uint64_t)(q0 + r) * 32 + c * 4 + j];
-            } else {
-                const uint64_t t = t0 + (r - MQ);
-                if (t < n) v = db[t * 32 + c * 4 + j];
-            }
-            pre[u] = v;
-        }
-    };
-    auto store_chunk = [&](int buf) {
-#pragma unroll
-        for (int u = 0; u < kLoads; u++) {
-            const int i = tid + u * kThreads;
-            *reinterpret_cast<uint4 *>(&pk[buf][(i >> 2) * CHB + (i & 3) * 16]) = pre[u];
-        }
-    };
-    // unpack 64-bit step s of the packed chunk in pk[pb] into uk[ub]
-    auto unpack = [&](int pb, int s, int ub) {
-        for (int i = tid; i < (MQ + MR) * 4; i += kThreads) {
-            const int r = i >> 2, g = i & 3;
-            const uint32_t bits = *reinterpret_cast<const uint16_t *>(&pk[pb][r * CHB + s * 8 + g * 2]);
-            *reinterpret_cast<uint4 *>(&uk[ub][r * UST + g * 16]) =
-                make_uint4(spread4(bits), spread4(bits >> 4), spread4(bits >> 8), spread4(bits >> 12));
-        }
-    };
-
-    constexpr int kSteps = QD_BITS / 64, kPerChunk = KCH / 64;
-    load_chunk(0);
-    store_chunk(0);
-    __syncthreads();
-    unpack(0, 0, 0);
-    __syncthreads();
-    for (int g = 0; g < kSteps; g++) {
-        const int c = g / kPerChunk, s = g % kPerChunk;
-        if (s == 0 && c + 1 < kSteps / kPerChunk) load_chunk(c + 1);  // in flight during this chunk
-        const uint8_t *ua = uk[g & 1];
-        const uint8_t *ubp = uk[g & 1] + MQ * UST;
-        v4i af[8], bf[4];
-#pragma unroll
-        for (int a = 0; a < 8; a++) af[a] = *reinterpret_cast<const v4i *>(ua + (wq * 128 + a * 16 + li) * UST + lg * 16);
-#pragma unroll
-        for (int b = 0; b < 4; b++) bf[b] = *reinterpret_cast<const v4i *>(ubp + (wr * 64 + b * 16 + li) * UST + lg * 16);
-#pragma unroll
-        for (int a = 0; a < 8; a++)
-#pragma unroll
-            for (int b = 0; b < 4; b++)
-                acc[a][b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(af[a], bf[b], acc[a][b], 0, 0, 0);
-        if (g + 1 < kSteps) {
-            const int c1 = (g + 1) / kPerChunk, s1 = (g + 1) % kPerChunk;
-            if (s1 == 0) {
-                store_chunk(c1 & 1);  // the other packed buffer: nobody reads it now
-                __syncthreads();
-            }
-            unpack(c1 & 1, s1, (g + 1) & 1);
-        }
-        __syncthreads();
+    for (int u = 0; u < mt::kLoads; u++) {
+        const int r = mt::slot_row(u);
+        if (r < MQ)
+            src[u] = q0 + r < nq ? q + (uint64_t)(q0 + r) * 32 : nullptr;
+        else
+            src[u] = t0 + (r - MQ) < n ? db + (t0 + (r - MQ)) * 32 : nullptr;
     }
+    mt::v4i acc[8][4];
+    mt::overlap_tile(src, sm, acc);
 
     // epilogue: keys of this lane's 32 queries x 4 rows
 #pragma unroll
     for (int a = 0; a < 8; a++)
 #pragma unroll
         for (int r = 0; r < 4; r++) {
-            const uint32_t qi = q0 + wq * 128 + a * 16 + lg * 4 + r;
+            const uint32_t qi = q0 + mt::acc_arow(a, r);
             if (qi >= nq) continue;
             const uint32_t pq = qpop[qi];
             const uint32_t wa = pq > 1 ? pq : 1, wb = (QD_BITS - pq) > 1 ? QD_BITS - pq : 1;
             const u64 th = thr[qi];
 #pragma unroll
             for (int b = 0; b < 4; b++) {
-                const uint64_t t = t0 + wr * 64 + b * 16 + li;
+                const uint64_t t = t0 + mt::acc_brow(b);
                 if (t >= n) continue;
                 const uint32_t C = (uint32_t)acc[a][b][r];
                 const uint32_t K = (pq - C) * wb + ((uint32_t)tpop[t] - C) * wa;
@@ -284,7 +204,7 @@ int knn_bruteforce_mfma(const uint64_t *d_db, uint64_t n, const uint64_t *d_q, u
         return done(fail(QD_ERR_DEVICE, "memset"));
     {
         KernelTimer timer("wh_scan_mfma", s);
-        hipLaunchKernelGGL(scan_mfma_kernel, dim3((uint32_t)(n_qtiles * n_rtiles)), dim3(kThreads), 0, s,
+        hipLaunchKernelGGL(scan_mfma_kernel, dim3((uint32_t)(n_qtiles * n_rtiles)), dim3(mt::kThreads), 0, s,
                            reinterpret_cast<const uint4 *>(d_db), n, reinterpret_cast<const uint4 *>(d_q), nq, tpop,
                            qpop, thr, n_qtiles, cnt, cand);
     }

@@ -22,8 +22,14 @@ struct qd_tree_s {
     int32_t *d_parent = nullptr;   // n_nodes: parent node (-1 for the root)
     uint8_t *d_depth = nullptr;    // n_nodes: level of the node (root 0)
     uint32_t *d_iperm = nullptr;   // n: leaf-order position of each database row
+    uint64_t n_blk = 0;            // blocks of 256 leaf-order rows
+    uint64_t *d_blk = nullptr;     // n_blk x 64 words: OR image of each block's rows
 };
 
 namespace qd {
 void tree_release(qd_tree_s *t);
+// Block images for the batched search (tree_blocked.hip).
+int tree_block_images(qd_tree_s *t, hipStream_t s);
+int knn_tree_blocked(qd_tree_t t, const uint64_t *d_q, uint32_t nq, uint32_t k, uint32_t *d_idx, int32_t *d_missed,
+                     int32_t *d_extra, float *d_dist, uint32_t *d_qstats, qd_stats *h_stats, hipStream_t s);
 }

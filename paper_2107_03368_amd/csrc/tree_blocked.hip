@@ -1,0 +1,736 @@
+// Batched Dissimilarity Tree search on the matrix cores (QD_ORDER_BLOCKED).
+//
+// The per-query traversal (tree_knn.hip) expands nodes one query at a time on
+// the vector ALUs.  This order searches a whole batch of queries at once over
+// the tree's leaf order cut into blocks of 256 consecutive rows.  Block b
+// holds leaf-order rows 256b .. 256b+255 and carries the sum (OR) image of
+// those rows, so every row t in it has K(q, t) >= A_lb(q, b) * wB with
+// A_lb = |q| - popcount(q AND OR_b): the node bound of Section 4.2 applied to
+// the block's rows.  Leaf order keeps each subtree's rows together, so a
+// block's image is about as tight as the image of a subtree of that size.
+//
+//  1. Bounds: A_lb for every (query, block) pair, on the matrix cores (the
+//     shared overlap tile, with the block images as B rows).
+//  2. Plan, per query: sorting the blocks by (A_lb, b) defines the rounds.
+//     Round 1 takes the first 16 blocks; round r >= 2 extends the covered
+//     prefix to about T2 * 2^(r-2) blocks, rounded down to whole bound levels
+//     (at least one more level), and the last round takes everything left.
+//  3. Round 1 (vector ALUs, one wave per query): the exact top k over the
+//     rows of those blocks, which gives the first k-th key.
+//  4. Rounds r >= 2 (matrix cores): block b takes part for query q when its
+//     (A_lb, b) lies in q's range for the round and A_lb * wB <= q's k-th
+//     key.  Every block lists its queries in query order; each tile of 256
+//     listed queries x the block's 256 rows is one overlap tile, and every row
+//     with K <= the query's k-th key is appended to the query's candidate
+//     buffer.  Each query then merges its candidates into its top k.  A query
+//     stops when no remaining block can hold a key <= its k-th key.
+//  5. Results; a query whose candidate buffer overflowed is searched again by
+//     the per-query best-first traversal.
+//
+// Exactness: a row with K <= the final k-th key lies in a block whose bound
+// is at most that key, hence at most the query's k-th key in every round (it
+// only decreases), so the block is evaluated in the round that covers its
+// (A_lb, b) and the row is appended.  The top k of the appended rows under
+// (K, row) are therefore the sequential-search result.
+#include <algorithm>
+#include <vector>
+
+#include "mfma_tile.h"
+#include "qd_device.h"
+#include "qd_internal.h"
+#include "qd_tree.h"
+
+namespace qd {
+
+int popcount_rows_launch(const uint64_t *d_db, uint64_t n, uint16_t *d_pop, hipStream_t s);
+int knn_tree_impl(qd_tree_t t, const uint64_t *d_q, uint32_t nq, uint32_t k, int order, const float *d_scores,
+                  uint32_t n_scored, uint32_t *d_idx, int32_t *d_missed, int32_t *d_extra, float *d_dist,
+                  uint32_t *d_qstats, qd_stats *h_stats, void *stream, uint32_t waves_per_cu, uint32_t *d_trace,
+                  uint32_t n_traced);
+
+namespace {
+
+constexpr uint32_t kBlk = mt::MB;          // rows per block
+constexpr uint32_t kM1 = 16;               // blocks in round 1
+constexpr int kRounds = 24;                // rounds 1 .. kRounds; the last takes every remaining block
+constexpr uint32_t kCap = 8128;            // candidate slots per query per round (kCap + k <= 8192)
+constexpr int kGroup = 16;                 // blocks per wave when building the lists
+constexpr uint32_t kInf = 0xFFFFFFFFu;
+constexpr uint32_t kLevels = QD_BITS + 1;  // A_lb in 0 .. 4096
+constexpr uint32_t kMaxBatch = 16384;      // queries per batch (list entries are 16-bit)
+
+// Position of block b of bound level L in the per-query block order; a round
+// covers the keys in (lo, hi].  Key 0 is below every block.
+__device__ __forceinline__ u64 range_key(uint32_t level, uint32_t b) { return ((u64)(level + 1) << 32) | b; }
+// Largest key of a block whose bound A_lb * wB does not exceed K.
+__device__ __forceinline__ u64 cap_key(uint32_t K, uint32_t wb) {
+    return K == kInf ? ~0ull : range_key(K / wb, kInf);
+}
+
+__device__ __forceinline__ uint32_t weight_a(uint32_t pq) { return pq > 1 ? pq : 1; }
+__device__ __forceinline__ uint32_t weight_b(uint32_t pq) { return (QD_BITS - pq) > 1 ? QD_BITS - pq : 1; }
+
+__device__ __forceinline__ uint32_t lanes_below(u64 mask) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+// OR image of each block of 256 leaf-order rows; one 64-thread block per
+// image, thread w owns word w.
+__global__ __launch_bounds__(64) void block_image_kernel(const uint64_t *__restrict__ sorted, uint64_t n,
+                                                         uint64_t *__restrict__ img) {
+    const uint64_t b = blockIdx.x;
+    const int w = threadIdx.x;
+    const uint64_t r0 = b * kBlk, r1 = r0 + kBlk < n ? r0 + kBlk : n;
+    uint64_t acc = 0;
+    for (uint64_t r = r0; r < r1; r++) acc |= sorted[r * QD_WORDS + w];
+    img[b * QD_WORDS + w] = acc;
+}
+
+// A_lb for a tile of 256 queries x 256 blocks, stored query-major
+// (lbq[q][b], for the per-query plan) and block-major (lbb[b][q], for the
+// per-block lists).  Queries q >= nqb get level 0xFFFF in lbb.
+__global__ __launch_bounds__(mt::kThreads) void bound_kernel(const uint4 *__restrict__ q, uint32_t nqb, uint32_t nqp,
+                                                             const uint4 *__restrict__ img, uint64_t nblk,
+                                                             const uint16_t *__restrict__ qpop, uint32_t n_qtiles,
+                                                             uint16_t *__restrict__ lbq, uint16_t *__restrict__ lbb) {
+    __shared__ mt::Smem sm;
+    const uint32_t q0 = (blockIdx.x % n_qtiles) * mt::MA;
+    const uint64_t b0 = (uint64_t)(blockIdx.x / n_qtiles) * mt::MB;
+    const uint4 *src[mt::kLoads];
+#pragma unroll
+    for (int u = 0; u < mt::kLoads; u++) {
+        const int r = mt::slot_row(u);
+        if (r < mt::MA)
+            src[u] = q0 + r < nqb ? q + (uint64_t)(q0 + r) * 32 : nullptr;
+        else
+            src[u] = b0 + (r - mt::MA) < nblk ? img + (b0 + (r - mt::MA)) * 32 : nullptr;
+    }
+    mt::v4i acc[8][4];
+    mt::overlap_tile(src, sm, acc);
+#pragma unroll
+    for (int a = 0; a < 8; a++)
+#pragma unroll
+        for (int bb = 0; bb < 4; bb++) {
+            const uint64_t blk = b0 + mt::acc_brow(bb);
+            if (blk >= nblk) continue;
+            const uint32_t qa = q0 + mt::acc_arow(a, 0);  // this lane's 4 consecutive queries
+            u64 packed = 0;
+#pragma unroll
+            for (int r = 0; r < 4; r++) {
+                const uint32_t qi = qa + r;
+                uint32_t v = 0xFFFFu;
+                if (qi < nqb) {
+                    v = (uint32_t)qpop[qi] - (uint32_t)acc[a][bb][r];
+                    lbq[(uint64_t)qi * nblk + blk] = (uint16_t)v;
+                }
+                packed |= (u64)v << (16 * r);
+            }
+            *reinterpret_cast<u64 *>(lbb + blk * nqp + qa) = packed;
+        }
+}
+
+// Per query: histogram of A_lb over the blocks, round 1's blocks (the first
+// min(16, nblk) in (A_lb, b) order, listed in block order) and the range end
+// of every round.  One 256-thread block per query.
+__global__ __launch_bounds__(256) void plan_kernel(const uint16_t *__restrict__ lbq, uint64_t nblk, uint64_t t2,
+                                                   u64 *__restrict__ cuts, uint32_t *__restrict__ r1list) {
+    __shared__ uint32_t cum[kLevels];
+    __shared__ uint32_t part[2][256];
+    __shared__ uint32_t s_bcut;
+    const uint32_t qi = blockIdx.x, tid = threadIdx.x;
+    const uint16_t *row = lbq + (uint64_t)qi * nblk;
+    for (uint32_t i = tid; i < kLevels; i += 256) cum[i] = 0;
+    if (tid == 0) s_bcut = kInf;
+    __syncthreads();
+    for (uint64_t b = tid; b < nblk; b += 256) atomicAdd(&cum[row[b]], 1u);
+    __syncthreads();
+    // inclusive prefix over the levels; thread t owns levels [t*per, t*per+per)
+    constexpr uint32_t per = (kLevels + 255) / 256;
+    uint32_t s = 0;
+    for (uint32_t i = 0; i < per; i++) {
+        const uint32_t L = tid * per + i;
+        if (L < kLevels) s += cum[L];
+    }
+    part[0][tid] = s;
+    __syncthreads();
+    if (tid == 0) {
+        uint32_t run = 0;
+        for (int t = 0; t < 256; t++) {
+            const uint32_t v = part[0][t];
+            part[0][t] = run;
+            run += v;
+        }
+    }
+    __syncthreads();
+    {
+        uint32_t run = part[0][tid];
+        for (uint32_t i = 0; i < per; i++) {
+            const uint32_t L = tid * per + i;
+            if (L < kLevels) {
+                run += cum[L];
+                cum[L] = run;
+            }
+        }
+    }
+    __syncthreads();
+    // round 1: all blocks below level L1 and the first r1 blocks of level L1
+    const uint32_t T1 = (uint32_t)(nblk < kM1 ? nblk : kM1);
+    uint32_t lo = 0, hi = kLevels - 1;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi) / 2;
+        if (cum[mid] >= T1)
+            hi = mid;
+        else
+            lo = mid + 1;
+    }
+    const uint32_t L1 = lo;
+    const uint32_t before = L1 ? cum[L1 - 1] : 0;
+    const uint32_t r1 = T1 - before, at_level = cum[L1] - before;
+    // ordered pass over contiguous chunks of blocks
+    const uint64_t chunk = (nblk + 255) / 256;
+    const uint64_t c0 = (uint64_t)tid * chunk, c1 = c0 + chunk < nblk ? c0 + chunk : nblk;
+    uint32_t n_lt = 0, n_eq = 0;
+    for (uint64_t b = c0; b < c1; b++) {
+        const uint32_t v = row[b];
+        n_lt += v < L1;
+        n_eq += v == L1;
+    }
+    part[0][tid] = n_lt;
+    part[1][tid] = n_eq;
+    __syncthreads();
+    if (tid == 0) {
+        uint32_t a = 0, e = 0;
+        for (int t = 0; t < 256; t++) {
+            const uint32_t va = part[0][t], ve = part[1][t];
+            part[0][t] = a;
+            part[1][t] = e;
+            a += va;
+            e += ve;
+        }
+    }
+    __syncthreads();
+    {
+        uint32_t eq_rank = part[1][tid];
+        uint32_t pos = part[0][tid] + (eq_rank < r1 ? eq_rank : r1);
+        for (uint64_t b = c0; b < c1; b++) {
+            const uint32_t v = row[b];
+            bool in = v < L1;
+            if (v == L1) {
+                in = eq_rank < r1;
+                if (eq_rank + 1 == r1 && r1 < at_level) s_bcut = (uint32_t)b;
+                eq_rank++;
+            }
+            if (in) r1list[(uint64_t)qi * kM1 + pos++] = (uint32_t)b;
+        }
+    }
+    __syncthreads();
+    if (tid == 0) {
+        u64 *c = cuts + (uint64_t)qi * (kRounds + 1);
+        c[0] = 0;
+        c[1] = range_key(L1, s_bcut);
+        uint32_t Lp = L1;
+        bool whole = s_bcut == kInf;
+        uint64_t T = t2;
+        for (int r = 2; r <= kRounds; r++) {
+            uint32_t L = kLevels - 1;
+            if (r < kRounds) {
+                // largest level whose cumulative count is <= T (or none)
+                int best = -1;
+                uint32_t a = 0, b = kLevels;  // search in [a, b)
+                while (a < b) {
+                    const uint32_t mid = (a + b) / 2;
+                    if ((uint64_t)cum[mid] <= T) {
+                        best = (int)mid;
+                        a = mid + 1;
+                    } else {
+                        b = mid;
+                    }
+                }
+                const uint32_t need = Lp + (whole ? 1u : 0u);
+                L = best >= (int)need ? (uint32_t)best : need;
+                if (L > kLevels - 1) L = kLevels - 1;
+            }
+            c[r] = range_key(L, kInf);
+            Lp = L;
+            whole = true;
+            T = T < (1ull << 40) ? 2 * T : T;
+        }
+    }
+}
+
+// Round 1 on the vector ALUs: one wave per query keeps the exact top k over
+// the rows of its round-1 blocks (8 lanes per row, 8 rows per step), then
+// sets the k-th key and the range of round 2.
+__global__ __launch_bounds__(256) void round1_kernel(const uint4 *__restrict__ q, uint32_t nqb, uint32_t k,
+                                                     const uint4 *__restrict__ sorted,
+                                                     const uint16_t *__restrict__ tpop,
+                                                     const uint32_t *__restrict__ perm, uint64_t n, uint64_t nblk,
+                                                     const uint32_t *__restrict__ r1list, uint32_t n1,
+                                                     const u64 *__restrict__ cuts, const uint16_t *__restrict__ qpop,
+                                                     u64 *__restrict__ top, uint32_t *__restrict__ ntop,
+                                                     uint32_t *__restrict__ thrk, u64 *__restrict__ rec,
+                                                     uint32_t *__restrict__ counters, uint32_t *__restrict__ qst) {
+    const int lane = lane_id();
+    const uint32_t qi = readfirst(blockIdx.x * 4 + (threadIdx.x >> 6));
+    if (qi >= nqb) return;
+    const int g = lane >> 3, j = lane & 7;
+    uint4 qv[4];
+#pragma unroll
+    for (int i = 0; i < 4; i++) qv[i] = q[(uint64_t)qi * 32 + j + 8 * i];
+    const uint32_t pq = readfirst(qpop[qi]);
+    const uint32_t wa = weight_a(pq), wb = weight_b(pq);
+    u64 list = KEY_NONE;  // lane r holds the r-th best key (K << 32 | row)
+    uint32_t kworst = kInf;
+    uint32_t rows = 0;
+    for (uint32_t i = 0; i < n1; i++) {
+        const uint32_t b = readfirst(r1list[(uint64_t)qi * kM1 + i]);
+        const uint64_t r0 = (uint64_t)b * kBlk;
+        const uint32_t m = readfirst((uint32_t)(n - r0 < kBlk ? n - r0 : kBlk));
+        rows += m;
+        for (uint32_t base = 0; base < m; base += 8) {
+            const uint32_t r = base + (uint32_t)g;
+            const bool valid = r < m;
+            const uint64_t pos = r0 + (valid ? r : 0);
+            uint4 tv[4];
+#pragma unroll
+            for (int i2 = 0; i2 < 4; i2++) tv[i2] = sorted[pos * 32 + j + 8 * i2];
+            const uint32_t c = sum8(popc_and4(tv[0], qv[0]) + popc_and4(tv[1], qv[1]) + popc_and4(tv[2], qv[2]) +
+                                    popc_and4(tv[3], qv[3]));
+            const uint32_t K = (pq - c) * wb + ((uint32_t)tpop[pos] - c) * wa;
+            const u64 key = valid ? ((u64)K << 32) | perm[pos] : KEY_NONE;
+            const u64 lim = readlane64(list, (int)k - 1);
+            u64 mk = ballot(j == 0 && key < lim);
+            while (mk) {
+                const int L = __builtin_ctzll(mk);
+                mk &= mk - 1;
+                const u64 cand = readlane64(key, L);
+                if (cand < readlane64(list, (int)k - 1)) list = list_insert(list, cand, k);
+            }
+        }
+    }
+    kworst = readfirst((uint32_t)(readlane64(list, (int)k - 1) >> 32));
+    if (lane < (int)k) top[(uint64_t)qi * k + lane] = list;
+    const uint32_t have = (uint32_t)__popcll(ballot(list != KEY_NONE));
+    if (lane == 0) {
+        ntop[qi] = have;
+        thrk[qi] = kworst;
+        const u64 *c = cuts + (uint64_t)qi * (kRounds + 1);
+        const u64 lo = c[1];
+        u64 hi = c[2];
+        const u64 cap = cap_key(kworst, wb);
+        hi = hi < cap ? hi : cap;
+        const bool active = hi > lo;
+        rec[2 * qi] = lo;
+        rec[2 * qi + 1] = active ? hi : 0;
+        if (active) atomicAdd(&counters[0], 1u);
+        if (qst) {
+            qst[(uint64_t)qi * 4 + 0] = n1;
+            qst[(uint64_t)qi * 4 + 1] = 1;
+            qst[(uint64_t)qi * 4 + 2] = (uint32_t)nblk;
+            qst[(uint64_t)qi * 4 + 3] = rows;
+        }
+    }
+}
+
+// Per-block query lists for one round: wave w of block x handles the
+// kGroup blocks starting at (4x + w) * kGroup and walks the queries in order.
+__global__ __launch_bounds__(256) void list_kernel(const uint16_t *__restrict__ lbb, uint64_t nblk, uint64_t n,
+                                                   uint32_t nqb, uint32_t nqp, const u64 *__restrict__ rec,
+                                                   uint16_t *__restrict__ list, uint32_t *__restrict__ cnt,
+                                                   uint32_t *__restrict__ qst) {
+    const int lane = lane_id();
+    const uint64_t b0 = ((uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * kGroup;
+    if (b0 >= nblk) return;
+    const uint32_t nb = readfirst((uint32_t)(nblk - b0 < (uint64_t)kGroup ? nblk - b0 : kGroup));
+    uint32_t c[kGroup];
+#pragma unroll
+    for (int jj = 0; jj < kGroup; jj++) c[jj] = 0;
+    for (uint32_t q0 = 0; q0 < nqb; q0 += 64) {
+        const uint32_t qi = q0 + (uint32_t)lane;
+        u64 lo = 0, hi = 0;
+        if (qi < nqb) {
+            lo = rec[2 * qi];
+            hi = rec[2 * qi + 1];
+        }
+        if (ballot(hi > lo) == 0) continue;
+        uint32_t mb = 0, mr = 0;
+#pragma unroll
+        for (int jj = 0; jj < kGroup; jj++) {
+            if ((uint32_t)jj < nb) {
+                const uint64_t b = b0 + jj;
+                const uint32_t lv = lbb[b * nqp + qi];
+                const u64 key = range_key(lv, (uint32_t)b);
+                const bool m = key > lo && key <= hi;
+                const u64 mask = ballot(m);
+                if (m) list[b * nqp + c[jj] + lanes_below(mask)] = (uint16_t)qi;
+                c[jj] += (uint32_t)__popcll(mask);
+                if (m) {
+                    mb++;
+                    mr += (uint32_t)(n - b * kBlk < kBlk ? n - b * kBlk : kBlk);
+                }
+            }
+        }
+        if (qst && mb) {
+            atomicAdd(&qst[(uint64_t)qi * 4 + 0], mb);
+            atomicAdd(&qst[(uint64_t)qi * 4 + 3], mr);
+        }
+    }
+    if (lane == 0)
+        for (uint32_t jj = 0; jj < nb; jj++) cnt[b0 + jj] = c[jj];
+}
+
+// Exclusive prefix of the tiles per block (256 listed queries per tile);
+// off[nblk] and *total receive the sum.
+__global__ __launch_bounds__(1024) void tile_scan_kernel(const uint32_t *__restrict__ cnt, uint64_t nblk,
+                                                         uint32_t *__restrict__ off, uint32_t *__restrict__ total) {
+    __shared__ uint32_t part[1024];
+    const uint32_t tid = threadIdx.x;
+    const uint64_t chunk = (nblk + 1023) / 1024;
+    const uint64_t c0 = (uint64_t)tid * chunk, c1 = c0 + chunk < nblk ? c0 + chunk : nblk;
+    uint32_t s = 0;
+    for (uint64_t b = c0; b < c1; b++) s += (cnt[b] + mt::MA - 1) / mt::MA;
+    part[tid] = s;
+    __syncthreads();
+    for (uint32_t d = 1; d < 1024; d <<= 1) {
+        const uint32_t v = tid >= d ? part[tid - d] : 0;
+        __syncthreads();
+        part[tid] += v;
+        __syncthreads();
+    }
+    uint32_t run = part[tid] - s;
+    for (uint64_t b = c0; b < c1; b++) {
+        off[b] = run;
+        run += (cnt[b] + mt::MA - 1) / mt::MA;
+    }
+    if (tid == 1023) {
+        off[nblk] = part[1023];
+        *total = part[1023];
+    }
+}
+
+// One tile: 256 listed queries of block b x the block's rows.  Block b and
+// the tile index come from the tile prefix (binary search).
+__global__ __launch_bounds__(mt::kThreads) void eval_kernel(const uint4 *__restrict__ q, const uint4 *__restrict__ sorted,
+                                                            uint64_t n, uint64_t nblk, uint32_t nqp,
+                                                            const uint16_t *__restrict__ list,
+                                                            const uint32_t *__restrict__ cnt,
+                                                            const uint32_t *__restrict__ off,
+                                                            const uint16_t *__restrict__ tpop,
+                                                            const uint32_t *__restrict__ perm,
+                                                            const uint16_t *__restrict__ qpop,
+                                                            const uint32_t *__restrict__ thrk,
+                                                            uint32_t *__restrict__ ccnt, u64 *__restrict__ cand) {
+    __shared__ mt::Smem sm;
+    const uint32_t x = blockIdx.x;
+    uint64_t lo = 0, hi = nblk;  // off[lo] <= x < off[hi]
+    while (hi - lo > 1) {
+        const uint64_t mid = (lo + hi) / 2;
+        if (off[mid] <= x)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    const uint64_t b = lo;
+    const uint32_t t0 = (x - off[b]) * mt::MA;
+    const uint32_t left = cnt[b] - t0;
+    const uint32_t m = left < (uint32_t)mt::MA ? left : (uint32_t)mt::MA;
+    const uint16_t *lq = list + b * nqp + t0;
+    const uint64_t r0 = b * kBlk;
+    const uint4 *src[mt::kLoads];
+#pragma unroll
+    for (int u = 0; u < mt::kLoads; u++) {
+        const int r = mt::slot_row(u);
+        if (r < mt::MA)
+            src[u] = (uint32_t)r < m ? q + (uint64_t)lq[r] * 32 : nullptr;
+        else
+            src[u] = r0 + (r - mt::MA) < n ? sorted + (r0 + (r - mt::MA)) * 32 : nullptr;
+    }
+    mt::v4i acc[8][4];
+    mt::overlap_tile(src, sm, acc);
+#pragma unroll
+    for (int a = 0; a < 8; a++)
+#pragma unroll
+        for (int r = 0; r < 4; r++) {
+            const uint32_t i = (uint32_t)mt::acc_arow(a, r);
+            if (i >= m) continue;
+            const uint32_t qi = lq[i];
+            const uint32_t pq = qpop[qi];
+            const uint32_t wa = weight_a(pq), wb = weight_b(pq);
+            const uint32_t th = thrk[qi];
+#pragma unroll
+            for (int bb = 0; bb < 4; bb++) {
+                const uint64_t row = r0 + mt::acc_brow(bb);
+                if (row >= n) continue;
+                const uint32_t C = (uint32_t)acc[a][bb][r];
+                const uint32_t K = (pq - C) * wb + ((uint32_t)tpop[row] - C) * wa;
+                if (K <= th) {
+                    const uint32_t pos = atomicAdd(&ccnt[qi], 1u);
+                    if (pos < kCap) cand[(uint64_t)qi * kCap + pos] = ((u64)K << 32) | perm[row];
+                }
+            }
+        }
+}
+
+// After round r: merge each running query's candidates into its top k, update
+// its k-th key and set its range for round r + 1.  One block per query.
+__global__ __launch_bounds__(256) void select_kernel(uint32_t k, int r, const uint16_t *__restrict__ qpop,
+                                                     const u64 *__restrict__ cuts, u64 *__restrict__ rec,
+                                                     uint32_t *__restrict__ ccnt, const u64 *__restrict__ cand,
+                                                     u64 *__restrict__ top, uint32_t *__restrict__ ntop,
+                                                     uint32_t *__restrict__ thrk, uint32_t *__restrict__ counters,
+                                                     uint32_t *__restrict__ redo, uint32_t *__restrict__ qst) {
+    __shared__ u64 keys[8192];
+    const uint32_t qi = blockIdx.x;
+    const u64 lo = rec[2 * qi], hi = rec[2 * qi + 1];
+    if (!(hi > lo)) return;  // not running
+    const uint32_t m = ccnt[qi];
+    if (m > kCap) {
+        if (threadIdx.x == 0) {
+            redo[atomicAdd(&counters[1], 1u)] = qi;
+            rec[2 * qi + 1] = 0;
+            ccnt[qi] = 0;
+        }
+        return;
+    }
+    const uint32_t nt = ntop[qi];
+    uint32_t have = nt, th = thrk[qi];
+    if (m > 0) {
+        const uint32_t total = nt + m;
+        const uint32_t np = next_pow2(total < 2 ? 2 : total);
+        for (uint32_t i = threadIdx.x; i < np; i += 256)
+            keys[i] = i < nt ? top[(uint64_t)qi * k + i] : (i < total ? cand[(uint64_t)qi * kCap + (i - nt)] : KEY_NONE);
+        __syncthreads();
+        block_bitonic_sort(keys, np);
+        have = total < k ? total : k;
+        for (uint32_t i = threadIdx.x; i < have; i += 256) top[(uint64_t)qi * k + i] = keys[i];
+        th = have == k ? (uint32_t)(keys[k - 1] >> 32) : kInf;
+    }
+    if (threadIdx.x == 0) {
+        ntop[qi] = have;
+        thrk[qi] = th;
+        ccnt[qi] = 0;
+        if (qst) qst[(uint64_t)qi * 4 + 1] += 1;
+        const u64 *c = cuts + (uint64_t)qi * (kRounds + 1);
+        const u64 nlo = c[r];
+        u64 nhi = 0;
+        if (r < kRounds) {
+            const uint32_t pq = qpop[qi];
+            const u64 cap = cap_key(th, weight_b(pq));
+            nhi = c[r + 1] < cap ? c[r + 1] : cap;
+        }
+        const bool active = nhi > nlo;
+        rec[2 * qi] = nlo;
+        rec[2 * qi + 1] = active ? nhi : 0;
+        if (active) atomicAdd(&counters[0], 1u);
+    }
+}
+
+// Results from the top-k keys: one wave per query, lane r writes rank r.
+__global__ __launch_bounds__(256) void emit_kernel(const uint64_t *__restrict__ q, uint32_t nqb, uint32_t k,
+                                                   const u64 *__restrict__ top, const uint32_t *__restrict__ ntop,
+                                                   const uint64_t *__restrict__ sorted,
+                                                   const uint32_t *__restrict__ iperm, uint32_t *idx, int32_t *missed,
+                                                   int32_t *extra, float *dist, const uint32_t *__restrict__ qst,
+                                                   uint32_t *d_qstats, unsigned long long *gstats) {
+    const int lane = lane_id();
+    const uint32_t qi = readfirst(blockIdx.x * 4 + (threadIdx.x >> 6));
+    if (qi >= nqb) return;
+    const uint32_t nt = ntop[qi];
+    if (lane < (int)k) {
+        const uint64_t o = (uint64_t)qi * k + lane;
+        if ((uint32_t)lane >= nt) {
+            idx[o] = QD_PAD_IDX;
+            missed[o] = -1;
+            extra[o] = -1;
+            dist[o] = __builtin_inff();
+        } else {
+            const u64 e = top[o];
+            const uint32_t row = (uint32_t)e;
+            const uint64_t *qq = q + (uint64_t)qi * QD_WORDS;
+            const uint64_t *tt = sorted + (uint64_t)iperm[row] * QD_WORDS;
+            uint32_t a = 0, b = 0, pq = 0;
+            for (int w = 0; w < QD_WORDS; w++) {
+                const uint64_t x = qq[w], y = tt[w];
+                a += __popcll(x & ~y);
+                b += __popcll(~x & y);
+                pq += __popcll(x);
+            }
+            const uint32_t wa = weight_a(pq), wb = weight_b(pq);
+            idx[o] = row;
+            missed[o] = (int32_t)a;
+            extra[o] = (int32_t)b;
+            dist[o] = (float)((double)(a * wb + b * wa) / ((double)wa * (double)wb));
+        }
+    }
+    if (qst && lane < 4) {
+        const uint32_t v = qst[(uint64_t)qi * 4 + lane];
+        if (d_qstats) d_qstats[(uint64_t)qi * 4 + lane] = v;
+        if (gstats) atomicAdd(&gstats[lane], (unsigned long long)v);
+    }
+}
+
+__global__ void gather_kernel(const uint4 *__restrict__ q, const uint32_t *__restrict__ list, uint32_t m,
+                              uint4 *__restrict__ out) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < m * 32) out[i] = q[(uint64_t)list[i >> 5] * 32 + (i & 31)];
+}
+
+template <class T>
+__global__ void scatter_kernel(const T *__restrict__ src, const uint32_t *__restrict__ list, uint32_t m, uint32_t k,
+                               T *__restrict__ dst) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < m * k) dst[(uint64_t)list[i / k] * k + (i % k)] = src[i];
+}
+
+inline size_t up256(size_t x) { return (x + 255) / 256 * 256; }
+
+}  // namespace
+
+int tree_block_images(qd_tree_s *t, hipStream_t s) {
+    t->n_blk = (t->n + kBlk - 1) / kBlk;
+    QD_HIP_CHECK(hipMalloc((void **)&t->d_blk, t->n_blk * 512));
+    hipLaunchKernelGGL(block_image_kernel, dim3((uint32_t)t->n_blk), dim3(64), 0, s, t->d_sorted, t->n, t->d_blk);
+    QD_HIP_CHECK(hipGetLastError());
+    return QD_OK;
+}
+
+int knn_tree_blocked(qd_tree_t t, const uint64_t *d_q, uint32_t nq, uint32_t k, uint32_t *d_idx, int32_t *d_missed,
+                     int32_t *d_extra, float *d_dist, uint32_t *d_qstats, qd_stats *h_stats, hipStream_t s) {
+    const uint64_t n = t->n, nblk = t->n_blk;
+    if (!t->d_blk || nblk == 0) return fail(QD_ERR_INVALID, "tree has no block images");
+    if (nblk > 0x7FFFFFFFull) return fail(QD_ERR_UNSUPPORTED, "too many blocks");
+    // batch: up to kMaxBatch queries, bound and list matrices within about 12 GiB
+    uint32_t qb = nq < kMaxBatch ? nq : kMaxBatch;
+    auto batch_bytes = [&](uint32_t b) { return (uint64_t)up256(b) * (nblk * 6 + kCap * 8 + (uint64_t)k * 8 + 512); };
+    while (qb > 256 && batch_bytes(qb) > (12ull << 30)) qb = (qb + 1) / 2;
+    const size_t P = up256(qb);
+    // workspace
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = o;
+        o += up256(bytes);
+        return at;
+    };
+    const size_t a_qpop = take(P * 2), a_lbq = take(P * nblk * 2), a_lbb = take(P * nblk * 2),
+                 a_list = take(P * nblk * 2), a_cuts = take(P * (kRounds + 1) * 8), a_r1 = take(P * kM1 * 4),
+                 a_rec = take(P * 16), a_thr = take(P * 4), a_ntop = take(P * 4), a_top = take(P * k * 8),
+                 a_ccnt = take(P * 4), a_cand = take(P * kCap * 8), a_cnt = take(nblk * 4),
+                 a_off = take((nblk + 1) * 4), a_ctr = take(16), a_redo = take(P * 4), a_qst = take(P * 16),
+                 a_gst = take(32);
+    char *ws = nullptr;
+    QD_HIP_CHECK(hipMallocAsync((void **)&ws, o, s));
+    uint16_t *qpop = (uint16_t *)(ws + a_qpop), *lbq = (uint16_t *)(ws + a_lbq), *lbb = (uint16_t *)(ws + a_lbb),
+             *list = (uint16_t *)(ws + a_list);
+    u64 *cuts = (u64 *)(ws + a_cuts), *rec = (u64 *)(ws + a_rec), *top = (u64 *)(ws + a_top),
+        *cand = (u64 *)(ws + a_cand);
+    uint32_t *r1list = (uint32_t *)(ws + a_r1), *thr = (uint32_t *)(ws + a_thr), *ntop = (uint32_t *)(ws + a_ntop),
+             *ccnt = (uint32_t *)(ws + a_ccnt), *cnt = (uint32_t *)(ws + a_cnt), *off = (uint32_t *)(ws + a_off),
+             *ctr = (uint32_t *)(ws + a_ctr), *redo = (uint32_t *)(ws + a_redo), *qst = (uint32_t *)(ws + a_qst);
+    unsigned long long *gst = (unsigned long long *)(ws + a_gst);
+    const bool want_stats = d_qstats || h_stats;
+    int rc = QD_OK;
+    auto done = [&](int code) {
+        (void)hipFreeAsync(ws, s);
+        return code;
+    };
+    if (hipMemsetAsync(gst, 0, 32, s) != hipSuccess) return done(fail(QD_ERR_DEVICE, "memset"));
+    for (uint32_t qb0 = 0; qb0 < nq; qb0 += qb) {
+        const uint32_t nqb = nq - qb0 < qb ? nq - qb0 : qb;
+        const uint32_t nqp = (uint32_t)up256(nqb);
+        const uint64_t *qq = d_q + (uint64_t)qb0 * QD_WORDS;
+        const uint4 *q4 = reinterpret_cast<const uint4 *>(qq);
+        rc = popcount_rows_launch(qq, nqb, qpop, s);
+        if (rc != QD_OK) return done(rc);
+        if (hipMemsetAsync(ccnt, 0, (size_t)nqb * 4, s) != hipSuccess || hipMemsetAsync(ctr, 0, 16, s) != hipSuccess)
+            return done(fail(QD_ERR_DEVICE, "memset"));
+        const uint32_t n_qtiles = nqp / mt::MA;
+        const uint64_t n_btiles = (nblk + mt::MB - 1) / mt::MB;
+        {
+            KernelTimer timer("tree_block_bounds", s);
+            hipLaunchKernelGGL(bound_kernel, dim3((uint32_t)(n_qtiles * n_btiles)), dim3(mt::kThreads), 0, s, q4, nqb,
+                               nqp, reinterpret_cast<const uint4 *>(t->d_blk), nblk, qpop, n_qtiles, lbq, lbb);
+        }
+        // round 2 covers about t2 blocks per query: enough that a block's list
+        // holds ~128 queries on average
+        uint64_t t2 = (128 * nblk + nqb - 1) / nqb;
+        if (t2 < 4 * kM1) t2 = 4 * kM1;
+        hipLaunchKernelGGL(plan_kernel, dim3(nqb), dim3(256), 0, s, lbq, nblk, t2, cuts, r1list);
+        const uint32_t n1 = (uint32_t)(nblk < kM1 ? nblk : kM1);
+        {
+            KernelTimer timer("tree_block_round1", s);
+            hipLaunchKernelGGL(round1_kernel, dim3((nqb + 3) / 4), dim3(256), 0, s, q4, nqb, k,
+                               reinterpret_cast<const uint4 *>(t->d_sorted), t->d_pop, t->d_perm, n, nblk, r1list, n1,
+                               cuts, qpop, top, ntop, thr, rec, ctr, want_stats ? qst : nullptr);
+        }
+        if (hipGetLastError() != hipSuccess) return done(fail(QD_ERR_DEVICE, "blocked search: launch failed"));
+        for (int r = 2; r <= kRounds; r++) {
+            {
+                KernelTimer timer("tree_block_lists", s);
+                const uint64_t waves = (nblk + kGroup - 1) / kGroup;
+                hipLaunchKernelGGL(list_kernel, dim3((uint32_t)((waves + 3) / 4)), dim3(256), 0, s, lbb, nblk, n, nqb,
+                                   nqp, rec, list, cnt, want_stats ? qst : nullptr);
+                hipLaunchKernelGGL(tile_scan_kernel, dim3(1), dim3(1024), 0, s, cnt, nblk, off, ctr + 2);
+            }
+            uint32_t h[4];
+            hipError_t e = hipMemcpyAsync(h, ctr, 16, hipMemcpyDeviceToHost, s);
+            if (e == hipSuccess) e = hipStreamSynchronize(s);
+            if (e != hipSuccess) return done(fail(QD_ERR_DEVICE, "blocked search: %s", hipGetErrorString(e)));
+            if (h[0] == 0) break;  // no query runs in this round
+            if (hipMemsetAsync(ctr, 0, 4, s) != hipSuccess) return done(fail(QD_ERR_DEVICE, "memset"));
+            if (h[2] > 0) {
+                KernelTimer timer("tree_block_eval", s);
+                hipLaunchKernelGGL(eval_kernel, dim3(h[2]), dim3(mt::kThreads), 0, s, q4,
+                                   reinterpret_cast<const uint4 *>(t->d_sorted), n, nblk, nqp, list, cnt, off,
+                                   t->d_pop, t->d_perm, qpop, thr, ccnt, cand);
+            }
+            {
+                KernelTimer timer("tree_block_select", s);
+                hipLaunchKernelGGL(select_kernel, dim3(nqb), dim3(256), 0, s, k, r, qpop, cuts, rec, ccnt, cand, top,
+                                   ntop, thr, ctr, redo, want_stats ? qst : nullptr);
+            }
+            if (hipGetLastError() != hipSuccess) return done(fail(QD_ERR_DEVICE, "blocked search: launch failed"));
+        }
+        uint32_t *oi = d_idx + (uint64_t)qb0 * k;
+        int32_t *om = d_missed + (uint64_t)qb0 * k, *ox = d_extra + (uint64_t)qb0 * k;
+        float *od = d_dist + (uint64_t)qb0 * k;
+        hipLaunchKernelGGL(emit_kernel, dim3((nqb + 3) / 4), dim3(256), 0, s, qq, nqb, k, top, ntop, t->d_sorted,
+                           t->d_iperm, oi, om, ox, od, want_stats ? qst : nullptr,
+                           d_qstats ? d_qstats + (uint64_t)qb0 * 4 : nullptr, h_stats ? gst : nullptr);
+        // queries whose candidate buffer overflowed
+        uint32_t h_redo = 0;
+        hipError_t e = hipMemcpyAsync(&h_redo, ctr + 1, 4, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return done(fail(QD_ERR_DEVICE, "blocked search: %s", hipGetErrorString(e)));
+        if (h_redo > 0) {
+            char *fb = nullptr;
+            QD_HIP_CHECK(hipMallocAsync((void **)&fb, (size_t)h_redo * (512 + (size_t)k * 16), s));
+            uint4 *gq = reinterpret_cast<uint4 *>(fb);
+            uint32_t *ri = reinterpret_cast<uint32_t *>(fb + (size_t)h_redo * 512);
+            int32_t *rm = reinterpret_cast<int32_t *>(ri + (size_t)h_redo * k), *rx = rm + (size_t)h_redo * k;
+            float *rd = reinterpret_cast<float *>(rx + (size_t)h_redo * k);
+            hipLaunchKernelGGL(gather_kernel, dim3((h_redo * 32 + 255) / 256), dim3(256), 0, s, q4, redo, h_redo, gq);
+            rc = knn_tree_impl(t, reinterpret_cast<const uint64_t *>(gq), h_redo, k, QD_ORDER_BEST_FIRST, nullptr, 0,
+                               ri, rm, rx, rd, nullptr, nullptr, s, 0, nullptr, 0);
+            if (rc == QD_OK) {
+                const dim3 g((h_redo * k + 255) / 256);
+                hipLaunchKernelGGL(scatter_kernel<uint32_t>, g, dim3(256), 0, s, ri, redo, h_redo, k, oi);
+                hipLaunchKernelGGL(scatter_kernel<int32_t>, g, dim3(256), 0, s, rm, redo, h_redo, k, om);
+                hipLaunchKernelGGL(scatter_kernel<int32_t>, g, dim3(256), 0, s, rx, redo, h_redo, k, ox);
+                hipLaunchKernelGGL(scatter_kernel<float>, g, dim3(256), 0, s, rd, redo, h_redo, k, od);
+                if (hipGetLastError() != hipSuccess) rc = fail(QD_ERR_DEVICE, "fallback scatter");
+            }
+            (void)hipFreeAsync(fb, s);
+            if (rc != QD_OK) return done(rc);
+        }
+    }
+    if (h_stats) {
+        unsigned long long hs[4];
+        hipError_t e = hipMemcpyAsync(hs, gst, sizeof hs, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return done(fail(QD_ERR_DEVICE, "stats: %s", hipGetErrorString(e)));
+        *h_stats = qd_stats{hs[0], hs[1], hs[2], hs[3]};
+    }
+    return done(QD_OK);
+}
+
+}  // namespace qd

@@ -474,7 +474,7 @@ struct DevBuf {
 void tree_release(qd_tree_s *t) {
     if (!t) return;
     void *ptrs[] = {t->d_sorted, t->d_perm,  t->d_or,    t->d_and,   t->d_child, t->d_begin,
-                    t->d_count,  t->d_pop,   t->d_parent, t->d_depth, t->d_iperm};
+                    t->d_count,  t->d_pop,   t->d_parent, t->d_depth, t->d_iperm, t->d_blk};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     delete t;
@@ -699,6 +699,7 @@ int tree_build_impl(const uint64_t *d_db, uint64_t n, const qd_build_params *par
     hipLaunchKernelGGL(invert_perm_kernel, dim3((uint32_t)std::min<uint64_t>((n + kBlock - 1) / kBlock, 65535)),
                        dim3(kBlock), 0, s, t->d_perm, n, t->d_iperm);
     int rc = qd_popcount_rows(t->d_sorted, n, t->d_pop, stream);
+    if (rc == QD_OK) rc = tree_block_images(t, s);
     if (rc != QD_OK) return cleanup(rc);
     if (hipStreamSynchronize(s) != hipSuccess || hipGetLastError() != hipSuccess)
         return cleanup(fail(QD_ERR_DEVICE, "tree build kernels failed"));

@@ -387,12 +387,17 @@ int knn_tree_impl(qd_tree_t t, const uint64_t *d_q, uint32_t nq, uint32_t k, int
                   uint32_t n_traced) {
     if (!t) return fail(QD_ERR_INVALID, "null tree");
     if (k < 1 || k > QD_MAX_K) return fail(QD_ERR_INVALID, "k=%u outside 1..%d", k, QD_MAX_K);
-    if (order != QD_ORDER_BEST_FIRST && order != QD_ORDER_DEPTH_FIRST)
+    if (order != QD_ORDER_BEST_FIRST && order != QD_ORDER_DEPTH_FIRST && order != QD_ORDER_BLOCKED)
         return fail(QD_ERR_INVALID, "unknown frontier order %d", order);
     if (h_stats) *h_stats = qd_stats{0, 0, 0, 0};
     if (nq == 0) return QD_OK;
     if (!d_q || !d_idx || !d_missed || !d_extra || !d_dist) return fail(QD_ERR_INVALID, "null pointer");
     if (!aligned16(d_q)) return fail(QD_ERR_INVALID, "queries must be 16-byte aligned");
+    if (order == QD_ORDER_BLOCKED) {
+        if (d_scores || d_trace) return fail(QD_ERR_INVALID, "the blocked order takes no scores or traces");
+        return knn_tree_blocked(t, d_q, nq, k, d_idx, d_missed, d_extra, d_dist, d_qstats, h_stats,
+                                (hipStream_t)stream);
+    }
     if (order == QD_ORDER_DEPTH_FIRST && t->depth + 2 > (uint32_t)kMaxStack)
         return fail(QD_ERR_UNSUPPORTED, "tree depth %u exceeds the depth-first stack (%d)", t->depth, kMaxStack);
     if (n_traced > t->n_nodes) return fail(QD_ERR_INVALID, "n_traced above the node count");

@@ -1,0 +1,128 @@
+"""Batched (blocked) tree search on the matrix cores against the CPU oracle.
+
+The blocked order must return the sequential-search result bit for bit: at
+sizes that span several rounds, several query tiles per block and a ragged
+last block; on degenerate inputs; when candidate buffers overflow (the
+per-query fallback); across query batches; and at 1M rows, where every query
+is compared with the per-query best-first search and sampled ones with the
+oracle."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def qd():
+    import paper_2107_03368_amd as qd
+    return qd
+
+
+def _t(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a).view(np.int64)).to("cuda:0")
+
+
+def _np(res):
+    idx, missed, extra, dist = (x.cpu().numpy() for x in res[:4])
+    return idx.view(np.uint32), missed, extra, dist
+
+
+def _same(res, ref, rows=None):
+    idx, missed, extra, dist = _np(res)
+    if rows is not None:
+        idx, missed, extra, dist = idx[rows], missed[rows], extra[rows], dist[rows]
+    assert np.array_equal(idx, ref.idx)
+    assert np.array_equal(missed, ref.missed)
+    assert np.array_equal(extra, ref.extra)
+    assert np.array_equal(dist, ref.dist)
+
+
+@pytest.mark.parametrize("k", [1, 10, 50])
+def test_blocked_matches_oracle_10k(qd, small_db, small_queries, k):
+    q, _ = small_queries
+    tree = qd.tree_build(_t(small_db))
+    ref = oracle.knn_brute(small_db, q, k)
+    _same(qd.knn_tree(tree, _t(q), k, order=qd.ORDER_BLOCKED), ref)
+
+
+@pytest.mark.parametrize("k", [1, 10, 64])
+def test_blocked_several_rounds_and_tiles(qd, k):
+    # 60,123 rows: 235 blocks, the last one ragged; 600 queries: up to three
+    # 256-query tiles per block; the round schedule 16, 64, 128, all.
+    db = synth.gen_db(60_123, 1101)
+    q, _ = synth.gen_queries(db, 600, 2101, 0.1, 0.6)
+    tree = qd.tree_build(_t(db))
+    ref = oracle.knn_brute(db, q, k)
+    res = qd.knn_tree(tree, _t(q), k, order=qd.ORDER_BLOCKED, query_stats=True, totals=True)
+    _same(res, ref)
+    st = res[4].cpu().numpy()
+    nblk = (db.shape[0] + 255) // 256
+    assert (st[:, 0] >= 16).all() and (st[:, 0] <= nblk).all()   # blocks evaluated
+    assert (st[:, 1] >= 1).all()                                # rounds
+    assert (st[:, 2] == nblk).all()                             # blocks bounded
+    # round 1 alone evaluates 16 blocks (one of them may be the ragged last block)
+    assert (st[:, 3] <= db.shape[0]).all() and (st[:, 3] >= 15 * 256 + db.shape[0] % 256).all()
+    if k == 1:
+        assert st[:, 3].mean() < 0.9 * db.shape[0]  # the bounds prune
+
+
+def test_blocked_edge_cases(qd):
+    base = synth.gen_db(500, 71)
+    db = np.concatenate([base, base[:100], np.zeros((5, 64), np.uint64)])
+    q = np.concatenate([base[:10], np.zeros((1, 64), np.uint64), np.full((1, 64), np.uint64(0xFFFFFFFFFFFFFFFF)),
+                        synth.gen_queries(base, 8, 72, 0.2, 0.6)[0]])
+    tree = qd.tree_build(_t(db))
+    for k in (1, 7, 64):
+        _same(qd.knn_tree(tree, _t(q), k, order=qd.ORDER_BLOCKED), oracle.knn_brute(db, q, k))
+    small = synth.gen_db(3, 73)  # fewer rows than k: padded results
+    _same(qd.knn_tree(qd.tree_build(_t(small)), _t(q), 5, order=qd.ORDER_BLOCKED), oracle.knn_brute(small, q, 5))
+    one = synth.gen_db(1, 74)
+    _same(qd.knn_tree(qd.tree_build(_t(one)), _t(q), 1, order=qd.ORDER_BLOCKED), oracle.knn_brute(one, q, 1))
+
+
+def test_blocked_overflow_fallback(qd):
+    # 30,000 copies of one descriptor: after round 1 the k-th key equals the
+    # copies' key, so round 2 appends every copy of its blocks (more than a
+    # candidate buffer holds) and the queries are searched again best-first.
+    rng_db = synth.gen_db(4000, 75)
+    dup = np.repeat(rng_db[:1], 30_000, axis=0)
+    db = np.concatenate([rng_db, dup])
+    q = np.concatenate([rng_db[:3], synth.gen_queries(rng_db, 5, 76, 0.2, 0.5)[0]])
+    tree = qd.tree_build(_t(db))
+    for k in (1, 10):
+        _same(qd.knn_tree(tree, _t(q), k, order=qd.ORDER_BLOCKED), oracle.knn_brute(db, q, k))
+
+
+def test_blocked_several_batches(qd):
+    # more queries than one batch holds (16,384)
+    db = synth.gen_db(5_000, 1102)
+    q, _ = synth.gen_queries(db, 16_500, 2102, 0.1, 0.6)
+    tree = qd.tree_build(_t(db))
+    res = qd.knn_tree(tree, _t(q), 10, order=qd.ORDER_BLOCKED)
+    ref_gpu = qd.knn_bruteforce(_t(db), _t(q), 10)
+    for a, b in zip(_np(res), _np(ref_gpu)):
+        assert np.array_equal(a, b)
+    rows = np.array([0, 1, 16_383, 16_384, 16_499])
+    _same(res, oracle.knn_brute(db, q[rows], 10), rows)
+
+
+@pytest.fixture(scope="module")
+def tree_1m(qd):
+    db = synth.gen_db(1_000_000, 1001)
+    return db, qd.tree_build(_t(db))
+
+
+@pytest.mark.parametrize("k", [1, 10, 50])
+def test_blocked_1m(qd, tree_1m, k):
+    db, tree = tree_1m
+    q, _ = synth.gen_queries(db, 4096, 2001, 0.1, 0.6)
+    res = qd.knn_tree(tree, _t(q), k, order=qd.ORDER_BLOCKED)
+    best = qd.knn_tree(tree, _t(q), k)
+    for a, b in zip(_np(res), _np(best)):
+        assert np.array_equal(a, b)
+    rows = np.array([0, 7, 2048, 4095])
+    _same(res, oracle.knn_brute(db, q[rows], k), rows)
