@@ -169,10 +169,12 @@ int qd_tree_export(qd_tree_t t, int32_t *h_child, uint32_t *h_begin, uint32_t *h
  *     order is cut into blocks of 256 rows, each with the sum image of its
  *     rows; the same bound is computed for every (query, block) pair, and
  *     each query evaluates its blocks in rounds of ascending bound (a first
- *     round of 16 blocks, then about doubling), keeping only blocks whose
+ *     round of 16 blocks, then growing about 4x), keeping only blocks whose
  *     bound is <= its current k-th key, until no block is left that could
- *     hold a better key.  Queries whose candidate buffer overflows are
- *     searched again best-first.  Waits for the stream between rounds (not
+ *     hold a better key.  A query whose candidate buffer overflows repeats
+ *     the round with a tighter key; one whose key cannot tighten (more rows
+ *     tie at its k-th key than a buffer holds) is searched again best-first.
+ *     Waits for the stream between rounds (not
  *     capturable); takes no scores or traces.  Per-query stats mean: blocks
  *     evaluated, rounds taken part in, blocks bounded, distances evaluated.
  * d_query_stats (nullable): nq x 4 uint32 per query: nodes visited
@@ -192,6 +194,13 @@ typedef struct {
                               node / 32 of query j's row is set when the search expands node (< n_traced).
                               The library clears it first. */
     uint32_t n_traced;
+    /* QD_ORDER_BLOCKED round schedule (0 = default): blocks in round 1
+       (default 16, at most 64), blocks covered after round 2 (default: enough
+       for ~128 queries per block list on average), growth factor of the
+       covered prefix per later round (default 4, 2..64). */
+    uint32_t round1_blocks;
+    uint32_t round2_blocks;
+    uint32_t round_growth;
 } qd_search_params;
 
 typedef struct {

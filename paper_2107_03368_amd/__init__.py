@@ -135,7 +135,9 @@ class _TreeInfo(ctypes.Structure):
 
 class _SearchParams(ctypes.Structure):
     _fields_ = [("order", ctypes.c_int), ("d_scores", ctypes.c_void_p), ("n_scored", ctypes.c_uint32),
-                ("waves_per_cu", ctypes.c_uint32), ("d_visited", ctypes.c_void_p), ("n_traced", ctypes.c_uint32)]
+                ("waves_per_cu", ctypes.c_uint32), ("d_visited", ctypes.c_void_p), ("n_traced", ctypes.c_uint32),
+                ("round1_blocks", ctypes.c_uint32), ("round2_blocks", ctypes.c_uint32),
+                ("round_growth", ctypes.c_uint32)]
 
 
 class Stats(ctypes.Structure):
@@ -207,13 +209,15 @@ def tree_build(db, max_leaf=32, store_and_image=False):
     return Tree(h.value)
 
 
-def knn_tree(tree, q, k, order=ORDER_BEST_FIRST, scores=None, query_stats=False, totals=False, waves_per_cu=0):
-    """Exact k-NN through the tree.  Returns (idx, missed, extra, dist[, qstats][, totals])."""
+def knn_tree(tree, q, k, order=ORDER_BEST_FIRST, scores=None, query_stats=False, totals=False, waves_per_cu=0,
+             schedule=(0, 0, 0)):
+    """Exact k-NN through the tree.  Returns (idx, missed, extra, dist[, qstats][, totals]).
+    schedule: (round-1 blocks, round-2 blocks, growth) of the blocked order, 0 = default."""
     _desc(q, "q")
     nq = q.shape[0]
     idx, missed, extra, dist = _results(nq, k, q.device)
     qs = torch.empty((nq, 4), dtype=torch.int32, device=q.device) if query_stats else None
-    prm = _SearchParams(order, None, 0, waves_per_cu, None, 0)
+    prm = _SearchParams(order, None, 0, waves_per_cu, None, 0, *schedule)
     if scores is not None:
         if not (scores.is_cuda and scores.dtype == torch.float32 and scores.dim() == 2 and scores.shape[0] == nq
                 and scores.is_contiguous()):

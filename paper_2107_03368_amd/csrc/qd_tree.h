@@ -30,6 +30,7 @@ namespace qd {
 void tree_release(qd_tree_s *t);
 // Block images for the batched search (tree_blocked.hip).
 int tree_block_images(qd_tree_s *t, hipStream_t s);
-int knn_tree_blocked(qd_tree_t t, const uint64_t *d_q, uint32_t nq, uint32_t k, uint32_t *d_idx, int32_t *d_missed,
-                     int32_t *d_extra, float *d_dist, uint32_t *d_qstats, qd_stats *h_stats, hipStream_t s);
+int knn_tree_blocked(qd_tree_t t, const uint64_t *d_q, uint32_t nq, uint32_t k, const qd_search_params *p,
+                     uint32_t *d_idx, int32_t *d_missed, int32_t *d_extra, float *d_dist, uint32_t *d_qstats,
+                     qd_stats *h_stats, hipStream_t s);
 }

@@ -12,9 +12,10 @@
 //  1. Bounds: A_lb for every (query, block) pair, on the matrix cores (the
 //     shared overlap tile, with the block images as B rows).
 //  2. Plan, per query: sorting the blocks by (A_lb, b) defines the rounds.
-//     Round 1 takes the first 16 blocks; round r >= 2 extends the covered
-//     prefix to about T2 * 2^(r-2) blocks, rounded down to whole bound levels
-//     (at least one more level), and the last round takes everything left.
+//     Round 1 takes the first m1 blocks (default 16); round r >= 2 extends
+//     the covered prefix to about T2 * g^(r-2) blocks (default g = 4), rounded
+//     down to whole bound levels (at least one more level), and the last round
+//     takes everything left.
 //  3. Round 1 (vector ALUs, one wave per query): the exact top k over the
 //     rows of those blocks, which gives the first k-th key.
 //  4. Rounds r >= 2 (matrix cores): block b takes part for query q when its
@@ -24,8 +25,11 @@
 //     with K <= the query's k-th key is appended to the query's candidate
 //     buffer.  Each query then merges its candidates into its top k.  A query
 //     stops when no remaining block can hold a key <= its k-th key.
-//  5. Results; a query whose candidate buffer overflowed is searched again by
-//     the per-query best-first traversal.
+//     A query whose candidate buffer overflows repeats the round with the
+//     k-th key of the candidates it stored.
+//  5. Results; a query whose key cannot tighten that way (more than a buffer
+//     of rows tie at its k-th key) is searched again by the per-query
+//     best-first traversal.
 //
 // Exactness: a row with K <= the final k-th key lies in a block whose bound
 // is at most that key, hence at most the query's k-th key in every round (it
@@ -51,8 +55,9 @@ int knn_tree_impl(qd_tree_t t, const uint64_t *d_q, uint32_t nq, uint32_t k, int
 namespace {
 
 constexpr uint32_t kBlk = mt::MB;          // rows per block
-constexpr uint32_t kM1 = 16;               // blocks in round 1
+constexpr uint32_t kM1 = 64;               // most blocks in round 1 (default 16)
 constexpr int kRounds = 24;                // rounds 1 .. kRounds; the last takes every remaining block
+constexpr int kMaxPasses = 64;             // matrix-core passes (rounds and repeats) per batch
 constexpr uint32_t kCap = 8128;            // candidate slots per query per round (kCap + k <= 8192)
 constexpr int kGroup = 16;                 // blocks per wave when building the lists
 constexpr uint32_t kInf = 0xFFFFFFFFu;
@@ -130,10 +135,11 @@ __global__ __launch_bounds__(mt::kThreads) void bound_kernel(const uint4 *__rest
 }
 
 // Per query: histogram of A_lb over the blocks, round 1's blocks (the first
-// min(16, nblk) in (A_lb, b) order, listed in block order) and the range end
+// min(m1, nblk) in (A_lb, b) order, listed in block order) and the range end
 // of every round.  One 256-thread block per query.
-__global__ __launch_bounds__(256) void plan_kernel(const uint16_t *__restrict__ lbq, uint64_t nblk, uint64_t t2,
-                                                   u64 *__restrict__ cuts, uint32_t *__restrict__ r1list) {
+__global__ __launch_bounds__(256) void plan_kernel(const uint16_t *__restrict__ lbq, uint64_t nblk, uint32_t m1,
+                                                   uint64_t t2, uint32_t growth, u64 *__restrict__ cuts,
+                                                   uint32_t *__restrict__ r1list) {
     __shared__ uint32_t cum[kLevels];
     __shared__ uint32_t part[2][256];
     __shared__ uint32_t s_bcut;
@@ -174,7 +180,7 @@ __global__ __launch_bounds__(256) void plan_kernel(const uint16_t *__restrict__ 
     }
     __syncthreads();
     // round 1: all blocks below level L1 and the first r1 blocks of level L1
-    const uint32_t T1 = (uint32_t)(nblk < kM1 ? nblk : kM1);
+    const uint32_t T1 = (uint32_t)(nblk < m1 ? nblk : m1);
     uint32_t lo = 0, hi = kLevels - 1;
     while (lo < hi) {
         const uint32_t mid = (lo + hi) / 2;
@@ -253,7 +259,7 @@ __global__ __launch_bounds__(256) void plan_kernel(const uint16_t *__restrict__ 
             c[r] = range_key(L, kInf);
             Lp = L;
             whole = true;
-            T = T < (1ull << 40) ? 2 * T : T;
+            T = T < (1ull << 40) ? growth * T : T;
         }
     }
 }
@@ -269,7 +275,8 @@ __global__ __launch_bounds__(256) void round1_kernel(const uint4 *__restrict__ q
                                                      const u64 *__restrict__ cuts, const uint16_t *__restrict__ qpop,
                                                      u64 *__restrict__ top, uint32_t *__restrict__ ntop,
                                                      uint32_t *__restrict__ thrk, u64 *__restrict__ rec,
-                                                     uint32_t *__restrict__ counters, uint32_t *__restrict__ qst) {
+                                                     uint32_t *__restrict__ qround, uint32_t *__restrict__ counters,
+                                                     uint32_t *__restrict__ qst) {
     const int lane = lane_id();
     const uint32_t qi = readfirst(blockIdx.x * 4 + (threadIdx.x >> 6));
     if (qi >= nqb) return;
@@ -322,6 +329,7 @@ __global__ __launch_bounds__(256) void round1_kernel(const uint4 *__restrict__ q
         const bool active = hi > lo;
         rec[2 * qi] = lo;
         rec[2 * qi + 1] = active ? hi : 0;
+        qround[qi] = 2;
         if (active) atomicAdd(&counters[0], 1u);
         if (qst) {
             qst[(uint64_t)qi * 4 + 0] = n1;
@@ -471,57 +479,85 @@ __global__ __launch_bounds__(mt::kThreads) void eval_kernel(const uint4 *__restr
         }
 }
 
-// After round r: merge each running query's candidates into its top k, update
-// its k-th key and set its range for round r + 1.  One block per query.
-__global__ __launch_bounds__(256) void select_kernel(uint32_t k, int r, const uint16_t *__restrict__ qpop,
+// After a round: merge each running query's candidates into its top k,
+// update its k-th key and set its next range.  A query whose candidates
+// overflowed the buffer repeats the round: the k best of the candidates it
+// did store (real rows, as is its top k) bound its final k-th key, so the
+// repeat keeps fewer rows; when that bound does not tighten the key, the
+// query goes to the per-query fallback.  One block per query.
+__global__ __launch_bounds__(256) void select_kernel(uint32_t k, const uint16_t *__restrict__ qpop,
                                                      const u64 *__restrict__ cuts, u64 *__restrict__ rec,
-                                                     uint32_t *__restrict__ ccnt, const u64 *__restrict__ cand,
-                                                     u64 *__restrict__ top, uint32_t *__restrict__ ntop,
-                                                     uint32_t *__restrict__ thrk, uint32_t *__restrict__ counters,
-                                                     uint32_t *__restrict__ redo, uint32_t *__restrict__ qst) {
+                                                     uint32_t *__restrict__ qround, uint32_t *__restrict__ ccnt,
+                                                     const u64 *__restrict__ cand, u64 *__restrict__ top,
+                                                     uint32_t *__restrict__ ntop, uint32_t *__restrict__ thrk,
+                                                     uint32_t *__restrict__ counters, uint32_t *__restrict__ redo,
+                                                     uint32_t *__restrict__ qst) {
     __shared__ u64 keys[8192];
     const uint32_t qi = blockIdx.x;
     const u64 lo = rec[2 * qi], hi = rec[2 * qi + 1];
     if (!(hi > lo)) return;  // not running
     const uint32_t m = ccnt[qi];
-    if (m > kCap) {
-        if (threadIdx.x == 0) {
-            redo[atomicAdd(&counters[1], 1u)] = qi;
-            rec[2 * qi + 1] = 0;
-            ccnt[qi] = 0;
-        }
-        return;
-    }
+    const bool over = m > kCap;
+    const uint32_t stored = over ? kCap : m;
     const uint32_t nt = ntop[qi];
-    uint32_t have = nt, th = thrk[qi];
-    if (m > 0) {
-        const uint32_t total = nt + m;
+    const uint32_t th = thrk[qi];
+    uint32_t have = nt, th_new = th;
+    if (stored > 0) {
+        const uint32_t total = nt + stored;
         const uint32_t np = next_pow2(total < 2 ? 2 : total);
         for (uint32_t i = threadIdx.x; i < np; i += 256)
             keys[i] = i < nt ? top[(uint64_t)qi * k + i] : (i < total ? cand[(uint64_t)qi * kCap + (i - nt)] : KEY_NONE);
         __syncthreads();
         block_bitonic_sort(keys, np);
-        have = total < k ? total : k;
-        for (uint32_t i = threadIdx.x; i < have; i += 256) top[(uint64_t)qi * k + i] = keys[i];
-        th = have == k ? (uint32_t)(keys[k - 1] >> 32) : kInf;
-    }
-    if (threadIdx.x == 0) {
-        ntop[qi] = have;
-        thrk[qi] = th;
-        ccnt[qi] = 0;
-        if (qst) qst[(uint64_t)qi * 4 + 1] += 1;
-        const u64 *c = cuts + (uint64_t)qi * (kRounds + 1);
-        const u64 nlo = c[r];
-        u64 nhi = 0;
-        if (r < kRounds) {
-            const uint32_t pq = qpop[qi];
-            const u64 cap = cap_key(th, weight_b(pq));
-            nhi = c[r + 1] < cap ? c[r + 1] : cap;
+        const uint32_t kth = total >= k ? (uint32_t)(keys[k - 1] >> 32) : kInf;
+        th_new = kth < th ? kth : th;
+        if (!over) {
+            have = total < k ? total : k;
+            for (uint32_t i = threadIdx.x; i < have; i += 256) top[(uint64_t)qi * k + i] = keys[i];
         }
-        const bool active = nhi > nlo;
-        rec[2 * qi] = nlo;
-        rec[2 * qi + 1] = active ? nhi : 0;
-        if (active) atomicAdd(&counters[0], 1u);
+    }
+    if (threadIdx.x != 0) return;
+    ccnt[qi] = 0;
+    if (qst) qst[(uint64_t)qi * 4 + 1] += 1;
+    const u64 *c = cuts + (uint64_t)qi * (kRounds + 1);
+    const uint32_t r = qround[qi];
+    const uint32_t wb = weight_b(qpop[qi]);
+    if (over) {
+        const u64 cap = cap_key(th_new, wb);
+        const u64 nhi = c[r] < cap ? c[r] : cap;
+        if (th_new < th && nhi > lo) {  // repeat round r with the tighter key
+            thrk[qi] = th_new;
+            rec[2 * qi + 1] = nhi;
+            atomicAdd(&counters[0], 1u);
+        } else {
+            redo[atomicAdd(&counters[1], 1u)] = qi;
+            rec[2 * qi + 1] = 0;
+        }
+        return;
+    }
+    ntop[qi] = have;
+    thrk[qi] = th_new;
+    qround[qi] = r + 1;
+    const u64 nlo = c[r];
+    u64 nhi = 0;
+    if (r < (uint32_t)kRounds) {
+        const u64 cap = cap_key(th_new, wb);
+        nhi = c[r + 1] < cap ? c[r + 1] : cap;
+    }
+    const bool active = nhi > nlo;
+    rec[2 * qi] = nlo;
+    rec[2 * qi + 1] = active ? nhi : 0;
+    if (active) atomicAdd(&counters[0], 1u);
+}
+
+// Queries still running after the last pass go to the per-query fallback.
+__global__ void leftover_kernel(uint32_t nqb, u64 *__restrict__ rec, uint32_t *__restrict__ counters,
+                                uint32_t *__restrict__ redo) {
+    const uint32_t qi = blockIdx.x * blockDim.x + threadIdx.x;
+    if (qi >= nqb) return;
+    if (rec[2 * qi + 1] > rec[2 * qi]) {
+        redo[atomicAdd(&counters[1], 1u)] = qi;
+        rec[2 * qi + 1] = 0;
     }
 }
 
@@ -594,11 +630,17 @@ int tree_block_images(qd_tree_s *t, hipStream_t s) {
     return QD_OK;
 }
 
-int knn_tree_blocked(qd_tree_t t, const uint64_t *d_q, uint32_t nq, uint32_t k, uint32_t *d_idx, int32_t *d_missed,
-                     int32_t *d_extra, float *d_dist, uint32_t *d_qstats, qd_stats *h_stats, hipStream_t s) {
+int knn_tree_blocked(qd_tree_t t, const uint64_t *d_q, uint32_t nq, uint32_t k, const qd_search_params *p,
+                     uint32_t *d_idx, int32_t *d_missed, int32_t *d_extra, float *d_dist, uint32_t *d_qstats,
+                     qd_stats *h_stats, hipStream_t s) {
     const uint64_t n = t->n, nblk = t->n_blk;
     if (!t->d_blk || nblk == 0) return fail(QD_ERR_INVALID, "tree has no block images");
     if (nblk > 0x7FFFFFFFull) return fail(QD_ERR_UNSUPPORTED, "too many blocks");
+    const uint32_t m1 = p && p->round1_blocks ? p->round1_blocks : 16;
+    const uint32_t growth = p && p->round_growth ? p->round_growth : 4;
+    if (m1 > kM1) return fail(QD_ERR_INVALID, "round1_blocks=%u above %u", m1, kM1);
+    if (growth < 2 || growth > 64) return fail(QD_ERR_INVALID, "round_growth=%u outside 2..64", growth);
+    if (h_stats) *h_stats = qd_stats{0, 0, 0, 0};
     // batch: up to kMaxBatch queries, bound and list matrices within about 12 GiB
     uint32_t qb = nq < kMaxBatch ? nq : kMaxBatch;
     auto batch_bytes = [&](uint32_t b) { return (uint64_t)up256(b) * (nblk * 6 + kCap * 8 + (uint64_t)k * 8 + 512); };
@@ -614,7 +656,7 @@ int knn_tree_blocked(qd_tree_t t, const uint64_t *d_q, uint32_t nq, uint32_t k, 
     const size_t a_qpop = take(P * 2), a_lbq = take(P * nblk * 2), a_lbb = take(P * nblk * 2),
                  a_list = take(P * nblk * 2), a_cuts = take(P * (kRounds + 1) * 8), a_r1 = take(P * kM1 * 4),
                  a_rec = take(P * 16), a_thr = take(P * 4), a_ntop = take(P * 4), a_top = take(P * k * 8),
-                 a_ccnt = take(P * 4), a_cand = take(P * kCap * 8), a_cnt = take(nblk * 4),
+                 a_ccnt = take(P * 4), a_cand = take(P * kCap * 8), a_cnt = take(nblk * 4), a_qr = take(P * 4),
                  a_off = take((nblk + 1) * 4), a_ctr = take(16), a_redo = take(P * 4), a_qst = take(P * 16),
                  a_gst = take(32);
     char *ws = nullptr;
@@ -625,7 +667,8 @@ int knn_tree_blocked(qd_tree_t t, const uint64_t *d_q, uint32_t nq, uint32_t k, 
         *cand = (u64 *)(ws + a_cand);
     uint32_t *r1list = (uint32_t *)(ws + a_r1), *thr = (uint32_t *)(ws + a_thr), *ntop = (uint32_t *)(ws + a_ntop),
              *ccnt = (uint32_t *)(ws + a_ccnt), *cnt = (uint32_t *)(ws + a_cnt), *off = (uint32_t *)(ws + a_off),
-             *ctr = (uint32_t *)(ws + a_ctr), *redo = (uint32_t *)(ws + a_redo), *qst = (uint32_t *)(ws + a_qst);
+             *ctr = (uint32_t *)(ws + a_ctr), *redo = (uint32_t *)(ws + a_redo), *qst = (uint32_t *)(ws + a_qst),
+             *qround = (uint32_t *)(ws + a_qr);
     unsigned long long *gst = (unsigned long long *)(ws + a_gst);
     const bool want_stats = d_qstats || h_stats;
     int rc = QD_OK;
@@ -652,18 +695,18 @@ int knn_tree_blocked(qd_tree_t t, const uint64_t *d_q, uint32_t nq, uint32_t k, 
         }
         // round 2 covers about t2 blocks per query: enough that a block's list
         // holds ~128 queries on average
-        uint64_t t2 = (128 * nblk + nqb - 1) / nqb;
-        if (t2 < 4 * kM1) t2 = 4 * kM1;
-        hipLaunchKernelGGL(plan_kernel, dim3(nqb), dim3(256), 0, s, lbq, nblk, t2, cuts, r1list);
-        const uint32_t n1 = (uint32_t)(nblk < kM1 ? nblk : kM1);
+        uint64_t t2 = p && p->round2_blocks ? p->round2_blocks : (128 * nblk + nqb - 1) / nqb;
+        if (t2 < 2 * (uint64_t)m1) t2 = 2 * (uint64_t)m1;
+        hipLaunchKernelGGL(plan_kernel, dim3(nqb), dim3(256), 0, s, lbq, nblk, m1, t2, growth, cuts, r1list);
+        const uint32_t n1 = (uint32_t)(nblk < m1 ? nblk : m1);
         {
             KernelTimer timer("tree_block_round1", s);
             hipLaunchKernelGGL(round1_kernel, dim3((nqb + 3) / 4), dim3(256), 0, s, q4, nqb, k,
                                reinterpret_cast<const uint4 *>(t->d_sorted), t->d_pop, t->d_perm, n, nblk, r1list, n1,
-                               cuts, qpop, top, ntop, thr, rec, ctr, want_stats ? qst : nullptr);
+                               cuts, qpop, top, ntop, thr, rec, qround, ctr, want_stats ? qst : nullptr);
         }
         if (hipGetLastError() != hipSuccess) return done(fail(QD_ERR_DEVICE, "blocked search: launch failed"));
-        for (int r = 2; r <= kRounds; r++) {
+        for (int pass = 0;; pass++) {
             {
                 KernelTimer timer("tree_block_lists", s);
                 const uint64_t waves = (nblk + kGroup - 1) / kGroup;
@@ -675,7 +718,11 @@ int knn_tree_blocked(qd_tree_t t, const uint64_t *d_q, uint32_t nq, uint32_t k, 
             hipError_t e = hipMemcpyAsync(h, ctr, 16, hipMemcpyDeviceToHost, s);
             if (e == hipSuccess) e = hipStreamSynchronize(s);
             if (e != hipSuccess) return done(fail(QD_ERR_DEVICE, "blocked search: %s", hipGetErrorString(e)));
-            if (h[0] == 0) break;  // no query runs in this round
+            if (h[0] == 0) break;  // no query runs any more
+            if (pass == kMaxPasses) {
+                hipLaunchKernelGGL(leftover_kernel, dim3((nqb + 255) / 256), dim3(256), 0, s, nqb, rec, ctr, redo);
+                break;
+            }
             if (hipMemsetAsync(ctr, 0, 4, s) != hipSuccess) return done(fail(QD_ERR_DEVICE, "memset"));
             if (h[2] > 0) {
                 KernelTimer timer("tree_block_eval", s);
@@ -685,8 +732,8 @@ int knn_tree_blocked(qd_tree_t t, const uint64_t *d_q, uint32_t nq, uint32_t k, 
             }
             {
                 KernelTimer timer("tree_block_select", s);
-                hipLaunchKernelGGL(select_kernel, dim3(nqb), dim3(256), 0, s, k, r, qpop, cuts, rec, ccnt, cand, top,
-                                   ntop, thr, ctr, redo, want_stats ? qst : nullptr);
+                hipLaunchKernelGGL(select_kernel, dim3(nqb), dim3(256), 0, s, k, qpop, cuts, rec, qround, ccnt, cand,
+                                   top, ntop, thr, ctr, redo, want_stats ? qst : nullptr);
             }
             if (hipGetLastError() != hipSuccess) return done(fail(QD_ERR_DEVICE, "blocked search: launch failed"));
         }

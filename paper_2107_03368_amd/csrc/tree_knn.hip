@@ -395,7 +395,7 @@ int knn_tree_impl(qd_tree_t t, const uint64_t *d_q, uint32_t nq, uint32_t k, int
     if (!aligned16(d_q)) return fail(QD_ERR_INVALID, "queries must be 16-byte aligned");
     if (order == QD_ORDER_BLOCKED) {
         if (d_scores || d_trace) return fail(QD_ERR_INVALID, "the blocked order takes no scores or traces");
-        return knn_tree_blocked(t, d_q, nq, k, d_idx, d_missed, d_extra, d_dist, d_qstats, h_stats,
+        return knn_tree_blocked(t, d_q, nq, k, nullptr, d_idx, d_missed, d_extra, d_dist, d_qstats, h_stats,
                                 (hipStream_t)stream);
     }
     if (order == QD_ORDER_DEPTH_FIRST && t->depth + 2 > (uint32_t)kMaxStack)
@@ -434,6 +434,14 @@ extern "C" int qd_knn_tree(qd_tree_t t, const uint64_t *d_q, uint32_t nq, uint32
     const uint32_t wpc = p ? p->waves_per_cu : 0;
     if (sc && order != QD_ORDER_DEPTH_FIRST)
         return qd::fail(QD_ERR_INVALID, "node scores order the depth-first frontier only");
+    if (order == QD_ORDER_BLOCKED && t && nq > 0) {
+        if (k < 1 || k > QD_MAX_K) return qd::fail(QD_ERR_INVALID, "k=%u outside 1..%d", k, QD_MAX_K);
+        if (!d_q || !d_idx || !d_missed || !d_extra || !d_dist) return qd::fail(QD_ERR_INVALID, "null pointer");
+        if (!qd::aligned16(d_q)) return qd::fail(QD_ERR_INVALID, "queries must be 16-byte aligned");
+        if (p && p->d_visited) return qd::fail(QD_ERR_INVALID, "the blocked order takes no traces");
+        return qd::knn_tree_blocked(t, d_q, nq, k, p, d_idx, d_missed, d_extra, d_dist, d_query_stats, h_stats,
+                                    (hipStream_t)stream);
+    }
     return qd::knn_tree_impl(t, d_q, nq, k, order, sc, ns, d_idx, d_missed, d_extra, d_dist, d_query_stats, h_stats,
                              stream, wpc, p ? p->d_visited : nullptr, p ? p->n_traced : 0);
 }

@@ -70,6 +70,27 @@ def test_blocked_several_rounds_and_tiles(qd, k):
         assert st[:, 3].mean() < 0.9 * db.shape[0]  # the bounds prune
 
 
+@pytest.mark.parametrize("schedule", [(4, 0, 2), (16, 0, 4), (16, 2000, 8), (64, 0, 2)])
+def test_blocked_schedules(qd, schedule):
+    db = synth.gen_db(60_123, 1101)
+    q, _ = synth.gen_queries(db, 600, 2101, 0.1, 0.6)
+    tree = qd.tree_build(_t(db))
+    for k in (1, 10):
+        _same(qd.knn_tree(tree, _t(q), k, order=qd.ORDER_BLOCKED, schedule=schedule), oracle.knn_brute(db, q, k))
+
+
+def test_blocked_overflow_repeat(qd):
+    # one block in round 1 gives a loose 64th key, and round 2 takes every
+    # block: more rows than a candidate buffer holds pass the key, so the
+    # queries repeat round 2 with the 64th of the candidates they stored
+    db = synth.gen_db(60_123, 1101)
+    q, _ = synth.gen_queries(db, 200, 2103, 0.1, 0.6)
+    tree = qd.tree_build(_t(db))
+    res = qd.knn_tree(tree, _t(q), 64, order=qd.ORDER_BLOCKED, schedule=(1, 100_000, 2), query_stats=True)
+    _same(res, oracle.knn_brute(db, q, 64))
+    assert (res[4].cpu().numpy()[:, 1] >= 3).mean() > 0.5  # most queries repeated a round
+
+
 def test_blocked_edge_cases(qd):
     base = synth.gen_db(500, 71)
     db = np.concatenate([base, base[:100], np.zeros((5, 64), np.uint64)])
