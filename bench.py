@@ -43,9 +43,8 @@ TRAIN_QUERIES, TRAIN_BATCH, TRAIN_EPOCHS, TRAIN_LR, N_SCORED = 1024, 16, 4, 1e-3
 # HBM bytes of one scan_mfma_kernel launch at the 10M x 8,192 workload, from the
 # FETCH_SIZE / WRITE_SIZE counters scaled by a 1 GiB copy (profiles/); None
 # until measured for the current kernel
-TRAFFIC = 41.12e9 + 0.521e9
-TRAFFIC_DETAIL = {"read_bytes": 41.12e9, "write_bytes": 0.521e9, "algorithmic_read_bytes": 5.124e9,
-                  "counter_scale": {"FETCH_SIZE": 2.0, "WRITE_SIZE": 1.0}}
+TRAFFIC = None
+TRAFFIC_DETAIL = None
 
 
 def log(*a):
@@ -59,7 +58,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="10m", choices=sorted(WORKLOADS))
     ap.add_argument("--cpu-sample", type=int, default=48, help="queries in the oracle's timed sample (0 = skip)")
-    ap.add_argument("--paths", default="brute,tree,learned")
+    ap.add_argument("--paths", default="brute,tree,learned",
+                    help="brute, tree (best-first, depth-first, blocked), blocked (blocked only), learned")
     ap.add_argument("--pmc-run", action="store_true",
                     help="only a 1 GiB device copy (counter calibration) and one sequential-search batch")
     args = ap.parse_args()
@@ -103,7 +103,7 @@ def main():
     tree = None
     train = None
     build_s = None
-    if ("tree" in wanted or "learned" in wanted) and hasattr(qd, "tree_build"):
+    if ("tree" in wanted or "learned" in wanted or "blocked" in wanted) and hasattr(qd, "tree_build"):
         t0 = time.time()
         tree = qd.tree_build(dbt)
         torch.cuda.synchronize()
@@ -112,6 +112,8 @@ def main():
         if "tree" in wanted:
             paths["tree"] = lambda: qd.knn_tree(tree, qt, k)
             paths["tree_dfs"] = lambda: qd.knn_tree(tree, qt, k, order=qd.ORDER_DEPTH_FIRST)
+            paths["tree_blocked"] = lambda: qd.knn_tree(tree, qt, k, order=qd.ORDER_BLOCKED)
+        elif "blocked" in wanted:
             paths["tree_blocked"] = lambda: qd.knn_tree(tree, qt, k, order=qd.ORDER_BLOCKED)
         if "learned" in wanted:
             # offline: train the frontier-order model on traces of the exact search over

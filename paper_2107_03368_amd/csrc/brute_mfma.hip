@@ -44,17 +44,14 @@ __global__ __launch_bounds__(mt::kThreads) void scan_mfma_kernel(const uint4 *__
     const uint64_t rt = blockIdx.x / n_qtiles;
     const uint32_t q0 = qt * MQ;
     const uint64_t t0 = rt * MR;
-    const uint4 *src[mt::kLoads];
-#pragma unroll
-    for (int u = 0; u < mt::kLoads; u++) {
-        const int r = mt::slot_row(u);
-        if (r < MQ)
-            src[u] = q0 + r < nq ? q + (uint64_t)(q0 + r) * 32 : nullptr;
-        else
-            src[u] = t0 + (r - MQ) < n ? db + (t0 + (r - MQ)) * 32 : nullptr;
-    }
+    const int r = mt::own_row();
+    const uint4 *row;
+    if (r < MQ)
+        row = q0 + r < nq ? q + (uint64_t)(q0 + r) * 32 : nullptr;
+    else
+        row = t0 + (r - MQ) < n ? db + (t0 + (r - MQ)) * 32 : nullptr;
     mt::v4i acc[8][4];
-    mt::overlap_tile(src, sm, acc);
+    mt::overlap_tile(row, sm, acc);
 
     // epilogue: keys of this lane's 32 queries x 4 rows
 #pragma unroll

@@ -101,17 +101,14 @@ __global__ __launch_bounds__(mt::kThreads) void bound_kernel(const uint4 *__rest
     __shared__ mt::Smem sm;
     const uint32_t q0 = (blockIdx.x % n_qtiles) * mt::MA;
     const uint64_t b0 = (uint64_t)(blockIdx.x / n_qtiles) * mt::MB;
-    const uint4 *src[mt::kLoads];
-#pragma unroll
-    for (int u = 0; u < mt::kLoads; u++) {
-        const int r = mt::slot_row(u);
-        if (r < mt::MA)
-            src[u] = q0 + r < nqb ? q + (uint64_t)(q0 + r) * 32 : nullptr;
-        else
-            src[u] = b0 + (r - mt::MA) < nblk ? img + (b0 + (r - mt::MA)) * 32 : nullptr;
-    }
+    const int r = mt::own_row();
+    const uint4 *row;
+    if (r < mt::MA)
+        row = q0 + r < nqb ? q + (uint64_t)(q0 + r) * 32 : nullptr;
+    else
+        row = b0 + (r - mt::MA) < nblk ? img + (b0 + (r - mt::MA)) * 32 : nullptr;
     mt::v4i acc[8][4];
-    mt::overlap_tile(src, sm, acc);
+    mt::overlap_tile(row, sm, acc);
 #pragma unroll
     for (int a = 0; a < 8; a++)
 #pragma unroll
@@ -444,17 +441,14 @@ __global__ __launch_bounds__(mt::kThreads) void eval_kernel(const uint4 *__restr
     const uint32_t m = left < (uint32_t)mt::MA ? left : (uint32_t)mt::MA;
     const uint16_t *lq = list + b * nqp + t0;
     const uint64_t r0 = b * kBlk;
-    const uint4 *src[mt::kLoads];
-#pragma unroll
-    for (int u = 0; u < mt::kLoads; u++) {
-        const int r = mt::slot_row(u);
-        if (r < mt::MA)
-            src[u] = (uint32_t)r < m ? q + (uint64_t)lq[r] * 32 : nullptr;
-        else
-            src[u] = r0 + (r - mt::MA) < n ? sorted + (r0 + (r - mt::MA)) * 32 : nullptr;
-    }
+    const int r = mt::own_row();
+    const uint4 *row;
+    if (r < mt::MA)
+        row = (uint32_t)r < m ? q + (uint64_t)lq[r] * 32 : nullptr;
+    else
+        row = r0 + (r - mt::MA) < n ? sorted + (r0 + (r - mt::MA)) * 32 : nullptr;
     mt::v4i acc[8][4];
-    mt::overlap_tile(src, sm, acc);
+    mt::overlap_tile(row, sm, acc);
 #pragma unroll
     for (int a = 0; a < 8; a++)
 #pragma unroll
