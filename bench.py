@@ -40,11 +40,19 @@ ROW_BYTES = 512
 # frontier-order model: trained on the 1M database's traces, scores the top
 # N_SCORED nodes (depth <= 10) of the searched tree
 TRAIN_QUERIES, TRAIN_BATCH, TRAIN_EPOCHS, TRAIN_LR, N_SCORED = 1024, 16, 4, 1e-3, 2047
-# HBM bytes of one scan_mfma_kernel launch at the 10M x 8,192 workload, from the
-# FETCH_SIZE / WRITE_SIZE counters scaled by a 1 GiB copy (profiles/); None
-# until measured for the current kernel
-TRAFFIC = None
-TRAFFIC_DETAIL = None
+# HBM bytes per launch of the matrix-core kernels at the 10M x 8,192 workload,
+# from the FETCH_SIZE / WRITE_SIZE counters (KiB) scaled by what they read for a
+# 1 GiB device copy (FETCH 524,315 KiB, WRITE 1,048,576 KiB); drop an entry
+# when its kernel changes
+TRAFFIC_DETAIL = {
+    # scan_mfma_kernel at 10M x 8,192: one launch
+    "scan_mfma_kernel": {"read_bytes": 20_080_463 * 2 * 1024, "write_bytes": 509_616 * 1024,
+                         "algorithmic_read_bytes": 5.124e9, "counter_scale": {"FETCH_SIZE": 2.0, "WRITE_SIZE": 1.0}},
+    # eval_kernel at 10M x 8,192, k = 10: the average of the 5 launches of one search
+    "eval_kernel": {"read_bytes": 12_157_918 / 5 * 2 * 1024, "write_bytes": 256_779 / 5 * 1024,
+                    "counter_scale": {"FETCH_SIZE": 2.0, "WRITE_SIZE": 1.0}},
+}
+TRAFFIC = {kname: d["read_bytes"] + d["write_bytes"] for kname, d in TRAFFIC_DETAIL.items()}
 
 
 def log(*a):
@@ -84,6 +92,8 @@ def main():
         dbt = torch.from_numpy(db.view(np.int64)).to(dev)
         qt = torch.from_numpy(q.view(np.int64)).to(dev)
         qd.knn_bruteforce(dbt, qt, w["k"])
+        tree = qd.tree_build(dbt)
+        qd.knn_tree(tree, qt, w["k"], order=qd.ORDER_BLOCKED)
         torch.cuda.synchronize()
         log("pmc run done")
         return
@@ -195,20 +205,41 @@ def main():
 
     step_ms = sum(p["ms"] for p in per_path.values())
     best = min(per_path, key=lambda p: per_path[p]["ms"])
-    bk = per_path["brute"]["kernels"]
-    if "wh_scan_mfma" in bk:
-        # int8 matrix-core scan: 2 ops (multiply, add) per bit pair per (query, row)
-        ms = bk["wh_scan_mfma"]["avg_ms"]
-        achieved = nq * n * 4096 * 2 / (ms * 1e-3) / 1e12
-        roofline = {"kernel": "scan_mfma_kernel", "bound": "mfma", "achieved": achieved, "peak": INT8_PEAK_TOPS,
-                    "unit": "TOP/s (int8 MFMA ops)", "frac": achieved / INT8_PEAK_TOPS, "traffic": TRAFFIC,
-                    "traffic_detail": TRAFFIC_DETAIL if TRAFFIC is not None else None, "avg_ms": ms}
-    else:
+    def scan_roofline():
+        bk = per_path["brute"]["kernels"]
+        if "wh_scan_mfma" in bk:
+            # int8 matrix-core scan: 2 ops (multiply, add) per bit pair per (query, row)
+            ms = bk["wh_scan_mfma"]["avg_ms"]
+            achieved = nq * n * 4096 * 2 / (ms * 1e-3) / 1e12
+            return {"kernel": "scan_mfma_kernel", "bound": "mfma", "achieved": achieved, "peak": INT8_PEAK_TOPS,
+                    "unit": "TOP/s (int8 MFMA ops)", "frac": achieved / INT8_PEAK_TOPS,
+                    "traffic": TRAFFIC.get("scan_mfma_kernel") if TRAFFIC else None, "avg_ms": ms}
         ms = bk["wh_scan_topk"]["avg_ms"]
         achieved = nq * n * OPS_PER_PAIR / (ms * 1e-3) / 1e12
-        roofline = {"kernel": "scan_topk_kernel", "bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS,
-                    "unit": "TOP/s (32-bit integer lane ops)", "frac": achieved / VALU_PEAK_TOPS, "traffic": None,
-                    "avg_ms": ms}
+        return {"kernel": "scan_topk_kernel", "bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS,
+                "unit": "TOP/s (32-bit integer lane ops)", "frac": achieved / VALU_PEAK_TOPS, "traffic": None,
+                "avg_ms": ms}
+
+    def blocked_roofline():
+        # eval_kernel: the (query, row) pairs of the matrix-core rounds (all evaluated
+        # rows minus round 1's, which run on the vector ALUs), 2 ops per bit pair
+        pb = per_path["tree_blocked"]
+        ev = pb["kernels"]["tree_block_eval"]
+        launches_per_call = ev["launches"] / args.steps
+        rows_r1 = min(16, (n + 255) // 256) * 256
+        pairs = nq * (pb["per_query"]["dists_evaluated"] - rows_r1)
+        ops_per_launch = pairs * 4096 * 2 / launches_per_call
+        achieved = ops_per_launch / (ev["avg_ms"] * 1e-3) / 1e12
+        tr = TRAFFIC.get("eval_kernel") if TRAFFIC else None
+        return {"kernel": "eval_kernel", "bound": "mfma", "achieved": achieved, "peak": INT8_PEAK_TOPS,
+                "unit": "TOP/s (int8 MFMA ops)", "frac": achieved / INT8_PEAK_TOPS, "traffic": tr,
+                "avg_ms": ev["avg_ms"], "ops_per_launch": ops_per_launch,
+                "launches_per_call": launches_per_call}
+
+    roofline_scan = scan_roofline()
+    roofline = blocked_roofline() if best == "tree_blocked" else roofline_scan
+    if TRAFFIC_DETAIL:
+        roofline["traffic_detail"] = TRAFFIC_DETAIL.get(roofline["kernel"])
 
     cpu = None
     if args.cpu_sample > 0:
@@ -240,6 +271,7 @@ def main():
         "brute_small_batch_hbm": hbm,
         "recall_source_row_at_1": recall,
         "roofline": roofline,
+        "roofline_scan": roofline_scan,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -40,6 +40,8 @@ __global__ __launch_bounds__(mt::kThreads) void scan_mfma_kernel(const uint4 *__
                                                                  const u64 *__restrict__ thr, uint32_t n_qtiles,
                                                                  uint32_t *__restrict__ cnt, u64 *__restrict__ cand) {
     __shared__ mt::Smem sm;
+    // consecutive workgroups share a row tile and spread over the XCDs, so every
+    // XCD's L2 keeps a few query tiles resident while the rows stream through
     const uint32_t qt = blockIdx.x % n_qtiles;
     const uint64_t rt = blockIdx.x / n_qtiles;
     const uint32_t q0 = qt * MQ;

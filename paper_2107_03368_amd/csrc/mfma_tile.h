@@ -42,6 +42,19 @@ struct Smem {
 // bit 8e with no two terms overlapping, so no carries occur.
 __device__ __forceinline__ uint32_t spread4(uint32_t x) { return ((x & 0xFu) * 0x00204081u) & 0x01010101u; }
 
+// Workgroups are dispatched to the 8 XCDs round-robin (workgroup x runs on
+// XCD x % 8), and each XCD has its own L2.  xcd_tile maps workgroup x to a
+// tile index so that every XCD gets one contiguous range of the n tiles: tiles
+// that share B rows (consecutive indices) then share one L2.  Returns false
+// for the padding workgroups of a grid of xcd_grid(n) workgroups.
+constexpr uint32_t kXcds = 8;
+__host__ __device__ inline uint64_t xcd_grid(uint64_t n) { return (n + kXcds - 1) / kXcds * kXcds; }
+__device__ __forceinline__ bool xcd_tile(uint64_t x, uint64_t n, uint64_t &tile) {
+    const uint64_t per = (n + kXcds - 1) / kXcds;
+    tile = (x % kXcds) * per + x / kXcds;
+    return tile < n;
+}
+
 // Row owned by this thread (0..511; < 256 is an A row).
 __device__ __forceinline__ int own_row() { return (int)threadIdx.x; }
 

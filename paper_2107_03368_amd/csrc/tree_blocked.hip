@@ -138,7 +138,7 @@ __global__ __launch_bounds__(256) void plan_kernel(const uint16_t *__restrict__ 
                                                    uint64_t t2, uint32_t growth, u64 *__restrict__ cuts,
                                                    uint32_t *__restrict__ r1list) {
     __shared__ uint32_t cum[kLevels];
-    __shared__ uint32_t part[2][256];
+    __shared__ uint32_t part[256];
     __shared__ uint32_t s_bcut;
     const uint32_t qi = blockIdx.x, tid = threadIdx.x;
     const uint16_t *row = lbq + (uint64_t)qi * nblk;
@@ -154,19 +154,19 @@ __global__ __launch_bounds__(256) void plan_kernel(const uint16_t *__restrict__ 
         const uint32_t L = tid * per + i;
         if (L < kLevels) s += cum[L];
     }
-    part[0][tid] = s;
+    part[tid] = s;
     __syncthreads();
     if (tid == 0) {
         uint32_t run = 0;
         for (int t = 0; t < 256; t++) {
-            const uint32_t v = part[0][t];
-            part[0][t] = run;
+            const uint32_t v = part[t];
+            part[t] = run;
             run += v;
         }
     }
     __syncthreads();
     {
-        uint32_t run = part[0][tid];
+        uint32_t run = part[tid];
         for (uint32_t i = 0; i < per; i++) {
             const uint32_t L = tid * per + i;
             if (L < kLevels) {
@@ -189,41 +189,23 @@ __global__ __launch_bounds__(256) void plan_kernel(const uint16_t *__restrict__ 
     const uint32_t L1 = lo;
     const uint32_t before = L1 ? cum[L1 - 1] : 0;
     const uint32_t r1 = T1 - before, at_level = cum[L1] - before;
-    // ordered pass over contiguous chunks of blocks
-    const uint64_t chunk = (nblk + 255) / 256;
-    const uint64_t c0 = (uint64_t)tid * chunk, c1 = c0 + chunk < nblk ? c0 + chunk : nblk;
-    uint32_t n_lt = 0, n_eq = 0;
-    for (uint64_t b = c0; b < c1; b++) {
-        const uint32_t v = row[b];
-        n_lt += v < L1;
-        n_eq += v == L1;
-    }
-    part[0][tid] = n_lt;
-    part[1][tid] = n_eq;
-    __syncthreads();
-    if (tid == 0) {
-        uint32_t a = 0, e = 0;
-        for (int t = 0; t < 256; t++) {
-            const uint32_t va = part[0][t], ve = part[1][t];
-            part[0][t] = a;
-            part[1][t] = e;
-            a += va;
-            e += ve;
-        }
-    }
-    __syncthreads();
-    {
-        uint32_t eq_rank = part[1][tid];
-        uint32_t pos = part[0][tid] + (eq_rank < r1 ? eq_rank : r1);
-        for (uint64_t b = c0; b < c1; b++) {
-            const uint32_t v = row[b];
-            bool in = v < L1;
-            if (v == L1) {
-                in = eq_rank < r1;
-                if (eq_rank + 1 == r1 && r1 < at_level) s_bcut = (uint32_t)b;
-                eq_rank++;
-            }
-            if (in) r1list[(uint64_t)qi * kM1 + pos++] = (uint32_t)b;
+    // one wave walks the blocks in order (coalesced), listing round 1's blocks
+    // and finding the last block of level L1 it takes
+    if (tid < 64) {
+        const int lane = (int)tid;
+        uint32_t pos = 0, eq_seen = 0;
+        for (uint64_t base = 0; base < nblk; base += 64) {
+            const uint64_t b = base + lane;
+            const uint32_t v = b < nblk ? row[b] : 0xFFFFu;
+            const bool eq = v == L1;
+            const u64 meq = ballot(eq);
+            const uint32_t rank = eq_seen + lanes_below(meq);
+            const bool in = v < L1 || (eq && rank < r1);
+            if (eq && rank + 1 == r1 && r1 < at_level) s_bcut = (uint32_t)b;
+            const u64 min_ = ballot(in);
+            if (in) r1list[(uint64_t)qi * kM1 + pos + lanes_below(min_)] = (uint32_t)b;
+            pos += (uint32_t)__popcll(min_);
+            eq_seen += (uint32_t)__popcll(meq);
         }
     }
     __syncthreads();
@@ -426,7 +408,9 @@ __global__ __launch_bounds__(mt::kThreads) void eval_kernel(const uint4 *__restr
                                                             const uint32_t *__restrict__ thrk,
                                                             uint32_t *__restrict__ ccnt, u64 *__restrict__ cand) {
     __shared__ mt::Smem sm;
-    const uint32_t x = blockIdx.x;
+    uint64_t xt;
+    if (!mt::xcd_tile(blockIdx.x, off[nblk], xt)) return;
+    const uint32_t x = (uint32_t)xt;  // tiles of one block are consecutive
     uint64_t lo = 0, hi = nblk;  // off[lo] <= x < off[hi]
     while (hi - lo > 1) {
         const uint64_t mid = (lo + hi) / 2;
@@ -720,7 +704,7 @@ int knn_tree_blocked(qd_tree_t t, const uint64_t *d_q, uint32_t nq, uint32_t k, 
             if (hipMemsetAsync(ctr, 0, 4, s) != hipSuccess) return done(fail(QD_ERR_DEVICE, "memset"));
             if (h[2] > 0) {
                 KernelTimer timer("tree_block_eval", s);
-                hipLaunchKernelGGL(eval_kernel, dim3(h[2]), dim3(mt::kThreads), 0, s, q4,
+                hipLaunchKernelGGL(eval_kernel, dim3((uint32_t)mt::xcd_grid(h[2])), dim3(mt::kThreads), 0, s, q4,
                                    reinterpret_cast<const uint4 *>(t->d_sorted), n, nblk, nqp, list, cnt, off,
                                    t->d_pop, t->d_perm, qpop, thr, ccnt, cand);
             }
