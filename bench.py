@@ -32,7 +32,7 @@ WORKLOADS = {
 
 # MI355X published peaks and unit counts
 HBM_PEAK_GBS = 8000.0
-INT8_PEAK_TOPS = 5000.0  # dense int8 MFMA
+FP4_PEAK_TFLOPS = 10100.0  # dense FP4 (e2m1) MFMA
 CUS, SIMDS, LANES, CLOCK_GHZ = 256, 4, 16, 2.4
 VALU_PEAK_TOPS = CUS * SIMDS * LANES * CLOCK_GHZ / 1000.0  # 32-bit lane ops: 39.3 T/s
 OPS_PER_PAIR = 256  # 128 x (AND + BCNT) over 4096 bits
@@ -44,14 +44,7 @@ TRAIN_QUERIES, TRAIN_BATCH, TRAIN_EPOCHS, TRAIN_LR, N_SCORED = 1024, 16, 4, 1e-3
 # from the FETCH_SIZE / WRITE_SIZE counters (KiB) scaled by what they read for a
 # 1 GiB device copy (FETCH 524,315 KiB, WRITE 1,048,576 KiB); drop an entry
 # when its kernel changes
-TRAFFIC_DETAIL = {
-    # scan_mfma_kernel at 10M x 8,192: one launch
-    "scan_mfma_kernel": {"read_bytes": 20_080_463 * 2 * 1024, "write_bytes": 509_616 * 1024,
-                         "algorithmic_read_bytes": 5.124e9, "counter_scale": {"FETCH_SIZE": 2.0, "WRITE_SIZE": 1.0}},
-    # eval_kernel at 10M x 8,192, k = 10: the average of the 5 launches of one search
-    "eval_kernel": {"read_bytes": 12_157_918 / 5 * 2 * 1024, "write_bytes": 256_779 / 5 * 1024,
-                    "counter_scale": {"FETCH_SIZE": 2.0, "WRITE_SIZE": 1.0}},
-}
+TRAFFIC_DETAIL = {}
 TRAFFIC = {kname: d["read_bytes"] + d["write_bytes"] for kname, d in TRAFFIC_DETAIL.items()}
 
 
@@ -208,11 +201,11 @@ def main():
     def scan_roofline():
         bk = per_path["brute"]["kernels"]
         if "wh_scan_mfma" in bk:
-            # int8 matrix-core scan: 2 ops (multiply, add) per bit pair per (query, row)
+            # FP4 matrix-core scan: 2 flop (multiply, add) per bit pair per (query, row)
             ms = bk["wh_scan_mfma"]["avg_ms"]
             achieved = nq * n * 4096 * 2 / (ms * 1e-3) / 1e12
-            return {"kernel": "scan_mfma_kernel", "bound": "mfma", "achieved": achieved, "peak": INT8_PEAK_TOPS,
-                    "unit": "TOP/s (int8 MFMA ops)", "frac": achieved / INT8_PEAK_TOPS,
+            return {"kernel": "scan_mfma_kernel", "bound": "mfma", "achieved": achieved, "peak": FP4_PEAK_TFLOPS,
+                    "unit": "TFLOP/s (fp4 MFMA)", "frac": achieved / FP4_PEAK_TFLOPS,
                     "traffic": TRAFFIC.get("scan_mfma_kernel") if TRAFFIC else None, "avg_ms": ms}
         ms = bk["wh_scan_topk"]["avg_ms"]
         achieved = nq * n * OPS_PER_PAIR / (ms * 1e-3) / 1e12
@@ -222,7 +215,7 @@ def main():
 
     def blocked_roofline():
         # eval_kernel: the (query, row) pairs of the matrix-core rounds (all evaluated
-        # rows minus round 1's, which run on the vector ALUs), 2 ops per bit pair
+        # rows minus round 1's, which run on the vector ALUs), 2 flop per bit pair
         pb = per_path["tree_blocked"]
         ev = pb["kernels"]["tree_block_eval"]
         launches_per_call = ev["launches"] / args.steps
@@ -231,8 +224,8 @@ def main():
         ops_per_launch = pairs * 4096 * 2 / launches_per_call
         achieved = ops_per_launch / (ev["avg_ms"] * 1e-3) / 1e12
         tr = TRAFFIC.get("eval_kernel") if TRAFFIC else None
-        return {"kernel": "eval_kernel", "bound": "mfma", "achieved": achieved, "peak": INT8_PEAK_TOPS,
-                "unit": "TOP/s (int8 MFMA ops)", "frac": achieved / INT8_PEAK_TOPS, "traffic": tr,
+        return {"kernel": "eval_kernel", "bound": "mfma", "achieved": achieved, "peak": FP4_PEAK_TFLOPS,
+                "unit": "TFLOP/s (fp4 MFMA)", "frac": achieved / FP4_PEAK_TFLOPS, "traffic": tr,
                 "avg_ms": ev["avg_ms"], "ops_per_launch": ops_per_launch,
                 "launches_per_call": launches_per_call}
 
@@ -262,7 +255,7 @@ def main():
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": step_ms,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "u32", "data": "synthetic",
+        "dtype": "fp4", "data": "synthetic",
         "config": {"workload": f"{args.workload}: {n} descriptors x {nq} queries, k={k}", "n": n, "queries": nq,
                    "k": k, "value_path": best},
         "paths": per_path,

@@ -52,7 +52,7 @@ __global__ __launch_bounds__(mt::kThreads) void scan_mfma_kernel(const uint4 *__
         row = q0 + r < nq ? q + (uint64_t)(q0 + r) * 32 : nullptr;
     else
         row = t0 + (r - MQ) < n ? db + (t0 + (r - MQ)) * 32 : nullptr;
-    mt::v4i acc[8][4];
+    mt::v4f acc[8][4];
     mt::overlap_tile(row, sm, acc);
 
     // epilogue: keys of this lane's 32 queries x 4 rows
@@ -69,7 +69,7 @@ __global__ __launch_bounds__(mt::kThreads) void scan_mfma_kernel(const uint4 *__
             for (int b = 0; b < 4; b++) {
                 const uint64_t t = t0 + mt::acc_brow(b);
                 if (t >= n) continue;
-                const uint32_t C = (uint32_t)acc[a][b][r];
+                const uint32_t C = mt::count(acc[a][b][r]);
                 const uint32_t K = (pq - C) * wb + ((uint32_t)tpop[t] - C) * wa;
                 const u64 key = ((u64)K << 32) | (uint32_t)t;
                 if (key <= th) {

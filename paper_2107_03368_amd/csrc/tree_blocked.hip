@@ -107,7 +107,7 @@ __global__ __launch_bounds__(mt::kThreads) void bound_kernel(const uint4 *__rest
         row = q0 + r < nqb ? q + (uint64_t)(q0 + r) * 32 : nullptr;
     else
         row = b0 + (r - mt::MA) < nblk ? img + (b0 + (r - mt::MA)) * 32 : nullptr;
-    mt::v4i acc[8][4];
+    mt::v4f acc[8][4];
     mt::overlap_tile(row, sm, acc);
 #pragma unroll
     for (int a = 0; a < 8; a++)
@@ -122,7 +122,7 @@ __global__ __launch_bounds__(mt::kThreads) void bound_kernel(const uint4 *__rest
                 const uint32_t qi = qa + r;
                 uint32_t v = 0xFFFFu;
                 if (qi < nqb) {
-                    v = (uint32_t)qpop[qi] - (uint32_t)acc[a][bb][r];
+                    v = (uint32_t)qpop[qi] - mt::count(acc[a][bb][r]);
                     lbq[(uint64_t)qi * nblk + blk] = (uint16_t)v;
                 }
                 packed |= (u64)v << (16 * r);
@@ -431,7 +431,7 @@ __global__ __launch_bounds__(mt::kThreads) void eval_kernel(const uint4 *__restr
         row = (uint32_t)r < m ? q + (uint64_t)lq[r] * 32 : nullptr;
     else
         row = r0 + (r - mt::MA) < n ? sorted + (r0 + (r - mt::MA)) * 32 : nullptr;
-    mt::v4i acc[8][4];
+    mt::v4f acc[8][4];
     mt::overlap_tile(row, sm, acc);
 #pragma unroll
     for (int a = 0; a < 8; a++)
@@ -447,7 +447,7 @@ __global__ __launch_bounds__(mt::kThreads) void eval_kernel(const uint4 *__restr
             for (int bb = 0; bb < 4; bb++) {
                 const uint64_t row = r0 + mt::acc_brow(bb);
                 if (row >= n) continue;
-                const uint32_t C = (uint32_t)acc[a][bb][r];
+                const uint32_t C = mt::count(acc[a][bb][r]);
                 const uint32_t K = (pq - C) * wb + ((uint32_t)tpop[row] - C) * wa;
                 if (K <= th) {
                     const uint32_t pos = atomicAdd(&ccnt[qi], 1u);
