@@ -40,6 +40,8 @@ __global__ __launch_bounds__(mt::kThreads) void scan_mfma_kernel(const uint4 *__
                                                                  const u64 *__restrict__ thr, uint32_t n_qtiles,
                                                                  uint32_t *__restrict__ cnt, u64 *__restrict__ cand) {
     __shared__ mt::Smem sm;
+    __shared__ uint32_t s_pq[MQ], s_tp[MR];  // |q| of the tile's queries, |t| of its rows
+    __shared__ u64 s_th[MQ];                 // the queries' candidate bounds
     // consecutive workgroups share a row tile and spread over the XCDs, so every
     // XCD's L2 keeps a few query tiles resident while the rows stream through
     const uint32_t qt = blockIdx.x % n_qtiles;
@@ -48,29 +50,37 @@ __global__ __launch_bounds__(mt::kThreads) void scan_mfma_kernel(const uint4 *__
     const uint64_t t0 = rt * MR;
     const int r = mt::own_row();
     const uint4 *row;
-    if (r < MQ)
-        row = q0 + r < nq ? q + (uint64_t)(q0 + r) * 32 : nullptr;
-    else
-        row = t0 + (r - MQ) < n ? db + (t0 + (r - MQ)) * 32 : nullptr;
+    if (r < MQ) {
+        const bool ok = q0 + r < nq;
+        row = ok ? q + (uint64_t)(q0 + r) * 32 : nullptr;
+        s_pq[r] = ok ? qpop[q0 + r] : 0;
+        s_th[r] = ok ? thr[q0 + r] : 0;
+    } else {
+        const bool ok = t0 + (r - MQ) < n;
+        row = ok ? db + (t0 + (r - MQ)) * 32 : nullptr;
+        s_tp[r - MQ] = ok ? tpop[t0 + (r - MQ)] : 0;
+    }
     mt::v4f acc[8][4];
-    mt::overlap_tile(row, sm, acc);
+    mt::overlap_tile(row, sm, acc);  // its barriers also publish the metadata above
 
     // epilogue: keys of this lane's 32 queries x 4 rows
 #pragma unroll
     for (int a = 0; a < 8; a++)
 #pragma unroll
-        for (int r = 0; r < 4; r++) {
-            const uint32_t qi = q0 + mt::acc_arow(a, r);
+        for (int rr = 0; rr < 4; rr++) {
+            const int ai = mt::acc_arow(a, rr);
+            const uint32_t qi = q0 + ai;
             if (qi >= nq) continue;
-            const uint32_t pq = qpop[qi];
+            const uint32_t pq = s_pq[ai];
             const uint32_t wa = pq > 1 ? pq : 1, wb = (QD_BITS - pq) > 1 ? QD_BITS - pq : 1;
-            const u64 th = thr[qi];
+            const u64 th = s_th[ai];
 #pragma unroll
             for (int b = 0; b < 4; b++) {
-                const uint64_t t = t0 + mt::acc_brow(b);
+                const int bi = mt::acc_brow(b);
+                const uint64_t t = t0 + bi;
                 if (t >= n) continue;
-                const uint32_t C = mt::count(acc[a][b][r]);
-                const uint32_t K = (pq - C) * wb + ((uint32_t)tpop[t] - C) * wa;
+                const uint32_t C = mt::count(acc[a][b][rr]);
+                const uint32_t K = (pq - C) * wb + (s_tp[bi] - C) * wa;
                 const u64 key = ((u64)K << 32) | (uint32_t)t;
                 if (key <= th) {
                     const uint32_t pos = atomicAdd(&cnt[qi], 1u);

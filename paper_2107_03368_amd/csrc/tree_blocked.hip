@@ -101,14 +101,17 @@ __global__ __launch_bounds__(mt::kThreads) void bound_kernel(const uint4 *__rest
     __shared__ mt::Smem sm;
     const uint32_t q0 = (blockIdx.x % n_qtiles) * mt::MA;
     const uint64_t b0 = (uint64_t)(blockIdx.x / n_qtiles) * mt::MB;
-    const int r = mt::own_row();
+    __shared__ uint32_t s_pq[mt::MA];
+    const int own = mt::own_row();
     const uint4 *row;
-    if (r < mt::MA)
-        row = q0 + r < nqb ? q + (uint64_t)(q0 + r) * 32 : nullptr;
-    else
-        row = b0 + (r - mt::MA) < nblk ? img + (b0 + (r - mt::MA)) * 32 : nullptr;
+    if (own < mt::MA) {
+        row = q0 + own < nqb ? q + (uint64_t)(q0 + own) * 32 : nullptr;
+        s_pq[own] = q0 + own < nqb ? qpop[q0 + own] : 0;
+    } else {
+        row = b0 + (own - mt::MA) < nblk ? img + (b0 + (own - mt::MA)) * 32 : nullptr;
+    }
     mt::v4f acc[8][4];
-    mt::overlap_tile(row, sm, acc);
+    mt::overlap_tile(row, sm, acc);  // its barriers also publish s_pq
 #pragma unroll
     for (int a = 0; a < 8; a++)
 #pragma unroll
@@ -122,7 +125,7 @@ __global__ __launch_bounds__(mt::kThreads) void bound_kernel(const uint4 *__rest
                 const uint32_t qi = qa + r;
                 uint32_t v = 0xFFFFu;
                 if (qi < nqb) {
-                    v = (uint32_t)qpop[qi] - mt::count(acc[a][bb][r]);
+                    v = s_pq[qi - q0] - mt::count(acc[a][bb][r]);
                     lbq[(uint64_t)qi * nblk + blk] = (uint16_t)v;
                 }
                 packed |= (u64)v << (16 * r);
@@ -425,33 +428,43 @@ __global__ __launch_bounds__(mt::kThreads) void eval_kernel(const uint4 *__restr
     const uint32_t m = left < (uint32_t)mt::MA ? left : (uint32_t)mt::MA;
     const uint16_t *lq = list + b * nqp + t0;
     const uint64_t r0 = b * kBlk;
+    __shared__ uint32_t s_qi[mt::MA], s_pq[mt::MA], s_th[mt::MA], s_tp[mt::MB];
     const int r = mt::own_row();
     const uint4 *row;
-    if (r < mt::MA)
-        row = (uint32_t)r < m ? q + (uint64_t)lq[r] * 32 : nullptr;
-    else
-        row = r0 + (r - mt::MA) < n ? sorted + (r0 + (r - mt::MA)) * 32 : nullptr;
+    if (r < mt::MA) {
+        const bool ok = (uint32_t)r < m;
+        const uint32_t qi = ok ? lq[r] : 0;
+        row = ok ? q + (uint64_t)qi * 32 : nullptr;
+        s_qi[r] = qi;
+        s_pq[r] = ok ? qpop[qi] : 0;
+        s_th[r] = ok ? thrk[qi] : 0;
+    } else {
+        const bool ok = r0 + (r - mt::MA) < n;
+        row = ok ? sorted + (r0 + (r - mt::MA)) * 32 : nullptr;
+        s_tp[r - mt::MA] = ok ? tpop[r0 + (r - mt::MA)] : 0;
+    }
     mt::v4f acc[8][4];
-    mt::overlap_tile(row, sm, acc);
+    mt::overlap_tile(row, sm, acc);  // its barriers also publish the metadata above
 #pragma unroll
     for (int a = 0; a < 8; a++)
 #pragma unroll
-        for (int r = 0; r < 4; r++) {
-            const uint32_t i = (uint32_t)mt::acc_arow(a, r);
+        for (int rr = 0; rr < 4; rr++) {
+            const uint32_t i = (uint32_t)mt::acc_arow(a, rr);
             if (i >= m) continue;
-            const uint32_t qi = lq[i];
-            const uint32_t pq = qpop[qi];
+            const uint32_t qi = s_qi[i];
+            const uint32_t pq = s_pq[i];
             const uint32_t wa = weight_a(pq), wb = weight_b(pq);
-            const uint32_t th = thrk[qi];
+            const uint32_t th = s_th[i];
 #pragma unroll
             for (int bb = 0; bb < 4; bb++) {
-                const uint64_t row = r0 + mt::acc_brow(bb);
-                if (row >= n) continue;
-                const uint32_t C = mt::count(acc[a][bb][r]);
-                const uint32_t K = (pq - C) * wb + ((uint32_t)tpop[row] - C) * wa;
+                const int bi = mt::acc_brow(bb);
+                const uint64_t rw = r0 + bi;
+                if (rw >= n) continue;
+                const uint32_t C = mt::count(acc[a][bb][rr]);
+                const uint32_t K = (pq - C) * wb + (s_tp[bi] - C) * wa;
                 if (K <= th) {
                     const uint32_t pos = atomicAdd(&ccnt[qi], 1u);
-                    if (pos < kCap) cand[(uint64_t)qi * kCap + pos] = ((u64)K << 32) | perm[row];
+                    if (pos < kCap) cand[(uint64_t)qi * kCap + pos] = ((u64)K << 32) | perm[rw];
                 }
             }
         }
