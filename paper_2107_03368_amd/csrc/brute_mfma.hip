@@ -50,18 +50,19 @@ __global__ __launch_bounds__(mt::kThreads) void scan_mfma_kernel(const uint4 *__
     const uint64_t t0 = rt * MR;
     const int r = mt::own_row();
     const uint4 *row;
+    bool ok;
     if (r < MQ) {
-        const bool ok = q0 + r < nq;
-        row = ok ? q + (uint64_t)(q0 + r) * 32 : nullptr;
+        ok = q0 + r < nq;
+        row = ok ? q + (uint64_t)(q0 + r) * 32 : q;
         s_pq[r] = ok ? qpop[q0 + r] : 0;
         s_th[r] = ok ? thr[q0 + r] : 0;
     } else {
-        const bool ok = t0 + (r - MQ) < n;
-        row = ok ? db + (t0 + (r - MQ)) * 32 : nullptr;
+        ok = t0 + (r - MQ) < n;
+        row = ok ? db + (t0 + (r - MQ)) * 32 : db;
         s_tp[r - MQ] = ok ? tpop[t0 + (r - MQ)] : 0;
     }
     mt::v4f acc[8][4];
-    mt::overlap_tile(row, sm, acc);  // its barriers also publish the metadata above
+    mt::overlap_tile(row, !ok, sm, acc);  // its barriers also publish the metadata above
 
     // epilogue: keys of this lane's 32 queries x 4 rows
 #pragma unroll

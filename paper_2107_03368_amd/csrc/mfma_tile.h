@@ -20,7 +20,7 @@
 // Lane l supplies A rows (l % 16) at k = 32*(l/16) .. +31 (16 bytes) and B
 // columns likewise, and receives C rows 4*(l/16) .. +3 of column l % 16.
 //
-// A null row reads as zeros.  The tile is the same whether rows are contiguous
+// A missing row reads as zeros.  The tile is the same whether rows are contiguous
 // (sequential search) or gathered through a list (the blocked tree search).
 #pragma once
 
@@ -61,9 +61,6 @@ __device__ __forceinline__ void unpack_half(uint4 p, uint8_t *dst) {
             make_uint4(nib8(w[j] & 0xFF), nib8((w[j] >> 8) & 0xFF), nib8((w[j] >> 16) & 0xFF), nib8(w[j] >> 24));
 }
 
-// Read in place of a missing row (all zero bits).
-static __device__ const uint4 zero_row[32] = {};
-
 // Workgroups are dispatched to the 8 XCDs round-robin (workgroup x runs on
 // XCD x % 8), and each XCD has its own L2.  xcd_tile maps workgroup x to a
 // tile index so that every XCD gets one contiguous range of the n tiles: tiles
@@ -93,8 +90,9 @@ __device__ __forceinline__ int acc_brow(int b) {
 // Exact count held by an accumulator entry.
 __device__ __forceinline__ uint32_t count(float c) { return (uint32_t)c; }
 
-// row: this thread's row (32 x 16 bytes) or null
-__device__ __forceinline__ void overlap_tile(const uint4 *row, Smem &sm, v4f (&acc)[8][4]) {
+// row: this thread's row (32 x 16 bytes), always a readable global row; when
+// zero is set its bits count as 0 (a missing row past the end of the input)
+__device__ __forceinline__ void overlap_tile(const uint4 *row, bool zero, Smem &sm, v4f (&acc)[8][4]) {
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int wq = w >> 2, wr = w & 3;  // 2 x 4 waves, each 128 A rows x 64 B rows
     const int li = lane & 15, lg = lane >> 4;
@@ -104,17 +102,22 @@ __device__ __forceinline__ void overlap_tile(const uint4 *row, Smem &sm, v4f (&a
 #pragma unroll
         for (int b = 0; b < 4; b++) acc[a][b] = v4f{0.f, 0.f, 0.f, 0.f};
 
-    // window v of this thread's row is its 16-byte pieces 2v, 2v+1
-    const uint4 *src = row ? row : zero_row;
+    // window v of this thread's row is its 16-byte pieces 2v, 2v+1 (global
+    // loads: a generic pointer would make them flat loads, which also hold
+    // the LDS counter the fragment reads wait on)
+    auto piece = [&](int i) {
+        const uint4 v = row[i];
+        return zero ? make_uint4(0, 0, 0, 0) : v;
+    };
     constexpr int kWins = 4096 / WIN;
-    unpack_half(src[0], sm.uk[0] + tid * UST);
-    unpack_half(src[1], sm.uk[0] + tid * UST + 64);
+    unpack_half(piece(0), sm.uk[0] + tid * UST);
+    unpack_half(piece(1), sm.uk[0] + tid * UST + 64);
     __syncthreads();
     for (int win = 0; win < kWins; win++) {  // window win is in buffer win & 1
         const int h = win & 1;
         const bool more = win + 1 < kWins;
         // the next window: in flight during this one's matrix steps
-        const uint4 n0 = src[more ? 2 * win + 2 : 0], n1 = src[more ? 2 * win + 3 : 1];
+        const uint4 n0 = piece(more ? 2 * win + 2 : 0), n1 = piece(more ? 2 * win + 3 : 1);
         const uint8_t *ua = sm.uk[h];
         const uint8_t *ubp = sm.uk[h] + MA * UST;
         uint8_t *nx = sm.uk[h ^ 1] + tid * UST;  // last read before the previous barrier

@@ -104,14 +104,17 @@ __global__ __launch_bounds__(mt::kThreads) void bound_kernel(const uint4 *__rest
     __shared__ uint32_t s_pq[mt::MA];
     const int own = mt::own_row();
     const uint4 *row;
+    bool ok;
     if (own < mt::MA) {
-        row = q0 + own < nqb ? q + (uint64_t)(q0 + own) * 32 : nullptr;
-        s_pq[own] = q0 + own < nqb ? qpop[q0 + own] : 0;
+        ok = q0 + own < nqb;
+        row = ok ? q + (uint64_t)(q0 + own) * 32 : q;
+        s_pq[own] = ok ? qpop[q0 + own] : 0;
     } else {
-        row = b0 + (own - mt::MA) < nblk ? img + (b0 + (own - mt::MA)) * 32 : nullptr;
+        ok = b0 + (own - mt::MA) < nblk;
+        row = ok ? img + (b0 + (own - mt::MA)) * 32 : img;
     }
     mt::v4f acc[8][4];
-    mt::overlap_tile(row, sm, acc);  // its barriers also publish s_pq
+    mt::overlap_tile(row, !ok, sm, acc);  // its barriers also publish s_pq
 #pragma unroll
     for (int a = 0; a < 8; a++)
 #pragma unroll
@@ -431,20 +434,21 @@ __global__ __launch_bounds__(mt::kThreads) void eval_kernel(const uint4 *__restr
     __shared__ uint32_t s_qi[mt::MA], s_pq[mt::MA], s_th[mt::MA], s_tp[mt::MB];
     const int r = mt::own_row();
     const uint4 *row;
+    bool ok;
     if (r < mt::MA) {
-        const bool ok = (uint32_t)r < m;
+        ok = (uint32_t)r < m;
         const uint32_t qi = ok ? lq[r] : 0;
-        row = ok ? q + (uint64_t)qi * 32 : nullptr;
+        row = q + (uint64_t)qi * 32;
         s_qi[r] = qi;
         s_pq[r] = ok ? qpop[qi] : 0;
         s_th[r] = ok ? thrk[qi] : 0;
     } else {
-        const bool ok = r0 + (r - mt::MA) < n;
-        row = ok ? sorted + (r0 + (r - mt::MA)) * 32 : nullptr;
+        ok = r0 + (r - mt::MA) < n;
+        row = ok ? sorted + (r0 + (r - mt::MA)) * 32 : sorted;
         s_tp[r - mt::MA] = ok ? tpop[r0 + (r - mt::MA)] : 0;
     }
     mt::v4f acc[8][4];
-    mt::overlap_tile(row, sm, acc);  // its barriers also publish the metadata above
+    mt::overlap_tile(row, !ok, sm, acc);  // its barriers also publish the metadata above
 #pragma unroll
     for (int a = 0; a < 8; a++)
 #pragma unroll
