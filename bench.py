@@ -44,7 +44,14 @@ TRAIN_QUERIES, TRAIN_BATCH, TRAIN_EPOCHS, TRAIN_LR, N_SCORED = 1024, 16, 4, 1e-3
 # from the FETCH_SIZE / WRITE_SIZE counters (KiB) scaled by what they read for a
 # 1 GiB device copy (FETCH 524,315 KiB, WRITE 1,048,576 KiB); drop an entry
 # when its kernel changes
-TRAFFIC_DETAIL = {}
+TRAFFIC_DETAIL = {
+    # scan_mfma_kernel at 10M x 8,192: one launch
+    "scan_mfma_kernel": {"read_bytes": 20_080_462 * 2 * 1024, "write_bytes": 515_391 * 1024,
+                         "algorithmic_read_bytes": 5.124e9, "counter_scale": {"FETCH_SIZE": 2.0, "WRITE_SIZE": 1.0}},
+    # eval_kernel at 10M x 8,192, k = 10: the average of the 5 launches of one search
+    "eval_kernel": {"read_bytes": 12_145_827 / 5 * 2 * 1024, "write_bytes": 256_244 / 5 * 1024,
+                    "counter_scale": {"FETCH_SIZE": 2.0, "WRITE_SIZE": 1.0}},
+}
 TRAFFIC = {kname: d["read_bytes"] + d["write_bytes"] for kname, d in TRAFFIC_DETAIL.items()}
 
 
