@@ -39,7 +39,7 @@ OPS_PER_PAIR = 256  # 128 x (AND + BCNT) over 4096 bits
 ROW_BYTES = 512
 # frontier-order model: trained on the 1M database's traces, scores the top
 # N_SCORED nodes (depth <= 10) of the searched tree
-TRAIN_QUERIES, TRAIN_BATCH, TRAIN_EPOCHS, TRAIN_LR, N_SCORED = 1024, 16, 4, 1e-3, 2047
+TRAIN_QUERIES, TRAIN_BATCH, TRAIN_EPOCHS, TRAIN_LR, N_SCORED = 4096, 32, 8, 2e-3, 2047
 # HBM bytes per launch of the matrix-core kernels at the 10M x 8,192 workload,
 # from the FETCH_SIZE / WRITE_SIZE counters (KiB) scaled by what they read for a
 # 1 GiB device copy (FETCH 524,315 KiB, WRITE 1,048,576 KiB); drop an entry

@@ -301,60 +301,117 @@ __global__ __launch_bounds__(kBlock) void head_kernel(const float *__restrict__ 
     }
 }
 
-// Column reductions for the head and layer-2 biases:
+// Column reductions for the head and layer-2 biases, in two deterministic
+// stages (fixed chunks of pairs, then a fixed-order sum over the chunks):
 //   g[W3+j] = sum_p ds[p] h2[p][j]   g[B2+j] = w3[j] sum_p ds[p] [h2[p][j] > 0]
 //   g[B3] = sum_p ds[p]              loss = mean_p loss[p]
-__global__ __launch_bounds__(kBlock) void head_grad_kernel(const float *__restrict__ h2, const float *__restrict__ ds,
-                                                           const float *__restrict__ lossv, uint64_t n_pairs,
-                                                           const uint16_t *__restrict__ w, float *__restrict__ g,
-                                                           float *__restrict__ loss) {
+constexpr uint32_t kHeadParts = 128;
+constexpr uint32_t kHeadPartLen = 2 * H + 2;  // a[H], b[H], sum ds, sum loss
+
+__global__ __launch_bounds__(kBlock) void head_partial_kernel(const float *__restrict__ h2,
+                                                              const float *__restrict__ ds,
+                                                              const float *__restrict__ lossv, uint64_t n_pairs,
+                                                              float *__restrict__ part) {
+    const uint32_t g = blockIdx.x;
+    const uint64_t chunk = (n_pairs + kHeadParts - 1) / kHeadParts;
+    const uint64_t p0 = g * chunk, p1 = p0 + chunk < n_pairs ? p0 + chunk : n_pairs;
     const int j = threadIdx.x;
     float a = 0.f, b = 0.f;
-    for (uint64_t p = 0; p < n_pairs; p++) {
+    for (uint64_t p = p0; p < p1; p++) {
         const float h = h2[p * H + j];
         a += ds[p] * h;
         b += h > 0.f ? ds[p] : 0.f;
     }
+    float *o = part + (size_t)g * kHeadPartLen;
+    o[j] = a;
+    o[H + j] = b;
+    if (j == 0) {
+        float sd = 0.f, sl = 0.f;
+        for (uint64_t p = p0; p < p1; p++) {
+            sd += ds[p];
+            sl += lossv[p];
+        }
+        o[2 * H] = sd;
+        o[2 * H + 1] = sl;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void head_final_kernel(const float *__restrict__ part, uint64_t n_pairs,
+                                                            const uint16_t *__restrict__ w, float *__restrict__ g,
+                                                            float *__restrict__ loss) {
+    const int j = threadIdx.x;
+    float a = 0.f, b = 0.f;
+    for (uint32_t k = 0; k < kHeadParts; k++) {
+        a += part[(size_t)k * kHeadPartLen + j];
+        b += part[(size_t)k * kHeadPartLen + H + j];
+    }
     g[OFF_W3 + j] = a;
     g[OFF_B2 + j] = b * bf2f(w[OFF_W3 + j]);
     if (j == 0) {
-        float s = 0.f, l = 0.f;
-        for (uint64_t p = 0; p < n_pairs; p++) {
-            s += ds[p];
-            l += lossv[p];
+        float sd = 0.f, sl = 0.f;
+        for (uint32_t k = 0; k < kHeadParts; k++) {
+            sd += part[(size_t)k * kHeadPartLen + 2 * H];
+            sl += part[(size_t)k * kHeadPartLen + 2 * H + 1];
         }
-        g[OFF_B3] = s;
-        if (loss) *loss = l / (float)n_pairs;
+        g[OFF_B3] = sd;
+        if (loss) *loss = sl / (float)n_pairs;
     }
 }
 
 // dz1[p][j] = dh1[p][j] * [h1[p][j] > 0]; then
 //   g[B1+j] = sum_p dz1   g[W1F + f*H + j] = sum_p feat[p][f] dz1[p][j]
 //   du[q][j] = sum over the pairs of query q of dz1 (pairs grouped by query)
-__global__ __launch_bounds__(kBlock) void layer1_grad_kernel(const float *__restrict__ dh1,
-                                                             const uint16_t *__restrict__ h1,
-                                                             const float *__restrict__ feat,
-                                                             const uint64_t *__restrict__ qoff, uint64_t qoff_base,
-                                                             uint32_t nq, float *__restrict__ g,
-                                                             float *__restrict__ du) {
+// Stage 1: block (q, c) sums chunk c of query q's pairs; stage 2 sums the
+// chunks in a fixed order.
+constexpr uint32_t kL1Chunks = 8;
+constexpr uint32_t kL1PartLen = (NF + 1) * H;  // gf[NF][H], su[H]
+
+__global__ __launch_bounds__(kBlock) void layer1_partial_kernel(const float *__restrict__ dh1,
+                                                                const uint16_t *__restrict__ h1,
+                                                                const float *__restrict__ feat,
+                                                                const uint64_t *__restrict__ qoff,
+                                                                uint64_t qoff_base, float *__restrict__ part) {
+    const uint32_t qi = blockIdx.x / kL1Chunks, c = blockIdx.x % kL1Chunks;
     const int j = threadIdx.x;
-    float gb = 0.f, gf[NF];
+    const uint64_t b0 = qoff[qi] - qoff_base, b1 = qoff[qi + 1] - qoff_base;
+    const uint64_t chunk = (b1 - b0 + kL1Chunks - 1) / kL1Chunks;
+    const uint64_t p0 = b0 + c * chunk < b1 ? b0 + c * chunk : b1;
+    const uint64_t p1 = p0 + chunk < b1 ? p0 + chunk : b1;
+    float su = 0.f, gf[NF];
 #pragma unroll
     for (int i = 0; i < NF; i++) gf[i] = 0.f;
-    for (uint32_t qi = 0; qi < nq; qi++) {
-        float su = 0.f;
-        for (uint64_t p = qoff[qi] - qoff_base; p < qoff[qi + 1] - qoff_base; p++) {
-            const float dz = bf2f(h1[p * 2 * H + j]) > 0.f ? dh1[p * H + j] : 0.f;
-            su += dz;
+    for (uint64_t p = p0; p < p1; p++) {
+        const float dz = bf2f(h1[p * 2 * H + j]) > 0.f ? dh1[p * H + j] : 0.f;
+        su += dz;
 #pragma unroll
-            for (int i = 0; i < NF; i++) gf[i] += feat[p * NF + i] * dz;
-        }
-        du[(size_t)qi * H + j] = su;
-        gb += su;
+        for (int i = 0; i < NF; i++) gf[i] += feat[p * NF + i] * dz;
     }
-    g[OFF_B1 + j] = gb;
+    float *o = part + (size_t)blockIdx.x * kL1PartLen;
 #pragma unroll
-    for (int i = 0; i < NF; i++) g[OFF_W1F + (size_t)i * H + j] = gf[i];
+    for (int i = 0; i < NF; i++) o[(size_t)i * H + j] = gf[i];
+    o[(size_t)NF * H + j] = su;
+}
+
+// Block i < NF: g[W1F + i*H + j]; block NF: du and g[B1].
+__global__ __launch_bounds__(kBlock) void layer1_final_kernel(const float *__restrict__ part, uint32_t nq,
+                                                              float *__restrict__ g, float *__restrict__ du) {
+    const uint32_t i = blockIdx.x;
+    const int j = threadIdx.x;
+    if (i < NF) {
+        float a = 0.f;
+        for (uint32_t k = 0; k < nq * kL1Chunks; k++) a += part[(size_t)k * kL1PartLen + (size_t)i * H + j];
+        g[OFF_W1F + (size_t)i * H + j] = a;
+    } else {
+        float gb = 0.f;
+        for (uint32_t qi = 0; qi < nq; qi++) {
+            float su = 0.f;
+            for (uint32_t c = 0; c < kL1Chunks; c++)
+                su += part[(size_t)(qi * kL1Chunks + c) * kL1PartLen + (size_t)NF * H + j];
+            du[(size_t)qi * H + j] = su;
+            gb += su;
+        }
+        g[OFF_B1 + j] = gb;
+    }
 }
 
 // g[W1Q + b*H + j] = sum_q bit(q, b) du[q][j]
@@ -439,6 +496,8 @@ struct Scratch {
     uint16_t *d2 = nullptr; // P x H   (training)
     float *dw2 = nullptr;   // H x H
     float *du = nullptr;    // nq x H
+    float *hpart = nullptr; // kHeadParts x kHeadPartLen
+    float *lpart = nullptr; // nq x kL1Chunks x kL1PartLen
 };
 
 }  // namespace
@@ -521,7 +580,9 @@ static int mlp_run(qd_model_t m, const uint64_t *d_q, uint32_t q0, uint32_t nq, 
     const uint64_t np = pad64(n_pairs ? n_pairs : 1);
     const bool train = y != nullptr;
     size_t bytes = (size_t)nq * H * 4 + np * H * 4 + np * H * 4 + np * 4;
-    if (train) bytes += np * H * 4 + np * 4 + np * 4 + np * H * 2 + (size_t)H * H * 4 + (size_t)nq * H * 4;
+    if (train)
+        bytes += np * H * 4 + np * 4 + np * 4 + np * H * 2 + (size_t)H * H * 4 + (size_t)nq * H * 4 +
+                 (size_t)kHeadParts * kHeadPartLen * 4 + (size_t)nq * kL1Chunks * kL1PartLen * 4;
     char *ws = nullptr;
     QD_HIP_CHECK(hipMallocAsync((void **)&ws, bytes + 64 * 16, s));
     char *c = ws;
@@ -542,6 +603,8 @@ static int mlp_run(qd_model_t m, const uint64_t *d_q, uint32_t q0, uint32_t nq, 
         S.d2 = (uint16_t *)take(np * H * 2);
         S.dw2 = (float *)take((size_t)H * H * 4);
         S.du = (float *)take((size_t)nq * H * 4);
+        S.hpart = (float *)take((size_t)kHeadParts * kHeadPartLen * 4);
+        S.lpart = (float *)take((size_t)nq * kL1Chunks * kL1PartLen * 4);
     }
     {
         KernelTimer timer("mlp_forward", s);
@@ -555,15 +618,17 @@ static int mlp_run(qd_model_t m, const uint64_t *d_q, uint32_t q0, uint32_t nq, 
     hipError_t e = hipGetLastError();
     if (train && e == hipSuccess) {
         KernelTimer timer("mlp_backward", s);
-        hipLaunchKernelGGL(head_grad_kernel, dim3(1), dim3(kBlock), 0, s, S.h2, S.ds, S.lossv, n_pairs, m->w, d_grads,
-                           d_loss);
+        hipLaunchKernelGGL(head_partial_kernel, dim3(kHeadParts), dim3(kBlock), 0, s, S.h2, S.ds, S.lossv, n_pairs,
+                           S.hpart);
+        hipLaunchKernelGGL(head_final_kernel, dim3(1), dim3(kBlock), 0, s, S.hpart, n_pairs, m->w, d_grads, d_loss);
         // dW2 = (h1_hi + h1_lo)^T d2 ; dh1 = d2 W2^T (into z2's buffer)
         gemm(s, true, false, S.h1, S.d2, S.dw2, H, H, (int)np, 2 * H, H, H);
         gemm(s, true, false, S.h1 + H, S.d2, S.dw2, H, H, (int)np, 2 * H, H, H, 1);
         gemm(s, false, true, S.d2, m->w + OFF_W2, S.z2, (int)np, H, H, H, H, H);
         hipLaunchKernelGGL(copy_grad_w2_kernel, dim3(H * H / kBlock), dim3(kBlock), 0, s, S.dw2, d_grads);
-        hipLaunchKernelGGL(layer1_grad_kernel, dim3(1), dim3(kBlock), 0, s, S.z2, S.h1, d_feat, d_qoff, qoff_base, nq,
-                           d_grads, S.du);
+        hipLaunchKernelGGL(layer1_partial_kernel, dim3(nq * kL1Chunks), dim3(kBlock), 0, s, S.z2, S.h1, d_feat, d_qoff,
+                           qoff_base, S.lpart);
+        hipLaunchKernelGGL(layer1_final_kernel, dim3(NF + 1), dim3(kBlock), 0, s, S.lpart, nq, d_grads, S.du);
         hipLaunchKernelGGL(w1q_grad_kernel, dim3(QD_BITS), dim3(kBlock), 0, s, d_q + (uint64_t)q0 * QD_WORDS, nq,
                            S.du, d_grads);
         e = hipGetLastError();

@@ -145,3 +145,32 @@ def test_training_lowers_the_loss_and_the_learned_search_is_exact(qd, setup, sma
         res = qd.knn_tree(tree, _t(q), k, order=qd.ORDER_DEPTH_FIRST, scores=scores)
         assert np.array_equal(res[0].cpu().numpy().view(np.uint32), ref.idx)
         assert np.array_equal(res[3].cpu().numpy(), ref.dist)
+
+
+def test_trained_order_gain_over_bound_order(qd):
+    """What the trained network gains: a model trained on traces of the exact
+    search over a 1M-row database orders the depth-first frontier of a
+    different 1M-row database; it must visit fewer nodes than the bound
+    order, and its results stay exact."""
+    import torch
+    dev = "cuda:0"
+    tdb = synth.gen_db(1_000_000, 1001)
+    ttree = qd.tree_build(torch.from_numpy(tdb.view(np.int64)).to(dev))
+    tq, _ = synth.gen_queries(tdb, 4096, 2001, 0.1, 0.6)
+    model = qd.Model(_t(synth.uniform_f32(omlp.NPARAMS, 3003, -0.05, 0.05)))
+    nb = 4096 // 32
+    qd.model_train(model, ttree, _t(tq), 10, 2047, 8, 32, 2e-3, batch_order=synth.permutation(nb, 3004))
+    db = synth.gen_db(1_000_000, 1005)
+    q, _ = synth.gen_queries(db, 1024, 2005, 0.1, 0.6)
+    tree = qd.tree_build(_t(db))
+    qt = _t(q)
+    plain = qd.knn_tree(tree, qt, 10, order=qd.ORDER_DEPTH_FIRST, totals=True)
+    scores = qd.model_score_tree(model, tree, qt, 2047)
+    learned = qd.knn_tree(tree, qt, 10, order=qd.ORDER_DEPTH_FIRST, scores=scores, totals=True)
+    best = qd.knn_tree(tree, qt, 10, totals=True)
+    for a, b in zip(plain[:4], learned[:4]):
+        assert torch.equal(a, b)
+    n_plain, n_learned, n_best = (r[-1]["nodes_visited"] / len(q) for r in (plain, learned, best))
+    print(f"nodes visited per query: bound order {n_plain:.0f}, learned order {n_learned:.0f}, "
+          f"best-first {n_best:.0f}")
+    assert n_best <= n_learned < n_plain
