@@ -218,7 +218,8 @@ BruteLaunch brute_launch_shape(uint64_t n, uint32_t nq, uint32_t k, uint32_t qt_
 int brute_launch(const BruteLaunch &sh, u64 *part, const uint64_t *d_db, uint64_t n, const uint64_t *d_q, uint32_t nq,
                  const uint32_t *nq_dev, uint32_t k, uint32_t *d_idx, int32_t *d_missed, int32_t *d_extra,
                  float *d_dist, hipStream_t s) {
-    if (sh.blocks > 0x7FFFFFFFull) return fail(QD_ERR_INVALID, "launch too large");
+    // the dispatch packet holds the grid size in work-items as a 32-bit number
+    if (sh.blocks * kBlock > 0xFFFFFFFFull) return fail(QD_ERR_UNSUPPORTED, "launch too large");
     const uint4 *db4 = reinterpret_cast<const uint4 *>(d_db);
     const uint4 *q4 = reinterpret_cast<const uint4 *>(d_q);
     dim3 grid((uint32_t)sh.blocks);

@@ -42,53 +42,57 @@ __global__ __launch_bounds__(mt::kThreads) void scan_mfma_kernel(const uint4 *__
     __shared__ mt::Smem sm;
     __shared__ uint32_t s_pq[MQ], s_tp[MR];  // |q| of the tile's queries, |t| of its rows
     __shared__ u64 s_th[MQ];                 // the queries' candidate bounds
-    // consecutive workgroups share a row tile and spread over the XCDs, so every
-    // XCD's L2 keeps a few query tiles resident while the rows stream through
-    const uint32_t qt = blockIdx.x % n_qtiles;
-    const uint64_t rt = blockIdx.x / n_qtiles;
-    const uint32_t q0 = qt * MQ;
-    const uint64_t t0 = rt * MR;
-    const int r = mt::own_row();
-    const uint4 *row;
-    bool ok;
-    if (r < MQ) {
-        ok = q0 + r < nq;
-        row = ok ? q + (uint64_t)(q0 + r) * 32 : q;
-        s_pq[r] = ok ? qpop[q0 + r] : 0;
-        s_th[r] = ok ? thr[q0 + r] : 0;
-    } else {
-        ok = t0 + (r - MQ) < n;
-        row = ok ? db + (t0 + (r - MQ)) * 32 : db;
-        s_tp[r - MQ] = ok ? tpop[t0 + (r - MQ)] : 0;
-    }
-    mt::v4f acc[8][4];
-    mt::overlap_tile(row, !ok, sm, acc);  // its barriers also publish the metadata above
+    const uint64_t n_tiles = (uint64_t)n_qtiles * ((n + MR - 1) / MR);
+    for (uint64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+        // consecutive tiles share a row tile and spread over the XCDs, so every
+        // XCD's L2 keeps a few query tiles resident while the rows stream through
+        const uint32_t qt = (uint32_t)(tile % n_qtiles);
+        const uint64_t rt = tile / n_qtiles;
+        const uint32_t q0 = qt * MQ;
+        const uint64_t t0 = rt * MR;
+        const int r = mt::own_row();
+        const uint4 *row;
+        bool ok;
+        if (r < MQ) {
+            ok = q0 + r < nq;
+            row = ok ? q + (uint64_t)(q0 + r) * 32 : q;
+            s_pq[r] = ok ? qpop[q0 + r] : 0;
+            s_th[r] = ok ? thr[q0 + r] : 0;
+        } else {
+            ok = t0 + (r - MQ) < n;
+            row = ok ? db + (t0 + (r - MQ)) * 32 : db;
+            s_tp[r - MQ] = ok ? tpop[t0 + (r - MQ)] : 0;
+        }
+        mt::v4f acc[8][4];
+        mt::overlap_tile(row, !ok, sm, acc);  // its barriers also publish the metadata above
 
-    // epilogue: keys of this lane's 32 queries x 4 rows
+        // epilogue: keys of this lane's 32 queries x 4 rows
 #pragma unroll
-    for (int a = 0; a < 8; a++)
+        for (int a = 0; a < 8; a++)
 #pragma unroll
-        for (int rr = 0; rr < 4; rr++) {
-            const int ai = mt::acc_arow(a, rr);
-            const uint32_t qi = q0 + ai;
-            if (qi >= nq) continue;
-            const uint32_t pq = s_pq[ai];
-            const uint32_t wa = pq > 1 ? pq : 1, wb = (QD_BITS - pq) > 1 ? QD_BITS - pq : 1;
-            const u64 th = s_th[ai];
+            for (int rr = 0; rr < 4; rr++) {
+                const int ai = mt::acc_arow(a, rr);
+                const uint32_t qi = q0 + ai;
+                if (qi >= nq) continue;
+                const uint32_t pq = s_pq[ai];
+                const uint32_t wa = pq > 1 ? pq : 1, wb = (QD_BITS - pq) > 1 ? QD_BITS - pq : 1;
+                const u64 th = s_th[ai];
 #pragma unroll
-            for (int b = 0; b < 4; b++) {
-                const int bi = mt::acc_brow(b);
-                const uint64_t t = t0 + bi;
-                if (t >= n) continue;
-                const uint32_t C = mt::count(acc[a][b][rr]);
-                const uint32_t K = (pq - C) * wb + (s_tp[bi] - C) * wa;
-                const u64 key = ((u64)K << 32) | (uint32_t)t;
-                if (key <= th) {
-                    const uint32_t pos = atomicAdd(&cnt[qi], 1u);
-                    if (pos < kCap) cand[(uint64_t)qi * kCap + pos] = key;
+                for (int b = 0; b < 4; b++) {
+                    const int bi = mt::acc_brow(b);
+                    const uint64_t t = t0 + bi;
+                    if (t >= n) continue;
+                    const uint32_t C = mt::count(acc[a][b][rr]);
+                    const uint32_t K = (pq - C) * wb + (s_tp[bi] - C) * wa;
+                    const u64 key = ((u64)K << 32) | (uint32_t)t;
+                    if (key <= th) {
+                        const uint32_t pos = atomicAdd(&cnt[qi], 1u);
+                        if (pos < kCap) cand[(uint64_t)qi * kCap + pos] = key;
+                    }
                 }
             }
-        }
+        __syncthreads();  // the next tile rewrites the metadata
+    }
 }
 
 // One block per query: sort the candidates (<= kCap), write the first k.
@@ -178,7 +182,6 @@ int knn_bruteforce_mfma(const uint64_t *d_db, uint64_t n, const uint64_t *d_q, u
     if (sample * 4 > n) return QD_ERR_UNSUPPORTED;
     const uint32_t n_qtiles = (nq + MQ - 1) / MQ;
     const uint64_t n_rtiles = (n + MR - 1) / MR;
-    if ((uint64_t)n_qtiles * n_rtiles > 0x7FFFFFFFull) return QD_ERR_UNSUPPORTED;
     // scratch: tpop n*2 | qpop nq*2 | thr nq*8 | cnt nq*4 | cand nq*cap*8 | sample outputs nq*k*16 | redo nq*4+4
     const size_t a_tpop = 0, a_qpop = a_tpop + (n * 2 + 255) / 256 * 256;
     const size_t a_thr = a_qpop + ((size_t)nq * 2 + 255) / 256 * 256;
@@ -214,7 +217,7 @@ int knn_bruteforce_mfma(const uint64_t *d_db, uint64_t n, const uint64_t *d_q, u
         return done(fail(QD_ERR_DEVICE, "memset"));
     {
         KernelTimer timer("wh_scan_mfma", s);
-        hipLaunchKernelGGL(scan_mfma_kernel, dim3((uint32_t)(n_qtiles * n_rtiles)), dim3(mt::kThreads), 0, s,
+        hipLaunchKernelGGL(scan_mfma_kernel, dim3((uint32_t)mt::tile_grid(n_qtiles * n_rtiles)), dim3(mt::kThreads), 0, s,
                            reinterpret_cast<const uint4 *>(d_db), n, reinterpret_cast<const uint4 *>(d_q), nq, tpop,
                            qpop, thr, n_qtiles, cnt, cand);
     }

@@ -67,6 +67,12 @@ __device__ __forceinline__ void unpack_half(uint4 p, uint8_t *dst) {
 // that share B rows (consecutive indices) then share one L2.  Returns false
 // for the padding workgroups of a grid of xcd_grid(n) workgroups.
 constexpr uint32_t kXcds = 8;
+// A dispatch packet holds the grid size in work-items as a 32-bit number, so a
+// launch of kThreads-thread workgroups stays below 2^32 / kThreads of them;
+// kernels take their tiles in a workgroup-stride loop over a grid of at most
+// kMaxGrid workgroups (a multiple of kXcds, so a workgroup keeps its XCD).
+constexpr uint64_t kMaxGrid = 1ull << 22;
+__host__ __device__ inline uint64_t tile_grid(uint64_t n) { return n < kMaxGrid ? n : kMaxGrid; }
 __host__ __device__ inline uint64_t xcd_grid(uint64_t n) { return (n + kXcds - 1) / kXcds * kXcds; }
 __device__ __forceinline__ bool xcd_tile(uint64_t x, uint64_t n, uint64_t &tile) {
     const uint64_t per = (n + kXcds - 1) / kXcds;

@@ -99,42 +99,46 @@ __global__ __launch_bounds__(mt::kThreads) void bound_kernel(const uint4 *__rest
                                                              const uint16_t *__restrict__ qpop, uint32_t n_qtiles,
                                                              uint16_t *__restrict__ lbq, uint16_t *__restrict__ lbb) {
     __shared__ mt::Smem sm;
-    const uint32_t q0 = (blockIdx.x % n_qtiles) * mt::MA;
-    const uint64_t b0 = (uint64_t)(blockIdx.x / n_qtiles) * mt::MB;
     __shared__ uint32_t s_pq[mt::MA];
-    const int own = mt::own_row();
-    const uint4 *row;
-    bool ok;
-    if (own < mt::MA) {
-        ok = q0 + own < nqb;
-        row = ok ? q + (uint64_t)(q0 + own) * 32 : q;
-        s_pq[own] = ok ? qpop[q0 + own] : 0;
-    } else {
-        ok = b0 + (own - mt::MA) < nblk;
-        row = ok ? img + (b0 + (own - mt::MA)) * 32 : img;
-    }
-    mt::v4f acc[8][4];
-    mt::overlap_tile(row, !ok, sm, acc);  // its barriers also publish s_pq
-#pragma unroll
-    for (int a = 0; a < 8; a++)
-#pragma unroll
-        for (int bb = 0; bb < 4; bb++) {
-            const uint64_t blk = b0 + mt::acc_brow(bb);
-            if (blk >= nblk) continue;
-            const uint32_t qa = q0 + mt::acc_arow(a, 0);  // this lane's 4 consecutive queries
-            u64 packed = 0;
-#pragma unroll
-            for (int r = 0; r < 4; r++) {
-                const uint32_t qi = qa + r;
-                uint32_t v = 0xFFFFu;
-                if (qi < nqb) {
-                    v = s_pq[qi - q0] - mt::count(acc[a][bb][r]);
-                    lbq[(uint64_t)qi * nblk + blk] = (uint16_t)v;
-                }
-                packed |= (u64)v << (16 * r);
-            }
-            *reinterpret_cast<u64 *>(lbb + blk * nqp + qa) = packed;
+    const uint64_t n_tiles = (uint64_t)n_qtiles * ((nblk + mt::MB - 1) / mt::MB);
+    for (uint64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+        const uint32_t q0 = (uint32_t)(tile % n_qtiles) * mt::MA;
+        const uint64_t b0 = (tile / n_qtiles) * mt::MB;
+        const int own = mt::own_row();
+        const uint4 *row;
+        bool ok;
+        if (own < mt::MA) {
+            ok = q0 + own < nqb;
+            row = ok ? q + (uint64_t)(q0 + own) * 32 : q;
+            s_pq[own] = ok ? qpop[q0 + own] : 0;
+        } else {
+            ok = b0 + (own - mt::MA) < nblk;
+            row = ok ? img + (b0 + (own - mt::MA)) * 32 : img;
         }
+        mt::v4f acc[8][4];
+        mt::overlap_tile(row, !ok, sm, acc);  // its barriers also publish s_pq
+#pragma unroll
+        for (int a = 0; a < 8; a++)
+#pragma unroll
+            for (int bb = 0; bb < 4; bb++) {
+                const uint64_t blk = b0 + mt::acc_brow(bb);
+                if (blk >= nblk) continue;
+                const uint32_t qa = q0 + mt::acc_arow(a, 0);  // this lane's 4 consecutive queries
+                u64 packed = 0;
+#pragma unroll
+                for (int r = 0; r < 4; r++) {
+                    const uint32_t qi = qa + r;
+                    uint32_t v = 0xFFFFu;
+                    if (qi < nqb) {
+                        v = s_pq[qi - q0] - mt::count(acc[a][bb][r]);
+                        lbq[(uint64_t)qi * nblk + blk] = (uint16_t)v;
+                    }
+                    packed |= (u64)v << (16 * r);
+                }
+                *reinterpret_cast<u64 *>(lbb + blk * nqp + qa) = packed;
+            }
+        __syncthreads();  // the next tile rewrites s_pq
+    }
 }
 
 // Per query: histogram of A_lb over the blocks, round 1's blocks (the first
@@ -414,64 +418,69 @@ __global__ __launch_bounds__(mt::kThreads) void eval_kernel(const uint4 *__restr
                                                             const uint32_t *__restrict__ thrk,
                                                             uint32_t *__restrict__ ccnt, u64 *__restrict__ cand) {
     __shared__ mt::Smem sm;
-    uint64_t xt;
-    if (!mt::xcd_tile(blockIdx.x, off[nblk], xt)) return;
-    const uint32_t x = (uint32_t)xt;  // tiles of one block are consecutive
-    uint64_t lo = 0, hi = nblk;  // off[lo] <= x < off[hi]
-    while (hi - lo > 1) {
-        const uint64_t mid = (lo + hi) / 2;
-        if (off[mid] <= x)
-            lo = mid;
-        else
-            hi = mid;
-    }
-    const uint64_t b = lo;
-    const uint32_t t0 = (x - off[b]) * mt::MA;
-    const uint32_t left = cnt[b] - t0;
-    const uint32_t m = left < (uint32_t)mt::MA ? left : (uint32_t)mt::MA;
-    const uint16_t *lq = list + b * nqp + t0;
-    const uint64_t r0 = b * kBlk;
     __shared__ uint32_t s_qi[mt::MA], s_pq[mt::MA], s_th[mt::MA], s_tp[mt::MB];
-    const int r = mt::own_row();
-    const uint4 *row;
-    bool ok;
-    if (r < mt::MA) {
-        ok = (uint32_t)r < m;
-        const uint32_t qi = ok ? lq[r] : 0;
-        row = q + (uint64_t)qi * 32;
-        s_qi[r] = qi;
-        s_pq[r] = ok ? qpop[qi] : 0;
-        s_th[r] = ok ? thrk[qi] : 0;
-    } else {
-        ok = r0 + (r - mt::MA) < n;
-        row = ok ? sorted + (r0 + (r - mt::MA)) * 32 : sorted;
-        s_tp[r - mt::MA] = ok ? tpop[r0 + (r - mt::MA)] : 0;
-    }
-    mt::v4f acc[8][4];
-    mt::overlap_tile(row, !ok, sm, acc);  // its barriers also publish the metadata above
+    const uint64_t total = off[nblk];
+    // workgroup v of the virtual grid runs on XCD v % 8 (gridDim.x is a multiple of 8)
+    for (uint64_t v = blockIdx.x; v < mt::xcd_grid(total); v += gridDim.x) {
+        uint64_t xt;
+        if (!mt::xcd_tile(v, total, xt)) continue;
+        const uint32_t x = (uint32_t)xt;  // tiles of one block are consecutive
+        uint64_t lo = 0, hi = nblk;  // off[lo] <= x < off[hi]
+        while (hi - lo > 1) {
+            const uint64_t mid = (lo + hi) / 2;
+            if (off[mid] <= x)
+                lo = mid;
+            else
+                hi = mid;
+        }
+        const uint64_t b = lo;
+        const uint32_t t0 = (x - off[b]) * mt::MA;
+        const uint32_t left = cnt[b] - t0;
+        const uint32_t m = left < (uint32_t)mt::MA ? left : (uint32_t)mt::MA;
+        const uint16_t *lq = list + b * nqp + t0;
+        const uint64_t r0 = b * kBlk;
+        const int r = mt::own_row();
+        const uint4 *row;
+        bool ok;
+        if (r < mt::MA) {
+            ok = (uint32_t)r < m;
+            const uint32_t qi = ok ? lq[r] : 0;
+            row = q + (uint64_t)qi * 32;
+            s_qi[r] = qi;
+            s_pq[r] = ok ? qpop[qi] : 0;
+            s_th[r] = ok ? thrk[qi] : 0;
+        } else {
+            ok = r0 + (r - mt::MA) < n;
+            row = ok ? sorted + (r0 + (r - mt::MA)) * 32 : sorted;
+            s_tp[r - mt::MA] = ok ? tpop[r0 + (r - mt::MA)] : 0;
+        }
+        mt::v4f acc[8][4];
+        mt::overlap_tile(row, !ok, sm, acc);  // its barriers also publish the metadata above
 #pragma unroll
-    for (int a = 0; a < 8; a++)
+        for (int a = 0; a < 8; a++)
 #pragma unroll
-        for (int rr = 0; rr < 4; rr++) {
-            const uint32_t i = (uint32_t)mt::acc_arow(a, rr);
-            if (i >= m) continue;
-            const uint32_t qi = s_qi[i];
-            const uint32_t pq = s_pq[i];
-            const uint32_t wa = weight_a(pq), wb = weight_b(pq);
-            const uint32_t th = s_th[i];
+            for (int rr = 0; rr < 4; rr++) {
+                const uint32_t i = (uint32_t)mt::acc_arow(a, rr);
+                if (i >= m) continue;
+                const uint32_t qi = s_qi[i];
+                const uint32_t pq = s_pq[i];
+                const uint32_t wa = weight_a(pq), wb = weight_b(pq);
+                const uint32_t th = s_th[i];
 #pragma unroll
-            for (int bb = 0; bb < 4; bb++) {
-                const int bi = mt::acc_brow(bb);
-                const uint64_t rw = r0 + bi;
-                if (rw >= n) continue;
-                const uint32_t C = mt::count(acc[a][bb][rr]);
-                const uint32_t K = (pq - C) * wb + (s_tp[bi] - C) * wa;
-                if (K <= th) {
-                    const uint32_t pos = atomicAdd(&ccnt[qi], 1u);
-                    if (pos < kCap) cand[(uint64_t)qi * kCap + pos] = ((u64)K << 32) | perm[rw];
+                for (int bb = 0; bb < 4; bb++) {
+                    const int bi = mt::acc_brow(bb);
+                    const uint64_t rw = r0 + bi;
+                    if (rw >= n) continue;
+                    const uint32_t C = mt::count(acc[a][bb][rr]);
+                    const uint32_t K = (pq - C) * wb + (s_tp[bi] - C) * wa;
+                    if (K <= th) {
+                        const uint32_t pos = atomicAdd(&ccnt[qi], 1u);
+                        if (pos < kCap) cand[(uint64_t)qi * kCap + pos] = ((u64)K << 32) | perm[rw];
+                    }
                 }
             }
-        }
+        __syncthreads();  // the next tile rewrites the metadata
+    }
 }
 
 // After a round: merge each running query's candidates into its top k,
@@ -685,7 +694,8 @@ int knn_tree_blocked(qd_tree_t t, const uint64_t *d_q, uint32_t nq, uint32_t k, 
         const uint64_t n_btiles = (nblk + mt::MB - 1) / mt::MB;
         {
             KernelTimer timer("tree_block_bounds", s);
-            hipLaunchKernelGGL(bound_kernel, dim3((uint32_t)(n_qtiles * n_btiles)), dim3(mt::kThreads), 0, s, q4, nqb,
+            hipLaunchKernelGGL(bound_kernel, dim3((uint32_t)mt::tile_grid(n_qtiles * n_btiles)), dim3(mt::kThreads), 0, s,
+                               q4, nqb,
                                nqp, reinterpret_cast<const uint4 *>(t->d_blk), nblk, qpop, n_qtiles, lbq, lbb);
         }
         // round 2 covers about t2 blocks per query: enough that a block's list
@@ -721,7 +731,8 @@ int knn_tree_blocked(qd_tree_t t, const uint64_t *d_q, uint32_t nq, uint32_t k, 
             if (hipMemsetAsync(ctr, 0, 4, s) != hipSuccess) return done(fail(QD_ERR_DEVICE, "memset"));
             if (h[2] > 0) {
                 KernelTimer timer("tree_block_eval", s);
-                hipLaunchKernelGGL(eval_kernel, dim3((uint32_t)mt::xcd_grid(h[2])), dim3(mt::kThreads), 0, s, q4,
+                hipLaunchKernelGGL(eval_kernel, dim3((uint32_t)mt::tile_grid(mt::xcd_grid(h[2]))), dim3(mt::kThreads), 0,
+                                   s, q4,
                                    reinterpret_cast<const uint4 *>(t->d_sorted), n, nblk, nqp, list, cnt, off,
                                    t->d_pop, t->d_perm, qpop, thr, ccnt, cand);
             }
