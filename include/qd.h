@@ -236,6 +236,22 @@ int qd_retrieve_objects(qd_tree_t t, const uint64_t *d_db, uint64_t n, const uin
                         uint32_t vote_threshold, const qd_search_params *params, uint32_t *d_votes,
                         int32_t *d_winner, uint32_t *d_used, uint32_t *d_nn_idx, void *stream);
 
+/* Retrieval that stops at the vote threshold (Section 3: descriptors are
+ * processed in order until an object reaches the threshold).  Same arguments
+ * and outputs as qd_retrieve_objects (vote_threshold 1..255), but each query
+ * object's descriptors are searched in rounds, in their given order, and an
+ * object stops as soon as its votes so far decide a winner: round r searches
+ * the next 16 * 2^(r-1) descriptors of every undecided object, all objects'
+ * in one batched k-NN call.  d_winner and d_used equal qd_retrieve_objects'
+ * exactly; d_votes counts the votes of the first d_used[g] descriptors of
+ * object g (all of them if it has no winner).  *h_searched (nullable)
+ * receives the number of descriptors searched (at least the sum of d_used,
+ * at most n_qdesc).  Synchronous (waits for the stream between rounds). */
+int qd_retrieve_objects_early(qd_tree_t t, const uint64_t *d_db, uint64_t n, const uint16_t *d_obj_of, uint32_t n_obj,
+                              const uint64_t *d_qdesc, uint64_t n_qdesc, const uint64_t *d_qoff, uint32_t nqo,
+                              uint32_t k, uint32_t vote_threshold, const qd_search_params *params, uint32_t *d_votes,
+                              int32_t *d_winner, uint32_t *d_used, uint64_t *h_searched, void *stream);
+
 /* ---------------------------------------------------------------------------
  * Learned frontier order (an extension: the paper orders the frontier by the
  * bound only).  A multilayer perceptron scores (query, node) pairs; the

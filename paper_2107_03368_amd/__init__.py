@@ -264,6 +264,31 @@ def retrieve_objects(qdesc, qoff, obj_of, n_obj, k, threshold=10, tree=None, db=
     return (votes, winner, used, nn) if return_nn else (votes, winner, used)
 
 
+_sig("qd_retrieve_objects_early", [_P, _P, _U64, _P, _U32, _P, _U64, _P, _U32, _U32, _U32,
+                                   ctypes.POINTER(_SearchParams), _P, _P, _P, ctypes.POINTER(ctypes.c_uint64), _P])
+
+
+def retrieve_objects_early(qdesc, qoff, obj_of, n_obj, k, threshold=10, tree=None, db=None, order=ORDER_BEST_FIRST):
+    """Retrieval that stops each query object at the vote threshold.  Returns
+    (votes over the descriptors used, winner, used, descriptors searched)."""
+    _desc(qdesc, "qdesc")
+    if tree is None:
+        _desc(db, "db")
+    nqo = qoff.shape[0] - 1
+    dev = qdesc.device
+    votes = torch.empty((nqo, n_obj), dtype=torch.int32, device=dev)
+    winner = torch.empty(nqo, dtype=torch.int32, device=dev)
+    used = torch.empty(nqo, dtype=torch.int32, device=dev)
+    searched = ctypes.c_uint64(0)
+    prm = _SearchParams(order, None, 0, 0, None, 0)
+    rc = _lib.qd_retrieve_objects_early(tree.handle if tree is not None else None, _ptr(db),
+                                        0 if db is None else db.shape[0], _ptr(obj_of), n_obj, _ptr(qdesc),
+                                        qdesc.shape[0], _ptr(qoff), nqo, k, threshold, ctypes.byref(prm), _ptr(votes),
+                                        _ptr(winner), _ptr(used), ctypes.byref(searched), _stream())
+    _check(rc, "qd_retrieve_objects_early")
+    return votes, winner, used, searched.value
+
+
 # ---------------------------------------------------------------------------
 # Learned frontier order (MLP)
 # ---------------------------------------------------------------------------

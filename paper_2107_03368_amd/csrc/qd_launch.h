@@ -30,6 +30,6 @@ int brute_launch(const BruteLaunch &L, u64 *part, const uint64_t *d_db, uint64_t
 
 int vote_launch(const uint32_t *nn, uint32_t k, const uint16_t *obj_of, uint64_t n_db, uint32_t n_obj,
                 const uint64_t *qoff, uint32_t nqo, const uint32_t *nqo_dev, uint32_t threshold, uint32_t *votes,
-                int32_t *winner, uint32_t *used, hipStream_t s);
+                int32_t *winner, uint32_t *used, hipStream_t s, const uint64_t *qend = nullptr);
 
 }  // namespace qd

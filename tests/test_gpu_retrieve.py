@@ -114,3 +114,44 @@ def test_autotuner_returns_a_timed_exact_configuration(qd):
         else:
             res = qd.knn_bruteforce(_t(db), _t(q), 10, query_tile=best["query_tile"])
         assert np.array_equal(res[0].cpu().numpy().view(np.uint32)[:4], ref.idx)
+
+
+def _prefix_votes(nn_idx, obj, n_obj, off, used):
+    """Oracle histogram over the first used[g] descriptors of each object."""
+    out = np.zeros((len(off) - 1, n_obj), np.uint32)
+    for g in range(len(off) - 1):
+        rows = nn_idx[int(off[g]):int(off[g]) + int(used[g])].reshape(-1)
+        o = obj[rows[rows != 0xFFFFFFFF]].astype(np.int64)
+        np.add.at(out[g], o[o < n_obj], 1)
+    return out
+
+
+@pytest.mark.parametrize("order", ["brute", "best_first", "blocked"])
+@pytest.mark.parametrize("k,threshold", [(1, 10), (5, 10), (3, 1), (2, 255)])
+def test_early_exit_matches_full_retrieval(qd, order, k, threshold):
+    # query objects of 15-300 descriptors: several rounds (16, 32, 64, ...)
+    db, obj, off, q, qobj = _workload(40, 300, 9, 15, 300, 91)
+    ref_nn = oracle.knn_brute(db, q, k)
+    rv, rw, ru = oracle.votes(ref_nn.idx, obj, 40, off, threshold)
+    tree = None if order == "brute" else qd.tree_build(_t(db))
+    o = qd.ORDER_BLOCKED if order == "blocked" else qd.ORDER_BEST_FIRST
+    votes, winner, used, searched = qd.retrieve_objects_early(_t(q), _t(off), _t(obj), 40, k, threshold, tree=tree,
+                                                              db=_t(db) if tree is None else None, order=o)
+    assert np.array_equal(winner.cpu().numpy(), rw)
+    assert np.array_equal(used.cpu().numpy().view(np.uint32), ru)
+    assert np.array_equal(votes.cpu().numpy().view(np.uint32), _prefix_votes(ref_nn.idx, obj, 40, off, ru))
+    assert int(ru.sum()) <= searched <= len(q)
+
+
+def test_early_exit_searches_a_fraction_at_scale(qd):
+    # 300 objects x 5,000 descriptors, 128 query objects of 200-4,000 descriptors, k = 5,
+    # threshold 10: the decisions equal the full retrieval's with far fewer searches
+    db, obj, off, q, qobj = _workload(300, 5000, 128, 200, 4000, 1002)
+    tree = qd.tree_build(_t(db))
+    full = qd.retrieve_objects(_t(q), _t(off), _t(obj), 300, 5, 10, tree=tree, order=qd.ORDER_BLOCKED)
+    votes, winner, used, searched = qd.retrieve_objects_early(_t(q), _t(off), _t(obj), 300, 5, 10, tree=tree,
+                                                              order=qd.ORDER_BLOCKED)
+    assert np.array_equal(winner.cpu().numpy(), full[1].cpu().numpy())
+    assert np.array_equal(used.cpu().numpy(), full[2].cpu().numpy())
+    print(f"searched {searched} of {len(q)} descriptors")
+    assert searched < 0.1 * len(q)
