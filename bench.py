@@ -30,6 +30,10 @@ WORKLOADS = {
     "small": dict(n=10_000, nq=100, pmin=0.1, pmax=0.5, k=10, seed_db=1000, seed_q=2000),
     # serving: 50M rows seen as 10,000 objects x 5,000 descriptors; query objects of
     # U{50..5000} descriptors of one object, partial and noisy, arriving as a Poisson stream
+    # partial-object retrieval: 300 objects x 5,000 descriptors, 128 query objects of
+    # U{200..4000} descriptors of one object, k = 5 votes per descriptor, threshold 10
+    "objects": dict(n_obj=300, per_obj=5000, n_qo=128, mmin=200, mmax=4000, pmin=0.2, pmax=0.7, k=5, threshold=10,
+                    seed_db=1002, seed_qo=1003, seed_q=1004),
     "stream50m": dict(n=50_000_000, n_obj=10_000, per_obj=5_000, n_qo=48, mmin=50, mmax=5000, pmin=0.1,
                       pmax=0.6, k=10, seed_db=1004, seed_q=2004, seed_qo=5004, seed_arrivals=6004,
                       max_batch=16384, loads=(0.5, 0.8, 0.95)),
@@ -89,6 +93,8 @@ def main():
     dev = torch.device("cuda:0")
     if args.workload == "stream50m":
         return stream_main(args, w, dev)
+    if args.workload == "objects":
+        return objects_main(args, w, dev)
     if args.pmc_run:
         # a plain copy of known size, to scale the HBM byte counters, then one batch
         src = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
@@ -283,6 +289,65 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+
+
+def objects_main(args, w, dev):
+    """Partial-object retrieval: every descriptor's k nearest neighbours vote
+    for their objects; the first object to reach the threshold wins.  Times
+    the whole batch through each path (all query objects in one call) and the
+    retrieval that stops each query object at the threshold."""
+    import torch
+    import synth
+    import paper_2107_03368_amd as qd
+
+    n = w["n_obj"] * w["per_obj"]
+    db = synth.gen_db(n, w["seed_db"])
+    obj = (np.arange(n) // w["per_obj"]).astype(np.uint16)
+    off, rows, qobj = synth.gen_query_objects(w["n_obj"], w["per_obj"], w["n_qo"], w["seed_qo"], w["mmin"], w["mmax"])
+    q, _ = synth.gen_queries(db, len(rows), w["seed_q"], w["pmin"], w["pmax"], src=rows)
+    dbt = torch.from_numpy(db.view(np.int64)).to(dev)
+    qt = torch.from_numpy(q.view(np.int64)).to(dev)
+    offt = torch.from_numpy(off.view(np.int64)).to(dev)
+    objt = torch.from_numpy(obj.view(np.int16)).to(dev)
+    tree = qd.tree_build(dbt)
+    k, thr, n_obj = w["k"], w["threshold"], w["n_obj"]
+    runs = {
+        "brute": lambda: qd.retrieve_objects(qt, offt, objt, n_obj, k, thr, db=dbt),
+        "tree_blocked": lambda: qd.retrieve_objects(qt, offt, objt, n_obj, k, thr, tree=tree, order=qd.ORDER_BLOCKED),
+        "tree_blocked_early_exit": lambda: qd.retrieve_objects_early(qt, offt, objt, n_obj, k, thr, tree=tree,
+                                                                     order=qd.ORDER_BLOCKED),
+        "brute_early_exit": lambda: qd.retrieve_objects_early(qt, offt, objt, n_obj, k, thr, db=dbt),
+    }
+    ref = [x.cpu() for x in runs["brute"]()[1:3]]
+    out = {}
+    for name, fn in runs.items():
+        r = fn()
+        if not all(torch.equal(a.cpu(), b) for a, b in zip(r[1:3], ref)):
+            raise SystemExit(f"{name}: winners differ from the sequential search's")
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            r = fn()
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.steps
+        out[name] = {"ms": dt * 1e3, "query_objects_per_s": w["n_qo"] / dt,
+                     "descriptor_queries_per_s": len(rows) / dt}
+        if name.endswith("early_exit"):
+            out[name]["descriptors_searched"] = r[3]
+        log(f"{name}: {dt * 1e3:.1f} ms per batch of {w['n_qo']} query objects ({len(rows)} descriptors)")
+    winner = ref[0].numpy()
+    res = {
+        "metric": "partial-object retrieval: query objects/s (k = 5 votes per descriptor, threshold 10)",
+        "value": max(v["query_objects_per_s"] for v in out.values()), "unit": "query objects/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "higher_is_better": True, "dtype": "fp4",
+        "data": "synthetic",
+        "config": {"workload": f"objects: {w['n_obj']} objects x {w['per_obj']} descriptors, {w['n_qo']} query "
+                               f"objects ({len(rows)} descriptors), k={k}, threshold={thr}"},
+        "paths": out, "winner_is_source_object": float((winner == qobj).mean()),
+    }
+    print(json.dumps(res), flush=True)
 
 
 def stream_main(args, w, dev):
