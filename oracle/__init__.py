@@ -53,6 +53,7 @@ def _load():
         lib.or_node_bound.restype = I64
         lib.or_tree_knn.argtypes = [P, P, P, P, P, P, P, I64, P, I64, I, P, P, P, P, P, P]
         lib.or_votes.argtypes = [P, I, P, I64, I64, P, I64, I64, P, P, P]
+        lib.or_object_scores.argtypes = [P, I64, P, I64, P, P, I64, P]
         _lib = lib
     return _lib
 
@@ -193,3 +194,18 @@ def votes(nn_idx, obj_of, n_obj, qoff, threshold=10):
     u = np.empty(nqo, np.uint32)
     lib.or_votes(_p(nn_idx), k, _p(obj_of), len(obj_of), n_obj, _p(qoff), nqo, threshold, _p(v), _p(w), _p(u))
     return v, w, u
+
+
+def object_scores(db, obj_of, n_obj, q, qoff):
+    """Summed nearest-neighbour distance of every query object to every
+    database object (nqo x n_obj float64; +inf for objects without rows)."""
+    lib = _load()
+    db = _desc(db)
+    q = _desc(q) if len(q) else np.zeros((0, 64), np.uint64)
+    obj_of = np.ascontiguousarray(obj_of, np.uint16)
+    qoff = np.ascontiguousarray(qoff, np.uint64)
+    nqo = len(qoff) - 1
+    out = np.empty((nqo, n_obj), np.float64)
+    lib.or_object_scores(_p(db), len(db), _p(obj_of), n_obj, _p(q), _p(qoff), nqo, _p(out))
+    return out
+

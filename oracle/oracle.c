@@ -477,3 +477,50 @@ void or_votes(const uint32_t *nn_idx, int k, const uint16_t *obj_of, int64_t n_d
             }
     }
 }
+
+/* ---------------------------------------------------------------------------
+ * Object-level distance score (Section 6.4, the object matching experiment
+ * behind Table 1 and the confusion matrices): the score of query object g
+ * against database object o is the sum, over the query object's descriptors
+ * in their given order, of the distance from the descriptor to its nearest
+ * descriptor of object o.  The distance is Eq. 1 as the double quotient
+ * K / (wA * wB) (not rounded to float); the sum is taken in double, one
+ * descriptor after the other.  A query object with descriptors scores
+ * +infinity against an object with no rows; an empty query object scores 0
+ * against every object; rows whose object id is >= n_obj belong to no object.
+ * scores: nqo x n_obj.
+ * ------------------------------------------------------------------------- */
+void or_object_scores(const uint64_t *db, int64_t n, const uint16_t *obj_of, int64_t n_obj, const uint64_t *q,
+                      const uint64_t *qoff, int64_t nqo, double *scores) {
+    int64_t *rows_of = (int64_t *)calloc((size_t)n_obj, sizeof(int64_t));
+    for (int64_t t = 0; t < n; t++)
+        if (obj_of[t] < n_obj) rows_of[obj_of[t]]++;
+#pragma omp parallel
+    {
+        int64_t *best = (int64_t *)malloc((size_t)n_obj * sizeof(int64_t));
+#pragma omp for schedule(dynamic, 1)
+        for (int64_t g = 0; g < nqo; g++) {
+            double *sg = scores + g * n_obj;
+            for (int64_t o = 0; o < n_obj; o++) sg[o] = 0.0;
+            for (uint64_t d = qoff[g]; d < qoff[g + 1]; d++) {
+                const uint64_t *qq = q + d * OR_WORDS;
+                const int64_t P = popcount_desc(qq);
+                for (int64_t o = 0; o < n_obj; o++) best[o] = INT64_MAX;
+                for (int64_t t = 0; t < n; t++) {
+                    const int64_t o = obj_of[t];
+                    if (o >= n_obj) continue;
+                    int64_t A, B;
+                    wh_counts(qq, db + t * OR_WORDS, &A, &B);
+                    const int64_t K = or_wh_key(A, B, P);
+                    if (K < best[o]) best[o] = K;
+                }
+                /* the minimum over no rows is +infinity */
+                for (int64_t o = 0; o < n_obj; o++)
+                    sg[o] += rows_of[o] ? (double)best[o] / ((double)w_a(P) * (double)w_b(P)) : __builtin_inf();
+            }
+        }
+        free(best);
+    }
+    free(rows_of);
+}
+

@@ -21,4 +21,6 @@ int or_tree_knn(const uint64_t *db, const int32_t *child, const int64_t *begin, 
 void or_votes(const uint32_t *nn_idx, int k, const uint16_t *obj_of, int64_t n_db, int64_t n_obj,
               const uint64_t *qoff, int64_t nqo, int64_t threshold, uint32_t *votes, int32_t *winner,
               uint32_t *used);
+void or_object_scores(const uint64_t *db, int64_t n, const uint16_t *obj_of, int64_t n_obj, const uint64_t *q,
+                      const uint64_t *qoff, int64_t nqo, double *scores);
 #endif
