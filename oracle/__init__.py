@@ -54,6 +54,7 @@ def _load():
         lib.or_tree_knn.argtypes = [P, P, P, P, P, P, P, I64, P, I64, I, P, P, P, P, P, P]
         lib.or_votes.argtypes = [P, I, P, I64, I64, P, I64, I64, P, P, P]
         lib.or_object_scores.argtypes = [P, I64, P, I64, P, P, I64, P]
+        lib.or_score_rows.argtypes = [P, I64, I64, I, P]
         _lib = lib
     return _lib
 
@@ -208,4 +209,15 @@ def object_scores(db, obj_of, n_obj, q, qoff):
     out = np.empty((nqo, n_obj), np.float64)
     lib.or_object_scores(_p(db), len(db), _p(obj_of), n_obj, _p(q), _p(qoff), nqo, _p(out))
     return out
+
+
+def score_rows(scores, normalize=True):
+    """Best object per row (lowest score, ties to the lower id, -1 if none is
+    finite) and, with normalize, the rows rescaled to [0, 1] (a copy)."""
+    lib = _load()
+    s = np.array(scores, dtype=np.float64, order="C", copy=True)
+    nqo, n_obj = s.shape
+    best = np.empty(nqo, np.int32)
+    lib.or_score_rows(_p(s), nqo, n_obj, 1 if normalize else 0, _p(best))
+    return best, s
 

@@ -492,35 +492,74 @@ void or_votes(const uint32_t *nn_idx, int k, const uint16_t *obj_of, int64_t n_d
  * ------------------------------------------------------------------------- */
 void or_object_scores(const uint64_t *db, int64_t n, const uint16_t *obj_of, int64_t n_obj, const uint64_t *q,
                       const uint64_t *qoff, int64_t nqo, double *scores) {
+    enum { CHUNK = 64 }; /* descriptors whose minima are found together (in parallel) */
     int64_t *rows_of = (int64_t *)calloc((size_t)n_obj, sizeof(int64_t));
+    int64_t *best = (int64_t *)malloc((size_t)CHUNK * (size_t)n_obj * sizeof(int64_t));
     for (int64_t t = 0; t < n; t++)
         if (obj_of[t] < n_obj) rows_of[obj_of[t]]++;
-#pragma omp parallel
-    {
-        int64_t *best = (int64_t *)malloc((size_t)n_obj * sizeof(int64_t));
-#pragma omp for schedule(dynamic, 1)
-        for (int64_t g = 0; g < nqo; g++) {
-            double *sg = scores + g * n_obj;
-            for (int64_t o = 0; o < n_obj; o++) sg[o] = 0.0;
-            for (uint64_t d = qoff[g]; d < qoff[g + 1]; d++) {
-                const uint64_t *qq = q + d * OR_WORDS;
+    for (int64_t g = 0; g < nqo; g++) {
+        double *sg = scores + g * n_obj;
+        for (int64_t o = 0; o < n_obj; o++) sg[o] = 0.0;
+        for (uint64_t c0 = qoff[g]; c0 < qoff[g + 1]; c0 += CHUNK) {
+            const int64_t m = (int64_t)(qoff[g + 1] - c0 < CHUNK ? qoff[g + 1] - c0 : CHUNK);
+            /* nearest row of every object, for each descriptor of the chunk */
+#pragma omp parallel for schedule(dynamic, 1)
+            for (int64_t j = 0; j < m; j++) {
+                const uint64_t *qq = q + (c0 + (uint64_t)j) * OR_WORDS;
                 const int64_t P = popcount_desc(qq);
-                for (int64_t o = 0; o < n_obj; o++) best[o] = INT64_MAX;
+                int64_t *bj = best + j * n_obj;
+                for (int64_t o = 0; o < n_obj; o++) bj[o] = INT64_MAX;
                 for (int64_t t = 0; t < n; t++) {
                     const int64_t o = obj_of[t];
                     if (o >= n_obj) continue;
                     int64_t A, B;
                     wh_counts(qq, db + t * OR_WORDS, &A, &B);
                     const int64_t K = or_wh_key(A, B, P);
-                    if (K < best[o]) best[o] = K;
+                    if (K < bj[o]) bj[o] = K;
                 }
-                /* the minimum over no rows is +infinity */
+            }
+            /* the terms, added in descriptor order; the minimum over no rows is +infinity */
+            for (int64_t j = 0; j < m; j++) {
+                const int64_t P = popcount_desc(q + (c0 + (uint64_t)j) * OR_WORDS);
                 for (int64_t o = 0; o < n_obj; o++)
-                    sg[o] += rows_of[o] ? (double)best[o] / ((double)w_a(P) * (double)w_b(P)) : __builtin_inf();
+                    sg[o] += rows_of[o] ? (double)best[j * n_obj + o] / ((double)w_a(P) * (double)w_b(P))
+                                        : __builtin_inf();
             }
         }
-        free(best);
     }
+    free(best);
     free(rows_of);
 }
 
+/* ---------------------------------------------------------------------------
+ * Ranking and confusion-matrix rows (Section 6.4, Table 1 and the confusion
+ * matrices).  For each query object g (one row of nqo x n_obj scores):
+ * best[g] = the object of lowest score, ties to the lower id, -1 when no
+ * score is finite (Table 1 counts the rows whose best object is the source).
+ * With normalize set, the row is rescaled in place to [0, 1] as
+ * (s - min) / (max - min) over its finite scores; a row whose finite scores
+ * are all equal becomes 0 there; non-finite scores become 1.
+ * ------------------------------------------------------------------------- */
+void or_score_rows(double *scores, int64_t nqo, int64_t n_obj, int normalize, int32_t *best) {
+    for (int64_t g = 0; g < nqo; g++) {
+        double *s = scores + g * n_obj;
+        int64_t arg = -1;
+        double mn = __builtin_inf(), mx = -__builtin_inf();
+        for (int64_t o = 0; o < n_obj; o++) {
+            if (!__builtin_isfinite(s[o])) continue;
+            if (s[o] < mn) {
+                mn = s[o];
+                arg = o;
+            }
+            if (s[o] > mx) mx = s[o];
+        }
+        best[g] = (int32_t)arg;
+        if (!normalize) continue;
+        for (int64_t o = 0; o < n_obj; o++) {
+            if (!__builtin_isfinite(s[o]))
+                s[o] = 1.0;
+            else
+                s[o] = mx > mn ? (s[o] - mn) / (mx - mn) : 0.0;
+        }
+    }
+}

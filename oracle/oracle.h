@@ -23,4 +23,5 @@ void or_votes(const uint32_t *nn_idx, int k, const uint16_t *obj_of, int64_t n_d
               uint32_t *used);
 void or_object_scores(const uint64_t *db, int64_t n, const uint16_t *obj_of, int64_t n_obj, const uint64_t *q,
                       const uint64_t *qoff, int64_t nqo, double *scores);
+void or_score_rows(double *scores, int64_t nqo, int64_t n_obj, int normalize, int32_t *best);
 #endif

@@ -101,3 +101,30 @@ def test_row_permutation_invariance():
     s = oracle.object_scores(db, obj, n_obj, q, off)
     p = synth.permutation(len(db), 77)
     assert np.array_equal(oracle.object_scores(db[p], obj[p], n_obj, q, off), s)
+
+
+def test_score_rows_hand_worked():
+    s = np.array([[3.0, 1.0, np.inf, 2.0],
+                  [2.0, 1.0, 1.0, 4.0],        # tie: the lower id wins
+                  [np.inf, np.inf, np.inf, np.inf],
+                  [5.0, 5.0, np.inf, 5.0]])
+    best, norm = oracle.score_rows(s)
+    assert best.tolist() == [1, 1, -1, 0]
+    assert norm.tolist() == [[1.0, 0.0, 1.0, 0.5],
+                             [1 / 3, 0.0, 0.0, 1.0],
+                             [1.0, 1.0, 1.0, 1.0],
+                             [0.0, 0.0, 1.0, 0.0]]
+    best2, same = oracle.score_rows(s, normalize=False)
+    assert best2.tolist() == best.tolist() and np.array_equal(same, s)
+
+
+def test_score_rows_properties():
+    db, obj, n_obj, q, off, qobj = _setup()
+    s = oracle.object_scores(db, obj, n_obj, q, off)
+    best, norm = oracle.score_rows(s)
+    assert np.array_equal(best, s.argmin(1))            # first minimum = lowest id
+    assert (norm.min(1) == 0).all() and (norm.max(1) == 1).all()
+    for g in range(len(s)):                             # the order of the objects is kept
+        assert np.array_equal(np.argsort(norm[g], kind="stable"), np.argsort(s[g], kind="stable"))
+    # a scale by a power of two changes no bit of the normalised rows
+    assert np.array_equal(oracle.score_rows(4 * s)[1], norm)
