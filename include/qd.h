@@ -252,6 +252,26 @@ int qd_retrieve_objects_early(qd_tree_t t, const uint64_t *d_db, uint64_t n, con
                               uint32_t k, uint32_t vote_threshold, const qd_search_params *params, uint32_t *d_votes,
                               int32_t *d_winner, uint32_t *d_used, uint64_t *h_searched, void *stream);
 
+/* Object-level distance scores (Section 6.4: the object matching behind
+ * Table 1 and the confusion matrices).  d_scores[g * n_obj + o] (float64,
+ * device, nqo x n_obj, written whole) = the sum, over query object g's
+ * descriptors d_qdesc[d_qoff[g] .. d_qoff[g+1]) in that order, of
+ * K / (wA * wB) for the row of object o nearest to the descriptor (Eq. 1;
+ * K, wA, wB as defined at the top of this file; the quotient and the running
+ * sum in float64, one descriptor after the other).  An object with no rows adds
+ * +inf per descriptor; an empty query object scores 0 against every object.
+ *   d_db: n x 64 words (device, 16-byte aligned; may be null when n = 0),
+ *   n < 2^32.  d_obj_of: n object ids (device uint16); rows with an id >=
+ *   n_obj belong to no object.  1 <= n_obj <= 65536.  d_qoff: nqo + 1
+ *   device offsets with d_qoff[0] = 0 <= ... <= d_qoff[nqo] = n_qdesc.
+ *   nqo = 0 is a no-op.
+ * Stream-ordered; allocates and frees its scratch on the stream (row order
+ * by object, and at most 1 GiB of per-descriptor minima per batch of query
+ * descriptors). */
+int qd_object_scores(const uint64_t *d_db, uint64_t n, const uint16_t *d_obj_of, uint32_t n_obj,
+                     const uint64_t *d_qdesc, uint64_t n_qdesc, const uint64_t *d_qoff, uint32_t nqo,
+                     double *d_scores, void *stream);
+
 /* ---------------------------------------------------------------------------
  * Learned frontier order (an extension: the paper orders the frontier by the
  * bound only).  A multilayer perceptron scores (query, node) pairs; the

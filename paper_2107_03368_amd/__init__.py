@@ -289,6 +289,22 @@ def retrieve_objects_early(qdesc, qoff, obj_of, n_obj, k, threshold=10, tree=Non
     return votes, winner, used, searched.value
 
 
+_sig("qd_object_scores", [_P, _U64, _P, _U32, _P, _U64, _P, _U32, _P, _P])
+
+
+def object_scores(db, obj_of, n_obj, qdesc, qoff):
+    """Summed nearest-neighbour distance of every query object (CSR qoff into
+    qdesc) to every database object: cuda float64 (nqo, n_obj)."""
+    _desc(db, "db")
+    _desc(qdesc, "qdesc")
+    nqo = qoff.shape[0] - 1
+    scores = torch.empty((nqo, n_obj), dtype=torch.float64, device=qdesc.device)
+    rc = _lib.qd_object_scores(_ptr(db), db.shape[0], _ptr(obj_of), n_obj, _ptr(qdesc), qdesc.shape[0], _ptr(qoff),
+                               nqo, _ptr(scores), _stream())
+    _check(rc, "qd_object_scores")
+    return scores
+
+
 # ---------------------------------------------------------------------------
 # Learned frontier order (MLP)
 # ---------------------------------------------------------------------------

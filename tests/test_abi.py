@@ -59,3 +59,19 @@ def test_argument_errors_are_reported_before_any_device_work():
     assert f(None, 100, a, 5, 10, a, a, a, a, None) == -1      # null database
     assert f(P(0x10008), 100, a, 5, 10, a, a, a, a, None) == -1  # misaligned rows
     assert f(a, 100, a, 0, 10, a, a, a, a, None) == 0          # nq = 0 is a no-op
+
+
+def test_object_score_argument_errors_without_device_work():
+    lib = ctypes.CDLL(LIB)
+    lib.qd_last_error.restype = ctypes.c_char_p
+    f = lib.qd_object_scores
+    P, U64, U32 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32
+    f.argtypes = [P, U64, P, U32, P, U64, P, U32, P, P]
+    a = P(0x10000)
+    assert f(a, 100, a, 0, a, 10, a, 2, a, None) == -1           # n_obj = 0
+    assert b"n_obj" in lib.qd_last_error()
+    assert f(a, 100, a, 65537, a, 10, a, 2, a, None) == -1       # ids are uint16
+    assert f(a, 100, a, 5, a, 10, a, 0, a, None) == 0            # nqo = 0 is a no-op
+    assert f(None, 100, a, 5, a, 10, a, 2, a, None) == -1        # null database with rows
+    assert f(a, 100, a, 5, a, 10, None, 2, a, None) == -1        # null offsets
+    assert f(a, 100, a, 5, P(0x10008), 10, a, 2, a, None) == -1  # misaligned descriptors
