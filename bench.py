@@ -337,6 +337,34 @@ def objects_main(args, w, dev):
         if name.endswith("early_exit"):
             out[name]["descriptors_searched"] = r[3]
         log(f"{name}: {dt * 1e3:.1f} ms per batch of {w['n_qo']} query objects ({len(rows)} descriptors)")
+    # object-level scores (summed nearest-neighbour distance per object pair)
+    # of every query object against every object, and the best-ranked object
+    def scores_fn():
+        sc = qd.object_scores(dbt, objt, n_obj, qt, offt)
+        return sc, qd.score_rows(sc)
+    for _ in range(args.warmup):
+        scores_fn()
+    torch.cuda.synchronize()
+    qd.profile_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        sc, best = scores_fn()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    scan_ms, scan_n = qd.profile_read("object_scan")
+    qd.profile_enable(False)
+    scan_ms /= max(scan_n, 1)
+    tflops = len(rows) * n * 2 * 4096 / (scan_n / args.steps) / (scan_ms * 1e-3) / 1e12
+    obj_scores = {
+        "ms": dt * 1e3, "query_objects_per_s": w["n_qo"] / dt,
+        "nn_matching_accuracy": float((best.cpu().numpy() == qobj).mean()),
+        "object_scan_ms_per_launch": scan_ms, "object_scan_launches": scan_n // args.steps,
+        "roofline_object_scan": {"bound": "mfma", "achieved": tflops, "peak": FP4_PEAK_TFLOPS, "unit": "TFLOP/s",
+                                 "frac": tflops / FP4_PEAK_TFLOPS, "traffic": None},
+    }
+    log(f"object_scores: {dt * 1e3:.1f} ms for {w['n_qo']} query objects x {n_obj} objects; "
+        f"object_scan {scan_ms:.1f} ms/launch = {tflops:.0f} TFLOP/s; "
+        f"accuracy {obj_scores['nn_matching_accuracy']:.3f}")
     winner = ref[0].numpy()
     res = {
         "metric": "partial-object retrieval: query objects/s (k = 5 votes per descriptor, threshold 10)",
@@ -346,6 +374,7 @@ def objects_main(args, w, dev):
         "config": {"workload": f"objects: {w['n_obj']} objects x {w['per_obj']} descriptors, {w['n_qo']} query "
                                f"objects ({len(rows)} descriptors), k={k}, threshold={thr}"},
         "paths": out, "winner_is_source_object": float((winner == qobj).mean()),
+        "object_scores": obj_scores,
     }
     print(json.dumps(res), flush=True)
 

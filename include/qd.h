@@ -272,6 +272,17 @@ int qd_object_scores(const uint64_t *d_db, uint64_t n, const uint16_t *d_obj_of,
                      const uint64_t *d_qdesc, uint64_t n_qdesc, const uint64_t *d_qoff, uint32_t nqo,
                      double *d_scores, void *stream);
 
+/* Ranking and confusion-matrix rows (Section 6.4: Table 1 counts the query
+ * objects whose best-ranked object is their source; the confusion matrices
+ * show each row of scores rescaled to [0, 1]).  d_scores: nqo x n_obj
+ * float64 (device, as written by qd_object_scores).  d_best[g] (device
+ * int32, nqo) = the object of lowest score in row g, ties to the lower id,
+ * -1 when no score of the row is finite.  With normalize != 0 each row is
+ * rewritten in place as (s - min) / (max - min) over its finite scores (0
+ * where they are all equal); non-finite scores become 1.  nqo = 0 is a
+ * no-op; n_obj >= 1.  Stream-ordered; allocates nothing. */
+int qd_score_rows(double *d_scores, uint32_t nqo, uint32_t n_obj, int normalize, int32_t *d_best, void *stream);
+
 /* ---------------------------------------------------------------------------
  * Learned frontier order (an extension: the paper orders the frontier by the
  * bound only).  A multilayer perceptron scores (query, node) pairs; the

@@ -305,6 +305,21 @@ def object_scores(db, obj_of, n_obj, qdesc, qoff):
     return scores
 
 
+_sig("qd_score_rows", [_P, _U32, _U32, ctypes.c_int, _P, _P])
+
+
+def score_rows(scores, normalize=True):
+    """Best object per query object (int32, -1 if no finite score) and, with
+    normalize, the rows of ``scores`` rescaled to [0, 1] in place."""
+    if not (scores.is_cuda and scores.dtype == torch.float64 and scores.dim() == 2 and scores.is_contiguous()):
+        raise ValueError("scores must be a contiguous cuda float64 tensor of shape (nqo, n_obj)")
+    best = torch.empty(scores.shape[0], dtype=torch.int32, device=scores.device)
+    rc = _lib.qd_score_rows(_ptr(scores), scores.shape[0], scores.shape[1], 1 if normalize else 0, _ptr(best),
+                            _stream())
+    _check(rc, "qd_score_rows")
+    return best
+
+
 # ---------------------------------------------------------------------------
 # Learned frontier order (MLP)
 # ---------------------------------------------------------------------------

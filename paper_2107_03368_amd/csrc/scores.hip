@@ -14,6 +14,8 @@
 // gives every (query object, object) pair one thread, which adds the terms
 // minK / (wA wB) in float64, descriptor after descriptor.  Query descriptors
 // are taken in batches that bound minK; each batch continues the running sums.
+// qd_score_rows ranks the objects of each query object and rescales its row
+// to [0, 1], the confusion-matrix row.
 #include "mfma_tile.h"
 #include "qd_device.h"
 #include "qd_internal.h"
@@ -227,6 +229,55 @@ __global__ __launch_bounds__(kBlock) void score_sum_kernel(const uint32_t *__res
     }
 }
 
+// One block per row of scores: the lowest finite score (ties to the lower
+// object id) and the highest, by a block reduction; then, with normalize, the
+// row rescaled in place.
+__global__ __launch_bounds__(kBlock) void score_rows_kernel(double *__restrict__ scores, uint32_t nqo, uint32_t n_obj,
+                                                            int normalize, int32_t *__restrict__ best) {
+    __shared__ double s_mn[kBlock], s_mx[kBlock];
+    __shared__ int32_t s_arg[kBlock];
+    const uint32_t tid = threadIdx.x;
+    for (uint32_t g = blockIdx.x; g < nqo; g += gridDim.x) {
+        double *row = scores + (uint64_t)g * n_obj;
+        double mn = __builtin_inf(), mx = -__builtin_inf();
+        int32_t arg = -1;
+        for (uint32_t o = tid; o < n_obj; o += kBlock) {  // increasing o: a tie keeps the first
+            const double v = row[o];
+            if (!__builtin_isfinite(v)) continue;
+            if (v < mn) {
+                mn = v;
+                arg = (int32_t)o;
+            }
+            mx = v > mx ? v : mx;
+        }
+        s_mn[tid] = mn;
+        s_mx[tid] = mx;
+        s_arg[tid] = arg;
+        __syncthreads();
+        for (uint32_t h = kBlock / 2; h > 0; h >>= 1) {
+            if (tid < h) {
+                const double m2 = s_mn[tid + h];
+                const int32_t a2 = s_arg[tid + h];
+                if (a2 >= 0 && (s_arg[tid] < 0 || m2 < s_mn[tid] || (m2 == s_mn[tid] && a2 < s_arg[tid]))) {
+                    s_mn[tid] = m2;
+                    s_arg[tid] = a2;
+                }
+                s_mx[tid] = s_mx[tid + h] > s_mx[tid] ? s_mx[tid + h] : s_mx[tid];
+            }
+            __syncthreads();
+        }
+        const double lo = s_mn[0], hi = s_mx[0];
+        if (tid == 0) best[g] = s_arg[0];
+        if (normalize) {
+            for (uint32_t o = tid; o < n_obj; o += kBlock) {
+                const double v = row[o];
+                row[o] = !__builtin_isfinite(v) ? 1.0 : hi > lo ? (v - lo) / (hi - lo) : 0.0;
+            }
+        }
+        __syncthreads();  // the next row reuses the reduction arrays
+    }
+}
+
 uint32_t blocks_for(uint64_t n, uint64_t cap) {
     const uint64_t b = (n + kBlock - 1) / kBlock;
     return (uint32_t)(b < 1 ? 1 : b > cap ? cap : b);
@@ -306,9 +357,9 @@ extern "C" int qd_object_scores(const uint64_t *d_db, uint64_t n, const uint16_t
         int rc = popcount_rows_launch(qb, nb, qpop, s);
         if (rc != QD_OK) return done(rc);
         if (n) {
-            KernelTimer timer("object_scan", s);
             const uint64_t m = (uint64_t)nb * n_obj;
             hipLaunchKernelGGL(fill_u32_kernel, dim3(blocks_for(m, cap)), dim3(kBlock), 0, s, minK, m, kNoKey);
+            KernelTimer timer("object_scan", s);
             const uint32_t n_qtiles = (nb + MQ - 1) / MQ;
             const uint64_t grid = mt::tile_grid((uint64_t)n_qtiles * row_tiles_max);
             hipLaunchKernelGGL(objscan_kernel, dim3((uint32_t)grid), dim3(mt::kThreads), 0, s,
@@ -326,3 +377,20 @@ extern "C" int qd_object_scores(const uint64_t *d_db, uint64_t n, const uint16_t
     }
     return done(QD_OK);
 }
+
+extern "C" int qd_score_rows(double *d_scores, uint32_t nqo, uint32_t n_obj, int normalize, int32_t *d_best,
+                             void *stream) {
+    using namespace qd;
+    clear_error();
+    if (nqo == 0) return QD_OK;
+    if (n_obj < 1) return fail(QD_ERR_INVALID, "n_obj=0");
+    if (!d_scores || !d_best) return fail(QD_ERR_INVALID, "null pointer");
+    hipStream_t s = (hipStream_t)stream;
+    const uint32_t cap = (uint32_t)device_cus() * 16;
+    KernelTimer timer("score_rows", s);
+    hipLaunchKernelGGL(score_rows_kernel, dim3(nqo < cap ? nqo : cap), dim3(kBlock), 0, s, d_scores, nqo, n_obj,
+                       normalize ? 1 : 0, d_best);
+    QD_HIP_CHECK(hipGetLastError());
+    return QD_OK;
+}
+

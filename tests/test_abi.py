@@ -75,3 +75,15 @@ def test_object_score_argument_errors_without_device_work():
     assert f(None, 100, a, 5, a, 10, a, 2, a, None) == -1        # null database with rows
     assert f(a, 100, a, 5, a, 10, None, 2, a, None) == -1        # null offsets
     assert f(a, 100, a, 5, P(0x10008), 10, a, 2, a, None) == -1  # misaligned descriptors
+
+
+def test_score_rows_argument_errors_without_device_work():
+    lib = ctypes.CDLL(LIB)
+    f = lib.qd_score_rows
+    P, U32 = ctypes.c_void_p, ctypes.c_uint32
+    f.argtypes = [P, U32, U32, ctypes.c_int, P, P]
+    a = P(0x10000)
+    assert f(a, 0, 5, 1, a, None) == 0       # nqo = 0 is a no-op
+    assert f(a, 3, 0, 1, a, None) == -1      # no objects
+    assert f(None, 3, 5, 1, a, None) == -1   # null scores
+    assert f(a, 3, 5, 1, None, None) == -1   # null best

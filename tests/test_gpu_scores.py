@@ -148,3 +148,43 @@ def test_retrieval_workload_sampled(qd):
     soff = np.concatenate([[0], np.cumsum(sizes[pick])]).astype(np.uint64)
     ref = oracle.object_scores(db, obj, n_obj, sub, soff)
     assert np.array_equal(got[pick], ref)
+
+
+def _rows_gpu(qd, s, normalize=True):
+    t = _t(np.ascontiguousarray(s, np.float64))
+    best = qd.score_rows(t, normalize)
+    return best.cpu().numpy(), t.cpu().numpy()
+
+
+@pytest.mark.parametrize("n_obj", [1, 7, 300, 1000, 65536])
+def test_score_rows_match_oracle(qd, n_obj):
+    # integer-valued scores (many ties), +inf entries, a constant row, an all-inf row
+    vals = synth.uniform_f32(9 * n_obj, 3141 + n_obj, 0.0, 20.0).astype(np.int64).astype(np.float64)
+    s = vals.reshape(9, n_obj)
+    s[1, ::3] = np.inf
+    s[2] = 4.0
+    s[3] = np.inf
+    s[4, -1] = 0.5
+    for normalize in (True, False):
+        best, norm = _rows_gpu(qd, s, normalize)
+        rbest, rnorm = oracle.score_rows(s, normalize)
+        assert np.array_equal(best, rbest)
+        assert np.array_equal(norm, rnorm)
+
+
+def test_confusion_rows_of_computed_scores(qd):
+    sizes = [700, 256, 257, 1, 0, 513, 90, 300, 0, 1024, 45, 600, 255, 380]
+    db, obj = _objects(sizes, 3101, extra_none=77)
+    q, off = _query_objects(db, obj, len(sizes), [120, 0, 1, 200, 37, 0, 150, 3, 100], 3102)
+    s = qd.object_scores(_t(db), _t(obj, np.int16), len(sizes), _t(q), _t(off, np.int64))
+    best = qd.score_rows(s)
+    rbest, rnorm = oracle.score_rows(oracle.object_scores(db, obj, len(sizes), q, off))
+    assert np.array_equal(best.cpu().numpy(), rbest)
+    assert np.array_equal(s.cpu().numpy(), rnorm)
+
+
+def test_score_rows_argument_errors(qd):
+    import torch
+    with pytest.raises(ValueError):
+        qd.score_rows(torch.zeros((2, 3), dtype=torch.float32, device="cuda:0"))
+    assert qd.score_rows(torch.zeros((0, 3), dtype=torch.float64, device="cuda:0")).shape == (0,)
