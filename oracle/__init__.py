@@ -51,7 +51,9 @@ def _load():
         lib.or_tree_build.restype = I64
         lib.or_node_bound.argtypes = [P, P, P]
         lib.or_node_bound.restype = I64
-        lib.or_tree_knn.argtypes = [P, P, P, P, P, P, P, I64, P, I64, I, P, P, P, P, P, P]
+        lib.or_node_bound_pop.argtypes = [P, P, P, I64, I64]
+        lib.or_node_bound_pop.restype = I64
+        lib.or_tree_knn.argtypes = [P, P, P, P, P, P, P, P, P, I64, P, I64, I, P, P, P, P, P, P]
         lib.or_votes.argtypes = [P, I, P, I64, I64, P, I64, I64, P, P, P]
         lib.or_object_scores.argtypes = [P, I64, P, I64, P, P, I64, P]
         lib.or_score_rows.argtypes = [P, I64, I64, I, P]
@@ -154,14 +156,29 @@ def tree_build(db, max_leaf=32):
                 and_img[:nn].copy(), perm)
 
 
-def node_bound(q, or_img, and_img=None):
+def node_bound(q, or_img, and_img=None, pop_range=None):
+    """Lower bound on the key of every row under a node; pop_range = (pmin,
+    pmax) of the node's rows adds the popcount-range terms."""
     lib = _load()
-    return lib.or_node_bound(_p(_desc(q)), _p(_desc(or_img)), _p(None if and_img is None else _desc(and_img)))
+    a = None if and_img is None else _desc(and_img)
+    if pop_range is not None:
+        return lib.or_node_bound_pop(_p(_desc(q)), _p(_desc(or_img)), _p(a), int(pop_range[0]), int(pop_range[1]))
+    return lib.or_node_bound(_p(_desc(q)), _p(_desc(or_img)), _p(a))
 
 
-def tree_knn(db, tree, q, k, use_and=False, score=None):
+def node_pop_range(db, tree):
+    """(pmin, pmax) per node: the smallest and largest popcount of its rows."""
+    db = _desc(db)
+    pop = np.unpackbits(db.view(np.uint8), axis=1).sum(1).astype(np.int64)[tree.perm]
+    pmin = np.array([pop[b:b + c].min() for b, c in zip(tree.begin, tree.count)], np.int64)
+    pmax = np.array([pop[b:b + c].max() for b, c in zip(tree.begin, tree.count)], np.int64)
+    return pmin, pmax
+
+
+def tree_knn(db, tree, q, k, use_and=False, score=None, use_pop=False):
     """Best-first k-NN over ``tree``.  ``score`` (nq, n_nodes) int64 replaces
-    the bound as the frontier order (results must not change)."""
+    the bound as the frontier order (results must not change); ``use_pop``
+    tightens the bound with each node's popcount range."""
     lib = _load()
     db = _desc(db)
     q = _desc(q)
@@ -171,12 +188,13 @@ def tree_knn(db, tree, q, k, use_and=False, score=None):
     count = np.ascontiguousarray(tree.count, np.int64)
     or_img = np.ascontiguousarray(tree.or_img, np.uint64)
     and_img = np.ascontiguousarray(tree.and_img, np.uint64) if use_and else None
+    pmin, pmax = node_pop_range(db, tree) if use_pop else (None, None)
     perm = np.ascontiguousarray(tree.perm, np.uint32)
     sc = None if score is None else np.ascontiguousarray(score, np.int64)
     out = Knn(np.empty((nq, k), np.uint32), np.empty((nq, k), np.int32), np.empty((nq, k), np.int32),
               np.empty((nq, k), np.float32), np.empty((nq, 3), np.int64))
-    rc = lib.or_tree_knn(_p(db), _p(child), _p(begin), _p(count), _p(or_img), _p(and_img), _p(perm),
-                         tree.n_nodes, _p(q), nq, k, _p(sc), _p(out.idx), _p(out.missed), _p(out.extra),
+    rc = lib.or_tree_knn(_p(db), _p(child), _p(begin), _p(count), _p(or_img), _p(and_img), _p(pmin), _p(pmax),
+                         _p(perm), tree.n_nodes, _p(q), nq, k, _p(sc), _p(out.idx), _p(out.missed), _p(out.extra),
                          _p(out.dist), _p(out.stats))
     assert rc == 0
     return out

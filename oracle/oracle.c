@@ -309,6 +309,26 @@ int64_t or_node_bound(const uint64_t *q, const uint64_t *or_img, const uint64_t 
     return a * w_b(P) + b * w_a(P);
 }
 
+/* The same bound tightened by the popcount range [pmin, pmax] of the node's
+ * rows.  A row t under the node shares at most min(ov, |t|) bits with q,
+ * where ov = popcount(q AND OR): so A >= |q| - min(ov, pmax), and
+ * B = |t| - C >= pmin - ov.  Together with the product-image term, B is at
+ * least the larger of the two (and of 0). */
+int64_t or_node_bound_pop(const uint64_t *q, const uint64_t *or_img, const uint64_t *and_img, int64_t pmin,
+                          int64_t pmax) {
+    int64_t P = popcount_desc(q);
+    int64_t ov = 0, b_and = 0;
+    for (int w = 0; w < OR_WORDS; w++) {
+        ov += __builtin_popcountll(q[w] & or_img[w]);
+        if (and_img) b_and += __builtin_popcountll(~q[w] & and_img[w]);
+    }
+    int64_t a = P - (ov < pmax ? ov : pmax);
+    int64_t b = pmin - ov;
+    if (b < b_and) b = b_and;
+    if (b < 0) b = 0;
+    return a * w_b(P) + b * w_a(P);
+}
+
 typedef struct {
     int64_t key;  /* priority (bound, or caller-given score) */
     int64_t node;
@@ -371,14 +391,22 @@ static void results_insert(or_cand *R, int64_t *nr, int k, or_cand c) {
  * early stop.  score != NULL: frontier ordered by score[node] (ascending),
  * every popped node re-checked against the current k-th key and skipped if it
  * cannot improve the results; the loop runs until the frontier is empty. */
+static int64_t bound_of(const uint64_t *qj, const uint64_t *or_img, const uint64_t *and_img, const int64_t *pmin,
+                        const int64_t *pmax, int64_t nd) {
+    const uint64_t *a = and_img ? and_img + nd * OR_WORDS : NULL;
+    if (pmin) return or_node_bound_pop(qj, or_img + nd * OR_WORDS, a, pmin[nd], pmax[nd]);
+    return or_node_bound(qj, or_img + nd * OR_WORDS, a);
+}
+
 static void tree_query(const uint64_t *db, const int32_t *child, const int64_t *begin, const int64_t *count,
-                       const uint64_t *or_img, const uint64_t *and_img, const uint32_t *perm, const uint64_t *qj,
-                       int k, const int64_t *score, or_cand *R, int64_t *nr_out, int64_t stats[3]) {
+                       const uint64_t *or_img, const uint64_t *and_img, const int64_t *pmin, const int64_t *pmax,
+                       const uint32_t *perm, const uint64_t *qj, int k, const int64_t *score, or_cand *R,
+                       int64_t *nr_out, int64_t stats[3]) {
     int64_t P = popcount_desc(qj);
     int64_t nr = 0;
     or_heap H = {0, 0, 0};
     int64_t visited = 0, bounds = 0, dists = 0;
-    int64_t b0 = or_node_bound(qj, or_img, and_img ? and_img : NULL);
+    int64_t b0 = bound_of(qj, or_img, and_img, pmin, pmax, 0);
     bounds++;
     or_open root = {score ? score[0] : b0, 0, b0};
     heap_push(&H, root);
@@ -403,7 +431,7 @@ static void tree_query(const uint64_t *db, const int32_t *child, const int64_t *
         } else {
             for (int s = 0; s < 2; s++) {
                 int64_t ch = child[2 * nd + s];
-                int64_t kb = or_node_bound(qj, or_img + ch * OR_WORDS, and_img ? and_img + ch * OR_WORDS : NULL);
+                int64_t kb = bound_of(qj, or_img, and_img, pmin, pmax, ch);
                 bounds++;
                 if (nr < k || kb <= R[k - 1].key) {
                     or_open o = {score ? score[ch] : kb, ch, kb};
@@ -420,12 +448,14 @@ static void tree_query(const uint64_t *db, const int32_t *child, const int64_t *
 }
 
 /* k-NN for nq queries over a tree in the layout or_tree_build writes.
- * and_img may be NULL (sum-image bound only).  stats (nullable) receives
+ * and_img may be NULL (sum-image bound only); pmin / pmax (both or neither)
+ * give each node's row popcount range for the tightened bound.  stats (nullable) receives
  * per query: nodes visited (processed pops), bounds evaluated, distances
  * evaluated.  score (nullable) gives per query a node priority array
  * (score + j * n_nodes), replacing the bound as the pop order. */
 int or_tree_knn(const uint64_t *db, const int32_t *child, const int64_t *begin, const int64_t *count,
-                const uint64_t *or_img, const uint64_t *and_img, const uint32_t *perm, int64_t n_nodes,
+                const uint64_t *or_img, const uint64_t *and_img, const int64_t *pmin, const int64_t *pmax,
+                const uint32_t *perm, int64_t n_nodes,
                 const uint64_t *q, int64_t nq, int k, const int64_t *score, uint32_t *idx, int32_t *missed,
                 int32_t *extra, float *dist, int64_t *stats) {
     if (k <= 0 || n_nodes <= 0) return -1;
@@ -434,8 +464,8 @@ int or_tree_knn(const uint64_t *db, const int32_t *child, const int64_t *begin, 
         const uint64_t *qj = q + j * OR_WORDS;
         or_cand *R = (or_cand *)malloc((size_t)k * sizeof(or_cand));
         int64_t nr, st[3];
-        tree_query(db, child, begin, count, or_img, and_img, perm, qj, k, score ? score + j * n_nodes : NULL, R,
-                   &nr, st);
+        tree_query(db, child, begin, count, or_img, and_img, pmin, pmax, perm, qj, k,
+                   score ? score + j * n_nodes : NULL, R, &nr, st);
         emit(R, nr, popcount_desc(qj), k, idx + j * k, missed + j * k, extra + j * k, dist + j * k);
         if (stats) {
             stats[3 * j] = st[0];

@@ -14,8 +14,11 @@ int64_t or_split_node(const uint64_t *db, const uint32_t *mem, int64_t n, uint8_
 int64_t or_tree_build(const uint64_t *db, int64_t n, int max_leaf, int64_t cap, int32_t *child, int64_t *begin,
                       int64_t *count, uint64_t *or_img, uint64_t *and_img, uint32_t *perm);
 int64_t or_node_bound(const uint64_t *q, const uint64_t *or_img, const uint64_t *and_img);
+int64_t or_node_bound_pop(const uint64_t *q, const uint64_t *or_img, const uint64_t *and_img, int64_t pmin,
+                          int64_t pmax);
 int or_tree_knn(const uint64_t *db, const int32_t *child, const int64_t *begin, const int64_t *count,
-                const uint64_t *or_img, const uint64_t *and_img, const uint32_t *perm, int64_t n_nodes,
+                const uint64_t *or_img, const uint64_t *and_img, const int64_t *pmin, const int64_t *pmax,
+                const uint32_t *perm, int64_t n_nodes,
                 const uint64_t *q, int64_t nq, int k, const int64_t *score, uint32_t *idx, int32_t *missed,
                 int32_t *extra, float *dist, int64_t *stats);
 void or_votes(const uint32_t *nn_idx, int k, const uint16_t *obj_of, int64_t n_db, int64_t n_obj,

@@ -112,11 +112,15 @@ def test_tree_search_equals_bruteforce(small_db, small_queries, k):
     a = oracle.knn_brute(small_db, q, k)
     b = oracle.tree_knn(small_db, t, q, k)
     c = oracle.tree_knn(small_db, t, q, k, use_and=True)
-    for r in (b, c):
+    d = oracle.tree_knn(small_db, t, q, k, use_pop=True)
+    e = oracle.tree_knn(small_db, t, q, k, use_and=True, use_pop=True)
+    for r in (b, c, d, e):
         assert (a.idx == r.idx).all() and (a.missed == r.missed).all() and (a.extra == r.extra).all()
         assert (a.dist == r.dist).all()
     assert (b.stats[:, 2] < small_db.shape[0]).mean() > 0.5  # the tree prunes on this data
     assert (c.stats[:, 0] <= b.stats[:, 0]).all()              # the product image only tightens
+    assert d.stats[:, 0].sum() < b.stats[:, 0].sum()           # so does the popcount range
+    assert e.stats[:, 0].sum() <= d.stats[:, 0].sum()
 
 
 def test_bound_never_exceeds_any_key():
@@ -126,6 +130,8 @@ def test_bound_never_exceeds_any_key():
     r = oracle.knn_brute(db, q, 600)
     P = _unpack(q).sum(1)
     wa, wb = np.maximum(P, 1), np.maximum(NB - P, 1)
+    pmin, pmax = oracle.node_pop_range(db, t)
+    tighter = 0
     for j in range(len(q)):
         key = np.empty(600, np.int64)
         key[r.idx[j]] = r.missed[j].astype(np.int64) * wb[j] + r.extra[j].astype(np.int64) * wa[j]
@@ -133,7 +139,39 @@ def test_bound_never_exceeds_any_key():
             rows = t.perm[t.begin[i]:t.begin[i] + t.count[i]]
             lb = oracle.node_bound(q[j], t.or_img[i])
             lb2 = oracle.node_bound(q[j], t.or_img[i], t.and_img[i])
-            assert lb <= lb2 <= key[rows].min()
+            pr = (pmin[i], pmax[i])
+            lb3 = oracle.node_bound(q[j], t.or_img[i], pop_range=pr)
+            lb4 = oracle.node_bound(q[j], t.or_img[i], t.and_img[i], pop_range=pr)
+            assert lb <= lb2 <= lb4 <= key[rows].min()
+            assert lb <= lb3 <= lb4
+            tighter += lb3 > lb
+
+
+    assert tighter > 0  # the popcount terms take part
+
+
+def test_popcount_range_bound_hand_worked():
+    # |q| = 100 (bits 0..99): wA = 100, wB = 3996
+    q = synth.from_bits(1, [range(100)])[0]
+    # rows of 10 and 12 bits, both disjoint from q: ov = 0, so A >= 100 and
+    # B >= pmin = 10; the 10-bit row reaches the bound exactly
+    rows = synth.from_bits(2, [range(200, 210), range(300, 312)])
+    img = rows[0] | rows[1]
+    assert oracle.node_bound(q, img) == 100 * 3996
+    assert oracle.node_bound(q, img, pop_range=(10, 12)) == 100 * 3996 + 10 * 100
+    # eight rows of 5 bits inside q's bits 0..39: the image covers 40 query
+    # bits (ov = 40) but no row more than 5, so A >= 95; every row reaches it
+    rows = synth.from_bits(8, [range(5 * i, 5 * i + 5) for i in range(8)])
+    img = np.bitwise_or.reduce(rows, axis=0)
+    assert oracle.node_bound(q, img) == 60 * 3996
+    assert oracle.node_bound(q, img, pop_range=(5, 5)) == 95 * 3996
+    # the product image's B term and the popcount term, the larger counts:
+    # rows of 40 bits outside q sharing 10 of them; B >= max(10, 40 - 0)
+    rows = synth.from_bits(2, [list(range(200, 210)) + list(range(300, 330)),
+                               list(range(200, 210)) + list(range(400, 430))])
+    img, and_img = rows[0] | rows[1], rows[0] & rows[1]
+    assert oracle.node_bound(q, img, and_img) == 100 * 3996 + 10 * 100
+    assert oracle.node_bound(q, img, and_img, pop_range=(40, 40)) == 100 * 3996 + 40 * 100
 
 
 def test_any_frontier_order_gives_the_same_result(small_db, small_queries):
