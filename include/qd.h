@@ -113,8 +113,9 @@ int qd_knn_bruteforce_shaped(const uint64_t *d_db, uint64_t n, const uint64_t *d
  * bit set moves to the "dissimilar" set, until the dissimilar set holds at
  * least half of the node; a move that would empty the similar set is not
  * applied, and a node that cannot be split stays a leaf.  Every node, leaves
- * included, stores the OR ("sum") image of its descriptors, and the AND
- * ("product") image if store_and_image is set.
+ * included, stores the OR ("sum") image of its descriptors, the AND
+ * ("product") image if store_and_image is set, and, unless plain_bound is
+ * set, the smallest and largest popcount of its descriptors.
  * Numbering: nodes are numbered breadth first from the root (0), the similar
  * child before the dissimilar one.  Node i covers leaf-order positions
  * begin[i] .. begin[i]+count[i]-1; perm maps a leaf-order position to the
@@ -128,11 +129,13 @@ typedef struct qd_tree_s *qd_tree_t;
 typedef struct {
     uint32_t max_leaf;        /* leaf when a node holds <= max_leaf rows; 0 = 32 (Section 4.1) */
     uint32_t store_and_image; /* 0 = sum images only (the paper's choice for sparse QUICCI) */
+    uint32_t plain_bound;     /* 1 = the paper's image bound only; 0 = also store each node's (and each
+                                 256-row block's) row popcount range and tighten the bound with it */
 } qd_build_params;
 
 typedef struct {
     uint64_t n, n_nodes, n_leaves;
-    uint32_t depth, max_leaf, has_and_image;
+    uint32_t depth, max_leaf, has_and_image, has_pop_range;
 } qd_tree_info_t;
 
 int qd_tree_build(const uint64_t *d_db, uint64_t n, const qd_build_params *params, void *stream, qd_tree_t *out);
@@ -151,15 +154,20 @@ int qd_tree_export(qd_tree_t t, int32_t *h_child, uint32_t *h_begin, uint32_t *h
  * A node's lower bound (minWHDist): every query 1-bit that is 0 in the
  * node's sum image is a type A error for all its rows, and every query 0-bit
  * that is 1 in its product image (when stored) a type B error, so all rows
- * under the node have key K >= Kb = A_lb*wB + B_lb*wA.  A child is queued
+ * under the node have key K >= Kb = A_lb*wB + B_lb*wA.  With popcount
+ * ranges (qd_build_params.plain_bound = 0) a row t shares at most
+ * min(ov, |t|) bits with q, ov = popcount(q AND sum image), so
+ * A_lb = |q| - min(ov, pmax) and B_lb = max(product-image term, pmin - ov, 0)
+ * for the node's popcount range [pmin, pmax]; the results do not change.  A child is queued
  * when fewer than k results exist or Kb <= the current k-th key; a popped
  * node with Kb above the k-th key is not expanded.  The result equals
  * qd_knn_bruteforce's exactly, whatever the order.
  * Orders:
  *   QD_ORDER_BEST_FIRST (default, the paper's priority queue): nodes leave
  *     the frontier in ascending floor(Kb / wB), which is the exact bound
- *     order when no product images are stored; the search stops at the first
- *     popped node whose bound exceeds the k-th key.
+ *     order for the sum-image bound alone; the search stops once that floor
+ *     exceeds the k-th key (nodes above the key in a lower bucket are
+ *     skipped).
  *   QD_ORDER_DEPTH_FIRST: a stack; each expansion visits the preferred child
  *     first: the higher score in d_scores when given (nq x n_scored floats,
  *     query-major, nodes 0..n_scored-1; e.g. a learned model's output), else
@@ -167,7 +175,9 @@ int qd_tree_export(qd_tree_t t, int32_t *h_child, uint32_t *h_begin, uint32_t *h
  *     empty, skipping popped nodes that cannot improve the result.
  *   QD_ORDER_BLOCKED: the whole batch at once on the matrix cores.  The leaf
  *     order is cut into blocks of 256 rows, each with the sum image of its
- *     rows; the same bound is computed for every (query, block) pair, and
+ *     rows (and their popcount range); the same bound, rounded down to a
+ *     multiple of wB (A_lb + floor(B_lb*wA/wB), at most 4096, times wB), is
+ *     computed for every (query, block) pair, and
  *     each query evaluates its blocks in rounds of ascending bound (a first
  *     round of 16 blocks, then growing about 4x), keeping only blocks whose
  *     bound is <= its current k-th key, until no block is left that could

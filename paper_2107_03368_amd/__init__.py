@@ -125,12 +125,13 @@ def profile_read(kernel):
 # Dissimilarity Tree
 # ---------------------------------------------------------------------------
 class _BuildParams(ctypes.Structure):
-    _fields_ = [("max_leaf", ctypes.c_uint32), ("store_and_image", ctypes.c_uint32)]
+    _fields_ = [("max_leaf", ctypes.c_uint32), ("store_and_image", ctypes.c_uint32), ("plain_bound", ctypes.c_uint32)]
 
 
 class _TreeInfo(ctypes.Structure):
     _fields_ = [("n", ctypes.c_uint64), ("n_nodes", ctypes.c_uint64), ("n_leaves", ctypes.c_uint64),
-                ("depth", ctypes.c_uint32), ("max_leaf", ctypes.c_uint32), ("has_and_image", ctypes.c_uint32)]
+                ("depth", ctypes.c_uint32), ("max_leaf", ctypes.c_uint32), ("has_and_image", ctypes.c_uint32),
+                ("has_pop_range", ctypes.c_uint32)]
 
 
 class _SearchParams(ctypes.Structure):
@@ -169,6 +170,7 @@ class Tree:
         _check(_lib.qd_tree_info(self._h, ctypes.byref(info)), "qd_tree_info")
         self.n, self.n_nodes, self.n_leaves = info.n, info.n_nodes, info.n_leaves
         self.depth, self.max_leaf, self.has_and_image = info.depth, info.max_leaf, bool(info.has_and_image)
+        self.has_pop_range = bool(info.has_pop_range)
 
     @property
     def handle(self):
@@ -200,9 +202,10 @@ class Tree:
         return dict(child=child, begin=begin, count=count, or_img=or_img, and_img=and_img, perm=perm)
 
 
-def tree_build(db, max_leaf=32, store_and_image=False):
+def tree_build(db, max_leaf=32, store_and_image=False, plain_bound=False):
+    """plain_bound: the paper's image bound only (no popcount ranges)."""
     _desc(db, "db")
-    prm = _BuildParams(max_leaf, 1 if store_and_image else 0)
+    prm = _BuildParams(max_leaf, 1 if store_and_image else 0, 1 if plain_bound else 0)
     h = ctypes.c_void_p()
     _check(_lib.qd_tree_build(_ptr(db), db.shape[0], ctypes.byref(prm), _stream(), ctypes.byref(h)),
            "qd_tree_build")

@@ -22,8 +22,11 @@ struct qd_tree_s {
     int32_t *d_parent = nullptr;   // n_nodes: parent node (-1 for the root)
     uint8_t *d_depth = nullptr;    // n_nodes: level of the node (root 0)
     uint32_t *d_iperm = nullptr;   // n: leaf-order position of each database row
+    uint16_t *d_pmin = nullptr;    // n_nodes: smallest row popcount under the node (null: plain bound)
+    uint16_t *d_pmax = nullptr;    // n_nodes: largest row popcount under the node
     uint64_t n_blk = 0;            // blocks of 256 leaf-order rows
     uint64_t *d_blk = nullptr;     // n_blk x 64 words: OR image of each block's rows
+    uint16_t *d_bpop = nullptr;    // n_blk x 2: smallest, largest row popcount of each block (null: plain)
 };
 
 namespace qd {

@@ -80,26 +80,52 @@ __device__ __forceinline__ uint32_t lanes_below(u64 mask) {
 }
 
 // OR image of each block of 256 leaf-order rows; one 64-thread block per
-// image, thread w owns word w.
+// image, thread w owns word w.  With bpop, also the smallest and largest
+// popcount of the block's rows.
 __global__ __launch_bounds__(64) void block_image_kernel(const uint64_t *__restrict__ sorted, uint64_t n,
-                                                         uint64_t *__restrict__ img) {
+                                                         uint64_t *__restrict__ img, const uint16_t *__restrict__ pop,
+                                                         uint16_t *__restrict__ bpop) {
     const uint64_t b = blockIdx.x;
     const int w = threadIdx.x;
     const uint64_t r0 = b * kBlk, r1 = r0 + kBlk < n ? r0 + kBlk : n;
     uint64_t acc = 0;
     for (uint64_t r = r0; r < r1; r++) acc |= sorted[r * QD_WORDS + w];
     img[b * QD_WORDS + w] = acc;
+    if (bpop) {
+        uint32_t mn = 0xFFFFu, mx = 0;
+        for (uint64_t r = r0 + w; r < r1; r += 64) {
+            const uint32_t v = pop[r];
+            mn = v < mn ? v : mn;
+            mx = v > mx ? v : mx;
+        }
+#pragma unroll
+        for (int sh = 1; sh < 64; sh <<= 1) {
+            const uint32_t a = (uint32_t)__shfl_xor((int)mn, sh), c = (uint32_t)__shfl_xor((int)mx, sh);
+            mn = a < mn ? a : mn;
+            mx = c > mx ? c : mx;
+        }
+        if (w == 0) {
+            bpop[2 * b] = (uint16_t)mn;
+            bpop[2 * b + 1] = (uint16_t)mx;
+        }
+    }
 }
 
-// A_lb for a tile of 256 queries x 256 blocks, stored query-major
-// (lbq[q][b], for the per-query plan) and block-major (lbb[b][q], for the
-// per-block lists).  Queries q >= nqb get level 0xFFFF in lbb.
+// Bound level L of every (query, block) pair in a tile of 256 queries x 256
+// blocks: every row of the block has key >= L * wB.  With the sum image
+// alone L = A_lb = |q| - ov (ov = popcount(q AND image)); with the block's
+// popcount range [pmin, pmax], A_lb = |q| - min(ov, pmax), B_lb =
+// max(pmin - ov, 0) and L = min(A_lb + floor(B_lb * wA / wB), 4096).  Stored
+// query-major (lbq[q][b], for the per-query plan) and block-major
+// (lbb[b][q], for the per-block lists).  Queries q >= nqb get level 0xFFFF
+// in lbb.
 __global__ __launch_bounds__(mt::kThreads) void bound_kernel(const uint4 *__restrict__ q, uint32_t nqb, uint32_t nqp,
                                                              const uint4 *__restrict__ img, uint64_t nblk,
+                                                             const uint16_t *__restrict__ bpop,
                                                              const uint16_t *__restrict__ qpop, uint32_t n_qtiles,
                                                              uint16_t *__restrict__ lbq, uint16_t *__restrict__ lbb) {
     __shared__ mt::Smem sm;
-    __shared__ uint32_t s_pq[mt::MA];
+    __shared__ uint32_t s_pq[mt::MA], s_pmin[mt::MB], s_pmax[mt::MB];
     const uint64_t n_tiles = (uint64_t)n_qtiles * ((nblk + mt::MB - 1) / mt::MB);
     for (uint64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
         const uint32_t q0 = (uint32_t)(tile % n_qtiles) * mt::MA;
@@ -114,15 +140,19 @@ __global__ __launch_bounds__(mt::kThreads) void bound_kernel(const uint4 *__rest
         } else {
             ok = b0 + (own - mt::MA) < nblk;
             row = ok ? img + (b0 + (own - mt::MA)) * 32 : img;
+            // without ranges: pmin = 0 and pmax = 4096 leave the plain bound
+            s_pmin[own - mt::MA] = ok && bpop ? bpop[2 * (b0 + (own - mt::MA))] : 0;
+            s_pmax[own - mt::MA] = ok && bpop ? bpop[2 * (b0 + (own - mt::MA)) + 1] : QD_BITS;
         }
         mt::v4f acc[8][4];
-        mt::overlap_tile(row, !ok, sm, acc);  // its barriers also publish s_pq
+        mt::overlap_tile(row, !ok, sm, acc);  // its barriers also publish s_pq, s_pmin, s_pmax
 #pragma unroll
         for (int a = 0; a < 8; a++)
 #pragma unroll
             for (int bb = 0; bb < 4; bb++) {
                 const uint64_t blk = b0 + mt::acc_brow(bb);
                 if (blk >= nblk) continue;
+                const uint32_t pmin = s_pmin[mt::acc_brow(bb)], pmax = s_pmax[mt::acc_brow(bb)];
                 const uint32_t qa = q0 + mt::acc_arow(a, 0);  // this lane's 4 consecutive queries
                 u64 packed = 0;
 #pragma unroll
@@ -130,7 +160,11 @@ __global__ __launch_bounds__(mt::kThreads) void bound_kernel(const uint4 *__rest
                     const uint32_t qi = qa + r;
                     uint32_t v = 0xFFFFu;
                     if (qi < nqb) {
-                        v = s_pq[qi - q0] - mt::count(acc[a][bb][r]);
+                        const uint32_t pq = s_pq[qi - q0], ov = mt::count(acc[a][bb][r]);
+                        const uint32_t al = pq - (ov < pmax ? ov : pmax);
+                        const uint32_t bl = pmin > ov ? pmin - ov : 0;
+                        v = bl ? al + bl * weight_a(pq) / weight_b(pq) : al;  // bl * wA < 2^24
+                        v = v < QD_BITS ? v : QD_BITS;
                         lbq[(uint64_t)qi * nblk + blk] = (uint16_t)v;
                     }
                     packed |= (u64)v << (16 * r);
@@ -629,7 +663,9 @@ inline size_t up256(size_t x) { return (x + 255) / 256 * 256; }
 int tree_block_images(qd_tree_s *t, hipStream_t s) {
     t->n_blk = (t->n + kBlk - 1) / kBlk;
     QD_HIP_CHECK(hipMalloc((void **)&t->d_blk, t->n_blk * 512));
-    hipLaunchKernelGGL(block_image_kernel, dim3((uint32_t)t->n_blk), dim3(64), 0, s, t->d_sorted, t->n, t->d_blk);
+    if (t->d_pmin) QD_HIP_CHECK(hipMalloc((void **)&t->d_bpop, t->n_blk * 4));
+    hipLaunchKernelGGL(block_image_kernel, dim3((uint32_t)t->n_blk), dim3(64), 0, s, t->d_sorted, t->n, t->d_blk,
+                       t->d_pop, t->d_bpop);
     QD_HIP_CHECK(hipGetLastError());
     return QD_OK;
 }
@@ -696,7 +732,8 @@ int knn_tree_blocked(qd_tree_t t, const uint64_t *d_q, uint32_t nq, uint32_t k, 
             KernelTimer timer("tree_block_bounds", s);
             hipLaunchKernelGGL(bound_kernel, dim3((uint32_t)mt::tile_grid(n_qtiles * n_btiles)), dim3(mt::kThreads), 0, s,
                                q4, nqb,
-                               nqp, reinterpret_cast<const uint4 *>(t->d_blk), nblk, qpop, n_qtiles, lbq, lbb);
+                               nqp, reinterpret_cast<const uint4 *>(t->d_blk), nblk, t->d_bpop, qpop, n_qtiles, lbq,
+                               lbb);
         }
         // round 2 covers about t2 blocks per query: enough that a block's list
         // holds ~128 queries on average

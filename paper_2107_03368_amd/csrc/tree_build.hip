@@ -409,12 +409,25 @@ __global__ __launch_bounds__(kBlock) void gather_rows_kernel(const uint4 *__rest
     for (uint64_t e = tid; e < n * 32; e += stride) sorted[e] = db[(uint64_t)perm[e >> 5] * 32 + (e & 31)];
 }
 
-// One wave per leaf: OR / AND over its rows of the leaf-ordered copy.
+// Smallest and largest of a wave's 64 values (every lane gets them).
+__device__ __forceinline__ void wave_min_max(uint32_t &mn, uint32_t &mx) {
+#pragma unroll
+    for (int sh = 1; sh < 64; sh <<= 1) {
+        const uint32_t a = (uint32_t)__shfl_xor((int)mn, sh), b = (uint32_t)__shfl_xor((int)mx, sh);
+        mn = a < mn ? a : mn;
+        mx = b > mx ? b : mx;
+    }
+}
+
+// One wave per leaf: OR / AND over its rows of the leaf-ordered copy, and
+// the popcount range of the rows (when pmin is given).
 __global__ __launch_bounds__(kBlock) void leaf_images_kernel(const uint4 *__restrict__ sorted,
                                                              const uint32_t *__restrict__ leaf_ids, uint32_t n_leaves,
                                                              const uint32_t *__restrict__ begin,
                                                              const uint32_t *__restrict__ count,
-                                                             uint4 *__restrict__ or_img, uint4 *__restrict__ and_img) {
+                                                             uint4 *__restrict__ or_img, uint4 *__restrict__ and_img,
+                                                             const uint16_t *__restrict__ pop,
+                                                             uint16_t *__restrict__ pmin, uint16_t *__restrict__ pmax) {
     const uint32_t w = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
     if (w >= n_leaves) return;
     const uint32_t node = leaf_ids[w];
@@ -436,12 +449,27 @@ __global__ __launch_bounds__(kBlock) void leaf_images_kernel(const uint4 *__rest
         or_img[(uint64_t)node * 32 + c] = make_uint4(o.x | o2.x, o.y | o2.y, o.z | o2.z, o.w | o2.w);
         if (and_img) and_img[(uint64_t)node * 32 + c] = make_uint4(a.x & a2.x, a.y & a2.y, a.z & a2.z, a.w & a2.w);
     }
+    if (pmin) {
+        uint32_t mn = 0xFFFFu, mx = 0;
+        for (uint32_t r = lane; r < m; r += 64) {
+            const uint32_t v = pop[b + r];
+            mn = v < mn ? v : mn;
+            mx = v > mx ? v : mx;
+        }
+        wave_min_max(mn, mx);
+        if (lane == 0) {
+            pmin[node] = (uint16_t)mn;
+            pmax[node] = (uint16_t)mx;
+        }
+    }
 }
 
-// Inner nodes of one level: image = combination of the two children's images.
+// Inner nodes of one level: images and popcount range combine the two
+// children's.
 __global__ __launch_bounds__(kBlock) void inner_images_kernel(const uint32_t *__restrict__ ids, uint32_t n_ids,
                                                               const int32_t *__restrict__ child,
-                                                              uint4 *__restrict__ or_img, uint4 *__restrict__ and_img) {
+                                                              uint4 *__restrict__ or_img, uint4 *__restrict__ and_img,
+                                                              uint16_t *__restrict__ pmin, uint16_t *__restrict__ pmax) {
     const uint64_t e = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
     if (e >= (uint64_t)n_ids * 32) return;
     const uint32_t node = ids[e >> 5], c = e & 31;
@@ -451,6 +479,10 @@ __global__ __launch_bounds__(kBlock) void inner_images_kernel(const uint32_t *__
     if (and_img) {
         const uint4 p = and_img[(uint64_t)s * 32 + c], r = and_img[(uint64_t)d * 32 + c];
         and_img[(uint64_t)node * 32 + c] = make_uint4(p.x & r.x, p.y & r.y, p.z & r.z, p.w & r.w);
+    }
+    if (pmin && c == 0) {
+        pmin[node] = pmin[s] < pmin[d] ? pmin[s] : pmin[d];
+        pmax[node] = pmax[s] > pmax[d] ? pmax[s] : pmax[d];
     }
 }
 
@@ -473,8 +505,9 @@ struct DevBuf {
 
 void tree_release(qd_tree_s *t) {
     if (!t) return;
-    void *ptrs[] = {t->d_sorted, t->d_perm,  t->d_or,    t->d_and,   t->d_child, t->d_begin,
-                    t->d_count,  t->d_pop,   t->d_parent, t->d_depth, t->d_iperm, t->d_blk};
+    void *ptrs[] = {t->d_sorted, t->d_perm,  t->d_or,     t->d_and,   t->d_child, t->d_begin, t->d_count,
+                    t->d_pop,    t->d_parent, t->d_depth, t->d_iperm, t->d_blk,   t->d_pmin,  t->d_pmax,
+                    t->d_bpop};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     delete t;
@@ -488,6 +521,7 @@ int tree_build_impl(const uint64_t *d_db, uint64_t n, const qd_build_params *par
     if (!aligned16(d_db)) return fail(QD_ERR_INVALID, "database must be 16-byte aligned");
     const uint32_t max_leaf = params && params->max_leaf ? params->max_leaf : 32;
     const bool want_and = params && params->store_and_image;
+    const bool want_pop = !(params && params->plain_bound);
     if (max_leaf > kSmall) return fail(QD_ERR_INVALID, "max_leaf %u above %u", max_leaf, kSmall);
     hipStream_t s = (hipStream_t)stream;
     const uint4 *db4 = reinterpret_cast<const uint4 *>(d_db);
@@ -643,7 +677,9 @@ int tree_build_impl(const uint64_t *d_db, uint64_t n, const qd_build_params *par
         hipMalloc((void **)&t->d_begin, nn * 4) != hipSuccess || hipMalloc((void **)&t->d_count, nn * 4) != hipSuccess ||
         hipMalloc((void **)&t->d_pop, n * 2) != hipSuccess || hipMalloc((void **)&t->d_parent, nn * 4) != hipSuccess ||
         hipMalloc((void **)&t->d_depth, nn) != hipSuccess || hipMalloc((void **)&t->d_iperm, n * 4) != hipSuccess ||
-        (want_and && hipMalloc((void **)&t->d_and, nn * 512) != hipSuccess))
+        (want_and && hipMalloc((void **)&t->d_and, nn * 512) != hipSuccess) ||
+        (want_pop && (hipMalloc((void **)&t->d_pmin, nn * 2) != hipSuccess ||
+                      hipMalloc((void **)&t->d_pmax, nn * 2) != hipSuccess)))
         return cleanup(fail(QD_ERR_OOM, "tree allocation failed"));
     std::vector<uint32_t> hb32(nn);
     uint32_t n_leaves = 0;
@@ -678,9 +714,14 @@ int tree_build_impl(const uint64_t *d_db, uint64_t n, const qd_build_params *par
     if (lid.alloc(std::max<uint64_t>(n_leaves, nn)) != hipSuccess) return cleanup(fail(QD_ERR_OOM, "alloc"));
     if (hipMemcpyAsync(lid.p, leaf_ids.data(), n_leaves * 4, hipMemcpyHostToDevice, s) != hipSuccess)
         return cleanup(fail(QD_ERR_DEVICE, "upload"));
+    {
+        const int rc = qd_popcount_rows(t->d_sorted, n, t->d_pop, stream);  // leaf-order rows
+        if (rc != QD_OK) return cleanup(rc);
+    }
     hipLaunchKernelGGL(leaf_images_kernel, dim3((n_leaves + 3) / 4), dim3(kBlock), 0, s,
                        reinterpret_cast<const uint4 *>(t->d_sorted), lid.p, n_leaves, t->d_begin, t->d_count,
-                       reinterpret_cast<uint4 *>(t->d_or), reinterpret_cast<uint4 *>(t->d_and));
+                       reinterpret_cast<uint4 *>(t->d_or), reinterpret_cast<uint4 *>(t->d_and), t->d_pop, t->d_pmin,
+                       t->d_pmax);
     if (hipStreamSynchronize(s) != hipSuccess) return cleanup(fail(QD_ERR_DEVICE, "leaf images"));
     // inner nodes, deepest level first
     for (int L = (int)level_first.size() - 2; L >= 0; L--) {
@@ -693,13 +734,12 @@ int tree_build_impl(const uint64_t *d_db, uint64_t n, const qd_build_params *par
         const uint64_t work = (uint64_t)inner.size() * 32;
         hipLaunchKernelGGL(inner_images_kernel, dim3((uint32_t)((work + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
                            lid.p, (uint32_t)inner.size(), t->d_child, reinterpret_cast<uint4 *>(t->d_or),
-                           reinterpret_cast<uint4 *>(t->d_and));
+                           reinterpret_cast<uint4 *>(t->d_and), t->d_pmin, t->d_pmax);
         if (hipStreamSynchronize(s) != hipSuccess) return cleanup(fail(QD_ERR_DEVICE, "inner images"));
     }
     hipLaunchKernelGGL(invert_perm_kernel, dim3((uint32_t)std::min<uint64_t>((n + kBlock - 1) / kBlock, 65535)),
                        dim3(kBlock), 0, s, t->d_perm, n, t->d_iperm);
-    int rc = qd_popcount_rows(t->d_sorted, n, t->d_pop, stream);
-    if (rc == QD_OK) rc = tree_block_images(t, s);
+    int rc = tree_block_images(t, s);
     if (rc != QD_OK) return cleanup(rc);
     if (hipStreamSynchronize(s) != hipSuccess || hipGetLastError() != hipSuccess)
         return cleanup(fail(QD_ERR_DEVICE, "tree build kernels failed"));
@@ -728,6 +768,7 @@ extern "C" int qd_tree_info(qd_tree_t t, qd_tree_info_t *info) {
     info->depth = t->depth;
     info->max_leaf = t->max_leaf;
     info->has_and_image = t->has_and ? 1 : 0;
+    info->has_pop_range = t->d_pmin ? 1 : 0;
     return QD_OK;
 }
 

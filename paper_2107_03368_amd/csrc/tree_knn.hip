@@ -6,16 +6,20 @@
 // type A error for every row under the node, so with
 //   A_lb = |q| - popcount(q AND OR)   (and, with product images,
 //   B_lb = popcount(NOT q AND AND))
-// every row under the node has key K >= Kb = A_lb*wB + B_lb*wA.  Children are
+// every row under the node has key K >= Kb = A_lb*wB + B_lb*wA.  With the
+// popcount range [pmin, pmax] of the node's rows, a row shares at most
+// min(ov, pmax) bits with q (ov = popcount(q AND OR)): A_lb = |q| -
+// min(ov, pmax), and B_lb is at least pmin - ov.  Children are
 // bounded when their parent is expanded; a child is queued when fewer than k
 // results exist or Kb <= the current k-th key; a popped node whose Kb exceeds
 // the k-th key is not expanded.
 //
 // Frontier orders:
 //  best-first (the paper's priority queue): a bucket queue on
-//    floor(Kb / wB) (= A_lb without product images, so nodes come out in
-//    exact bound order); the search stops at the first popped node whose
-//    bound exceeds the k-th key.  Each bucket is a stack of 16-entry chunks in
+//    floor(Kb / wB) (= A_lb for the sum-image bound alone, so nodes come out
+//    in exact bound order); the search stops once the popped bucket's lower
+//    end exceeds the k-th key (a popped node above the key in a lower bucket
+//    is skipped: with B terms a bucket holds bounds up to wB apart).  Each bucket is a stack of 16-entry chunks in
 //    the wave's global workspace, its (chunk, fill) word in LDS, and a
 //    4096-bit occupancy map spread over the 64 lanes finds the lowest
 //    non-empty bucket with one ballot.  Only lane 0 touches the chunk memory.
@@ -48,6 +52,8 @@ struct TreeView {
     const uint32_t *begin;
     const uint32_t *count;
     const uint16_t *pop;
+    const uint16_t *pmin;  // nullable: per node, the smallest and largest row popcount
+    const uint16_t *pmax;
 };
 
 struct Scores {
@@ -116,13 +122,23 @@ __global__ __launch_bounds__(kBlock) void tree_knn_kernel(TreeView T, const uint
         uint32_t nfree = 0; // best-first: chunks on the free list
         int sp = 0;         // depth-first: stack depth
 
-        auto bound_pair = [&](int32_t c0, int32_t c1, uint32_t &kb0, uint32_t &kb1) {
-            const int32_t c = lane < 32 ? c0 : c1;
+        // bound of node c from its images (each half-wave holds one node's
+        // 32 chunks) and, when stored, its rows' popcount range
+        auto node_bound = [&](int32_t c) -> uint32_t {
             const uint4 o = T.orimg[(uint64_t)c * 32 + (lane & 31)];
-            uint32_t ov = sum32(popc_and4(qn, o));
+            const uint32_t ov = sum32(popc_and4(qn, o));
             uint32_t bl = 0;
             if (has_and) bl = sum32(popc_and4(nqn, T.andimg[(uint64_t)c * 32 + (lane & 31)]));
-            const uint32_t kb = (pq - ov) * wb + bl * wa;
+            uint32_t al = pq - ov;
+            if (T.pmin) {
+                const uint32_t lo = T.pmin[c], hi = T.pmax[c];
+                al = pq - (ov < hi ? ov : hi);
+                bl = lo > ov && lo - ov > bl ? lo - ov : bl;
+            }
+            return al * wb + bl * wa;
+        };
+        auto bound_pair = [&](int32_t c0, int32_t c1, uint32_t &kb0, uint32_t &kb1) {
+            const uint32_t kb = node_bound(lane < 32 ? c0 : c1);
             kb0 = readlane(kb, 0);
             kb1 = readlane(kb, 32);
         };
@@ -179,17 +195,14 @@ __global__ __launch_bounds__(kBlock) void tree_knn_kernel(TreeView T, const uint
 
         // root
         {
-            const uint4 o = T.orimg[lane & 31];
-            uint32_t ov = sum32(popc_and4(qn, o));
-            uint32_t bl = 0;
-            if (has_and) bl = sum32(popc_and4(nqn, T.andimg[lane & 31]));
-            const uint32_t kb = readlane((pq - ov) * wb + bl * wa, 0);
+            const uint32_t kb = readlane(node_bound(0), 0);
             bounds++;
             push(kb, 0);
         }
 
         for (;;) {
             u64 e;
+            uint32_t floor_kb = 0;  // best-first: lower end of the popped bucket, a bound on every open node
             if (kBest) {
                 const u64 nz = ballot(occ != 0);
                 if (!nz) break;
@@ -216,6 +229,7 @@ __global__ __launch_bounds__(kBlock) void tree_knn_kernel(TreeView T, const uint
                     }
                 }
                 e = readlane64(got, 0);
+                floor_kb = b * wb;
                 if (readfirst(freed) != kNone) nfree++;
                 if (readfirst(emptied) && lane == L) occ &= ~(1ull << (b & 63));
             } else {
@@ -225,8 +239,10 @@ __global__ __launch_bounds__(kBlock) void tree_knn_kernel(TreeView T, const uint
             }
             const uint32_t kb = readfirst((uint32_t)(e >> 32)), node = readfirst((uint32_t)e);
             if (kworst != kNone && kb > kworst) {
-                if (kBest) break;  // every open node is at least this far
-                continue;          // depth-first: this entry cannot improve the result
+                // best-first: once the bucket's lower end is past the k-th key,
+                // every open node is; a node of a lower bucket is only skipped
+                if (kBest && floor_kb > kworst) break;
+                continue;  // this entry cannot improve the result
             }
             visited++;
             if (trace && node < n_traced && lane == 0)
@@ -366,7 +382,8 @@ int tree_launch(qd_tree_t t, const TreeLaunch &L, char *ws, const uint64_t *d_q,
     uint32_t *chunk_prev = reinterpret_cast<uint32_t *>(ws + L.head);
     u64 *pool = reinterpret_cast<u64 *>(ws + L.head + L.prev_bytes);
     TreeView T{reinterpret_cast<const uint4 *>(t->d_sorted), t->d_perm, reinterpret_cast<const uint4 *>(t->d_or),
-               reinterpret_cast<const uint4 *>(t->d_and), t->d_child, t->d_begin, t->d_count, t->d_pop};
+               reinterpret_cast<const uint4 *>(t->d_and), t->d_child, t->d_begin, t->d_count, t->d_pop,
+               t->d_pmin, t->d_pmax};
     Scores S{d_scores, d_scores ? n_scored : 0};
     KernelTimer timer("tree_knn", s);
     if (order == QD_ORDER_BEST_FIRST)

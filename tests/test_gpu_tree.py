@@ -78,24 +78,37 @@ def test_search_matches_oracle_10k(qd, small_db, small_queries, k):
     best = qd.knn_tree(tree, _t(q), k, query_stats=True)
     _same(best, ref)
     _same(qd.knn_tree(tree, _t(q), k, order=qd.ORDER_DEPTH_FIRST), ref)
-    # traversal statistics follow the oracle's best-first search (ties may pop
-    # in another order, so allow a small difference)
+    # traversal statistics follow the oracle's best-first search with the same
+    # bound (ties may pop in another order, so allow a small difference)
     ot = oracle.tree_build(small_db)
-    ostats = oracle.tree_knn(small_db, ot, q, k).stats
+    ostats = oracle.tree_knn(small_db, ot, q, k, use_pop=True).stats
     g = best[4].cpu().numpy()
     assert abs(g[:, 0].sum() - ostats[:, 0].sum()) <= 0.02 * ostats[:, 0].sum()
     assert (g[:, 3] <= small_db.shape[0]).all()
+    # the paper's plain image bound: same results, the oracle's plain node counts
+    plain = qd.tree_build(_t(small_db), plain_bound=True)
+    assert tree.has_pop_range and not plain.has_pop_range
+    pres = qd.knn_tree(plain, _t(q), k, query_stats=True)
+    _same(pres, ref)
+    _same(qd.knn_tree(plain, _t(q), k, order=qd.ORDER_DEPTH_FIRST), ref)
+    pstats = oracle.tree_knn(small_db, ot, q, k).stats
+    gp = pres[4].cpu().numpy()
+    assert abs(gp[:, 0].sum() - pstats[:, 0].sum()) <= 0.02 * pstats[:, 0].sum()
+    assert g[:, 0].sum() < gp[:, 0].sum()  # the popcount range prunes more
 
 
-def test_search_with_product_images_and_scores(qd, small_db, small_queries):
+@pytest.mark.parametrize("plain", [False, True])
+def test_search_with_product_images_and_scores(qd, small_db, small_queries, plain):
     import torch
     q, _ = small_queries
-    tree = qd.tree_build(_t(small_db), store_and_image=True)
-    ref = oracle.knn_brute(small_db, q, 10)
-    _same(qd.knn_tree(tree, _t(q), 10), ref)
-    for seed in (1, 2):
-        sc = torch.from_numpy(np.random.default_rng(seed).random((len(q), tree.n_nodes), dtype=np.float32))
-        _same(qd.knn_tree(tree, _t(q), 10, order=qd.ORDER_DEPTH_FIRST, scores=sc.cuda()), ref)
+    tree = qd.tree_build(_t(small_db), store_and_image=True, plain_bound=plain)
+    for k in (1, 10):
+        ref = oracle.knn_brute(small_db, q, k)
+        _same(qd.knn_tree(tree, _t(q), k), ref)
+        _same(qd.knn_tree(tree, _t(q), k, order=qd.ORDER_BLOCKED), ref)
+        for seed in (1, 2):
+            sc = torch.from_numpy(np.random.default_rng(seed).random((len(q), tree.n_nodes), dtype=np.float32))
+            _same(qd.knn_tree(tree, _t(q), k, order=qd.ORDER_DEPTH_FIRST, scores=sc.cuda()), ref)
 
 
 def test_search_edge_cases(qd):
@@ -152,5 +165,14 @@ def test_search_1m_sampled_queries(qd, tree_1m, k):
     q, _ = synth.gen_queries(db, 4096, 2001, 0.1, 0.6)
     rows = np.array([0, 5, 1000, 3333, 4095])
     ref = oracle.knn_brute(db, q[rows], k)
-    _same(qd.knn_tree(tree, _t(q), k), ref, rows)
+    best = qd.knn_tree(tree, _t(q), k, totals=True)
+    _same(best, ref, rows)
     _same(qd.knn_tree(tree, _t(q), k, order=qd.ORDER_DEPTH_FIRST), ref, rows)
+    # the plain image bound gives the same neighbours for every query, with more nodes
+    plain = qd.tree_build(_t(db), plain_bound=True)
+    pres = qd.knn_tree(plain, _t(q), k, totals=True)
+    for a, b in zip(best[:4], pres[:4]):
+        assert np.array_equal(a.cpu().numpy(), b.cpu().numpy())
+    print(f"k={k}: nodes visited per query {best[-1]['nodes_visited'] / len(q):.0f} with popcount ranges, "
+          f"{pres[-1]['nodes_visited'] / len(q):.0f} plain")
+    assert best[-1]["nodes_visited"] < pres[-1]["nodes_visited"]

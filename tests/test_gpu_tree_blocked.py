@@ -147,3 +147,17 @@ def test_blocked_1m(qd, tree_1m, k):
         assert np.array_equal(a, b)
     rows = np.array([0, 7, 2048, 4095])
     _same(res, oracle.knn_brute(db, q[rows], k), rows)
+
+
+@pytest.mark.parametrize("k", [1, 10])
+def test_blocked_popcount_range_and_plain_bound(qd, k):
+    # blocks bounded with their rows' popcount range and with the plain image
+    # bound: identical results; the range adds no blocks (up to round granularity)
+    db = synth.gen_db(60_123, 1101)
+    q, _ = synth.gen_queries(db, 600, 2101, 0.1, 0.6)
+    ref = oracle.knn_brute(db, q, k)
+    pop = qd.knn_tree(qd.tree_build(_t(db)), _t(q), k, order=qd.ORDER_BLOCKED, query_stats=True)
+    plain = qd.knn_tree(qd.tree_build(_t(db), plain_bound=True), _t(q), k, order=qd.ORDER_BLOCKED, query_stats=True)
+    _same(pop, ref)
+    _same(plain, ref)
+    assert pop[4].cpu().numpy()[:, 0].sum() <= 1.01 * plain[4].cpu().numpy()[:, 0].sum()
