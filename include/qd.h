@@ -104,6 +104,28 @@ int qd_knn_bruteforce_shaped(const uint64_t *d_db, uint64_t n, const uint64_t *d
                              int32_t *d_extra, float *d_dist, void *stream);
 
 /* ---------------------------------------------------------------------------
+ * Bit-plane index for small query batches (the sequential search of Section
+ * 6.2, reorganised).  qd_planes_build stores the n descriptors transposed:
+ * plane b (one per bit position, 4096) holds bit b of every row, row i at bit
+ * i % 64 of word i / 64, so a query reads only its |q| planes (and a
+ * popcount per candidate row) instead of all 512-byte rows.  The index takes
+ * about n x 512 bytes plus 2 bytes per row, keeps a pointer to d_db (which
+ * must outlive it: the final step reads the result rows) and is built
+ * synchronously on `stream`.  Free with qd_planes_free.
+ * qd_knn_planes returns exactly qd_knn_bruteforce's results (same arguments
+ * and outputs, see "Results" above).  Each wave counts, for one query and a
+ * range of 64-row plane words, the overlaps of all 64 rows at once in
+ * bit-sliced counters, and computes keys only for rows whose overlap can
+ * still reach the wave's current k-th key.
+ * ------------------------------------------------------------------------- */
+typedef struct qd_planes_s *qd_planes_t;
+
+int qd_planes_build(const uint64_t *d_db, uint64_t n, void *stream, qd_planes_t *out);
+int qd_planes_free(qd_planes_t p);
+int qd_knn_planes(qd_planes_t p, const uint64_t *d_q, uint32_t nq, uint32_t k, uint32_t *d_idx, int32_t *d_missed,
+                  int32_t *d_extra, float *d_dist, void *stream);
+
+/* ---------------------------------------------------------------------------
  * Dissimilarity Tree (Section 4).
  *
  * qd_tree_build indexes a fixed set of n descriptors (Section 4.1, Listing 1):

@@ -239,6 +239,45 @@ def knn_tree(tree, q, k, order=ORDER_BEST_FIRST, scores=None, query_stats=False,
 
 
 # ---------------------------------------------------------------------------
+# Bit-plane index (small query batches)
+_sig("qd_planes_build", [_P, _U64, _P, ctypes.POINTER(ctypes.c_void_p)])
+_sig("qd_planes_free", [_P])
+_sig("qd_knn_planes", [_P, _P, _U32, _U32, _P, _P, _P, _P, _P])
+
+
+class Planes:
+    """A library-owned bit-plane index of ``db`` (kept alive with it)."""
+
+    def __init__(self, db):
+        _desc(db, "db")
+        self._db = db  # the index reads the result rows from it
+        h = ctypes.c_void_p()
+        _check(_lib.qd_planes_build(_ptr(db), db.shape[0], _stream(), ctypes.byref(h)), "qd_planes_build")
+        self._h = h
+        self.n = db.shape[0]
+
+    def free(self):
+        if self._h:
+            _lib.qd_planes_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def knn_planes(planes, q, k):
+    """Exact k-NN through the bit-plane index: (idx, missed, extra, dist)."""
+    _desc(q, "q")
+    out = _results(q.shape[0], k, q.device)
+    _check(_lib.qd_knn_planes(planes._h, _ptr(q), q.shape[0], k, *(_ptr(t) for t in out), _stream()),
+           "qd_knn_planes")
+    return out
+
+
+# ---------------------------------------------------------------------------
 # Retrieval by voting
 # ---------------------------------------------------------------------------
 _sig("qd_retrieve_objects", [_P, _P, _U64, _P, _U32, _P, _U64, _P, _U32, _U32, _U32, ctypes.POINTER(_SearchParams),

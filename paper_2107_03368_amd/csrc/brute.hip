@@ -100,8 +100,9 @@ __global__ __launch_bounds__(kBlock) void scan_topk_kernel(const uint4 *__restri
 // One block per query: exact top k from n_parts sorted lists of k keys, then
 // the result rows.  U = the k-th smallest list head bounds the k-th key from
 // above (those k heads are k distinct candidates), and only lists whose head
-// is <= U (at most k of them) can hold keys <= U, so at most k*k candidates
-// are gathered and sorted.
+// is <= U (at most k of them: keys are distinct) can hold keys <= U, so at
+// most k*k candidates are gathered and sorted.  The lists are first read
+// only at their heads, then the qualifying lists' entries all at once.
 __global__ __launch_bounds__(kBlock) void merge_emit_kernel(const u64 *__restrict__ part, uint32_t n_parts,
                                                             uint32_t k, const uint64_t *__restrict__ q,
                                                             const uint64_t *__restrict__ db, uint32_t *idx,
@@ -110,22 +111,28 @@ __global__ __launch_bounds__(kBlock) void merge_emit_kernel(const u64 *__restric
     if (nq_dev && blockIdx.x >= *nq_dev) return;  // whole block
     __shared__ u64 heads[kMaxParts];
     __shared__ u64 cand[kMaxCand];
-    __shared__ uint32_t ncand;
+    __shared__ uint32_t qual[QD_MAX_K];
+    __shared__ uint32_t ncand, nqual;
     const uint32_t qi = blockIdx.x;
     const u64 *lists = part + (uint64_t)qi * n_parts * k;
     const uint32_t hp = next_pow2(n_parts < 2 ? 2 : n_parts);
     for (uint32_t i = threadIdx.x; i < hp; i += blockDim.x) heads[i] = i < n_parts ? lists[(uint64_t)i * k] : KEY_NONE;
-    if (threadIdx.x == 0) ncand = 0;
+    if (threadIdx.x == 0) ncand = nqual = 0;
     __syncthreads();
     block_bitonic_sort(heads, hp);
     const u64 U = k <= n_parts ? heads[k - 1] : KEY_NONE;
     for (uint32_t p = threadIdx.x; p < n_parts; p += blockDim.x) {
-        const u64 *L = lists + (uint64_t)p * k;
-        for (uint32_t r = 0; r < k; r++) {
-            const u64 e = L[r];
-            if (e == KEY_NONE || e > U) break;
-            cand[atomicAdd(&ncand, 1u)] = e;
+        const u64 h = lists[(uint64_t)p * k];
+        if (h != KEY_NONE && h <= U) {
+            const uint32_t at = atomicAdd(&nqual, 1u);
+            if (at < QD_MAX_K) qual[at] = p;
         }
+    }
+    __syncthreads();
+    const uint32_t nl = nqual < (uint32_t)QD_MAX_K ? nqual : (uint32_t)QD_MAX_K;
+    for (uint32_t i = threadIdx.x; i < nl * k; i += blockDim.x) {
+        const u64 e = lists[(uint64_t)qual[i / k] * k + i % k];
+        if (e != KEY_NONE && e <= U) cand[atomicAdd(&ncand, 1u)] = e;  // a prefix of each list
     }
     __syncthreads();
     const uint32_t nc = ncand;
@@ -239,6 +246,17 @@ int brute_launch(const BruteLaunch &sh, u64 *part, const uint64_t *d_db, uint64_
         hipLaunchKernelGGL(merge_emit_kernel, dim3(nq), dim3(kBlock), 0, s, part, sh.n_parts, k, d_q, d_db, d_idx,
                            d_missed, d_extra, d_dist, nq_dev);
     }
+    QD_HIP_CHECK(hipGetLastError());
+    return QD_OK;
+}
+
+int merge_launch(const u64 *part, uint32_t n_parts, uint32_t k, const uint64_t *d_q, const uint64_t *d_db,
+                 uint32_t nq, uint32_t *d_idx, int32_t *d_missed, int32_t *d_extra, float *d_dist, hipStream_t s) {
+    if (n_parts < 1 || n_parts > kMaxParts) return fail(QD_ERR_INVALID, "%u lists per query outside 1..%u", n_parts,
+                                                        kMaxParts);
+    KernelTimer timer("topk_merge", s);
+    hipLaunchKernelGGL(merge_emit_kernel, dim3(nq), dim3(kBlock), 0, s, part, n_parts, k, d_q, d_db, d_idx, d_missed,
+                       d_extra, d_dist, nullptr);
     QD_HIP_CHECK(hipGetLastError());
     return QD_OK;
 }

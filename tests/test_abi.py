@@ -87,3 +87,20 @@ def test_score_rows_argument_errors_without_device_work():
     assert f(a, 3, 0, 1, a, None) == -1      # no objects
     assert f(None, 3, 5, 1, a, None) == -1   # null scores
     assert f(a, 3, 5, 1, None, None) == -1   # null best
+
+
+def test_planes_argument_errors_without_device_work():
+    lib = ctypes.CDLL(LIB)
+    P, U64, U32 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32
+    b = lib.qd_planes_build
+    b.argtypes = [P, U64, P, ctypes.POINTER(P)]
+    h = P()
+    a = P(0x10000)
+    assert b(None, 10, None, ctypes.byref(h)) == -1           # null database
+    assert b(a, 0, None, ctypes.byref(h)) == -1               # no rows
+    assert b(P(0x10008), 10, None, ctypes.byref(h)) == -1     # misaligned
+    assert b(a, 10, None, None) == -1                         # no output handle
+    f = lib.qd_knn_planes
+    f.argtypes = [P, P, U32, U32, P, P, P, P, P]
+    assert f(None, a, 1, 1, a, a, a, a, None) == -1           # no index
+    assert lib.qd_planes_free(None) == 0
