@@ -63,6 +63,11 @@ constexpr int kGroup = 16;                 // blocks per wave when building the 
 constexpr uint32_t kInf = 0xFFFFFFFFu;
 constexpr uint32_t kLevels = QD_BITS + 1;  // A_lb in 0 .. 4096
 constexpr uint32_t kMaxBatch = 16384;      // queries per batch (list entries are 16-bit)
+// A block listed for fewer queries than this is evaluated on the vector ALUs,
+// one wave per (query, block) pair, instead of in a matrix-core tile that
+// costs the same for 1 or 256 listed queries (measured at 10M rows: 16, 24
+// and 32 within 1%, 48 2% and 96 7% slower).
+constexpr uint32_t kShortList = 24;
 
 // Position of block b of bound level L in the per-query block order; a round
 // covers the keys in (lo, hi].  Key 0 is below every block.
@@ -410,32 +415,101 @@ __global__ __launch_bounds__(256) void list_kernel(const uint16_t *__restrict__ 
         for (uint32_t jj = 0; jj < nb; jj++) cnt[b0 + jj] = c[jj];
 }
 
-// Exclusive prefix of the tiles per block (256 listed queries per tile);
-// off[nblk] and *total receive the sum.
+// Matrix-core tiles of a block listed for c queries (256 per tile; none for
+// a short list) and its (query, block) pairs for the vector ALUs.
+__device__ __forceinline__ uint32_t mfma_tiles(uint32_t c) { return c >= kShortList ? (c + mt::MA - 1) / mt::MA : 0; }
+__device__ __forceinline__ uint32_t short_pairs(uint32_t c) { return c >= kShortList ? 0 : c; }
+
+// Exclusive prefixes over the blocks of the matrix-core tiles (off) and of
+// the short-list pairs (voff); off[nblk], voff[nblk], total[0] and total[1]
+// receive the sums.
 __global__ __launch_bounds__(1024) void tile_scan_kernel(const uint32_t *__restrict__ cnt, uint64_t nblk,
-                                                         uint32_t *__restrict__ off, uint32_t *__restrict__ total) {
-    __shared__ uint32_t part[1024];
+                                                         uint32_t *__restrict__ off, uint32_t *__restrict__ voff,
+                                                         uint32_t *__restrict__ total) {
+    __shared__ uint32_t part[1024], vpart[1024];
     const uint32_t tid = threadIdx.x;
     const uint64_t chunk = (nblk + 1023) / 1024;
     const uint64_t c0 = (uint64_t)tid * chunk, c1 = c0 + chunk < nblk ? c0 + chunk : nblk;
-    uint32_t s = 0;
-    for (uint64_t b = c0; b < c1; b++) s += (cnt[b] + mt::MA - 1) / mt::MA;
+    uint32_t s = 0, vs = 0;
+    for (uint64_t b = c0; b < c1; b++) {
+        s += mfma_tiles(cnt[b]);
+        vs += short_pairs(cnt[b]);
+    }
     part[tid] = s;
+    vpart[tid] = vs;
     __syncthreads();
     for (uint32_t d = 1; d < 1024; d <<= 1) {
         const uint32_t v = tid >= d ? part[tid - d] : 0;
+        const uint32_t vv = tid >= d ? vpart[tid - d] : 0;
         __syncthreads();
         part[tid] += v;
+        vpart[tid] += vv;
         __syncthreads();
     }
-    uint32_t run = part[tid] - s;
+    uint32_t run = part[tid] - s, vrun = vpart[tid] - vs;
     for (uint64_t b = c0; b < c1; b++) {
         off[b] = run;
-        run += (cnt[b] + mt::MA - 1) / mt::MA;
+        voff[b] = vrun;
+        run += mfma_tiles(cnt[b]);
+        vrun += short_pairs(cnt[b]);
     }
     if (tid == 1023) {
         off[nblk] = part[1023];
-        *total = part[1023];
+        voff[nblk] = vpart[1023];
+        total[0] = part[1023];
+        total[1] = vpart[1023];
+    }
+}
+
+// The (query, block) pairs of short lists on the vector ALUs: one wave per
+// pair, 8 lanes per row and 8 rows per step over the block's rows; rows with
+// K <= the query's k-th key join its candidates, as in eval_kernel.
+__global__ __launch_bounds__(256) void eval_short_kernel(const uint4 *__restrict__ q, const uint4 *__restrict__ sorted,
+                                                         uint64_t n, uint64_t nblk, uint32_t nqp,
+                                                         const uint16_t *__restrict__ list,
+                                                         const uint32_t *__restrict__ voff,
+                                                         const uint16_t *__restrict__ tpop,
+                                                         const uint32_t *__restrict__ perm,
+                                                         const uint16_t *__restrict__ qpop,
+                                                         const uint32_t *__restrict__ thrk, uint32_t *__restrict__ ccnt,
+                                                         u64 *__restrict__ cand) {
+    const int lane = lane_id(), g = lane >> 3, j = lane & 7;
+    const uint64_t total = voff[nblk];
+    const uint64_t nw = (uint64_t)gridDim.x * 4;
+    for (uint64_t i = readfirst(blockIdx.x * 4 + (threadIdx.x >> 6)); i < total; i += nw) {
+        uint64_t lo = 0, hi = nblk;  // voff[lo] <= i < voff[hi]
+        while (hi - lo > 1) {
+            const uint64_t mid = (lo + hi) / 2;
+            if (voff[mid] <= i)
+                lo = mid;
+            else
+                hi = mid;
+        }
+        const uint64_t b = lo;
+        const uint32_t qi = readfirst((uint32_t)list[b * nqp + (i - voff[b])]);
+        uint4 qv[4];
+#pragma unroll
+        for (int ii = 0; ii < 4; ii++) qv[ii] = q[(uint64_t)qi * 32 + j + 8 * ii];
+        const uint32_t pq = readfirst(qpop[qi]);
+        const uint32_t wa = weight_a(pq), wb = weight_b(pq);
+        const uint32_t th = readfirst(thrk[qi]);
+        const uint64_t r0 = b * kBlk;
+        const uint32_t m = (uint32_t)(n - r0 < kBlk ? n - r0 : kBlk);
+        for (uint32_t base = 0; base < m; base += 8) {
+            const uint32_t r = base + (uint32_t)g;
+            const bool valid = r < m;
+            const uint64_t pos = r0 + (valid ? r : 0);
+            uint4 tv[4];
+#pragma unroll
+            for (int ii = 0; ii < 4; ii++) tv[ii] = sorted[pos * 32 + j + 8 * ii];
+            const uint32_t c = sum8(popc_and4(tv[0], qv[0]) + popc_and4(tv[1], qv[1]) + popc_and4(tv[2], qv[2]) +
+                                    popc_and4(tv[3], qv[3]));
+            const uint32_t K = (pq - c) * wb + ((uint32_t)tpop[pos] - c) * wa;
+            if (valid && j == 0 && K <= th) {
+                const uint32_t at = atomicAdd(&ccnt[qi], 1u);
+                if (at < kCap) cand[(uint64_t)qi * kCap + at] = ((u64)K << 32) | perm[pos];
+            }
+        }
     }
 }
 
@@ -467,7 +541,7 @@ __global__ __launch_bounds__(mt::kThreads) void eval_kernel(const uint4 *__restr
             else
                 hi = mid;
         }
-        const uint64_t b = lo;
+        const uint64_t b = lo;  // a block with tiles has a list of at least kShortList queries
         const uint32_t t0 = (x - off[b]) * mt::MA;
         const uint32_t left = cnt[b] - t0;
         const uint32_t m = left < (uint32_t)mt::MA ? left : (uint32_t)mt::MA;
@@ -697,7 +771,7 @@ int knn_tree_blocked(qd_tree_t t, const uint64_t *d_q, uint32_t nq, uint32_t k, 
                  a_list = take(P * nblk * 2), a_cuts = take(P * (kRounds + 1) * 8), a_r1 = take(P * kM1 * 4),
                  a_rec = take(P * 16), a_thr = take(P * 4), a_ntop = take(P * 4), a_top = take(P * k * 8),
                  a_ccnt = take(P * 4), a_cand = take(P * kCap * 8), a_cnt = take(nblk * 4), a_qr = take(P * 4),
-                 a_off = take((nblk + 1) * 4), a_ctr = take(16), a_redo = take(P * 4), a_qst = take(P * 16),
+                 a_off = take((nblk + 1) * 4), a_voff = take((nblk + 1) * 4), a_ctr = take(16), a_redo = take(P * 4), a_qst = take(P * 16),
                  a_gst = take(32);
     char *ws = nullptr;
     QD_HIP_CHECK(hipMallocAsync((void **)&ws, o, s));
@@ -707,7 +781,7 @@ int knn_tree_blocked(qd_tree_t t, const uint64_t *d_q, uint32_t nq, uint32_t k, 
         *cand = (u64 *)(ws + a_cand);
     uint32_t *r1list = (uint32_t *)(ws + a_r1), *thr = (uint32_t *)(ws + a_thr), *ntop = (uint32_t *)(ws + a_ntop),
              *ccnt = (uint32_t *)(ws + a_ccnt), *cnt = (uint32_t *)(ws + a_cnt), *off = (uint32_t *)(ws + a_off),
-             *ctr = (uint32_t *)(ws + a_ctr), *redo = (uint32_t *)(ws + a_redo), *qst = (uint32_t *)(ws + a_qst),
+             *voff = (uint32_t *)(ws + a_voff), *ctr = (uint32_t *)(ws + a_ctr), *redo = (uint32_t *)(ws + a_redo), *qst = (uint32_t *)(ws + a_qst),
              *qround = (uint32_t *)(ws + a_qr);
     unsigned long long *gst = (unsigned long long *)(ws + a_gst);
     const bool want_stats = d_qstats || h_stats;
@@ -754,7 +828,7 @@ int knn_tree_blocked(qd_tree_t t, const uint64_t *d_q, uint32_t nq, uint32_t k, 
                 const uint64_t waves = (nblk + kGroup - 1) / kGroup;
                 hipLaunchKernelGGL(list_kernel, dim3((uint32_t)((waves + 3) / 4)), dim3(256), 0, s, lbb, nblk, n, nqb,
                                    nqp, rec, list, cnt, want_stats ? qst : nullptr);
-                hipLaunchKernelGGL(tile_scan_kernel, dim3(1), dim3(1024), 0, s, cnt, nblk, off, ctr + 2);
+                hipLaunchKernelGGL(tile_scan_kernel, dim3(1), dim3(1024), 0, s, cnt, nblk, off, voff, ctr + 2);
             }
             uint32_t h[4];
             hipError_t e = hipMemcpyAsync(h, ctr, 16, hipMemcpyDeviceToHost, s);
@@ -772,6 +846,13 @@ int knn_tree_blocked(qd_tree_t t, const uint64_t *d_q, uint32_t nq, uint32_t k, 
                                    s, q4,
                                    reinterpret_cast<const uint4 *>(t->d_sorted), n, nblk, nqp, list, cnt, off,
                                    t->d_pop, t->d_perm, qpop, thr, ccnt, cand);
+            }
+            if (h[3] > 0) {
+                KernelTimer timer("tree_block_eval_short", s);
+                const uint64_t waves = std::min<uint64_t>(h[3], (uint64_t)device_cus() * 32);
+                hipLaunchKernelGGL(eval_short_kernel, dim3((uint32_t)((waves + 3) / 4)), dim3(256), 0, s, q4,
+                                   reinterpret_cast<const uint4 *>(t->d_sorted), n, nblk, nqp, list, voff, t->d_pop,
+                                   t->d_perm, qpop, thr, ccnt, cand);
             }
             {
                 KernelTimer timer("tree_block_select", s);
