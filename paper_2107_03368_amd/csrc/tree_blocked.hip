@@ -524,9 +524,11 @@ __global__ __launch_bounds__(mt::kThreads) void eval_kernel(const uint4 *__restr
                                                             const uint32_t *__restrict__ perm,
                                                             const uint16_t *__restrict__ qpop,
                                                             const uint32_t *__restrict__ thrk,
+                                                            const uint16_t *__restrict__ bpop,
                                                             uint32_t *__restrict__ ccnt, u64 *__restrict__ cand) {
     __shared__ mt::Smem sm;
     __shared__ uint32_t s_qi[mt::MA], s_pq[mt::MA], s_th[mt::MA], s_tp[mt::MB];
+    __shared__ float s_cmin[mt::MA];  // per query slot: the least overlap that can reach its k-th key
     const uint64_t total = off[nblk];
     // workgroup v of the virtual grid runs on XCD v % 8 (gridDim.x is a multiple of 8)
     for (uint64_t v = blockIdx.x; v < mt::xcd_grid(total); v += gridDim.x) {
@@ -554,9 +556,16 @@ __global__ __launch_bounds__(mt::kThreads) void eval_kernel(const uint4 *__restr
             ok = (uint32_t)r < m;
             const uint32_t qi = ok ? lq[r] : 0;
             row = q + (uint64_t)qi * 32;
+            const uint32_t pq = ok ? qpop[qi] : 0, th = ok ? thrk[qi] : 0;
             s_qi[r] = qi;
-            s_pq[r] = ok ? qpop[qi] : 0;
-            s_th[r] = ok ? thrk[qi] : 0;
+            s_pq[r] = pq;
+            s_th[r] = th;
+            // K = |q|*wB + |t|*wA - C*(wA + wB) with |t| >= the block's smallest
+            // popcount: a row with C below cmin has K above the k-th key
+            const uint32_t wa = weight_a(pq), wb = weight_b(pq);
+            const int64_t X = (int64_t)pq * wb + (int64_t)(bpop ? bpop[2 * b] : 0) * wa - (int64_t)th;
+            const int64_t cmin = X <= 0 ? 0 : (X + wa + wb - 1) / (wa + wb);
+            s_cmin[r] = ok ? (float)cmin : 1e30f;
         } else {
             ok = r0 + (r - mt::MA) < n;
             row = ok ? sorted + (r0 + (r - mt::MA)) * 32 : sorted;
@@ -569,6 +578,10 @@ __global__ __launch_bounds__(mt::kThreads) void eval_kernel(const uint4 *__restr
 #pragma unroll
             for (int rr = 0; rr < 4; rr++) {
                 const uint32_t i = (uint32_t)mt::acc_arow(a, rr);
+                // most (query, row) pairs miss the k-th key by far: test this
+                // lane's 4 rows at once against the least useful overlap
+                const float mx = fmaxf(fmaxf(acc[a][0][rr], acc[a][1][rr]), fmaxf(acc[a][2][rr], acc[a][3][rr]));
+                if (mx < s_cmin[i]) continue;
                 if (i >= m) continue;
                 const uint32_t qi = s_qi[i];
                 const uint32_t pq = s_pq[i];
@@ -845,7 +858,7 @@ int knn_tree_blocked(qd_tree_t t, const uint64_t *d_q, uint32_t nq, uint32_t k, 
                 hipLaunchKernelGGL(eval_kernel, dim3((uint32_t)mt::tile_grid(mt::xcd_grid(h[2]))), dim3(mt::kThreads), 0,
                                    s, q4,
                                    reinterpret_cast<const uint4 *>(t->d_sorted), n, nblk, nqp, list, cnt, off,
-                                   t->d_pop, t->d_perm, qpop, thr, ccnt, cand);
+                                   t->d_pop, t->d_perm, qpop, thr, t->d_bpop, ccnt, cand);
             }
             if (h[3] > 0) {
                 KernelTimer timer("tree_block_eval_short", s);
