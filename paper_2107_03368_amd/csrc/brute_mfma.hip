@@ -42,6 +42,7 @@ __global__ __launch_bounds__(mt::kThreads) void scan_mfma_kernel(const uint4 *__
     __shared__ mt::Smem sm;
     __shared__ uint32_t s_pq[MQ], s_tp[MR];  // |q| of the tile's queries, |t| of its rows
     __shared__ u64 s_th[MQ];                 // the queries' candidate bounds
+    __shared__ float s_cmin[MQ];             // per query: the least overlap that can reach its bound
     const uint64_t n_tiles = (uint64_t)n_qtiles * ((n + MR - 1) / MR);
     for (uint64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
         // consecutive tiles share a row tile and spread over the XCDs, so every
@@ -56,8 +57,16 @@ __global__ __launch_bounds__(mt::kThreads) void scan_mfma_kernel(const uint4 *__
         if (r < MQ) {
             ok = q0 + r < nq;
             row = ok ? q + (uint64_t)(q0 + r) * 32 : q;
-            s_pq[r] = ok ? qpop[q0 + r] : 0;
-            s_th[r] = ok ? thr[q0 + r] : 0;
+            const uint32_t pq = ok ? qpop[q0 + r] : 0;
+            const u64 th = ok ? thr[q0 + r] : 0;
+            s_pq[r] = pq;
+            s_th[r] = th;
+            // K = |q|*wB + |t|*wA - C*(wA + wB) >= |q|*wB - C*(wA + wB): a row
+            // with C below cmin has K above the bound's key
+            const uint32_t wa = pq > 1 ? pq : 1, wb = (QD_BITS - pq) > 1 ? QD_BITS - pq : 1;
+            const int64_t X = (int64_t)pq * wb - (int64_t)(th >> 32);
+            const int64_t cmin = X <= 0 ? 0 : (X + wa + wb - 1) / (wa + wb);
+            s_cmin[r] = ok ? (float)cmin : 1e30f;
         } else {
             ok = t0 + (r - MQ) < n;
             row = ok ? db + (t0 + (r - MQ)) * 32 : db;
@@ -72,6 +81,9 @@ __global__ __launch_bounds__(mt::kThreads) void scan_mfma_kernel(const uint4 *__
 #pragma unroll
             for (int rr = 0; rr < 4; rr++) {
                 const int ai = mt::acc_arow(a, rr);
+                // test this lane's 4 rows of the query at once (most miss by far)
+                const float mx = fmaxf(fmaxf(acc[a][0][rr], acc[a][1][rr]), fmaxf(acc[a][2][rr], acc[a][3][rr]));
+                if (mx < s_cmin[ai]) continue;
                 const uint32_t qi = q0 + ai;
                 if (qi >= nq) continue;
                 const uint32_t pq = s_pq[ai];
