@@ -189,14 +189,18 @@ def main():
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / args.steps
         kernels = {}
-        for kname in ("wh_scan_mfma", "wh_scan_topk", "topk_merge", "topk_select", "tree_knn", "mlp_features",
-                      "mlp_forward", "tree_block_bounds", "tree_block_round1", "tree_block_lists", "tree_block_eval",
+        for kname in ("wh_scan_mfma", "wh_scan_mfma_sample", "wh_scan_topk", "topk_merge", "topk_select",
+                      "topk_select_sample", "tree_knn", "mlp_features", "mlp_forward", "tree_block_bounds",
+                      "tree_block_round1", "tree_block_lists", "tree_block_eval", "tree_block_eval_short",
                       "tree_block_select"):
             ms, cnt = qd.profile_read(kname)
             if cnt:
                 kernels[kname] = {"avg_ms": ms / cnt, "launches": cnt}
+        counters = {c: qd.profile_counter(c) / args.steps for c in ("tree_block_tiles", "tree_block_short_pairs")}
         qd.profile_enable(False)
         per_path[name] = {"ms": dt * 1e3, "queries_per_s": nq / dt, "kernels": kernels}
+        if name == "tree_blocked":
+            per_path[name]["per_call"] = counters
         if name.startswith("tree"):
             st = (qd.knn_tree(tree, qt, k, totals=True) if name == "tree" else
                   qd.knn_tree(tree, qt, k, order=qd.ORDER_BLOCKED, totals=True) if name == "tree_blocked" else
@@ -240,20 +244,23 @@ def main():
                 "avg_ms": ms}
 
     def blocked_roofline():
-        # eval_kernel: the (query, row) pairs of the matrix-core rounds (all evaluated
-        # rows minus round 1's, which run on the vector ALUs), 2 flop per bit pair
+        # eval_kernel: the (query, row) pairs of the matrix-core tiles (all evaluated
+        # rows minus round 1's and the short lists', which run on the vector ALUs),
+        # 2 flop per bit pair
         pb = per_path["tree_blocked"]
         ev = pb["kernels"]["tree_block_eval"]
         launches_per_call = ev["launches"] / args.steps
         rows_r1 = min(16, (n + 255) // 256) * 256
-        pairs = nq * (pb["per_query"]["dists_evaluated"] - rows_r1)
+        pairs = nq * (pb["per_query"]["dists_evaluated"] - rows_r1) - pb["per_call"]["tree_block_short_pairs"] * 256
         ops_per_launch = pairs * 4096 * 2 / launches_per_call
+        tiles = pb["per_call"]["tree_block_tiles"]
+        fill = pairs / (tiles * 256 * 256) if tiles else None
         achieved = ops_per_launch / (ev["avg_ms"] * 1e-3) / 1e12
         tr = TRAFFIC.get("eval_kernel") if TRAFFIC else None
         return {"kernel": "eval_kernel", "bound": "mfma", "achieved": achieved, "peak": FP4_PEAK_TFLOPS,
                 "unit": "TFLOP/s (fp4 MFMA)", "frac": achieved / FP4_PEAK_TFLOPS, "traffic": tr,
                 "avg_ms": ev["avg_ms"], "ops_per_launch": ops_per_launch,
-                "launches_per_call": launches_per_call}
+                "launches_per_call": launches_per_call, "tiles_per_call": tiles, "tile_fill": fill}
 
     roofline_scan = scan_roofline()
     roofline = blocked_roofline() if best == "tree_blocked" else roofline_scan

@@ -76,6 +76,11 @@ int qd_version(void);
  * if it never ran).  Process-wide; not meant for concurrent callers. */
 int qd_profile_enable(int on);
 int qd_profile_read(const char *kernel, double *total_ms, uint64_t *launches);
+/* Named work counters kept while profiling is on (cleared with the totals):
+ * "tree_block_tiles" = matrix-core tiles and "tree_block_short_pairs" =
+ * (query, block) pairs evaluated on the vector ALUs by the blocked search.
+ * *total = 0 for a counter that never counted. */
+int qd_profile_counter(const char *name, uint64_t *total);
 
 /* ---------------------------------------------------------------------------
  * Per-row popcount |t| (the sum over all bits of a descriptor, the column

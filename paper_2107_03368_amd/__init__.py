@@ -113,6 +113,16 @@ def profile_enable(on=True):
     _check(_lib.qd_profile_enable(1 if on else 0), "qd_profile_enable")
 
 
+_sig("qd_profile_counter", [ctypes.c_char_p, ctypes.POINTER(ctypes.c_uint64)])
+
+
+def profile_counter(name):
+    """A named work counter summed since profiling was enabled."""
+    v = ctypes.c_uint64()
+    _check(_lib.qd_profile_counter(name.encode(), ctypes.byref(v)), "qd_profile_counter")
+    return v.value
+
+
 def profile_read(kernel):
     """(total ms, launches) of a timed kernel since profiling was enabled."""
     ms = ctypes.c_double()

@@ -90,12 +90,35 @@ static void drain_pending() {
     g_pending.clear();
 }
 
+static std::vector<std::pair<std::string, uint64_t>> g_counters;
+
+void profile_count(const char *name, uint64_t amount) {
+    if (!g_prof_on) return;
+    std::lock_guard<std::mutex> lock(g_prof_mu);
+    for (auto &c : g_counters)
+        if (c.first == name) {
+            c.second += amount;
+            return;
+        }
+    g_counters.push_back({name, amount});
+}
+
 }  // namespace qd
+
+extern "C" int qd_profile_counter(const char *name, uint64_t *total) {
+    if (!name || !total) return qd::fail(QD_ERR_INVALID, "null pointer");
+    std::lock_guard<std::mutex> lock(qd::g_prof_mu);
+    *total = 0;
+    for (auto &c : qd::g_counters)
+        if (c.first == name) *total = c.second;
+    return QD_OK;
+}
 
 extern "C" int qd_profile_enable(int on) {
     std::lock_guard<std::mutex> lock(qd::g_prof_mu);
     qd::drain_pending();
     qd::g_totals.clear();
+    qd::g_counters.clear();
     qd::g_prof_on = on != 0;
     return QD_OK;
 }

@@ -7,7 +7,8 @@
 //
 // Selection: a first sequential search over a sample of the rows gives each
 // query an upper bound U_q on its k-th key (the sample's k-th key: those k
-// rows are candidates too).  The matrix pass keeps every (row, key) with
+// rows are candidates too); for a large sample that search runs on the
+// matrix cores as well, with its own smaller sample.  The matrix pass keeps every (row, key) with
 // key <= U_q in a per-query candidate buffer; the exact top k are all among
 // them.  A final kernel sorts each query's candidates and writes the
 // results; queries whose buffer overflowed are searched again by the
@@ -32,6 +33,7 @@ constexpr int kBlock = 256;
 constexpr int MQ = mt::MA;        // queries per block
 constexpr int MR = mt::MB;        // rows per block
 constexpr uint32_t kCap = 8192;   // candidate slots per query
+thread_local int g_sample_depth = 0;  // > 0 inside the search of a threshold sample
 
 __global__ __launch_bounds__(mt::kThreads) void scan_mfma_kernel(const uint4 *__restrict__ db, uint64_t n,
                                                                  const uint4 *__restrict__ q, uint32_t nq,
@@ -220,21 +222,24 @@ int knn_bruteforce_mfma(const uint64_t *d_db, uint64_t n, const uint64_t *d_q, u
     int rc = popcount_rows_launch(d_db, n, tpop, s);
     if (rc == QD_OK) rc = popcount_rows_launch(d_q, nq, qpop, s);
     if (rc != QD_OK) return done(rc);
-    // thresholds from the first `sample` rows
-    rc = knn_bruteforce_impl(d_db, sample, d_q, nq, k, sidx, smis, sext, sdist, stream, 16, 0);  // register-tiled scan
+    // thresholds from the first `sample` rows (large samples take this same
+    // path, with a sample of their own; its launches are timed apart)
+    ++g_sample_depth;
+    rc = knn_bruteforce_impl(d_db, sample, d_q, nq, k, sidx, smis, sext, sdist, stream, 0, 0);
+    --g_sample_depth;
     if (rc != QD_OK) return done(rc);
     hipLaunchKernelGGL(sample_threshold_kernel, dim3((nq + 255) / 256), dim3(256), 0, s, sidx, smis, sext, qpop, nq, k,
                        thr);
     if (hipMemsetAsync(cnt, 0, (size_t)nq * 4, s) != hipSuccess || hipMemsetAsync(n_redo, 0, 4, s) != hipSuccess)
         return done(fail(QD_ERR_DEVICE, "memset"));
     {
-        KernelTimer timer("wh_scan_mfma", s);
+        KernelTimer timer(g_sample_depth ? "wh_scan_mfma_sample" : "wh_scan_mfma", s);
         hipLaunchKernelGGL(scan_mfma_kernel, dim3((uint32_t)mt::tile_grid(n_qtiles * n_rtiles)), dim3(mt::kThreads), 0, s,
                            reinterpret_cast<const uint4 *>(d_db), n, reinterpret_cast<const uint4 *>(d_q), nq, tpop,
                            qpop, thr, n_qtiles, cnt, cand);
     }
     {
-        KernelTimer timer("topk_select", s);
+        KernelTimer timer(g_sample_depth ? "topk_select_sample" : "topk_select", s);
         hipLaunchKernelGGL(select_emit_kernel, dim3(nq), dim3(kBlock), 0, s, cnt, cand, k, d_q, d_db, d_idx, d_missed,
                            d_extra, d_dist, redo, n_redo);
     }

@@ -27,6 +27,8 @@ int device_cus();
 // profiling is on, a KernelTimer brackets one launch; durations are summed
 // per kernel name when read.
 bool profiling();
+// Adds to a named counter while profiling is on (read with qd_profile_counter).
+void profile_count(const char *name, uint64_t amount);
 class KernelTimer {
   public:
     KernelTimer(const char *name, hipStream_t s);

@@ -853,6 +853,8 @@ int knn_tree_blocked(qd_tree_t t, const uint64_t *d_q, uint32_t nq, uint32_t k, 
                 break;
             }
             if (hipMemsetAsync(ctr, 0, 4, s) != hipSuccess) return done(fail(QD_ERR_DEVICE, "memset"));
+            profile_count("tree_block_tiles", h[2]);
+            profile_count("tree_block_short_pairs", h[3]);
             if (h[2] > 0) {
                 KernelTimer timer("tree_block_eval", s);
                 hipLaunchKernelGGL(eval_kernel, dim3((uint32_t)mt::tile_grid(mt::xcd_grid(h[2]))), dim3(mt::kThreads), 0,
