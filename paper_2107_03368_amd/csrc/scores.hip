@@ -34,6 +34,18 @@ constexpr uint64_t kMinKBytes = 1ull << 30;    // minK of one batch
 constexpr uint64_t kMaxBatch = 1ull << 18;     // query descriptors per batch
 constexpr uint32_t kMaxObjects = 65536;        // object ids are uint16
 
+// Smallest of the 16 values of a row of lanes (every lane of the row gets it).
+__device__ __forceinline__ uint32_t min16(uint32_t v) {
+    uint32_t t = (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, false);  // quad_perm 1,0,3,2
+    v = t < v ? t : v;
+    t = (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x4E, 0xF, 0xF, false);  // quad_perm 2,3,0,1
+    v = t < v ? t : v;
+    t = (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x141, 0xF, 0xF, false);  // row_half_mirror
+    v = t < v ? t : v;
+    t = (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x140, 0xF, 0xF, false);  // row_mirror
+    return t < v ? t : v;
+}
+
 __global__ void fill_u32_kernel(uint32_t *p, uint64_t n, uint32_t v) {
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
         p[i] = v;
@@ -150,28 +162,32 @@ __global__ __launch_bounds__(mt::kThreads) void objscan_kernel(
         mt::v4f acc[8][4];
         mt::overlap_tile(row, !ok, sm, acc);  // its barriers also publish the metadata above
 
-        // this lane's 32 descriptors x 4 rows: smallest key per descriptor
+        // this lane's 32 descriptors x 4 rows: smallest key per descriptor.
+        // K = |q|*wB - (C*(wA + wB) - |t|*wA), so the smallest K is |q|*wB
+        // minus the largest C*(wA + wB) - |t|*wA; rows past the tile's end
+        // get |t| = 32767, which no real row's value can lose to.
+        int32_t tpv[4];
+#pragma unroll
+        for (int b = 0; b < 4; b++) {
+            const int bi = mt::acc_brow(b);
+            tpv[b] = (uint32_t)bi < nb ? (int32_t)s_tp[bi] : 32767;
+        }
 #pragma unroll
         for (int a = 0; a < 8; a++)
 #pragma unroll
             for (int rr = 0; rr < 4; rr++) {
                 const int ai = mt::acc_arow(a, rr);
                 const uint32_t pq = s_pq[ai];
-                const uint32_t wa = pq > 1 ? pq : 1, wb = (QD_BITS - pq) > 1 ? QD_BITS - pq : 1;
-                uint32_t m = kNoKey;
+                const int32_t wa = pq > 1 ? (int32_t)pq : 1, wb = (QD_BITS - pq) > 1 ? (int32_t)(QD_BITS - pq) : 1;
+                int32_t vmax = (int32_t)mt::count(acc[a][0][rr]) * (wa + wb) - tpv[0] * wa;
 #pragma unroll
-                for (int b = 0; b < 4; b++) {
-                    const int bi = mt::acc_brow(b);
-                    const uint32_t C = mt::count(acc[a][b][rr]);
-                    const uint32_t K = (pq - C) * wb + (s_tp[bi] - C) * wa;
-                    if ((uint32_t)bi < nb && K < m) m = K;
+                for (int b = 1; b < 4; b++) {
+                    const int32_t v = (int32_t)mt::count(acc[a][b][rr]) * (wa + wb) - tpv[b] * wa;
+                    vmax = v > vmax ? v : vmax;
                 }
-                // the 16 lanes of a lane group hold the same descriptors, 16 rows each
-#pragma unroll
-                for (int sh = 1; sh < 16; sh <<= 1) {
-                    const uint32_t v = (uint32_t)__shfl_xor((int)m, sh);
-                    m = v < m ? v : m;
-                }
+                uint32_t m = (uint32_t)((int32_t)pq * wb - vmax);
+                // the 16 lanes of a row hold the same descriptors, 16 rows each
+                m = min16(m);
                 if ((lane & 15) == 0) atomicMin(&s_min[ai], m);  // the 4 waves of this descriptor half
             }
         __syncthreads();
