@@ -475,8 +475,14 @@ __global__ __launch_bounds__(256) void eval_short_kernel(const uint4 *__restrict
                                                          u64 *__restrict__ cand) {
     const int lane = lane_id(), g = lane >> 3, j = lane & 7;
     const uint64_t total = voff[nblk];
-    const uint64_t nw = (uint64_t)gridDim.x * 4;
-    for (uint64_t i = readfirst(blockIdx.x * 4 + (threadIdx.x >> 6)); i < total; i += nw) {
+    const uint64_t groups = (total + 3) / 4;  // four consecutive pairs per workgroup
+    // workgroup v of the virtual grid runs on XCD v % 8 (gridDim.x is a multiple of 8): each XCD
+    // takes a contiguous range of pairs, so a block's rows are fetched into one L2
+    for (uint64_t v = blockIdx.x; v < mt::xcd_grid(groups); v += gridDim.x) {
+        uint64_t grp;
+        if (!mt::xcd_tile(v, groups, grp)) continue;
+        const uint64_t i = readfirst((uint32_t)(grp * 4 + (threadIdx.x >> 6)));
+        if (i >= total) continue;
         uint64_t lo = 0, hi = nblk;  // voff[lo] <= i < voff[hi]
         while (hi - lo > 1) {
             const uint64_t mid = (lo + hi) / 2;
@@ -864,8 +870,9 @@ int knn_tree_blocked(qd_tree_t t, const uint64_t *d_q, uint32_t nq, uint32_t k, 
             }
             if (h[3] > 0) {
                 KernelTimer timer("tree_block_eval_short", s);
-                const uint64_t waves = std::min<uint64_t>(h[3], (uint64_t)device_cus() * 32);
-                hipLaunchKernelGGL(eval_short_kernel, dim3((uint32_t)((waves + 3) / 4)), dim3(256), 0, s, q4,
+                const uint64_t groups = (h[3] + 3) / 4;
+                const uint64_t grid = mt::xcd_grid(std::min<uint64_t>(groups, (uint64_t)device_cus() * 8));
+                hipLaunchKernelGGL(eval_short_kernel, dim3((uint32_t)grid), dim3(256), 0, s, q4,
                                    reinterpret_cast<const uint4 *>(t->d_sorted), n, nblk, nqp, list, voff, t->d_pop,
                                    t->d_perm, qpop, thr, ccnt, cand);
             }
