@@ -63,10 +63,11 @@ constexpr int kGroup = 16;                 // blocks per wave when building the 
 constexpr uint32_t kInf = 0xFFFFFFFFu;
 constexpr uint32_t kLevels = QD_BITS + 1;  // A_lb in 0 .. 4096
 constexpr uint32_t kMaxBatch = 16384;      // queries per batch (list entries are 16-bit)
-// A block listed for fewer queries than this is evaluated on the vector ALUs,
-// one wave per (query, block) pair, instead of in a matrix-core tile that
-// costs the same for 1 or 256 listed queries (measured at 10M rows: 16, 24
-// and 32 within 1%, 48 2% and 96 7% slower).
+// A block list (or the rest of one past its full 256-query tiles) shorter
+// than this is evaluated on the vector ALUs, one wave per (query, block)
+// pair, instead of in a matrix-core tile that costs the same for 1 or 256
+// listed queries (measured at 10M rows: 16, 24 and 32 within 1%, 48 2% and
+// 96 7% slower).
 constexpr uint32_t kShortList = 24;
 
 // Position of block b of bound level L in the per-query block order; a round
@@ -415,10 +416,12 @@ __global__ __launch_bounds__(256) void list_kernel(const uint16_t *__restrict__ 
         for (uint32_t jj = 0; jj < nb; jj++) cnt[b0 + jj] = c[jj];
 }
 
-// Matrix-core tiles of a block listed for c queries (256 per tile; none for
-// a short list) and its (query, block) pairs for the vector ALUs.
-__device__ __forceinline__ uint32_t mfma_tiles(uint32_t c) { return c >= kShortList ? (c + mt::MA - 1) / mt::MA : 0; }
-__device__ __forceinline__ uint32_t short_pairs(uint32_t c) { return c >= kShortList ? 0 : c; }
+// A block listed for c queries: full tiles of 256 queries on the matrix
+// cores, the rest of the list as one more tile if it holds at least
+// kShortList queries, else as (query, block) pairs for the vector ALUs (the
+// last short_pairs(c) entries of the list).
+__device__ __forceinline__ uint32_t short_pairs(uint32_t c) { return c % mt::MA >= kShortList ? 0 : c % mt::MA; }
+__device__ __forceinline__ uint32_t mfma_tiles(uint32_t c) { return (c - short_pairs(c) + mt::MA - 1) / mt::MA; }
 
 // Exclusive prefixes over the blocks of the matrix-core tiles (off) and of
 // the short-list pairs (voff); off[nblk], voff[nblk], total[0] and total[1]
@@ -467,6 +470,7 @@ __global__ __launch_bounds__(1024) void tile_scan_kernel(const uint32_t *__restr
 __global__ __launch_bounds__(256) void eval_short_kernel(const uint4 *__restrict__ q, const uint4 *__restrict__ sorted,
                                                          uint64_t n, uint64_t nblk, uint32_t nqp,
                                                          const uint16_t *__restrict__ list,
+                                                         const uint32_t *__restrict__ cnt,
                                                          const uint32_t *__restrict__ voff,
                                                          const uint16_t *__restrict__ tpop,
                                                          const uint32_t *__restrict__ perm,
@@ -492,7 +496,8 @@ __global__ __launch_bounds__(256) void eval_short_kernel(const uint4 *__restrict
                 hi = mid;
         }
         const uint64_t b = lo;
-        const uint32_t qi = readfirst((uint32_t)list[b * nqp + (i - voff[b])]);
+        const uint32_t c = cnt[b];
+        const uint32_t qi = readfirst((uint32_t)list[b * nqp + (c - short_pairs(c)) + (i - voff[b])]);
         uint4 qv[4];
 #pragma unroll
         for (int ii = 0; ii < 4; ii++) qv[ii] = q[(uint64_t)qi * 32 + j + 8 * ii];
@@ -549,9 +554,9 @@ __global__ __launch_bounds__(mt::kThreads) void eval_kernel(const uint4 *__restr
             else
                 hi = mid;
         }
-        const uint64_t b = lo;  // a block with tiles has a list of at least kShortList queries
+        const uint64_t b = lo;
         const uint32_t t0 = (x - off[b]) * mt::MA;
-        const uint32_t left = cnt[b] - t0;
+        const uint32_t left = cnt[b] - short_pairs(cnt[b]) - t0;  // the list's short rest is not in a tile
         const uint32_t m = left < (uint32_t)mt::MA ? left : (uint32_t)mt::MA;
         const uint16_t *lq = list + b * nqp + t0;
         const uint64_t r0 = b * kBlk;
@@ -873,7 +878,7 @@ int knn_tree_blocked(qd_tree_t t, const uint64_t *d_q, uint32_t nq, uint32_t k, 
                 const uint64_t groups = (h[3] + 3) / 4;
                 const uint64_t grid = mt::xcd_grid(std::min<uint64_t>(groups, (uint64_t)device_cus() * 8));
                 hipLaunchKernelGGL(eval_short_kernel, dim3((uint32_t)grid), dim3(256), 0, s, q4,
-                                   reinterpret_cast<const uint4 *>(t->d_sorted), n, nblk, nqp, list, voff, t->d_pop,
+                                   reinterpret_cast<const uint4 *>(t->d_sorted), n, nblk, nqp, list, cnt, voff, t->d_pop,
                                    t->d_perm, qpop, thr, ccnt, cand);
             }
             {
