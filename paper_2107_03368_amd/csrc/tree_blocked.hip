@@ -59,7 +59,7 @@ constexpr uint32_t kM1 = 64;               // most blocks in round 1 (default 16
 constexpr int kRounds = 24;                // rounds 1 .. kRounds; the last takes every remaining block
 constexpr int kMaxPasses = 64;             // matrix-core passes (rounds and repeats) per batch
 constexpr uint32_t kCap = 8128;            // candidate slots per query per round (kCap + k <= 8192)
-constexpr int kGroup = 16;                 // blocks per wave when building the lists
+constexpr int kGroup = 8;                  // blocks per wave when building the lists (more waves hide the loads' latency)
 constexpr uint32_t kInf = 0xFFFFFFFFu;
 constexpr uint32_t kLevels = QD_BITS + 1;  // A_lb in 0 .. 4096
 constexpr uint32_t kMaxBatch = 16384;      // queries per batch (list entries are 16-bit)
