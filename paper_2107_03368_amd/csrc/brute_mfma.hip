@@ -67,7 +67,7 @@ __global__ __launch_bounds__(mt::kThreads) void scan_mfma_kernel(const uint4 *__
             // with C below cmin has K above the bound's key
             const uint32_t wa = pq > 1 ? pq : 1, wb = (QD_BITS - pq) > 1 ? QD_BITS - pq : 1;
             const int64_t X = (int64_t)pq * wb - (int64_t)(th >> 32);
-            const int64_t cmin = X <= 0 ? 0 : (X + wa + wb - 1) / (wa + wb);
+            const uint32_t cmin = X <= 0 ? 0u : ((uint32_t)X + wa + wb - 1) / (wa + wb);  // 0 < X < 2^24
             s_cmin[r] = ok ? (float)cmin : 1e30f;
         } else {
             ok = t0 + (r - MQ) < n;

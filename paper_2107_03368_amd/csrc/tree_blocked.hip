@@ -575,7 +575,7 @@ __global__ __launch_bounds__(mt::kThreads) void eval_kernel(const uint4 *__restr
             // popcount: a row with C below cmin has K above the k-th key
             const uint32_t wa = weight_a(pq), wb = weight_b(pq);
             const int64_t X = (int64_t)pq * wb + (int64_t)(bpop ? bpop[2 * b] : 0) * wa - (int64_t)th;
-            const int64_t cmin = X <= 0 ? 0 : (X + wa + wb - 1) / (wa + wb);
+            const uint32_t cmin = X <= 0 ? 0u : ((uint32_t)X + wa + wb - 1) / (wa + wb);  // 0 < X < 2^26
             s_cmin[r] = ok ? (float)cmin : 1e30f;
         } else {
             ok = r0 + (r - mt::MA) < n;

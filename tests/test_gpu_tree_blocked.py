@@ -161,3 +161,22 @@ def test_blocked_popcount_range_and_plain_bound(qd, k):
     _same(pop, ref)
     _same(plain, ref)
     assert pop[4].cpu().numpy()[:, 0].sum() <= 1.01 * plain[4].cpu().numpy()[:, 0].sum()
+
+
+def test_blocked_work_counters(qd):
+    # while profiling, the search counts its matrix-core tiles and the
+    # (query, block) pairs of short lists it ran on the vector ALUs
+    db = synth.gen_db(60_123, 1101)
+    q, _ = synth.gen_queries(db, 600, 2101, 0.1, 0.6)
+    tree = qd.tree_build(_t(db))
+    qd.profile_enable(True)
+    res = qd.knn_tree(tree, _t(q), 10, order=qd.ORDER_BLOCKED, query_stats=True)
+    tiles, short = qd.profile_counter("tree_block_tiles"), qd.profile_counter("tree_block_short_pairs")
+    qd.profile_enable(False)
+    _same(res, oracle.knn_brute(db, q, 10))
+    listed = int(res[4].cpu().numpy()[:, 0].astype(np.int64).sum()) - 16 * len(q)  # past round 1
+    assert tiles > 0 and short > 0
+    assert short <= listed <= short + 256 * tiles
+    qd.profile_enable(True)  # counters start again from zero
+    assert qd.profile_counter("tree_block_tiles") == 0
+    qd.profile_enable(False)
