@@ -60,6 +60,7 @@ constexpr int kRounds = 24;                // rounds 1 .. kRounds; the last take
 constexpr int kMaxPasses = 64;             // matrix-core passes (rounds and repeats) per batch
 constexpr uint32_t kCap = 8128;            // candidate slots per query per round (kCap + k <= 8192)
 constexpr int kGroup = 8;                  // blocks per wave when building the lists (more waves hide the loads' latency)
+static_assert(32 % kGroup == 0, "a wave's blocks share one word of done bits");
 constexpr uint32_t kInf = 0xFFFFFFFFu;
 constexpr uint32_t kLevels = QD_BITS + 1;  // A_lb in 0 .. 4096
 constexpr uint32_t kMaxBatch = 16384;      // queries per batch (list entries are 16-bit)
@@ -79,6 +80,14 @@ __device__ __forceinline__ u64 cap_key(uint32_t K, uint32_t wb) {
 }
 
 __device__ __forceinline__ uint32_t weight_a(uint32_t pq) { return pq > 1 ? pq : 1; }
+
+// The keys a query running round r may evaluate early, to fill a tile of
+// round r: those of round r + 1, (c[r], min(c[r+1], cap)]; none after the
+// last round.  Stored as (lo, hi) with hi <= lo meaning none.
+__device__ __forceinline__ void set_fill_range(u64 *fr, const u64 *c, uint32_t r, u64 cap) {
+    fr[0] = r < (uint32_t)kRounds ? c[r] : 0;
+    fr[1] = r < (uint32_t)kRounds ? (c[r + 1] < cap ? c[r + 1] : cap) : 0;
+}
 __device__ __forceinline__ uint32_t weight_b(uint32_t pq) { return (QD_BITS - pq) > 1 ? QD_BITS - pq : 1; }
 
 __device__ __forceinline__ uint32_t lanes_below(u64 mask) {
@@ -304,8 +313,8 @@ __global__ __launch_bounds__(256) void round1_kernel(const uint4 *__restrict__ q
                                                      const u64 *__restrict__ cuts, const uint16_t *__restrict__ qpop,
                                                      u64 *__restrict__ top, uint32_t *__restrict__ ntop,
                                                      uint32_t *__restrict__ thrk, u64 *__restrict__ rec,
-                                                     uint32_t *__restrict__ qround, uint32_t *__restrict__ counters,
-                                                     uint32_t *__restrict__ qst) {
+                                                     u64 *__restrict__ frange, uint32_t *__restrict__ qround,
+                                                     uint32_t *__restrict__ counters, uint32_t *__restrict__ qst) {
     const int lane = lane_id();
     const uint32_t qi = readfirst(blockIdx.x * 4 + (threadIdx.x >> 6));
     if (qi >= nqb) return;
@@ -358,6 +367,7 @@ __global__ __launch_bounds__(256) void round1_kernel(const uint4 *__restrict__ q
         const bool active = hi > lo;
         rec[2 * qi] = lo;
         rec[2 * qi + 1] = active ? hi : 0;
+        set_fill_range(frange + 2 * qi, c, 2, cap);
         qround[qi] = 2;
         if (active) atomicAdd(&counters[0], 1u);
         if (qst) {
@@ -371,25 +381,42 @@ __global__ __launch_bounds__(256) void round1_kernel(const uint4 *__restrict__ q
 
 // Per-block query lists for one round: wave w of block x handles the
 // kGroup blocks starting at (4x + w) * kGroup and walks the queries in order.
+// A query is listed for a block whose key lies in its range of this round,
+// unless an earlier round already evaluated the pair (done bit).  The same
+// walk collects, per block, up to 255 queries whose next round covers the
+// block (fill range); the first of them fill the free query slots of the
+// block's last tile and are marked done, so the next round skips them.
+// Filling uses the tile the round runs anyway; such a pair is evaluated once,
+// against a k-th key at least as large as the next round's, so no row is lost.
 __global__ __launch_bounds__(256) void list_kernel(const uint16_t *__restrict__ lbb, uint64_t nblk, uint64_t n,
                                                    uint32_t nqb, uint32_t nqp, const u64 *__restrict__ rec,
-                                                   uint16_t *__restrict__ list, uint32_t *__restrict__ cnt,
-                                                   uint32_t *__restrict__ qst) {
+                                                   const u64 *__restrict__ frange, uint32_t *__restrict__ done,
+                                                   uint64_t dw, uint16_t *__restrict__ list,
+                                                   uint32_t *__restrict__ cnt, uint32_t *__restrict__ qst) {
+    __shared__ uint16_t s_fill[4][kGroup][mt::MA - 1];  // per wave and block: fill candidates
     const int lane = lane_id();
+    uint16_t(*fillq)[mt::MA - 1] = s_fill[threadIdx.x >> 6];
     const uint64_t b0 = ((uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * kGroup;
     if (b0 >= nblk) return;
     const uint32_t nb = readfirst((uint32_t)(nblk - b0 < (uint64_t)kGroup ? nblk - b0 : kGroup));
-    uint32_t c[kGroup];
+    const uint64_t dword = b0 / 32;  // the group's done bits share one word
+    const uint32_t dshift = (uint32_t)(b0 % 32);
+    uint32_t c[kGroup], f[kGroup];
 #pragma unroll
-    for (int jj = 0; jj < kGroup; jj++) c[jj] = 0;
+    for (int jj = 0; jj < kGroup; jj++) c[jj] = f[jj] = 0;
     for (uint32_t q0 = 0; q0 < nqb; q0 += 64) {
         const uint32_t qi = q0 + (uint32_t)lane;
-        u64 lo = 0, hi = 0;
+        u64 lo = 0, hi = 0, flo = 0, fhi = 0;
         if (qi < nqb) {
             lo = rec[2 * qi];
             hi = rec[2 * qi + 1];
+            if (hi > lo) {  // only a query running this round has its candidates merged
+                flo = frange[2 * qi];
+                fhi = frange[2 * qi + 1];
+            }
         }
         if (ballot(hi > lo) == 0) continue;
+        const uint32_t dbits = hi > lo ? done[(uint64_t)qi * dw + dword] >> dshift : 0;
         uint32_t mb = 0, mr = 0;
 #pragma unroll
         for (int jj = 0; jj < kGroup; jj++) {
@@ -397,13 +424,22 @@ __global__ __launch_bounds__(256) void list_kernel(const uint16_t *__restrict__ 
                 const uint64_t b = b0 + jj;
                 const uint32_t lv = lbb[b * nqp + qi];
                 const u64 key = range_key(lv, (uint32_t)b);
-                const bool m = key > lo && key <= hi;
+                const bool d = (dbits >> jj) & 1u;
+                const bool m = key > lo && key <= hi && !d;
                 const u64 mask = ballot(m);
                 if (m) list[b * nqp + c[jj] + lanes_below(mask)] = (uint16_t)qi;
                 c[jj] += (uint32_t)__popcll(mask);
                 if (m) {
                     mb++;
-                    mr += (uint32_t)(n - b * kBlk < kBlk ? n - b * kBlk : kBlk);
+                    mr += b + 1 < nblk ? (uint32_t)kBlk : (uint32_t)(n - b * kBlk);
+                }
+                if (f[jj] < mt::MA - 1) {  // fill candidates, in query order
+                    const bool mf = key > flo && key <= fhi && !d;
+                    const u64 fmask = ballot(mf);
+                    const uint32_t at = f[jj] + lanes_below(fmask);
+                    if (mf && at < mt::MA - 1) fillq[jj][at] = (uint16_t)qi;
+                    const uint32_t t = f[jj] + (uint32_t)__popcll(fmask);
+                    f[jj] = t < mt::MA - 1 ? t : mt::MA - 1;
                 }
             }
         }
@@ -412,8 +448,22 @@ __global__ __launch_bounds__(256) void list_kernel(const uint16_t *__restrict__ 
             atomicAdd(&qst[(uint64_t)qi * 4 + 3], mr);
         }
     }
-    if (lane == 0)
-        for (uint32_t jj = 0; jj < nb; jj++) cnt[b0 + jj] = c[jj];
+    // the first candidates fill the last tile's free slots
+    for (uint32_t jj = 0; jj < nb; jj++) {
+        const uint64_t b = b0 + jj;
+        const uint32_t free_slots = c[jj] % mt::MA ? mt::MA - c[jj] % mt::MA : 0;
+        const uint32_t take = f[jj] < free_slots ? f[jj] : free_slots;
+        for (uint32_t i = (uint32_t)lane; i < take; i += 64) {
+            const uint32_t qi = fillq[jj][i];  // written by this wave above (LDS keeps its order)
+            list[b * nqp + c[jj] + i] = (uint16_t)qi;
+            atomicOr(&done[(uint64_t)qi * dw + dword], 1u << (dshift + jj));
+            if (qst) {
+                atomicAdd(&qst[(uint64_t)qi * 4 + 0], 1u);
+                atomicAdd(&qst[(uint64_t)qi * 4 + 3], b + 1 < nblk ? (uint32_t)kBlk : (uint32_t)(n - b * kBlk));
+            }
+        }
+        if (lane == 0) cnt[b] = c[jj] + take;
+    }
 }
 
 // A block listed for c queries: full tiles of 256 queries on the matrix
@@ -620,14 +670,18 @@ __global__ __launch_bounds__(mt::kThreads) void eval_kernel(const uint4 *__restr
 // overflowed the buffer repeats the round: the k best of the candidates it
 // did store (real rows, as is its top k) bound its final k-th key, so the
 // repeat keeps fewer rows; when that bound does not tighten the key, the
-// query goes to the per-query fallback.  One block per query.
+// query goes to the per-query fallback.  Either way the next-round pairs
+// filled into this round are forgotten (their done bits cleared).  One block
+// per query.
 __global__ __launch_bounds__(256) void select_kernel(uint32_t k, const uint16_t *__restrict__ qpop,
                                                      const u64 *__restrict__ cuts, u64 *__restrict__ rec,
                                                      uint32_t *__restrict__ qround, uint32_t *__restrict__ ccnt,
                                                      const u64 *__restrict__ cand, u64 *__restrict__ top,
                                                      uint32_t *__restrict__ ntop, uint32_t *__restrict__ thrk,
                                                      uint32_t *__restrict__ counters, uint32_t *__restrict__ redo,
-                                                     uint32_t *__restrict__ qst) {
+                                                     uint32_t *__restrict__ qst, const uint16_t *__restrict__ lbq,
+                                                     uint64_t nblk, uint32_t *__restrict__ done, uint64_t dw,
+                                                     u64 *__restrict__ frange) {
     __shared__ u64 keys[8192];
     const uint32_t qi = blockIdx.x;
     const u64 lo = rec[2 * qi], hi = rec[2 * qi + 1];
@@ -652,6 +706,19 @@ __global__ __launch_bounds__(256) void select_kernel(uint32_t k, const uint16_t 
             for (uint32_t i = threadIdx.x; i < have; i += 256) top[(uint64_t)qi * k + i] = keys[i];
         }
     }
+    if (over) {
+        // the pairs this round filled in from the next one lost candidates too:
+        // clear their done bits (keys past this round's end), so they are listed again
+        const u64 end = cuts[(uint64_t)qi * (kRounds + 1) + qround[qi]];
+        for (uint64_t wd = threadIdx.x; wd < dw; wd += 256) {
+            uint32_t clear = 0;
+            for (uint32_t j = 0; j < 32; j++) {
+                const uint64_t b = wd * 32 + j;
+                if (b < nblk && range_key(lbq[(uint64_t)qi * nblk + b], (uint32_t)b) > end) clear |= 1u << j;
+            }
+            done[(uint64_t)qi * dw + wd] &= ~clear;
+        }
+    }
     if (threadIdx.x != 0) return;
     ccnt[qi] = 0;
     if (qst) qst[(uint64_t)qi * 4 + 1] += 1;
@@ -664,6 +731,7 @@ __global__ __launch_bounds__(256) void select_kernel(uint32_t k, const uint16_t 
         if (th_new < th && nhi > lo) {  // repeat round r with the tighter key
             thrk[qi] = th_new;
             rec[2 * qi + 1] = nhi;
+            set_fill_range(frange + 2 * qi, c, r, cap);
             atomicAdd(&counters[0], 1u);
         } else {
             redo[atomicAdd(&counters[1], 1u)] = qi;
@@ -675,14 +743,13 @@ __global__ __launch_bounds__(256) void select_kernel(uint32_t k, const uint16_t 
     thrk[qi] = th_new;
     qround[qi] = r + 1;
     const u64 nlo = c[r];
+    const u64 cap = cap_key(th_new, wb);
     u64 nhi = 0;
-    if (r < (uint32_t)kRounds) {
-        const u64 cap = cap_key(th_new, wb);
-        nhi = c[r + 1] < cap ? c[r + 1] : cap;
-    }
+    if (r < (uint32_t)kRounds) nhi = c[r + 1] < cap ? c[r + 1] : cap;
     const bool active = nhi > nlo;
     rec[2 * qi] = nlo;
     rec[2 * qi + 1] = active ? nhi : 0;
+    set_fill_range(frange + 2 * qi, c, r + 1, cap);
     if (active) atomicAdd(&counters[0], 1u);
 }
 
@@ -781,7 +848,9 @@ int knn_tree_blocked(qd_tree_t t, const uint64_t *d_q, uint32_t nq, uint32_t k, 
     if (h_stats) *h_stats = qd_stats{0, 0, 0, 0};
     // batch: up to kMaxBatch queries, bound and list matrices within about 12 GiB
     uint32_t qb = nq < kMaxBatch ? nq : kMaxBatch;
-    auto batch_bytes = [&](uint32_t b) { return (uint64_t)up256(b) * (nblk * 6 + kCap * 8 + (uint64_t)k * 8 + 512); };
+    auto batch_bytes = [&](uint32_t b) {
+        return (uint64_t)up256(b) * (nblk * 6 + (nblk + 31) / 32 * 4 + kCap * 8 + (uint64_t)k * 8 + 512);
+    };
     while (qb > 256 && batch_bytes(qb) > (12ull << 30)) qb = (qb + 1) / 2;
     const size_t P = up256(qb);
     // workspace
@@ -795,7 +864,8 @@ int knn_tree_blocked(qd_tree_t t, const uint64_t *d_q, uint32_t nq, uint32_t k, 
                  a_list = take(P * nblk * 2), a_cuts = take(P * (kRounds + 1) * 8), a_r1 = take(P * kM1 * 4),
                  a_rec = take(P * 16), a_thr = take(P * 4), a_ntop = take(P * 4), a_top = take(P * k * 8),
                  a_ccnt = take(P * 4), a_cand = take(P * kCap * 8), a_cnt = take(nblk * 4), a_qr = take(P * 4),
-                 a_off = take((nblk + 1) * 4), a_voff = take((nblk + 1) * 4), a_ctr = take(16), a_redo = take(P * 4), a_qst = take(P * 16),
+                 a_off = take((nblk + 1) * 4), a_voff = take((nblk + 1) * 4), a_ctr = take(16),
+                 a_done = take(P * ((nblk + 31) / 32) * 4), a_fr = take(P * 16), a_redo = take(P * 4), a_qst = take(P * 16),
                  a_gst = take(32);
     char *ws = nullptr;
     QD_HIP_CHECK(hipMallocAsync((void **)&ws, o, s));
@@ -805,9 +875,10 @@ int knn_tree_blocked(qd_tree_t t, const uint64_t *d_q, uint32_t nq, uint32_t k, 
         *cand = (u64 *)(ws + a_cand);
     uint32_t *r1list = (uint32_t *)(ws + a_r1), *thr = (uint32_t *)(ws + a_thr), *ntop = (uint32_t *)(ws + a_ntop),
              *ccnt = (uint32_t *)(ws + a_ccnt), *cnt = (uint32_t *)(ws + a_cnt), *off = (uint32_t *)(ws + a_off),
-             *voff = (uint32_t *)(ws + a_voff), *ctr = (uint32_t *)(ws + a_ctr), *redo = (uint32_t *)(ws + a_redo), *qst = (uint32_t *)(ws + a_qst),
+             *voff = (uint32_t *)(ws + a_voff), *ctr = (uint32_t *)(ws + a_ctr), *donebits = (uint32_t *)(ws + a_done), *redo = (uint32_t *)(ws + a_redo), *qst = (uint32_t *)(ws + a_qst),
              *qround = (uint32_t *)(ws + a_qr);
     unsigned long long *gst = (unsigned long long *)(ws + a_gst);
+    u64 *frange = (u64 *)(ws + a_fr);
     const bool want_stats = d_qstats || h_stats;
     int rc = QD_OK;
     auto done = [&](int code) {
@@ -822,7 +893,9 @@ int knn_tree_blocked(qd_tree_t t, const uint64_t *d_q, uint32_t nq, uint32_t k, 
         const uint4 *q4 = reinterpret_cast<const uint4 *>(qq);
         rc = popcount_rows_launch(qq, nqb, qpop, s);
         if (rc != QD_OK) return done(rc);
-        if (hipMemsetAsync(ccnt, 0, (size_t)nqb * 4, s) != hipSuccess || hipMemsetAsync(ctr, 0, 16, s) != hipSuccess)
+        const uint64_t dw = (nblk + 31) / 32;  // done-bit words per query
+        if (hipMemsetAsync(ccnt, 0, (size_t)nqb * 4, s) != hipSuccess || hipMemsetAsync(ctr, 0, 16, s) != hipSuccess ||
+            hipMemsetAsync(donebits, 0, (size_t)nqb * dw * 4, s) != hipSuccess)
             return done(fail(QD_ERR_DEVICE, "memset"));
         const uint32_t n_qtiles = nqp / mt::MA;
         const uint64_t n_btiles = (nblk + mt::MB - 1) / mt::MB;
@@ -843,7 +916,7 @@ int knn_tree_blocked(qd_tree_t t, const uint64_t *d_q, uint32_t nq, uint32_t k, 
             KernelTimer timer("tree_block_round1", s);
             hipLaunchKernelGGL(round1_kernel, dim3((nqb + 3) / 4), dim3(256), 0, s, q4, nqb, k,
                                reinterpret_cast<const uint4 *>(t->d_sorted), t->d_pop, t->d_perm, n, nblk, r1list, n1,
-                               cuts, qpop, top, ntop, thr, rec, qround, ctr, want_stats ? qst : nullptr);
+                               cuts, qpop, top, ntop, thr, rec, frange, qround, ctr, want_stats ? qst : nullptr);
         }
         if (hipGetLastError() != hipSuccess) return done(fail(QD_ERR_DEVICE, "blocked search: launch failed"));
         for (int pass = 0;; pass++) {
@@ -851,7 +924,7 @@ int knn_tree_blocked(qd_tree_t t, const uint64_t *d_q, uint32_t nq, uint32_t k, 
                 KernelTimer timer("tree_block_lists", s);
                 const uint64_t waves = (nblk + kGroup - 1) / kGroup;
                 hipLaunchKernelGGL(list_kernel, dim3((uint32_t)((waves + 3) / 4)), dim3(256), 0, s, lbb, nblk, n, nqb,
-                                   nqp, rec, list, cnt, want_stats ? qst : nullptr);
+                                   nqp, rec, frange, donebits, dw, list, cnt, want_stats ? qst : nullptr);
                 hipLaunchKernelGGL(tile_scan_kernel, dim3(1), dim3(1024), 0, s, cnt, nblk, off, voff, ctr + 2);
             }
             uint32_t h[4];
@@ -884,7 +957,8 @@ int knn_tree_blocked(qd_tree_t t, const uint64_t *d_q, uint32_t nq, uint32_t k, 
             {
                 KernelTimer timer("tree_block_select", s);
                 hipLaunchKernelGGL(select_kernel, dim3(nqb), dim3(256), 0, s, k, qpop, cuts, rec, qround, ccnt, cand,
-                                   top, ntop, thr, ctr, redo, want_stats ? qst : nullptr);
+                                   top, ntop, thr, ctr, redo, want_stats ? qst : nullptr, lbq, nblk, donebits, dw,
+                                   frange);
             }
             if (hipGetLastError() != hipSuccess) return done(fail(QD_ERR_DEVICE, "blocked search: launch failed"));
         }
