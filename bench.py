@@ -191,7 +191,7 @@ def main():
         kernels = {}
         for kname in ("wh_scan_mfma", "wh_scan_mfma_sample", "wh_scan_topk", "topk_merge", "topk_select",
                       "topk_select_sample", "tree_knn", "mlp_features", "mlp_forward", "tree_block_bounds",
-                      "tree_block_round1", "tree_block_lists", "tree_block_eval", "tree_block_eval_short",
+                      "tree_block_plan", "tree_block_round1", "tree_block_lists", "tree_block_eval", "tree_block_eval_short",
                       "tree_block_select"):
             ms, cnt = qd.profile_read(kname)
             if cnt:

@@ -249,22 +249,32 @@ __global__ __launch_bounds__(256) void plan_kernel(const uint16_t *__restrict__ 
     const uint32_t before = L1 ? cum[L1 - 1] : 0;
     const uint32_t r1 = T1 - before, at_level = cum[L1] - before;
     // one wave walks the blocks in order (coalesced), listing round 1's blocks
-    // and finding the last block of level L1 it takes
+    // and finding the last block of level L1 it takes; the levels of 8 steps
+    // are loaded at once, so their latencies overlap
     if (tid < 64) {
         const int lane = (int)tid;
         uint32_t pos = 0, eq_seen = 0;
-        for (uint64_t base = 0; base < nblk; base += 64) {
-            const uint64_t b = base + lane;
-            const uint32_t v = b < nblk ? row[b] : 0xFFFFu;
-            const bool eq = v == L1;
-            const u64 meq = ballot(eq);
-            const uint32_t rank = eq_seen + lanes_below(meq);
-            const bool in = v < L1 || (eq && rank < r1);
-            if (eq && rank + 1 == r1 && r1 < at_level) s_bcut = (uint32_t)b;
-            const u64 min_ = ballot(in);
-            if (in) r1list[(uint64_t)qi * kM1 + pos + lanes_below(min_)] = (uint32_t)b;
-            pos += (uint32_t)__popcll(min_);
-            eq_seen += (uint32_t)__popcll(meq);
+        for (uint64_t base = 0; base < nblk; base += 512) {
+            uint32_t vs[8];
+#pragma unroll
+            for (int i = 0; i < 8; i++) {
+                const uint64_t b = base + 64 * i + lane;
+                vs[i] = b < nblk ? row[b] : 0xFFFFu;
+            }
+#pragma unroll
+            for (int i = 0; i < 8; i++) {
+                const uint64_t b = base + 64 * i + lane;
+                const uint32_t v = vs[i];
+                const bool eq = v == L1;
+                const u64 meq = ballot(eq);
+                const uint32_t rank = eq_seen + lanes_below(meq);
+                const bool in = v < L1 || (eq && rank < r1);
+                if (eq && rank + 1 == r1 && r1 < at_level) s_bcut = (uint32_t)b;
+                const u64 min_ = ballot(in);
+                if (in) r1list[(uint64_t)qi * kM1 + pos + lanes_below(min_)] = (uint32_t)b;
+                pos += (uint32_t)__popcll(min_);
+                eq_seen += (uint32_t)__popcll(meq);
+            }
         }
     }
     __syncthreads();
@@ -910,7 +920,10 @@ int knn_tree_blocked(qd_tree_t t, const uint64_t *d_q, uint32_t nq, uint32_t k, 
         // holds ~128 queries on average
         uint64_t t2 = p && p->round2_blocks ? p->round2_blocks : (128 * nblk + nqb - 1) / nqb;
         if (t2 < 2 * (uint64_t)m1) t2 = 2 * (uint64_t)m1;
-        hipLaunchKernelGGL(plan_kernel, dim3(nqb), dim3(256), 0, s, lbq, nblk, m1, t2, growth, cuts, r1list);
+        {
+            KernelTimer timer("tree_block_plan", s);
+            hipLaunchKernelGGL(plan_kernel, dim3(nqb), dim3(256), 0, s, lbq, nblk, m1, t2, growth, cuts, r1list);
+        }
         const uint32_t n1 = (uint32_t)(nblk < m1 ? nblk : m1);
         {
             KernelTimer timer("tree_block_round1", s);
