@@ -485,9 +485,10 @@ __device__ __forceinline__ uint32_t mfma_tiles(uint32_t c) { return (c - short_p
 
 // Exclusive prefixes over the blocks of the matrix-core tiles (off) and of
 // the short-list pairs (voff); off[nblk], voff[nblk], total[0] and total[1]
-// receive the sums.
+// receive the sums; tile_blk[x] = the block of tile x.
 __global__ __launch_bounds__(1024) void tile_scan_kernel(const uint32_t *__restrict__ cnt, uint64_t nblk,
                                                          uint32_t *__restrict__ off, uint32_t *__restrict__ voff,
+                                                         uint32_t *__restrict__ tile_blk,
                                                          uint32_t *__restrict__ total) {
     __shared__ uint32_t part[1024], vpart[1024];
     const uint32_t tid = threadIdx.x;
@@ -513,7 +514,9 @@ __global__ __launch_bounds__(1024) void tile_scan_kernel(const uint32_t *__restr
     for (uint64_t b = c0; b < c1; b++) {
         off[b] = run;
         voff[b] = vrun;
-        run += mfma_tiles(cnt[b]);
+        const uint32_t nt = mfma_tiles(cnt[b]);
+        for (uint32_t i = 0; i < nt; i++) tile_blk[run + i] = (uint32_t)b;
+        run += nt;
         vrun += short_pairs(cnt[b]);
     }
     if (tid == 1023) {
@@ -591,6 +594,7 @@ __global__ __launch_bounds__(mt::kThreads) void eval_kernel(const uint4 *__restr
                                                             const uint16_t *__restrict__ list,
                                                             const uint32_t *__restrict__ cnt,
                                                             const uint32_t *__restrict__ off,
+                                                            const uint32_t *__restrict__ tile_blk,
                                                             const uint16_t *__restrict__ tpop,
                                                             const uint32_t *__restrict__ perm,
                                                             const uint16_t *__restrict__ qpop,
@@ -606,15 +610,7 @@ __global__ __launch_bounds__(mt::kThreads) void eval_kernel(const uint4 *__restr
         uint64_t xt;
         if (!mt::xcd_tile(v, total, xt)) continue;
         const uint32_t x = (uint32_t)xt;  // tiles of one block are consecutive
-        uint64_t lo = 0, hi = nblk;  // off[lo] <= x < off[hi]
-        while (hi - lo > 1) {
-            const uint64_t mid = (lo + hi) / 2;
-            if (off[mid] <= x)
-                lo = mid;
-            else
-                hi = mid;
-        }
-        const uint64_t b = lo;
+        const uint64_t b = tile_blk[x];
         const uint32_t t0 = (x - off[b]) * mt::MA;
         const uint32_t left = cnt[b] - short_pairs(cnt[b]) - t0;  // the list's short rest is not in a tile
         const uint32_t m = left < (uint32_t)mt::MA ? left : (uint32_t)mt::MA;
@@ -875,7 +871,9 @@ int knn_tree_blocked(qd_tree_t t, const uint64_t *d_q, uint32_t nq, uint32_t k, 
                  a_rec = take(P * 16), a_thr = take(P * 4), a_ntop = take(P * 4), a_top = take(P * k * 8),
                  a_ccnt = take(P * 4), a_cand = take(P * kCap * 8), a_cnt = take(nblk * 4), a_qr = take(P * 4),
                  a_off = take((nblk + 1) * 4), a_voff = take((nblk + 1) * 4), a_ctr = take(16),
-                 a_done = take(P * ((nblk + 31) / 32) * 4), a_fr = take(P * 16), a_redo = take(P * 4), a_qst = take(P * 16),
+                 a_done = take(P * ((nblk + 31) / 32) * 4), a_fr = take(P * 16),
+                 a_tblk = take(nblk * (P / mt::MA) * 4),  // tiles: at most ceil(nqb / 256) per block
+                 a_redo = take(P * 4), a_qst = take(P * 16),
                  a_gst = take(32);
     char *ws = nullptr;
     QD_HIP_CHECK(hipMallocAsync((void **)&ws, o, s));
@@ -889,6 +887,7 @@ int knn_tree_blocked(qd_tree_t t, const uint64_t *d_q, uint32_t nq, uint32_t k, 
              *qround = (uint32_t *)(ws + a_qr);
     unsigned long long *gst = (unsigned long long *)(ws + a_gst);
     u64 *frange = (u64 *)(ws + a_fr);
+    uint32_t *tile_blk = (uint32_t *)(ws + a_tblk);
     const bool want_stats = d_qstats || h_stats;
     int rc = QD_OK;
     auto done = [&](int code) {
@@ -938,7 +937,7 @@ int knn_tree_blocked(qd_tree_t t, const uint64_t *d_q, uint32_t nq, uint32_t k, 
                 const uint64_t waves = (nblk + kGroup - 1) / kGroup;
                 hipLaunchKernelGGL(list_kernel, dim3((uint32_t)((waves + 3) / 4)), dim3(256), 0, s, lbb, nblk, n, nqb,
                                    nqp, rec, frange, donebits, dw, list, cnt, want_stats ? qst : nullptr);
-                hipLaunchKernelGGL(tile_scan_kernel, dim3(1), dim3(1024), 0, s, cnt, nblk, off, voff, ctr + 2);
+                hipLaunchKernelGGL(tile_scan_kernel, dim3(1), dim3(1024), 0, s, cnt, nblk, off, voff, tile_blk, ctr + 2);
             }
             uint32_t h[4];
             hipError_t e = hipMemcpyAsync(h, ctr, 16, hipMemcpyDeviceToHost, s);
@@ -957,7 +956,7 @@ int knn_tree_blocked(qd_tree_t t, const uint64_t *d_q, uint32_t nq, uint32_t k, 
                 hipLaunchKernelGGL(eval_kernel, dim3((uint32_t)mt::tile_grid(mt::xcd_grid(h[2]))), dim3(mt::kThreads), 0,
                                    s, q4,
                                    reinterpret_cast<const uint4 *>(t->d_sorted), n, nblk, nqp, list, cnt, off,
-                                   t->d_pop, t->d_perm, qpop, thr, t->d_bpop, ccnt, cand);
+                                   tile_blk, t->d_pop, t->d_perm, qpop, thr, t->d_bpop, ccnt, cand);
             }
             if (h[3] > 0) {
                 KernelTimer timer("tree_block_eval_short", s);
