@@ -202,12 +202,25 @@ def main():
         if name == "tree_blocked":
             per_path[name]["per_call"] = counters
         if name.startswith("tree"):
-            st = (qd.knn_tree(tree, qt, k, totals=True) if name == "tree" else
-                  qd.knn_tree(tree, qt, k, order=qd.ORDER_BLOCKED, totals=True) if name == "tree_blocked" else
-                  qd.knn_tree(tree, qt, k, order=qd.ORDER_DEPTH_FIRST, totals=True,
-                              scores=qd.model_score_tree(model, tree, qt, n_scored) if name == "tree_learned"
-                              else None))[-1]
+            res = (qd.knn_tree(tree, qt, k, totals=True, query_stats=True) if name == "tree" else
+                   qd.knn_tree(tree, qt, k, order=qd.ORDER_BLOCKED, totals=True, query_stats=True)
+                   if name == "tree_blocked" else
+                   qd.knn_tree(tree, qt, k, order=qd.ORDER_DEPTH_FIRST, totals=True, query_stats=True,
+                               scores=qd.model_score_tree(model, tree, qt, n_scored) if name == "tree_learned"
+                               else None))
+            st, qs = res[-1], res[-2].cpu().numpy().astype(np.int64)
             per_path[name]["per_query"] = {kk: v / nq for kk, v in st.items()}
+            per_path[name]["nodes_visited_p50_p99"] = [float(np.percentile(qs[:, 0], 50)),
+                                                       float(np.percentile(qs[:, 0], 99))]
+            if name != "tree_blocked":
+                # per-query traversal: child OR images (512 B per bound) and leaf rows with
+                # their popcounts (514 B per distance) gathered from HBM
+                gb = (st["bounds_evaluated"] * 512 + st["dists_evaluated"] * 514) / dt / 1e9
+                per_path[name]["gather_GB_s"] = gb
+                per_path[name]["gather_frac_of_hbm_peak"] = gb / HBM_PEAK_GBS
+            if name == "tree_learned":
+                sc_ms = sum(v["avg_ms"] * v["launches"] for kk, v in kernels.items() if kk.startswith("mlp"))
+                per_path[name]["score_time_fraction"] = sc_ms / args.steps / (dt * 1e3)
         log(f"{name}: {dt * 1e3:.2f} ms/batch, {nq / dt:.0f} q/s, kernels {kernels}")
 
     # small-batch scan: HBM-bound regime (one pass over the rows serves <= 8 queries)
@@ -225,6 +238,22 @@ def main():
         gbs = (n * ROW_BYTES + qn * ROW_BYTES) / (avg * 1e-3) / 1e9
         hbm[f"q{qn}"] = {"scan_ms": avg, "GB_s": gbs, "frac": gbs / HBM_PEAK_GBS}
         log(f"scan at {qn} queries: {avg:.3f} ms, {gbs:.0f} GB/s ({gbs / HBM_PEAK_GBS:.1%} of HBM peak)")
+
+    # register-tiled scan at 512 queries (16 per tile): VALU-bound, 256 32-bit lane ops per pair
+    valu = None
+    if "brute" in per_path:
+        qn = min(512, nq)
+        fn = lambda: qd.knn_bruteforce(dbt, qt[:qn], k, query_tile=16)
+        fn()
+        torch.cuda.synchronize()
+        qd.profile_enable(True)
+        fn()
+        ms, cnt = qd.profile_read("wh_scan_topk")
+        qd.profile_enable(False)
+        tops = qn * n * OPS_PER_PAIR / (ms / cnt * 1e-3) / 1e12
+        valu = {"queries": qn, "scan_ms": ms / cnt, "TOP_s": tops, "frac_of_valu_peak": tops / VALU_PEAK_TOPS}
+        log(f"register-tiled scan at {qn} queries: {ms / cnt:.1f} ms, {tops:.1f} T lane-ops/s "
+            f"({tops / VALU_PEAK_TOPS:.1%} of the VALU peak)")
 
     step_ms = sum(p["ms"] for p in per_path.values())
     best = min(per_path, key=lambda p: per_path[p]["ms"])
@@ -279,6 +308,12 @@ def main():
         threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
         cpu = {"value": m / cdt, "unit": "queries/s", "cores": threads, "kind": "oracle",
                "sample": f"first {m} of the {nq} queries, sequential search over all {n} rows, k={k}"}
+        try:
+            with open("/proc/cpuinfo") as f:
+                cpu["cpu_model"] = next(l.split(":", 1)[1].strip() for l in f if l.startswith("model name"))
+        except (OSError, StopIteration):
+            pass
+        cpu["logical_cpus"] = os.cpu_count()
         log(f"oracle: {m} queries in {cdt:.1f}s")
 
     out = {
@@ -295,6 +330,7 @@ def main():
         "tree_build_s": build_s,
         "order_model_training": train,
         "brute_small_batch_hbm": hbm,
+        "brute_register_tiled_valu": valu,
         "recall_source_row_at_1": recall,
         "roofline": roofline,
         "roofline_scan": roofline_scan,
