@@ -79,7 +79,9 @@ __global__ __launch_bounds__(mt::kThreads) void scan_mfma_kernel(const uint4 *__
 
         // epilogue: keys of this lane's 32 queries x 4 rows
 #pragma unroll
-        for (int a = 0; a < 8; a++)
+        for (int a = 0; a < 8; a++) {
+            // one group of queries at a time, so their metadata loads stay next to their use
+            __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int rr = 0; rr < 4; rr++) {
                 const int ai = mt::acc_arow(a, rr);
@@ -105,6 +107,7 @@ __global__ __launch_bounds__(mt::kThreads) void scan_mfma_kernel(const uint4 *__
                     }
                 }
             }
+        }
         __syncthreads();  // the next tile rewrites the metadata
     }
 }

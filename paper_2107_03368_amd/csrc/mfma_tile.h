@@ -10,15 +10,20 @@
 // operands, since the sum over K does not depend on it.
 //
 // A block of 8 waves owns the 256 x 256 tile, and thread t owns row t (A rows
-// 0..255, then B rows).  The K dimension is streamed in windows of 256 bits:
-// each thread loads its row's next window into registers while the current
-// one is multiplied, then unpacks it to 128 bytes of elements in LDS (rows 144
-// bytes apart, so 16 consecutive rows fall on distinct banks).  Windows are
-// double-buffered: while the matrix cores consume window w, the threads
-// unpack window w+1 into the other buffer, with one barrier per window.
-// Every wave multiplies its 128 x 64 eighth as 8 x 4 tiles per 128-bit step.
-// Lane l supplies A rows (l % 16) at k = 32*(l/16) .. +31 (16 bytes) and B
-// columns likewise, and receives C rows 4*(l/16) .. +3 of column l % 16.
+// 0..255, then B rows).  The K dimension is streamed in windows of 512 bits:
+// each thread copies its row's window, still packed, into LDS (rows 72 bytes
+// apart), three windows deep: window w + 2 is loaded into registers at the
+// start of window w and stored at its end, before the one barrier per window,
+// so the reads of window w + 1 never wait for a barrier.  Every wave
+// multiplies its 128 x 64 eighth as 8 x 4 tiles per 128-bit matrix step.  In
+// step s of a window, lane l reads one 32-bit word of a row, word 4s + l/16
+// of row l % 16 of each fragment, and expands it in registers to the 32
+// elements the instruction takes from it (k = 32*(l/16) .. +31): element
+// 8j + i holds bit 4i + j, so four shift-and-mask operations make the 16
+// bytes.  With rows 18 words apart the 64 lanes of such a read fall on
+// distinct banks in each half.  The words of the next step are read while
+// the current one runs.  Lane l receives C rows 4*(l/16) .. +3 of column
+// l % 16.
 //
 // A missing row reads as zeros.  The tile is the same whether rows are contiguous
 // (sequential search) or gathered through a list (the blocked tree search).
@@ -32,33 +37,23 @@ namespace mt {
 constexpr int kThreads = 512;  // 8 waves, one row per thread
 constexpr int MA = 256;        // A rows (queries) per tile
 constexpr int MB = 256;        // B rows per tile
-constexpr int WIN = 256;       // bits per window (two 128-bit matrix steps)
-constexpr int UST = 144;       // unpacked row stride in LDS (128 bytes + 16 pad)
+constexpr int WIN = 512;       // bits per window (four 128-bit matrix steps)
+constexpr int RST = 72;        // packed row stride in LDS (64 bytes + 8 pad)
+constexpr int NBUF = 3;        // windows held in LDS
 
 typedef int v4i __attribute__((ext_vector_type(4)));
 typedef int v8i __attribute__((ext_vector_type(8)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 
 struct Smem {
-    uint8_t uk[2][(MA + MB) * UST];  // unpacked window, double-buffered
+    uint8_t rw[NBUF][(MA + MB) * RST];  // packed windows
 };
 
-// 8 bits -> 8 elements of 0/1 (e2m1 0x1 = 0.5) in the nibbles of a word,
-// nibble 2i holding bit i and nibble 2i+1 bit i+4.  The multiply copies the
-// low 7 bits to offsets 0, 7, 14, 21 without overlap (so without carries); the
-// mask keeps bits 0, 4, 1, 5, 2, 6, 3 at nibbles 0..6; bit 7 goes to nibble 7.
-__device__ __forceinline__ uint32_t nib8(uint32_t y) {
-    return (((y & 0x7Fu) * 0x00204081u) & 0x11111111u) | ((y & 0x80u) << 21);
-}
-
-// 128 bits -> 64 bytes of elements at dst (16-byte aligned); input word j
-// becomes bytes 16j .. 16j+15
-__device__ __forceinline__ void unpack_half(uint4 p, uint8_t *dst) {
-    const uint32_t w[4] = {p.x, p.y, p.z, p.w};
-#pragma unroll
-    for (int j = 0; j < 4; j++)
-        *reinterpret_cast<uint4 *>(dst + j * 16) =
-            make_uint4(nib8(w[j] & 0xFF), nib8((w[j] >> 8) & 0xFF), nib8((w[j] >> 16) & 0xFF), nib8(w[j] >> 24));
+// 32 bits -> the 32 e2m1 elements (0 or 0.5) of one lane's operand: element
+// 8j + i (nibble i of word j) holds bit 4i + j
+__device__ __forceinline__ v8i expand(uint32_t w) {
+    constexpr uint32_t M = 0x11111111u;
+    return v8i{(int)(w & M), (int)((w >> 1) & M), (int)((w >> 2) & M), (int)((w >> 3) & M), 0, 0, 0, 0};
 }
 
 // Workgroups are dispatched to the 8 XCDs round-robin (workgroup x runs on
@@ -108,51 +103,78 @@ __device__ __forceinline__ void overlap_tile(const uint4 *row, bool zero, Smem &
 #pragma unroll
         for (int b = 0; b < 4; b++) acc[a][b] = v4f{0.f, 0.f, 0.f, 0.f};
 
-    // window v of this thread's row is its 16-byte pieces 2v, 2v+1 (global
+    // window v of this thread's row is its 16-byte pieces 4v .. 4v+3 (global
     // loads: a generic pointer would make them flat loads, which also hold
     // the LDS counter the fragment reads wait on)
-    auto piece = [&](int i) {
-        const uint4 v = row[i];
-        return zero ? make_uint4(0, 0, 0, 0) : v;
+    // Loaded as they are; a missing row is masked to zeros only when stored, so
+    // nothing waits for the loads before then (and no branch skips them).
+    const uint32_t keep = zero ? 0u : ~0u;
+    auto piece = [&](int i) { return row[i]; };
+    auto stage = [&](uint8_t *dst, uint4 p0, uint4 p1, uint4 p2, uint4 p3) {
+        uint2 *d = reinterpret_cast<uint2 *>(dst + tid * RST);  // 8-byte aligned
+        d[0] = make_uint2(p0.x & keep, p0.y & keep);
+        d[1] = make_uint2(p0.z & keep, p0.w & keep);
+        d[2] = make_uint2(p1.x & keep, p1.y & keep);
+        d[3] = make_uint2(p1.z & keep, p1.w & keep);
+        d[4] = make_uint2(p2.x & keep, p2.y & keep);
+        d[5] = make_uint2(p2.z & keep, p2.w & keep);
+        d[6] = make_uint2(p3.x & keep, p3.y & keep);
+        d[7] = make_uint2(p3.z & keep, p3.w & keep);
     };
     constexpr int kWins = 4096 / WIN;
-    unpack_half(piece(0), sm.uk[0] + tid * UST);
-    unpack_half(piece(1), sm.uk[0] + tid * UST + 64);
+    stage(sm.rw[0], piece(0), piece(1), piece(2), piece(3));
+    stage(sm.rw[1], piece(4), piece(5), piece(6), piece(7));
     __syncthreads();
-    for (int win = 0; win < kWins; win++) {  // window win is in buffer win & 1
-        const int h = win & 1;
-        const bool more = win + 1 < kWins;
-        // the next window: in flight during this one's matrix steps
-        const uint4 n0 = piece(more ? 2 * win + 2 : 0), n1 = piece(more ? 2 * win + 3 : 1);
-        const uint8_t *ua = sm.uk[h];
-        const uint8_t *ubp = sm.uk[h] + MA * UST;
-        uint8_t *nx = sm.uk[h ^ 1] + tid * UST;  // last read before the previous barrier
+    // fragment f < 8: A rows wq*128 + 16f + li; f >= 8: B rows wr*64 + 16(f-8) + li
+    int roff[12];
 #pragma unroll
-        for (int ks = 0; ks < 2; ks++) {
-            v4i af[8], bf[4];
+    for (int f = 0; f < 12; f++)
+        roff[f] = (f < 8 ? wq * 128 + f * 16 + li : MA + wr * 64 + (f - 8) * 16 + li) * RST + lg * 4;
+    uint32_t r[2][12];  // the words of this step and of the next
 #pragma unroll
-            for (int a = 0; a < 8; a++)
-                af[a] = *reinterpret_cast<const v4i *>(ua + (wq * 128 + a * 16 + li) * UST + ks * 64 + lg * 16);
+    for (int f = 0; f < 12; f++) r[0][f] = *reinterpret_cast<const uint32_t *>(sm.rw[0] + roff[f]);
+    auto step = [&](const uint32_t (&x)[12]) {
+        v8i bv[4];
+#pragma unroll
+        for (int b = 0; b < 4; b++) bv[b] = expand(x[8 + b]);
+#pragma unroll
+        for (int a = 0; a < 8; a++) {
+            const v8i av = expand(x[a]);
 #pragma unroll
             for (int b = 0; b < 4; b++)
-                bf[b] = *reinterpret_cast<const v4i *>(ubp + (wr * 64 + b * 16 + li) * UST + ks * 64 + lg * 16);
+                // formats 4 = e2m1 for both operands; scales 128 = 2^1
+                acc[a][b] =
+                    __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(av, bv[b], acc[a][b], 4, 4, 0, 128, 0, 128);
+        }
+    };
+    // Every window runs the same code: the last two load pieces of window 0
+    // and 1 again (in bounds) and store them into buffers no later window of
+    // this tile reads, and the last reads words it does not use, so the
+    // compiler keeps one loop instead of peeling its end.
+    int cur = 0;  // buffer of window win; window win + 1 is in the next, win + 2 goes to the one after
+    for (int win = 0; win < kWins; win++) {
+        const int nxt = cur == NBUF - 1 ? 0 : cur + 1, stg = nxt == NBUF - 1 ? 0 : nxt + 1;
+        const uint8_t *buf = sm.rw[cur];
+        const int nb = (4 * win + 8) & 31;
+        const uint4 n0 = piece(nb), n1 = piece(nb + 1), n2 = piece(nb + 2), n3 = piece(nb + 3);
 #pragma unroll
-            for (int a = 0; a < 8; a++)
+        for (int s = 0; s < 4; s++) {
+            // the next step's words: from this window, or the first of the next
+            // window (published by the previous window's barrier)
+            const uint8_t *src = s < 3 ? buf + (s + 1) * 16 : sm.rw[nxt];
 #pragma unroll
-                for (int b = 0; b < 4; b++) {
-                    const v8i av = {af[a][0], af[a][1], af[a][2], af[a][3], 0, 0, 0, 0};
-                    const v8i bv = {bf[b][0], bf[b][1], bf[b][2], bf[b][3], 0, 0, 0, 0};
-                    // formats 4 = e2m1 for both operands; scales 128 = 2^1
-                    acc[a][b] =
-                        __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(av, bv, acc[a][b], 4, 4, 0, 128, 0, 128);
-                }
-            // one step's fragments live at a time (register budget of two waves per SIMD)
+            for (int f = 0; f < 12; f++) r[(s + 1) & 1][f] = *reinterpret_cast<const uint32_t *>(src + roff[f]);
+            // one step at a time: the next step's reads go out before this step's work
             __builtin_amdgcn_sched_barrier(0);
-            // half ks of the next window, into the other buffer
-            if (more) unpack_half(ks == 0 ? n0 : n1, nx + ks * 64);
+            step(r[s & 1]);
             __builtin_amdgcn_sched_barrier(0);
         }
+        // the buffer of window win - 1: every wave finished reading it before
+        // the previous barrier
+        __builtin_amdgcn_sched_barrier(0);
+        stage(sm.rw[stg], n0, n1, n2, n3);
         __syncthreads();
+        cur = nxt;
     }
 }
 

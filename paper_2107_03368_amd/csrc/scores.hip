@@ -173,7 +173,9 @@ __global__ __launch_bounds__(mt::kThreads) void objscan_kernel(
             tpv[b] = (uint32_t)bi < nb ? (int32_t)s_tp[bi] : 32767;
         }
 #pragma unroll
-        for (int a = 0; a < 8; a++)
+        for (int a = 0; a < 8; a++) {
+            // one group of queries at a time, so their metadata loads stay next to their use
+            __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int rr = 0; rr < 4; rr++) {
                 const int ai = mt::acc_arow(a, rr);
@@ -190,6 +192,7 @@ __global__ __launch_bounds__(mt::kThreads) void objscan_kernel(
                 m = min16(m);
                 if ((lane & 15) == 0) atomicMin(&s_min[ai], m);  // the 4 waves of this descriptor half
             }
+        }
         __syncthreads();
         if (r < MQ && q0 + r < nq) atomicMin(&minK[(uint64_t)(q0 + r) * n_obj + o], s_min[r]);
         // the next tile rewrites s_pq / s_tp only after every lane has read them (above);

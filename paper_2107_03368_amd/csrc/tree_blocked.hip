@@ -162,7 +162,9 @@ __global__ __launch_bounds__(mt::kThreads) void bound_kernel(const uint4 *__rest
         mt::v4f acc[8][4];
         mt::overlap_tile(row, !ok, sm, acc);  // its barriers also publish s_pq, s_pmin, s_pmax
 #pragma unroll
-        for (int a = 0; a < 8; a++)
+        for (int a = 0; a < 8; a++) {
+            // one group of queries at a time, so their metadata loads stay next to their use
+            __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int bb = 0; bb < 4; bb++) {
                 const uint64_t blk = b0 + mt::acc_brow(bb);
@@ -186,6 +188,7 @@ __global__ __launch_bounds__(mt::kThreads) void bound_kernel(const uint4 *__rest
                 }
                 *reinterpret_cast<u64 *>(lbb + blk * nqp + qa) = packed;
             }
+        }
         __syncthreads();  // the next tile rewrites s_pq
     }
 }
@@ -641,7 +644,9 @@ __global__ __launch_bounds__(mt::kThreads) void eval_kernel(const uint4 *__restr
         mt::v4f acc[8][4];
         mt::overlap_tile(row, !ok, sm, acc);  // its barriers also publish the metadata above
 #pragma unroll
-        for (int a = 0; a < 8; a++)
+        for (int a = 0; a < 8; a++) {
+            // one group of queries at a time, so their metadata loads stay next to their use
+            __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int rr = 0; rr < 4; rr++) {
                 const uint32_t i = (uint32_t)mt::acc_arow(a, rr);
@@ -667,6 +672,7 @@ __global__ __launch_bounds__(mt::kThreads) void eval_kernel(const uint4 *__restr
                     }
                 }
             }
+        }
         __syncthreads();  // the next tile rewrites the metadata
     }
 }
