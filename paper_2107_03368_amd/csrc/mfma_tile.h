@@ -91,9 +91,54 @@ __device__ __forceinline__ int acc_brow(int b) {
 // Exact count held by an accumulator entry.
 __device__ __forceinline__ uint32_t count(float c) { return (uint32_t)c; }
 
-// row: this thread's row (32 x 16 bytes), always a readable global row; when
-// zero is set its bits count as 0 (a missing row past the end of the input)
-__device__ __forceinline__ void overlap_tile(const uint4 *row, bool zero, Smem &sm, v4f (&acc)[8][4]) {
+// Tiles in a row, streamed: while a tile's last two windows run, the next
+// tile's first two windows are loaded and stored, and the words of its first
+// step are read, so a tile that follows another starts without waiting for
+// its loads.  `Stream` carries that state from one tile to the next.
+struct Stream {
+    int cur;           // buffer holding window 0 of the next tile to run
+    uint32_t r0[12];   // the words of that tile's first step
+};
+
+// Rows: this thread's row (32 x 16 bytes), always a readable global row; when
+// the zero flag is set its bits count as 0 (a missing row past the end of
+// the input).  A global-memory pointer: a generic one would make the window
+// loads flat loads, which also hold the LDS counter the fragment reads wait on.
+
+// Stage the first two windows of a stream's first tile.
+__device__ __forceinline__ void stream_begin(const uint4 *row, bool zero, Smem &sm, Stream &st) {
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int wq = w >> 2, wr = w & 3, li = lane & 15, lg = lane >> 4;
+    const uint32_t keep = zero ? 0u : ~0u;
+#pragma unroll
+    for (int v = 0; v < 2; v++) {
+        uint2 *d = reinterpret_cast<uint2 *>(sm.rw[v] + tid * RST);
+#pragma unroll
+        for (int c = 0; c < 4; c++) {
+            const uint4 p = row[4 * v + c];
+            d[2 * c] = make_uint2(p.x & keep, p.y & keep);
+            d[2 * c + 1] = make_uint2(p.z & keep, p.w & keep);
+        }
+    }
+    __syncthreads();
+    st.cur = 0;
+#pragma unroll
+    for (int f = 0; f < 12; f++)
+        st.r0[f] = *reinterpret_cast<const uint32_t *>(
+            sm.rw[0] + (f < 8 ? wq * 128 + f * 16 + li : MA + wr * 64 + (f - 8) * 16 + li) * RST + lg * 4);
+}
+
+// Multiply the stream's current tile (rows `row`) while staging the first two
+// windows of the next one (rows `next`, read when windows 6 and 7 load them,
+// so the hook may still set them; the current rows again after the last
+// tile: in bounds, never used).  hook(win) runs after window win's barrier,
+// win = 0..7, for the kernel's own work on the next tile (such as a chain of
+// dependent metadata loads, one link per window, which then never stalls a
+// wave: a whole window passes between a load and its use).
+template <class Hook>
+__device__ __forceinline__ void stream_tile(const uint4 *row, bool zero, const uint4 *const &next,
+                                            const bool &next_zero, Smem &sm, Stream &st, v4f (&acc)[8][4],
+                                            Hook &&hook) {
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int wq = w >> 2, wr = w & 3;  // 2 x 4 waves, each 128 A rows x 64 B rows
     const int li = lane & 15, lg = lane >> 4;
@@ -103,28 +148,22 @@ __device__ __forceinline__ void overlap_tile(const uint4 *row, bool zero, Smem &
 #pragma unroll
         for (int b = 0; b < 4; b++) acc[a][b] = v4f{0.f, 0.f, 0.f, 0.f};
 
-    // window v of this thread's row is its 16-byte pieces 4v .. 4v+3 (global
-    // loads: a generic pointer would make them flat loads, which also hold
-    // the LDS counter the fragment reads wait on)
-    // Loaded as they are; a missing row is masked to zeros only when stored, so
+    // window v of a row is its 16-byte pieces 4v .. 4v+3.  Pieces are loaded
+    // as they are and a missing row is masked to zeros only when stored, so
     // nothing waits for the loads before then (and no branch skips them).
     const uint32_t keep = zero ? 0u : ~0u;
-    auto piece = [&](int i) { return row[i]; };
-    auto stage = [&](uint8_t *dst, uint4 p0, uint4 p1, uint4 p2, uint4 p3) {
+    auto stage = [&](uint8_t *dst, uint4 p0, uint4 p1, uint4 p2, uint4 p3, uint32_t k) {
         uint2 *d = reinterpret_cast<uint2 *>(dst + tid * RST);  // 8-byte aligned
-        d[0] = make_uint2(p0.x & keep, p0.y & keep);
-        d[1] = make_uint2(p0.z & keep, p0.w & keep);
-        d[2] = make_uint2(p1.x & keep, p1.y & keep);
-        d[3] = make_uint2(p1.z & keep, p1.w & keep);
-        d[4] = make_uint2(p2.x & keep, p2.y & keep);
-        d[5] = make_uint2(p2.z & keep, p2.w & keep);
-        d[6] = make_uint2(p3.x & keep, p3.y & keep);
-        d[7] = make_uint2(p3.z & keep, p3.w & keep);
+        d[0] = make_uint2(p0.x & k, p0.y & k);
+        d[1] = make_uint2(p0.z & k, p0.w & k);
+        d[2] = make_uint2(p1.x & k, p1.y & k);
+        d[3] = make_uint2(p1.z & k, p1.w & k);
+        d[4] = make_uint2(p2.x & k, p2.y & k);
+        d[5] = make_uint2(p2.z & k, p2.w & k);
+        d[6] = make_uint2(p3.x & k, p3.y & k);
+        d[7] = make_uint2(p3.z & k, p3.w & k);
     };
     constexpr int kWins = 4096 / WIN;
-    stage(sm.rw[0], piece(0), piece(1), piece(2), piece(3));
-    stage(sm.rw[1], piece(4), piece(5), piece(6), piece(7));
-    __syncthreads();
     // fragment f < 8: A rows wq*128 + 16f + li; f >= 8: B rows wr*64 + 16(f-8) + li
     int roff[12];
 #pragma unroll
@@ -132,7 +171,7 @@ __device__ __forceinline__ void overlap_tile(const uint4 *row, bool zero, Smem &
         roff[f] = (f < 8 ? wq * 128 + f * 16 + li : MA + wr * 64 + (f - 8) * 16 + li) * RST + lg * 4;
     uint32_t r[2][12];  // the words of this step and of the next
 #pragma unroll
-    for (int f = 0; f < 12; f++) r[0][f] = *reinterpret_cast<const uint32_t *>(sm.rw[0] + roff[f]);
+    for (int f = 0; f < 12; f++) r[0][f] = st.r0[f];
     auto step = [&](const uint32_t (&x)[12]) {
         v8i bv[4];
 #pragma unroll
@@ -147,23 +186,25 @@ __device__ __forceinline__ void overlap_tile(const uint4 *row, bool zero, Smem &
                     __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(av, bv[b], acc[a][b], 4, 4, 0, 128, 0, 128);
         }
     };
-    // Every window runs the same code: the last two load pieces of window 0
-    // and 1 again (in bounds) and store them into buffers no later window of
-    // this tile reads, and the last reads words it does not use, so the
-    // compiler keeps one loop instead of peeling its end.
-    int cur = 0;  // buffer of window win; window win + 1 is in the next, win + 2 goes to the one after
+    // Every window runs the same code, so the compiler keeps one loop instead
+    // of peeling its end (a peeled end spilled registers in the kernels).
+    int cur = st.cur;  // buffer of window win; window win + 1 is in the next, win + 2 goes to the one after
     for (int win = 0; win < kWins; win++) {
         const int nxt = cur == NBUF - 1 ? 0 : cur + 1, stg = nxt == NBUF - 1 ? 0 : nxt + 1;
         const uint8_t *buf = sm.rw[cur];
+        // window win + 2 of this tile, or window win - 6 of the next
+        const bool own = win + 2 < kWins;
+        const uint4 *src = own ? row : next;
+        const uint32_t k = own ? keep : (next_zero ? 0u : ~0u);
         const int nb = (4 * win + 8) & 31;
-        const uint4 n0 = piece(nb), n1 = piece(nb + 1), n2 = piece(nb + 2), n3 = piece(nb + 3);
+        const uint4 n0 = src[nb], n1 = src[nb + 1], n2 = src[nb + 2], n3 = src[nb + 3];
 #pragma unroll
         for (int s = 0; s < 4; s++) {
             // the next step's words: from this window, or the first of the next
             // window (published by the previous window's barrier)
-            const uint8_t *src = s < 3 ? buf + (s + 1) * 16 : sm.rw[nxt];
+            const uint8_t *from = s < 3 ? buf + (s + 1) * 16 : sm.rw[nxt];
 #pragma unroll
-            for (int f = 0; f < 12; f++) r[(s + 1) & 1][f] = *reinterpret_cast<const uint32_t *>(src + roff[f]);
+            for (int f = 0; f < 12; f++) r[(s + 1) & 1][f] = *reinterpret_cast<const uint32_t *>(from + roff[f]);
             // one step at a time: the next step's reads go out before this step's work
             __builtin_amdgcn_sched_barrier(0);
             step(r[s & 1]);
@@ -171,11 +212,21 @@ __device__ __forceinline__ void overlap_tile(const uint4 *row, bool zero, Smem &
         }
         // the buffer of window win - 1: every wave finished reading it before
         // the previous barrier
-        __builtin_amdgcn_sched_barrier(0);
-        stage(sm.rw[stg], n0, n1, n2, n3);
+        stage(sm.rw[stg], n0, n1, n2, n3, k);
         __syncthreads();
+        hook(win);
         cur = nxt;
     }
+    st.cur = cur;
+#pragma unroll
+    for (int f = 0; f < 12; f++) st.r0[f] = r[0][f];
+}
+
+// One tile on its own.
+__device__ __forceinline__ void overlap_tile(const uint4 *row, bool zero, Smem &sm, v4f (&acc)[8][4]) {
+    Stream st;
+    stream_begin(row, zero, sm, st);
+    stream_tile(row, zero, row, zero, sm, st, acc, [](int) {});
 }
 
 }  // namespace mt

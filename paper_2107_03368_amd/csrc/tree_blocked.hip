@@ -488,10 +488,12 @@ __device__ __forceinline__ uint32_t mfma_tiles(uint32_t c) { return (c - short_p
 
 // Exclusive prefixes over the blocks of the matrix-core tiles (off) and of
 // the short-list pairs (voff); off[nblk], voff[nblk], total[0] and total[1]
-// receive the sums; tile_blk[x] = the block of tile x.
+// receive the sums; tinfo[x] = (block, offset of the tile's first query in
+// the block's list, queries in the tile, the block's smallest popcount).
 __global__ __launch_bounds__(1024) void tile_scan_kernel(const uint32_t *__restrict__ cnt, uint64_t nblk,
+                                                         const uint16_t *__restrict__ bpop,
                                                          uint32_t *__restrict__ off, uint32_t *__restrict__ voff,
-                                                         uint32_t *__restrict__ tile_blk,
+                                                         uint4 *__restrict__ tinfo,
                                                          uint32_t *__restrict__ total) {
     __shared__ uint32_t part[1024], vpart[1024];
     const uint32_t tid = threadIdx.x;
@@ -518,7 +520,12 @@ __global__ __launch_bounds__(1024) void tile_scan_kernel(const uint32_t *__restr
         off[b] = run;
         voff[b] = vrun;
         const uint32_t nt = mfma_tiles(cnt[b]);
-        for (uint32_t i = 0; i < nt; i++) tile_blk[run + i] = (uint32_t)b;
+        const uint32_t listed = cnt[b] - short_pairs(cnt[b]);  // the list's short rest is not in a tile
+        const uint32_t bp = bpop ? bpop[2 * b] : 0;
+        for (uint32_t i = 0; i < nt; i++) {
+            const uint32_t t0 = i * mt::MA, m = listed - t0 < (uint32_t)mt::MA ? listed - t0 : (uint32_t)mt::MA;
+            tinfo[run + i] = make_uint4((uint32_t)b, t0, m, bp);
+        }
         run += nt;
         vrun += short_pairs(cnt[b]);
     }
@@ -590,59 +597,126 @@ __global__ __launch_bounds__(256) void eval_short_kernel(const uint4 *__restrict
     }
 }
 
-// One tile: 256 listed queries of block b x the block's rows.  Block b and
-// the tile index come from the tile prefix (binary search).
+// Tiles of 256 listed queries of a block x the block's rows, in a persistent
+// grid: workgroup x takes tiles x, x + G, x + 2G, ... of the virtual tile
+// order (G = gridDim.x, a multiple of 8, so the workgroup stays on one XCD and
+// the XCD's tiles form one contiguous range of the tile list).  The tiles are
+// streamed: the next tile's first two windows are staged during the current
+// tile's last two, and its metadata is fetched during the current tile, one
+// dependent load per window, so the matrix cores do not wait for a tile to
+// start.
 __global__ __launch_bounds__(mt::kThreads) void eval_kernel(const uint4 *__restrict__ q, const uint4 *__restrict__ sorted,
-                                                            uint64_t n, uint64_t nblk, uint32_t nqp,
+                                                            uint64_t n, uint32_t nqp, uint32_t total,
                                                             const uint16_t *__restrict__ list,
-                                                            const uint32_t *__restrict__ cnt,
-                                                            const uint32_t *__restrict__ off,
-                                                            const uint32_t *__restrict__ tile_blk,
+                                                            const uint4 *__restrict__ tinfo,
                                                             const uint16_t *__restrict__ tpop,
                                                             const uint32_t *__restrict__ perm,
                                                             const uint16_t *__restrict__ qpop,
                                                             const uint32_t *__restrict__ thrk,
-                                                            const uint16_t *__restrict__ bpop,
                                                             uint32_t *__restrict__ ccnt, u64 *__restrict__ cand) {
     __shared__ mt::Smem sm;
     __shared__ uint32_t s_qi[mt::MA], s_pq[mt::MA], s_th[mt::MA], s_tp[mt::MB];
     __shared__ float s_cmin[mt::MA];  // per query slot: the least overlap that can reach its k-th key
-    const uint64_t total = off[nblk];
-    // workgroup v of the virtual grid runs on XCD v % 8 (gridDim.x is a multiple of 8)
-    for (uint64_t v = blockIdx.x; v < mt::xcd_grid(total); v += gridDim.x) {
-        uint64_t xt;
-        if (!mt::xcd_tile(v, total, xt)) continue;
-        const uint32_t x = (uint32_t)xt;  // tiles of one block are consecutive
-        const uint64_t b = tile_blk[x];
-        const uint32_t t0 = (x - off[b]) * mt::MA;
-        const uint32_t left = cnt[b] - short_pairs(cnt[b]) - t0;  // the list's short rest is not in a tile
-        const uint32_t m = left < (uint32_t)mt::MA ? left : (uint32_t)mt::MA;
-        const uint16_t *lq = list + b * nqp + t0;
-        const uint64_t r0 = b * kBlk;
-        const int r = mt::own_row();
-        const uint4 *row;
-        bool ok;
-        if (r < mt::MA) {
-            ok = (uint32_t)r < m;
-            const uint32_t qi = ok ? lq[r] : 0;
-            row = q + (uint64_t)qi * 32;
-            const uint32_t pq = ok ? qpop[qi] : 0, th = ok ? thrk[qi] : 0;
+    const uint64_t vend = mt::xcd_grid(total);
+    const int r = mt::own_row();
+    const bool arow = r < mt::MA;  // the same in a whole wave
+    // a lane-varying zero: keeps the per-tile record load a vector load (a
+    // scalar load shares its completion counter with the LDS reads)
+    const uint32_t vz = __builtin_amdgcn_mbcnt_lo(0u, 0u);
+    // A tile's fetch is three dependent loads: its record (block b, list
+    // offset t0, queries m, the block's smallest popcount), then this thread's
+    // list entry (A rows) or row popcount (B rows), then the query's |q| and
+    // k-th key.  Every load is unconditional and in bounds (a row past m or n
+    // reads a valid entry and is masked when used).
+    uint4 info;          // the record
+    uint32_t pb, pc, pd; // loads in flight: list entry or |t|; |q|; k-th key
+    uint32_t qi = 0, tp = 0, pq = 0, th = 0;
+    bool ok = false;
+    auto issue_b = [&](const uint4 &in) {
+        const uint64_t r0 = (uint64_t)in.x * kBlk;
+        pb = arow ? list[(uint64_t)in.x * nqp + in.y + r]  // t0 + 256 <= nqp: the entry exists
+                  : tpop[r0 + (r - mt::MA) < n ? r0 + (r - mt::MA) : n - 1];
+    };
+    auto take_b = [&](const uint4 &in) {
+        const uint64_t r0 = (uint64_t)in.x * kBlk;
+        ok = arow ? (uint32_t)r < in.z : r0 + (r - mt::MA) < n;
+        qi = arow && ok ? pb : 0;
+        tp = !arow && ok ? pb : 0;
+    };
+    auto issue_c = [&]() {
+        pc = qpop[qi];
+        pd = thrk[qi];
+    };
+    auto take_c = [&]() {
+        pq = arow && ok ? pc : 0;
+        th = arow && ok ? pd : 0;
+    };
+    // K = |q|*wB + |t|*wA - C*(wA + wB) with |t| >= the block's smallest
+    // popcount: a row with C below cmin has K above the k-th key
+    auto cmin_of = [&](const uint4 &in) -> float {
+        const uint32_t wa = weight_a(pq), wb = weight_b(pq);
+        const int64_t X = (int64_t)pq * wb + (int64_t)in.w * wa - (int64_t)th;
+        const uint32_t cmin = X <= 0 ? 0u : ((uint32_t)X + wa + wb - 1) / (wa + wb);  // 0 < X < 2^26
+        return arow && ok ? (float)cmin : 1e30f;
+    };
+    auto row_of = [&](const uint4 &in) -> const uint4 * {
+        const uint64_t r0 = (uint64_t)in.x * kBlk;
+        return arow ? q + (uint64_t)qi * 32 : sorted + (ok ? r0 + (r - mt::MA) : 0) * 32;
+    };
+    auto publish = [&](float cmin) {  // read after the next barrier
+        if (arow) {
             s_qi[r] = qi;
             s_pq[r] = pq;
             s_th[r] = th;
-            // K = |q|*wB + |t|*wA - C*(wA + wB) with |t| >= the block's smallest
-            // popcount: a row with C below cmin has K above the k-th key
-            const uint32_t wa = weight_a(pq), wb = weight_b(pq);
-            const int64_t X = (int64_t)pq * wb + (int64_t)(bpop ? bpop[2 * b] : 0) * wa - (int64_t)th;
-            const uint32_t cmin = X <= 0 ? 0u : ((uint32_t)X + wa + wb - 1) / (wa + wb);  // 0 < X < 2^26
-            s_cmin[r] = ok ? (float)cmin : 1e30f;
+            s_cmin[r] = cmin;
         } else {
-            ok = r0 + (r - mt::MA) < n;
-            row = ok ? sorted + (r0 + (r - mt::MA)) * 32 : sorted;
-            s_tp[r - mt::MA] = ok ? tpop[r0 + (r - mt::MA)] : 0;
+            s_tp[r - mt::MA] = tp;
         }
+    };
+
+    uint64_t v = blockIdx.x, xt;
+    if (!(v < vend && mt::xcd_tile(v, total, xt))) return;  // whole workgroup: no tile
+    // the first tile: fetched here, waiting for each load
+    info = tinfo[xt + vz];
+    issue_b(info);
+    take_b(info);
+    issue_c();
+    take_c();
+    uint4 cur = info;
+    const uint4 *row = row_of(cur);
+    bool cur_ok = ok;
+    publish(cmin_of(cur));
+    mt::Stream st;
+    mt::stream_begin(row, !cur_ok, sm, st);  // its barrier also publishes the metadata
+    for (;;) {
+        // tiles of this workgroup only run out at the end of its XCD's range
+        const uint64_t vn = v + gridDim.x;
+        const bool more = vn < vend && mt::xcd_tile(vn, total, xt);
+        const uint64_t xn = more ? xt : 0;
+        uint4 pa = info;      // the next tile's record, in flight
+        const uint4 *nrow = row;
+        bool nok = false;
+        float ncmin = 0.f;
         mt::v4f acc[8][4];
-        mt::overlap_tile(row, !ok, sm, acc);  // its barriers also publish the metadata above
+        // after window w: take what window w - 1 loaded (the window's own store
+        // waited for every earlier load), then issue the next loads
+        bool nzero = true;
+        mt::stream_tile(row, !cur_ok, nrow, nzero, sm, st, acc, [&](int win) {
+            if (win == 1) info = pa;
+            if (win == 2) take_b(info);
+            if (win == 3) {
+                take_c();
+                ncmin = cmin_of(info);
+                nrow = row_of(info);
+                nok = ok;
+                nzero = !more || !ok;
+            }
+            pa = tinfo[xn + vz];
+            issue_b(info);
+            issue_c();
+        });
+        const uint64_t r0 = (uint64_t)cur.x * kBlk;
+        const uint32_t m = cur.z;
 #pragma unroll
         for (int a = 0; a < 8; a++) {
             // one group of queries at a time, so their metadata loads stay next to their use
@@ -655,25 +729,31 @@ __global__ __launch_bounds__(mt::kThreads) void eval_kernel(const uint4 *__restr
                 const float mx = fmaxf(fmaxf(acc[a][0][rr], acc[a][1][rr]), fmaxf(acc[a][2][rr], acc[a][3][rr]));
                 if (mx < s_cmin[i]) continue;
                 if (i >= m) continue;
-                const uint32_t qi = s_qi[i];
-                const uint32_t pq = s_pq[i];
-                const uint32_t wa = weight_a(pq), wb = weight_b(pq);
-                const uint32_t th = s_th[i];
+                const uint32_t qk = s_qi[i];
+                const uint32_t pk = s_pq[i];
+                const uint32_t wa = weight_a(pk), wb = weight_b(pk);
+                const uint32_t tk = s_th[i];
 #pragma unroll
                 for (int bb = 0; bb < 4; bb++) {
                     const int bi = mt::acc_brow(bb);
                     const uint64_t rw = r0 + bi;
                     if (rw >= n) continue;
                     const uint32_t C = mt::count(acc[a][bb][rr]);
-                    const uint32_t K = (pq - C) * wb + (s_tp[bi] - C) * wa;
-                    if (K <= th) {
-                        const uint32_t pos = atomicAdd(&ccnt[qi], 1u);
-                        if (pos < kCap) cand[(uint64_t)qi * kCap + pos] = ((u64)K << 32) | perm[rw];
+                    const uint32_t K = (pk - C) * wb + (s_tp[bi] - C) * wa;
+                    if (K <= tk) {
+                        const uint32_t pos = atomicAdd(&ccnt[qk], 1u);
+                        if (pos < kCap) cand[(uint64_t)qk * kCap + pos] = ((u64)K << 32) | perm[rw];
                     }
                 }
             }
         }
-        __syncthreads();  // the next tile rewrites the metadata
+        __syncthreads();  // the metadata is rewritten next
+        if (!more) break;
+        publish(ncmin);
+        cur = info;
+        row = nrow;
+        cur_ok = nok;
+        v = vn;
     }
 }
 
@@ -878,7 +958,7 @@ int knn_tree_blocked(qd_tree_t t, const uint64_t *d_q, uint32_t nq, uint32_t k, 
                  a_ccnt = take(P * 4), a_cand = take(P * kCap * 8), a_cnt = take(nblk * 4), a_qr = take(P * 4),
                  a_off = take((nblk + 1) * 4), a_voff = take((nblk + 1) * 4), a_ctr = take(16),
                  a_done = take(P * ((nblk + 31) / 32) * 4), a_fr = take(P * 16),
-                 a_tblk = take(nblk * (P / mt::MA) * 4),  // tiles: at most ceil(nqb / 256) per block
+                 a_tblk = take(nblk * (P / mt::MA) * 16),  // tile records: at most ceil(nqb / 256) per block
                  a_redo = take(P * 4), a_qst = take(P * 16),
                  a_gst = take(32);
     char *ws = nullptr;
@@ -893,7 +973,7 @@ int knn_tree_blocked(qd_tree_t t, const uint64_t *d_q, uint32_t nq, uint32_t k, 
              *qround = (uint32_t *)(ws + a_qr);
     unsigned long long *gst = (unsigned long long *)(ws + a_gst);
     u64 *frange = (u64 *)(ws + a_fr);
-    uint32_t *tile_blk = (uint32_t *)(ws + a_tblk);
+    uint4 *tinfo = (uint4 *)(ws + a_tblk);
     const bool want_stats = d_qstats || h_stats;
     int rc = QD_OK;
     auto done = [&](int code) {
@@ -943,7 +1023,8 @@ int knn_tree_blocked(qd_tree_t t, const uint64_t *d_q, uint32_t nq, uint32_t k, 
                 const uint64_t waves = (nblk + kGroup - 1) / kGroup;
                 hipLaunchKernelGGL(list_kernel, dim3((uint32_t)((waves + 3) / 4)), dim3(256), 0, s, lbb, nblk, n, nqb,
                                    nqp, rec, frange, donebits, dw, list, cnt, want_stats ? qst : nullptr);
-                hipLaunchKernelGGL(tile_scan_kernel, dim3(1), dim3(1024), 0, s, cnt, nblk, off, voff, tile_blk, ctr + 2);
+                hipLaunchKernelGGL(tile_scan_kernel, dim3(1), dim3(1024), 0, s, cnt, nblk, t->d_bpop, off, voff, tinfo,
+                                   ctr + 2);
             }
             uint32_t h[4];
             hipError_t e = hipMemcpyAsync(h, ctr, 16, hipMemcpyDeviceToHost, s);
@@ -959,10 +1040,12 @@ int knn_tree_blocked(qd_tree_t t, const uint64_t *d_q, uint32_t nq, uint32_t k, 
             profile_count("tree_block_short_pairs", h[3]);
             if (h[2] > 0) {
                 KernelTimer timer("tree_block_eval", s);
-                hipLaunchKernelGGL(eval_kernel, dim3((uint32_t)mt::tile_grid(mt::xcd_grid(h[2]))), dim3(mt::kThreads), 0,
-                                   s, q4,
-                                   reinterpret_cast<const uint4 *>(t->d_sorted), n, nblk, nqp, list, cnt, off,
-                                   tile_blk, t->d_pop, t->d_perm, qpop, thr, t->d_bpop, ccnt, cand);
+                // persistent: one workgroup per CU (the tile's LDS and registers
+                // leave room for one), a multiple of the 8 XCDs
+                const uint64_t grid = std::min<uint64_t>(mt::xcd_grid(h[2]), mt::xcd_grid((uint64_t)device_cus()));
+                hipLaunchKernelGGL(eval_kernel, dim3((uint32_t)grid), dim3(mt::kThreads), 0, s, q4,
+                                   reinterpret_cast<const uint4 *>(t->d_sorted), n, nqp, h[2], list, tinfo, t->d_pop,
+                                   t->d_perm, qpop, thr, ccnt, cand);
             }
             if (h[3] > 0) {
                 KernelTimer timer("tree_block_eval_short", s);
