@@ -35,6 +35,13 @@ constexpr int MR = mt::MB;        // rows per block
 constexpr uint32_t kCap = 8192;   // candidate slots per query
 thread_local int g_sample_depth = 0;  // > 0 inside the search of a threshold sample
 
+// Tiles of 256 queries x 256 rows in a persistent grid: workgroup x takes
+// tiles x, x + G, x + 2G, ... (G = gridDim.x).  Consecutive tiles share a row
+// tile and spread over the XCDs, so every XCD's L2 keeps a few query tiles
+// resident while the rows stream through.  The tiles are streamed: the next
+// tile's first two windows are staged during the current tile's last two and
+// its metadata is loaded during the current tile, so the matrix cores do not
+// wait for a tile to start.
 __global__ __launch_bounds__(mt::kThreads) void scan_mfma_kernel(const uint4 *__restrict__ db, uint64_t n,
                                                                  const uint4 *__restrict__ q, uint32_t nq,
                                                                  const uint16_t *__restrict__ tpop,
@@ -42,40 +49,83 @@ __global__ __launch_bounds__(mt::kThreads) void scan_mfma_kernel(const uint4 *__
                                                                  const u64 *__restrict__ thr, uint32_t n_qtiles,
                                                                  uint32_t *__restrict__ cnt, u64 *__restrict__ cand) {
     __shared__ mt::Smem sm;
-    __shared__ uint32_t s_pq[MQ], s_tp[MR];  // |q| of the tile's queries, |t| of its rows
-    __shared__ u64 s_th[MQ];                 // the queries' candidate bounds
-    __shared__ float s_cmin[MQ];             // per query: the least overlap that can reach its bound
+    // Per tile row (queries 0..255, then rows): |q| or |t|, and for queries the
+    // candidate bound and the least overlap that can reach it (the row half of
+    // these two is written but not read, so every thread stores alike).  Two
+    // sets: the current tile's, and the next tile's, written during the current tile.
+    __shared__ uint32_t s_p[2][MQ + MR];
+    __shared__ u64 s_th[2][MQ + MR];
+    __shared__ float s_cmin[2][MQ + MR];
     const uint64_t n_tiles = (uint64_t)n_qtiles * ((n + MR - 1) / MR);
-    for (uint64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
-        // consecutive tiles share a row tile and spread over the XCDs, so every
-        // XCD's L2 keeps a few query tiles resident while the rows stream through
-        const uint32_t qt = (uint32_t)(tile % n_qtiles);
-        const uint64_t rt = tile / n_qtiles;
-        const uint32_t q0 = qt * MQ;
-        const uint64_t t0 = rt * MR;
-        const int r = mt::own_row();
+    const int r = mt::own_row();
+    const bool arow = r < MQ;  // the same in a whole wave
+    // this thread's row of tile `tile` and the index of its metadata (always in bounds)
+    struct Part {
         const uint4 *row;
         bool ok;
-        if (r < MQ) {
-            ok = q0 + r < nq;
-            row = ok ? q + (uint64_t)(q0 + r) * 32 : q;
-            const uint32_t pq = ok ? qpop[q0 + r] : 0;
-            const u64 th = ok ? thr[q0 + r] : 0;
-            s_pq[r] = pq;
-            s_th[r] = th;
-            // K = |q|*wB + |t|*wA - C*(wA + wB) >= |q|*wB - C*(wA + wB): a row
-            // with C below cmin has K above the bound's key
-            const uint32_t wa = pq > 1 ? pq : 1, wb = (QD_BITS - pq) > 1 ? QD_BITS - pq : 1;
-            const int64_t X = (int64_t)pq * wb - (int64_t)(th >> 32);
-            const uint32_t cmin = X <= 0 ? 0u : ((uint32_t)X + wa + wb - 1) / (wa + wb);  // 0 < X < 2^24
-            s_cmin[r] = ok ? (float)cmin : 1e30f;
+        uint64_t at;  // query or row index whose |q| / bound or |t| this thread loads
+    };
+    auto part_of = [&](uint64_t tile) {
+        const uint32_t q0 = (uint32_t)(tile % n_qtiles) * MQ;
+        const uint64_t t0 = tile / n_qtiles * MR;
+        Part p;
+        if (arow) {
+            p.ok = q0 + r < nq;
+            p.at = p.ok ? q0 + r : 0;
+            p.row = q + p.at * 32;
         } else {
-            ok = t0 + (r - MQ) < n;
-            row = ok ? db + (t0 + (r - MQ)) * 32 : db;
-            s_tp[r - MQ] = ok ? tpop[t0 + (r - MQ)] : 0;
+            p.ok = t0 + (r - MQ) < n;
+            p.at = p.ok ? t0 + (r - MQ) : 0;
+            p.row = db + p.at * 32;
         }
+        return p;
+    };
+    // loads of a part's metadata: issued one window before they are used
+    uint32_t lp;  // |q| or |t|
+    u64 lt;       // the query's bound
+    auto issue = [&](const Part &p) {
+        lp = arow ? qpop[p.at] : tpop[p.at];
+        lt = thr[arow ? p.at : 0];
+    };
+    auto publish = [&](const Part &p, int h) {  // read after the next barrier; no branch
+        const uint32_t pv = p.ok ? lp : 0;
+        const u64 th = p.ok && arow ? lt : 0;
+        // K = |q|*wB + |t|*wA - C*(wA + wB) >= |q|*wB - C*(wA + wB): a row
+        // with C below cmin has K above the bound's key
+        const uint32_t wa = pv > 1 ? pv : 1, wb = (QD_BITS - pv) > 1 ? QD_BITS - pv : 1;
+        const int64_t X = (int64_t)pv * wb - (int64_t)(th >> 32);
+        // X <= 0 gives 0 either way; dividing always keeps the store free of branches
+        const uint32_t cmin = ((uint32_t)(X > 0 ? X : 0) + wa + wb - 1) / (wa + wb);  // X < 2^24
+        s_p[h][r] = pv;
+        s_th[h][r] = th;
+        s_cmin[h][r] = p.ok ? (float)cmin : 1e30f;
+    };
+    uint64_t tile = blockIdx.x;
+    if (tile >= n_tiles) return;  // whole workgroup
+    Part cur = part_of(tile);
+    issue(cur);
+    int h = 0;  // the current tile's metadata set
+    publish(cur, h);
+    mt::Stream st;
+    mt::stream_begin(cur.row, !cur.ok, sm, st);  // its barrier also publishes the metadata
+    for (;;) {
+        const uint64_t tn = tile + gridDim.x;
+        const bool more = tn < n_tiles;
+        const Part nx = part_of(more ? tn : tile);
+        const bool nzero = !more || !nx.ok;
         mt::v4f acc[8][4];
-        mt::overlap_tile(row, !ok, sm, acc);  // its barriers also publish the metadata above
+        // the next tile's metadata: loaded after every window and stored after
+        // the next one (a window later, so no store waits for its load) into
+        // the other set, which the previous tile's epilogue finished reading;
+        // the same code after every window keeps the window loop one block
+        // (after window 0 the set receives this tile's metadata, overwritten
+        // after window 1)
+        mt::stream_tile(cur.row, !cur.ok, nx.row, nzero, sm, st, acc, [&](int) {
+            publish(nx, h ^ 1);
+            issue(nx);
+        });
+        const uint32_t q0 = (uint32_t)(tile % n_qtiles) * MQ;
+        const uint64_t t0 = tile / n_qtiles * MR;
 
         // epilogue: keys of this lane's 32 queries x 4 rows
 #pragma unroll
@@ -87,19 +137,19 @@ __global__ __launch_bounds__(mt::kThreads) void scan_mfma_kernel(const uint4 *__
                 const int ai = mt::acc_arow(a, rr);
                 // test this lane's 4 rows of the query at once (most miss by far)
                 const float mx = fmaxf(fmaxf(acc[a][0][rr], acc[a][1][rr]), fmaxf(acc[a][2][rr], acc[a][3][rr]));
-                if (mx < s_cmin[ai]) continue;
+                if (mx < s_cmin[h][ai]) continue;
                 const uint32_t qi = q0 + ai;
                 if (qi >= nq) continue;
-                const uint32_t pq = s_pq[ai];
+                const uint32_t pq = s_p[h][ai];
                 const uint32_t wa = pq > 1 ? pq : 1, wb = (QD_BITS - pq) > 1 ? QD_BITS - pq : 1;
-                const u64 th = s_th[ai];
+                const u64 th = s_th[h][ai];
 #pragma unroll
                 for (int b = 0; b < 4; b++) {
                     const int bi = mt::acc_brow(b);
                     const uint64_t t = t0 + bi;
                     if (t >= n) continue;
                     const uint32_t C = mt::count(acc[a][b][rr]);
-                    const uint32_t K = (pq - C) * wb + (s_tp[bi] - C) * wa;
+                    const uint32_t K = (pq - C) * wb + (s_p[h][MQ + bi] - C) * wa;
                     const u64 key = ((u64)K << 32) | (uint32_t)t;
                     if (key <= th) {
                         const uint32_t pos = atomicAdd(&cnt[qi], 1u);
@@ -108,7 +158,11 @@ __global__ __launch_bounds__(mt::kThreads) void scan_mfma_kernel(const uint4 *__
                 }
             }
         }
-        __syncthreads();  // the next tile rewrites the metadata
+        __syncthreads();  // this set is rewritten during the next tile
+        if (!more) break;
+        h ^= 1;
+        cur = nx;
+        tile = tn;
     }
 }
 
@@ -237,7 +291,9 @@ int knn_bruteforce_mfma(const uint64_t *d_db, uint64_t n, const uint64_t *d_q, u
         return done(fail(QD_ERR_DEVICE, "memset"));
     {
         KernelTimer timer(g_sample_depth ? "wh_scan_mfma_sample" : "wh_scan_mfma", s);
-        hipLaunchKernelGGL(scan_mfma_kernel, dim3((uint32_t)mt::tile_grid(n_qtiles * n_rtiles)), dim3(mt::kThreads), 0, s,
+        // persistent: one workgroup per CU (the tile's LDS and registers leave room for one)
+        const uint64_t grid = std::min<uint64_t>(n_qtiles * n_rtiles, (uint64_t)device_cus());
+        hipLaunchKernelGGL(scan_mfma_kernel, dim3((uint32_t)grid), dim3(mt::kThreads), 0, s,
                            reinterpret_cast<const uint4 *>(d_db), n, reinterpret_cast<const uint4 *>(d_q), nq, tpop,
                            qpop, thr, n_qtiles, cnt, cand);
     }
