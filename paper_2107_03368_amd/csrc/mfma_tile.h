@@ -3,11 +3,12 @@
 // C[i][j] = popcount(A_i AND B_j), the term every weighted distance and every
 // node bound of Eq. 1 is built from.  Over the 4096 bit positions this is a
 // dense {0,1} matrix product.  It runs as the FP4 (e2m1) matrix instruction
-// v_mfma_scale_f32_16x16x128_f8f6f4: every bit becomes one 4-bit element
-// (0 or 0.5), both operands carry the block scale 2, so every product is 0
-// or 1 and the fp32 accumulator holds the exact count (at most 4096 < 2^24).
-// The order in which bits become elements only has to be the same for both
-// operands, since the sum over K does not depend on it.
+// v_mfma_scale_f32_16x16x128_f8f6f4: every bit becomes one 4-bit element,
+// zero or a power of two whose value on the A side is the reciprocal of its
+// value on the B side, so every product is 0 or 1 and the fp32 accumulator
+// holds the exact count (at most 4096 < 2^24).  The order in which bits
+// become elements only has to be the same for both operands, since the sum
+// over K does not depend on it.
 //
 // A block of 8 waves owns the 256 x 256 tile, and thread t owns row t (A rows
 // 0..255, then B rows).  The K dimension is streamed in windows of 512 bits:
@@ -19,8 +20,8 @@
 // step s of a window, lane l reads one 32-bit word of a row, word 4s + l/16
 // of row l % 16 of each fragment, and expands it in registers to the 32
 // elements the instruction takes from it (k = 32*(l/16) .. +31): element
-// 8j + i holds bit 4i + j, so four shift-and-mask operations make the 16
-// bytes.  With rows 18 words apart the 64 lanes of such a read fall on
+// 8j + i holds bit 4i + j, so a few shift-and-mask operations make the 16
+// bytes (expand_a, expand_b).  With rows 18 words apart the 64 lanes of such a read fall on
 // distinct banks in each half.  The words of the next step are read while
 // the current one runs.  Lane l receives C rows 4*(l/16) .. +3 of column
 // l % 16.
@@ -49,11 +50,19 @@ struct Smem {
     uint8_t rw[NBUF][(MA + MB) * RST];  // packed windows
 };
 
-// 32 bits -> the 32 e2m1 elements (0 or 0.5) of one lane's operand: element
-// 8j + i (nibble i of word j) holds bit 4i + j
-__device__ __forceinline__ v8i expand(uint32_t w) {
+// 32 bits -> the 32 e2m1 elements of one lane's operand: element 8j + i
+// (nibble i of word j) comes from bit 4i + j.  The A side keeps bits 0..2 of
+// each nibble where they are (values 0.5, 1 and 2) and moves bit 3, the e2m1
+// sign bit, to bit 2 (value 2); the B side gives the same bits the reciprocal
+// values (2, 1, 0.5 and 0.5), so the product of two set bits is exactly 1
+// and three of the A side's four words need no shift.
+__device__ __forceinline__ v8i expand_a(uint32_t w) {
     constexpr uint32_t M = 0x11111111u;
-    return v8i{(int)(w & M), (int)((w >> 1) & M), (int)((w >> 2) & M), (int)((w >> 3) & M), 0, 0, 0, 0};
+    return v8i{(int)(w & M), (int)(w & (M << 1)), (int)(w & (M << 2)), (int)((w >> 1) & (M << 2)), 0, 0, 0, 0};
+}
+__device__ __forceinline__ v8i expand_b(uint32_t w) {
+    constexpr uint32_t M = 0x11111111u;
+    return v8i{(int)((w << 2) & (M << 2)), (int)(w & (M << 1)), (int)((w >> 2) & M), (int)((w >> 3) & M), 0, 0, 0, 0};
 }
 
 // Workgroups are dispatched to the 8 XCDs round-robin (workgroup x runs on
@@ -175,15 +184,15 @@ __device__ __forceinline__ void stream_tile(const uint4 *row, bool zero, const u
     auto step = [&](const uint32_t (&x)[12]) {
         v8i bv[4];
 #pragma unroll
-        for (int b = 0; b < 4; b++) bv[b] = expand(x[8 + b]);
+        for (int b = 0; b < 4; b++) bv[b] = expand_b(x[8 + b]);
 #pragma unroll
         for (int a = 0; a < 8; a++) {
-            const v8i av = expand(x[a]);
+            const v8i av = expand_a(x[a]);
 #pragma unroll
             for (int b = 0; b < 4; b++)
-                // formats 4 = e2m1 for both operands; scales 128 = 2^1
+                // formats 4 = e2m1 for both operands; scales 127 = 2^0
                 acc[a][b] =
-                    __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(av, bv[b], acc[a][b], 4, 4, 0, 128, 0, 128);
+                    __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(av, bv[b], acc[a][b], 4, 4, 0, 127, 0, 127);
         }
     };
     // Every window runs the same code, so the compiler keeps one loop instead
