@@ -404,7 +404,7 @@ __global__ __launch_bounds__(256) void round1_kernel(const uint4 *__restrict__ q
 __global__ __launch_bounds__(256) void list_kernel(const uint16_t *__restrict__ lbb, uint64_t nblk, uint64_t n,
                                                    uint32_t nqb, uint32_t nqp, const u64 *__restrict__ rec,
                                                    const u64 *__restrict__ frange, uint32_t *__restrict__ done,
-                                                   uint64_t dw, uint16_t *__restrict__ list,
+                                                   uint16_t *__restrict__ list,
                                                    uint32_t *__restrict__ cnt, uint32_t *__restrict__ qst) {
     __shared__ uint16_t s_fill[4][kGroup][mt::MA - 1];  // per wave and block: fill candidates
     const int lane = lane_id();
@@ -417,48 +417,65 @@ __global__ __launch_bounds__(256) void list_kernel(const uint16_t *__restrict__ 
     uint32_t c[kGroup], f[kGroup];
 #pragma unroll
     for (int jj = 0; jj < kGroup; jj++) c[jj] = f[jj] = 0;
-    for (uint32_t q0 = 0; q0 < nqb; q0 += 64) {
-        const uint32_t qi = q0 + (uint32_t)lane;
-        u64 lo = 0, hi = 0, flo = 0, fhi = 0;
-        if (qi < nqb) {
-            lo = rec[2 * qi];
-            hi = rec[2 * qi + 1];
-            if (hi > lo) {  // only a query running this round has its candidates merged
-                flo = frange[2 * qi];
-                fhi = frange[2 * qi + 1];
-            }
-        }
-        if (ballot(hi > lo) == 0) continue;
-        const uint32_t dbits = hi > lo ? done[(uint64_t)qi * dw + dword] >> dshift : 0;
-        uint32_t mb = 0, mr = 0;
+    // kChunks chunks of 64 queries at a time: all their loads are issued first
+    // (unconditionally, in bounds), so the walk waits for memory once per
+    // kChunks chunks instead of twice per chunk
+    constexpr int kChunks = 2;
+    for (uint32_t q00 = 0; q00 < nqb; q00 += 64 * kChunks) {
+        u64 rlo[kChunks], rhi[kChunks], rflo[kChunks], rfhi[kChunks];
+        uint32_t rdone[kChunks];
+        uint16_t rlv[kChunks][kGroup];
 #pragma unroll
-        for (int jj = 0; jj < kGroup; jj++) {
-            if ((uint32_t)jj < nb) {
-                const uint64_t b = b0 + jj;
-                const uint32_t lv = lbb[b * nqp + qi];
-                const u64 key = range_key(lv, (uint32_t)b);
-                const bool d = (dbits >> jj) & 1u;
-                const bool m = key > lo && key <= hi && !d;
-                const u64 mask = ballot(m);
-                if (m) list[b * nqp + c[jj] + lanes_below(mask)] = (uint16_t)qi;
-                c[jj] += (uint32_t)__popcll(mask);
-                if (m) {
-                    mb++;
-                    mr += b + 1 < nblk ? (uint32_t)kBlk : (uint32_t)(n - b * kBlk);
-                }
-                if (f[jj] < mt::MA - 1) {  // fill candidates, in query order
-                    const bool mf = key > flo && key <= fhi && !d;
-                    const u64 fmask = ballot(mf);
-                    const uint32_t at = f[jj] + lanes_below(fmask);
-                    if (mf && at < mt::MA - 1) fillq[jj][at] = (uint16_t)qi;
-                    const uint32_t t = f[jj] + (uint32_t)__popcll(fmask);
-                    f[jj] = t < mt::MA - 1 ? t : mt::MA - 1;
+        for (int u = 0; u < kChunks; u++) {
+            const uint32_t qi = q00 + 64 * u + (uint32_t)lane;
+            const uint32_t qc = qi < nqb ? qi : nqb - 1;
+            rlo[u] = rec[2 * qc];
+            rhi[u] = rec[2 * qc + 1];
+            rflo[u] = frange[2 * qc];
+            rfhi[u] = frange[2 * qc + 1];
+            rdone[u] = done[(uint64_t)dword * nqp + qc];
+#pragma unroll
+            for (int jj = 0; jj < kGroup; jj++)
+                rlv[u][jj] = lbb[(b0 + ((uint32_t)jj < nb ? jj : 0)) * nqp + qc];
+        }
+#pragma unroll
+        for (int u = 0; u < kChunks; u++) {
+            const uint32_t qi = q00 + 64 * u + (uint32_t)lane;
+            const bool in = qi < nqb;
+            const u64 lo = in ? rlo[u] : 0, hi = in ? rhi[u] : 0;
+            const bool run = hi > lo;  // only a query running this round has its candidates merged
+            const u64 flo = run ? rflo[u] : 0, fhi = run ? rfhi[u] : 0;
+            if (ballot(run) == 0) continue;
+            const uint32_t dbits = run ? rdone[u] >> dshift : 0;
+            uint32_t mb = 0, mr = 0;
+#pragma unroll
+            for (int jj = 0; jj < kGroup; jj++) {
+                if ((uint32_t)jj < nb) {
+                    const uint64_t b = b0 + jj;
+                    const u64 key = range_key(rlv[u][jj], (uint32_t)b);
+                    const bool d = (dbits >> jj) & 1u;
+                    const bool m = key > lo && key <= hi && !d;
+                    const u64 mask = ballot(m);
+                    if (m) list[b * nqp + c[jj] + lanes_below(mask)] = (uint16_t)qi;
+                    c[jj] += (uint32_t)__popcll(mask);
+                    if (m) {
+                        mb++;
+                        mr += b + 1 < nblk ? (uint32_t)kBlk : (uint32_t)(n - b * kBlk);
+                    }
+                    if (f[jj] < mt::MA - 1) {  // fill candidates, in query order
+                        const bool mf = key > flo && key <= fhi && !d;
+                        const u64 fmask = ballot(mf);
+                        const uint32_t at = f[jj] + lanes_below(fmask);
+                        if (mf && at < mt::MA - 1) fillq[jj][at] = (uint16_t)qi;
+                        const uint32_t t = f[jj] + (uint32_t)__popcll(fmask);
+                        f[jj] = t < mt::MA - 1 ? t : mt::MA - 1;
+                    }
                 }
             }
-        }
-        if (qst && mb) {
-            atomicAdd(&qst[(uint64_t)qi * 4 + 0], mb);
-            atomicAdd(&qst[(uint64_t)qi * 4 + 3], mr);
+            if (qst && mb) {
+                atomicAdd(&qst[(uint64_t)qi * 4 + 0], mb);
+                atomicAdd(&qst[(uint64_t)qi * 4 + 3], mr);
+            }
         }
     }
     // the first candidates fill the last tile's free slots
@@ -469,7 +486,7 @@ __global__ __launch_bounds__(256) void list_kernel(const uint16_t *__restrict__ 
         for (uint32_t i = (uint32_t)lane; i < take; i += 64) {
             const uint32_t qi = fillq[jj][i];  // written by this wave above (LDS keeps its order)
             list[b * nqp + c[jj] + i] = (uint16_t)qi;
-            atomicOr(&done[(uint64_t)qi * dw + dword], 1u << (dshift + jj));
+            atomicOr(&done[(uint64_t)dword * nqp + qi], 1u << (dshift + jj));
             if (qst) {
                 atomicAdd(&qst[(uint64_t)qi * 4 + 0], 1u);
                 atomicAdd(&qst[(uint64_t)qi * 4 + 3], b + 1 < nblk ? (uint32_t)kBlk : (uint32_t)(n - b * kBlk));
@@ -772,7 +789,7 @@ __global__ __launch_bounds__(256) void select_kernel(uint32_t k, const uint16_t 
                                                      uint32_t *__restrict__ ntop, uint32_t *__restrict__ thrk,
                                                      uint32_t *__restrict__ counters, uint32_t *__restrict__ redo,
                                                      uint32_t *__restrict__ qst, const uint16_t *__restrict__ lbq,
-                                                     uint64_t nblk, uint32_t *__restrict__ done, uint64_t dw,
+                                                     uint64_t nblk, uint32_t *__restrict__ done, uint64_t dw, uint32_t nqp,
                                                      u64 *__restrict__ frange) {
     __shared__ u64 keys[8192];
     const uint32_t qi = blockIdx.x;
@@ -808,7 +825,7 @@ __global__ __launch_bounds__(256) void select_kernel(uint32_t k, const uint16_t 
                 const uint64_t b = wd * 32 + j;
                 if (b < nblk && range_key(lbq[(uint64_t)qi * nblk + b], (uint32_t)b) > end) clear |= 1u << j;
             }
-            done[(uint64_t)qi * dw + wd] &= ~clear;
+            done[(uint64_t)wd * nqp + qi] &= ~clear;
         }
     }
     if (threadIdx.x != 0) return;
@@ -988,9 +1005,9 @@ int knn_tree_blocked(qd_tree_t t, const uint64_t *d_q, uint32_t nq, uint32_t k, 
         const uint4 *q4 = reinterpret_cast<const uint4 *>(qq);
         rc = popcount_rows_launch(qq, nqb, qpop, s);
         if (rc != QD_OK) return done(rc);
-        const uint64_t dw = (nblk + 31) / 32;  // done-bit words per query
+        const uint64_t dw = (nblk + 31) / 32;  // done-bit words per query, stored word-major (word, query)
         if (hipMemsetAsync(ccnt, 0, (size_t)nqb * 4, s) != hipSuccess || hipMemsetAsync(ctr, 0, 16, s) != hipSuccess ||
-            hipMemsetAsync(donebits, 0, (size_t)nqb * dw * 4, s) != hipSuccess)
+            hipMemsetAsync(donebits, 0, (size_t)nqp * dw * 4, s) != hipSuccess)
             return done(fail(QD_ERR_DEVICE, "memset"));
         const uint32_t n_qtiles = nqp / mt::MA;
         const uint64_t n_btiles = (nblk + mt::MB - 1) / mt::MB;
@@ -1022,7 +1039,7 @@ int knn_tree_blocked(qd_tree_t t, const uint64_t *d_q, uint32_t nq, uint32_t k, 
                 KernelTimer timer("tree_block_lists", s);
                 const uint64_t waves = (nblk + kGroup - 1) / kGroup;
                 hipLaunchKernelGGL(list_kernel, dim3((uint32_t)((waves + 3) / 4)), dim3(256), 0, s, lbb, nblk, n, nqb,
-                                   nqp, rec, frange, donebits, dw, list, cnt, want_stats ? qst : nullptr);
+                                   nqp, rec, frange, donebits, list, cnt, want_stats ? qst : nullptr);
                 hipLaunchKernelGGL(tile_scan_kernel, dim3(1), dim3(1024), 0, s, cnt, nblk, t->d_bpop, off, voff, tinfo,
                                    ctr + 2);
             }
@@ -1058,7 +1075,7 @@ int knn_tree_blocked(qd_tree_t t, const uint64_t *d_q, uint32_t nq, uint32_t k, 
             {
                 KernelTimer timer("tree_block_select", s);
                 hipLaunchKernelGGL(select_kernel, dim3(nqb), dim3(256), 0, s, k, qpop, cuts, rec, qround, ccnt, cand,
-                                   top, ntop, thr, ctr, redo, want_stats ? qst : nullptr, lbq, nblk, donebits, dw,
+                                   top, ntop, thr, ctr, redo, want_stats ? qst : nullptr, lbq, nblk, donebits, dw, nqp,
                                    frange);
             }
             if (hipGetLastError() != hipSuccess) return done(fail(QD_ERR_DEVICE, "blocked search: launch failed"));
