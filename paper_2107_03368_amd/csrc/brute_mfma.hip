@@ -56,6 +56,11 @@ __global__ __launch_bounds__(mt::kThreads) void scan_mfma_kernel(const uint4 *__
     __shared__ uint32_t s_p[2][MQ + MR];
     __shared__ u64 s_th[2][MQ + MR];
     __shared__ float s_cmin[2][MQ + MR];
+    // per wave: the tile's passing (query, key, row) entries, appended in order
+    // and written out together, so the candidate slots' atomics overlap
+    // instead of waiting one after another
+    constexpr uint32_t kQueue = 320;  // room for one (a, rr) group's 256 entries past the flush mark
+    __shared__ uint32_t s_cq[mt::kThreads / 64][kQueue][3];
     const uint64_t n_tiles = (uint64_t)n_qtiles * ((n + MR - 1) / MR);
     const int r = mt::own_row();
     const bool arow = r < MQ;  // the same in a whole wave
@@ -128,6 +133,17 @@ __global__ __launch_bounds__(mt::kThreads) void scan_mfma_kernel(const uint4 *__
         const uint64_t t0 = tile / n_qtiles * MR;
 
         // epilogue: keys of this lane's 32 queries x 4 rows
+        const int lane = r & 63;
+        uint32_t (*cq)[3] = s_cq[r >> 6];
+        uint32_t nqe = 0;  // entries in this wave's queue (the same in every lane)
+        auto flush = [&]() {
+            for (uint32_t e = lane; e < nqe; e += 64) {
+                const uint32_t qi = cq[e][0];
+                const uint32_t pos = atomicAdd(&cnt[qi], 1u);
+                if (pos < kCap) cand[(uint64_t)qi * kCap + pos] = ((u64)cq[e][1] << 32) | cq[e][2];
+            }
+            nqe = 0;
+        };
 #pragma unroll
         for (int a = 0; a < 8; a++) {
             // one group of queries at a time, so their metadata loads stay next to their use
@@ -137,9 +153,9 @@ __global__ __launch_bounds__(mt::kThreads) void scan_mfma_kernel(const uint4 *__
                 const int ai = mt::acc_arow(a, rr);
                 // test this lane's 4 rows of the query at once (most miss by far)
                 const float mx = fmaxf(fmaxf(acc[a][0][rr], acc[a][1][rr]), fmaxf(acc[a][2][rr], acc[a][3][rr]));
-                if (mx < s_cmin[h][ai]) continue;
                 const uint32_t qi = q0 + ai;
-                if (qi >= nq) continue;
+                const bool act = mx >= s_cmin[h][ai] && qi < nq;
+                if (ballot(act) == 0) continue;
                 const uint32_t pq = s_p[h][ai];
                 const uint32_t wa = pq > 1 ? pq : 1, wb = (QD_BITS - pq) > 1 ? QD_BITS - pq : 1;
                 const u64 th = s_th[h][ai];
@@ -147,17 +163,23 @@ __global__ __launch_bounds__(mt::kThreads) void scan_mfma_kernel(const uint4 *__
                 for (int b = 0; b < 4; b++) {
                     const int bi = mt::acc_brow(b);
                     const uint64_t t = t0 + bi;
-                    if (t >= n) continue;
                     const uint32_t C = mt::count(acc[a][b][rr]);
                     const uint32_t K = (pq - C) * wb + (s_p[h][MQ + bi] - C) * wa;
                     const u64 key = ((u64)K << 32) | (uint32_t)t;
-                    if (key <= th) {
-                        const uint32_t pos = atomicAdd(&cnt[qi], 1u);
-                        if (pos < kCap) cand[(uint64_t)qi * kCap + pos] = key;
+                    const bool pass = act && t < n && key <= th;
+                    const u64 pm = ballot(pass);
+                    if (pass) {
+                        const uint32_t e = nqe + lanes_below(pm);
+                        cq[e][0] = qi;
+                        cq[e][1] = K;
+                        cq[e][2] = (uint32_t)t;
                     }
+                    nqe += (uint32_t)__popcll(pm);
                 }
+                if (nqe > kQueue - 256) flush();  // the next group adds at most 4 x 64
             }
         }
+        flush();
         __syncthreads();  // this set is rewritten during the next tile
         if (!more) break;
         h ^= 1;

@@ -90,10 +90,6 @@ __device__ __forceinline__ void set_fill_range(u64 *fr, const u64 *c, uint32_t r
 }
 __device__ __forceinline__ uint32_t weight_b(uint32_t pq) { return (QD_BITS - pq) > 1 ? QD_BITS - pq : 1; }
 
-__device__ __forceinline__ uint32_t lanes_below(u64 mask) {
-    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
-}
-
 // OR image of each block of 256 leaf-order rows; one 64-thread block per
 // image, thread w owns word w.  With bpop, also the smallest and largest
 // popcount of the block's rows.
@@ -634,6 +630,11 @@ __global__ __launch_bounds__(mt::kThreads) void eval_kernel(const uint4 *__restr
     __shared__ mt::Smem sm;
     __shared__ uint32_t s_qi[mt::MA], s_pq[mt::MA], s_th[mt::MA], s_tp[mt::MB];
     __shared__ float s_cmin[mt::MA];  // per query slot: the least overlap that can reach its k-th key
+    // per wave: the tile's passing (query, key, row) entries, appended in order
+    // and written out together, so the candidate slots' atomics overlap
+    // instead of waiting one after another
+    constexpr uint32_t kQueue = 320;  // room for one (a, rr) group's 256 entries past the flush mark
+    __shared__ uint32_t s_cq[mt::kThreads / 64][kQueue][3];
     const uint64_t vend = mt::xcd_grid(total);
     const int r = mt::own_row();
     const bool arow = r < mt::MA;  // the same in a whole wave
@@ -734,6 +735,17 @@ __global__ __launch_bounds__(mt::kThreads) void eval_kernel(const uint4 *__restr
         });
         const uint64_t r0 = (uint64_t)cur.x * kBlk;
         const uint32_t m = cur.z;
+        const int wv = r >> 6, lane = r & 63;
+        uint32_t (*cq)[3] = s_cq[wv];
+        uint32_t nq = 0;  // entries in this wave's queue (the same in every lane)
+        auto flush = [&]() {
+            for (uint32_t e = lane; e < nq; e += 64) {
+                const uint32_t qk = cq[e][0], K = cq[e][1], rw = cq[e][2];
+                const uint32_t pos = atomicAdd(&ccnt[qk], 1u);
+                if (pos < kCap) cand[(uint64_t)qk * kCap + pos] = ((u64)K << 32) | perm[rw];
+            }
+            nq = 0;
+        };
 #pragma unroll
         for (int a = 0; a < 8; a++) {
             // one group of queries at a time, so their metadata loads stay next to their use
@@ -744,8 +756,8 @@ __global__ __launch_bounds__(mt::kThreads) void eval_kernel(const uint4 *__restr
                 // most (query, row) pairs miss the k-th key by far: test this
                 // lane's 4 rows at once against the least useful overlap
                 const float mx = fmaxf(fmaxf(acc[a][0][rr], acc[a][1][rr]), fmaxf(acc[a][2][rr], acc[a][3][rr]));
-                if (mx < s_cmin[i]) continue;
-                if (i >= m) continue;
+                const bool act = mx >= s_cmin[i] && i < m;
+                if (ballot(act) == 0) continue;
                 const uint32_t qk = s_qi[i];
                 const uint32_t pk = s_pq[i];
                 const uint32_t wa = weight_a(pk), wb = weight_b(pk);
@@ -754,16 +766,22 @@ __global__ __launch_bounds__(mt::kThreads) void eval_kernel(const uint4 *__restr
                 for (int bb = 0; bb < 4; bb++) {
                     const int bi = mt::acc_brow(bb);
                     const uint64_t rw = r0 + bi;
-                    if (rw >= n) continue;
                     const uint32_t C = mt::count(acc[a][bb][rr]);
                     const uint32_t K = (pk - C) * wb + (s_tp[bi] - C) * wa;
-                    if (K <= tk) {
-                        const uint32_t pos = atomicAdd(&ccnt[qk], 1u);
-                        if (pos < kCap) cand[(uint64_t)qk * kCap + pos] = ((u64)K << 32) | perm[rw];
+                    const bool pass = act && rw < n && K <= tk;
+                    const u64 pm = ballot(pass);
+                    if (pass) {
+                        const uint32_t e = nq + lanes_below(pm);
+                        cq[e][0] = qk;
+                        cq[e][1] = K;
+                        cq[e][2] = (uint32_t)rw;
                     }
+                    nq += (uint32_t)__popcll(pm);
                 }
+                if (nq > kQueue - 256) flush();  // the next group adds at most 4 x 64
             }
         }
+        flush();
         __syncthreads();  // the metadata is rewritten next
         if (!more) break;
         publish(ncmin);
