@@ -388,8 +388,38 @@ __global__ __launch_bounds__(256) void round1_kernel(const uint4 *__restrict__ q
     }
 }
 
+// The queries running this round (rec[2q + 1] > rec[2q]), in query order:
+// act[0 .. *nact).  One block of 1024 threads.
+__global__ __launch_bounds__(1024) void active_kernel(const u64 *__restrict__ rec, uint32_t nqb,
+                                                      uint32_t *__restrict__ act, uint32_t *__restrict__ nact) {
+    __shared__ uint32_t wsum[16];
+    __shared__ uint32_t base;
+    const uint32_t tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    if (tid == 0) base = 0;
+    __syncthreads();
+    for (uint32_t q0 = 0; q0 < nqb; q0 += 1024) {
+        const uint32_t qi = q0 + tid;
+        const bool run = qi < nqb && rec[2 * qi + 1] > rec[2 * qi];
+        const u64 m = ballot(run);
+        if (lane == 0) wsum[w] = (uint32_t)__popcll(m);
+        __syncthreads();
+        uint32_t before = base;
+        for (uint32_t v = 0; v < w; v++) before += wsum[v];
+        if (run) act[before + lanes_below(m)] = qi;
+        __syncthreads();
+        if (tid == 0) {
+            uint32_t t = 0;
+            for (uint32_t v = 0; v < 16; v++) t += wsum[v];
+            base += t;
+        }
+        __syncthreads();
+    }
+    if (tid == 0) *nact = base;
+}
+
 // Per-block query lists for one round: wave w of block x handles the
-// kGroup blocks starting at (4x + w) * kGroup and walks the queries in order.
+// kGroup blocks starting at (4x + w) * kGroup and walks the running queries
+// (act, in query order).
 // A query is listed for a block whose key lies in its range of this round,
 // unless an earlier round already evaluated the pair (done bit).  The same
 // walk collects, per block, up to 255 queries whose next round covers the
@@ -398,7 +428,8 @@ __global__ __launch_bounds__(256) void round1_kernel(const uint4 *__restrict__ q
 // Filling uses the tile the round runs anyway; such a pair is evaluated once,
 // against a k-th key at least as large as the next round's, so no row is lost.
 __global__ __launch_bounds__(256) void list_kernel(const uint16_t *__restrict__ lbb, uint64_t nblk, uint64_t n,
-                                                   uint32_t nqb, uint32_t nqp, const u64 *__restrict__ rec,
+                                                   uint32_t nqp, const uint32_t *__restrict__ act,
+                                                   const uint32_t *__restrict__ nact, const u64 *__restrict__ rec,
                                                    const u64 *__restrict__ frange, uint32_t *__restrict__ done,
                                                    uint16_t *__restrict__ list,
                                                    uint32_t *__restrict__ cnt, uint32_t *__restrict__ qst) {
@@ -417,14 +448,19 @@ __global__ __launch_bounds__(256) void list_kernel(const uint16_t *__restrict__ 
     // (unconditionally, in bounds), so the walk waits for memory once per
     // kChunks chunks instead of twice per chunk
     constexpr int kChunks = 2;
-    for (uint32_t q00 = 0; q00 < nqb; q00 += 64 * kChunks) {
+    const uint32_t na = readfirst(*nact);
+    for (uint32_t i00 = 0; i00 < na; i00 += 64 * kChunks) {
         u64 rlo[kChunks], rhi[kChunks], rflo[kChunks], rfhi[kChunks];
-        uint32_t rdone[kChunks];
+        uint32_t rdone[kChunks], rq[kChunks];
         uint16_t rlv[kChunks][kGroup];
 #pragma unroll
         for (int u = 0; u < kChunks; u++) {
-            const uint32_t qi = q00 + 64 * u + (uint32_t)lane;
-            const uint32_t qc = qi < nqb ? qi : nqb - 1;
+            const uint32_t ia = i00 + 64 * u + (uint32_t)lane;
+            rq[u] = act[ia < na ? ia : na - 1];
+        }
+#pragma unroll
+        for (int u = 0; u < kChunks; u++) {
+            const uint32_t qc = rq[u];
             rlo[u] = rec[2 * qc];
             rhi[u] = rec[2 * qc + 1];
             rflo[u] = frange[2 * qc];
@@ -436,8 +472,8 @@ __global__ __launch_bounds__(256) void list_kernel(const uint16_t *__restrict__ 
         }
 #pragma unroll
         for (int u = 0; u < kChunks; u++) {
-            const uint32_t qi = q00 + 64 * u + (uint32_t)lane;
-            const bool in = qi < nqb;
+            const uint32_t qi = rq[u];
+            const bool in = i00 + 64 * u + (uint32_t)lane < na;
             const u64 lo = in ? rlo[u] : 0, hi = in ? rhi[u] : 0;
             const bool run = hi > lo;  // only a query running this round has its candidates merged
             const u64 flo = run ? rflo[u] : 0, fhi = run ? rfhi[u] : 0;
@@ -991,6 +1027,7 @@ int knn_tree_blocked(qd_tree_t t, const uint64_t *d_q, uint32_t nq, uint32_t k, 
                  a_list = take(P * nblk * 2), a_cuts = take(P * (kRounds + 1) * 8), a_r1 = take(P * kM1 * 4),
                  a_rec = take(P * 16), a_thr = take(P * 4), a_ntop = take(P * 4), a_top = take(P * k * 8),
                  a_ccnt = take(P * 4), a_cand = take(P * kCap * 8), a_cnt = take(nblk * 4), a_qr = take(P * 4),
+                 a_act = take(P * 4 + 4),
                  a_off = take((nblk + 1) * 4), a_voff = take((nblk + 1) * 4), a_ctr = take(16),
                  a_done = take(P * ((nblk + 31) / 32) * 4), a_fr = take(P * 16),
                  a_tblk = take(nblk * (P / mt::MA) * 16),  // tile records: at most ceil(nqb / 256) per block
@@ -1009,6 +1046,7 @@ int knn_tree_blocked(qd_tree_t t, const uint64_t *d_q, uint32_t nq, uint32_t k, 
     unsigned long long *gst = (unsigned long long *)(ws + a_gst);
     u64 *frange = (u64 *)(ws + a_fr);
     uint4 *tinfo = (uint4 *)(ws + a_tblk);
+    uint32_t *act = (uint32_t *)(ws + a_act), *nact = act + P;
     const bool want_stats = d_qstats || h_stats;
     int rc = QD_OK;
     auto done = [&](int code) {
@@ -1056,8 +1094,9 @@ int knn_tree_blocked(qd_tree_t t, const uint64_t *d_q, uint32_t nq, uint32_t k, 
             {
                 KernelTimer timer("tree_block_lists", s);
                 const uint64_t waves = (nblk + kGroup - 1) / kGroup;
-                hipLaunchKernelGGL(list_kernel, dim3((uint32_t)((waves + 3) / 4)), dim3(256), 0, s, lbb, nblk, n, nqb,
-                                   nqp, rec, frange, donebits, list, cnt, want_stats ? qst : nullptr);
+                hipLaunchKernelGGL(active_kernel, dim3(1), dim3(1024), 0, s, rec, nqb, act, nact);
+                hipLaunchKernelGGL(list_kernel, dim3((uint32_t)((waves + 3) / 4)), dim3(256), 0, s, lbb, nblk, n, nqp,
+                                   act, nact, rec, frange, donebits, list, cnt, want_stats ? qst : nullptr);
                 hipLaunchKernelGGL(tile_scan_kernel, dim3(1), dim3(1024), 0, s, cnt, nblk, t->d_bpop, off, voff, tinfo,
                                    ctr + 2);
             }
