@@ -35,10 +35,14 @@ constexpr int MR = mt::MB;        // rows per block
 constexpr uint32_t kCap = 8192;   // candidate slots per query
 thread_local int g_sample_depth = 0;  // > 0 inside the search of a threshold sample
 
-// Tiles of 256 queries x 256 rows in a persistent grid: workgroup x takes
-// tiles x, x + G, x + 2G, ... (G = gridDim.x).  Consecutive tiles share a row
-// tile and spread over the XCDs, so every XCD's L2 keeps a few query tiles
-// resident while the rows stream through.  The tiles are streamed: the next
+// Tiles of 256 queries x 256 rows in a persistent grid of G workgroups.
+// When the query tiles and G split evenly over the 8 XCDs, the workgroups of
+// XCD c (x % 8 == c) run the query tiles c, c + 8, ... against every row
+// tile, taking (row tile, query tile) pairs in order from a counter of their
+// own; otherwise all workgroups share one counter over all tiles.  Claimed in
+// order, as the hardware would dispatch one workgroup per tile, the few
+// tiles of a row tile run at about the same time, so each L2 fetches a row
+// tile once and keeps its XCD's queries.  The tiles are streamed: the next
 // tile's first two windows are staged during the current tile's last two and
 // its metadata is loaded during the current tile, so the matrix cores do not
 // wait for a tile to start.
@@ -47,6 +51,7 @@ __global__ __launch_bounds__(mt::kThreads) void scan_mfma_kernel(const uint4 *__
                                                                  const uint16_t *__restrict__ tpop,
                                                                  const uint16_t *__restrict__ qpop,
                                                                  const u64 *__restrict__ thr, uint32_t n_qtiles,
+                                                                 uint32_t *__restrict__ tctr,
                                                                  uint32_t *__restrict__ cnt, u64 *__restrict__ cand) {
     __shared__ mt::Smem sm;
     // Per tile row (queries 0..255, then rows): |q| or |t|, and for queries the
@@ -61,7 +66,6 @@ __global__ __launch_bounds__(mt::kThreads) void scan_mfma_kernel(const uint4 *__
     // instead of waiting one after another
     constexpr uint32_t kQueue = 320;  // room for one (a, rr) group's 256 entries past the flush mark
     __shared__ uint32_t s_cq[mt::kThreads / 64][kQueue][3];
-    const uint64_t n_tiles = (uint64_t)n_qtiles * ((n + MR - 1) / MR);
     const int r = mt::own_row();
     const bool arow = r < MQ;  // the same in a whole wave
     // this thread's row of tile `tile` and the index of its metadata (always in bounds)
@@ -70,9 +74,23 @@ __global__ __launch_bounds__(mt::kThreads) void scan_mfma_kernel(const uint4 *__
         bool ok;
         uint64_t at;  // query or row index whose |q| / bound or |t| this thread loads
     };
-    auto part_of = [&](uint64_t tile) {
-        const uint32_t q0 = (uint32_t)(tile % n_qtiles) * MQ;
-        const uint64_t t0 = tile / n_qtiles * MR;
+    // the claimable tiles: j = 0 .. count - 1 -> (query tile, row tile)
+    const uint64_t n_rtiles = (n + MR - 1) / MR, G = gridDim.x, x = blockIdx.x;
+    const bool by_xcd = n_qtiles % mt::kXcds == 0 && G % mt::kXcds == 0;
+    const uint32_t qper = by_xcd ? n_qtiles / mt::kXcds : n_qtiles;  // query tiles per row tile of a counter
+    const uint32_t cx = by_xcd ? (uint32_t)(x % mt::kXcds) : 0;
+    const uint64_t count = n_rtiles * qper;
+    uint32_t *ctr = tctr + cx;
+    auto coords = [&](uint64_t j, uint32_t &qt, uint64_t &rt) {
+        rt = j / qper;
+        qt = (by_xcd ? cx : 0) + (by_xcd ? mt::kXcds : 1) * (uint32_t)(j % qper);
+    };
+    auto part_of = [&](uint64_t j) {
+        uint32_t qt;
+        uint64_t rt;
+        coords(j, qt, rt);
+        const uint32_t q0 = qt * MQ;
+        const uint64_t t0 = rt * MR;
         Part p;
         if (arow) {
             p.ok = q0 + r < nq;
@@ -105,8 +123,14 @@ __global__ __launch_bounds__(mt::kThreads) void scan_mfma_kernel(const uint4 *__
         s_th[h][r] = th;
         s_cmin[h][r] = p.ok ? (float)cmin : 1e30f;
     };
-    uint64_t tile = blockIdx.x;
-    if (tile >= n_tiles) return;  // whole workgroup
+    __shared__ uint32_t s_claim[2];
+    if (r == 0) {
+        s_claim[0] = atomicAdd(ctr, 1u);
+        s_claim[1] = atomicAdd(ctr, 1u);
+    }
+    __syncthreads();
+    uint64_t tile = s_claim[0], tn = s_claim[1];  // this tile, the next
+    if (tile >= count) return;  // whole workgroup
     Part cur = part_of(tile);
     issue(cur);
     int h = 0;  // the current tile's metadata set
@@ -114,9 +138,11 @@ __global__ __launch_bounds__(mt::kThreads) void scan_mfma_kernel(const uint4 *__
     mt::Stream st;
     mt::stream_begin(cur.row, !cur.ok, sm, st);  // its barrier also publishes the metadata
     for (;;) {
-        const uint64_t tn = tile + gridDim.x;
-        const bool more = tn < n_tiles;
+        const bool more = tn < count;
         const Part nx = part_of(more ? tn : tile);
+        // the tile after next: claimed now, taken after this tile
+        uint32_t claim = 0;
+        if (r == 0 && more) claim = atomicAdd(ctr, 1u);
         const bool nzero = !more || !nx.ok;
         mt::v4f acc[8][4];
         // the next tile's metadata: loaded after every window and stored after
@@ -129,8 +155,11 @@ __global__ __launch_bounds__(mt::kThreads) void scan_mfma_kernel(const uint4 *__
             publish(nx, h ^ 1);
             issue(nx);
         });
-        const uint32_t q0 = (uint32_t)(tile % n_qtiles) * MQ;
-        const uint64_t t0 = tile / n_qtiles * MR;
+        uint32_t qt;
+        uint64_t rt;
+        coords(tile, qt, rt);
+        const uint32_t q0 = qt * MQ;
+        const uint64_t t0 = rt * MR;
 
         // epilogue: keys of this lane's 32 queries x 4 rows
         const int lane = r & 63;
@@ -180,11 +209,13 @@ __global__ __launch_bounds__(mt::kThreads) void scan_mfma_kernel(const uint4 *__
             }
         }
         flush();
+        if (r == 0) s_claim[0] = claim;
         __syncthreads();  // this set is rewritten during the next tile
         if (!more) break;
         h ^= 1;
         cur = nx;
         tile = tn;
+        tn = s_claim[0];
     }
 }
 
@@ -309,7 +340,9 @@ int knn_bruteforce_mfma(const uint64_t *d_db, uint64_t n, const uint64_t *d_q, u
     if (rc != QD_OK) return done(rc);
     hipLaunchKernelGGL(sample_threshold_kernel, dim3((nq + 255) / 256), dim3(256), 0, s, sidx, smis, sext, qpop, nq, k,
                        thr);
-    if (hipMemsetAsync(cnt, 0, (size_t)nq * 4, s) != hipSuccess || hipMemsetAsync(n_redo, 0, 4, s) != hipSuccess)
+    uint32_t *tctr = n_redo + 1;  // one tile counter per XCD (in the last 256 bytes)
+    if (hipMemsetAsync(cnt, 0, (size_t)nq * 4, s) != hipSuccess ||
+        hipMemsetAsync(n_redo, 0, 4 * (1 + mt::kXcds), s) != hipSuccess)
         return done(fail(QD_ERR_DEVICE, "memset"));
     {
         KernelTimer timer(g_sample_depth ? "wh_scan_mfma_sample" : "wh_scan_mfma", s);
@@ -317,7 +350,7 @@ int knn_bruteforce_mfma(const uint64_t *d_db, uint64_t n, const uint64_t *d_q, u
         const uint64_t grid = std::min<uint64_t>(n_qtiles * n_rtiles, (uint64_t)device_cus());
         hipLaunchKernelGGL(scan_mfma_kernel, dim3((uint32_t)grid), dim3(mt::kThreads), 0, s,
                            reinterpret_cast<const uint4 *>(d_db), n, reinterpret_cast<const uint4 *>(d_q), nq, tpop,
-                           qpop, thr, n_qtiles, cnt, cand);
+                           qpop, thr, n_qtiles, tctr, cnt, cand);
     }
     {
         KernelTimer timer(g_sample_depth ? "topk_select_sample" : "topk_select", s);
