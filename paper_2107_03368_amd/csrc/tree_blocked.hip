@@ -856,10 +856,64 @@ __global__ __launch_bounds__(256) void select_kernel(uint32_t k, const uint16_t 
     const uint32_t th = thrk[qi];
     uint32_t have = nt, th_new = th;
     if (stored > 0) {
-        const uint32_t total = nt + stored;
-        const uint32_t np = next_pow2(total < 2 ? 2 : total);
-        for (uint32_t i = threadIdx.x; i < np; i += 256)
-            keys[i] = i < nt ? top[(uint64_t)qi * k + i] : (i < total ? cand[(uint64_t)qi * kCap + (i - nt)] : KEY_NONE);
+        const uint32_t total = nt + stored;  // <= k + kCap <= 8192
+        auto key_at = [&](uint32_t i) {
+            return i < nt ? top[(uint64_t)qi * k + i] : cand[(uint64_t)qi * kCap + (i - nt)];
+        };
+        uint32_t np = 0;  // sort keys[0 .. np), which holds the k smallest keys
+        if (total > 1024) {
+            // Large sets: the k-th smallest K by bisection over this thread's
+            // (at most 32) key values, then only the keys with K up to it
+            // are sorted.  Every key's K is at most the query's k-th key
+            // (candidates are written only below it), so K* lies in [0, th].
+            uint32_t kv[32];
+#pragma unroll
+            for (int j = 0; j < 32; j++) {
+                const uint32_t i = threadIdx.x + 256u * j;
+                kv[j] = i < total ? (uint32_t)(key_at(i) >> 32) : 0xFFFFFFFFu;
+            }
+            __shared__ uint32_t s_part[4];
+            auto count_le = [&](uint32_t v) {  // keys with K <= v, in every thread
+                uint32_t c = 0;
+#pragma unroll
+                for (int j = 0; j < 32; j++) c += kv[j] <= v;
+                c = (uint32_t)wave_sum_f((float)c);  // <= 8192: exact in fp32
+                __syncthreads();  // the previous count's partial sums were read
+                if ((threadIdx.x & 63) == 0) s_part[threadIdx.x >> 6] = c;
+                __syncthreads();
+                return s_part[0] + s_part[1] + s_part[2] + s_part[3];
+            };
+            uint32_t lo = 0, hi = th;  // count_le(th) = total >= k
+            while (lo < hi) {
+                const uint32_t mid = lo + (hi - lo) / 2;
+                if (count_le(mid) >= k) hi = mid;
+                else lo = mid + 1;
+            }
+            const uint32_t c = count_le(lo);
+            if (c <= 1024) {
+                // keys with K <= K*, compacted into keys[0 .. c) in key-index order
+                __shared__ uint32_t s_base;
+                if (threadIdx.x == 0) s_base = 0;
+                __syncthreads();
+#pragma unroll
+                for (int j = 0; j < 32; j++) {
+                    const uint32_t i = threadIdx.x + 256u * j;
+                    const bool in = kv[j] <= lo;
+                    const u64 bm = ballot(in);
+                    uint32_t base = 0;
+                    if ((threadIdx.x & 63) == 0 && bm) base = atomicAdd(&s_base, (uint32_t)__popcll(bm));
+                    base = readlane(base, 0);
+                    if (in) keys[base + lanes_below(bm)] = key_at(i);
+                }
+                np = next_pow2(c < 2 ? 2 : c);
+                __syncthreads();
+                for (uint32_t i = c + threadIdx.x; i < np; i += 256) keys[i] = KEY_NONE;
+            }
+        }
+        if (np == 0) {  // small sets, or a K* shared by more than 1,024 keys: sort them all
+            np = next_pow2(total < 2 ? 2 : total);
+            for (uint32_t i = threadIdx.x; i < np; i += 256) keys[i] = i < total ? key_at(i) : KEY_NONE;
+        }
         __syncthreads();
         block_bitonic_sort(keys, np);
         const uint32_t kth = total >= k ? (uint32_t)(keys[k - 1] >> 32) : kInf;
