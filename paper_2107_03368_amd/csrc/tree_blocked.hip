@@ -428,7 +428,7 @@ __global__ __launch_bounds__(1024) void active_kernel(const u64 *__restrict__ re
 // Filling uses the tile the round runs anyway; such a pair is evaluated once,
 // against a k-th key at least as large as the next round's, so no row is lost.
 __global__ __launch_bounds__(256) void list_kernel(const uint16_t *__restrict__ lbb, uint64_t nblk, uint64_t n,
-                                                   uint32_t nqp, const uint32_t *__restrict__ act,
+                                                   uint32_t nqb, uint32_t nqp, const uint32_t *__restrict__ act,
                                                    const uint32_t *__restrict__ nact, const u64 *__restrict__ rec,
                                                    const u64 *__restrict__ frange, uint32_t *__restrict__ done,
                                                    uint16_t *__restrict__ list,
@@ -449,14 +449,21 @@ __global__ __launch_bounds__(256) void list_kernel(const uint16_t *__restrict__ 
     // kChunks chunks instead of twice per chunk
     constexpr int kChunks = 2;
     const uint32_t na = readfirst(*nact);
+    // when every query runs the list is the identity and is not read; else the
+    // next batch's query ids are loaded while this batch is walked
+    const bool all = na == nqb;
+    auto qid = [&](uint32_t ia) { return all ? (ia < na ? ia : na - 1) : act[ia < na ? ia : na - 1]; };
+    uint32_t nq_next[kChunks];
+#pragma unroll
+    for (int u = 0; u < kChunks; u++) nq_next[u] = na ? qid(64 * u + (uint32_t)lane) : 0;
     for (uint32_t i00 = 0; i00 < na; i00 += 64 * kChunks) {
         u64 rlo[kChunks], rhi[kChunks], rflo[kChunks], rfhi[kChunks];
         uint32_t rdone[kChunks], rq[kChunks];
         uint16_t rlv[kChunks][kGroup];
 #pragma unroll
         for (int u = 0; u < kChunks; u++) {
-            const uint32_t ia = i00 + 64 * u + (uint32_t)lane;
-            rq[u] = act[ia < na ? ia : na - 1];
+            rq[u] = nq_next[u];
+            nq_next[u] = qid(i00 + 64 * (kChunks + u) + (uint32_t)lane);
         }
 #pragma unroll
         for (int u = 0; u < kChunks; u++) {
@@ -1149,8 +1156,8 @@ int knn_tree_blocked(qd_tree_t t, const uint64_t *d_q, uint32_t nq, uint32_t k, 
                 KernelTimer timer("tree_block_lists", s);
                 const uint64_t waves = (nblk + kGroup - 1) / kGroup;
                 hipLaunchKernelGGL(active_kernel, dim3(1), dim3(1024), 0, s, rec, nqb, act, nact);
-                hipLaunchKernelGGL(list_kernel, dim3((uint32_t)((waves + 3) / 4)), dim3(256), 0, s, lbb, nblk, n, nqp,
-                                   act, nact, rec, frange, donebits, list, cnt, want_stats ? qst : nullptr);
+                hipLaunchKernelGGL(list_kernel, dim3((uint32_t)((waves + 3) / 4)), dim3(256), 0, s, lbb, nblk, n, nqb,
+                                   nqp, act, nact, rec, frange, donebits, list, cnt, want_stats ? qst : nullptr);
                 hipLaunchKernelGGL(tile_scan_kernel, dim3(1), dim3(1024), 0, s, cnt, nblk, t->d_bpop, off, voff, tinfo,
                                    ctr + 2);
             }
