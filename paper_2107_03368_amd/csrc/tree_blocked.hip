@@ -247,18 +247,49 @@ __global__ __launch_bounds__(256) void plan_kernel(const uint16_t *__restrict__ 
     const uint32_t L1 = lo;
     const uint32_t before = L1 ? cum[L1 - 1] : 0;
     const uint32_t r1 = T1 - before, at_level = cum[L1] - before;
-    // one wave walks the blocks in order (coalesced), listing round 1's blocks
-    // and finding the last block of level L1 it takes; the levels of 8 steps
-    // are loaded at once, so their latencies overlap
-    if (tid < 64) {
-        const int lane = (int)tid;
-        uint32_t pos = 0, eq_seen = 0;
-        for (uint64_t base = 0; base < nblk; base += 512) {
+    // Round 1's blocks, listed in block order: the 4 waves take a quarter of
+    // the blocks each; they first count the blocks below level L1 and at L1
+    // in their quarter, so each knows how many of each come before it, then
+    // list their quarter's blocks and find the last block of level L1 taken.
+    // The levels of 8 steps are loaded at once, so their latencies overlap.
+    __shared__ uint32_t s_lt[4], s_eq[4];
+    const int lane = (int)(tid & 63), wv = (int)(tid >> 6);
+    const uint64_t quarter = (nblk + 3) / 4;
+    const uint64_t w0 = quarter * wv, w1 = w0 + quarter < nblk ? w0 + quarter : nblk;
+    {
+        uint32_t lt = 0, eq = 0;
+        for (uint64_t base = w0; base < w1; base += 512) {
             uint32_t vs[8];
 #pragma unroll
             for (int i = 0; i < 8; i++) {
                 const uint64_t b = base + 64 * i + lane;
-                vs[i] = b < nblk ? row[b] : 0xFFFFu;
+                vs[i] = b < w1 ? row[b] : 0xFFFFu;
+            }
+#pragma unroll
+            for (int i = 0; i < 8; i++) {
+                lt += (uint32_t)__popcll(ballot(vs[i] < L1));
+                eq += (uint32_t)__popcll(ballot(vs[i] == L1));
+            }
+        }
+        if (lane == 0) {
+            s_lt[wv] = lt;
+            s_eq[wv] = eq;
+        }
+    }
+    __syncthreads();
+    {
+        uint32_t lt_before = 0, eq_seen = 0;
+        for (int v = 0; v < wv; v++) {
+            lt_before += s_lt[v];
+            eq_seen += s_eq[v];
+        }
+        uint32_t pos = lt_before + (eq_seen < r1 ? eq_seen : r1);
+        for (uint64_t base = w0; base < w1; base += 512) {
+            uint32_t vs[8];
+#pragma unroll
+            for (int i = 0; i < 8; i++) {
+                const uint64_t b = base + 64 * i + lane;
+                vs[i] = b < w1 ? row[b] : 0xFFFFu;
             }
 #pragma unroll
             for (int i = 0; i < 8; i++) {
