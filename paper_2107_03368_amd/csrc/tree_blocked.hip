@@ -203,7 +203,18 @@ __global__ __launch_bounds__(256) void plan_kernel(const uint16_t *__restrict__ 
     for (uint32_t i = tid; i < kLevels; i += 256) cum[i] = 0;
     if (tid == 0) s_bcut = kInf;
     __syncthreads();
-    for (uint64_t b = tid; b < nblk; b += 256) atomicAdd(&cum[row[b]], 1u);
+    // eight loads in flight per thread, then their counts
+    for (uint64_t b0 = tid; b0 < nblk; b0 += 256 * 8) {
+        uint32_t v[8];
+#pragma unroll
+        for (int i = 0; i < 8; i++) {
+            const uint64_t b = b0 + 256 * i;
+            v[i] = b < nblk ? row[b] : kLevels;
+        }
+#pragma unroll
+        for (int i = 0; i < 8; i++)
+            if (v[i] < kLevels) atomicAdd(&cum[v[i]], 1u);
+    }
     __syncthreads();
     // inclusive prefix over the levels; thread t owns levels [t*per, t*per+per)
     constexpr uint32_t per = (kLevels + 255) / 256;
