@@ -597,10 +597,17 @@ __global__ __launch_bounds__(1024) void tile_scan_kernel(const uint32_t *__restr
     const uint32_t tid = threadIdx.x;
     const uint64_t chunk = (nblk + 1023) / 1024;
     const uint64_t c0 = (uint64_t)tid * chunk, c1 = c0 + chunk < nblk ? c0 + chunk : nblk;
+    // a thread's blocks eight at a time, so their loads are in flight together
     uint32_t s = 0, vs = 0;
-    for (uint64_t b = c0; b < c1; b++) {
-        s += mfma_tiles(cnt[b]);
-        vs += short_pairs(cnt[b]);
+    for (uint64_t b0 = c0; b0 < c1; b0 += 8) {
+        uint32_t cv[8];
+#pragma unroll
+        for (int i = 0; i < 8; i++) cv[i] = b0 + i < c1 ? cnt[b0 + i] : 0;  // 0: no tiles, no pairs
+#pragma unroll
+        for (int i = 0; i < 8; i++) {
+            s += mfma_tiles(cv[i]);
+            vs += short_pairs(cv[i]);
+        }
     }
     part[tid] = s;
     vpart[tid] = vs;
@@ -614,18 +621,28 @@ __global__ __launch_bounds__(1024) void tile_scan_kernel(const uint32_t *__restr
         __syncthreads();
     }
     uint32_t run = part[tid] - s, vrun = vpart[tid] - vs;
-    for (uint64_t b = c0; b < c1; b++) {
-        off[b] = run;
-        voff[b] = vrun;
-        const uint32_t nt = mfma_tiles(cnt[b]);
-        const uint32_t listed = cnt[b] - short_pairs(cnt[b]);  // the list's short rest is not in a tile
-        const uint32_t bp = bpop ? bpop[2 * b] : 0;
-        for (uint32_t i = 0; i < nt; i++) {
-            const uint32_t t0 = i * mt::MA, m = listed - t0 < (uint32_t)mt::MA ? listed - t0 : (uint32_t)mt::MA;
-            tinfo[run + i] = make_uint4((uint32_t)b, t0, m, bp);
+    for (uint64_t b0 = c0; b0 < c1; b0 += 8) {
+        uint32_t cv[8], bv[8];
+#pragma unroll
+        for (int i = 0; i < 8; i++) {
+            cv[i] = b0 + i < c1 ? cnt[b0 + i] : 0;
+            bv[i] = bpop && b0 + i < c1 ? bpop[2 * (b0 + i)] : 0;
         }
-        run += nt;
-        vrun += short_pairs(cnt[b]);
+#pragma unroll
+        for (int i = 0; i < 8; i++) {
+            const uint64_t b = b0 + i;
+            if (b >= c1) break;
+            off[b] = run;
+            voff[b] = vrun;
+            const uint32_t nt = mfma_tiles(cv[i]);
+            const uint32_t listed = cv[i] - short_pairs(cv[i]);  // the list's short rest is not in a tile
+            for (uint32_t t = 0; t < nt; t++) {
+                const uint32_t t0 = t * mt::MA, m = listed - t0 < (uint32_t)mt::MA ? listed - t0 : (uint32_t)mt::MA;
+                tinfo[run + t] = make_uint4((uint32_t)b, t0, m, bv[i]);
+            }
+            run += nt;
+            vrun += short_pairs(cv[i]);
+        }
     }
     if (tid == 1023) {
         off[nblk] = part[1023];
