@@ -253,19 +253,33 @@ __global__ __launch_bounds__(kBlock) void tree_knn_kernel(TreeView T, const uint
                 leaves++;
                 const uint32_t b0 = readfirst(T.begin[node]), m = readfirst(T.count[node]);
                 dists += m;
-                for (uint32_t base = 0; base < m; base += 8) {
+                for (uint32_t base0 = 0; base0 < m; base0 += 32) {
+                    // up to 32 rows (4 groups of 8) loaded before any is reduced,
+                    // so a whole leaf costs one round trip to memory
+                    uint32_t cs[4], tps[4], rows[4];
+#pragma unroll
+                    for (int u = 0; u < 4; u++) {
+                        const uint32_t r = base0 + 8 * u + (uint32_t)g;
+                        const uint64_t pos = (uint64_t)b0 + (r < m ? r : 0);
+                        uint4 tv[4];
+#pragma unroll
+                        for (int i = 0; i < 4; i++) tv[i] = T.sorted[pos * 32 + j + 8 * i];
+                        cs[u] = popc_and4(tv[0], qv[0]) + popc_and4(tv[1], qv[1]) + popc_and4(tv[2], qv[2]) +
+                                popc_and4(tv[3], qv[3]);
+                        tps[u] = T.pop[pos];
+                        rows[u] = T.perm[pos];
+                    }
+#pragma unroll
+                    for (int u = 0; u < 4; u++) {
+                    const uint32_t base = base0 + 8 * u;
+                    if (base >= m) break;
                     const uint32_t r = base + (uint32_t)g;
                     const bool valid = r < m;
-                    const uint64_t pos = (uint64_t)b0 + (valid ? r : 0);
-                    uint4 tv[4];
-#pragma unroll
-                    for (int i = 0; i < 4; i++) tv[i] = T.sorted[pos * 32 + j + 8 * i];
-                    const uint32_t c = sum8(popc_and4(tv[0], qv[0]) + popc_and4(tv[1], qv[1]) +
-                                            popc_and4(tv[2], qv[2]) + popc_and4(tv[3], qv[3]));
-                    const uint32_t tp = T.pop[pos];
+                    const uint32_t c = sum8(cs[u]);
+                    const uint32_t tp = tps[u];
                     const uint32_t A = pq - c, B = tp - c;
                     const uint32_t K = A * wb + B * wa;
-                    const uint32_t row = T.perm[pos];
+                    const uint32_t row = rows[u];
                     const u64 key = valid ? ((u64)K << 32) | row : KEY_NONE;
                     const u64 thr = kworst == kNone ? KEY_NONE : readlane64(list, (int)k - 1);
                     u64 mk = ballot(j == 0 && key < thr);
@@ -287,6 +301,7 @@ __global__ __launch_bounds__(kBlock) void tree_knn_kernel(TreeView T, const uint
                         }
                     }
                     kworst = readfirst(readlane((uint32_t)(readlane64(list, (int)k - 1) >> 32), 0));
+                    }
                 }
             } else {
                 uint32_t kb0, kb1;
