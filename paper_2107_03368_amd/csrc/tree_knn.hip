@@ -74,15 +74,19 @@ __global__ __launch_bounds__(kBlock) void tree_knn_kernel(TreeView T, const uint
                                                           const uint32_t *__restrict__ nq_dev) {
     __shared__ uint32_t bstate_all[kBest ? kWaves * kBuckets : 1];
     __shared__ u64 stack_all[kBest ? 1 : kWaves * kMaxStack];
+    __shared__ u64 sinfo_all[kBest ? 1 : kWaves * kMaxStack];  // the entries' node info
     const int lane = lane_id();
     const int wave = threadIdx.x >> 6;
     const int g = lane >> 3, j = lane & 7;
     const uint64_t slot = (uint64_t)blockIdx.x * kWaves + wave;
     u64 *mypool = pool + slot * pool_chunks * kChunk;
+    // the entries' node info, in a second pool of the same shape
+    u64 *myinfo = pool + ((uint64_t)gridDim.x * kWaves + slot) * pool_chunks * kChunk;
     uint32_t *myprev = chunk_prev + slot * pool_chunks * 2;
     uint32_t *myfree = myprev + pool_chunks;
     uint32_t *bstate = bstate_all + (kBest ? wave * kBuckets : 0);
     u64 *stack = stack_all + (kBest ? 0 : wave * kMaxStack);
+    u64 *sinfo = sinfo_all + (kBest ? 0 : wave * kMaxStack);
     const bool has_and = T.andimg != nullptr;
     if (nq_dev) nq = readfirst(*nq_dev);  // size given on the device (captured graphs)
 
@@ -137,16 +141,28 @@ __global__ __launch_bounds__(kBlock) void tree_knn_kernel(TreeView T, const uint
             }
             return al * wb + bl * wa;
         };
-        auto bound_pair = [&](int32_t c0, int32_t c1, uint32_t &kb0, uint32_t &kb1) {
-            const uint32_t kb = node_bound(lane < 32 ? c0 : c1);
+        // what a node's expansion needs, fetched when the node is bounded (in
+        // parallel with its images) and kept with its queue entry, so popping
+        // it waits for no load: a leaf's row range (bit 63 set) or its children
+        auto info_of = [&](int32_t c) -> u64 {
+            const int32_t a = T.child[2 * (uint64_t)c], b = T.child[2 * (uint64_t)c + 1];
+            const uint32_t bg = T.begin[c], ct = T.count[c];
+            return a < 0 ? ((1ull << 63) | ((u64)ct << 32) | bg) : (((u64)(uint32_t)b << 32) | (uint32_t)a);
+        };
+        auto bound_pair = [&](int32_t c0, int32_t c1, uint32_t &kb0, uint32_t &kb1, u64 &in0, u64 &in1) {
+            const int32_t c = lane < 32 ? c0 : c1;
+            const uint32_t kb = node_bound(c);
+            const u64 in = info_of(c);
             kb0 = readlane(kb, 0);
             kb1 = readlane(kb, 32);
+            in0 = readlane64(in, 0);
+            in1 = readlane64(in, 32);
         };
         auto take_chunk = [&]() -> uint32_t {  // lane 0 only; capacity is sized so it never runs out
             const uint32_t c = nfree > 0 ? myfree[nfree - 1] : alloc;
             return c < pool_chunks ? c : (uint32_t)(pool_chunks - 1);
         };
-        auto push = [&](uint32_t kb, uint32_t node) {
+        auto push = [&](uint32_t kb, uint32_t node, u64 info) {
             const u64 e = ((u64)kb << 32) | node;
             if (kBest) {
                 uint32_t b = kb / wb;
@@ -159,6 +175,7 @@ __global__ __launch_bounds__(kBlock) void tree_knn_kernel(TreeView T, const uint
                         took = 1;
                         myprev[c] = kNone;
                         mypool[(uint64_t)c * kChunk] = e;
+                        myinfo[(uint64_t)c * kChunk] = info;
                         bstate[b] = (c << 5) | 1u;
                     } else {
                         const uint32_t st = bstate[b];
@@ -168,9 +185,11 @@ __global__ __launch_bounds__(kBlock) void tree_knn_kernel(TreeView T, const uint
                             took = 1;
                             myprev[c2] = c;
                             mypool[(uint64_t)c2 * kChunk] = e;
+                            myinfo[(uint64_t)c2 * kChunk] = info;
                             bstate[b] = (c2 << 5) | 1u;
                         } else {
                             mypool[(uint64_t)c * kChunk + f] = e;
+                            myinfo[(uint64_t)c * kChunk + f] = info;
                             bstate[b] = (c << 5) | (f + 1);
                         }
                     }
@@ -187,7 +206,10 @@ __global__ __launch_bounds__(kBlock) void tree_knn_kernel(TreeView T, const uint
                 }
             } else {
                 if (readfirst((uint32_t)sp) < (uint32_t)kMaxStack) {
-                    if (lane == 0) stack[sp] = e;
+                    if (lane == 0) {
+                        stack[sp] = e;
+                        sinfo[sp] = info;
+                    }
                     sp = (int)readfirst((uint32_t)sp + 1);
                 }
             }
@@ -196,24 +218,26 @@ __global__ __launch_bounds__(kBlock) void tree_knn_kernel(TreeView T, const uint
         // root
         {
             const uint32_t kb = readlane(node_bound(0), 0);
+            const u64 in = readlane64(info_of(0), 0);
             bounds++;
-            push(kb, 0);
+            push(kb, 0, in);
         }
 
         for (;;) {
-            u64 e;
+            u64 e, ninfo;
             uint32_t floor_kb = 0;  // best-first: lower end of the popped bucket, a bound on every open node
             if (kBest) {
                 const u64 nz = ballot(occ != 0);
                 if (!nz) break;
                 const int L = __builtin_ctzll(nz);
                 const uint32_t b = 64u * (uint32_t)L + (uint32_t)__builtin_ctzll(readlane64(occ, L));
-                u64 got = 0;
+                u64 got = 0, gin = 0;
                 uint32_t emptied = 0, freed = kNone;
                 if (lane == 0) {
                     const uint32_t st = bstate[b];
                     const uint32_t c = st >> 5, f = (st & 31u) - 1;
                     got = mypool[(uint64_t)c * kChunk + f];
+                    gin = myinfo[(uint64_t)c * kChunk + f];
                     if (f == 0) {
                         const uint32_t pc = myprev[c];
                         if (pc == kNone) {
@@ -229,6 +253,7 @@ __global__ __launch_bounds__(kBlock) void tree_knn_kernel(TreeView T, const uint
                     }
                 }
                 e = readlane64(got, 0);
+                ninfo = readlane64(gin, 0);
                 floor_kb = b * wb;
                 if (readfirst(freed) != kNone) nfree++;
                 if (readfirst(emptied) && lane == L) occ &= ~(1ull << (b & 63));
@@ -236,6 +261,7 @@ __global__ __launch_bounds__(kBlock) void tree_knn_kernel(TreeView T, const uint
                 if (readfirst((uint32_t)sp) == 0) break;
                 sp = (int)readfirst((uint32_t)sp - 1);
                 e = readlane64(lane == 0 ? stack[sp] : 0ull, 0);
+                ninfo = readlane64(lane == 0 ? sinfo[sp] : 0ull, 0);
             }
             const uint32_t kb = readfirst((uint32_t)(e >> 32)), node = readfirst((uint32_t)e);
             if (kworst != kNone && kb > kworst) {
@@ -247,11 +273,9 @@ __global__ __launch_bounds__(kBlock) void tree_knn_kernel(TreeView T, const uint
             visited++;
             if (trace && node < n_traced && lane == 0)
                 atomicOr(&trace[(uint64_t)qi * ((n_traced + 31) / 32) + node / 32], 1u << (node & 31));
-            const int32_t c0 = (int32_t)readfirst((uint32_t)T.child[2 * node]);
-            const int32_t c1 = (int32_t)readfirst((uint32_t)T.child[2 * node + 1]);
-            if (c0 < 0) {
+            if (ninfo >> 63) {
                 leaves++;
-                const uint32_t b0 = readfirst(T.begin[node]), m = readfirst(T.count[node]);
+                const uint32_t b0 = readfirst((uint32_t)ninfo), m = readfirst((uint32_t)(ninfo >> 32) & 0x7FFFFFFFu);
                 dists += m;
                 for (uint32_t base0 = 0; base0 < m; base0 += 32) {
                     // up to 32 rows (4 groups of 8) loaded before any is reduced,
@@ -304,24 +328,26 @@ __global__ __launch_bounds__(kBlock) void tree_knn_kernel(TreeView T, const uint
                     }
                 }
             } else {
+                const int32_t c0 = (int32_t)readfirst((uint32_t)ninfo), c1 = (int32_t)readfirst((uint32_t)(ninfo >> 32));
                 uint32_t kb0, kb1;
-                bound_pair(c0, c1, kb0, kb1);
+                u64 in0, in1;
+                bound_pair(c0, c1, kb0, kb1, in0, in1);
                 bounds += 2;
                 const bool ok0 = kworst == kNone || kb0 <= kworst;
                 const bool ok1 = kworst == kNone || kb1 <= kworst;
                 if (kBest) {
-                    if (ok0) push(kb0, (uint32_t)c0);
-                    if (ok1) push(kb1, (uint32_t)c1);
+                    if (ok0) push(kb0, (uint32_t)c0, in0);
+                    if (ok1) push(kb1, (uint32_t)c1, in1);
                 } else {
                     // preferred child last, so it is popped first
                     bool first1 = kb1 < kb0;  // lower bound first; ties: similar child
                     if (qs && (uint32_t)c0 < S.n_scored && (uint32_t)c1 < S.n_scored) first1 = qs[c1] > qs[c0];
                     if (first1) {
-                        if (ok0) push(kb0, (uint32_t)c0);
-                        if (ok1) push(kb1, (uint32_t)c1);
+                        if (ok0) push(kb0, (uint32_t)c0, in0);
+                        if (ok1) push(kb1, (uint32_t)c1, in1);
                     } else {
-                        if (ok1) push(kb1, (uint32_t)c1);
-                        if (ok0) push(kb0, (uint32_t)c0);
+                        if (ok1) push(kb1, (uint32_t)c1, in1);
+                        if (ok0) push(kb0, (uint32_t)c0, in0);
                     }
                 }
             }
@@ -382,7 +408,7 @@ TreeLaunch tree_launch_shape(qd_tree_t t, uint32_t nq_max, int order, uint32_t w
     L.pool_chunks = order == QD_ORDER_BEST_FIRST ? t->n_nodes / kChunk + 2 * kBuckets + 2 : 1;
     L.head = 256;  // [counter | pad | stats x4 | pad]
     L.prev_bytes = (size_t)(L.slots * L.pool_chunks * 8 + 255) / 256 * 256;  // prev + free list
-    L.pool_bytes = (size_t)L.slots * L.pool_chunks * kChunk * 8;
+    L.pool_bytes = (size_t)L.slots * L.pool_chunks * kChunk * 16;  // entries, then their node info
     return L;
 }
 
