@@ -16,13 +16,14 @@
 //
 // Frontier orders:
 //  best-first (the paper's priority queue): a bucket queue on
-//    floor(Kb / wB) (= A_lb for the sum-image bound alone, so nodes come out
-//    in exact bound order); the search stops once the popped bucket's lower
-//    end exceeds the k-th key (a popped node above the key in a lower bucket
-//    is skipped: with B terms a bucket holds bounds up to wB apart).  Each bucket is a stack of 16-entry chunks in
-//    the wave's global workspace, its (chunk, fill) word in LDS, and a
-//    4096-bit occupancy map spread over the 64 lanes finds the lowest
-//    non-empty bucket with one ballot.  Only lane 0 touches the chunk memory.
+//    floor(Kb / 2wB) (2 levels of A_lb per bucket for the sum-image bound
+//    alone: the buckets' state then takes half the LDS, so 12 waves fit on a
+//    CU instead of 8); the search stops once the popped bucket's lower end
+//    exceeds the k-th key, and a popped node above the key is skipped, so the
+//    result stays exact.  Each bucket is a stack of 16-entry chunks in the
+//    wave's global workspace, its (chunk, fill) word in LDS, and a 2048-bit
+//    occupancy map spread over the 64 lanes finds the lowest non-empty bucket
+//    with one ballot.  Only lane 0 touches the chunk memory.
 //  depth-first: a stack in LDS; at every expansion the preferred child is
 //    visited first (lower bound, or higher learned score where scores are
 //    given); popped nodes are re-checked against the k-th key and skipped
@@ -38,7 +39,8 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr int kWaves = kBlock / 64;
-constexpr int kBuckets = 4096;
+constexpr int kBuckets = 2048;
+constexpr uint32_t kBucketLevels = 2;  // bound levels (multiples of wB) per bucket
 constexpr uint32_t kChunk = 16;
 constexpr uint32_t kNone = 0xFFFFFFFFu;
 constexpr int kMaxStack = 256;
@@ -165,7 +167,7 @@ __global__ __launch_bounds__(kBlock) void tree_knn_kernel(TreeView T, const uint
         auto push = [&](uint32_t kb, uint32_t node, u64 info) {
             const u64 e = ((u64)kb << 32) | node;
             if (kBest) {
-                uint32_t b = kb / wb;
+                uint32_t b = kb / (kBucketLevels * wb);
                 b = b < kBuckets ? b : kBuckets - 1;
                 const bool tb = (readlane64(touched, (int)(b >> 6)) >> (b & 63)) & 1ull;
                 uint32_t took = 0;
@@ -254,7 +256,7 @@ __global__ __launch_bounds__(kBlock) void tree_knn_kernel(TreeView T, const uint
                 }
                 e = readlane64(got, 0);
                 ninfo = readlane64(gin, 0);
-                floor_kb = b * wb;
+                floor_kb = b * kBucketLevels * wb;
                 if (readfirst(freed) != kNone) nfree++;
                 if (readfirst(emptied) && lane == L) occ &= ~(1ull << (b & 63));
             } else {
@@ -395,7 +397,7 @@ __global__ void zero_words_kernel(uint32_t *p, uint32_t n) {
 TreeLaunch tree_launch_shape(qd_tree_t t, uint32_t nq_max, int order, uint32_t waves_per_cu) {
     TreeLaunch L;
     const int cus = device_cus();
-    if (waves_per_cu == 0) waves_per_cu = order == QD_ORDER_BEST_FIRST ? 8 : 16;
+    if (waves_per_cu == 0) waves_per_cu = order == QD_ORDER_BEST_FIRST ? 12 : 16;
     uint64_t blocks = ((uint64_t)cus * waves_per_cu + kWaves - 1) / kWaves;
     const uint64_t need = ((uint64_t)(nq_max ? nq_max : 1) + kWaves - 1) / kWaves;
     if (blocks > need) blocks = need;
