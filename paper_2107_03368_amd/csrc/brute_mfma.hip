@@ -114,11 +114,13 @@ __global__ __launch_bounds__(mt::kThreads) void scan_mfma_kernel(const uint4 *__
         const uint32_t pv = p.ok ? lp : 0;
         const u64 th = p.ok && arow ? lt : 0;
         // K = |q|*wB + |t|*wA - C*(wA + wB) >= |q|*wB - C*(wA + wB): a row
-        // with C below cmin has K above the bound's key
-        const uint32_t wa = pv > 1 ? pv : 1, wb = (QD_BITS - pv) > 1 ? QD_BITS - pv : 1;
+        // with C*(wA + wB) below X = |q|*wB - (the bound's key) has K above
+        // it.  wA + wB is 4096, or 4097 when |q| is 0 or 4096, so a row can
+        // only pass with C >= ceil(X / 4097) = cmin (a division by a
+        // constant, a multiply and a shift; the exact key test follows)
+        const uint32_t wb = (QD_BITS - pv) > 1 ? QD_BITS - pv : 1;
         const int64_t X = (int64_t)pv * wb - (int64_t)(th >> 32);
-        // X <= 0 gives 0 either way; dividing always keeps the store free of branches
-        const uint32_t cmin = ((uint32_t)(X > 0 ? X : 0) + wa + wb - 1) / (wa + wb);  // X < 2^24
+        const uint32_t cmin = ((uint32_t)(X > 0 ? X : 0) + 4096u) / 4097u;  // X < 2^24
         s_p[h][r] = pv;
         s_th[h][r] = th;
         s_cmin[h][r] = p.ok ? (float)cmin : 1e30f;

@@ -111,22 +111,28 @@ struct Stream {
 
 // Rows: this thread's row (32 x 16 bytes), always a readable global row; when
 // the zero flag is set its bits count as 0 (a missing row past the end of
-// the input).  A global-memory pointer: a generic one would make the window
-// loads flat loads, which also hold the LDS counter the fragment reads wait on.
+// the input), read from a row of zeros, so the loaded words need no mask.  A
+// global-memory pointer: a generic one would make the window loads flat
+// loads, which also hold the LDS counter the fragment reads wait on (the row
+// of zeros is a global variable, so a choice between it and a row stays
+// global).
+static __device__ uint4 kZeroRow[32];  // never written: zero-initialised
+
+__device__ __forceinline__ const uint4 *row_or_zero(const uint4 *row, bool zero) { return zero ? kZeroRow : row; }
 
 // Stage the first two windows of a stream's first tile.
 __device__ __forceinline__ void stream_begin(const uint4 *row, bool zero, Smem &sm, Stream &st) {
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int wq = w >> 2, wr = w & 3, li = lane & 15, lg = lane >> 4;
-    const uint32_t keep = zero ? 0u : ~0u;
+    const uint4 *src = row_or_zero(row, zero);
 #pragma unroll
     for (int v = 0; v < 2; v++) {
         uint2 *d = reinterpret_cast<uint2 *>(sm.rw[v] + tid * RST);
 #pragma unroll
         for (int c = 0; c < 4; c++) {
-            const uint4 p = row[4 * v + c];
-            d[2 * c] = make_uint2(p.x & keep, p.y & keep);
-            d[2 * c + 1] = make_uint2(p.z & keep, p.w & keep);
+            const uint4 p = src[4 * v + c];
+            d[2 * c] = make_uint2(p.x, p.y);
+            d[2 * c + 1] = make_uint2(p.z, p.w);
         }
     }
     __syncthreads();
@@ -157,20 +163,20 @@ __device__ __forceinline__ void stream_tile(const uint4 *row, bool zero, const u
 #pragma unroll
         for (int b = 0; b < 4; b++) acc[a][b] = v4f{0.f, 0.f, 0.f, 0.f};
 
-    // window v of a row is its 16-byte pieces 4v .. 4v+3.  Pieces are loaded
-    // as they are and a missing row is masked to zeros only when stored, so
+    // window v of a row is its 16-byte pieces 4v .. 4v+3, loaded as they
+    // are (a missing row from the row of zeros) and stored unchanged, so
     // nothing waits for the loads before then (and no branch skips them).
-    const uint32_t keep = zero ? 0u : ~0u;
-    auto stage = [&](uint8_t *dst, uint4 p0, uint4 p1, uint4 p2, uint4 p3, uint32_t k) {
+    const uint4 *const own_src = row_or_zero(row, zero);
+    auto stage = [&](uint8_t *dst, uint4 p0, uint4 p1, uint4 p2, uint4 p3) {
         uint2 *d = reinterpret_cast<uint2 *>(dst + tid * RST);  // 8-byte aligned
-        d[0] = make_uint2(p0.x & k, p0.y & k);
-        d[1] = make_uint2(p0.z & k, p0.w & k);
-        d[2] = make_uint2(p1.x & k, p1.y & k);
-        d[3] = make_uint2(p1.z & k, p1.w & k);
-        d[4] = make_uint2(p2.x & k, p2.y & k);
-        d[5] = make_uint2(p2.z & k, p2.w & k);
-        d[6] = make_uint2(p3.x & k, p3.y & k);
-        d[7] = make_uint2(p3.z & k, p3.w & k);
+        d[0] = make_uint2(p0.x, p0.y);
+        d[1] = make_uint2(p0.z, p0.w);
+        d[2] = make_uint2(p1.x, p1.y);
+        d[3] = make_uint2(p1.z, p1.w);
+        d[4] = make_uint2(p2.x, p2.y);
+        d[5] = make_uint2(p2.z, p2.w);
+        d[6] = make_uint2(p3.x, p3.y);
+        d[7] = make_uint2(p3.z, p3.w);
     };
     constexpr int kWins = 4096 / WIN;
     // fragment f < 8: A rows wq*128 + 16f + li; f >= 8: B rows wr*64 + 16(f-8) + li
@@ -203,8 +209,7 @@ __device__ __forceinline__ void stream_tile(const uint4 *row, bool zero, const u
         const uint8_t *buf = sm.rw[cur];
         // window win + 2 of this tile, or window win - 6 of the next
         const bool own = win + 2 < kWins;
-        const uint4 *src = own ? row : next;
-        const uint32_t k = own ? keep : (next_zero ? 0u : ~0u);
+        const uint4 *src = own ? own_src : row_or_zero(next, next_zero);
         const int nb = (4 * win + 8) & 31;
         const uint4 n0 = src[nb], n1 = src[nb + 1], n2 = src[nb + 2], n3 = src[nb + 3];
 #pragma unroll
@@ -221,7 +226,7 @@ __device__ __forceinline__ void stream_tile(const uint4 *row, bool zero, const u
         }
         // the buffer of window win - 1: every wave finished reading it before
         // the previous barrier
-        stage(sm.rw[stg], n0, n1, n2, n3, k);
+        stage(sm.rw[stg], n0, n1, n2, n3);
         __syncthreads();
         hook(win);
         cur = nxt;

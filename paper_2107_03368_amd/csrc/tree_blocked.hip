@@ -772,11 +772,14 @@ __global__ __launch_bounds__(mt::kThreads) void eval_kernel(const uint4 *__restr
         th = arow && ok ? pd : 0;
     };
     // K = |q|*wB + |t|*wA - C*(wA + wB) with |t| >= the block's smallest
-    // popcount: a row with C below cmin has K above the k-th key
+    // popcount: a row with C*(wA + wB) below X = |q|*wB + min|t|*wA - (the
+    // k-th key) has K above the k-th key.  wA + wB is 4096, or 4097 when |q|
+    // is 0 or 4096, so a row can only pass with C >= ceil(X / 4097) = cmin
+    // (a division by a constant; the exact key test follows)
     auto cmin_of = [&](const uint4 &in) -> float {
         const uint32_t wa = weight_a(pq), wb = weight_b(pq);
         const int64_t X = (int64_t)pq * wb + (int64_t)in.w * wa - (int64_t)th;
-        const uint32_t cmin = X <= 0 ? 0u : ((uint32_t)X + wa + wb - 1) / (wa + wb);  // 0 < X < 2^26
+        const uint32_t cmin = X <= 0 ? 0u : ((uint32_t)X + 4096u) / 4097u;  // 0 < X < 2^26
         return arow && ok ? (float)cmin : 1e30f;
     };
     auto row_of = [&](const uint4 &in) -> const uint4 * {
