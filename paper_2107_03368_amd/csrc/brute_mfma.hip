@@ -119,8 +119,9 @@ __global__ __launch_bounds__(mt::kThreads) void scan_mfma_kernel(const uint4 *__
         // only pass with C >= ceil(X / 4097) = cmin (a division by a
         // constant, a multiply and a shift; the exact key test follows)
         const uint32_t wb = (QD_BITS - pv) > 1 ? QD_BITS - pv : 1;
-        const int64_t X = (int64_t)pv * wb - (int64_t)(th >> 32);
-        const uint32_t cmin = ((uint32_t)(X > 0 ? X : 0) + 4096u) / 4097u;  // X < 2^24
+        const uint32_t P = __umul24(pv, wb), Kb = (uint32_t)(th >> 32);  // |q|*wB <= 2^22
+        const uint32_t X = P - (P < Kb ? P : Kb);                          // max(P - Kb, 0)
+        const uint32_t cmin = (X + 4096u) / 4097u;
         s_p[h][r] = pv;
         s_th[h][r] = th;
         s_cmin[h][r] = p.ok ? (float)cmin : 1e30f;

@@ -778,8 +778,9 @@ __global__ __launch_bounds__(mt::kThreads) void eval_kernel(const uint4 *__restr
     // (a division by a constant; the exact key test follows)
     auto cmin_of = [&](const uint4 &in) -> float {
         const uint32_t wa = weight_a(pq), wb = weight_b(pq);
-        const int64_t X = (int64_t)pq * wb + (int64_t)in.w * wa - (int64_t)th;
-        const uint32_t cmin = X <= 0 ? 0u : ((uint32_t)X + 4096u) / 4097u;  // 0 < X < 2^26
+        const uint32_t S = __umul24(pq, wb) + __umul24(in.w, wa);  // |q|*wB + min|t|*wA < 2^25
+        const uint32_t X = S - (S < th ? S : th);                    // max(S - k-th key, 0)
+        const uint32_t cmin = (X + 4096u) / 4097u;
         return arow && ok ? (float)cmin : 1e30f;
     };
     auto row_of = [&](const uint4 &in) -> const uint4 * {
