@@ -96,10 +96,11 @@ def test_1m_workload_sampled_queries(qd, db_1m, k):
 
 
 def test_matrix_core_path_equals_register_scan_and_oracle(qd):
-    # >= 512 queries over >= 65,536 rows take the int8-MFMA path by default;
-    # the register-tiled scan (an explicit query tile) must agree bit for bit
+    # >= 512 queries over >= 65,536 rows take the FP4 matrix-core path by
+    # default; the register-tiled scan (an explicit query tile) must agree bit
+    # for bit
     db = synth.gen_db(100_003, 1011)  # ragged against the 256-row tile
-    q, _ = synth.gen_queries(db, 600, 2011, 0.1, 0.6)  # ragged against the 128-query tile
+    q, _ = synth.gen_queries(db, 600, 2011, 0.1, 0.6)  # ragged against the 256-query tile
     for k in (1, 10, 50):
         a = qd.knn_bruteforce(_t(db), _t(q), k)
         b = qd.knn_bruteforce(_t(db), _t(q), k, query_tile=16)
