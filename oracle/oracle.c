@@ -485,6 +485,7 @@ int or_tree_knn(const uint64_t *db, const int32_t *child, const int64_t *begin, 
  * in processing order and, within a descriptor, in neighbour rank order.
  * used[g] = descriptors processed when the winner appeared (all of them if
  * none did; winner = -1).  votes[g][o] counts every descriptor's votes.
+ * A neighbour whose row belongs to no object (id >= n_obj) casts no vote.
  * ------------------------------------------------------------------------- */
 void or_votes(const uint32_t *nn_idx, int k, const uint16_t *obj_of, int64_t n_db, int64_t n_obj,
               const uint64_t *qoff, int64_t nqo, int64_t threshold, uint32_t *votes, int32_t *winner,
@@ -499,6 +500,7 @@ void or_votes(const uint32_t *nn_idx, int k, const uint16_t *obj_of, int64_t n_d
                 uint32_t row = nn_idx[d * (uint64_t)k + (uint64_t)r];
                 if (row == 0xFFFFFFFFu || (int64_t)row >= n_db) continue;
                 uint16_t o = obj_of[row];
+                if ((int64_t)o >= n_obj) continue;
                 v[o]++;
                 if (winner[g] < 0 && (int64_t)v[o] >= threshold) {
                     winner[g] = (int32_t)o;

@@ -95,19 +95,34 @@ def test_1m_workload_sampled_queries(qd, db_1m, k):
     _same(res, ref, rows)
 
 
+def _degenerate_rows(n, seed):
+    """n rows: all zero, all one, and dense random rows (about half the bits)."""
+    rng = np.random.default_rng(seed)
+    dense = rng.integers(0, 2 ** 63, (n, 64), dtype=np.int64).view(np.uint64) ^ \
+        (rng.integers(0, 2, (n, 64), dtype=np.uint64) << np.uint64(63))
+    dense[0::3] = 0
+    dense[1::3] = np.uint64(0xFFFFFFFFFFFFFFFF)
+    return dense
+
+
 def test_matrix_core_path_equals_register_scan_and_oracle(qd):
     # >= 512 queries over >= 65,536 rows take the FP4 matrix-core path by
     # default; the register-tiled scan (an explicit query tile) must agree bit
-    # for bit
+    # for bit, and the oracle on every query.  Among them: all-zero and all-one
+    # queries (|q| = 0 and 4096, the ends of the weights) and all-zero,
+    # all-one and dense rows (overlap counts up to 4096)
     db = synth.gen_db(100_003, 1011)  # ragged against the 256-row tile
+    db[5000:5030] = _degenerate_rows(30, 1013)
     q, _ = synth.gen_queries(db, 600, 2011, 0.1, 0.6)  # ragged against the 256-query tile
+    q[100:120] = 0
+    q[300:320] = np.uint64(0xFFFFFFFFFFFFFFFF)
+    q[590:596] = _degenerate_rows(6, 1014)
     for k in (1, 10, 50):
         a = qd.knn_bruteforce(_t(db), _t(q), k)
         b = qd.knn_bruteforce(_t(db), _t(q), k, query_tile=16)
         for x, y in zip(a, b):
             assert np.array_equal(x.cpu().numpy(), y.cpu().numpy())
-        rows = np.array([0, 127, 128, 599])
-        _same(a, oracle.knn_brute(db, q[rows], k), rows)
+        _same(a, oracle.knn_brute(db, q, k))
 
 
 def test_matrix_core_path_overflow_falls_back_exactly(qd):

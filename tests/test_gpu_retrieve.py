@@ -63,6 +63,25 @@ def test_many_objects_and_empty_query_objects(qd):
     assert np.array_equal(used.cpu().numpy().view(np.uint32), ru)
 
 
+@pytest.mark.parametrize("use_tree", [False, True])
+def test_rows_of_no_object_cast_no_vote(qd, use_tree):
+    # a third of the rows carry object ids >= n_obj (some of them the largest
+    # uint16): their neighbours cast no vote, on the GPU as in the oracle
+    db, obj, off, q, qobj = _workload(20, 200, 6, 15, 60, 63)
+    obj = obj.copy()
+    obj[::3] = np.where(np.arange(len(obj))[::3] % 2 == 0, 20, 65535).astype(np.uint16)
+    for k, threshold in ((1, 3), (5, 10)):
+        ref_nn = oracle.knn_brute(db, q, k)
+        rv, rw, ru = oracle.votes(ref_nn.idx, obj, 20, off, threshold)
+        assert rv.sum() < k * len(q)  # some neighbours did fall on such rows
+        tree = qd.tree_build(_t(db)) if use_tree else None
+        votes, winner, used = qd.retrieve_objects(_t(q), _t(off), _t(obj), 20, k, threshold, tree=tree,
+                                                  db=None if use_tree else _t(db))
+        assert np.array_equal(votes.cpu().numpy().view(np.uint32), rv)
+        assert np.array_equal(winner.cpu().numpy(), rw)
+        assert np.array_equal(used.cpu().numpy().view(np.uint32), ru)
+
+
 def test_objects_workload_full_scale(qd):
     # 300 objects x 5,000 descriptors, 128 query objects of 200-4,000 descriptors, k = 5:
     # the votes of the whole batch follow the oracle's vote rule on the GPU's neighbours,

@@ -105,6 +105,33 @@ def test_blocked_edge_cases(qd):
     _same(qd.knn_tree(qd.tree_build(_t(one)), _t(q), 1, order=qd.ORDER_BLOCKED), oracle.knn_brute(one, q, 1))
 
 
+@pytest.mark.parametrize("plain_bound", [False, True])
+def test_blocked_degenerate_queries_on_the_matrix_cores(qd, plain_bound):
+    # block lists long enough (>= 24 queries) for the matrix-core tiles, made
+    # of degenerate queries only: all zero (|q| = 0: every block's bound is 0,
+    # the key is the row's popcount), all one (|q| = 4096), one set bit, and
+    # all but one bit; the rows include all-zero, all-one and dense rows
+    db = synth.gen_db(60_123, 1104)
+    rng = np.random.default_rng(1105)
+    at = rng.choice(len(db), 60, replace=False)
+    db[at[:20]] = 0
+    db[at[20:40]] = np.uint64(0xFFFFFFFFFFFFFFFF)
+    db[at[40:]] = rng.integers(0, 2 ** 63, (20, 64), dtype=np.int64).view(np.uint64)
+    one_bit = np.zeros((40, 64), np.uint64)
+    one_bit[np.arange(40), rng.integers(0, 64, 40)] = np.uint64(1) << rng.integers(0, 64, 40).astype(np.uint64)
+    all_but = ~one_bit
+    q = np.concatenate([np.zeros((40, 64), np.uint64), np.full((40, 64), np.uint64(0xFFFFFFFFFFFFFFFF)),
+                        one_bit, all_but])
+    tree = qd.tree_build(_t(db), plain_bound=plain_bound)
+    for k in (1, 10, 64):
+        qd.profile_enable(True)
+        res = qd.knn_tree(tree, _t(q), k, order=qd.ORDER_BLOCKED)
+        tiles = qd.profile_counter("tree_block_tiles")
+        qd.profile_enable(False)
+        _same(res, oracle.knn_brute(db, q, k))
+        assert tiles > 0
+
+
 def test_blocked_overflow_fallback(qd):
     # 30,000 copies of one descriptor: after round 1 the k-th key equals the
     # copies' key, so round 2 appends every copy of its blocks (more than a

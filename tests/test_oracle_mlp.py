@@ -87,3 +87,67 @@ def test_features_on_hand_made_nodes():
     assert np.isclose(f[0, 10 + 10], 0.5) and np.isclose(f[0, 21 + 10], 0.0)  # band of rows 60-63
     # node 2: the dissimilar child covers one query bit
     assert np.isclose(f[1, 0], 19 / 20) and f[1, 7] == 0.0 and np.isclose(f[1, 3], 0.5)
+
+
+def _hand_params():
+    """A network worked out by hand: every weight is zero except a few, all
+    exact in bfloat16.  Query bit b = 64*3 + 5 (image row 3, column 5) drives
+    hidden unit 0 up (+2) and unit 1 down (-3, below its bias of +1, so its
+    ReLU clips it); feature 4 adds 0.5 * f4 to unit 0.  In the second layer
+    unit 0 feeds output unit 0 (x1.5, bias -3/16) and output unit 1 (x-1,
+    clipped); a clipped unit 1 would add x10 to output unit 0.  The score is
+    0.5 * h2[0] + 7 * h2[1] + 1/4."""
+    W = {name: np.zeros(shape) for name, shape in mlp.SIZES}
+    b = 64 * 3 + 5
+    W["W1q"][b, 0], W["W1q"][b, 1] = 2.0, -3.0
+    W["b1"][1] = 1.0
+    W["W1f"][4, 0] = 0.5
+    W["W2"][0, 0], W["W2"][1, 0], W["W2"][0, 1] = 1.5, 10.0, -1.0
+    W["b2"][0] = -0.1875
+    W["w3"][0], W["w3"][1] = 0.5, 7.0
+    W["b3"][0] = 0.25
+    return mlp.pack(W).astype(np.float32), b
+
+
+def test_forward_on_a_hand_worked_network():
+    p, b = _hand_params()
+    q = np.zeros((3, 64), np.uint64)
+    q[0, 3] = np.uint64(1) << np.uint64(5)                              # bit b only
+    q[1, 3] = np.uint64(1) << np.uint64(5)
+    q[1, 40] = np.uint64(1) << np.uint64(63)                            # plus a bit with zero weights
+    q[2, 5] = np.uint64(1) << np.uint64(3)                              # row 5, column 3: not bit b
+    assert mlp.query_bits(q)[0].nonzero()[0].tolist() == [b]
+    feat = np.zeros((3, mlp.NF), np.float32)
+    feat[:, 4] = 0.25
+    s, c = mlp.forward(p, q, [0, 1, 2], feat)
+    # queries 0 and 1: z1 = [2 + 0.125, -3 + 1] -> h1 = [2.125, 0];
+    # z2 = [1.5 * 2.125 - 0.1875, -2.125] -> h2 = [3, 0]; s = 0.5 * 3 + 0.25
+    assert s[0] == 1.75 and s[1] == 1.75
+    assert c["h1"][0, 0] == 2.125 and c["z1"][0, 1] == -2.0 and c["h1"][0, 1] == 0.0
+    # query 2 lacks bit b: h1 = [0.125, 1]; z2[0] = 1.5 * 0.125 + 10 * 1 - 0.1875 = 10,
+    # z2[1] = -0.125 -> 0; s = 0.5 * 10 + 0.25
+    assert s[2] == 5.25
+
+
+def test_gradient_on_a_hand_worked_network():
+    p, b = _hand_params()
+    q = np.zeros((1, 64), np.uint64)
+    q[0, 3] = np.uint64(1) << np.uint64(5)
+    feat = np.zeros((1, mlp.NF), np.float32)
+    feat[0, 4] = 0.25
+    loss, g = mlp.loss_and_grad(p, q, [0], feat, [1.0])
+    ds = 1.0 / (1.0 + np.exp(-1.75)) - 1.0  # d loss / d s for label 1 at s = 1.75
+    assert np.isclose(loss, np.log1p(np.exp(-1.75)), rtol=1e-14)
+    G = mlp.unpack(g.astype(np.float64), round_bf16=False)
+    # only the paths through the unclipped units 0 (layer 1) and 0 (layer 2) carry gradient
+    assert np.isclose(G["b3"][0], ds, rtol=1e-14)
+    assert np.isclose(G["w3"][0], 3.0 * ds, rtol=1e-14) and G["w3"][1] == 0.0
+    assert np.isclose(G["b2"][0], 0.5 * ds, rtol=1e-14) and G["b2"][1] == 0.0
+    assert np.isclose(G["W2"][0, 0], 0.5 * ds * 2.125, rtol=1e-14)
+    assert G["W2"][1, 0] == 0.0 and G["W2"][0, 1] == 0.0
+    assert np.isclose(G["b1"][0], 0.75 * ds, rtol=1e-14) and G["b1"][1] == 0.0
+    assert np.isclose(G["W1q"][b, 0], 0.75 * ds, rtol=1e-14) and G["W1q"][b, 1] == 0.0
+    assert np.count_nonzero(G["W1q"]) == 1                     # only the query's one set bit, unit 0
+    assert np.isclose(G["W1f"][4, 0], 0.75 * ds * 0.25, rtol=1e-14)
+    assert np.count_nonzero(G["W1f"]) == 1                     # the other features are zero
+    assert sum(np.count_nonzero(v) for v in G.values()) == 7

@@ -34,3 +34,18 @@ def test_vote_totals_and_planted_object():
     assert (w == qobj).all()
     # with every first neighbour in the right object, the winner needs at most 10 descriptors
     assert (u <= 10).all()
+
+
+def test_rows_of_no_object_cast_no_vote():
+    # rows 1 and 3 carry ids 7 and 3, both >= n_obj = 3: they belong to no object
+    obj = np.array([0, 7, 1, 3, 2, 2], np.uint16)
+    #   d0 -> rows 1, 0   votes: o0=1 (row 1 casts none)
+    #   d1 -> rows 3, 0   votes: o0=2  <- o0 reaches 2 at descriptor 2
+    #   d2 -> rows 1, 3   no votes
+    nn = np.array([[1, 0], [3, 0], [1, 3]], np.uint32)
+    v, w, u = oracle.votes(nn, obj, 3, np.array([0, 3], np.uint64), threshold=2)
+    assert v.tolist() == [[2, 0, 0]]
+    assert w.tolist() == [0] and u.tolist() == [2]
+    # no object reaches the threshold when only rows of no object are found
+    v, w, u = oracle.votes(nn[2:], obj, 3, np.array([0, 1], np.uint64), threshold=1)
+    assert v.tolist() == [[0, 0, 0]] and w.tolist() == [-1] and u.tolist() == [1]
