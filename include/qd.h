@@ -108,6 +108,22 @@ int qd_knn_bruteforce_shaped(const uint64_t *d_db, uint64_t n, const uint64_t *d
                              uint32_t query_tile, uint32_t row_parts, uint32_t *d_idx, int32_t *d_missed,
                              int32_t *d_extra, float *d_dist, void *stream);
 
+/* For callers that cannot allocate device memory (code under hipGraph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * search as qd_knn_bruteforce, same arguments and results, on the
+ * register-tiled scan, with no device allocation and no allocating library
+ * call.  Its scratch (each wave's top-k lists) is a fixed device array of
+ * QD_NOALLOC_SCRATCH_BYTES inside the library, one per GPU, held until the
+ * process ends; its address is looked up on the first call on each device.
+ * Requests whose lists cannot fit (nq * k above QD_NOALLOC_SCRATCH_BYTES / 8)
+ * return QD_ERR_INVALID; the row slices per query are reduced as needed
+ * otherwise.  Calls on one GPU share that array: calls that overlap on one
+ * device (other streams, other threads) race and must be serialised by the
+ * caller.  Stream-ordered; nothing to free. */
+#define QD_NOALLOC_SCRATCH_BYTES (32ull << 20)
+int qd_knn_bruteforce_noalloc(const uint64_t *d_db, uint64_t n, const uint64_t *d_q, uint32_t nq, uint32_t k,
+                              uint32_t *d_idx, int32_t *d_missed, int32_t *d_extra, float *d_dist, void *stream);
+
 /* ---------------------------------------------------------------------------
  * Bit-plane index for small query batches (the sequential search of Section
  * 6.2, reorganised).  qd_planes_build stores the n descriptors transposed:

@@ -109,6 +109,26 @@ def knn_bruteforce(db, q, k, query_tile=0, row_parts=0):
     return idx, missed, extra, dist
 
 
+_sig("qd_knn_bruteforce_noalloc", [_P, _U64, _P, _U32, _U32, _P, _P, _P, _P, _P])
+NOALLOC_SCRATCH_BYTES = 32 << 20
+
+
+def knn_bruteforce_noalloc(db, q, k, out=None):
+    """Sequential search that allocates no device memory inside the library
+    (its scratch is a fixed array per GPU).  ``out`` = (idx, missed, extra,
+    dist) tensors of shape (nq, k) to write into; new ones if omitted."""
+    _desc(db, "db")
+    _desc(q, "q")
+    idx, missed, extra, dist = out if out is not None else _results(q.shape[0], k, db.device)
+    for t, dt in zip((idx, missed, extra, dist), (torch.int32, torch.int32, torch.int32, torch.float32)):
+        if not (t.is_cuda and t.dtype == dt and t.is_contiguous() and t.numel() >= q.shape[0] * k):
+            raise ValueError("outputs must be contiguous cuda tensors of nq x k int32/int32/int32/float32")
+    rc = _lib.qd_knn_bruteforce_noalloc(_ptr(db), db.shape[0], _ptr(q), q.shape[0], k, _ptr(idx), _ptr(missed),
+                                        _ptr(extra), _ptr(dist), _stream())
+    _check(rc, "qd_knn_bruteforce_noalloc")
+    return idx, missed, extra, dist
+
+
 def profile_enable(on=True):
     _check(_lib.qd_profile_enable(1 if on else 0), "qd_profile_enable")
 

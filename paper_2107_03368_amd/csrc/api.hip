@@ -54,7 +54,7 @@ static std::vector<KernelTotal> g_totals;
 bool profiling() { return g_prof_on; }
 
 KernelTimer::KernelTimer(const char *name, hipStream_t s) : name_(name), s_(s) {
-    if (!g_prof_on) return;
+    if (!g_prof_on || !name) return;  // a null name times nothing (and creates no events)
     hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
     if (hipStreamIsCapturing(s_, &cap) != hipSuccess || cap != hipStreamCaptureStatusNone) return;  // no events in graphs
     if (hipEventCreate(&a_) != hipSuccess || hipEventCreate(&b_) != hipSuccess) {

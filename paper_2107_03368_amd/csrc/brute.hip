@@ -224,14 +224,14 @@ BruteLaunch brute_launch_shape(uint64_t n, uint32_t nq, uint32_t k, uint32_t qt_
 
 int brute_launch(const BruteLaunch &sh, u64 *part, const uint64_t *d_db, uint64_t n, const uint64_t *d_q, uint32_t nq,
                  const uint32_t *nq_dev, uint32_t k, uint32_t *d_idx, int32_t *d_missed, int32_t *d_extra,
-                 float *d_dist, hipStream_t s) {
+                 float *d_dist, hipStream_t s, bool timed) {
     // the dispatch packet holds the grid size in work-items as a 32-bit number
     if (sh.blocks * kBlock > 0xFFFFFFFFull) return fail(QD_ERR_UNSUPPORTED, "launch too large");
     const uint4 *db4 = reinterpret_cast<const uint4 *>(d_db);
     const uint4 *q4 = reinterpret_cast<const uint4 *>(d_q);
     dim3 grid((uint32_t)sh.blocks);
     {
-        KernelTimer timer("wh_scan_topk", s);
+        KernelTimer timer(timed ? "wh_scan_topk" : nullptr, s);
         switch (sh.qt) {
             case 1: launch_scan<1>(grid, s, db4, n, q4, nq, k, sh.n_qtiles, sh.n_parts, sh.rows_per_part, part, nq_dev); break;
             case 2: launch_scan<2>(grid, s, db4, n, q4, nq, k, sh.n_qtiles, sh.n_parts, sh.rows_per_part, part, nq_dev); break;
@@ -242,7 +242,7 @@ int brute_launch(const BruteLaunch &sh, u64 *part, const uint64_t *d_db, uint64_
     }
     QD_HIP_CHECK(hipGetLastError());
     {
-        KernelTimer timer("topk_merge", s);
+        KernelTimer timer(timed ? "topk_merge" : nullptr, s);
         hipLaunchKernelGGL(merge_emit_kernel, dim3(nq), dim3(kBlock), 0, s, part, sh.n_parts, k, d_q, d_db, d_idx,
                            d_missed, d_extra, d_dist, nq_dev);
     }

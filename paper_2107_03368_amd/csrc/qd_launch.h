@@ -26,7 +26,7 @@ struct BruteLaunch {
 BruteLaunch brute_launch_shape(uint64_t n, uint32_t nq_max, uint32_t k, uint32_t qt_force, uint32_t parts_force);
 int brute_launch(const BruteLaunch &L, u64 *part, const uint64_t *d_db, uint64_t n, const uint64_t *d_q, uint32_t nq,
                  const uint32_t *nq_dev, uint32_t k, uint32_t *d_idx, int32_t *d_missed, int32_t *d_extra,
-                 float *d_dist, hipStream_t s);
+                 float *d_dist, hipStream_t s, bool timed = true);
 
 int vote_launch(const uint32_t *nn, uint32_t k, const uint16_t *obj_of, uint64_t n_db, uint32_t n_obj,
                 const uint64_t *qoff, uint32_t nqo, const uint32_t *nqo_dev, uint32_t threshold, uint32_t *votes,

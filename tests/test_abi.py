@@ -104,3 +104,20 @@ def test_planes_argument_errors_without_device_work():
     f.argtypes = [P, P, U32, U32, P, P, P, P, P]
     assert f(None, a, 1, 1, a, a, a, a, None) == -1           # no index
     assert lib.qd_planes_free(None) == 0
+
+
+def test_noalloc_argument_errors_without_device_work():
+    lib = ctypes.CDLL(LIB)
+    lib.qd_last_error.restype = ctypes.c_char_p
+    f = lib.qd_knn_bruteforce_noalloc
+    P, U64, U32 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32
+    f.argtypes = [P, U64, P, U32, U32, P, P, P, P, P]
+    a = P(0x10000)
+    assert f(a, 100, a, 5, 0, a, a, a, a, None) == -1            # k = 0
+    assert f(a, 0, a, 5, 10, a, a, a, a, None) == -1             # empty database
+    assert f(a, 100, a, 5, 10, None, a, a, a, None) == -1        # null output
+    assert f(P(0x10008), 100, a, 5, 10, a, a, a, a, None) == -1  # misaligned rows
+    assert f(a, 100, a, 0, 10, a, a, a, a, None) == 0            # nq = 0 is a no-op
+    # the lists of nq * k keys (one per query at the least) exceed the fixed scratch
+    assert f(a, 100, a, 65_537, 64, a, a, a, a, None) == -1
+    assert b"scratch" in lib.qd_last_error()
