@@ -77,7 +77,10 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="10m", choices=sorted(WORKLOADS))
-    ap.add_argument("--cpu-sample", type=int, default=48, help="queries in the oracle's timed sample (0 = skip)")
+    ap.add_argument("--cpu-sample", type=int, default=64, help="queries in the oracle's timed sample (0 = skip)")
+    ap.add_argument("--cpu-sample-1t", type=int, default=8, help="queries in the oracle's single-thread sample")
+    ap.add_argument("--cpu-tree-rows", type=int, default=100_000,
+                    help="rows of the prefix the oracle builds and searches its tree on (0 = skip)")
     ap.add_argument("--paths", default="brute,tree,learned",
                     help="brute, tree (best-first, depth-first, blocked), blocked (blocked only), learned")
     ap.add_argument("--max-batch", type=int, default=0, help="stream50m: descriptors per batch (0 = workload's)")
@@ -131,6 +134,7 @@ def main():
     paths["brute"] = lambda: qd.knn_bruteforce(dbt, qt, k)
     tree = None
     train = None
+    model = None
     build_s = None
     if ("tree" in wanted or "learned" in wanted or "blocked" in wanted) and hasattr(qd, "tree_build"):
         t0 = time.time()
@@ -162,11 +166,13 @@ def main():
             log(f"order model trained on {npairs} traced pairs in {train['seconds']:.1f}s, loss "
                 f"{train['loss_first']:.4f} -> {train['loss_last']:.4f}")
             n_scored = min(N_SCORED, tree.n_nodes)
-
-            def learned():
-                sc = qd.model_score_tree(model, tree, qt, n_scored)
-                return qd.knn_tree(tree, qt, k, order=qd.ORDER_DEPTH_FIRST, scores=sc)
-            paths["tree_learned"] = learned
+            # per-query depth-first search in the model's order (the library scores
+            # the top n_scored nodes), and the blocked search starting where the
+            # model leads
+            paths["tree_learned"] = lambda: qd.knn_tree(tree, qt, k, order=qd.ORDER_DEPTH_FIRST, model=model,
+                                                        n_scored=n_scored)
+            if "tree_blocked" in paths:
+                paths["tree_blocked_learned"] = lambda: qd.knn_tree(tree, qt, k, order=qd.ORDER_BLOCKED, model=model)
 
     # reference result for the cross-path exactness check (outside timing)
     ref = [x.cpu() for x in paths["brute"]()]
@@ -199,29 +205,69 @@ def main():
         counters = {c: qd.profile_counter(c) / args.steps for c in ("tree_block_tiles", "tree_block_short_pairs")}
         qd.profile_enable(False)
         per_path[name] = {"ms": dt * 1e3, "queries_per_s": nq / dt, "kernels": kernels}
-        if name == "tree_blocked":
+        if name.startswith("tree_blocked"):
             per_path[name]["per_call"] = counters
         if name.startswith("tree"):
-            res = (qd.knn_tree(tree, qt, k, totals=True, query_stats=True) if name == "tree" else
-                   qd.knn_tree(tree, qt, k, order=qd.ORDER_BLOCKED, totals=True, query_stats=True)
-                   if name == "tree_blocked" else
-                   qd.knn_tree(tree, qt, k, order=qd.ORDER_DEPTH_FIRST, totals=True, query_stats=True,
-                               scores=qd.model_score_tree(model, tree, qt, n_scored) if name == "tree_learned"
-                               else None))
+            kw = {"tree": {}, "tree_dfs": dict(order=qd.ORDER_DEPTH_FIRST),
+                  "tree_blocked": dict(order=qd.ORDER_BLOCKED),
+                  "tree_learned": dict(order=qd.ORDER_DEPTH_FIRST, model=model, n_scored=N_SCORED),
+                  "tree_blocked_learned": dict(order=qd.ORDER_BLOCKED, model=model)}[name]
+            res = qd.knn_tree(tree, qt, k, totals=True, query_stats=True, **kw)
             st, qs = res[-1], res[-2].cpu().numpy().astype(np.int64)
             per_path[name]["per_query"] = {kk: v / nq for kk, v in st.items()}
             per_path[name]["nodes_visited_p50_p99"] = [float(np.percentile(qs[:, 0], 50)),
                                                        float(np.percentile(qs[:, 0], 99))]
-            if name != "tree_blocked":
+            if name.startswith("tree_blocked"):
+                # blocks evaluated (round 1 included) and rounds taken part in, per query
+                per_path[name]["blocks_per_query"] = st["nodes_visited"] / nq
+                per_path[name]["rounds_per_query"] = st["leaves_visited"] / nq
+            else:
                 # per-query traversal: child OR images (512 B per bound) and leaf rows with
                 # their popcounts (514 B per distance) gathered from HBM
                 gb = (st["bounds_evaluated"] * 512 + st["dists_evaluated"] * 514) / dt / 1e9
                 per_path[name]["gather_GB_s"] = gb
                 per_path[name]["gather_frac_of_hbm_peak"] = gb / HBM_PEAK_GBS
-            if name == "tree_learned":
+            if name.endswith("learned"):
                 sc_ms = sum(v["avg_ms"] * v["launches"] for kk, v in kernels.items() if kk.startswith("mlp"))
                 per_path[name]["score_time_fraction"] = sc_ms / args.steps / (dt * 1e3)
         log(f"{name}: {dt * 1e3:.2f} ms/batch, {nq / dt:.0f} q/s, kernels {kernels}")
+
+    # the learned start where an order can save blocks: at k = 1 the bound order
+    # evaluates more than the fewest blocks any exact order must (at k = 10 it is
+    # within half a percent of them); a model trained on k = 1 traces
+    learned_k1 = None
+    if "tree_blocked_learned" in paths:
+        t0 = time.time()
+        tdb = synth.gen_db(1_000_000, 1001)
+        tq, _ = synth.gen_queries(tdb, TRAIN_QUERIES, 2001, 0.1, 0.6)
+        ttree = qd.tree_build(torch.from_numpy(tdb.view(np.int64)).to(dev))
+        model1 = qd.Model(torch.from_numpy(synth.uniform_f32(qd.MLP_NPARAMS, 3003, -0.05, 0.05)).to(dev))
+        nb = (TRAIN_QUERIES + TRAIN_BATCH - 1) // TRAIN_BATCH
+        _, npairs1 = qd.model_train(model1, ttree, torch.from_numpy(tq.view(np.int64)).to(dev), 1, N_SCORED,
+                                    TRAIN_EPOCHS, TRAIN_BATCH, TRAIN_LR, batch_order=synth.permutation(nb, 3004))
+        del ttree, tdb
+        train1_s = time.time() - t0
+        k1 = {}
+        res1 = {}
+        for name, mdl in (("blocked", None), ("blocked_learned", model1)):
+            fn = lambda: qd.knn_tree(tree, qt, 1, order=qd.ORDER_BLOCKED, model=mdl)
+            for _ in range(args.warmup):
+                fn()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                fn()
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / args.steps
+            r = qd.knn_tree(tree, qt, 1, order=qd.ORDER_BLOCKED, model=mdl, totals=True, query_stats=True)
+            res1[name] = [x.cpu() for x in r[:4]]
+            k1[name] = {"ms": dt * 1e3, "queries_per_s": nq / dt, "blocks_per_query": r[-1]["nodes_visited"] / nq}
+        if not all(torch.equal(a, b) for a, b in zip(res1["blocked"], res1["blocked_learned"])):
+            raise SystemExit("k = 1: learned start differs from the bound-order start")
+        learned_k1 = {"training_pairs": npairs1, "training_s": train1_s, **k1}
+        log(f"k=1: blocked {k1['blocked']['ms']:.2f} ms ({k1['blocked']['blocks_per_query']:.0f} blocks/query), "
+            f"learned start {k1['blocked_learned']['ms']:.2f} ms "
+            f"({k1['blocked_learned']['blocks_per_query']:.0f} blocks/query)")
 
     # small-batch scan: HBM-bound regime (one pass over the rows serves <= 8 queries)
     hbm = {}
@@ -298,23 +344,7 @@ def main():
 
     cpu = None
     if args.cpu_sample > 0:
-        import oracle
-        m = min(args.cpu_sample, nq)
-        t0 = time.perf_counter()
-        r = oracle.knn_brute(db, q[:m], k)
-        cdt = time.perf_counter() - t0
-        if not np.array_equal(r.idx, ref[0][:m].numpy().view(np.uint32)):
-            raise SystemExit("oracle sample differs from GPU sequential search")
-        threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-        cpu = {"value": m / cdt, "unit": "queries/s", "cores": threads, "kind": "oracle",
-               "sample": f"first {m} of the {nq} queries, sequential search over all {n} rows, k={k}"}
-        try:
-            with open("/proc/cpuinfo") as f:
-                cpu["cpu_model"] = next(l.split(":", 1)[1].strip() for l in f if l.startswith("model name"))
-        except (OSError, StopIteration):
-            pass
-        cpu["logical_cpus"] = os.cpu_count()
-        log(f"oracle: {m} queries in {cdt:.1f}s")
+        cpu = cpu_baseline(args, db, q, ref, w, dev)
 
     out = {
         "metric": "exact kNN queries/s (4096-bit WHD) at 10M descs: brute vs tree vs tree+learned order",
@@ -325,10 +355,11 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "fp4", "data": "synthetic",
         "config": {"workload": f"{args.workload}: {n} descriptors x {nq} queries, k={k}", "n": n, "queries": nq,
-                   "k": k, "value_path": best},
+                   "k": k, "value_path": best, "value_path_ms_per_batch": per_path[best]["ms"]},
         "paths": per_path,
         "tree_build_s": build_s,
         "order_model_training": train,
+        "learned_start_k1": learned_k1,
         "brute_small_batch_hbm": hbm,
         "brute_register_tiled_valu": valu,
         "recall_source_row_at_1": recall,
@@ -337,6 +368,95 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+
+
+def physical_cores():
+    """(physical cores, CPU model) from /proc/cpuinfo: distinct (package, core) pairs."""
+    cores, model, phys, core = set(), None, None, None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                key, _, val = line.partition(":")
+                key, val = key.strip(), val.strip()
+                if key == "model name" and model is None:
+                    model = val
+                elif key == "physical id":
+                    phys = val
+                elif key == "core id":
+                    core = val
+                elif not key and phys is not None:
+                    cores.add((phys, core))
+                    phys = core = None
+        if phys is not None:
+            cores.add((phys, core))
+    except OSError:
+        pass
+    return (len(cores) or None), model
+
+
+def cpu_baseline(args, db, q, ref, w, dev):
+    """The oracle timed on this host on bounded samples of the workload: its
+    sequential search over all rows (all threads, then one), and its tree build
+    and tree search over a prefix of the rows.  Every sample's results are
+    compared with the GPU's on all four outputs."""
+    import torch
+    import oracle
+    import synth
+    import paper_2107_03368_amd as qd
+    n, nq, k = w["n"], w["nq"], w["k"]
+    threads = oracle.max_threads()
+    m = min(args.cpu_sample, nq)
+    t0 = time.perf_counter()
+    r = oracle.knn_brute(db, q[:m], k)
+    cdt = time.perf_counter() - t0
+
+    def same(res, gpu, rows):
+        return all(np.array_equal(a, b) for a, b in zip(
+            (res.idx, res.missed, res.extra, res.dist),
+            (gpu[0][rows].numpy().view(np.uint32), gpu[1][rows].numpy(), gpu[2][rows].numpy(), gpu[3][rows].numpy())))
+    if not same(r, ref, slice(0, m)):
+        raise SystemExit("oracle sample differs from GPU sequential search")
+    log(f"oracle: {m} queries in {cdt:.1f}s on {threads} threads")
+    m1 = min(args.cpu_sample_1t, m)
+    oracle.set_threads(1)
+    t0 = time.perf_counter()
+    r1 = oracle.knn_brute(db, q[:m1], k)
+    dt1 = time.perf_counter() - t0
+    oracle.set_threads(threads)
+    if not same(r1, ref, slice(0, m1)):
+        raise SystemExit("single-thread oracle sample differs from GPU sequential search")
+    log(f"oracle: {m1} queries in {dt1:.1f}s on 1 thread")
+    phys, model = physical_cores()
+    cpu = {"value": m / cdt, "unit": "queries/s", "cores": threads, "kind": "oracle",
+           "sample": f"first {m} of the {nq} queries, sequential search over all {n} rows, k={k}",
+           "single_thread": {"value": m1 / dt1, "unit": "queries/s", "sample": f"first {m1} queries"},
+           "physical_cores": phys, "logical_cpus": os.cpu_count(),
+           "cpus_allowed": len(os.sched_getaffinity(0)), "cpu_model": model}
+    nt = min(args.cpu_tree_rows, n)
+    if nt > 0:
+        # the oracle's tree (Listing 1 move loop, single-threaded) and its best-first
+        # search over a prefix of the rows, with queries drawn from that prefix
+        sub = np.ascontiguousarray(db[:nt])
+        tq, _ = synth.gen_queries(sub, 512, w["seed_q"] + 100, w["pmin"], w["pmax"])
+        t0 = time.perf_counter()
+        otree = oracle.tree_build(sub)
+        build_s = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        rt = oracle.tree_knn(sub, otree, tq, k, use_pop=True)
+        tree_s = time.perf_counter() - t0
+        subt = torch.from_numpy(sub.view(np.int64)).to(dev)
+        tqt = torch.from_numpy(tq.view(np.int64)).to(dev)
+        gtree = qd.tree_build(subt)
+        g = [x.cpu() for x in qd.knn_tree(gtree, tqt, k, order=qd.ORDER_BLOCKED)]
+        if not same(rt, g, slice(None)):
+            raise SystemExit("oracle tree search differs from the GPU blocked tree search")
+        del gtree, subt
+        cpu["tree_prefix"] = {"rows": nt, "queries": len(tq), "threads": threads,
+                              "build_s": build_s, "build_threads": 1,
+                              "search_queries_per_s": len(tq) / tree_s,
+                              "nodes_visited_per_query": float(rt.stats[:, 0].mean())}
+        log(f"oracle tree on {nt} rows: build {build_s:.1f}s, search {len(tq) / tree_s:.0f} q/s")
+    return cpu
 
 
 def objects_main(args, w, dev):
@@ -359,9 +479,24 @@ def objects_main(args, w, dev):
     objt = torch.from_numpy(obj.view(np.int16)).to(dev)
     tree = qd.tree_build(dbt)
     k, thr, n_obj = w["k"], w["threshold"], w["n_obj"]
+    # autotuned: the blocked round schedule and the sequential scan's path, each
+    # timed on a sample batch (the first 16,384 descriptors); then one plan per
+    # path, created once, serves the whole batch as a graph replay
+    t0 = time.perf_counter()
+    sample = qt[:min(16384, len(rows))]
+    tuned_tree, cands_tree = qd.autotune(sample, k, tree=tree, reps=2, orders=(qd.ORDER_BLOCKED,))
+    tuned_seq, cands_seq = qd.autotune(sample, k, db=dbt, reps=2)
+    tune_s = time.perf_counter() - t0
+    log(f"autotuned in {tune_s:.1f}s: tree {tuned_tree}, sequential {tuned_seq}")
+    plan_tree = qd.Plan(objt, n_obj, max_qdesc=len(rows), max_qobj=w["n_qo"], k=k, threshold=thr, tree=tree,
+                        order=qd.ORDER_BLOCKED, schedule=tuned_tree["schedule"])
+    plan_seq = qd.Plan(objt, n_obj, max_qdesc=len(rows), max_qobj=w["n_qo"], k=k, threshold=thr, db=dbt,
+                       query_tile=tuned_seq["query_tile"])
     runs = {
         "brute": lambda: qd.retrieve_objects(qt, offt, objt, n_obj, k, thr, db=dbt),
+        "brute_plan": lambda: plan_seq.run(qt, offt),
         "tree_blocked": lambda: qd.retrieve_objects(qt, offt, objt, n_obj, k, thr, tree=tree, order=qd.ORDER_BLOCKED),
+        "tree_blocked_plan": lambda: plan_tree.run(qt, offt),
         "tree_blocked_early_exit": lambda: qd.retrieve_objects_early(qt, offt, objt, n_obj, k, thr, tree=tree,
                                                                      order=qd.ORDER_BLOCKED),
         "brute_early_exit": lambda: qd.retrieve_objects_early(qt, offt, objt, n_obj, k, thr, db=dbt),
@@ -423,6 +558,8 @@ def objects_main(args, w, dev):
                                f"objects ({len(rows)} descriptors), k={k}, threshold={thr}"},
         "paths": out, "winner_is_source_object": float((winner == qobj).mean()),
         "object_scores": obj_scores,
+        "autotune": {"seconds": tune_s, "sample_descriptors": int(sample.shape[0]), "tree": tuned_tree,
+                     "sequential": tuned_seq, "tree_candidates": cands_tree, "sequential_candidates": cands_seq},
     }
     print(json.dumps(res), flush=True)
 
@@ -523,22 +660,56 @@ def stream_main(args, w, dev):
     k = w["k"]
     max_batch = args.max_batch or w["max_batch"]
     sizes = np.diff(off).astype(np.int64)
+    # query objects' descriptors vote for their objects (rows of object o: o*5000 .. o*5000+4999)
+    objt = torch.from_numpy((np.arange(w["n"]) // w["per_obj"]).astype(np.uint16).view(np.int16)).to(dev)
+    # the blocked schedule, autotuned on the first full batch; plans created
+    # once (outside timing) serve every batch as a graph replay
+    nb0 = int(min(max_batch, len(rows)))
+    t0 = time.perf_counter()
+    tuned, _ = qd.autotune(qt[:nb0], k, tree=tree, reps=2, orders=(qd.ORDER_BLOCKED,))
+    tune_s = time.perf_counter() - t0
+    log(f"autotuned blocked schedule {tuned['schedule']} in {tune_s:.1f}s")
+    max_objs = w["n_qo"]
+    plan_tree = qd.Plan(objt, w["n_obj"], max_qdesc=max_batch, max_qobj=max_objs, k=k, threshold=10, tree=tree,
+                        order=qd.ORDER_BLOCKED, schedule=tuned["schedule"])
+    plan_seq = qd.Plan(objt, w["n_obj"], max_qdesc=max_batch, max_qobj=max_objs, k=k, threshold=10, db=dbt)
+
+    def plan_path(plan):
+        def run(o0, o1):
+            a = int(off[o0])
+            sub = torch.from_numpy((off[o0:o1 + 1] - off[o0]).view(np.int64)).to(dev)
+            return plan.run(qt[a:int(off[o1])], sub)
+        return run
     paths = {"brute": lambda a, b: qd.knn_bruteforce(dbt, qt[a:b], k),
              "tree_blocked": lambda a, b: qd.knn_tree(tree, qt[a:b], k, order=qd.ORDER_BLOCKED)}
+    plans = {"brute_plan": plan_path(plan_seq), "tree_blocked_plan": plan_path(plan_tree)}
     # exactness on the first full batch
-    nb0 = int(min(max_batch, len(rows)))
     ref = [x.cpu() for x in paths["brute"](0, nb0)]
     out = [x.cpu() for x in paths["tree_blocked"](0, nb0)]
     if not all(torch.equal(a, b) for a, b in zip(ref, out)):
         raise SystemExit("blocked tree search differs from sequential search")
+    o_end = int(np.searchsorted(off, nb0, side="right")) - 1  # whole objects within the first batch
+    pv = [plans[name](0, max(o_end, 1)) for name in plans]
+    direct = qd.retrieve_objects(qt[:int(off[max(o_end, 1)])],
+                                 torch.from_numpy(off[:max(o_end, 1) + 1].view(np.int64)).to(dev), objt, w["n_obj"], k,
+                                 10, db=dbt)
+    for name, got in zip(plans, pv):
+        if not all(torch.equal(a, b) for a, b in zip(got, direct)):
+            raise SystemExit(f"{name}: votes differ from direct retrieval")
 
     def run_batch(fn, o0, o1):
         a, b = int(off[o0]), int(off[o1])
         torch.cuda.synchronize()
         t = time.perf_counter()
-        fn(a, b)
+        if getattr(fn, "by_object", False):
+            fn(o0, o1)
+        else:
+            fn(a, b)
         torch.cuda.synchronize()
         return time.perf_counter() - t
+    for fn in plans.values():
+        fn.by_object = True
+    paths.update(plans)
 
     def batches(start_objects):
         """Whole objects from the list, greedily up to max_batch descriptors (>= 1 object)."""
@@ -590,12 +761,14 @@ def stream_main(args, w, dev):
         result[name] = per
     out = {
         "metric": "exact kNN serving at 50M descriptors: queries/s and p50/p99 latency per query object",
-        "value": result["tree_blocked"]["saturated_queries_per_s"], "unit": "queries/s",
+        "value": max(r["saturated_queries_per_s"] for r in result.values()), "unit": "queries/s",
+        "value_path": max(result, key=lambda nm: result[nm]["saturated_queries_per_s"]),
         "n_gpus": 1, "higher_is_better": True, "dtype": "fp4", "data": "synthetic",
         "config": {"workload": f"stream50m: {w['n']} descriptors, {w['n_qo']} query objects of "
                                f"{w['mmin']}-{w['mmax']} descriptors ({len(rows)} in all), k={k}, "
                                f"batches of up to {max_batch} descriptors"},
         "tree_build_s": build_s, "paths": result,
+        "autotune": {"seconds": tune_s, "sample_descriptors": nb0, "tree": tuned},
     }
     print(json.dumps(out), flush=True)
 

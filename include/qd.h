@@ -59,11 +59,23 @@ typedef enum {
     QD_ERR_DEVICE = -3,      /* HIP runtime or kernel launch failure */
     QD_ERR_UNSUPPORTED = -4, /* valid request this build does not serve */
     QD_ERR_ABORTED = -5,     /* stopped through an abort flag */
-    QD_ERR_FORMAT = -6       /* malformed serialized data */
+    QD_ERR_FORMAT = -6,      /* malformed serialized data */
+    QD_ERR_IO = -7           /* a file could not be opened, read or written */
 } qd_status;
 
 /* Message for the calling thread's last non-OK status ("" if none). */
 const char *qd_last_error(void);
+
+/* Cancellation of long synchronous calls.  After qd_set_abort_flag(flag),
+ * the calling thread's multi-step synchronous calls read *flag before each
+ * step -- qd_tree_build before each level, qd_tree_load before its device
+ * pass, qd_model_train before each step, qd_retrieve_objects_early before
+ * each round, qd_autotune before each candidate -- and when it is non-zero
+ * they wait for the work they queued, release their scratch and return
+ * QD_ERR_ABORTED (their outputs are then undefined; a model keeps the steps
+ * it took).  The flag may be written from another thread or a signal
+ * handler; NULL removes it.  Asynchronous calls do not read it. */
+int qd_set_abort_flag(const volatile int *flag);
 
 /* Library version as MAJOR*10000 + MINOR*100 + PATCH. */
 int qd_version(void);
@@ -185,6 +197,22 @@ int qd_tree_build(const uint64_t *d_db, uint64_t n, const qd_build_params *param
 int qd_tree_free(qd_tree_t t);
 int qd_tree_info(qd_tree_t t, qd_tree_info_t *info);
 
+/* Save a tree to a file and load it back (Section 4.1: the index is built
+ * once, offline, and queried afterwards).  The file holds the rows in leaf
+ * order, the leaf-order permutation and the breadth-first structure (child
+ * pairs, begin, count) behind a 64-byte versioned header with FNV-1a hashes
+ * of the header and of the payload; the layout is documented in
+ * csrc/tree_io.hip.  qd_tree_load reads the whole file and checks header,
+ * hashes and structure on the host before any device work: a file that fails
+ * returns QD_ERR_FORMAT (QD_ERR_IO if it cannot be opened or read) and
+ * allocates nothing.  It then rebuilds every derived array (images,
+ * popcounts, popcount ranges, block images) from the rows on the current
+ * device, so the loaded tree answers every query exactly as the saved one.
+ * Both calls are synchronous; qd_tree_load uses `stream` for its device
+ * work.  The caller frees the loaded tree with qd_tree_free. */
+int qd_tree_save(qd_tree_t t, const char *path);
+int qd_tree_load(const char *path, void *stream, qd_tree_t *out);
+
 /* Copy the tree's arrays to caller-owned HOST buffers (any may be NULL):
  * h_child n_nodes x 2 (similar, dissimilar; -1 for leaves), h_begin and
  * h_count n_nodes, h_or / h_and n_nodes x 64 words, h_perm n.  Synchronous. */
@@ -226,9 +254,9 @@ int qd_tree_export(qd_tree_t t, int32_t *h_child, uint32_t *h_begin, uint32_t *h
  *     bound is <= its current k-th key, until no block is left that could
  *     hold a better key.  A query whose candidate buffer overflows repeats
  *     the round with a tighter key; one whose key cannot tighten (more rows
- *     tie at its k-th key than a buffer holds) is searched again best-first.
- *     Waits for the stream between rounds (not
- *     capturable); takes no scores or traces.  Per-query stats mean: blocks
+ *     tie at its k-th key than a buffer holds) is searched again depth-first.
+ *     A direct call waits for the stream between rounds; plans run it
+ *     without host waits (see qd_plan_create).  Takes no scores or traces.  Per-query stats mean: blocks
  *     evaluated, rounds taken part in, blocks bounded, distances evaluated.
  * d_query_stats (nullable): nq x 4 uint32 per query: nodes visited
  * (expanded pops, leaves and inner nodes), leaves visited, bounds evaluated,
@@ -237,6 +265,7 @@ int qd_tree_export(qd_tree_t t, int32_t *h_child, uint32_t *h_begin, uint32_t *h
  * which of the first n_traced nodes each query expanded (traversal traces).
  * ------------------------------------------------------------------------- */
 typedef enum { QD_ORDER_BEST_FIRST = 0, QD_ORDER_DEPTH_FIRST = 1, QD_ORDER_BLOCKED = 2 } qd_order;
+typedef struct qd_model_s *qd_model_t; /* learned-order model, see below */
 
 typedef struct {
     qd_order order;
@@ -254,6 +283,18 @@ typedef struct {
     uint32_t round1_blocks;
     uint32_t round2_blocks;
     uint32_t round_growth;
+    /* Learned order (nullable; see "Learned frontier order" below).
+       QD_ORDER_DEPTH_FIRST: the library scores nodes 0 .. n_scored-1 of the
+       tree for every query (n_scored 0 = min(2047, nodes)) and visits the
+       higher-scoring child first, as with d_scores (which must then be NULL).
+       QD_ORDER_BLOCKED: round 1 starts where the model leads: from the root,
+       the search enters at every inner node holding more than round1_blocks
+       x 256 rows the child the model scores higher (ties: the similar child),
+       and round 1 evaluates the round1_blocks consecutive blocks of the leaf
+       order that begin with the reached node's first block; the other blocks
+       follow in the bound-ordered rounds.  Results are identical with and
+       without a model. */
+    qd_model_t model;
 } qd_search_params;
 
 typedef struct {
@@ -360,8 +401,6 @@ int qd_score_rows(double *d_scores, uint32_t nqo, uint32_t n_obj, int normalize,
 #define QD_MLP_FEATURES 32
 #define QD_MLP_NPARAMS 1123073
 
-typedef struct qd_model_s *qd_model_t;
-
 /* New model from device fp32 parameters (copied); synchronous. */
 int qd_model_create(const float *d_params, void *stream, qd_model_t *out);
 int qd_model_free(qd_model_t m);
@@ -414,19 +453,25 @@ int qd_model_train(qd_model_t m, qd_tree_t t, const uint64_t *d_q, uint32_t nq, 
 /* ---------------------------------------------------------------------------
  * Batched retrieval plans (an extension: the paper runs query objects one
  * descriptor at a time).  A plan fixes the search (tree t, or sequential
- * search over d_db when t is NULL; params picks the tree frontier order and
- * occupancy, query_tile the sequential scan's tile, 0 = 16), k, the vote
- * threshold and the largest batch (max_qdesc descriptors in max_qobj query
- * objects).  It allocates all its device memory at creation and records one
- * batch -- the k-NN of every descriptor in one launch, then the votes -- into
- * a hipGraph whose kernels read the batch size from device memory.
- * qd_plan_run serves one batch exactly as qd_retrieve_objects would (same
- * arguments and outputs): it copies the inputs into the plan, replays the
- * graph on `stream` and copies the outputs out; it allocates nothing and never
- * waits for the device.  Runs of one plan must not overlap (they share its
- * buffers).  The plan keeps pointers to t, d_db and d_obj_of, which must
- * outlive it.  The sequential search in a plan always uses the register-tiled
- * scan (the matrix-core path needs a host decision per batch).
+ * search over d_db when t is NULL), k, the vote threshold and the largest
+ * batch (max_qdesc descriptors in max_qobj query objects).  params picks the
+ * tree's order (best-first, depth-first or blocked, with occupancy or round
+ * schedule; no model, scores or traces); query_tile picks the sequential
+ * scan: 0 = the matrix cores when max_qdesc >= 512 over >= 65,536 rows (as
+ * qd_knn_bruteforce decides for a batch of max_qdesc), else the register-tiled
+ * scan with that tile (0 = 16).  It allocates all its device memory at
+ * creation and records one batch -- the k-NN of every descriptor, then the
+ * votes -- into a hipGraph whose kernels read the batch size from device
+ * memory and never wait for the host: the blocked order runs a fixed number
+ * of rounds per batch of up to 16,384 descriptors (queries still running
+ * after them, and queries whose candidates overflow, are searched again one
+ * by one, exactly), the matrix-core scan's overflow fallback takes its count
+ * from the device.  qd_plan_run serves one batch exactly as
+ * qd_retrieve_objects would (same arguments and outputs): it copies the
+ * inputs into the plan, replays the graph on `stream` and copies the outputs
+ * out; it allocates nothing and never waits for the device.  Runs of one
+ * plan must not overlap (they share its buffers).  The plan keeps pointers to
+ * t, d_db and d_obj_of, which must outlive it.
  * ------------------------------------------------------------------------- */
 typedef struct qd_plan_s *qd_plan_t;
 
@@ -439,7 +484,9 @@ int qd_plan_free(qd_plan_t p);
 
 /* ---------------------------------------------------------------------------
  * Autotuner: times every launch configuration of a k-NN batch (tree t:
- * frontier order x waves per CU; sequential search: automatic path and query
+ * best-first and depth-first x waves per CU, and the blocked order x round
+ * schedules -- round-1 blocks 8, 16, 32, growth 2, 4, 8, round-2 coverage
+ * half, default and double; sequential search: automatic path and query
  * tiles 4, 8, 16) over `reps` runs after one warm-up on the caller's sample
  * batch, and returns the fastest in *best (every configuration returns the
  * same exact result).  With `all`, every candidate's timing is written too.
@@ -451,13 +498,17 @@ int qd_plan_free(qd_plan_t p);
 typedef struct {
     int path;              /* 1 = tree search, 0 = sequential search */
     qd_order order;        /* tree: frontier order */
-    uint32_t waves_per_cu; /* tree: occupancy (0 = default) */
+    uint32_t waves_per_cu; /* tree, per-query orders: occupancy (0 = default) */
     uint32_t query_tile;   /* sequential: query tile (0 = automatic, matrix cores for large batches) */
     float ms;              /* mean time of one batch */
+    uint32_t round1_blocks, round2_blocks, round_growth; /* blocked order: qd_search_params' schedule */
 } qd_tuning;
 
+/* order_mask (tree only): the frontier orders to time, bit (1 << order) for
+ * each qd_order; 0 = all.  The cache key includes it. */
 int qd_autotune(qd_tree_t t, const uint64_t *d_db, uint64_t n, const uint64_t *d_q, uint32_t nq, uint32_t k,
-                uint32_t reps, qd_tuning *best, qd_tuning *all, uint32_t max_all, uint32_t *n_all, void *stream);
+                uint32_t reps, uint32_t order_mask, qd_tuning *best, qd_tuning *all, uint32_t max_all,
+                uint32_t *n_all, void *stream);
 
 #ifdef __cplusplus
 }

@@ -57,6 +57,8 @@ def _load():
         lib.or_votes.argtypes = [P, I, P, I64, I64, P, I64, I64, P, P, P]
         lib.or_object_scores.argtypes = [P, I64, P, I64, P, P, I64, P]
         lib.or_score_rows.argtypes = [P, I64, I64, I, P]
+        lib.or_set_threads.argtypes = [I]
+        lib.or_max_threads.restype = I
         _lib = lib
     return _lib
 
@@ -198,6 +200,15 @@ def tree_knn(db, tree, q, k, use_and=False, score=None, use_pop=False):
                          _p(out.dist), _p(out.stats))
     assert rc == 0
     return out
+
+
+def set_threads(n):
+    """Threads the oracle's parallel loops use from now on (timing only)."""
+    _load().or_set_threads(int(n))
+
+
+def max_threads():
+    return _load().or_max_threads()
 
 
 def votes(nn_idx, obj_of, n_obj, qoff, threshold=10):

@@ -38,6 +38,7 @@
  *    the k-th key.  The bound uses the sum image (the product-image term is
  *    optional; the paper omits the product image for sparse QUICCI).
  */
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -595,3 +596,7 @@ void or_score_rows(double *scores, int64_t nqo, int64_t n_obj, int normalize, in
         }
     }
 }
+
+/* Threads of the parallel loops above (for timing the oracle on fewer cores). */
+void or_set_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
+int or_max_threads(void) { return omp_get_max_threads(); }

@@ -168,7 +168,7 @@ class _SearchParams(ctypes.Structure):
     _fields_ = [("order", ctypes.c_int), ("d_scores", ctypes.c_void_p), ("n_scored", ctypes.c_uint32),
                 ("waves_per_cu", ctypes.c_uint32), ("d_visited", ctypes.c_void_p), ("n_traced", ctypes.c_uint32),
                 ("round1_blocks", ctypes.c_uint32), ("round2_blocks", ctypes.c_uint32),
-                ("round_growth", ctypes.c_uint32)]
+                ("round_growth", ctypes.c_uint32), ("model", ctypes.c_void_p)]
 
 
 class Stats(ctypes.Structure):
@@ -232,6 +232,22 @@ class Tree:
         return dict(child=child, begin=begin, count=count, or_img=or_img, and_img=and_img, perm=perm)
 
 
+_sig("qd_tree_save", [_P, ctypes.c_char_p])
+_sig("qd_tree_load", [ctypes.c_char_p, _P, ctypes.POINTER(ctypes.c_void_p)])
+
+
+def tree_save(tree, path):
+    """Write the tree (rows in leaf order, permutation, structure) to a file."""
+    _check(_lib.qd_tree_save(tree.handle, os.fsencode(path)), "qd_tree_save")
+
+
+def tree_load(path):
+    """A tree read from a file written by tree_save, on the current device."""
+    h = ctypes.c_void_p()
+    _check(_lib.qd_tree_load(os.fsencode(path), _stream(), ctypes.byref(h)), "qd_tree_load")
+    return Tree(h.value)
+
+
 def tree_build(db, max_leaf=32, store_and_image=False, plain_bound=False):
     """plain_bound: the paper's image bound only (no popcount ranges)."""
     _desc(db, "db")
@@ -243,14 +259,18 @@ def tree_build(db, max_leaf=32, store_and_image=False, plain_bound=False):
 
 
 def knn_tree(tree, q, k, order=ORDER_BEST_FIRST, scores=None, query_stats=False, totals=False, waves_per_cu=0,
-             schedule=(0, 0, 0)):
+             schedule=(0, 0, 0), model=None, n_scored=0):
     """Exact k-NN through the tree.  Returns (idx, missed, extra, dist[, qstats][, totals]).
-    schedule: (round-1 blocks, round-2 blocks, growth) of the blocked order, 0 = default."""
+    schedule: (round-1 blocks, round-2 blocks, growth) of the blocked order, 0 = default.
+    model: a Model that orders the depth-first search (scoring nodes below n_scored,
+    0 = default) or picks where the blocked search starts."""
     _desc(q, "q")
     nq = q.shape[0]
     idx, missed, extra, dist = _results(nq, k, q.device)
     qs = torch.empty((nq, 4), dtype=torch.int32, device=q.device) if query_stats else None
-    prm = _SearchParams(order, None, 0, waves_per_cu, None, 0, *schedule)
+    prm = _SearchParams(order, None, n_scored, waves_per_cu, None, 0, *schedule)
+    if model is not None:
+        prm.model = model.handle.value
     if scores is not None:
         if not (scores.is_cuda and scores.dtype == torch.float32 and scores.dim() == 2 and scores.shape[0] == nq
                 and scores.is_contiguous()):
@@ -315,7 +335,7 @@ _sig("qd_retrieve_objects", [_P, _P, _U64, _P, _U32, _P, _U64, _P, _U32, _U32, _
 
 
 def retrieve_objects(qdesc, qoff, obj_of, n_obj, k, threshold=10, tree=None, db=None, order=ORDER_BEST_FIRST,
-                     return_nn=False):
+                     return_nn=False, schedule=(0, 0, 0)):
     """Vote histogram (nqo, n_obj), winner (nqo,), descriptors used (nqo,)[, neighbour rows].
 
     qoff: cuda int64 (nqo+1) CSR offsets into qdesc; obj_of: cuda int16 object id per database row."""
@@ -328,7 +348,7 @@ def retrieve_objects(qdesc, qoff, obj_of, n_obj, k, threshold=10, tree=None, db=
     winner = torch.empty(nqo, dtype=torch.int32, device=dev)
     used = torch.empty(nqo, dtype=torch.int32, device=dev)
     nn = torch.empty((qdesc.shape[0], k), dtype=torch.int32, device=dev) if return_nn else None
-    prm = _SearchParams(order, None, 0, 0, None, 0)
+    prm = _SearchParams(order, None, 0, 0, None, 0, *schedule)
     rc = _lib.qd_retrieve_objects(tree.handle if tree is not None else None, _ptr(db), 0 if db is None else db.shape[0],
                                   _ptr(obj_of), n_obj, _ptr(qdesc), qdesc.shape[0], _ptr(qoff), nqo, k, threshold,
                                   ctypes.byref(prm), _ptr(votes), _ptr(winner), _ptr(used), _ptr(nn), _stream())
@@ -539,19 +559,21 @@ def model_train(model, tree, q, k, n_traced, epochs, batch_queries, lr, batch_or
 # ---------------------------------------------------------------------------
 class _Tuning(ctypes.Structure):
     _fields_ = [("path", ctypes.c_int), ("order", ctypes.c_int), ("waves_per_cu", ctypes.c_uint32),
-                ("query_tile", ctypes.c_uint32), ("ms", ctypes.c_float)]
+                ("query_tile", ctypes.c_uint32), ("ms", ctypes.c_float), ("round1_blocks", ctypes.c_uint32),
+                ("round2_blocks", ctypes.c_uint32), ("round_growth", ctypes.c_uint32)]
 
     def as_dict(self):
         return {"path": "tree" if self.path else "sequential", "order": self.order,
-                "waves_per_cu": self.waves_per_cu, "query_tile": self.query_tile, "ms": self.ms}
+                "waves_per_cu": self.waves_per_cu, "query_tile": self.query_tile, "ms": self.ms,
+                "schedule": (self.round1_blocks, self.round2_blocks, self.round_growth)}
 
 
 _sig("qd_plan_create", [_P, _P, _U64, _P, _U32, _U64, _U32, _U32, _U32, ctypes.POINTER(_SearchParams), _U32,
                         ctypes.POINTER(ctypes.c_void_p)])
 _sig("qd_plan_run", [_P, _P, _U64, _P, _U32, _P, _P, _P, _P])
 _sig("qd_plan_free", [_P])
-_sig("qd_autotune", [_P, _P, _U64, _P, _U32, _U32, _U32, ctypes.POINTER(_Tuning), ctypes.POINTER(_Tuning), _U32,
-                     ctypes.POINTER(ctypes.c_uint32), _P])
+_sig("qd_autotune", [_P, _P, _U64, _P, _U32, _U32, _U32, _U32, ctypes.POINTER(_Tuning), ctypes.POINTER(_Tuning),
+                     _U32, ctypes.POINTER(ctypes.c_uint32), _P])
 
 
 class Plan:
@@ -559,11 +581,11 @@ class Plan:
     recorded in a hipGraph and replayed per run."""
 
     def __init__(self, obj_of, n_obj, max_qdesc, max_qobj, k, threshold=10, tree=None, db=None,
-                 order=ORDER_BEST_FIRST, waves_per_cu=0, query_tile=0):
+                 order=ORDER_BEST_FIRST, waves_per_cu=0, query_tile=0, schedule=(0, 0, 0)):
         if tree is None:
             _desc(db, "db")
         self._keep = (tree, db, obj_of)  # the plan points into these
-        prm = _SearchParams(order, None, 0, waves_per_cu, None, 0)
+        prm = _SearchParams(order, None, 0, waves_per_cu, None, 0, *schedule)
         h = ctypes.c_void_p()
         _check(_lib.qd_plan_create(tree.handle if tree is not None else None, _ptr(db),
                                    0 if db is None else db.shape[0], _ptr(obj_of), n_obj, max_qdesc, max_qobj, k,
@@ -594,13 +616,15 @@ class Plan:
             pass
 
 
-def autotune(q, k, tree=None, db=None, reps=3, with_all=True):
-    """(best configuration, all candidates) for a k-NN batch; see qd_autotune."""
+def autotune(q, k, tree=None, db=None, reps=3, with_all=True, orders=None):
+    """(best configuration, all candidates) for a k-NN batch; see qd_autotune.
+    orders: the tree frontier orders to time (None = all)."""
     _desc(q, "q")
     best = _Tuning()
-    all_ = (_Tuning * 16)()
+    all_ = (_Tuning * 32)()
     n_all = ctypes.c_uint32()
+    mask = 0 if orders is None else sum(1 << o for o in orders)
     _check(_lib.qd_autotune(tree.handle if tree is not None else None, _ptr(db), 0 if db is None else db.shape[0],
-                            _ptr(q), q.shape[0], k, reps, ctypes.byref(best), all_ if with_all else None, 16,
+                            _ptr(q), q.shape[0], k, reps, mask, ctypes.byref(best), all_ if with_all else None, 32,
                             ctypes.byref(n_all), _stream()), "qd_autotune")
     return best.as_dict(), [all_[i].as_dict() for i in range(n_all.value)]

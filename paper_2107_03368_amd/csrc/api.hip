@@ -11,6 +11,9 @@
 namespace qd {
 
 static thread_local char g_err[512] = "";
+static thread_local const volatile int *g_abort = nullptr;
+
+bool abort_requested() { return g_abort && *g_abort != 0; }
 
 int fail(int code, const char *fmt, ...) {
     va_list ap;
@@ -139,4 +142,9 @@ extern "C" int qd_profile_read(const char *kernel, double *total_ms, uint64_t *l
 
 extern "C" const char *qd_last_error(void) { return qd::g_err; }
 
-extern "C" int qd_version(void) { return 100; }
+extern "C" int qd_set_abort_flag(const volatile int *flag) {
+    qd::g_abort = flag;
+    return QD_OK;
+}
+
+extern "C" int qd_version(void) { return 200; }

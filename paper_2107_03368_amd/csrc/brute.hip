@@ -276,10 +276,9 @@ int popcount_rows_launch(const uint64_t *d_db, uint64_t n, uint16_t *d_pop, hipS
     return QD_OK;
 }
 
-// Batches of at least this many queries over at least kMfmaMinRows rows use
-// the matrix-core path (the overlap counts are then a dense contraction).
-constexpr uint32_t kMfmaMinQueries = 512;
-constexpr uint64_t kMfmaMinRows = 1u << 16;
+// Batches of at least kMfmaMinQueries queries over at least kMfmaMinRows
+// rows use the matrix-core path (the overlap counts are then a dense
+// contraction).
 
 int knn_bruteforce_impl(const uint64_t *d_db, uint64_t n, const uint64_t *d_q, uint32_t nq, uint32_t k,
                         uint32_t *d_idx, int32_t *d_missed, int32_t *d_extra, float *d_dist, void *stream,

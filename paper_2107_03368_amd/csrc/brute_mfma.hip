@@ -19,6 +19,7 @@
 #include "mfma_tile.h"
 #include "qd_device.h"
 #include "qd_internal.h"
+#include "qd_launch.h"
 
 namespace qd {
 
@@ -33,7 +34,6 @@ constexpr int kBlock = 256;
 constexpr int MQ = mt::MA;        // queries per block
 constexpr int MR = mt::MB;        // rows per block
 constexpr uint32_t kCap = 8192;   // candidate slots per query
-thread_local int g_sample_depth = 0;  // > 0 inside the search of a threshold sample
 
 // Tiles of 256 queries x 256 rows in a persistent grid of G workgroups.
 // When the query tiles and G split evenly over the 8 XCDs, the workgroups of
@@ -52,8 +52,13 @@ __global__ __launch_bounds__(mt::kThreads) void scan_mfma_kernel(const uint4 *__
                                                                  const uint16_t *__restrict__ qpop,
                                                                  const u64 *__restrict__ thr, uint32_t n_qtiles,
                                                                  uint32_t *__restrict__ tctr,
-                                                                 uint32_t *__restrict__ cnt, u64 *__restrict__ cand) {
+                                                                 uint32_t *__restrict__ cnt, u64 *__restrict__ cand,
+                                                                 const uint32_t *__restrict__ nq_dev) {
     __shared__ mt::Smem sm;
+    if (nq_dev) {  // the batch's size on the device (captured graphs): fewer query tiles
+        nq = min(nq, *nq_dev);
+        n_qtiles = (nq + MQ - 1) / MQ;
+    }
     // Per tile row (queries 0..255, then rows): |q| or |t|, and for queries the
     // candidate bound and the least overlap that can reach it (the row half of
     // these two is written but not read, so every thread stores alike).  Two
@@ -229,9 +234,11 @@ __global__ __launch_bounds__(kBlock) void select_emit_kernel(const uint32_t *__r
                                                              const uint64_t *__restrict__ q,
                                                              const uint64_t *__restrict__ db, uint32_t *idx,
                                                              int32_t *missed, int32_t *extra, float *dist,
-                                                             uint32_t *redo, uint32_t *n_redo) {
+                                                             uint32_t *redo, uint32_t *n_redo,
+                                                             const uint32_t *__restrict__ nq_dev) {
     __shared__ u64 keys[kCap];
     const uint32_t qi = blockIdx.x;
+    if (nq_dev && qi >= *nq_dev) return;  // whole block
     const uint32_t m = cnt[qi];
     if (m > kCap) {
         if (threadIdx.x == 0) redo[atomicAdd(n_redo, 1u)] = qi;
@@ -284,114 +291,169 @@ __global__ void sample_threshold_kernel(const uint32_t *__restrict__ idx, const 
                                    : ((u64)((uint32_t)missed[o] * wb + (uint32_t)extra[o] * wa) << 32) | idx[o];
 }
 
-__global__ void gather_queries_kernel(const uint4 *__restrict__ q, const uint32_t *__restrict__ list, uint32_t m,
-                                      uint4 *__restrict__ out) {
+// The overflowed queries (list[0 .. *m)) gathered into consecutive rows.
+__global__ void gather_queries_kernel(const uint4 *__restrict__ q, const uint32_t *__restrict__ list,
+                                      const uint32_t *__restrict__ m, uint4 *__restrict__ out) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < m * 32) out[i] = q[(uint64_t)list[i >> 5] * 32 + (i & 31)];
+    if (i < *m * 32) out[i] = q[(uint64_t)list[i >> 5] * 32 + (i & 31)];
 }
 
+// Their results back to their queries' rows.
 template <class T>
-__global__ void scatter_rows_kernel(const T *__restrict__ src, const uint32_t *__restrict__ list, uint32_t m,
-                                    uint32_t k, T *__restrict__ dst) {
+__global__ void scatter_rows_kernel(const T *__restrict__ src, const uint32_t *__restrict__ list,
+                                    const uint32_t *__restrict__ m, uint32_t k, T *__restrict__ dst) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < m * k) dst[(uint64_t)list[i / k] * k + (i % k)] = src[i];
+    if (i < *m * k) dst[(uint64_t)list[i / k] * k + (i % k)] = src[i];
 }
+
+// Clears n words (a kernel, not a memset node, so a captured graph replays it reliably).
+__global__ void zero_words_kernel(uint32_t *__restrict__ p, uint64_t n) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = 0;
+}
+
+
+// Rows of the threshold sample of a matrix-core pass over n rows: about
+// k*n/1024, so about 1,024 candidates per query are expected.
+inline uint64_t sample_rows(uint64_t n, uint32_t k) { return std::max<uint64_t>((uint64_t)k * 64, (n * k + 1023) / 1024); }
+inline size_t al256(size_t b) { return (b + 255) / 256 * 256; }
 
 }  // namespace
+
+// Level l searches rows [0, rows[l]) for the batch; every level but the last
+// is a matrix-core pass whose thresholds come from level l + 1 over its
+// sample (a prefix of the rows); the last level is the register-tiled scan.
+MfmaLayout mfma_layout(uint64_t n, uint32_t nq, uint32_t k) {
+    MfmaLayout L;
+    uint64_t rows = n;
+    // level 0 is a matrix-core pass (the caller checked); deeper ones when big enough
+    for (;;) {
+        L.rows.push_back(rows);
+        const uint64_t smp = sample_rows(rows, k);
+        const bool mfma = L.rows.size() == 1 ? smp * 4 <= rows
+                                             : nq >= kMfmaMinQueries && rows >= kMfmaMinRows && smp * 4 <= rows;
+        if (!mfma || L.rows.size() == kMaxLevels) break;
+        rows = smp;
+    }
+    const size_t levels = L.rows.size();
+    L.base = brute_launch_shape(L.rows.back(), nq, k, 0, 0);
+    size_t fb_part = 0;
+    for (size_t l = 0; l + 1 < levels; l++) {
+        L.fb[l] = brute_launch_shape(L.rows[l], nq, k, 16, 0);
+        fb_part = std::max(fb_part, L.fb[l].part_bytes);
+    }
+    size_t o = 0;
+    auto take = [&](size_t b) {
+        const size_t at = o;
+        o += al256(b);
+        return at;
+    };
+    L.tpop = take(n * 2);
+    L.qpop = take((size_t)nq * 2);
+    L.cnt = take((size_t)nq * 4);
+    L.cand = take((size_t)nq * kCap * 8);
+    L.redo = take((size_t)nq * 4);
+    L.ctr = take(4 * (1 + mt::kXcds));
+    for (size_t l = 0; l + 1 < levels; l++) {
+        L.thr[l] = take((size_t)nq * 8);
+        L.smp[l] = take((size_t)nq * k * 16);  // the sample's results: level l + 1's outputs
+    }
+    L.base_part = take(L.base.part_bytes);
+    L.gq = take((size_t)nq * 512);
+    L.fbr = take((size_t)nq * k * 16);
+    L.fb_part = take(fb_part);
+    L.bytes = o;
+    return L;
+}
+
+// Level l of the search of nq queries (nq_dev: their count on the device,
+// nullable) into the four result arrays; nothing waits for the host.
+static int mfma_level(const MfmaLayout &L, size_t l, char *ws, const uint64_t *d_db, const uint64_t *d_q, uint32_t nq,
+                      const uint32_t *nq_dev, uint32_t k, uint32_t *idx, int32_t *mis, int32_t *ext, float *dist,
+                      hipStream_t s) {
+    const uint64_t n = L.rows[l];
+    const bool top = l == 0;
+    if (l + 1 == L.rows.size())  // the register-tiled scan
+        return brute_launch(L.base, reinterpret_cast<u64 *>(ws + L.base_part), d_db, n, d_q, nq, nq_dev, k, idx, mis,
+                            ext, dist, s);
+    // thresholds from the sample: level l + 1 over the first rows
+    uint32_t *sidx = (uint32_t *)(ws + L.smp[l]);
+    int32_t *smis = (int32_t *)(sidx + (size_t)nq * k), *sext = smis + (size_t)nq * k;
+    float *sdist = (float *)(sext + (size_t)nq * k);
+    int rc = mfma_level(L, l + 1, ws, d_db, d_q, nq, nq_dev, k, sidx, smis, sext, sdist, s);
+    if (rc != QD_OK) return rc;
+    const uint16_t *tpop = (const uint16_t *)(ws + L.tpop), *qpop = (const uint16_t *)(ws + L.qpop);
+    u64 *thr = (u64 *)(ws + L.thr[l]);
+    uint32_t *cnt = (uint32_t *)(ws + L.cnt), *redo = (uint32_t *)(ws + L.redo), *ctr = (uint32_t *)(ws + L.ctr);
+    uint32_t *n_redo = ctr, *tctr = ctr + 1;  // overflow count, one tile counter per XCD
+    u64 *cand = (u64 *)(ws + L.cand);
+    hipLaunchKernelGGL(sample_threshold_kernel, dim3((nq + 255) / 256), dim3(256), 0, s, sidx, smis, sext, qpop, nq, k,
+                       thr);
+    hipLaunchKernelGGL(zero_words_kernel, dim3((uint32_t)std::min<uint64_t>((nq + 255) / 256, 1024)), dim3(256), 0, s,
+                       cnt, (uint64_t)nq);
+    hipLaunchKernelGGL(zero_words_kernel, dim3(1), dim3(64), 0, s, ctr, (uint64_t)(1 + mt::kXcds));
+    const uint32_t n_qtiles = (nq + MQ - 1) / MQ;
+    const uint64_t n_rtiles = (n + MR - 1) / MR;
+    {
+        KernelTimer timer(top ? "wh_scan_mfma" : "wh_scan_mfma_sample", s);
+        // persistent: one workgroup per CU (the tile's LDS and registers leave room for one)
+        const uint64_t grid = std::min<uint64_t>(n_qtiles * n_rtiles, (uint64_t)device_cus());
+        hipLaunchKernelGGL(scan_mfma_kernel, dim3((uint32_t)grid), dim3(mt::kThreads), 0, s,
+                           reinterpret_cast<const uint4 *>(d_db), n, reinterpret_cast<const uint4 *>(d_q), nq, tpop,
+                           qpop, thr, n_qtiles, tctr, cnt, cand, nq_dev);
+    }
+    {
+        KernelTimer timer(top ? "topk_select" : "topk_select_sample", s);
+        hipLaunchKernelGGL(select_emit_kernel, dim3(nq), dim3(kBlock), 0, s, cnt, cand, k, d_q, d_db, idx, mis, ext,
+                           dist, redo, n_redo, nq_dev);
+    }
+    // queries whose candidate buffer overflowed: searched again by the
+    // register-tiled scan over this level's rows; their count stays on the
+    // device, so an empty fallback only costs launches that find no work
+    uint4 *gq = (uint4 *)(ws + L.gq);
+    uint32_t *ri = (uint32_t *)(ws + L.fbr);
+    int32_t *rm = (int32_t *)(ri + (size_t)nq * k), *rx = rm + (size_t)nq * k;
+    float *rd = (float *)(rx + (size_t)nq * k);
+    hipLaunchKernelGGL(gather_queries_kernel, dim3((nq * 32 + 255) / 256), dim3(256), 0, s,
+                       reinterpret_cast<const uint4 *>(d_q), redo, n_redo, gq);
+    rc = brute_launch(L.fb[l], reinterpret_cast<u64 *>(ws + L.fb_part), d_db, n, reinterpret_cast<const uint64_t *>(gq),
+                      nq, n_redo, k, ri, rm, rx, rd, s, /*timed=*/false);
+    if (rc != QD_OK) return rc;
+    const dim3 g((nq * k + 255) / 256);
+    hipLaunchKernelGGL(scatter_rows_kernel<uint32_t>, g, dim3(256), 0, s, ri, redo, n_redo, k, idx);
+    hipLaunchKernelGGL(scatter_rows_kernel<int32_t>, g, dim3(256), 0, s, rm, redo, n_redo, k, mis);
+    hipLaunchKernelGGL(scatter_rows_kernel<int32_t>, g, dim3(256), 0, s, rx, redo, n_redo, k, ext);
+    hipLaunchKernelGGL(scatter_rows_kernel<float>, g, dim3(256), 0, s, rd, redo, n_redo, k, dist);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(QD_ERR_DEVICE, "matrix-core scan: %s", hipGetErrorString(e));
+    return QD_OK;
+}
+
+int mfma_run(const MfmaLayout &L, char *ws, const uint64_t *d_db, const uint64_t *d_q, uint32_t nq,
+             const uint32_t *nq_dev, uint32_t k, uint32_t *d_idx, int32_t *d_missed, int32_t *d_extra, float *d_dist,
+             hipStream_t s) {
+    int rc = popcount_rows_launch(d_db, L.rows[0], (uint16_t *)(ws + L.tpop), s);
+    if (rc == QD_OK) rc = popcount_rows_launch(d_q, nq, (uint16_t *)(ws + L.qpop), s);
+    if (rc != QD_OK) return rc;
+    return mfma_level(L, 0, ws, d_db, d_q, nq, nq_dev, k, d_idx, d_missed, d_extra, d_dist, s);
+}
+
+bool mfma_eligible(uint64_t n, uint32_t nq, uint32_t k) {
+    return nq >= kMfmaMinQueries && n >= kMfmaMinRows && sample_rows(n, k) * 4 <= n;
+}
 
 // Matrix-core path for large batches; returns QD_ERR_UNSUPPORTED when the
 // shape is not worth it (the caller then uses the register-tiled scan).
 int knn_bruteforce_mfma(const uint64_t *d_db, uint64_t n, const uint64_t *d_q, uint32_t nq, uint32_t k,
                         uint32_t *d_idx, int32_t *d_missed, int32_t *d_extra, float *d_dist, void *stream) {
     hipStream_t s = (hipStream_t)stream;
-    // sample: about k*n/1024 rows, so about 1,024 candidates per query are expected
-    uint64_t sample = std::max<uint64_t>((uint64_t)k * 64, (n * k + 1023) / 1024);
-    if (sample * 4 > n) return QD_ERR_UNSUPPORTED;
-    const uint32_t n_qtiles = (nq + MQ - 1) / MQ;
-    const uint64_t n_rtiles = (n + MR - 1) / MR;
-    // scratch: tpop n*2 | qpop nq*2 | thr nq*8 | cnt nq*4 | cand nq*cap*8 | sample outputs nq*k*16 | redo nq*4+4
-    const size_t a_tpop = 0, a_qpop = a_tpop + (n * 2 + 255) / 256 * 256;
-    const size_t a_thr = a_qpop + ((size_t)nq * 2 + 255) / 256 * 256;
-    const size_t a_cnt = a_thr + (size_t)nq * 8;
-    const size_t a_cand = a_cnt + ((size_t)nq * 4 + 255) / 256 * 256;
-    const size_t a_smp = a_cand + (size_t)nq * kCap * 8;
-    const size_t a_redo = a_smp + (size_t)nq * k * 16;
-    const size_t bytes = a_redo + (size_t)nq * 4 + 256;
+    if (sample_rows(n, k) * 4 > n) return QD_ERR_UNSUPPORTED;
+    const MfmaLayout L = mfma_layout(n, nq, k);
     char *ws = nullptr;
-    QD_HIP_CHECK(hipMallocAsync((void **)&ws, bytes, s));
-    uint16_t *tpop = (uint16_t *)(ws + a_tpop), *qpop = (uint16_t *)(ws + a_qpop);
-    u64 *thr = (u64 *)(ws + a_thr);
-    uint32_t *cnt = (uint32_t *)(ws + a_cnt);
-    u64 *cand = (u64 *)(ws + a_cand);
-    uint32_t *sidx = (uint32_t *)(ws + a_smp);
-    int32_t *smis = (int32_t *)(sidx + (size_t)nq * k), *sext = smis + (size_t)nq * k;
-    float *sdist = (float *)(sext + (size_t)nq * k);
-    uint32_t *redo = (uint32_t *)(ws + a_redo);
-    uint32_t *n_redo = redo + nq;
-    auto done = [&](int rc) {
-        (void)hipFreeAsync(ws, s);
-        return rc;
-    };
-    int rc = popcount_rows_launch(d_db, n, tpop, s);
-    if (rc == QD_OK) rc = popcount_rows_launch(d_q, nq, qpop, s);
-    if (rc != QD_OK) return done(rc);
-    // thresholds from the first `sample` rows (large samples take this same
-    // path, with a sample of their own; its launches are timed apart)
-    ++g_sample_depth;
-    rc = knn_bruteforce_impl(d_db, sample, d_q, nq, k, sidx, smis, sext, sdist, stream, 0, 0);
-    --g_sample_depth;
-    if (rc != QD_OK) return done(rc);
-    hipLaunchKernelGGL(sample_threshold_kernel, dim3((nq + 255) / 256), dim3(256), 0, s, sidx, smis, sext, qpop, nq, k,
-                       thr);
-    uint32_t *tctr = n_redo + 1;  // one tile counter per XCD (in the last 256 bytes)
-    if (hipMemsetAsync(cnt, 0, (size_t)nq * 4, s) != hipSuccess ||
-        hipMemsetAsync(n_redo, 0, 4 * (1 + mt::kXcds), s) != hipSuccess)
-        return done(fail(QD_ERR_DEVICE, "memset"));
-    {
-        KernelTimer timer(g_sample_depth ? "wh_scan_mfma_sample" : "wh_scan_mfma", s);
-        // persistent: one workgroup per CU (the tile's LDS and registers leave room for one)
-        const uint64_t grid = std::min<uint64_t>(n_qtiles * n_rtiles, (uint64_t)device_cus());
-        hipLaunchKernelGGL(scan_mfma_kernel, dim3((uint32_t)grid), dim3(mt::kThreads), 0, s,
-                           reinterpret_cast<const uint4 *>(d_db), n, reinterpret_cast<const uint4 *>(d_q), nq, tpop,
-                           qpop, thr, n_qtiles, tctr, cnt, cand);
-    }
-    {
-        KernelTimer timer(g_sample_depth ? "topk_select_sample" : "topk_select", s);
-        hipLaunchKernelGGL(select_emit_kernel, dim3(nq), dim3(kBlock), 0, s, cnt, cand, k, d_q, d_db, d_idx, d_missed,
-                           d_extra, d_dist, redo, n_redo);
-    }
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return done(fail(QD_ERR_DEVICE, "matrix-core scan: %s", hipGetErrorString(e)));
-    // queries whose candidate buffer overflowed: search them again with the scan
-    uint32_t h_redo = 0;
-    e = hipMemcpyAsync(&h_redo, n_redo, 4, hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    if (e != hipSuccess) return done(fail(QD_ERR_DEVICE, "overflow check: %s", hipGetErrorString(e)));
-    if (h_redo > 0) {
-        uint4 *gq = nullptr;
-        char *ro = nullptr;
-        if (hipMallocAsync((void **)&gq, (size_t)h_redo * 512, s) != hipSuccess ||
-            hipMallocAsync((void **)&ro, (size_t)h_redo * k * 16, s) != hipSuccess)
-            return done(fail(QD_ERR_OOM, "fallback scratch"));
-        hipLaunchKernelGGL(gather_queries_kernel, dim3((h_redo * 32 + 255) / 256), dim3(256), 0, s,
-                           reinterpret_cast<const uint4 *>(d_q), redo, h_redo, gq);
-        uint32_t *ri = (uint32_t *)ro;
-        int32_t *rm = (int32_t *)(ri + (size_t)h_redo * k), *rx = rm + (size_t)h_redo * k;
-        float *rd = (float *)(rx + (size_t)h_redo * k);
-        rc = knn_bruteforce_impl(d_db, n, reinterpret_cast<const uint64_t *>(gq), h_redo, k, ri, rm, rx, rd, stream, 16,
-                                 0);
-        if (rc == QD_OK) {
-            const dim3 g((h_redo * k + 255) / 256);
-            hipLaunchKernelGGL(scatter_rows_kernel<uint32_t>, g, dim3(256), 0, s, ri, redo, h_redo, k, d_idx);
-            hipLaunchKernelGGL(scatter_rows_kernel<int32_t>, g, dim3(256), 0, s, rm, redo, h_redo, k, d_missed);
-            hipLaunchKernelGGL(scatter_rows_kernel<int32_t>, g, dim3(256), 0, s, rx, redo, h_redo, k, d_extra);
-            hipLaunchKernelGGL(scatter_rows_kernel<float>, g, dim3(256), 0, s, rd, redo, h_redo, k, d_dist);
-            if (hipGetLastError() != hipSuccess) rc = fail(QD_ERR_DEVICE, "fallback scatter");
-        }
-        (void)hipFreeAsync(gq, s);
-        (void)hipFreeAsync(ro, s);
-    }
-    return done(rc);
+    QD_HIP_CHECK(hipMallocAsync((void **)&ws, L.bytes, s));
+    const int rc = mfma_run(L, ws, d_db, d_q, nq, nullptr, k, d_idx, d_missed, d_extra, d_dist, s);
+    (void)hipFreeAsync(ws, s);
+    return rc;
 }
 
 }  // namespace qd

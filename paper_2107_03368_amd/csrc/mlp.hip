@@ -573,13 +573,14 @@ extern "C" int qd_model_features(qd_tree_t t, const uint64_t *d_q, const uint32_
 // q0 .. q0+nq-1 of d_q, pair p belongs to query P.q(p).  With labels y the
 // full gradient goes to d_grads (QD_MLP_NPARAMS) and the mean loss to d_loss;
 // this path needs the pairs as explicit arrays grouped by query (d_qoff).
+// u_pre (nullable): the per-query layer-1 sums u (nq x H), already formed.
 static int mlp_run(qd_model_t m, const uint64_t *d_q, uint32_t q0, uint32_t nq, qd::PairIdx P,
                    const uint64_t *d_qoff, uint64_t qoff_base, const float *d_feat, uint64_t n_pairs, const float *y,
-                   float *d_scores, float *d_grads, float *d_loss, hipStream_t s) {
+                   float *d_scores, float *d_grads, float *d_loss, hipStream_t s, float *u_pre = nullptr) {
     using namespace qd;
     const uint64_t np = pad64(n_pairs ? n_pairs : 1);
     const bool train = y != nullptr;
-    size_t bytes = (size_t)nq * H * 4 + np * H * 4 + np * H * 4 + np * 4;
+    size_t bytes = (u_pre ? 0 : (size_t)nq * H * 4) + np * H * 4 + np * H * 4 + np * 4;
     if (train)
         bytes += np * H * 4 + np * 4 + np * 4 + np * H * 2 + (size_t)H * H * 4 + (size_t)nq * H * 4 +
                  (size_t)kHeadParts * kHeadPartLen * 4 + (size_t)nq * kL1Chunks * kL1PartLen * 4;
@@ -592,7 +593,7 @@ static int mlp_run(qd_model_t m, const uint64_t *d_q, uint32_t q0, uint32_t nq, 
         return r;
     };
     Scratch S;
-    S.u = (float *)take((size_t)nq * H * 4);
+    S.u = u_pre ? u_pre : (float *)take((size_t)nq * H * 4);
     S.h1 = (uint16_t *)take(np * H * 4);
     S.z2 = (float *)take(np * H * 4);
     S.s = (float *)take(np * 4);
@@ -608,7 +609,7 @@ static int mlp_run(qd_model_t m, const uint64_t *d_q, uint32_t q0, uint32_t nq, 
     }
     {
         KernelTimer timer("mlp_forward", s);
-        hipLaunchKernelGGL(uq_kernel, dim3(nq), dim3(kBlock), 0, s, d_q, q0, m->w, S.u);
+        if (!u_pre) hipLaunchKernelGGL(uq_kernel, dim3(nq), dim3(kBlock), 0, s, d_q, q0, m->w, S.u);
         hipLaunchKernelGGL(layer1_kernel, dim3((uint32_t)np), dim3(kBlock), 0, s, S.u, P, q0, d_feat, n_pairs, m->w,
                            S.h1);
         gemm(s, false, false, S.h1, m->w2x2, S.z2, (int)np, H, 2 * H, 2 * H, H, H);
@@ -702,6 +703,89 @@ extern "C" int qd_model_score_tree(qd_model_t m, qd_tree_t t, const uint64_t *d_
     (void)hipFreeAsync(feat, s);
     return rc;
 }
+
+// ---- learned start of the blocked search --------------------------------
+
+namespace qd {
+namespace {
+
+// The pair of children of every query's current node: pairs 2i and 2i + 1
+// score the similar and the dissimilar child of cur[i] when that node is an
+// inner node above max_rows rows; otherwise both name cur[i] (scored, unused).
+__global__ void descend_pairs_kernel(const uint32_t *__restrict__ cur, uint32_t nq, const int32_t *__restrict__ child,
+                                     const uint32_t *__restrict__ count, uint32_t max_rows,
+                                     uint32_t *__restrict__ pq, uint32_t *__restrict__ pn) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nq) return;
+    const uint32_t node = cur[i];
+    const int32_t a = child[2 * node];
+    const bool go = a >= 0 && count[node] > max_rows;
+    pq[2 * i] = pq[2 * i + 1] = i;
+    pn[2 * i] = go ? (uint32_t)a : node;
+    pn[2 * i + 1] = go ? (uint32_t)child[2 * node + 1] : node;
+}
+
+// Enter the higher-scoring child (ties: the similar child).
+__global__ void descend_pick_kernel(uint32_t *__restrict__ cur, uint32_t nq, const int32_t *__restrict__ child,
+                                    const uint32_t *__restrict__ count, uint32_t max_rows,
+                                    const float *__restrict__ sc) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nq) return;
+    const uint32_t node = cur[i];
+    const int32_t a = child[2 * node];
+    if (a < 0 || count[node] <= max_rows) return;
+    cur[i] = sc[2 * i + 1] > sc[2 * i] ? (uint32_t)child[2 * node + 1] : (uint32_t)a;
+}
+
+__global__ void fill_u32_kernel(uint32_t *__restrict__ p, uint32_t n, uint32_t v) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+}  // namespace
+
+int model_descend(qd_model_t m, qd_tree_t t, const uint64_t *d_q, uint32_t nq, uint32_t max_rows, uint32_t *d_node,
+                  hipStream_t s) {
+    if (check_model(m) != QD_OK || !t) return fail(QD_ERR_INVALID, "null model or tree");
+    if (nq == 0) return QD_OK;
+    const uint64_t np = 2ull * nq;
+    char *ws = nullptr;
+    const size_t bytes = (size_t)nq * H * 4 + np * 8 + np * NF * 4 + np * 4 + 4 * 256;
+    QD_HIP_CHECK(hipMallocAsync((void **)&ws, bytes, s));
+    char *c = ws;
+    auto take = [&](size_t b) {
+        char *r = c;
+        c += (b + 255) / 256 * 256;
+        return r;
+    };
+    float *u = (float *)take((size_t)nq * H * 4);
+    uint32_t *pq = (uint32_t *)take(np * 4), *pn = (uint32_t *)take(np * 4);
+    float *feat = (float *)take(np * NF * 4), *sc = (float *)take(np * 4);
+    const dim3 g((nq + 255) / 256);
+    int rc = QD_OK;
+    {
+        KernelTimer timer("mlp_forward", s);
+        hipLaunchKernelGGL(fill_u32_kernel, g, dim3(256), 0, s, d_node, nq, 0u);  // every query starts at the root
+        hipLaunchKernelGGL(uq_kernel, dim3(nq), dim3(kBlock), 0, s, d_q, 0u, m->w, u);  // shared by every level
+    }
+    for (size_t L = 0; L < t->level_max.size() && t->level_max[L] > max_rows && rc == QD_OK; L++) {
+        hipLaunchKernelGGL(descend_pairs_kernel, g, dim3(256), 0, s, d_node, nq, t->d_child, t->d_count, max_rows, pq,
+                           pn);
+        {
+            KernelTimer timer("mlp_features", s);
+            rc = features_launch(t, d_q, PairIdx{pq, pn, 0, 1}, np, feat, s);
+        }
+        if (rc == QD_OK)
+            rc = mlp_run(m, d_q, 0, nq, PairIdx{pq, pn, 0, 1}, nullptr, 0, feat, np, nullptr, sc, nullptr, nullptr, s,
+                         u);
+        hipLaunchKernelGGL(descend_pick_kernel, g, dim3(256), 0, s, d_node, nq, t->d_child, t->d_count, max_rows, sc);
+    }
+    if (rc == QD_OK && hipGetLastError() != hipSuccess) rc = fail(QD_ERR_DEVICE, "model descent: launch failed");
+    (void)hipFreeAsync(ws, s);
+    return rc;
+}
+
+}  // namespace qd
 
 // ---- training pairs from traversal traces ------------------------------
 
@@ -891,6 +975,10 @@ extern "C" int qd_model_train(qd_model_t m, qd_tree_t t, const uint64_t *d_q, ui
     uint64_t step = 0;
     for (uint32_t e = 0; e < epochs; e++)
         for (uint32_t bi = 0; bi < nb; bi++) {
+            if (abort_requested()) {  // between steps: the queued ones finish first
+                (void)hipStreamSynchronize(s);
+                return fail(QD_ERR_ABORTED, "training aborted after %llu steps", (unsigned long long)step);
+            }
             const uint32_t b = h_batch_order ? h_batch_order[bi] % nb : bi;
             const uint32_t qa = b * batch_queries, qb = std::min(nq, qa + batch_queries);
             const uint64_t p0 = hoff[qa], p1 = hoff[qb];

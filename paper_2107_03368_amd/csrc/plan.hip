@@ -56,6 +56,14 @@ __global__ void set_sizes_kernel(uint32_t *sizes, uint32_t n_qdesc, uint32_t nqo
     sizes[1] = nqo;
 }
 
+// Blocked order: the descriptors of batch i of qb each, sizes[2 + i].
+__global__ void batch_sizes_kernel(uint32_t *sizes, uint32_t n_batches, uint32_t qb) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_batches) return;
+    const uint64_t b0 = (uint64_t)i * qb, nd = sizes[0];
+    sizes[2 + i] = nd > b0 ? (uint32_t)(nd - b0 < qb ? nd - b0 : qb) : 0u;
+}
+
 void plan_release(qd_plan_s *p) {
     if (!p) return;
     if (p->exec) (void)hipGraphExecDestroy(p->exec);
@@ -83,8 +91,15 @@ extern "C" int qd_plan_create(qd_tree_t t, const uint64_t *d_db, uint64_t n, con
     if (params && (params->d_scores || params->d_visited))
         return fail(QD_ERR_INVALID, "scores and traces are per call of qd_knn_tree only");
     const int order = params ? (int)params->order : QD_ORDER_BEST_FIRST;
-    if (t && order != QD_ORDER_BEST_FIRST && order != QD_ORDER_DEPTH_FIRST)
+    if (t && order != QD_ORDER_BEST_FIRST && order != QD_ORDER_DEPTH_FIRST && order != QD_ORDER_BLOCKED)
         return fail(QD_ERR_INVALID, "unknown frontier order");
+    if (params && params->model)
+        return fail(QD_ERR_UNSUPPORTED, "a plan takes no model (scoring allocates per call)");
+    const bool blocked = t && order == QD_ORDER_BLOCKED;
+    if (blocked) {
+        const int rc = blocked_check(t, params);
+        if (rc != QD_OK) return rc;
+    }
     qd_plan_s *p = new qd_plan_s();
     p->tree = t;
     p->db = d_db;
@@ -99,8 +114,21 @@ extern "C" int qd_plan_create(qd_tree_t t, const uint64_t *d_db, uint64_t n, con
     const uint32_t nqmax = (uint32_t)max_qdesc;
     TreeLaunch TL;
     BruteLaunch BL;
+    BlockedLayout KL;
+    MfmaLayout ML;
+    uint32_t n_batches = 1;
     size_t ws_bytes;
-    if (t) {
+    // sequential search: the matrix cores when the largest batch is big enough
+    // (query_tile 0), else the register-tiled scan
+    const bool mfma = !t && query_tile == 0 && mfma_eligible(n, nqmax, k);
+    if (blocked) {
+        KL = blocked_layout(t, nqmax, k);
+        n_batches = (uint32_t)((nqmax + KL.qb - 1) / KL.qb);
+        ws_bytes = KL.bytes;
+    } else if (mfma) {
+        ML = mfma_layout(n, nqmax, k);
+        ws_bytes = ML.bytes;
+    } else if (t) {
         TL = tree_launch_shape(t, nqmax, order, params ? params->waves_per_cu : 0);
         ws_bytes = TL.total();
     } else {
@@ -110,7 +138,7 @@ extern "C" int qd_plan_create(qd_tree_t t, const uint64_t *d_db, uint64_t n, con
     // one allocation: q | qoff | sizes | nn mi ex di | votes winner used | ws
     auto al = [](size_t b) { return (b + 255) / 256 * 256; };
     const size_t o_q = 0, o_off = o_q + al(max_qdesc * 512), o_sz = o_off + al(((size_t)max_qobj + 1) * 8);
-    const size_t o_nn = o_sz + 256, m = (size_t)max_qdesc * k;
+    const size_t o_nn = o_sz + al(((size_t)n_batches + 2) * 4), m = (size_t)max_qdesc * k;
     const size_t o_mi = o_nn + al(m * 4), o_ex = o_mi + al(m * 4), o_di = o_ex + al(m * 4);
     const size_t o_vo = o_di + al(m * 4), o_wi = o_vo + al((size_t)max_qobj * n_obj * 4);
     const size_t o_us = o_wi + al((size_t)max_qobj * 4), o_ws = o_us + al((size_t)max_qobj * 4);
@@ -139,7 +167,20 @@ extern "C" int qd_plan_create(qd_tree_t t, const uint64_t *d_db, uint64_t n, con
     int rc = QD_OK;
     hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-        if (t)
+        if (blocked) {
+            // batches of KL.qb descriptors, each with its size on the device
+            hipLaunchKernelGGL(batch_sizes_kernel, dim3((n_batches + 255) / 256), dim3(256), 0, cs, p->sizes,
+                               n_batches, KL.qb);
+            for (uint32_t i = 0; i < n_batches && rc == QD_OK; i++) {
+                const uint64_t b0 = (uint64_t)i * KL.qb;
+                const uint32_t nqb = (uint32_t)std::min<uint64_t>(KL.qb, nqmax - b0);
+                const uint64_t o = b0 * k;
+                rc = blocked_batch(t, KL, p->ws, p->q + b0 * QD_WORDS, nqb, p->sizes + 2 + i, k, params, p->nn + o,
+                                   p->mi + o, p->ex + o, p->di + o, nullptr, nullptr, /*graph=*/true, cs);
+            }
+        } else if (mfma) {
+            rc = mfma_run(ML, p->ws, d_db, p->q, nqmax, p->sizes, k, p->nn, p->mi, p->ex, p->di, cs);
+        } else if (t)
             rc = tree_launch(t, TL, p->ws, p->q, nqmax, p->sizes, k, order, nullptr, 0, p->nn, p->mi, p->ex, p->di,
                              nullptr, nullptr, 0, cs);
         else
@@ -209,12 +250,13 @@ int knn_tree_impl(qd_tree_t t, const uint64_t *d_q, uint32_t nq, uint32_t k, int
                   uint32_t n_traced);
 
 namespace {
-using TuneKey = std::tuple<int, uint64_t, uint64_t, uint32_t, uint32_t>;  // device, n, nodes, nq, k
+using TuneKey = std::tuple<int, uint64_t, uint64_t, uint32_t, uint32_t, uint32_t>;  // device, n, nodes, nq, k, mask
 std::mutex g_tune_mu;
 std::map<TuneKey, qd_tuning> g_tune;
 bool g_tune_loaded = false;
 
-// Optional file cache: one line per entry, "dev n nodes nq k path order wpc qt ms".
+// Optional file cache: one line per entry,
+// "dev n nodes nq k mask path order wpc qt ms round1 round2 growth".
 void tune_load() {
     if (g_tune_loaded) return;
     g_tune_loaded = true;
@@ -224,12 +266,12 @@ void tune_load() {
     if (!fp) return;
     int dev, path, order;
     unsigned long long n, nodes;
-    unsigned nq, k, wpc, qt;
+    unsigned nq, k, mask, wpc, qt, r1, r2, gr;
     float ms;
-    while (fscanf(fp, "%d %llu %llu %u %u %d %d %u %u %f", &dev, &n, &nodes, &nq, &k, &path, &order, &wpc, &qt,
-                  &ms) == 10) {
-        qd_tuning t{path, (qd_order)order, wpc, qt, ms};
-        g_tune[TuneKey{dev, n, nodes, nq, k}] = t;
+    while (fscanf(fp, "%d %llu %llu %u %u %u %d %d %u %u %f %u %u %u", &dev, &n, &nodes, &nq, &k, &mask, &path,
+                  &order, &wpc, &qt, &ms, &r1, &r2, &gr) == 14) {
+        qd_tuning t{path, (qd_order)order, wpc, qt, ms, r1, r2, gr};
+        g_tune[TuneKey{dev, n, nodes, nq, k, mask}] = t;
     }
     fclose(fp);
 }
@@ -240,17 +282,18 @@ void tune_store(const TuneKey &key, const qd_tuning &t) {
     if (!f) return;
     FILE *fp = fopen(f, "a");
     if (!fp) return;
-    fprintf(fp, "%d %llu %llu %u %u %d %d %u %u %.6f\n", std::get<0>(key), (unsigned long long)std::get<1>(key),
-            (unsigned long long)std::get<2>(key), std::get<3>(key), std::get<4>(key), t.path, (int)t.order,
-            t.waves_per_cu, t.query_tile, t.ms);
+    fprintf(fp, "%d %llu %llu %u %u %u %d %d %u %u %.6f %u %u %u\n", std::get<0>(key),
+            (unsigned long long)std::get<1>(key), (unsigned long long)std::get<2>(key), std::get<3>(key),
+            std::get<4>(key), std::get<5>(key), t.path, (int)t.order, t.waves_per_cu, t.query_tile, t.ms,
+            t.round1_blocks, t.round2_blocks, t.round_growth);
     fclose(fp);
 }
 }  // namespace
 }  // namespace qd
 
 extern "C" int qd_autotune(qd_tree_t t, const uint64_t *d_db, uint64_t n, const uint64_t *d_q, uint32_t nq,
-                           uint32_t k, uint32_t reps, qd_tuning *best, qd_tuning *all, uint32_t max_all,
-                           uint32_t *n_all, void *stream) {
+                           uint32_t k, uint32_t reps, uint32_t order_mask, qd_tuning *best, qd_tuning *all,
+                           uint32_t max_all, uint32_t *n_all, void *stream) {
     using namespace qd;
     if (!best || (!t && (!d_db || n < 1)) || !d_q || nq == 0) return fail(QD_ERR_INVALID, "bad autotune arguments");
     if (k < 1 || k > QD_MAX_K) return fail(QD_ERR_INVALID, "k=%u outside 1..%d", k, QD_MAX_K);
@@ -258,7 +301,10 @@ extern "C" int qd_autotune(qd_tree_t t, const uint64_t *d_db, uint64_t n, const 
     hipStream_t s = (hipStream_t)stream;
     int dev = 0;
     (void)hipGetDevice(&dev);
-    const TuneKey key{dev, t ? t->n : n, t ? t->n_nodes : 0, nq, k};
+    const uint32_t all_orders = (1u << QD_ORDER_BEST_FIRST) | (1u << QD_ORDER_DEPTH_FIRST) | (1u << QD_ORDER_BLOCKED);
+    const uint32_t mask = t ? (order_mask ? order_mask & all_orders : all_orders) : 0;
+    if (t && mask == 0) return fail(QD_ERR_INVALID, "order_mask 0x%x names no frontier order", order_mask);
+    const TuneKey key{dev, t ? t->n : n, t ? t->n_nodes : 0, nq, k, mask};
     {
         std::lock_guard<std::mutex> lock(g_tune_mu);
         tune_load();
@@ -273,11 +319,21 @@ extern "C" int qd_autotune(qd_tree_t t, const uint64_t *d_db, uint64_t n, const 
     if (t) {
         for (int order : {QD_ORDER_BEST_FIRST, QD_ORDER_DEPTH_FIRST})
             for (uint32_t wpc : {4u, 8u, 16u, 32u}) {
+                if (!(mask & (1u << order))) continue;
                 if (order == QD_ORDER_BEST_FIRST && wpc > 8) continue;  // LDS holds 8 best-first waves per CU
-                cand.push_back({1, (qd_order)order, wpc, 0, 0.f});
+                cand.push_back({1, (qd_order)order, wpc, 0, 0.f, 0, 0, 0});
             }
+        // the blocked order's round schedule around its default (16 blocks in
+        // round 1, round 2 at ~128 queries per block list, growth 4)
+        const uint64_t t2 = std::max<uint64_t>(32, (128 * t->n_blk + nq - 1) / nq);
+        const uint32_t half = (uint32_t)std::min<uint64_t>(t2 / 2, 0xFFFFFFFFull);
+        const uint32_t dbl = (uint32_t)std::min<uint64_t>(t2 * 2, 0xFFFFFFFFull);
+        const uint32_t sched[][3] = {{16, 0, 4}, {8, 0, 4}, {32, 0, 4}, {16, 0, 2},
+                                     {16, 0, 8}, {16, half, 4}, {16, dbl, 4}};
+        if (mask & (1u << QD_ORDER_BLOCKED))
+            for (auto &sc : sched) cand.push_back({1, QD_ORDER_BLOCKED, 0, 0, 0.f, sc[0], sc[1], sc[2]});
     } else {
-        for (uint32_t qt : {0u, 4u, 8u, 16u}) cand.push_back({0, QD_ORDER_BEST_FIRST, 0, qt, 0.f});
+        for (uint32_t qt : {0u, 4u, 8u, 16u}) cand.push_back({0, QD_ORDER_BEST_FIRST, 0, qt, 0.f, 0, 0, 0});
     }
     char *ws = nullptr;
     const size_t m = (size_t)nq * k;
@@ -290,7 +346,19 @@ extern "C" int qd_autotune(qd_tree_t t, const uint64_t *d_db, uint64_t n, const 
     (void)hipEventCreate(&b);
     int rc = QD_OK;
     for (auto &c : cand) {
+        if (abort_requested()) {  // between candidates
+            rc = fail(QD_ERR_ABORTED, "autotune aborted");
+            break;
+        }
         auto run = [&]() {
+            if (c.path && c.order == QD_ORDER_BLOCKED) {
+                qd_search_params sp{};
+                sp.order = QD_ORDER_BLOCKED;
+                sp.round1_blocks = c.round1_blocks;
+                sp.round2_blocks = c.round2_blocks;
+                sp.round_growth = c.round_growth;
+                return knn_tree_blocked(t, d_q, nq, k, &sp, idx, mi, ex, di, nullptr, nullptr, s);
+            }
             return c.path ? knn_tree_impl(t, d_q, nq, k, (int)c.order, nullptr, 0, idx, mi, ex, di, nullptr, nullptr,
                                           stream, c.waves_per_cu, nullptr, 0)
                           : knn_bruteforce_impl(d_db, n, d_q, nq, k, idx, mi, ex, di, stream, c.query_tile, 0);

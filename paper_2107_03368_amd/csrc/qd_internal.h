@@ -17,6 +17,8 @@ constexpr u64 KEY_NONE = ~0ull;
 // Record a message for qd_last_error() and return `code`.
 int fail(int code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
 void clear_error();
+// The calling thread's abort flag (qd_set_abort_flag) is set.
+bool abort_requested();
 
 inline bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
 

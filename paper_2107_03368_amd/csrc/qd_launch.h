@@ -3,6 +3,8 @@
 // from device memory, so a plan can record it once in a hipGraph.
 #pragma once
 
+#include <vector>
+
 #include "qd_internal.h"
 
 namespace qd {
@@ -18,6 +20,24 @@ int tree_launch(qd_tree_t t, const TreeLaunch &L, char *ws, const uint64_t *d_q,
                 uint32_t *d_idx, int32_t *d_missed, int32_t *d_extra, float *d_dist, uint32_t *d_qstats,
                 uint32_t *d_trace, uint32_t n_traced, hipStream_t s);
 
+// The blocked tree search (QD_ORDER_BLOCKED) on a workspace the caller
+// owns: batches of up to qb queries, byte offsets of every buffer in it.
+struct BlockedLayout {
+    uint32_t qb = 0;
+    size_t qpop = 0, lbq = 0, lbb = 0, list = 0, cuts = 0, r1 = 0, rec = 0, thr = 0, ntop = 0, top = 0, ccnt = 0,
+           cand = 0, cnt = 0, qr = 0, act = 0, off = 0, voff = 0, ctr = 0, done = 0, fr = 0, tinfo = 0, redo = 0,
+           qst = 0, lnode = 0, gst = 0, fbq = 0, fbr = 0, fbws = 0, bytes = 0;
+    TreeLaunch fb;  // the per-query fallback's depth-first launch
+};
+int blocked_check(qd_tree_t t, const qd_search_params *p);
+BlockedLayout blocked_layout(qd_tree_t t, uint32_t nq_max, uint32_t k);
+// One batch of nqb queries (at most L.qb); nq_dev (nullable): the batch's
+// size on the device.  graph: no host synchronisation (capturable).
+int blocked_batch(qd_tree_t t, const BlockedLayout &L, char *ws, const uint64_t *d_q, uint32_t nqb,
+                  const uint32_t *nq_dev, uint32_t k, const qd_search_params *p, uint32_t *d_idx, int32_t *d_missed,
+                  int32_t *d_extra, float *d_dist, uint32_t *d_qstats, unsigned long long *gst, bool graph,
+                  hipStream_t s);
+
 struct BruteLaunch {
     uint32_t qt = 0, n_qtiles = 0, n_parts = 0;
     uint64_t rows_per_part = 0, blocks = 0;
@@ -27,6 +47,27 @@ BruteLaunch brute_launch_shape(uint64_t n, uint32_t nq_max, uint32_t k, uint32_t
 int brute_launch(const BruteLaunch &L, u64 *part, const uint64_t *d_db, uint64_t n, const uint64_t *d_q, uint32_t nq,
                  const uint32_t *nq_dev, uint32_t k, uint32_t *d_idx, int32_t *d_missed, int32_t *d_extra,
                  float *d_dist, hipStream_t s, bool timed = true);
+
+// The matrix-core sequential search on a workspace the caller owns.  Level
+// l searches the first rows[l] rows; every level but the last is a
+// matrix-core pass whose candidate bounds come from the next level (a
+// sample), the last level is the register-tiled scan.
+constexpr uint32_t kMfmaMinQueries = 512;  // smaller batches take the register-tiled scan
+constexpr uint64_t kMfmaMinRows = 1u << 16;
+constexpr int kMaxLevels = 4;
+struct MfmaLayout {
+    std::vector<uint64_t> rows;
+    BruteLaunch base, fb[kMaxLevels];
+    size_t tpop = 0, qpop = 0, cnt = 0, cand = 0, redo = 0, ctr = 0, thr[kMaxLevels] = {}, smp[kMaxLevels] = {},
+           base_part = 0, gq = 0, fbr = 0, fb_part = 0, bytes = 0;
+};
+// Whether a batch of nq queries over n rows takes the matrix cores.
+bool mfma_eligible(uint64_t n, uint32_t nq, uint32_t k);
+MfmaLayout mfma_layout(uint64_t n, uint32_t nq_max, uint32_t k);
+// nq_dev (nullable): the batch's size on the device (<= nq).  Never waits for the host.
+int mfma_run(const MfmaLayout &L, char *ws, const uint64_t *d_db, const uint64_t *d_q, uint32_t nq,
+             const uint32_t *nq_dev, uint32_t k, uint32_t *d_idx, int32_t *d_missed, int32_t *d_extra, float *d_dist,
+             hipStream_t s);
 
 int vote_launch(const uint32_t *nn, uint32_t k, const uint16_t *obj_of, uint64_t n_db, uint32_t n_obj,
                 const uint64_t *qoff, uint32_t nqo, const uint32_t *nqo_dev, uint32_t threshold, uint32_t *votes,

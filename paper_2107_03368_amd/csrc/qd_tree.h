@@ -1,6 +1,8 @@
 // Library-owned Dissimilarity Tree (opaque to callers as qd_tree_t).
 #pragma once
 
+#include <vector>
+
 #include "qd_internal.h"
 
 struct qd_tree_s {
@@ -27,10 +29,24 @@ struct qd_tree_s {
     uint64_t n_blk = 0;            // blocks of 256 leaf-order rows
     uint64_t *d_blk = nullptr;     // n_blk x 64 words: OR image of each block's rows
     uint16_t *d_bpop = nullptr;    // n_blk x 2: smallest, largest row popcount of each block (null: plain)
+    std::vector<uint32_t> level_max;  // host: most rows of any node of each level (root level 0)
 };
 
 namespace qd {
+struct TreeLaunch;  // qd_launch.h
 void tree_release(qd_tree_s *t);
+// Completes a tree whose n, n_nodes, max_leaf, has_and, d_sorted (rows in
+// leaf order) and d_perm are set, from its breadth-first structure (child
+// pairs, begin, count): uploads the structure, derives parents, levels,
+// popcounts, images, popcount ranges (want_pop), the inverse permutation and
+// the block images.  Synchronous; on failure it releases t.
+// Learned start of the blocked search: d_node[i] = the node reached from the
+// root by entering, at every inner node holding more than max_rows rows, the
+// child the model scores higher for query i (ties: the similar child).
+int model_descend(qd_model_t m, qd_tree_t t, const uint64_t *d_q, uint32_t nq, uint32_t max_rows, uint32_t *d_node,
+                  hipStream_t s);
+int tree_finish(qd_tree_s *t, const std::vector<int32_t> &child, const std::vector<uint32_t> &begin,
+                const std::vector<uint32_t> &count, bool want_pop, hipStream_t s);
 // Block images for the batched search (tree_blocked.hip).
 int tree_block_images(qd_tree_s *t, hipStream_t s);
 int knn_tree_blocked(qd_tree_t t, const uint64_t *d_q, uint32_t nq, uint32_t k, const qd_search_params *p,

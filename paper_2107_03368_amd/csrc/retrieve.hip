@@ -255,6 +255,10 @@ extern "C" int qd_retrieve_objects_early(qd_tree_t t, const uint64_t *d_db, uint
     std::vector<uint32_t> h_used(nqo), h_ids;
     uint64_t searched = 0;
     for (uint64_t chunk = 16;; chunk *= 2) {
+        if (abort_requested()) {  // between rounds
+            (void)hipStreamSynchronize(s);
+            return done(fail(QD_ERR_ABORTED, "retrieval aborted"));
+        }
         h_ids.clear();
         for (uint32_t g = 0; g < nqo; g++) {
             if (decided[g]) continue;

@@ -28,8 +28,14 @@
 //     A query whose candidate buffer overflows repeats the round with the
 //     k-th key of the candidates it stored.
 //  5. Results; a query whose key cannot tighten that way (more than a buffer
-//     of rows tie at its k-th key) is searched again by the per-query
-//     best-first traversal.
+//     of rows tie at its k-th key), or that still runs after the last pass,
+//     is searched again by the per-query depth-first traversal.
+//
+// Driving the rounds: a direct call checks on the host after each pass
+// whether any query still runs.  A captured plan runs a fixed number of
+// passes instead; every kernel reads its work (running queries, tile and
+// pair counts, the batch size) from device memory, so a pass with nothing
+// to do only costs its launches, and nothing waits for the host.
 //
 // Exactness: a row with K <= the final k-th key lies in a block whose bound
 // is at most that key, hence at most the query's k-th key in every round (it
@@ -42,6 +48,7 @@
 #include "mfma_tile.h"
 #include "qd_device.h"
 #include "qd_internal.h"
+#include "qd_launch.h"
 #include "qd_tree.h"
 
 namespace qd {
@@ -58,6 +65,10 @@ constexpr uint32_t kBlk = mt::MB;          // rows per block
 constexpr uint32_t kM1 = 64;               // most blocks in round 1 (default 16)
 constexpr int kRounds = 24;                // rounds 1 .. kRounds; the last takes every remaining block
 constexpr int kMaxPasses = 64;             // matrix-core passes (rounds and repeats) per batch
+// Passes of a batch that runs without the host (captured graphs).  The
+// searches measured here finish in 5 to 6 passes (rounds plus overflow
+// repeats); a query still running after them takes the exact fallback.
+constexpr int kGraphPasses = 10;
 constexpr uint32_t kCap = 8128;            // candidate slots per query per round (kCap + k <= 8192)
 constexpr int kGroup = 8;                  // blocks per wave when building the lists (more waves hide the loads' latency)
 static_assert(32 % kGroup == 0, "a wave's blocks share one word of done bits");
@@ -134,12 +145,15 @@ __global__ __launch_bounds__(mt::kThreads) void bound_kernel(const uint4 *__rest
                                                              const uint4 *__restrict__ img, uint64_t nblk,
                                                              const uint16_t *__restrict__ bpop,
                                                              const uint16_t *__restrict__ qpop, uint32_t n_qtiles,
-                                                             uint16_t *__restrict__ lbq, uint16_t *__restrict__ lbb) {
+                                                             uint16_t *__restrict__ lbq, uint16_t *__restrict__ lbb,
+                                                             const uint32_t *__restrict__ nq_dev) {
     __shared__ mt::Smem sm;
     __shared__ uint32_t s_pq[mt::MA], s_pmin[mt::MB], s_pmax[mt::MB];
+    if (nq_dev) nqb = min(nqb, *nq_dev);  // the batch's size on the device (captured graphs)
     const uint64_t n_tiles = (uint64_t)n_qtiles * ((nblk + mt::MB - 1) / mt::MB);
     for (uint64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
         const uint32_t q0 = (uint32_t)(tile % n_qtiles) * mt::MA;
+        if (q0 >= nqb) continue;  // whole workgroup: no query of this tile is in the batch
         const uint64_t b0 = (tile / n_qtiles) * mt::MB;
         const int own = mt::own_row();
         const uint4 *row;
@@ -194,11 +208,17 @@ __global__ __launch_bounds__(mt::kThreads) void bound_kernel(const uint4 *__rest
 // of every round.  One 256-thread block per query.
 __global__ __launch_bounds__(256) void plan_kernel(const uint16_t *__restrict__ lbq, uint64_t nblk, uint32_t m1,
                                                    uint64_t t2, uint32_t growth, u64 *__restrict__ cuts,
-                                                   uint32_t *__restrict__ r1list) {
+                                                   uint32_t *__restrict__ r1list, const uint32_t *__restrict__ nq_dev) {
     __shared__ uint32_t cum[kLevels];
     __shared__ uint32_t part[256];
     __shared__ uint32_t s_bcut;
     const uint32_t qi = blockIdx.x, tid = threadIdx.x;
+    const uint32_t nqb = nq_dev ? min(gridDim.x, *nq_dev) : gridDim.x;
+    if (qi >= nqb) return;  // whole block
+    // t2 = 0: round 2 covers enough blocks that a block's list holds ~128
+    // queries on average
+    if (t2 == 0) t2 = (128 * nblk + nqb - 1) / nqb;
+    if (t2 < 2 * (uint64_t)m1) t2 = 2 * (uint64_t)m1;
     const uint16_t *row = lbq + (uint64_t)qi * nblk;
     for (uint32_t i = tid; i < kLevels; i += 256) cum[i] = 0;
     if (tid == 0) s_bcut = kInf;
@@ -365,10 +385,18 @@ __global__ __launch_bounds__(256) void round1_kernel(const uint4 *__restrict__ q
                                                      u64 *__restrict__ top, uint32_t *__restrict__ ntop,
                                                      uint32_t *__restrict__ thrk, u64 *__restrict__ rec,
                                                      u64 *__restrict__ frange, uint32_t *__restrict__ qround,
-                                                     uint32_t *__restrict__ counters, uint32_t *__restrict__ qst) {
+                                                     uint32_t *__restrict__ counters, uint32_t *__restrict__ qst,
+                                                     const uint32_t *__restrict__ nq_dev) {
     const int lane = lane_id();
     const uint32_t qi = readfirst(blockIdx.x * 4 + (threadIdx.x >> 6));
     if (qi >= nqb) return;
+    if (nq_dev && qi >= *nq_dev) {  // beyond the batch on the device: never runs
+        if (lane == 0) {
+            rec[2 * qi] = rec[2 * qi + 1] = 0;
+            ntop[qi] = 0;
+        }
+        return;
+    }
     const int g = lane >> 3, j = lane & 7;
     uint4 qv[4];
 #pragma unroll
@@ -428,6 +456,28 @@ __global__ __launch_bounds__(256) void round1_kernel(const uint4 *__restrict__ q
             qst[(uint64_t)qi * 4 + 3] = rows;
         }
     }
+}
+
+// Learned start: round 1 takes the n1 consecutive blocks of the leaf order
+// that begin with the first block of the node the model's descent reached
+// (moved back so they stay inside the rows).  Those pairs are marked done, and
+// round 2's range starts at the lowest key (cuts[1] = 0), so every other block
+// is still covered by the bound-ordered rounds and no block is evaluated twice.
+// One thread per query.
+__global__ void learned_start_kernel(const uint32_t *__restrict__ node, uint32_t nqb,
+                                     const uint32_t *__restrict__ begin, uint64_t nblk, uint32_t n1,
+                                     uint32_t *__restrict__ r1list, u64 *__restrict__ cuts, uint32_t *__restrict__ done,
+                                     uint32_t nqp) {
+    const uint32_t qi = blockIdx.x * blockDim.x + threadIdx.x;
+    if (qi >= nqb) return;
+    uint64_t b0 = begin[node[qi]] / kBlk;
+    if (b0 + n1 > nblk) b0 = nblk - n1;
+    for (uint32_t i = 0; i < n1; i++) {
+        const uint64_t b = b0 + i;
+        r1list[(uint64_t)qi * kM1 + i] = (uint32_t)b;
+        done[(b / 32) * nqp + qi] |= 1u << (b % 32);  // this thread owns query qi's bits
+    }
+    cuts[(uint64_t)qi * (kRounds + 1) + 1] = 0;
 }
 
 // The queries running this round (rec[2q + 1] > rec[2q]), in query order:
@@ -721,7 +771,7 @@ __global__ __launch_bounds__(256) void eval_short_kernel(const uint4 *__restrict
 // dependent load per window, so the matrix cores do not wait for a tile to
 // start.
 __global__ __launch_bounds__(mt::kThreads) void eval_kernel(const uint4 *__restrict__ q, const uint4 *__restrict__ sorted,
-                                                            uint64_t n, uint32_t nqp, uint32_t total,
+                                                            uint64_t n, uint32_t nqp, const uint32_t *__restrict__ ntiles,
                                                             const uint16_t *__restrict__ list,
                                                             const uint4 *__restrict__ tinfo,
                                                             const uint16_t *__restrict__ tpop,
@@ -737,6 +787,7 @@ __global__ __launch_bounds__(mt::kThreads) void eval_kernel(const uint4 *__restr
     // instead of waiting one after another
     constexpr uint32_t kQueue = 320;  // room for one (a, rr) group's 256 entries past the flush mark
     __shared__ uint32_t s_cq[mt::kThreads / 64][kQueue][3];
+    const uint32_t total = *ntiles;  // written by the tile prefix
     const uint64_t vend = mt::xcd_grid(total);
     const int r = mt::own_row();
     const bool arow = r < mt::MA;  // the same in a whole wave
@@ -914,7 +965,8 @@ __global__ __launch_bounds__(256) void select_kernel(uint32_t k, const uint16_t 
                                                      uint32_t *__restrict__ counters, uint32_t *__restrict__ redo,
                                                      uint32_t *__restrict__ qst, const uint16_t *__restrict__ lbq,
                                                      uint64_t nblk, uint32_t *__restrict__ done, uint64_t dw, uint32_t nqp,
-                                                     u64 *__restrict__ frange) {
+                                                     u64 *__restrict__ frange, const uint32_t *__restrict__ r1list,
+                                                     uint32_t n1_marked) {
     __shared__ u64 keys[8192];
     const uint32_t qi = blockIdx.x;
     const u64 lo = rec[2 * qi], hi = rec[2 * qi + 1];
@@ -1005,6 +1057,14 @@ __global__ __launch_bounds__(256) void select_kernel(uint32_t k, const uint16_t 
             }
             done[(uint64_t)wd * nqp + qi] &= ~clear;
         }
+        if (n1_marked) {
+            // a learned round 1 evaluated blocks anywhere in the key order: they stay done
+            __syncthreads();
+            for (uint32_t i = threadIdx.x; i < n1_marked; i += 256) {
+                const uint32_t b = r1list[(uint64_t)qi * kM1 + i];
+                atomicOr(&done[(uint64_t)(b / 32) * nqp + qi], 1u << (b % 32));
+            }
+        }
     }
     if (threadIdx.x != 0) return;
     ccnt[qi] = 0;
@@ -1057,10 +1117,11 @@ __global__ __launch_bounds__(256) void emit_kernel(const uint64_t *__restrict__ 
                                                    const uint64_t *__restrict__ sorted,
                                                    const uint32_t *__restrict__ iperm, uint32_t *idx, int32_t *missed,
                                                    int32_t *extra, float *dist, const uint32_t *__restrict__ qst,
-                                                   uint32_t *d_qstats, unsigned long long *gstats) {
+                                                   uint32_t *d_qstats, unsigned long long *gstats,
+                                                   const uint32_t *__restrict__ nq_dev) {
     const int lane = lane_id();
     const uint32_t qi = readfirst(blockIdx.x * 4 + (threadIdx.x >> 6));
-    if (qi >= nqb) return;
+    if (qi >= nqb || (nq_dev && qi >= *nq_dev)) return;
     const uint32_t nt = ntop[qi];
     if (lane < (int)k) {
         const uint64_t o = (uint64_t)qi * k + lane;
@@ -1095,17 +1156,26 @@ __global__ __launch_bounds__(256) void emit_kernel(const uint64_t *__restrict__ 
     }
 }
 
-__global__ void gather_kernel(const uint4 *__restrict__ q, const uint32_t *__restrict__ list, uint32_t m,
-                              uint4 *__restrict__ out) {
+// The fallback's queries (list[0 .. *m)) gathered into consecutive rows.
+__global__ void gather_kernel(const uint4 *__restrict__ q, const uint32_t *__restrict__ list,
+                              const uint32_t *__restrict__ m, uint4 *__restrict__ out) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < m * 32) out[i] = q[(uint64_t)list[i >> 5] * 32 + (i & 31)];
+    if (i < *m * 32) out[i] = q[(uint64_t)list[i >> 5] * 32 + (i & 31)];
 }
 
+// The fallback's results back to their queries' rows.
 template <class T>
-__global__ void scatter_kernel(const T *__restrict__ src, const uint32_t *__restrict__ list, uint32_t m, uint32_t k,
-                               T *__restrict__ dst) {
+__global__ void scatter_kernel(const T *__restrict__ src, const uint32_t *__restrict__ list,
+                               const uint32_t *__restrict__ m, uint32_t k, T *__restrict__ dst) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < m * k) dst[(uint64_t)list[i / k] * k + (i % k)] = src[i];
+    if (i < *m * k) dst[(uint64_t)list[i / k] * k + (i % k)] = src[i];
+}
+
+// Clears n words (a kernel, not a memset node, so a captured graph replays it
+// reliably).
+__global__ void zero_kernel(uint32_t *__restrict__ p, uint64_t n) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = 0;
 }
 
 inline size_t up256(size_t x) { return (x + 255) / 256 * 256; }
@@ -1122,186 +1192,237 @@ int tree_block_images(qd_tree_s *t, hipStream_t s) {
     return QD_OK;
 }
 
-int knn_tree_blocked(qd_tree_t t, const uint64_t *d_q, uint32_t nq, uint32_t k, const qd_search_params *p,
-                     uint32_t *d_idx, int32_t *d_missed, int32_t *d_extra, float *d_dist, uint32_t *d_qstats,
-                     qd_stats *h_stats, hipStream_t s) {
-    const uint64_t n = t->n, nblk = t->n_blk;
-    if (!t->d_blk || nblk == 0) return fail(QD_ERR_INVALID, "tree has no block images");
-    if (nblk > 0x7FFFFFFFull) return fail(QD_ERR_UNSUPPORTED, "too many blocks");
-    const uint32_t m1 = p && p->round1_blocks ? p->round1_blocks : 16;
-    const uint32_t growth = p && p->round_growth ? p->round_growth : 4;
-    if (m1 > kM1) return fail(QD_ERR_INVALID, "round1_blocks=%u above %u", m1, kM1);
-    if (growth < 2 || growth > 64) return fail(QD_ERR_INVALID, "round_growth=%u outside 2..64", growth);
-    if (h_stats) *h_stats = qd_stats{0, 0, 0, 0};
+// Workspace of one batch of up to qb queries (offsets into one allocation).
+BlockedLayout blocked_layout(qd_tree_t t, uint32_t nq, uint32_t k) {
+    BlockedLayout L;
+    const uint64_t nblk = t->n_blk;
     // batch: up to kMaxBatch queries, bound and list matrices within about 12 GiB
     uint32_t qb = nq < kMaxBatch ? nq : kMaxBatch;
+    if (qb == 0) qb = 1;
     auto batch_bytes = [&](uint32_t b) {
         return (uint64_t)up256(b) * (nblk * 6 + (nblk + 31) / 32 * 4 + kCap * 8 + (uint64_t)k * 8 + 512);
     };
     while (qb > 256 && batch_bytes(qb) > (12ull << 30)) qb = (qb + 1) / 2;
+    L.qb = qb;
     const size_t P = up256(qb);
-    // workspace
     size_t o = 0;
     auto take = [&](size_t bytes) {
         const size_t at = o;
         o += up256(bytes);
         return at;
     };
-    const size_t a_qpop = take(P * 2), a_lbq = take(P * nblk * 2), a_lbb = take(P * nblk * 2),
-                 a_list = take(P * nblk * 2), a_cuts = take(P * (kRounds + 1) * 8), a_r1 = take(P * kM1 * 4),
-                 a_rec = take(P * 16), a_thr = take(P * 4), a_ntop = take(P * 4), a_top = take(P * k * 8),
-                 a_ccnt = take(P * 4), a_cand = take(P * kCap * 8), a_cnt = take(nblk * 4), a_qr = take(P * 4),
-                 a_act = take(P * 4 + 4),
-                 a_off = take((nblk + 1) * 4), a_voff = take((nblk + 1) * 4), a_ctr = take(16),
-                 a_done = take(P * ((nblk + 31) / 32) * 4), a_fr = take(P * 16),
-                 a_tblk = take(nblk * (P / mt::MA) * 16),  // tile records: at most ceil(nqb / 256) per block
-                 a_redo = take(P * 4), a_qst = take(P * 16),
-                 a_gst = take(32);
-    char *ws = nullptr;
-    QD_HIP_CHECK(hipMallocAsync((void **)&ws, o, s));
-    uint16_t *qpop = (uint16_t *)(ws + a_qpop), *lbq = (uint16_t *)(ws + a_lbq), *lbb = (uint16_t *)(ws + a_lbb),
-             *list = (uint16_t *)(ws + a_list);
-    u64 *cuts = (u64 *)(ws + a_cuts), *rec = (u64 *)(ws + a_rec), *top = (u64 *)(ws + a_top),
-        *cand = (u64 *)(ws + a_cand);
-    uint32_t *r1list = (uint32_t *)(ws + a_r1), *thr = (uint32_t *)(ws + a_thr), *ntop = (uint32_t *)(ws + a_ntop),
-             *ccnt = (uint32_t *)(ws + a_ccnt), *cnt = (uint32_t *)(ws + a_cnt), *off = (uint32_t *)(ws + a_off),
-             *voff = (uint32_t *)(ws + a_voff), *ctr = (uint32_t *)(ws + a_ctr), *donebits = (uint32_t *)(ws + a_done), *redo = (uint32_t *)(ws + a_redo), *qst = (uint32_t *)(ws + a_qst),
-             *qround = (uint32_t *)(ws + a_qr);
-    unsigned long long *gst = (unsigned long long *)(ws + a_gst);
-    u64 *frange = (u64 *)(ws + a_fr);
-    uint4 *tinfo = (uint4 *)(ws + a_tblk);
-    uint32_t *act = (uint32_t *)(ws + a_act), *nact = act + P;
-    const bool want_stats = d_qstats || h_stats;
-    int rc = QD_OK;
-    auto done = [&](int code) {
-        (void)hipFreeAsync(ws, s);
-        return code;
-    };
-    if (hipMemsetAsync(gst, 0, 32, s) != hipSuccess) return done(fail(QD_ERR_DEVICE, "memset"));
-    for (uint32_t qb0 = 0; qb0 < nq; qb0 += qb) {
-        const uint32_t nqb = nq - qb0 < qb ? nq - qb0 : qb;
-        const uint32_t nqp = (uint32_t)up256(nqb);
-        const uint64_t *qq = d_q + (uint64_t)qb0 * QD_WORDS;
-        const uint4 *q4 = reinterpret_cast<const uint4 *>(qq);
-        rc = popcount_rows_launch(qq, nqb, qpop, s);
-        if (rc != QD_OK) return done(rc);
-        const uint64_t dw = (nblk + 31) / 32;  // done-bit words per query, stored word-major (word, query)
-        if (hipMemsetAsync(ccnt, 0, (size_t)nqb * 4, s) != hipSuccess || hipMemsetAsync(ctr, 0, 16, s) != hipSuccess ||
-            hipMemsetAsync(donebits, 0, (size_t)nqp * dw * 4, s) != hipSuccess)
-            return done(fail(QD_ERR_DEVICE, "memset"));
-        const uint32_t n_qtiles = nqp / mt::MA;
-        const uint64_t n_btiles = (nblk + mt::MB - 1) / mt::MB;
-        {
-            KernelTimer timer("tree_block_bounds", s);
-            hipLaunchKernelGGL(bound_kernel, dim3((uint32_t)mt::tile_grid(n_qtiles * n_btiles)), dim3(mt::kThreads), 0, s,
-                               q4, nqb,
-                               nqp, reinterpret_cast<const uint4 *>(t->d_blk), nblk, t->d_bpop, qpop, n_qtiles, lbq,
-                               lbb);
-        }
-        // round 2 covers about t2 blocks per query: enough that a block's list
-        // holds ~128 queries on average
-        uint64_t t2 = p && p->round2_blocks ? p->round2_blocks : (128 * nblk + nqb - 1) / nqb;
-        if (t2 < 2 * (uint64_t)m1) t2 = 2 * (uint64_t)m1;
-        {
-            KernelTimer timer("tree_block_plan", s);
-            hipLaunchKernelGGL(plan_kernel, dim3(nqb), dim3(256), 0, s, lbq, nblk, m1, t2, growth, cuts, r1list);
-        }
-        const uint32_t n1 = (uint32_t)(nblk < m1 ? nblk : m1);
-        {
-            KernelTimer timer("tree_block_round1", s);
-            hipLaunchKernelGGL(round1_kernel, dim3((nqb + 3) / 4), dim3(256), 0, s, q4, nqb, k,
-                               reinterpret_cast<const uint4 *>(t->d_sorted), t->d_pop, t->d_perm, n, nblk, r1list, n1,
-                               cuts, qpop, top, ntop, thr, rec, frange, qround, ctr, want_stats ? qst : nullptr);
-        }
-        if (hipGetLastError() != hipSuccess) return done(fail(QD_ERR_DEVICE, "blocked search: launch failed"));
-        for (int pass = 0;; pass++) {
-            {
-                KernelTimer timer("tree_block_lists", s);
-                const uint64_t waves = (nblk + kGroup - 1) / kGroup;
-                hipLaunchKernelGGL(active_kernel, dim3(1), dim3(1024), 0, s, rec, nqb, act, nact);
-                hipLaunchKernelGGL(list_kernel, dim3((uint32_t)((waves + 3) / 4)), dim3(256), 0, s, lbb, nblk, n, nqb,
-                                   nqp, act, nact, rec, frange, donebits, list, cnt, want_stats ? qst : nullptr);
-                hipLaunchKernelGGL(tile_scan_kernel, dim3(1), dim3(1024), 0, s, cnt, nblk, t->d_bpop, off, voff, tinfo,
-                                   ctr + 2);
-            }
-            uint32_t h[4];
-            hipError_t e = hipMemcpyAsync(h, ctr, 16, hipMemcpyDeviceToHost, s);
-            if (e == hipSuccess) e = hipStreamSynchronize(s);
-            if (e != hipSuccess) return done(fail(QD_ERR_DEVICE, "blocked search: %s", hipGetErrorString(e)));
-            if (h[0] == 0) break;  // no query runs any more
-            if (pass == kMaxPasses) {
-                hipLaunchKernelGGL(leftover_kernel, dim3((nqb + 255) / 256), dim3(256), 0, s, nqb, rec, ctr, redo);
-                break;
-            }
-            if (hipMemsetAsync(ctr, 0, 4, s) != hipSuccess) return done(fail(QD_ERR_DEVICE, "memset"));
-            profile_count("tree_block_tiles", h[2]);
-            profile_count("tree_block_short_pairs", h[3]);
-            if (h[2] > 0) {
-                KernelTimer timer("tree_block_eval", s);
-                // persistent: one workgroup per CU (the tile's LDS and registers
-                // leave room for one), a multiple of the 8 XCDs
-                const uint64_t grid = std::min<uint64_t>(mt::xcd_grid(h[2]), mt::xcd_grid((uint64_t)device_cus()));
-                hipLaunchKernelGGL(eval_kernel, dim3((uint32_t)grid), dim3(mt::kThreads), 0, s, q4,
-                                   reinterpret_cast<const uint4 *>(t->d_sorted), n, nqp, h[2], list, tinfo, t->d_pop,
-                                   t->d_perm, qpop, thr, ccnt, cand);
-            }
-            if (h[3] > 0) {
-                KernelTimer timer("tree_block_eval_short", s);
-                const uint64_t groups = (h[3] + 3) / 4;
-                const uint64_t grid = mt::xcd_grid(std::min<uint64_t>(groups, (uint64_t)device_cus() * 8));
-                hipLaunchKernelGGL(eval_short_kernel, dim3((uint32_t)grid), dim3(256), 0, s, q4,
-                                   reinterpret_cast<const uint4 *>(t->d_sorted), n, nblk, nqp, list, cnt, voff, t->d_pop,
-                                   t->d_perm, qpop, thr, ccnt, cand);
-            }
-            {
-                KernelTimer timer("tree_block_select", s);
-                hipLaunchKernelGGL(select_kernel, dim3(nqb), dim3(256), 0, s, k, qpop, cuts, rec, qround, ccnt, cand,
-                                   top, ntop, thr, ctr, redo, want_stats ? qst : nullptr, lbq, nblk, donebits, dw, nqp,
-                                   frange);
-            }
-            if (hipGetLastError() != hipSuccess) return done(fail(QD_ERR_DEVICE, "blocked search: launch failed"));
-        }
-        uint32_t *oi = d_idx + (uint64_t)qb0 * k;
-        int32_t *om = d_missed + (uint64_t)qb0 * k, *ox = d_extra + (uint64_t)qb0 * k;
-        float *od = d_dist + (uint64_t)qb0 * k;
-        hipLaunchKernelGGL(emit_kernel, dim3((nqb + 3) / 4), dim3(256), 0, s, qq, nqb, k, top, ntop, t->d_sorted,
-                           t->d_iperm, oi, om, ox, od, want_stats ? qst : nullptr,
-                           d_qstats ? d_qstats + (uint64_t)qb0 * 4 : nullptr, h_stats ? gst : nullptr);
-        // queries whose candidate buffer overflowed
-        uint32_t h_redo = 0;
-        hipError_t e = hipMemcpyAsync(&h_redo, ctr + 1, 4, hipMemcpyDeviceToHost, s);
-        if (e == hipSuccess) e = hipStreamSynchronize(s);
-        if (e != hipSuccess) return done(fail(QD_ERR_DEVICE, "blocked search: %s", hipGetErrorString(e)));
-        if (h_redo > 0) {
-            char *fb = nullptr;
-            QD_HIP_CHECK(hipMallocAsync((void **)&fb, (size_t)h_redo * (512 + (size_t)k * 16), s));
-            uint4 *gq = reinterpret_cast<uint4 *>(fb);
-            uint32_t *ri = reinterpret_cast<uint32_t *>(fb + (size_t)h_redo * 512);
-            int32_t *rm = reinterpret_cast<int32_t *>(ri + (size_t)h_redo * k), *rx = rm + (size_t)h_redo * k;
-            float *rd = reinterpret_cast<float *>(rx + (size_t)h_redo * k);
-            hipLaunchKernelGGL(gather_kernel, dim3((h_redo * 32 + 255) / 256), dim3(256), 0, s, q4, redo, h_redo, gq);
-            rc = knn_tree_impl(t, reinterpret_cast<const uint64_t *>(gq), h_redo, k, QD_ORDER_BEST_FIRST, nullptr, 0,
-                               ri, rm, rx, rd, nullptr, nullptr, s, 0, nullptr, 0);
-            if (rc == QD_OK) {
-                const dim3 g((h_redo * k + 255) / 256);
-                hipLaunchKernelGGL(scatter_kernel<uint32_t>, g, dim3(256), 0, s, ri, redo, h_redo, k, oi);
-                hipLaunchKernelGGL(scatter_kernel<int32_t>, g, dim3(256), 0, s, rm, redo, h_redo, k, om);
-                hipLaunchKernelGGL(scatter_kernel<int32_t>, g, dim3(256), 0, s, rx, redo, h_redo, k, ox);
-                hipLaunchKernelGGL(scatter_kernel<float>, g, dim3(256), 0, s, rd, redo, h_redo, k, od);
-                if (hipGetLastError() != hipSuccess) rc = fail(QD_ERR_DEVICE, "fallback scatter");
-            }
-            (void)hipFreeAsync(fb, s);
-            if (rc != QD_OK) return done(rc);
-        }
+    L.qpop = take(P * 2);
+    L.lbq = take(P * nblk * 2);
+    L.lbb = take(P * nblk * 2);
+    L.list = take(P * nblk * 2);
+    L.cuts = take(P * (kRounds + 1) * 8);
+    L.r1 = take(P * kM1 * 4);
+    L.rec = take(P * 16);
+    L.thr = take(P * 4);
+    L.ntop = take(P * 4);
+    L.top = take(P * k * 8);
+    L.ccnt = take(P * 4);
+    L.cand = take(P * kCap * 8);
+    L.cnt = take(nblk * 4);
+    L.qr = take(P * 4);
+    L.act = take(P * 4 + 4);
+    L.off = take((nblk + 1) * 4);
+    L.voff = take((nblk + 1) * 4);
+    L.ctr = take(64);
+    L.done = take(P * ((nblk + 31) / 32) * 4);
+    L.fr = take(P * 16);
+    L.tinfo = take(nblk * (P / mt::MA) * 16);  // tile records: at most ceil(nqb / 256) per block
+    L.redo = take(P * 4);
+    L.qst = take(P * 16);
+    L.lnode = take(P * 4);
+    L.gst = take(32);
+    // the per-query fallback for queries whose key cannot tighten: gathered
+    // queries, their results, and a depth-first traversal's workspace
+    L.fb = tree_launch_shape(t, qb, QD_ORDER_DEPTH_FIRST, 0);
+    L.fbq = take(P * 512);
+    L.fbr = take(P * k * 16);
+    L.fbws = take(L.fb.total());
+    L.bytes = o;
+    return L;
+}
+
+// One batch of nqb queries (nqb <= L.qb) at qq; nq_dev (nullable): the
+// batch's size on the device, at most nqb.  With graph, nothing waits for
+// the host: the rounds run as kGraphPasses fixed passes whose kernels read
+// their work from device memory (a pass with no running query does nothing),
+// queries still running after them take the fallback, and the launches can
+// be captured.  Otherwise the host checks after each pass whether any query
+// still runs.  gst (nullable): totals of the per-query stats.
+int blocked_batch(qd_tree_t t, const BlockedLayout &L, char *ws, const uint64_t *qq, uint32_t nqb,
+                  const uint32_t *nq_dev, uint32_t k, const qd_search_params *p, uint32_t *oi, int32_t *om,
+                  int32_t *ox, float *od, uint32_t *d_qstats, unsigned long long *gst, bool graph, hipStream_t s) {
+    const uint64_t n = t->n, nblk = t->n_blk;
+    const uint32_t m1 = p && p->round1_blocks ? p->round1_blocks : 16;
+    const uint32_t growth = p && p->round_growth ? p->round_growth : 4;
+    const uint64_t t2 = p ? p->round2_blocks : 0;
+    qd_model_t model = p ? p->model : nullptr;
+    const size_t P = up256(L.qb);
+    uint16_t *qpop = (uint16_t *)(ws + L.qpop), *lbq = (uint16_t *)(ws + L.lbq), *lbb = (uint16_t *)(ws + L.lbb),
+             *list = (uint16_t *)(ws + L.list);
+    u64 *cuts = (u64 *)(ws + L.cuts), *rec = (u64 *)(ws + L.rec), *top = (u64 *)(ws + L.top),
+        *cand = (u64 *)(ws + L.cand), *frange = (u64 *)(ws + L.fr);
+    uint32_t *r1list = (uint32_t *)(ws + L.r1), *thr = (uint32_t *)(ws + L.thr), *ntop = (uint32_t *)(ws + L.ntop),
+             *ccnt = (uint32_t *)(ws + L.ccnt), *cnt = (uint32_t *)(ws + L.cnt), *off = (uint32_t *)(ws + L.off),
+             *voff = (uint32_t *)(ws + L.voff), *ctr = (uint32_t *)(ws + L.ctr), *donebits = (uint32_t *)(ws + L.done),
+             *redo = (uint32_t *)(ws + L.redo), *qst = (uint32_t *)(ws + L.qst), *qround = (uint32_t *)(ws + L.qr),
+             *lnode = (uint32_t *)(ws + L.lnode);
+    uint4 *tinfo = (uint4 *)(ws + L.tinfo);
+    uint32_t *act = (uint32_t *)(ws + L.act), *nact = act + P;
+    const bool want_stats = d_qstats || gst;
+    const uint32_t nqp = (uint32_t)up256(nqb);
+    const uint4 *q4 = reinterpret_cast<const uint4 *>(qq);
+    const uint64_t dw = (nblk + 31) / 32;  // done-bit words per query, stored word-major (word, query)
+    int rc = popcount_rows_launch(qq, nqb, qpop, s);
+    if (rc != QD_OK) return rc;
+    // counters: [0] running (round 1 and select), [1] fallback queries, [2] tiles, [3] short pairs
+    hipLaunchKernelGGL(zero_kernel, dim3(1), dim3(64), 0, s, ctr, (uint64_t)16);
+    hipLaunchKernelGGL(zero_kernel, dim3((uint32_t)std::min<uint64_t>((nqb + 255) / 256, 1024)), dim3(256), 0, s, ccnt,
+                       (uint64_t)nqb);
+    hipLaunchKernelGGL(zero_kernel, dim3((uint32_t)std::min<uint64_t>((nqp * dw + 255) / 256, 4096)), dim3(256), 0, s,
+                       donebits, (uint64_t)nqp * dw);
+    const uint32_t n_qtiles = nqp / mt::MA;
+    const uint64_t n_btiles = (nblk + mt::MB - 1) / mt::MB;
+    {
+        KernelTimer timer("tree_block_bounds", s);
+        hipLaunchKernelGGL(bound_kernel, dim3((uint32_t)mt::tile_grid(n_qtiles * n_btiles)), dim3(mt::kThreads), 0, s,
+                           q4, nqb, nqp, reinterpret_cast<const uint4 *>(t->d_blk), nblk, t->d_bpop, qpop, n_qtiles,
+                           lbq, lbb, nq_dev);
     }
-    if (h_stats) {
+    {
+        KernelTimer timer("tree_block_plan", s);
+        hipLaunchKernelGGL(plan_kernel, dim3(nqb), dim3(256), 0, s, lbq, nblk, m1, t2, growth, cuts, r1list, nq_dev);
+    }
+    const uint32_t n1 = (uint32_t)(nblk < m1 ? nblk : m1);
+    if (model) {
+        rc = model_descend(model, t, qq, nqb, n1 * kBlk, lnode, s);
+        if (rc != QD_OK) return rc;
+        hipLaunchKernelGGL(learned_start_kernel, dim3((nqb + 255) / 256), dim3(256), 0, s, lnode, nqb, t->d_begin,
+                           nblk, n1, r1list, cuts, donebits, nqp);
+    }
+    {
+        KernelTimer timer("tree_block_round1", s);
+        hipLaunchKernelGGL(round1_kernel, dim3((nqb + 3) / 4), dim3(256), 0, s, q4, nqb, k,
+                           reinterpret_cast<const uint4 *>(t->d_sorted), t->d_pop, t->d_perm, n, nblk, r1list, n1,
+                           cuts, qpop, top, ntop, thr, rec, frange, qround, ctr, want_stats ? qst : nullptr, nq_dev);
+    }
+    if (hipGetLastError() != hipSuccess) return fail(QD_ERR_DEVICE, "blocked search: launch failed");
+    // persistent matrix-core tiles: one workgroup per CU (the tile's LDS and
+    // registers leave room for one), a multiple of the 8 XCDs
+    const uint64_t eval_grid = mt::xcd_grid((uint64_t)device_cus());
+    const uint64_t short_grid = mt::xcd_grid((uint64_t)device_cus() * 8);
+    const int passes = graph ? kGraphPasses : kMaxPasses;
+    bool running = true;
+    uint32_t h[5] = {0, 0, 0, 1, 1};  // direct calls: running queries, counters (tiles, short pairs at 3, 4)
+    for (int pass = 0; pass < passes; pass++) {
+        {
+            KernelTimer timer("tree_block_lists", s);
+            const uint64_t waves = (nblk + kGroup - 1) / kGroup;
+            hipLaunchKernelGGL(active_kernel, dim3(1), dim3(1024), 0, s, rec, nqb, act, nact);
+            hipLaunchKernelGGL(list_kernel, dim3((uint32_t)((waves + 3) / 4)), dim3(256), 0, s, lbb, nblk, n, nqb,
+                               nqp, act, nact, rec, frange, donebits, list, cnt, want_stats ? qst : nullptr);
+            hipLaunchKernelGGL(tile_scan_kernel, dim3(1), dim3(1024), 0, s, cnt, nblk, t->d_bpop, off, voff, tinfo,
+                               ctr + 2);
+        }
+        if (!graph) {
+            // the host decides whether another pass is needed
+            hipError_t e = hipMemcpyAsync(h, nact, 4, hipMemcpyDeviceToHost, s);
+            if (e == hipSuccess) e = hipMemcpyAsync(h + 1, ctr, 16, hipMemcpyDeviceToHost, s);
+            if (e == hipSuccess) e = hipStreamSynchronize(s);
+            if (e != hipSuccess) return fail(QD_ERR_DEVICE, "blocked search: %s", hipGetErrorString(e));
+            if (h[0] == 0) {
+                running = false;
+                break;  // no query runs any more
+            }
+            profile_count("tree_block_tiles", h[3]);
+            profile_count("tree_block_short_pairs", h[4]);
+        }
+        if (h[3] > 0) {  // a direct call skips a launch it knows has no tiles
+            KernelTimer timer("tree_block_eval", s);
+            hipLaunchKernelGGL(eval_kernel, dim3((uint32_t)eval_grid), dim3(mt::kThreads), 0, s, q4,
+                               reinterpret_cast<const uint4 *>(t->d_sorted), n, nqp, ctr + 2, list, tinfo, t->d_pop,
+                               t->d_perm, qpop, thr, ccnt, cand);
+        }
+        if (h[4] > 0) {
+            KernelTimer timer("tree_block_eval_short", s);
+            hipLaunchKernelGGL(eval_short_kernel, dim3((uint32_t)short_grid), dim3(256), 0, s, q4,
+                               reinterpret_cast<const uint4 *>(t->d_sorted), n, nblk, nqp, list, cnt, voff, t->d_pop,
+                               t->d_perm, qpop, thr, ccnt, cand);
+        }
+        {
+            KernelTimer timer("tree_block_select", s);
+            hipLaunchKernelGGL(select_kernel, dim3(nqb), dim3(256), 0, s, k, qpop, cuts, rec, qround, ccnt, cand,
+                               top, ntop, thr, ctr, redo, want_stats ? qst : nullptr, lbq, nblk, donebits, dw, nqp,
+                               frange, r1list, model ? n1 : 0u);
+        }
+        if (hipGetLastError() != hipSuccess) return fail(QD_ERR_DEVICE, "blocked search: launch failed");
+    }
+    // queries still running after the last pass join the fallback
+    if (running)
+        hipLaunchKernelGGL(leftover_kernel, dim3((nqb + 255) / 256), dim3(256), 0, s, nqb, rec, ctr, redo);
+    hipLaunchKernelGGL(emit_kernel, dim3((nqb + 3) / 4), dim3(256), 0, s, qq, nqb, k, top, ntop, t->d_sorted,
+                       t->d_iperm, oi, om, ox, od, want_stats ? qst : nullptr, d_qstats, gst, nq_dev);
+    // The fallback: queries whose candidate buffer overflowed with a key that
+    // could not tighten (more rows tie at it than a buffer holds), searched
+    // one by one depth-first; their count (ctr[1]) stays on the device, so an
+    // empty fallback only costs launches that find no work.
+    uint4 *gq = reinterpret_cast<uint4 *>(ws + L.fbq);
+    uint32_t *ri = reinterpret_cast<uint32_t *>(ws + L.fbr);
+    int32_t *rm = reinterpret_cast<int32_t *>(ri + P * k), *rx = rm + P * k;
+    float *rd = reinterpret_cast<float *>(rx + P * k);
+    hipLaunchKernelGGL(gather_kernel, dim3((nqb * 32 + 255) / 256), dim3(256), 0, s, q4, redo, ctr + 1, gq);
+    rc = tree_launch(t, L.fb, ws + L.fbws, reinterpret_cast<const uint64_t *>(gq), nqb, ctr + 1, k,
+                     QD_ORDER_DEPTH_FIRST, nullptr, 0, ri, rm, rx, rd, nullptr, nullptr, 0, s);
+    if (rc != QD_OK) return rc;
+    const dim3 g((nqb * k + 255) / 256);
+    hipLaunchKernelGGL(scatter_kernel<uint32_t>, g, dim3(256), 0, s, ri, redo, ctr + 1, k, oi);
+    hipLaunchKernelGGL(scatter_kernel<int32_t>, g, dim3(256), 0, s, rm, redo, ctr + 1, k, om);
+    hipLaunchKernelGGL(scatter_kernel<int32_t>, g, dim3(256), 0, s, rx, redo, ctr + 1, k, ox);
+    hipLaunchKernelGGL(scatter_kernel<float>, g, dim3(256), 0, s, rd, redo, ctr + 1, k, od);
+    if (hipGetLastError() != hipSuccess) return fail(QD_ERR_DEVICE, "blocked search: fallback launch failed");
+    return QD_OK;
+}
+
+int knn_tree_blocked(qd_tree_t t, const uint64_t *d_q, uint32_t nq, uint32_t k, const qd_search_params *p,
+                     uint32_t *d_idx, int32_t *d_missed, int32_t *d_extra, float *d_dist, uint32_t *d_qstats,
+                     qd_stats *h_stats, hipStream_t s) {
+    int rc = blocked_check(t, p);
+    if (rc != QD_OK) return rc;
+    if (h_stats) *h_stats = qd_stats{0, 0, 0, 0};
+    const BlockedLayout L = blocked_layout(t, nq, k);
+    char *ws = nullptr;
+    QD_HIP_CHECK(hipMallocAsync((void **)&ws, L.bytes, s));
+    unsigned long long *gst = h_stats ? (unsigned long long *)(ws + L.gst) : nullptr;
+    if (gst) hipLaunchKernelGGL(zero_kernel, dim3(1), dim3(64), 0, s, (uint32_t *)gst, (uint64_t)8);
+    for (uint32_t qb0 = 0; qb0 < nq && rc == QD_OK; qb0 += L.qb) {
+        const uint32_t nqb = nq - qb0 < L.qb ? nq - qb0 : L.qb;
+        const uint64_t o = (uint64_t)qb0 * k;
+        rc = blocked_batch(t, L, ws, d_q + (uint64_t)qb0 * QD_WORDS, nqb, nullptr, k, p, d_idx + o, d_missed + o,
+                           d_extra + o, d_dist + o, d_qstats ? d_qstats + (uint64_t)qb0 * 4 : nullptr, gst, false, s);
+    }
+    if (rc == QD_OK && h_stats) {
         unsigned long long hs[4];
         hipError_t e = hipMemcpyAsync(hs, gst, sizeof hs, hipMemcpyDeviceToHost, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
-        if (e != hipSuccess) return done(fail(QD_ERR_DEVICE, "stats: %s", hipGetErrorString(e)));
-        *h_stats = qd_stats{hs[0], hs[1], hs[2], hs[3]};
+        if (e != hipSuccess) rc = fail(QD_ERR_DEVICE, "stats: %s", hipGetErrorString(e));
+        else *h_stats = qd_stats{hs[0], hs[1], hs[2], hs[3]};
     }
-    return done(QD_OK);
+    (void)hipFreeAsync(ws, s);
+    return rc;
+}
+
+int blocked_check(qd_tree_t t, const qd_search_params *p) {
+    if (!t->d_blk || t->n_blk == 0) return fail(QD_ERR_INVALID, "tree has no block images");
+    if (t->n_blk > 0x7FFFFFFFull) return fail(QD_ERR_UNSUPPORTED, "too many blocks");
+    const uint32_t m1 = p && p->round1_blocks ? p->round1_blocks : 16;
+    const uint32_t growth = p && p->round_growth ? p->round_growth : 4;
+    if (m1 > kM1) return fail(QD_ERR_INVALID, "round1_blocks=%u above %u", m1, kM1);
+    if (growth < 2 || growth > 64) return fail(QD_ERR_INVALID, "round_growth=%u outside 2..64", growth);
+    return QD_OK;
 }
 
 }  // namespace qd

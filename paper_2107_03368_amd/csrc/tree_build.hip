@@ -523,6 +523,7 @@ int tree_build_impl(const uint64_t *d_db, uint64_t n, const qd_build_params *par
     const bool want_and = params && params->store_and_image;
     const bool want_pop = !(params && params->plain_bound);
     if (max_leaf > kSmall) return fail(QD_ERR_INVALID, "max_leaf %u above %u", max_leaf, kSmall);
+    if (abort_requested()) return fail(QD_ERR_ABORTED, "tree build aborted");
     hipStream_t s = (hipStream_t)stream;
     const uint4 *db4 = reinterpret_cast<const uint4 *>(d_db);
 
@@ -551,6 +552,10 @@ int tree_build_impl(const uint64_t *d_db, uint64_t n, const qd_build_params *par
     uint32_t *pin = perm_a.p, *pout = perm_b.p;
     uint64_t lv0 = 0, lv1 = 1;
     while (lv0 < lv1) {
+        if (abort_requested()) {  // between levels: nothing of this level is queued yet
+            (void)hipStreamSynchronize(s);
+            return fail(QD_ERR_ABORTED, "tree build aborted");
+        }
         std::vector<uint32_t> small, big;
         for (uint64_t i = lv0; i < lv1; i++) {
             if (count[i] <= max_leaf) continue;
@@ -666,14 +671,37 @@ int tree_build_impl(const uint64_t *d_db, uint64_t n, const qd_build_params *par
     t->n = n;
     t->n_nodes = nn;
     t->max_leaf = max_leaf;
-    t->depth = (uint32_t)level_first.size() - 1;
     t->has_and = want_and;
+    if (hipMalloc((void **)&t->d_sorted, n * 512) != hipSuccess || hipMalloc((void **)&t->d_perm, n * 4) != hipSuccess) {
+        tree_release(t);
+        return fail(QD_ERR_OOM, "tree allocation failed");
+    }
+    if (hipMemcpyAsync(t->d_perm, pin, n * 4, hipMemcpyDeviceToDevice, s) != hipSuccess) {
+        tree_release(t);
+        return fail(QD_ERR_DEVICE, "tree upload failed");
+    }
+    {
+        uint64_t blocks = std::min<uint64_t>((n * 32 + kBlock - 1) / kBlock, (uint64_t)device_cus() * 64);
+        hipLaunchKernelGGL(gather_rows_kernel, dim3((uint32_t)blocks), dim3(kBlock), 0, s, db4, t->d_perm, n,
+                           reinterpret_cast<uint4 *>(t->d_sorted));
+    }
+    std::vector<uint32_t> hb32(nn);
+    for (uint64_t i = 0; i < nn; i++) hb32[i] = (uint32_t)begin[i];
+    const int rc = tree_finish(t, child, hb32, count, want_pop, s);
+    if (rc != QD_OK) return rc;  // tree_finish released t
+    *out = t;
+    return QD_OK;
+}
+
+int tree_finish(qd_tree_s *t, const std::vector<int32_t> &child, const std::vector<uint32_t> &begin,
+                const std::vector<uint32_t> &count, bool want_pop, hipStream_t s) {
+    const uint64_t n = t->n, nn = t->n_nodes;
+    const bool want_and = t->has_and;
     auto cleanup = [&](int code) {
         tree_release(t);
         return code;
     };
-    if (hipMalloc((void **)&t->d_sorted, n * 512) != hipSuccess || hipMalloc((void **)&t->d_perm, n * 4) != hipSuccess ||
-        hipMalloc((void **)&t->d_or, nn * 512) != hipSuccess || hipMalloc((void **)&t->d_child, nn * 8) != hipSuccess ||
+    if (hipMalloc((void **)&t->d_or, nn * 512) != hipSuccess || hipMalloc((void **)&t->d_child, nn * 8) != hipSuccess ||
         hipMalloc((void **)&t->d_begin, nn * 4) != hipSuccess || hipMalloc((void **)&t->d_count, nn * 4) != hipSuccess ||
         hipMalloc((void **)&t->d_pop, n * 2) != hipSuccess || hipMalloc((void **)&t->d_parent, nn * 4) != hipSuccess ||
         hipMalloc((void **)&t->d_depth, nn) != hipSuccess || hipMalloc((void **)&t->d_iperm, n * 4) != hipSuccess ||
@@ -681,41 +709,42 @@ int tree_build_impl(const uint64_t *d_db, uint64_t n, const qd_build_params *par
         (want_pop && (hipMalloc((void **)&t->d_pmin, nn * 2) != hipSuccess ||
                       hipMalloc((void **)&t->d_pmax, nn * 2) != hipSuccess)))
         return cleanup(fail(QD_ERR_OOM, "tree allocation failed"));
-    std::vector<uint32_t> hb32(nn);
-    uint32_t n_leaves = 0;
     std::vector<uint32_t> leaf_ids;
-    for (uint64_t i = 0; i < nn; i++) {
-        hb32[i] = (uint32_t)begin[i];
+    for (uint64_t i = 0; i < nn; i++)
         if (child[2 * i] < 0) leaf_ids.push_back((uint32_t)i);
-    }
-    n_leaves = (uint32_t)leaf_ids.size();
+    const uint32_t n_leaves = (uint32_t)leaf_ids.size();
     t->n_leaves = n_leaves;
+    // breadth-first numbering: a level's nodes are consecutive, children after parents
     std::vector<int32_t> parent(nn, -1);
+    std::vector<uint32_t> level(nn, 0);
     std::vector<uint8_t> depth(nn, 0);
     for (uint64_t i = 0; i < nn; i++)
         if (child[2 * i] >= 0) {
             parent[child[2 * i]] = parent[child[2 * i + 1]] = (int32_t)i;
-            depth[child[2 * i]] = depth[child[2 * i + 1]] = (uint8_t)std::min(255, depth[i] + 1);
+            level[child[2 * i]] = level[child[2 * i + 1]] = level[i] + 1;
         }
+    std::vector<uint32_t> level_first{0};
+    for (uint64_t i = 1; i < nn; i++)
+        if (level[i] != level[i - 1]) level_first.push_back((uint32_t)i);
+    level_first.push_back((uint32_t)nn);
+    t->depth = (uint32_t)level_first.size() - 1;
+    t->level_max.assign(t->depth, 0);
+    for (uint64_t i = 0; i < nn; i++) {
+        depth[i] = (uint8_t)std::min<uint32_t>(255, level[i]);
+        t->level_max[level[i]] = std::max(t->level_max[level[i]], count[i]);
+    }
     if (hipMemcpyAsync(t->d_parent, parent.data(), nn * 4, hipMemcpyHostToDevice, s) != hipSuccess ||
-        hipMemcpyAsync(t->d_depth, depth.data(), nn, hipMemcpyHostToDevice, s) != hipSuccess)
-        return cleanup(fail(QD_ERR_DEVICE, "tree upload failed"));
-    if (hipMemcpyAsync(t->d_perm, pin, n * 4, hipMemcpyDeviceToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(t->d_depth, depth.data(), nn, hipMemcpyHostToDevice, s) != hipSuccess ||
         hipMemcpyAsync(t->d_child, child.data(), nn * 8, hipMemcpyHostToDevice, s) != hipSuccess ||
-        hipMemcpyAsync(t->d_begin, hb32.data(), nn * 4, hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(t->d_begin, begin.data(), nn * 4, hipMemcpyHostToDevice, s) != hipSuccess ||
         hipMemcpyAsync(t->d_count, count.data(), nn * 4, hipMemcpyHostToDevice, s) != hipSuccess)
         return cleanup(fail(QD_ERR_DEVICE, "tree upload failed"));
-    {
-        uint64_t blocks = std::min<uint64_t>((n * 32 + kBlock - 1) / kBlock, (uint64_t)device_cus() * 64);
-        hipLaunchKernelGGL(gather_rows_kernel, dim3((uint32_t)blocks), dim3(kBlock), 0, s, db4, t->d_perm, n,
-                           reinterpret_cast<uint4 *>(t->d_sorted));
-    }
     DevBuf<uint32_t> lid;
     if (lid.alloc(std::max<uint64_t>(n_leaves, nn)) != hipSuccess) return cleanup(fail(QD_ERR_OOM, "alloc"));
     if (hipMemcpyAsync(lid.p, leaf_ids.data(), n_leaves * 4, hipMemcpyHostToDevice, s) != hipSuccess)
         return cleanup(fail(QD_ERR_DEVICE, "upload"));
     {
-        const int rc = qd_popcount_rows(t->d_sorted, n, t->d_pop, stream);  // leaf-order rows
+        const int rc = qd_popcount_rows(t->d_sorted, n, t->d_pop, s);  // leaf-order rows
         if (rc != QD_OK) return cleanup(rc);
     }
     hipLaunchKernelGGL(leaf_images_kernel, dim3((n_leaves + 3) / 4), dim3(kBlock), 0, s,
@@ -744,7 +773,6 @@ int tree_build_impl(const uint64_t *d_db, uint64_t n, const qd_build_params *par
     if (hipStreamSynchronize(s) != hipSuccess || hipGetLastError() != hipSuccess)
         return cleanup(fail(QD_ERR_DEVICE, "tree build kernels failed"));
     (void)hipGetDevice(&t->device);
-    *out = t;
     return QD_OK;
 }
 

@@ -490,10 +490,30 @@ extern "C" int qd_knn_tree(qd_tree_t t, const uint64_t *d_q, uint32_t nq, uint32
                            uint32_t *d_query_stats, qd_stats *h_stats, void *stream) {
     const int order = p ? (int)p->order : QD_ORDER_BEST_FIRST;
     const float *sc = p ? p->d_scores : nullptr;
-    const uint32_t ns = p ? p->n_scored : 0;
+    uint32_t ns = p ? p->n_scored : 0;
     const uint32_t wpc = p ? p->waves_per_cu : 0;
+    qd_model_t model = p ? p->model : nullptr;
     if (sc && order != QD_ORDER_DEPTH_FIRST)
         return qd::fail(QD_ERR_INVALID, "node scores order the depth-first frontier only");
+    if (model && order == QD_ORDER_BEST_FIRST)
+        return qd::fail(QD_ERR_INVALID, "a model orders the depth-first and blocked searches only");
+    if (model && sc) return qd::fail(QD_ERR_INVALID, "give node scores or a model, not both");
+    if (model && order == QD_ORDER_DEPTH_FIRST && t && nq > 0) {
+        // score the top nodes for every query, then search in that order
+        if (ns == 0) ns = (uint32_t)std::min<uint64_t>(2047, t->n_nodes);
+        if (ns > t->n_nodes) return qd::fail(QD_ERR_INVALID, "n_scored %u above the node count", ns);
+        if (k < 1 || k > QD_MAX_K) return qd::fail(QD_ERR_INVALID, "k=%u outside 1..%d", k, QD_MAX_K);
+        if (!d_q || !d_idx || !d_missed || !d_extra || !d_dist) return qd::fail(QD_ERR_INVALID, "null pointer");
+        hipStream_t s = (hipStream_t)stream;
+        float *scores = nullptr;
+        QD_HIP_CHECK(hipMallocAsync((void **)&scores, (size_t)nq * ns * sizeof(float), s));
+        int rc = qd_model_score_tree(model, t, d_q, nq, ns, scores, stream);
+        if (rc == QD_OK)
+            rc = qd::knn_tree_impl(t, d_q, nq, k, order, scores, ns, d_idx, d_missed, d_extra, d_dist, d_query_stats,
+                                   h_stats, stream, wpc, p->d_visited, p->n_traced);
+        (void)hipFreeAsync(scores, s);
+        return rc;
+    }
     if (order == QD_ORDER_BLOCKED && t && nq > 0) {
         if (k < 1 || k > QD_MAX_K) return qd::fail(QD_ERR_INVALID, "k=%u outside 1..%d", k, QD_MAX_K);
         if (!d_q || !d_idx || !d_missed || !d_extra || !d_dist) return qd::fail(QD_ERR_INVALID, "null pointer");

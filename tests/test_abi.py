@@ -121,3 +121,34 @@ def test_noalloc_argument_errors_without_device_work():
     # the lists of nq * k keys (one per query at the least) exceed the fixed scratch
     assert f(a, 100, a, 65_537, 64, a, a, a, a, None) == -1
     assert b"scratch" in lib.qd_last_error()
+
+
+def test_abort_flag_stops_synchronous_calls_before_device_work(tmp_path):
+    # a set flag stops the tree build before its first step (fake,
+    # never-dereferenced pointers: no device is touched), and the tree load
+    # after its host checks; a cleared flag lets the same call proceed to its
+    # argument checks and device work
+    import sys
+    sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+    from test_tree_file import GOOD, tree_file
+    lib = ctypes.CDLL(LIB)
+    lib.qd_last_error.restype = ctypes.c_char_p
+    P, U64 = ctypes.c_void_p, ctypes.c_uint64
+    flag = ctypes.c_int(1)
+    assert lib.qd_set_abort_flag(ctypes.byref(flag)) == 0
+    build = lib.qd_tree_build
+    build.argtypes = [P, U64, P, P, ctypes.POINTER(P)]
+    h = P()
+    try:
+        assert build(P(0x10000), 100, None, None, ctypes.byref(h)) == -5  # QD_ERR_ABORTED
+        assert b"aborted" in lib.qd_last_error()
+        assert build(None, 100, None, None, ctypes.byref(h)) == -1      # argument checks come first
+        path = tmp_path / "t.qdtree"
+        path.write_bytes(tree_file(**GOOD))
+        load = lib.qd_tree_load
+        load.argtypes = [ctypes.c_char_p, P, ctypes.POINTER(P)]
+        assert load(os.fsencode(str(path)), None, ctypes.byref(h)) == -5
+        flag.value = 0
+        assert load(os.fsencode(str(path)), None, ctypes.byref(h)) not in (-5, -6, -7)
+    finally:
+        lib.qd_set_abort_flag(None)

@@ -181,3 +181,61 @@ def test_trained_order_gain_over_bound_order(qd):
     print(f"nodes visited per query: bound order {n_plain:.0f}, learned order {n_learned:.0f}, "
           f"best-first {n_best:.0f}")
     assert n_best <= n_learned < n_plain
+
+
+def test_model_handle_orders_depth_first_as_explicit_scores(qd, setup):
+    # a model passed with the search scores the same nodes the caller would
+    # score with qd_model_score_tree: same results, same work per query
+    q, tree, *_ = setup
+    model = qd.Model(_t(_params(13)))
+    n = min(511, tree.n_nodes)
+    sc = qd.model_score_tree(model, tree, _t(q), n)
+    a = qd.knn_tree(tree, _t(q), 10, order=qd.ORDER_DEPTH_FIRST, scores=sc, query_stats=True)
+    b = qd.knn_tree(tree, _t(q), 10, order=qd.ORDER_DEPTH_FIRST, model=model, n_scored=n, query_stats=True)
+    for x, y in zip(a, b):
+        assert np.array_equal(x.cpu().numpy(), y.cpu().numpy())
+    with pytest.raises(qd.QDError):
+        qd.knn_tree(tree, _t(q), 10, model=model)  # best-first takes no model
+
+
+@pytest.fixture(scope="module")
+def blocked_case(qd):
+    # 60,123 rows (235 blocks, the last ragged), 600 queries: several rounds and tiles
+    db = synth.gen_db(60_123, 1101)
+    q, _ = synth.gen_queries(db, 600, 2101, 0.1, 0.6)
+    return db, q, qd.tree_build(_t(db))
+
+
+@pytest.mark.parametrize("k,schedule", [(1, (0, 0, 0)), (10, (0, 0, 0)), (10, (4, 0, 2)), (50, (64, 0, 2)),
+                                        (64, (1, 100_000, 2))])
+def test_learned_start_of_the_blocked_search_is_exact(qd, blocked_case, k, schedule):
+    # round 1 where the model leads (an untrained model: an arbitrary start);
+    # the last case overflows the candidate buffers in round 2, so queries
+    # repeat it with their round-1 blocks still marked done
+    db, q, tree = blocked_case
+    model = qd.Model(_t(_params(17)))
+    ref = oracle.knn_brute(db, q, k)
+    res = qd.knn_tree(tree, _t(q), k, order=qd.ORDER_BLOCKED, model=model, schedule=schedule, query_stats=True)
+    out = [x.cpu().numpy() for x in res]
+    assert np.array_equal(out[0].view(np.uint32), ref.idx)
+    assert np.array_equal(out[1], ref.missed) and np.array_equal(out[2], ref.extra)
+    assert np.array_equal(out[3], ref.dist)
+    plain = qd.knn_tree(tree, _t(q), k, order=qd.ORDER_BLOCKED, schedule=schedule, query_stats=True)
+    # the learned start changed the work of some queries (the path ran), not the results
+    assert (plain[4].cpu().numpy() != out[4]).any()
+
+
+def test_learned_start_with_the_per_query_fallback(qd):
+    # 30,000 copies of one row: round 2 overflows for good and the queries are
+    # searched again best-first, after a learned round 1
+    rng_db = synth.gen_db(4000, 75)
+    db = np.concatenate([rng_db, np.repeat(rng_db[:1], 30_000, axis=0)])
+    q = np.concatenate([rng_db[:3], synth.gen_queries(rng_db, 5, 76, 0.2, 0.5)[0]])
+    tree = qd.tree_build(_t(db))
+    model = qd.Model(_t(_params(19)))
+    for k in (1, 10):
+        ref = oracle.knn_brute(db, q, k)
+        out = [x.cpu().numpy() for x in qd.knn_tree(tree, _t(q), k, order=qd.ORDER_BLOCKED, model=model)]
+        assert np.array_equal(out[0].view(np.uint32), ref.idx)
+        assert np.array_equal(out[1], ref.missed) and np.array_equal(out[2], ref.extra)
+        assert np.array_equal(out[3], ref.dist)

@@ -99,24 +99,60 @@ def test_objects_workload_full_scale(qd):
     assert (rw == qobj).mean() >= 0.95  # the workload is retrievable
 
 
-@pytest.mark.parametrize("use_tree", [True, False])
-def test_plan_graph_replays_match_direct_retrieval(qd, use_tree):
+@pytest.mark.parametrize("path", ["best_first", "blocked", "sequential", "matrix_cores"])
+def test_plan_graph_replays_match_direct_retrieval(qd, path):
+    # the matrix-core scan needs >= 65,536 rows and >= 512 descriptors in the
+    # largest batch; the plan keeps it for the smaller batches too
     import torch
-    db, obj, off, q, qobj = _workload(40, 300, 24, 20, 120, 91)
+    n_obj = 280 if path == "matrix_cores" else 40
+    db, obj, off, q, qobj = _workload(n_obj, 250 if path == "matrix_cores" else 300, 24, 20, 120, 91)
+    assert path != "matrix_cores" or (len(db) >= 65_536 and len(q) >= 512)
+    use_tree = path in ("best_first", "blocked")
+    order = qd.ORDER_BLOCKED if path == "blocked" else qd.ORDER_BEST_FIRST
     tree = qd.tree_build(_t(db)) if use_tree else None
     dbt = None if use_tree else _t(db)
-    plan = qd.Plan(_t(obj), 40, max_qdesc=len(q), max_qobj=24, k=5, threshold=10, tree=tree, db=dbt)
+    plan = qd.Plan(_t(obj), n_obj, max_qdesc=len(q), max_qobj=24, k=5, threshold=10, tree=tree, db=dbt, order=order,
+                   query_tile=16 if path == "sequential" else 0)
     # batches of different sizes, with eager library work between the replays
     for lo, hi in ((0, 24), (3, 10), (0, 1), (5, 24)):
         sub = np.asarray(off[lo:hi + 1], np.uint64) - off[lo]
         qs = q[int(off[lo]):int(off[hi])]
         got = plan.run(_t(qs), _t(sub))
-        ref = qd.retrieve_objects(_t(qs), _t(sub), _t(obj), 40, 5, 10, tree=tree, db=dbt)
+        ref = qd.retrieve_objects(_t(qs), _t(sub), _t(obj), n_obj, 5, 10, tree=tree, db=dbt, order=order)
         torch.cuda.synchronize()
         for a, b in zip(got, ref):
             assert torch.equal(a, b)
-        rv, rw, ru = oracle.votes(oracle.knn_brute(db, qs, 5).idx, obj, 40, sub, 10)
+        rv, rw, ru = oracle.votes(oracle.knn_brute(db, qs, 5).idx, obj, n_obj, sub, 10)
+        assert np.array_equal(got[0].cpu().numpy().view(np.uint32), rv)
         assert np.array_equal(got[1].cpu().numpy(), rw)
+        assert np.array_equal(got[2].cpu().numpy().view(np.uint32), ru)
+
+
+def test_blocked_plan_with_several_batches(qd):
+    # more descriptors than one blocked batch holds (16,384): the plan records
+    # two batches, each reading its size from the device; replays of shrinking
+    # batches (the second batch empty, then a tiny one) with eager work between
+    import torch
+    n_obj, per = 25, 200
+    db = synth.gen_db(n_obj * per, 97)
+    obj = (np.arange(n_obj * per) // per).astype(np.uint16)
+    q, _ = synth.gen_queries(db, 20_000, 98, 0.1, 0.6)
+    tree = qd.tree_build(_t(db))
+    plan = qd.Plan(_t(obj), n_obj, max_qdesc=20_000, max_qobj=4, k=10, threshold=10, tree=tree,
+                   order=qd.ORDER_BLOCKED)
+    for nd in (20_000, 16_384, 9, 17_001):
+        off = np.array([0, nd // 3, nd // 2, nd], np.uint64)
+        got = plan.run(_t(q[:nd]), _t(off))
+        ref = qd.retrieve_objects(_t(q[:nd]), _t(off), _t(obj), n_obj, 10, 10, tree=tree, order=qd.ORDER_BLOCKED,
+                                  return_nn=True)
+        torch.cuda.synchronize()
+        for a, b in zip(got, ref[:3]):
+            assert torch.equal(a, b)
+        nn = ref[3].cpu().numpy().view(np.uint32)
+        rows = np.array([0, nd // 2, nd - 1])
+        assert np.array_equal(nn[rows], oracle.knn_brute(db, q[rows], 10).idx)
+        rv, rw, ru = oracle.votes(nn, obj, n_obj, off, 10)
+        assert np.array_equal(got[0].cpu().numpy().view(np.uint32), rv)
 
 
 def test_autotuner_returns_a_timed_exact_configuration(qd):
@@ -129,7 +165,10 @@ def test_autotuner_returns_a_timed_exact_configuration(qd):
         assert len(cands) >= 3 and all(c["ms"] > 0 for c in cands)
         assert best["ms"] == min(c["ms"] for c in cands)
         if "tree" in kw:
-            res = qd.knn_tree(tree, _t(q), 10, order=best["order"], waves_per_cu=best["waves_per_cu"])
+            assert any(c["order"] == qd.ORDER_BLOCKED for c in cands)  # the round schedules were timed
+            assert len({c["schedule"] for c in cands if c["order"] == qd.ORDER_BLOCKED}) >= 5
+            res = qd.knn_tree(tree, _t(q), 10, order=best["order"], waves_per_cu=best["waves_per_cu"],
+                              schedule=best["schedule"])
         else:
             res = qd.knn_bruteforce(_t(db), _t(q), 10, query_tile=best["query_tile"])
         assert np.array_equal(res[0].cpu().numpy().view(np.uint32)[:4], ref.idx)
