@@ -85,7 +85,9 @@ def main():
                     help="brute, tree (best-first, depth-first, blocked), blocked (blocked only), learned")
     ap.add_argument("--max-batch", type=int, default=0, help="stream50m: descriptors per batch (0 = workload's)")
     ap.add_argument("--pmc-run", action="store_true",
-                    help="only a 1 GiB device copy (counter calibration) and one sequential-search batch")
+                    help="only a 1 GiB device copy (counter calibration) and one batch of each --pmc-paths path")
+    ap.add_argument("--pmc-paths", default="brute,blocked",
+                    help="--pmc-run: brute, blocked, best_first, depth_first")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU; --gpus must be 1"}))
@@ -113,9 +115,14 @@ def main():
         q, _ = synth.gen_queries(db, w["nq"], w["seed_q"], w["pmin"], w["pmax"])
         dbt = torch.from_numpy(db.view(np.int64)).to(dev)
         qt = torch.from_numpy(q.view(np.int64)).to(dev)
-        qd.knn_bruteforce(dbt, qt, w["k"])
+        pp = args.pmc_paths.split(",")
+        if "brute" in pp:
+            qd.knn_bruteforce(dbt, qt, w["k"])
         tree = qd.tree_build(dbt)
-        qd.knn_tree(tree, qt, w["k"], order=qd.ORDER_BLOCKED)
+        for name, order in (("blocked", qd.ORDER_BLOCKED), ("best_first", qd.ORDER_BEST_FIRST),
+                            ("depth_first", qd.ORDER_DEPTH_FIRST)):
+            if name in pp:
+                qd.knn_tree(tree, qt, w["k"], order=order)
         torch.cuda.synchronize()
         log("pmc run done")
         return
@@ -145,9 +152,11 @@ def main():
         if "tree" in wanted:
             paths["tree"] = lambda: qd.knn_tree(tree, qt, k)
             paths["tree_dfs"] = lambda: qd.knn_tree(tree, qt, k, order=qd.ORDER_DEPTH_FIRST)
+        if "tree" in wanted or "blocked" in wanted:
             paths["tree_blocked"] = lambda: qd.knn_tree(tree, qt, k, order=qd.ORDER_BLOCKED)
-        elif "blocked" in wanted:
-            paths["tree_blocked"] = lambda: qd.knn_tree(tree, qt, k, order=qd.ORDER_BLOCKED)
+            # round 1 at the consecutive blocks the bound's descent reaches
+            paths["tree_blocked_descent"] = lambda: qd.knn_tree(tree, qt, k, order=qd.ORDER_BLOCKED,
+                                                                start=qd.START_BOUND_DESCENT)
         if "learned" in wanted:
             # offline: train the frontier-order model on traces of the exact search over
             # the 1M-descriptor database (seed 1001) with its own queries
@@ -196,7 +205,8 @@ def main():
         dt = (time.perf_counter() - t0) / args.steps
         kernels = {}
         for kname in ("wh_scan_mfma", "wh_scan_mfma_sample", "wh_scan_topk", "topk_merge", "topk_select",
-                      "topk_select_sample", "tree_knn", "mlp_features", "mlp_forward", "tree_block_bounds",
+                      "topk_select_sample", "tree_knn", "mlp_features", "mlp_forward", "tree_block_descend",
+                      "tree_block_bounds",
                       "tree_block_plan", "tree_block_round1", "tree_block_lists", "tree_block_eval", "tree_block_eval_short",
                       "tree_block_select"):
             ms, cnt = qd.profile_read(kname)
@@ -210,6 +220,7 @@ def main():
         if name.startswith("tree"):
             kw = {"tree": {}, "tree_dfs": dict(order=qd.ORDER_DEPTH_FIRST),
                   "tree_blocked": dict(order=qd.ORDER_BLOCKED),
+                  "tree_blocked_descent": dict(order=qd.ORDER_BLOCKED, start=qd.START_BOUND_DESCENT),
                   "tree_learned": dict(order=qd.ORDER_DEPTH_FIRST, model=model, n_scored=N_SCORED),
                   "tree_blocked_learned": dict(order=qd.ORDER_BLOCKED, model=model)}[name]
             res = qd.knn_tree(tree, qt, k, totals=True, query_stats=True, **kw)
@@ -318,11 +329,11 @@ def main():
                 "unit": "TOP/s (32-bit integer lane ops)", "frac": achieved / VALU_PEAK_TOPS, "traffic": None,
                 "avg_ms": ms}
 
-    def blocked_roofline():
+    def blocked_roofline(name):
         # eval_kernel: the (query, row) pairs of the matrix-core tiles (all evaluated
         # rows minus round 1's and the short lists', which run on the vector ALUs),
         # 2 flop per bit pair
-        pb = per_path["tree_blocked"]
+        pb = per_path[name]
         ev = pb["kernels"]["tree_block_eval"]
         launches_per_call = ev["launches"] / args.steps
         rows_r1 = min(16, (n + 255) // 256) * 256
@@ -338,7 +349,7 @@ def main():
                 "launches_per_call": launches_per_call, "tiles_per_call": tiles, "tile_fill": fill}
 
     roofline_scan = scan_roofline()
-    roofline = blocked_roofline() if best == "tree_blocked" else roofline_scan
+    roofline = blocked_roofline(best) if best.startswith("tree_blocked") else roofline_scan
     if TRAFFIC_DETAIL:
         roofline["traffic_detail"] = TRAFFIC_DETAIL.get(roofline["kernel"])
 
@@ -489,7 +500,7 @@ def objects_main(args, w, dev):
     tune_s = time.perf_counter() - t0
     log(f"autotuned in {tune_s:.1f}s: tree {tuned_tree}, sequential {tuned_seq}")
     plan_tree = qd.Plan(objt, n_obj, max_qdesc=len(rows), max_qobj=w["n_qo"], k=k, threshold=thr, tree=tree,
-                        order=qd.ORDER_BLOCKED, schedule=tuned_tree["schedule"])
+                        order=qd.ORDER_BLOCKED, schedule=tuned_tree["schedule"], start=tuned_tree["start"])
     plan_seq = qd.Plan(objt, n_obj, max_qdesc=len(rows), max_qobj=w["n_qo"], k=k, threshold=thr, db=dbt,
                        query_tile=tuned_seq["query_tile"])
     runs = {
@@ -671,7 +682,7 @@ def stream_main(args, w, dev):
     log(f"autotuned blocked schedule {tuned['schedule']} in {tune_s:.1f}s")
     max_objs = w["n_qo"]
     plan_tree = qd.Plan(objt, w["n_obj"], max_qdesc=max_batch, max_qobj=max_objs, k=k, threshold=10, tree=tree,
-                        order=qd.ORDER_BLOCKED, schedule=tuned["schedule"])
+                        order=qd.ORDER_BLOCKED, schedule=tuned["schedule"], start=tuned["start"])
     plan_seq = qd.Plan(objt, w["n_obj"], max_qdesc=max_batch, max_qobj=max_objs, k=k, threshold=10, db=dbt)
 
     def plan_path(plan):

@@ -295,7 +295,16 @@ typedef struct {
        follow in the bound-ordered rounds.  Results are identical with and
        without a model. */
     qd_model_t model;
+    /* QD_ORDER_BLOCKED without a model: where round 1 starts.
+       QD_START_LOWEST_BOUND (0): the round1_blocks blocks of lowest bound.
+       QD_START_BOUND_DESCENT: the round1_blocks consecutive blocks that begin
+       with the first block of the node reached from the root by entering, at
+       every inner node above round1_blocks x 256 rows, the child of lower
+       bound (ties: the similar child); the other blocks follow in the
+       bound-ordered rounds, as with a model.  Results are identical. */
+    uint32_t round1_start;
 } qd_search_params;
+enum { QD_START_LOWEST_BOUND = 0, QD_START_BOUND_DESCENT = 1 };
 
 typedef struct {
     uint64_t nodes_visited, leaves_visited, bounds_evaluated, dists_evaluated;
@@ -486,7 +495,8 @@ int qd_plan_free(qd_plan_t p);
  * Autotuner: times every launch configuration of a k-NN batch (tree t:
  * best-first and depth-first x waves per CU, and the blocked order x round
  * schedules -- round-1 blocks 8, 16, 32, growth 2, 4, 8, round-2 coverage
- * half, default and double; sequential search: automatic path and query
+ * half, default and double, round 1 at the lowest bounds or at the bound's
+ * descent; sequential search: automatic path and query
  * tiles 4, 8, 16) over `reps` runs after one warm-up on the caller's sample
  * batch, and returns the fastest in *best (every configuration returns the
  * same exact result).  With `all`, every candidate's timing is written too.
@@ -502,6 +512,7 @@ typedef struct {
     uint32_t query_tile;   /* sequential: query tile (0 = automatic, matrix cores for large batches) */
     float ms;              /* mean time of one batch */
     uint32_t round1_blocks, round2_blocks, round_growth; /* blocked order: qd_search_params' schedule */
+    uint32_t round1_start; /* blocked order: qd_search_params.round1_start */
 } qd_tuning;
 
 /* order_mask (tree only): the frontier orders to time, bit (1 << order) for

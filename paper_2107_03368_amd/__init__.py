@@ -168,7 +168,7 @@ class _SearchParams(ctypes.Structure):
     _fields_ = [("order", ctypes.c_int), ("d_scores", ctypes.c_void_p), ("n_scored", ctypes.c_uint32),
                 ("waves_per_cu", ctypes.c_uint32), ("d_visited", ctypes.c_void_p), ("n_traced", ctypes.c_uint32),
                 ("round1_blocks", ctypes.c_uint32), ("round2_blocks", ctypes.c_uint32),
-                ("round_growth", ctypes.c_uint32), ("model", ctypes.c_void_p)]
+                ("round_growth", ctypes.c_uint32), ("model", ctypes.c_void_p), ("round1_start", ctypes.c_uint32)]
 
 
 class Stats(ctypes.Structure):
@@ -258,8 +258,12 @@ def tree_build(db, max_leaf=32, store_and_image=False, plain_bound=False):
     return Tree(h.value)
 
 
+START_LOWEST_BOUND = 0
+START_BOUND_DESCENT = 1
+
+
 def knn_tree(tree, q, k, order=ORDER_BEST_FIRST, scores=None, query_stats=False, totals=False, waves_per_cu=0,
-             schedule=(0, 0, 0), model=None, n_scored=0):
+             schedule=(0, 0, 0), model=None, n_scored=0, start=START_LOWEST_BOUND):
     """Exact k-NN through the tree.  Returns (idx, missed, extra, dist[, qstats][, totals]).
     schedule: (round-1 blocks, round-2 blocks, growth) of the blocked order, 0 = default.
     model: a Model that orders the depth-first search (scoring nodes below n_scored,
@@ -269,6 +273,7 @@ def knn_tree(tree, q, k, order=ORDER_BEST_FIRST, scores=None, query_stats=False,
     idx, missed, extra, dist = _results(nq, k, q.device)
     qs = torch.empty((nq, 4), dtype=torch.int32, device=q.device) if query_stats else None
     prm = _SearchParams(order, None, n_scored, waves_per_cu, None, 0, *schedule)
+    prm.round1_start = start
     if model is not None:
         prm.model = model.handle.value
     if scores is not None:
@@ -560,12 +565,13 @@ def model_train(model, tree, q, k, n_traced, epochs, batch_queries, lr, batch_or
 class _Tuning(ctypes.Structure):
     _fields_ = [("path", ctypes.c_int), ("order", ctypes.c_int), ("waves_per_cu", ctypes.c_uint32),
                 ("query_tile", ctypes.c_uint32), ("ms", ctypes.c_float), ("round1_blocks", ctypes.c_uint32),
-                ("round2_blocks", ctypes.c_uint32), ("round_growth", ctypes.c_uint32)]
+                ("round2_blocks", ctypes.c_uint32), ("round_growth", ctypes.c_uint32),
+                ("round1_start", ctypes.c_uint32)]
 
     def as_dict(self):
         return {"path": "tree" if self.path else "sequential", "order": self.order,
                 "waves_per_cu": self.waves_per_cu, "query_tile": self.query_tile, "ms": self.ms,
-                "schedule": (self.round1_blocks, self.round2_blocks, self.round_growth)}
+                "schedule": (self.round1_blocks, self.round2_blocks, self.round_growth), "start": self.round1_start}
 
 
 _sig("qd_plan_create", [_P, _P, _U64, _P, _U32, _U64, _U32, _U32, _U32, ctypes.POINTER(_SearchParams), _U32,
@@ -581,11 +587,12 @@ class Plan:
     recorded in a hipGraph and replayed per run."""
 
     def __init__(self, obj_of, n_obj, max_qdesc, max_qobj, k, threshold=10, tree=None, db=None,
-                 order=ORDER_BEST_FIRST, waves_per_cu=0, query_tile=0, schedule=(0, 0, 0)):
+                 order=ORDER_BEST_FIRST, waves_per_cu=0, query_tile=0, schedule=(0, 0, 0), start=START_LOWEST_BOUND):
         if tree is None:
             _desc(db, "db")
         self._keep = (tree, db, obj_of)  # the plan points into these
         prm = _SearchParams(order, None, 0, waves_per_cu, None, 0, *schedule)
+        prm.round1_start = start
         h = ctypes.c_void_p()
         _check(_lib.qd_plan_create(tree.handle if tree is not None else None, _ptr(db),
                                    0 if db is None else db.shape[0], _ptr(obj_of), n_obj, max_qdesc, max_qobj, k,

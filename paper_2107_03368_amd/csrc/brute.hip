@@ -63,13 +63,23 @@ __global__ __launch_bounds__(kBlock) void scan_topk_kernel(const uint4 *__restri
         thr[t] = qi < nq ? KEY_NONE : 0;  // padding queries never insert
     }
 
+    // rows of the next step are loaded before this step's work, so a wave
+    // always has a step's loads in flight while it counts
+    uint4 tn[4];
+    {
+        const uint64_t row = r0 + g;
+#pragma unroll
+        for (int i = 0; i < 4; i++) tn[i] = row < r1 ? db[row * 32 + j + 8 * i] : make_uint4(0, 0, 0, 0);
+    }
     for (uint64_t base = r0; base < r1; base += kRowsPerStep) {
         const uint64_t row = base + g;
         const bool valid = row < r1;
         uint4 tv[4];
-        const uint4 *src = db + row * 32 + j;
 #pragma unroll
-        for (int i = 0; i < 4; i++) tv[i] = valid ? src[8 * i] : make_uint4(0, 0, 0, 0);
+        for (int i = 0; i < 4; i++) tv[i] = tn[i];
+        const uint64_t nrow = row + kRowsPerStep;
+#pragma unroll
+        for (int i = 0; i < 4; i++) tn[i] = nrow < r1 ? db[nrow * 32 + j + 8 * i] : make_uint4(0, 0, 0, 0);
         const uint32_t tp = sum8(popc4(tv[0]) + popc4(tv[1]) + popc4(tv[2]) + popc4(tv[3]));
 #pragma unroll
         for (int t = 0; t < QT; t++) {

@@ -256,7 +256,7 @@ std::map<TuneKey, qd_tuning> g_tune;
 bool g_tune_loaded = false;
 
 // Optional file cache: one line per entry,
-// "dev n nodes nq k mask path order wpc qt ms round1 round2 growth".
+// "dev n nodes nq k mask path order wpc qt ms round1 round2 growth start".
 void tune_load() {
     if (g_tune_loaded) return;
     g_tune_loaded = true;
@@ -266,11 +266,11 @@ void tune_load() {
     if (!fp) return;
     int dev, path, order;
     unsigned long long n, nodes;
-    unsigned nq, k, mask, wpc, qt, r1, r2, gr;
+    unsigned nq, k, mask, wpc, qt, r1, r2, gr, st;
     float ms;
-    while (fscanf(fp, "%d %llu %llu %u %u %u %d %d %u %u %f %u %u %u", &dev, &n, &nodes, &nq, &k, &mask, &path,
-                  &order, &wpc, &qt, &ms, &r1, &r2, &gr) == 14) {
-        qd_tuning t{path, (qd_order)order, wpc, qt, ms, r1, r2, gr};
+    while (fscanf(fp, "%d %llu %llu %u %u %u %d %d %u %u %f %u %u %u %u", &dev, &n, &nodes, &nq, &k, &mask, &path,
+                  &order, &wpc, &qt, &ms, &r1, &r2, &gr, &st) == 15) {
+        qd_tuning t{path, (qd_order)order, wpc, qt, ms, r1, r2, gr, st};
         g_tune[TuneKey{dev, n, nodes, nq, k, mask}] = t;
     }
     fclose(fp);
@@ -282,10 +282,10 @@ void tune_store(const TuneKey &key, const qd_tuning &t) {
     if (!f) return;
     FILE *fp = fopen(f, "a");
     if (!fp) return;
-    fprintf(fp, "%d %llu %llu %u %u %u %d %d %u %u %.6f %u %u %u\n", std::get<0>(key),
+    fprintf(fp, "%d %llu %llu %u %u %u %d %d %u %u %.6f %u %u %u %u\n", std::get<0>(key),
             (unsigned long long)std::get<1>(key), (unsigned long long)std::get<2>(key), std::get<3>(key),
             std::get<4>(key), std::get<5>(key), t.path, (int)t.order, t.waves_per_cu, t.query_tile, t.ms,
-            t.round1_blocks, t.round2_blocks, t.round_growth);
+            t.round1_blocks, t.round2_blocks, t.round_growth, t.round1_start);
     fclose(fp);
 }
 }  // namespace
@@ -321,19 +321,19 @@ extern "C" int qd_autotune(qd_tree_t t, const uint64_t *d_db, uint64_t n, const 
             for (uint32_t wpc : {4u, 8u, 16u, 32u}) {
                 if (!(mask & (1u << order))) continue;
                 if (order == QD_ORDER_BEST_FIRST && wpc > 8) continue;  // LDS holds 8 best-first waves per CU
-                cand.push_back({1, (qd_order)order, wpc, 0, 0.f, 0, 0, 0});
+                cand.push_back({1, (qd_order)order, wpc, 0, 0.f, 0, 0, 0, 0});
             }
         // the blocked order's round schedule around its default (16 blocks in
         // round 1, round 2 at ~128 queries per block list, growth 4)
         const uint64_t t2 = std::max<uint64_t>(32, (128 * t->n_blk + nq - 1) / nq);
         const uint32_t half = (uint32_t)std::min<uint64_t>(t2 / 2, 0xFFFFFFFFull);
         const uint32_t dbl = (uint32_t)std::min<uint64_t>(t2 * 2, 0xFFFFFFFFull);
-        const uint32_t sched[][3] = {{16, 0, 4}, {8, 0, 4}, {32, 0, 4}, {16, 0, 2},
-                                     {16, 0, 8}, {16, half, 4}, {16, dbl, 4}};
+        const uint32_t sched[][4] = {{16, 0, 4, 0}, {8, 0, 4, 0}, {32, 0, 4, 0}, {16, 0, 2, 0}, {16, 0, 8, 0},
+                                     {16, half, 4, 0}, {16, dbl, 4, 0}, {16, 0, 4, 1}, {8, 0, 4, 1}};
         if (mask & (1u << QD_ORDER_BLOCKED))
-            for (auto &sc : sched) cand.push_back({1, QD_ORDER_BLOCKED, 0, 0, 0.f, sc[0], sc[1], sc[2]});
+            for (auto &sc : sched) cand.push_back({1, QD_ORDER_BLOCKED, 0, 0, 0.f, sc[0], sc[1], sc[2], sc[3]});
     } else {
-        for (uint32_t qt : {0u, 4u, 8u, 16u}) cand.push_back({0, QD_ORDER_BEST_FIRST, 0, qt, 0.f, 0, 0, 0});
+        for (uint32_t qt : {0u, 4u, 8u, 16u}) cand.push_back({0, QD_ORDER_BEST_FIRST, 0, qt, 0.f, 0, 0, 0, 0});
     }
     char *ws = nullptr;
     const size_t m = (size_t)nq * k;
@@ -357,6 +357,7 @@ extern "C" int qd_autotune(qd_tree_t t, const uint64_t *d_db, uint64_t n, const 
                 sp.round1_blocks = c.round1_blocks;
                 sp.round2_blocks = c.round2_blocks;
                 sp.round_growth = c.round_growth;
+                sp.round1_start = c.round1_start;
                 return knn_tree_blocked(t, d_q, nq, k, &sp, idx, mi, ex, di, nullptr, nullptr, s);
             }
             return c.path ? knn_tree_impl(t, d_q, nq, k, (int)c.order, nullptr, 0, idx, mi, ex, di, nullptr, nullptr,

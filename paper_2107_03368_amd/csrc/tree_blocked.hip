@@ -458,8 +458,52 @@ __global__ __launch_bounds__(256) void round1_kernel(const uint4 *__restrict__ q
     }
 }
 
-// Learned start: round 1 takes the n1 consecutive blocks of the leaf order
-// that begin with the first block of the node the model's descent reached
+// Bound-led start: from the root, enter at every inner node holding more than
+// max_rows rows the child with the lower bound (the node bound of Section
+// 4.2 with the popcount range when stored; ties: the similar child), as the
+// depth-first traversal's first descent does.  One wave per query, a
+// half-wave per child (its 32 image chunks).
+__global__ __launch_bounds__(256) void bound_descend_kernel(const uint4 *__restrict__ q, uint32_t nqb,
+                                                            const uint16_t *__restrict__ qpop,
+                                                            const uint4 *__restrict__ orimg,
+                                                            const int32_t *__restrict__ child,
+                                                            const uint32_t *__restrict__ count,
+                                                            const uint16_t *__restrict__ pmin,
+                                                            const uint16_t *__restrict__ pmax, uint32_t max_rows,
+                                                            uint32_t *__restrict__ node_out,
+                                                            const uint32_t *__restrict__ nq_dev) {
+    const int lane = lane_id();
+    const uint32_t qi = readfirst(blockIdx.x * 4 + (threadIdx.x >> 6));
+    if (qi >= nqb || (nq_dev && qi >= *nq_dev)) return;
+    const uint4 qn = q[(uint64_t)qi * 32 + (lane & 31)];
+    const uint32_t pq = readfirst(qpop[qi]);
+    const uint32_t wa = weight_a(pq), wb = weight_b(pq);
+    uint32_t node = 0;
+    for (;;) {
+        const int32_t c0 = child[2 * (uint64_t)node];
+        if (c0 < 0 || count[node] <= max_rows) break;
+        const int32_t c1 = child[2 * (uint64_t)node + 1];
+        const int32_t c = lane < 32 ? c0 : c1;
+        const uint4 o = orimg[(uint64_t)c * 32 + (lane & 31)];
+        uint32_t ov = popc_and4(qn, o);
+#pragma unroll
+        for (int sh = 1; sh < 32; sh <<= 1) ov += (uint32_t)__shfl_xor((int)ov, sh);
+        uint32_t al = pq - ov, bl = 0;
+        if (pmin) {
+            const uint32_t lo = pmin[c], hi = pmax[c];
+            al = pq - (ov < hi ? ov : hi);
+            bl = lo > ov ? lo - ov : 0;
+        }
+        const uint32_t kb = al * wb + bl * wa;
+        const uint32_t k0 = readlane(kb, 0), k1 = readlane(kb, 32);
+        node = readfirst((uint32_t)(k1 < k0 ? c1 : c0));
+    }
+    if (lane == 0) node_out[qi] = node;
+}
+
+// Start at a descent's node (the model's or the bound's): round 1 takes the
+// n1 consecutive blocks of the leaf order that begin with the first block of
+// the node the descent reached
 // (moved back so they stay inside the rows).  Those pairs are marked done, and
 // round 2's range starts at the lowest key (cuts[1] = 0), so every other block
 // is still covered by the bound-ordered rounds and no block is evaluated twice.
@@ -467,9 +511,9 @@ __global__ __launch_bounds__(256) void round1_kernel(const uint4 *__restrict__ q
 __global__ void learned_start_kernel(const uint32_t *__restrict__ node, uint32_t nqb,
                                      const uint32_t *__restrict__ begin, uint64_t nblk, uint32_t n1,
                                      uint32_t *__restrict__ r1list, u64 *__restrict__ cuts, uint32_t *__restrict__ done,
-                                     uint32_t nqp) {
+                                     uint32_t nqp, const uint32_t *__restrict__ nq_dev) {
     const uint32_t qi = blockIdx.x * blockDim.x + threadIdx.x;
-    if (qi >= nqb) return;
+    if (qi >= nqb || (nq_dev && qi >= *nq_dev)) return;
     uint64_t b0 = begin[node[qi]] / kBlk;
     if (b0 + n1 > nblk) b0 = nblk - n1;
     for (uint32_t i = 0; i < n1; i++) {
@@ -1298,12 +1342,21 @@ int blocked_batch(qd_tree_t t, const BlockedLayout &L, char *ws, const uint64_t 
         hipLaunchKernelGGL(plan_kernel, dim3(nqb), dim3(256), 0, s, lbq, nblk, m1, t2, growth, cuts, r1list, nq_dev);
     }
     const uint32_t n1 = (uint32_t)(nblk < m1 ? nblk : m1);
+    // round 1 at consecutive blocks where a descent from the root leads: the
+    // model's (learned order) or the bound's
+    const bool descend = model || (p && p->round1_start == QD_START_BOUND_DESCENT);
     if (model) {
         rc = model_descend(model, t, qq, nqb, n1 * kBlk, lnode, s);
         if (rc != QD_OK) return rc;
-        hipLaunchKernelGGL(learned_start_kernel, dim3((nqb + 255) / 256), dim3(256), 0, s, lnode, nqb, t->d_begin,
-                           nblk, n1, r1list, cuts, donebits, nqp);
+    } else if (descend) {
+        KernelTimer timer("tree_block_descend", s);
+        hipLaunchKernelGGL(bound_descend_kernel, dim3((nqb + 3) / 4), dim3(256), 0, s, q4, nqb, qpop,
+                           reinterpret_cast<const uint4 *>(t->d_or), t->d_child, t->d_count, t->d_pmin, t->d_pmax,
+                           n1 * kBlk, lnode, nq_dev);
     }
+    if (descend)
+        hipLaunchKernelGGL(learned_start_kernel, dim3((nqb + 255) / 256), dim3(256), 0, s, lnode, nqb, t->d_begin,
+                           nblk, n1, r1list, cuts, donebits, nqp, nq_dev);
     {
         KernelTimer timer("tree_block_round1", s);
         hipLaunchKernelGGL(round1_kernel, dim3((nqb + 3) / 4), dim3(256), 0, s, q4, nqb, k,
@@ -1357,7 +1410,7 @@ int blocked_batch(qd_tree_t t, const BlockedLayout &L, char *ws, const uint64_t 
             KernelTimer timer("tree_block_select", s);
             hipLaunchKernelGGL(select_kernel, dim3(nqb), dim3(256), 0, s, k, qpop, cuts, rec, qround, ccnt, cand,
                                top, ntop, thr, ctr, redo, want_stats ? qst : nullptr, lbq, nblk, donebits, dw, nqp,
-                               frange, r1list, model ? n1 : 0u);
+                               frange, r1list, descend ? n1 : 0u);
         }
         if (hipGetLastError() != hipSuccess) return fail(QD_ERR_DEVICE, "blocked search: launch failed");
     }
@@ -1422,6 +1475,8 @@ int blocked_check(qd_tree_t t, const qd_search_params *p) {
     const uint32_t growth = p && p->round_growth ? p->round_growth : 4;
     if (m1 > kM1) return fail(QD_ERR_INVALID, "round1_blocks=%u above %u", m1, kM1);
     if (growth < 2 || growth > 64) return fail(QD_ERR_INVALID, "round_growth=%u outside 2..64", growth);
+    if (p && p->round1_start > QD_START_BOUND_DESCENT)
+        return fail(QD_ERR_INVALID, "round1_start=%u unknown", p->round1_start);
     return QD_OK;
 }
 

@@ -128,7 +128,8 @@ def test_plan_graph_replays_match_direct_retrieval(qd, path):
         assert np.array_equal(got[2].cpu().numpy().view(np.uint32), ru)
 
 
-def test_blocked_plan_with_several_batches(qd):
+@pytest.mark.parametrize("start", [0, 1])
+def test_blocked_plan_with_several_batches(qd, start):
     # more descriptors than one blocked batch holds (16,384): the plan records
     # two batches, each reading its size from the device; replays of shrinking
     # batches (the second batch empty, then a tiny one) with eager work between
@@ -139,7 +140,7 @@ def test_blocked_plan_with_several_batches(qd):
     q, _ = synth.gen_queries(db, 20_000, 98, 0.1, 0.6)
     tree = qd.tree_build(_t(db))
     plan = qd.Plan(_t(obj), n_obj, max_qdesc=20_000, max_qobj=4, k=10, threshold=10, tree=tree,
-                   order=qd.ORDER_BLOCKED)
+                   order=qd.ORDER_BLOCKED, start=start)
     for nd in (20_000, 16_384, 9, 17_001):
         off = np.array([0, nd // 3, nd // 2, nd], np.uint64)
         got = plan.run(_t(q[:nd]), _t(off))
@@ -168,7 +169,7 @@ def test_autotuner_returns_a_timed_exact_configuration(qd):
             assert any(c["order"] == qd.ORDER_BLOCKED for c in cands)  # the round schedules were timed
             assert len({c["schedule"] for c in cands if c["order"] == qd.ORDER_BLOCKED}) >= 5
             res = qd.knn_tree(tree, _t(q), 10, order=best["order"], waves_per_cu=best["waves_per_cu"],
-                              schedule=best["schedule"])
+                              schedule=best["schedule"], start=best["start"])
         else:
             res = qd.knn_bruteforce(_t(db), _t(q), 10, query_tile=best["query_tile"])
         assert np.array_equal(res[0].cpu().numpy().view(np.uint32)[:4], ref.idx)

@@ -79,6 +79,21 @@ def test_blocked_schedules(qd, schedule):
         _same(qd.knn_tree(tree, _t(q), k, order=qd.ORDER_BLOCKED, schedule=schedule), oracle.knn_brute(db, q, k))
 
 
+@pytest.mark.parametrize("k,schedule", [(1, (0, 0, 0)), (10, (0, 0, 0)), (10, (4, 0, 2)), (50, (64, 0, 2)),
+                                        (64, (1, 100_000, 2))])
+def test_blocked_bound_descent_start(qd, k, schedule):
+    # round 1 at the consecutive blocks the bound's descent reaches; the last
+    # case overflows round 2 and repeats it with round 1's blocks still done
+    db = synth.gen_db(60_123, 1101)
+    q, _ = synth.gen_queries(db, 600, 2101, 0.1, 0.6)
+    tree = qd.tree_build(_t(db))
+    res = qd.knn_tree(tree, _t(q), k, order=qd.ORDER_BLOCKED, schedule=schedule, start=qd.START_BOUND_DESCENT,
+                      query_stats=True)
+    _same(res, oracle.knn_brute(db, q, k))
+    plain = qd.knn_tree(tree, _t(q), k, order=qd.ORDER_BLOCKED, schedule=schedule, query_stats=True)
+    assert (plain[4].cpu().numpy() != res[4].cpu().numpy()).any()  # another start: other work, same results
+
+
 def test_blocked_overflow_repeat(qd):
     # one block in round 1 gives a loose 64th key, and round 2 takes every
     # block: more rows than a candidate buffer holds pass the key, so the
@@ -124,12 +139,14 @@ def test_blocked_degenerate_queries_on_the_matrix_cores(qd, plain_bound):
                         one_bit, all_but])
     tree = qd.tree_build(_t(db), plain_bound=plain_bound)
     for k in (1, 10, 64):
+        ref = oracle.knn_brute(db, q, k)
         qd.profile_enable(True)
         res = qd.knn_tree(tree, _t(q), k, order=qd.ORDER_BLOCKED)
         tiles = qd.profile_counter("tree_block_tiles")
         qd.profile_enable(False)
-        _same(res, oracle.knn_brute(db, q, k))
+        _same(res, ref)
         assert tiles > 0
+        _same(qd.knn_tree(tree, _t(q), k, order=qd.ORDER_BLOCKED, start=qd.START_BOUND_DESCENT), ref)
 
 
 def test_blocked_overflow_fallback(qd):
