@@ -15,6 +15,8 @@ struct TreeLaunch {
     size_t total() const { return head + prev_bytes + pool_bytes; }
 };
 TreeLaunch tree_launch_shape(qd_tree_t t, uint32_t nq_max, int order, uint32_t waves_per_cu);
+// The depth-first order's LDS stack holds the tree's depth.
+bool depth_first_fits(qd_tree_t t);
 int tree_launch(qd_tree_t t, const TreeLaunch &L, char *ws, const uint64_t *d_q, uint32_t nq,
                 const uint32_t *nq_dev, uint32_t k, int order, const float *d_scores, uint32_t n_scored,
                 uint32_t *d_idx, int32_t *d_missed, int32_t *d_extra, float *d_dist, uint32_t *d_qstats,
@@ -27,7 +29,8 @@ struct BlockedLayout {
     size_t qpop = 0, lbq = 0, lbb = 0, list = 0, cuts = 0, r1 = 0, rec = 0, thr = 0, ntop = 0, top = 0, ccnt = 0,
            cand = 0, cnt = 0, qr = 0, act = 0, off = 0, voff = 0, ctr = 0, done = 0, fr = 0, tinfo = 0, redo = 0,
            qst = 0, lnode = 0, gst = 0, fbq = 0, fbr = 0, fbws = 0, bytes = 0;
-    TreeLaunch fb;  // the per-query fallback's depth-first launch
+    TreeLaunch fb;  // the per-query fallback's launch
+    int fb_order = QD_ORDER_DEPTH_FIRST;
 };
 int blocked_check(qd_tree_t t, const qd_search_params *p);
 BlockedLayout blocked_layout(qd_tree_t t, uint32_t nq_max, uint32_t k);

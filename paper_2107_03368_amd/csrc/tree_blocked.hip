@@ -1281,8 +1281,11 @@ BlockedLayout blocked_layout(qd_tree_t t, uint32_t nq, uint32_t k) {
     L.lnode = take(P * 4);
     L.gst = take(32);
     // the per-query fallback for queries whose key cannot tighten: gathered
-    // queries, their results, and a depth-first traversal's workspace
-    L.fb = tree_launch_shape(t, qb, QD_ORDER_DEPTH_FIRST, 0);
+    // queries, their results, and a depth-first traversal's workspace (a
+    // best-first one at one wave per CU for a tree deeper than the
+    // depth-first stack: its bucket pools are large, and the fallback is rare)
+    L.fb_order = depth_first_fits(t) ? QD_ORDER_DEPTH_FIRST : QD_ORDER_BEST_FIRST;
+    L.fb = tree_launch_shape(t, qb, L.fb_order, L.fb_order == QD_ORDER_DEPTH_FIRST ? 0 : 1);
     L.fbq = take(P * 512);
     L.fbr = take(P * k * 16);
     L.fbws = take(L.fb.total());
@@ -1428,8 +1431,8 @@ int blocked_batch(qd_tree_t t, const BlockedLayout &L, char *ws, const uint64_t 
     int32_t *rm = reinterpret_cast<int32_t *>(ri + P * k), *rx = rm + P * k;
     float *rd = reinterpret_cast<float *>(rx + P * k);
     hipLaunchKernelGGL(gather_kernel, dim3((nqb * 32 + 255) / 256), dim3(256), 0, s, q4, redo, ctr + 1, gq);
-    rc = tree_launch(t, L.fb, ws + L.fbws, reinterpret_cast<const uint64_t *>(gq), nqb, ctr + 1, k,
-                     QD_ORDER_DEPTH_FIRST, nullptr, 0, ri, rm, rx, rd, nullptr, nullptr, 0, s);
+    rc = tree_launch(t, L.fb, ws + L.fbws, reinterpret_cast<const uint64_t *>(gq), nqb, ctr + 1, k, L.fb_order,
+                     nullptr, 0, ri, rm, rx, rd, nullptr, nullptr, 0, s);
     if (rc != QD_OK) return rc;
     const dim3 g((nqb * k + 255) / 256);
     hipLaunchKernelGGL(scatter_kernel<uint32_t>, g, dim3(256), 0, s, ri, redo, ctr + 1, k, oi);

@@ -44,6 +44,12 @@ constexpr uint32_t kBucketLevels = 2;  // bound levels (multiples of wB) per buc
 constexpr uint32_t kChunk = 16;
 constexpr uint32_t kNone = 0xFFFFFFFFu;
 constexpr int kMaxStack = 256;
+// Best-first: entries of the bucket being popped live in a small LDS stack of
+// the wave ("hot" bucket) while it has room; the other buckets' entries live
+// in the wave's chunks in global memory.  A child's bound is never below its
+// parent's, so pushes never go below the bucket being popped, and most pops
+// take an entry from LDS instead of waiting for global memory.
+constexpr uint32_t kHot = 32;
 
 struct TreeView {
     const uint4 *sorted;
@@ -75,8 +81,8 @@ __global__ __launch_bounds__(kBlock) void tree_knn_kernel(TreeView T, const uint
                                                           uint32_t *trace, uint32_t n_traced,
                                                           const uint32_t *__restrict__ nq_dev) {
     __shared__ uint32_t bstate_all[kBest ? kWaves * kBuckets : 1];
-    __shared__ u64 stack_all[kBest ? 1 : kWaves * kMaxStack];
-    __shared__ u64 sinfo_all[kBest ? 1 : kWaves * kMaxStack];  // the entries' node info
+    __shared__ u64 stack_all[kBest ? kWaves * kHot : kWaves * kMaxStack];  // best-first: the hot bucket's entries
+    __shared__ u64 sinfo_all[kBest ? kWaves * kHot : kWaves * kMaxStack];  // the entries' node info
     const int lane = lane_id();
     const int wave = threadIdx.x >> 6;
     const int g = lane >> 3, j = lane & 7;
@@ -87,8 +93,8 @@ __global__ __launch_bounds__(kBlock) void tree_knn_kernel(TreeView T, const uint
     uint32_t *myprev = chunk_prev + slot * pool_chunks * 2;
     uint32_t *myfree = myprev + pool_chunks;
     uint32_t *bstate = bstate_all + (kBest ? wave * kBuckets : 0);
-    u64 *stack = stack_all + (kBest ? 0 : wave * kMaxStack);
-    u64 *sinfo = sinfo_all + (kBest ? 0 : wave * kMaxStack);
+    u64 *stack = stack_all + wave * (kBest ? kHot : kMaxStack);
+    u64 *sinfo = sinfo_all + wave * (kBest ? kHot : kMaxStack);
     const bool has_and = T.andimg != nullptr;
     if (nq_dev) nq = readfirst(*nq_dev);  // size given on the device (captured graphs)
 
@@ -126,7 +132,8 @@ __global__ __launch_bounds__(kBlock) void tree_knn_kernel(TreeView T, const uint
         u64 touched = 0;    // best-first: buckets whose state word is valid for this query
         uint32_t alloc = 0; // best-first: chunks handed out so far
         uint32_t nfree = 0; // best-first: chunks on the free list
-        int sp = 0;         // depth-first: stack depth
+        int sp = 0;         // depth-first: stack depth; best-first: entries of the hot bucket in LDS
+        uint32_t hot_b = kNone;  // best-first: the bucket whose new entries go to LDS
 
         // bound of node c from its images (each half-wave holds one node's
         // 32 chunks) and, when stored, its rows' popcount range
@@ -169,10 +176,15 @@ __global__ __launch_bounds__(kBlock) void tree_knn_kernel(TreeView T, const uint
             if (kBest) {
                 uint32_t b = kb / (kBucketLevels * wb);
                 b = b < kBuckets ? b : kBuckets - 1;
+                // the hot bucket's entries go to the LDS stack while it has room
+                const bool to_hot = b == hot_b && readfirst((uint32_t)sp) < kHot;
                 const bool tb = (readlane64(touched, (int)(b >> 6)) >> (b & 63)) & 1ull;
                 uint32_t took = 0;
                 if (lane == 0) {
-                    if (!tb) {
+                    if (to_hot) {
+                        stack[sp] = e;
+                        sinfo[sp] = info;
+                    } else if (!tb) {
                         const uint32_t c = take_chunk();
                         took = 1;
                         myprev[c] = kNone;
@@ -196,16 +208,17 @@ __global__ __launch_bounds__(kBlock) void tree_knn_kernel(TreeView T, const uint
                         }
                     }
                 }
+                sp = (int)readfirst((uint32_t)sp + (to_hot ? 1u : 0u));
                 if (readfirst(took)) {
                     if (nfree > 0)
                         nfree--;
                     else
                         alloc++;
                 }
-                if (lane == (int)(b >> 6)) {
-                    occ |= 1ull << (b & 63);
-                    touched |= 1ull << (b & 63);
-                }
+                // the bucket is non-empty; its chunk state is valid once a chunk was written
+                const u64 bit = lane == (int)(b >> 6) ? 1ull << (b & 63) : 0ull;
+                occ |= bit;
+                touched |= to_hot ? 0ull : bit;
             } else {
                 if (readfirst((uint32_t)sp) < (uint32_t)kMaxStack) {
                     if (lane == 0) {
@@ -222,6 +235,8 @@ __global__ __launch_bounds__(kBlock) void tree_knn_kernel(TreeView T, const uint
             const uint32_t kb = readlane(node_bound(0), 0);
             const u64 in = readlane64(info_of(0), 0);
             bounds++;
+            if (kBest) hot_b = readfirst(kb / (kBucketLevels * wb) < (uint32_t)kBuckets ? kb / (kBucketLevels * wb)
+                                                                                          : kBuckets - 1);
             push(kb, 0, in);
         }
 
@@ -233,32 +248,46 @@ __global__ __launch_bounds__(kBlock) void tree_knn_kernel(TreeView T, const uint
                 if (!nz) break;
                 const int L = __builtin_ctzll(nz);
                 const uint32_t b = 64u * (uint32_t)L + (uint32_t)__builtin_ctzll(readlane64(occ, L));
-                u64 got = 0, gin = 0;
-                uint32_t emptied = 0, freed = kNone;
-                if (lane == 0) {
-                    const uint32_t st = bstate[b];
-                    const uint32_t c = st >> 5, f = (st & 31u) - 1;
-                    got = mypool[(uint64_t)c * kChunk + f];
-                    gin = myinfo[(uint64_t)c * kChunk + f];
-                    if (f == 0) {
-                        const uint32_t pc = myprev[c];
-                        if (pc == kNone) {
-                            bstate[b] = c << 5;  // keep the emptied chunk for this bucket
-                            emptied = 1;
-                        } else {
-                            bstate[b] = (pc << 5) | kChunk;
-                            myfree[nfree] = c;
-                            freed = c;
-                        }
-                    } else {
-                        bstate[b] = (c << 5) | f;
-                    }
-                }
-                e = readlane64(got, 0);
-                ninfo = readlane64(gin, 0);
                 floor_kb = b * kBucketLevels * wb;
-                if (readfirst(freed) != kNone) nfree++;
-                if (readfirst(emptied) && lane == L) occ &= ~(1ull << (b & 63));
+                if (b == hot_b && readfirst((uint32_t)sp) > 0) {
+                    // the hot bucket's newest entry, from LDS
+                    sp = (int)readfirst((uint32_t)sp - 1);
+                    e = readlane64(lane == 0 ? stack[sp] : 0ull, 0);
+                    ninfo = readlane64(lane == 0 ? sinfo[sp] : 0ull, 0);
+                    // once the stack is empty, the bucket is empty unless its chunks still hold entries
+                    const bool tb = (readlane64(touched, (int)(b >> 6)) >> (b & 63)) & 1ull;
+                    const uint32_t fill = readfirst(sp != 0 ? 1u : (tb && lane == 0 ? bstate[b] & 31u : 0u));
+                    occ &= fill == 0 && lane == L ? ~(1ull << (b & 63)) : ~0ull;
+                } else {
+                    // the bucket's entries are in its chunks; it becomes the hot
+                    // bucket (the LDS stack is empty: buckets below hot_b are empty)
+                    hot_b = b;
+                    u64 got = 0, gin = 0;
+                    uint32_t emptied = 0, freed = kNone;
+                    if (lane == 0) {
+                        const uint32_t st = bstate[b];
+                        const uint32_t c = st >> 5, f = (st & 31u) - 1;
+                        got = mypool[(uint64_t)c * kChunk + f];
+                        gin = myinfo[(uint64_t)c * kChunk + f];
+                        if (f == 0) {
+                            const uint32_t pc = myprev[c];
+                            if (pc == kNone) {
+                                bstate[b] = c << 5;  // keep the emptied chunk for this bucket
+                                emptied = 1;
+                            } else {
+                                bstate[b] = (pc << 5) | kChunk;
+                                myfree[nfree] = c;
+                                freed = c;
+                            }
+                        } else {
+                            bstate[b] = (c << 5) | f;
+                        }
+                    }
+                    e = readlane64(got, 0);
+                    ninfo = readlane64(gin, 0);
+                    if (readfirst(freed) != kNone) nfree++;
+                    occ &= readfirst(emptied) && lane == L ? ~(1ull << (b & 63)) : ~0ull;
+                }
             } else {
                 if (readfirst((uint32_t)sp) == 0) break;
                 sp = (int)readfirst((uint32_t)sp - 1);
@@ -394,6 +423,8 @@ __global__ void zero_words_kernel(uint32_t *p, uint32_t n) {
     for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0;
 }
 
+bool depth_first_fits(qd_tree_t t) { return t->depth + 2 <= (uint32_t)kMaxStack; }
+
 TreeLaunch tree_launch_shape(qd_tree_t t, uint32_t nq_max, int order, uint32_t waves_per_cu) {
     TreeLaunch L;
     const int cus = device_cus();
@@ -458,7 +489,7 @@ int knn_tree_impl(qd_tree_t t, const uint64_t *d_q, uint32_t nq, uint32_t k, int
         return knn_tree_blocked(t, d_q, nq, k, nullptr, d_idx, d_missed, d_extra, d_dist, d_qstats, h_stats,
                                 (hipStream_t)stream);
     }
-    if (order == QD_ORDER_DEPTH_FIRST && t->depth + 2 > (uint32_t)kMaxStack)
+    if (order == QD_ORDER_DEPTH_FIRST && !depth_first_fits(t))
         return fail(QD_ERR_UNSUPPORTED, "tree depth %u exceeds the depth-first stack (%d)", t->depth, kMaxStack);
     if (n_traced > t->n_nodes) return fail(QD_ERR_INVALID, "n_traced above the node count");
     hipStream_t s = (hipStream_t)stream;

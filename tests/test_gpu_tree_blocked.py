@@ -224,3 +224,25 @@ def test_blocked_work_counters(qd):
     qd.profile_enable(True)  # counters start again from zero
     assert qd.profile_counter("tree_block_tiles") == 0
     qd.profile_enable(False)
+
+
+def test_deep_tree_fallback_is_best_first(qd):
+    # rows "every bit but bit i" make every split peel off one row (the least
+    # popular bit is in all rows but one), so the tree is about 300 levels
+    # deep, deeper than the depth-first order's stack; 30,000 all-one rows
+    # tie at key 0 for an all-one query, more than a candidate buffer holds,
+    # so those queries take the blocked search's fallback, which must then
+    # search best-first
+    chain = np.full((300, 64), np.uint64(0xFFFFFFFFFFFFFFFF))
+    for i in range(300):
+        chain[i, i // 64] &= ~(np.uint64(1) << np.uint64(i % 64))
+    db = np.concatenate([chain, np.full((30_000, 64), np.uint64(0xFFFFFFFFFFFFFFFF))])
+    tree = qd.tree_build(_t(db))
+    assert tree.depth > 256
+    q = np.concatenate([db[:1], db[150:151], db[-1:], synth.gen_queries(chain, 5, 77, 0.2, 0.5)[0]])
+    with pytest.raises(qd.QDError):
+        qd.knn_tree(tree, _t(q), 10, order=qd.ORDER_DEPTH_FIRST)  # the stack cannot hold this tree
+    for k in (1, 10):
+        ref = oracle.knn_brute(db, q, k)
+        _same(qd.knn_tree(tree, _t(q), k, order=qd.ORDER_BLOCKED), ref)
+        _same(qd.knn_tree(tree, _t(q), k), ref)
