@@ -35,7 +35,7 @@ WORKLOADS = {
     "objects": dict(n_obj=300, per_obj=5000, n_qo=128, mmin=200, mmax=4000, pmin=0.2, pmax=0.7, k=5, threshold=10,
                     seed_db=1002, seed_qo=1003, seed_q=1004),
     # small batches over the 10M database: the bit-plane index against the row scan
-    "smallbatch10m": dict(n=10_000_000, batches=(1, 8, 64, 256), pmin=0.1, pmax=0.6, k=10, seed_db=1003,
+    "smallbatch10m": dict(n=10_000_000, batches=(1, 8, 16, 64, 256), pmin=0.1, pmax=0.6, k=10, seed_db=1003,
                           seed_q=2003),
     "stream50m": dict(n=50_000_000, n_obj=10_000, per_obj=5_000, n_qo=48, mmin=50, mmax=5000, pmin=0.1,
                       pmax=0.6, k=10, seed_db=1004, seed_q=2004, seed_qo=5004, seed_arrivals=6004,
@@ -87,7 +87,7 @@ def main():
     ap.add_argument("--pmc-run", action="store_true",
                     help="only a 1 GiB device copy (counter calibration) and one batch of each --pmc-paths path")
     ap.add_argument("--pmc-paths", default="brute,blocked",
-                    help="--pmc-run: brute, blocked, best_first, depth_first")
+                    help="--pmc-run: brute, small1, small8, small16, blocked, best_first, depth_first")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU; --gpus must be 1"}))
@@ -118,11 +118,16 @@ def main():
         pp = args.pmc_paths.split(",")
         if "brute" in pp:
             qd.knn_bruteforce(dbt, qt, w["k"])
-        tree = qd.tree_build(dbt)
-        for name, order in (("blocked", qd.ORDER_BLOCKED), ("best_first", qd.ORDER_BEST_FIRST),
-                            ("depth_first", qd.ORDER_DEPTH_FIRST)):
-            if name in pp:
-                qd.knn_tree(tree, qt, w["k"], order=order)
+        for qn in (1, 8, 16):  # the small-batch row scans
+            if f"small{qn}" in pp:
+                qd.knn_bruteforce(dbt, qt[:qn], w["k"])
+        orders = (("blocked", qd.ORDER_BLOCKED), ("best_first", qd.ORDER_BEST_FIRST),
+                  ("depth_first", qd.ORDER_DEPTH_FIRST))
+        if any(name in pp for name, _ in orders):
+            tree = qd.tree_build(dbt)
+            for name, order in orders:
+                if name in pp:
+                    qd.knn_tree(tree, qt, w["k"], order=order)
         torch.cuda.synchronize()
         log("pmc run done")
         return
@@ -280,21 +285,23 @@ def main():
             f"learned start {k1['blocked_learned']['ms']:.2f} ms "
             f"({k1['blocked_learned']['blocks_per_query']:.0f} blocks/query)")
 
-    # small-batch scan: HBM-bound regime (one pass over the rows serves <= 8 queries)
+    # small-batch scan: HBM-bound regime (one pass over the rows serves <= 16
+    # queries: the vector-ALU scan for 1-2 queries, the matrix query tile above)
     hbm = {}
-    for qn in (1, 8):
+    for qn in (1, 8, 16):
         fn = lambda: qd.knn_bruteforce(dbt, qt[:qn], k)
         fn()
         torch.cuda.synchronize()
         qd.profile_enable(True)
         for _ in range(5):
             fn()
-        ms, cnt = qd.profile_read("wh_scan_topk")
+        (ms_v, cnt_v), (ms_m, cnt_m) = qd.profile_read("wh_scan_topk"), qd.profile_read("wh_scan_small_mfma")
         qd.profile_enable(False)
-        avg = ms / cnt
+        kname = "scan_small_mfma_kernel" if cnt_m else "scan_topk_kernel"
+        avg = (ms_v + ms_m) / (cnt_v + cnt_m)
         gbs = (n * ROW_BYTES + qn * ROW_BYTES) / (avg * 1e-3) / 1e9
-        hbm[f"q{qn}"] = {"scan_ms": avg, "GB_s": gbs, "frac": gbs / HBM_PEAK_GBS}
-        log(f"scan at {qn} queries: {avg:.3f} ms, {gbs:.0f} GB/s ({gbs / HBM_PEAK_GBS:.1%} of HBM peak)")
+        hbm[f"q{qn}"] = {"kernel": kname, "scan_ms": avg, "GB_s": gbs, "frac": gbs / HBM_PEAK_GBS}
+        log(f"scan at {qn} queries ({kname}): {avg:.3f} ms, {gbs:.0f} GB/s ({gbs / HBM_PEAK_GBS:.1%} of HBM peak)")
 
     # register-tiled scan at 512 queries (16 per tile): VALU-bound, 256 32-bit lane ops per pair
     valu = None
@@ -618,6 +625,11 @@ def smallbatch_main(args, w, dev):
             if name == "planes":
                 ms, cnt = qd.profile_read("planes_scan")
                 res["planes_scan_ms"] = ms / max(cnt, 1)
+            else:
+                (ms_v, cnt_v), (ms_m, cnt_m) = qd.profile_read("wh_scan_topk"), qd.profile_read("wh_scan_small_mfma")
+                res["rows_scan_kernel"] = "scan_small_mfma_kernel" if cnt_m else "scan_topk_kernel"
+                res["rows_scan_ms"] = (ms_v + ms_m) / max(cnt_v + cnt_m, 1)
+                res["rows_scan_gbs"] = n * ROW_BYTES / (res["rows_scan_ms"] * 1e-3) / 1e9
             qd.profile_enable(False)
             res[name + "_ms"] = dt * 1e3
             res[name + "_qps"] = nq / dt
@@ -627,7 +639,8 @@ def smallbatch_main(args, w, dev):
                    planes_scan_gbs=alg / (res["planes_scan_ms"] * 1e-3) / 1e9)
         rows.append(res)
         log(f"batch {nq}: planes {res['planes_ms']:.3f} ms ({res['planes_qps']:.0f} q/s, scan "
-            f"{res['planes_scan_gbs']:.0f} GB/s), rows {res['rows_ms']:.3f} ms ({res['rows_qps']:.0f} q/s)")
+            f"{res['planes_scan_gbs']:.0f} GB/s), rows {res['rows_ms']:.3f} ms ({res['rows_qps']:.0f} q/s, "
+            f"{res['rows_scan_kernel']} {res['rows_scan_ms']:.3f} ms, {res['rows_scan_gbs']:.0f} GB/s of rows)")
     top = rows[-1]
     out = {
         "metric": "small-batch exact kNN queries/s (4096-bit WHD, 10M descs, k=10): bit-plane index vs row scan",

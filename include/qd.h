@@ -113,18 +113,22 @@ int qd_knn_bruteforce(const uint64_t *d_db, uint64_t n, const uint64_t *d_q, uin
 
 /* Same search with an explicit launch shape, for tuning and for tests that
  * check that results do not depend on it: query_tile = queries served per
- * pass over a row slice (1, 2, 4, 8 or 16; 0 = automatic), row_parts = row
+ * pass over a row slice (1, 2, 4, 8 or 16 on the vector ALUs;
+ * QD_QUERY_TILE_MATRIX: tiles of 16 queries whose overlap counts with 16 rows
+ * at a time are one matrix-core product; 0 = automatic), row_parts = row
  * slices per query tile (1..4096, clipped to at least 256 rows per slice;
  * 0 = automatic).  Results are identical for every shape. */
+#define QD_QUERY_TILE_MATRIX 256u
 int qd_knn_bruteforce_shaped(const uint64_t *d_db, uint64_t n, const uint64_t *d_q, uint32_t nq, uint32_t k,
                              uint32_t query_tile, uint32_t row_parts, uint32_t *d_idx, int32_t *d_missed,
                              int32_t *d_extra, float *d_dist, void *stream);
 
 /* For callers that cannot allocate device memory (code under hipGraph
  * capture, tight serving loops, harnesses that forbid hipMalloc): the same
- * search as qd_knn_bruteforce, same arguments and results, on the
- * register-tiled scan, with no device allocation and no allocating library
- * call.  Its scratch (each wave's top-k lists) is a fixed device array of
+ * search as qd_knn_bruteforce, same arguments and results, on its row scan
+ * (vector-ALU or matrix-core query tiles, chosen as there; never the
+ * large-batch matrix-core path), with no device allocation and no allocating
+ * library call.  Its scratch (each wave's top-k lists) is a fixed device array of
  * QD_NOALLOC_SCRATCH_BYTES inside the library, one per GPU, held until the
  * process ends; its address is looked up on the first call on each device.
  * Requests whose lists cannot fit (nq * k above QD_NOALLOC_SCRATCH_BYTES / 8)
@@ -467,8 +471,9 @@ int qd_model_train(qd_model_t m, qd_tree_t t, const uint64_t *d_q, uint32_t nq, 
  * tree's order (best-first, depth-first or blocked, with occupancy or round
  * schedule; no model, scores or traces); query_tile picks the sequential
  * scan: 0 = the matrix cores when max_qdesc >= 512 over >= 65,536 rows (as
- * qd_knn_bruteforce decides for a batch of max_qdesc), else the register-tiled
- * scan with that tile (0 = 16).  It allocates all its device memory at
+ * qd_knn_bruteforce decides for a batch of max_qdesc), else the row scan with
+ * that query tile (as in qd_knn_bruteforce_shaped; 0 = the one
+ * qd_knn_bruteforce picks for max_qdesc queries).  It allocates all its device memory at
  * creation and records one batch -- the k-NN of every descriptor, then the
  * votes -- into a hipGraph whose kernels read the batch size from device
  * memory and never wait for the host: the blocked order runs a fixed number
@@ -497,7 +502,7 @@ int qd_plan_free(qd_plan_t p);
  * schedules -- round-1 blocks 8, 16, 32, growth 2, 4, 8, round-2 coverage
  * half, default and double, round 1 at the lowest bounds or at the bound's
  * descent; sequential search: automatic path and query
- * tiles 4, 8, 16) over `reps` runs after one warm-up on the caller's sample
+ * tiles 4, 8, 16 and QD_QUERY_TILE_MATRIX) over `reps` runs after one warm-up on the caller's sample
  * batch, and returns the fastest in *best (every configuration returns the
  * same exact result).  With `all`, every candidate's timing is written too.
  * Results are cached per (device, rows, nodes, nq, k) for the process, and in
@@ -509,7 +514,7 @@ typedef struct {
     int path;              /* 1 = tree search, 0 = sequential search */
     qd_order order;        /* tree: frontier order */
     uint32_t waves_per_cu; /* tree, per-query orders: occupancy (0 = default) */
-    uint32_t query_tile;   /* sequential: query tile (0 = automatic, matrix cores for large batches) */
+    uint32_t query_tile;   /* sequential: query tile (0 = automatic; see qd_knn_bruteforce_shaped) */
     float ms;              /* mean time of one batch */
     uint32_t round1_blocks, round2_blocks, round_growth; /* blocked order: qd_search_params' schedule */
     uint32_t round1_start; /* blocked order: qd_search_params.round1_start */

@@ -93,6 +93,9 @@ def popcount_rows(db):
     return out
 
 
+QUERY_TILE_MATRIX = 256  # query_tile: tiles of 16 queries on the matrix cores
+
+
 def knn_bruteforce(db, q, k, query_tile=0, row_parts=0):
     """Exact k-NN by sequential search.  Returns (idx, missed, extra, dist),
     each (nq, k); idx holds uint32 row numbers in int32 storage (PAD_IDX = -1)."""

@@ -12,6 +12,15 @@
 // one register across the 64 lanes and inserts only candidates below the
 // current k-th key.  A merge kernel then reduces the per-wave lists of every
 // query to the exact top k and writes the results.
+//
+// Batches of a few queries take the same slices on the matrix cores instead
+// (scan_small_mfma_kernel): a wave holds 16 queries and counts 16 rows
+// against them at a time as one FP4 matrix product (the encoding of
+// mfma_tile.h), so its vector work per row no longer grows with the number
+// of queries.
+#include <mutex>
+
+#include "mfma_tile.h"
 #include "qd_device.h"
 #include "qd_internal.h"
 #include "qd_launch.h"
@@ -107,6 +116,131 @@ __global__ __launch_bounds__(kBlock) void scan_topk_kernel(const uint4 *__restri
     }
 }
 
+// Tiles of 16 queries on the matrix cores.  A wave keeps the 16 queries of
+// its tile in registers and streams its slice of rows 16 at a time.  The
+// 16 x 16 overlap counts of a group are one chain of 32 FP4 matrix steps
+// (expand_a / expand_b of mfma_tile.h): lane l (row or query l % 16, lane
+// group g = l / 16) loads the 16-byte pieces 4i + g, i = 0..7, of its row,
+// and step 4i + c takes word c of piece i, so the four lane groups of a step
+// cover four different words and the 32 steps cover all 128.  One load
+// instruction reads 64 contiguous bytes of each of the 16 rows.  Lane l then
+// holds the counts of queries 4g .. 4g + 3 against row l % 16; the row's
+// popcount is summed over its four lanes.  The per-query k-lists are kept in
+// LDS and taken into a register (one entry per lane) only to insert, while
+// every lane filters with the current k-th key of its four queries.  Rows
+// past the slice's end are read as the slice's last row and never listed.
+constexpr int kSmallQ = 16;     // queries per wave (one matrix tile)
+constexpr int kSmallRows = 16;  // rows per matrix product
+
+__global__ __launch_bounds__(kBlock) void scan_small_mfma_kernel(const uint4 *__restrict__ db, uint64_t n,
+                                                                 const uint4 *__restrict__ q, uint32_t nq,
+                                                                 uint32_t k, uint32_t n_qtiles, uint32_t n_parts,
+                                                                 uint64_t rows_per_part, u64 *__restrict__ part,
+                                                                 const uint32_t *__restrict__ nq_dev) {
+    extern __shared__ u64 lists_lds[];  // kWavesPerBlock x kSmallQ x k keys
+    if (nq_dev) {
+        nq = *nq_dev;  // size given on the device (captured graphs)
+        if ((blockIdx.x % n_qtiles) * kSmallQ >= nq) return;  // whole block
+    }
+    const int lane = lane_id();
+    const int li = lane & 15, lg = lane >> 4;
+    const uint32_t qtile = blockIdx.x % n_qtiles;
+    const uint32_t wv = threadIdx.x >> 6;
+    const uint32_t p = readfirst((blockIdx.x / n_qtiles) * kWavesPerBlock + wv);
+    if (p >= n_parts) return;  // whole wave
+    const uint64_t r0 = (uint64_t)p * rows_per_part;
+    const uint64_t r1 = r0 + rows_per_part < n ? r0 + rows_per_part : n;
+    u64 *wl = lists_lds + (size_t)wv * kSmallQ * k;
+
+    // words of query li taken by this lane's group, and its popcount
+    uint32_t qw[32];
+    uint32_t s = 0;
+    {
+        const uint32_t qi = qtile * kSmallQ + li;
+#pragma unroll
+        for (int i = 0; i < 8; i++) {
+            const uint4 v = qi < nq ? q[(uint64_t)qi * 32 + 4 * i + lg] : make_uint4(0, 0, 0, 0);
+            qw[4 * i] = v.x;
+            qw[4 * i + 1] = v.y;
+            qw[4 * i + 2] = v.z;
+            qw[4 * i + 3] = v.w;
+            s += popc4(v);
+        }
+    }
+    s += (uint32_t)__shfl_xor((int)s, 16);
+    s += (uint32_t)__shfl_xor((int)s, 32);  // every lane of column li: |query li|
+    // constants of this lane's accumulator rows, queries 4 lg + r
+    uint32_t pq[4], wa[4], wb[4];
+    u64 thr[4];
+#pragma unroll
+    for (int r = 0; r < 4; r++) {
+        pq[r] = (uint32_t)__shfl((int)s, 4 * lg + r);
+        wa[r] = pq[r] > 1 ? pq[r] : 1;
+        wb[r] = (QD_BITS - pq[r]) > 1 ? QD_BITS - pq[r] : 1;
+        thr[r] = qtile * kSmallQ + 4 * lg + r < nq ? KEY_NONE : 0;  // padding queries never list
+    }
+    for (int t = 0; t < kSmallQ; t++)
+        if (lane < (int)k) wl[t * k + lane] = KEY_NONE;
+
+    auto load = [&](uint64_t base, uint4 (&t)[8]) {
+        const uint64_t row = base + li < r1 ? base + li : r1 - 1;
+        const uint4 *src = db + row * 32 + lg;
+#pragma unroll
+        for (int i = 0; i < 8; i++) t[i] = src[4 * i];
+    };
+    // the next group's rows are loaded before this group's work
+    uint4 tn[8];
+    load(r0, tn);
+    for (uint64_t base = r0; base < r1; base += kSmallRows) {
+        uint4 tv[8];
+#pragma unroll
+        for (int i = 0; i < 8; i++) tv[i] = tn[i];
+        if (base + kSmallRows < r1) load(base + kSmallRows, tn);
+        mt::v4f acc = {0.f, 0.f, 0.f, 0.f};
+        uint32_t tp = 0;
+#pragma unroll
+        for (int i = 0; i < 8; i++) {
+            const uint32_t w4[4] = {tv[i].x, tv[i].y, tv[i].z, tv[i].w};
+#pragma unroll
+            for (int c = 0; c < 4; c++) {
+                tp += __popc(w4[c]);
+                // formats 4 = e2m1 for both operands; scales 127 = 2^0
+                acc = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(mt::expand_a(qw[4 * i + c]),
+                                                                       mt::expand_b(w4[c]), acc, 4, 4, 0, 127, 0,
+                                                                       127);
+            }
+        }
+        tp += (uint32_t)__shfl_xor((int)tp, 16);
+        tp += (uint32_t)__shfl_xor((int)tp, 32);  // |row li|
+        const uint64_t row = base + li;
+        const bool valid = row < r1;
+#pragma unroll
+        for (int r = 0; r < 4; r++) {
+            const uint32_t c = mt::count(acc[r]);
+            const uint32_t K = (pq[r] - c) * wb[r] + (tp - c) * wa[r];
+            const u64 key = valid ? ((u64)K << 32) | (uint32_t)row : KEY_NONE;
+            u64 m = ballot(key < thr[r]);
+            while (m) {
+                const int L = __builtin_ctzll(m);
+                m &= m - 1;
+                const uint32_t t = 4 * (L >> 4) + r;  // the query of lane L's row r
+                const u64 c2 = readlane64(key, L);
+                u64 lst = lane < (int)k ? wl[t * k + lane] : KEY_NONE;
+                if (c2 < readlane64(lst, (int)k - 1)) {
+                    lst = list_insert(lst, c2, k);
+                    if (lane < (int)k) wl[t * k + lane] = lst;
+                    const u64 nk = readlane64(lst, (int)k - 1);
+                    if (lg == (L >> 4)) thr[r] = nk;  // the lanes whose row r is query t
+                }
+            }
+        }
+    }
+    for (int t = 0; t < kSmallQ; t++) {
+        const uint32_t qi = qtile * kSmallQ + t;
+        if (qi < nq && lane < (int)k) part[((uint64_t)qi * n_parts + p) * k + lane] = wl[t * k + lane];
+    }
+}
+
 // One block per query: exact top k from n_parts sorted lists of k keys, then
 // the result rows.  U = the k-th smallest list head bounds the k-th key from
 // above (those k heads are k distinct candidates), and only lists whose head
@@ -198,6 +332,28 @@ __global__ __launch_bounds__(kBlock) void popcount_rows_kernel(const uint4 *__re
     }
 }
 
+size_t small_lds_bytes(uint32_t k) { return (size_t)kWavesPerBlock * kSmallQ * k * sizeof(u64); }
+
+// Waves of scan_small_mfma_kernel the whole device holds at once, for lists of k.
+uint64_t small_mfma_resident_waves(uint32_t k) {
+    static std::mutex mu;
+    static uint32_t cache[64][QD_MAX_K + 1] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) dev = 0;
+    std::lock_guard<std::mutex> lock(mu);
+    if (cache[dev][k] == 0) {
+        int nb = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, scan_small_mfma_kernel, kBlock, small_lds_bytes(k)) !=
+                hipSuccess ||
+            nb < 1) {
+            (void)hipGetLastError();
+            nb = 2;
+        }
+        cache[dev][k] = (uint32_t)nb * kWavesPerBlock;
+    }
+    return (uint64_t)cache[dev][k] * device_cus();
+}
+
 template <int QT>
 void launch_scan(dim3 grid, hipStream_t s, const uint4 *db, uint64_t n, const uint4 *q, uint32_t nq, uint32_t k,
                  uint32_t n_qtiles, uint32_t n_parts, uint64_t rpp, u64 *part, const uint32_t *nq_dev) {
@@ -210,21 +366,36 @@ void launch_scan(dim3 grid, hipStream_t s, const uint4 *db, uint64_t n, const ui
 BruteLaunch brute_launch_shape(uint64_t n, uint32_t nq, uint32_t k, uint32_t qt_force, uint32_t parts_force) {
     BruteLaunch sh;
     uint32_t qt = qt_force;
-    if (qt == 0) qt = nq <= 1 ? 1 : nq <= 2 ? 2 : nq <= 4 ? 4 : nq <= 8 ? 8 : 16;
+    if (qt == 0)
+        qt = nq >= kSmallMfmaMinQueries ? QD_QUERY_TILE_MATRIX
+             : nq <= 1                  ? 1
+             : nq <= 2                  ? 2
+             : nq <= 4                  ? 4
+             : nq <= 8                  ? 8
+                                        : 16;
     sh.qt = qt;
-    sh.n_qtiles = (nq + qt - 1) / qt;
+    const bool matrix = qt == QD_QUERY_TILE_MATRIX;
+    const uint32_t per_tile = matrix ? (uint32_t)kSmallQ : qt;
+    sh.n_qtiles = (nq + per_tile - 1) / per_tile;
     if (sh.n_qtiles == 0) sh.n_qtiles = 1;
     uint64_t parts = parts_force;
     if (parts == 0) {
-        const uint64_t want_waves = (uint64_t)device_cus() * 16;
-        parts = (want_waves + sh.n_qtiles - 1) / sh.n_qtiles;
+        if (matrix) {
+            // one wave per resident slot: every wave runs from start to end
+            const uint64_t slots = small_mfma_resident_waves(k);
+            parts = slots / sh.n_qtiles;
+        } else {
+            const uint64_t want_waves = (uint64_t)device_cus() * 16;
+            parts = (want_waves + sh.n_qtiles - 1) / sh.n_qtiles;
+        }
     }
     const uint64_t max_by_rows = (n + 255) / 256;  // at least 256 rows per wave
     if (parts > max_by_rows) parts = max_by_rows;
     if (parts > kMaxParts) parts = kMaxParts;
     if (parts < 1) parts = 1;
+    const uint64_t step = matrix ? (uint64_t)kSmallRows : (uint64_t)kRowsPerStep;
     uint64_t rpp = (n + parts - 1) / parts;
-    rpp = (rpp + kRowsPerStep - 1) / kRowsPerStep * kRowsPerStep;
+    rpp = (rpp + step - 1) / step * step;
     sh.rows_per_part = rpp;
     sh.n_parts = (uint32_t)((n + rpp - 1) / rpp);
     sh.blocks = (uint64_t)((sh.n_parts + kWavesPerBlock - 1) / kWavesPerBlock) * sh.n_qtiles;
@@ -240,7 +411,11 @@ int brute_launch(const BruteLaunch &sh, u64 *part, const uint64_t *d_db, uint64_
     const uint4 *db4 = reinterpret_cast<const uint4 *>(d_db);
     const uint4 *q4 = reinterpret_cast<const uint4 *>(d_q);
     dim3 grid((uint32_t)sh.blocks);
-    {
+    if (sh.qt == QD_QUERY_TILE_MATRIX) {
+        KernelTimer timer(timed ? "wh_scan_small_mfma" : nullptr, s);
+        hipLaunchKernelGGL(scan_small_mfma_kernel, grid, dim3(kBlock), small_lds_bytes(k), s, db4, n, q4, nq, k,
+                           sh.n_qtiles, sh.n_parts, sh.rows_per_part, part, nq_dev);
+    } else {
         KernelTimer timer(timed ? "wh_scan_topk" : nullptr, s);
         switch (sh.qt) {
             case 1: launch_scan<1>(grid, s, db4, n, q4, nq, k, sh.n_qtiles, sh.n_parts, sh.rows_per_part, part, nq_dev); break;
@@ -298,8 +473,9 @@ int knn_bruteforce_impl(const uint64_t *d_db, uint64_t n, const uint64_t *d_q, u
     if (nq == 0) return QD_OK;
     if (!d_db || !d_q || !d_idx || !d_missed || !d_extra || !d_dist) return fail(QD_ERR_INVALID, "null pointer");
     if (!aligned16(d_db) || !aligned16(d_q)) return fail(QD_ERR_INVALID, "descriptor arrays must be 16-byte aligned");
-    if (qt_force && qt_force != 1 && qt_force != 2 && qt_force != 4 && qt_force != 8 && qt_force != 16)
-        return fail(QD_ERR_INVALID, "query tile %u not in {1,2,4,8,16}", qt_force);
+    if (qt_force && qt_force != 1 && qt_force != 2 && qt_force != 4 && qt_force != 8 && qt_force != 16 &&
+        qt_force != QD_QUERY_TILE_MATRIX)
+        return fail(QD_ERR_INVALID, "query tile %u not in {1,2,4,8,16,QD_QUERY_TILE_MATRIX}", qt_force);
     if (qt_force == 0 && parts_force == 0 && nq >= kMfmaMinQueries && n >= kMfmaMinRows) {
         const int rc = knn_bruteforce_mfma(d_db, n, d_q, nq, k, d_idx, d_missed, d_extra, d_dist, stream);
         if (rc != QD_ERR_UNSUPPORTED) return rc;

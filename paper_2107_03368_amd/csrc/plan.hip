@@ -95,6 +95,9 @@ extern "C" int qd_plan_create(qd_tree_t t, const uint64_t *d_db, uint64_t n, con
         return fail(QD_ERR_INVALID, "unknown frontier order");
     if (params && params->model)
         return fail(QD_ERR_UNSUPPORTED, "a plan takes no model (scoring allocates per call)");
+    if (query_tile != 0 && query_tile != 1 && query_tile != 2 && query_tile != 4 && query_tile != 8 &&
+        query_tile != 16 && query_tile != QD_QUERY_TILE_MATRIX)
+        return fail(QD_ERR_INVALID, "query tile %u not in {0,1,2,4,8,16,QD_QUERY_TILE_MATRIX}", query_tile);
     const bool blocked = t && order == QD_ORDER_BLOCKED;
     if (blocked) {
         const int rc = blocked_check(t, params);
@@ -118,8 +121,9 @@ extern "C" int qd_plan_create(qd_tree_t t, const uint64_t *d_db, uint64_t n, con
     MfmaLayout ML;
     uint32_t n_batches = 1;
     size_t ws_bytes;
-    // sequential search: the matrix cores when the largest batch is big enough
-    // (query_tile 0), else the register-tiled scan
+    // sequential search: the large-batch matrix-core path when the largest
+    // batch is big enough (query_tile 0), else the row scan with that tile
+    // (0: chosen for the largest batch as qd_knn_bruteforce would)
     const bool mfma = !t && query_tile == 0 && mfma_eligible(n, nqmax, k);
     if (blocked) {
         KL = blocked_layout(t, nqmax, k);
@@ -132,7 +136,7 @@ extern "C" int qd_plan_create(qd_tree_t t, const uint64_t *d_db, uint64_t n, con
         TL = tree_launch_shape(t, nqmax, order, params ? params->waves_per_cu : 0);
         ws_bytes = TL.total();
     } else {
-        BL = brute_launch_shape(n, nqmax, k, query_tile ? query_tile : 16, 0);
+        BL = brute_launch_shape(n, nqmax, k, query_tile, 0);
         ws_bytes = BL.part_bytes;
     }
     // one allocation: q | qoff | sizes | nn mi ex di | votes winner used | ws
@@ -333,7 +337,8 @@ extern "C" int qd_autotune(qd_tree_t t, const uint64_t *d_db, uint64_t n, const 
         if (mask & (1u << QD_ORDER_BLOCKED))
             for (auto &sc : sched) cand.push_back({1, QD_ORDER_BLOCKED, 0, 0, 0.f, sc[0], sc[1], sc[2], sc[3]});
     } else {
-        for (uint32_t qt : {0u, 4u, 8u, 16u}) cand.push_back({0, QD_ORDER_BEST_FIRST, 0, qt, 0.f, 0, 0, 0, 0});
+        for (uint32_t qt : {0u, 4u, 8u, 16u, QD_QUERY_TILE_MATRIX})
+            cand.push_back({0, QD_ORDER_BEST_FIRST, 0, qt, 0.f, 0, 0, 0, 0});
     }
     char *ws = nullptr;
     const size_t m = (size_t)nq * k;

@@ -41,6 +41,9 @@ int blocked_batch(qd_tree_t t, const BlockedLayout &L, char *ws, const uint64_t 
                   int32_t *d_extra, float *d_dist, uint32_t *d_qstats, unsigned long long *gst, bool graph,
                   hipStream_t s);
 
+// Batches of at least this many queries scan in tiles of 16 queries on the
+// matrix cores (QD_QUERY_TILE_MATRIX), smaller ones on the vector ALUs.
+constexpr uint32_t kSmallMfmaMinQueries = 3;
 struct BruteLaunch {
     uint32_t qt = 0, n_qtiles = 0, n_parts = 0;
     uint64_t rows_per_part = 0, blocks = 0;

@@ -61,6 +61,23 @@ def test_argument_errors_are_reported_before_any_device_work():
     assert f(a, 100, a, 0, 10, a, a, a, a, None) == 0          # nq = 0 is a no-op
 
 
+def test_query_tile_values_are_checked_before_device_work():
+    lib = ctypes.CDLL(LIB)
+    lib.qd_last_error.restype = ctypes.c_char_p
+    P, U64, U32 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32
+    f = lib.qd_knn_bruteforce_shaped
+    f.argtypes = [P, U64, P, U32, U32, U32, U32, P, P, P, P, P]
+    a = P(0x10000)
+    for tile in (3, 32, 255, 257):
+        assert f(a, 100, a, 5, 10, tile, 0, a, a, a, a, None) == -1
+        assert b"query tile" in lib.qd_last_error()
+    g = lib.qd_plan_create
+    g.argtypes = [P, P, U64, P, U32, U64, U32, U32, U32, P, U32, ctypes.POINTER(P)]
+    h = P()
+    assert g(None, a, 100, a, 4, 64, 4, 10, 0, None, 24, ctypes.byref(h)) == -1
+    assert b"query tile" in lib.qd_last_error() and not h.value
+
+
 def test_object_score_argument_errors_without_device_work():
     lib = ctypes.CDLL(LIB)
     lib.qd_last_error.restype = ctypes.c_char_p

@@ -53,6 +53,16 @@ def test_result_independent_of_launch_shape(qd, small_db, small_queries, tile, p
     _same(qd.knn_bruteforce(_t(db), _t(q), 13, query_tile=tile, row_parts=parts), ref)
 
 
+@pytest.mark.parametrize("parts", [0, 1, 5, 4096])
+def test_matrix_query_tile_independent_of_launch_shape(qd, small_db, small_queries, parts):
+    # tiles of 16 queries on the matrix cores: 37 queries (ragged against the
+    # tile) over 9,999 rows (ragged against the 16-row product)
+    q, _ = small_queries
+    q, db = q[:37], small_db[:9_999]
+    ref = oracle.knn_brute(db, q, 13)
+    _same(qd.knn_bruteforce(_t(db), _t(q), 13, query_tile=qd.QUERY_TILE_MATRIX, row_parts=parts), ref)
+
+
 def test_ties_duplicates_and_degenerate_queries(qd):
     rng = np.random.default_rng(3)
     base = synth.gen_db(200, 51)
@@ -123,6 +133,27 @@ def test_matrix_core_path_equals_register_scan_and_oracle(qd):
         for x, y in zip(a, b):
             assert np.array_equal(x.cpu().numpy(), y.cpu().numpy())
         _same(a, oracle.knn_brute(db, q, k))
+
+
+@pytest.mark.parametrize("nq", [1, 3, 4, 15, 16, 17, 40])
+def test_matrix_query_tile_batch_sizes_and_degenerate_inputs(qd, nq):
+    # small batches (3 or more queries take the matrix query tile by default):
+    # every batch size around the 16-query tile, all-zero, all-one and dense
+    # rows and queries (|q| = 0 and 4096, overlap counts up to 4096), k up to
+    # the 64-entry limit; equal to the oracle and to the vector-ALU scan
+    db = synth.gen_db(20_011, 1021)
+    db[777:807] = _degenerate_rows(30, 1022)
+    q, _ = synth.gen_queries(db, nq, 2021, 0.1, 0.6)
+    if nq >= 3:
+        q[:3] = _degenerate_rows(3, 1023)
+    for k in (1, 10, 64):
+        a = qd.knn_bruteforce(_t(db), _t(q), k, query_tile=qd.QUERY_TILE_MATRIX)
+        b = qd.knn_bruteforce(_t(db), _t(q), k, query_tile=16)
+        for x, y in zip(a, b):
+            assert np.array_equal(x.cpu().numpy(), y.cpu().numpy())
+        _same(a, oracle.knn_brute(db, q, k))
+        if nq >= 3:
+            _same(qd.knn_bruteforce(_t(db), _t(q), k), oracle.knn_brute(db, q, k))
 
 
 def test_matrix_core_path_overflow_falls_back_exactly(qd):
