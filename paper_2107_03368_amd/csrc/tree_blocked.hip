@@ -813,7 +813,13 @@ __global__ __launch_bounds__(256) void eval_short_kernel(const uint4 *__restrict
 // streamed: the next tile's first two windows are staged during the current
 // tile's last two, and its metadata is fetched during the current tile, one
 // dependent load per window, so the matrix cores do not wait for a tile to
-// start.
+// start.  The metadata of consecutive tiles alternates between two LDS
+// copies, so no barrier closes a tile: a wave that finishes its epilogue
+// goes on to the next tile's first window while others still test their
+// pairs (the window buffers are free: every wave read them before the last
+// window's barrier).  A wave's passing pairs claim their candidate slots
+// (the atomics) at the end of its epilogue and are written during the next
+// tile's first window, once the slots have come back.
 __global__ __launch_bounds__(mt::kThreads) void eval_kernel(const uint4 *__restrict__ q, const uint4 *__restrict__ sorted,
                                                             uint64_t n, uint32_t nqp, const uint32_t *__restrict__ ntiles,
                                                             const uint16_t *__restrict__ list,
@@ -824,8 +830,9 @@ __global__ __launch_bounds__(mt::kThreads) void eval_kernel(const uint4 *__restr
                                                             const uint32_t *__restrict__ thrk,
                                                             uint32_t *__restrict__ ccnt, u64 *__restrict__ cand) {
     __shared__ mt::Smem sm;
-    __shared__ uint32_t s_qi[mt::MA], s_pq[mt::MA], s_th[mt::MA], s_tp[mt::MB];
-    __shared__ float s_cmin[mt::MA];  // per query slot: the least overlap that can reach its k-th key
+    // two copies (tiles alternate): query slot's query, |q|, k-th key; row's |t|
+    __shared__ uint32_t s_qi[2][mt::MA], s_pq[2][mt::MA], s_th[2][mt::MA], s_tp[2][mt::MB];
+    __shared__ float s_cmin[2][mt::MA];  // per query slot: the least overlap that can reach its k-th key
     // per wave: the tile's passing (query, key, row) entries, appended in order
     // and written out together, so the candidate slots' atomics overlap
     // instead of waiting one after another
@@ -882,14 +889,14 @@ __global__ __launch_bounds__(mt::kThreads) void eval_kernel(const uint4 *__restr
         const uint64_t r0 = (uint64_t)in.x * kBlk;
         return arow ? q + (uint64_t)qi * 32 : sorted + (ok ? r0 + (r - mt::MA) : 0) * 32;
     };
-    auto publish = [&](float cmin) {  // read after the next barrier
+    auto publish = [&](float cmin, int pb) {  // read after the next barrier
         if (arow) {
-            s_qi[r] = qi;
-            s_pq[r] = pq;
-            s_th[r] = th;
-            s_cmin[r] = cmin;
+            s_qi[pb][r] = qi;
+            s_pq[pb][r] = pq;
+            s_th[pb][r] = th;
+            s_cmin[pb][r] = cmin;
         } else {
-            s_tp[r - mt::MA] = tp;
+            s_tp[pb][r - mt::MA] = tp;
         }
     };
 
@@ -904,9 +911,20 @@ __global__ __launch_bounds__(mt::kThreads) void eval_kernel(const uint4 *__restr
     uint4 cur = info;
     const uint4 *row = row_of(cur);
     bool cur_ok = ok;
-    publish(cmin_of(cur));
+    int par = 0;  // metadata copy of the current tile
+    publish(cmin_of(cur), par);
     mt::Stream st;
     mt::stream_begin(row, !cur_ok, sm, st);  // its barrier also publishes the metadata
+    const int wv = r >> 6, lane = r & 63;
+    uint32_t (*cq)[3] = s_cq[wv];
+    // the previous tile's passing pairs still to be written: entry `lane` of
+    // this wave's queue, its claimed slot and its row's original index
+    uint32_t dn = 0, dpos = 0, dperm = 0;
+    auto store_claimed = [&]() {
+        if ((uint32_t)lane < dn && dpos < kCap)
+            cand[(uint64_t)cq[lane][0] * kCap + dpos] = ((u64)cq[lane][1] << 32) | dperm;
+        dn = 0;
+    };
     for (;;) {
         // tiles of this workgroup only run out at the end of its XCD's range
         const uint64_t vn = v + gridDim.x;
@@ -921,6 +939,7 @@ __global__ __launch_bounds__(mt::kThreads) void eval_kernel(const uint4 *__restr
         // waited for every earlier load), then issue the next loads
         bool nzero = true;
         mt::stream_tile(row, !cur_ok, nrow, nzero, sm, st, acc, [&](int win) {
+            if (win == 0) store_claimed();
             if (win == 1) info = pa;
             if (win == 2) take_b(info);
             if (win == 3) {
@@ -936,8 +955,8 @@ __global__ __launch_bounds__(mt::kThreads) void eval_kernel(const uint4 *__restr
         });
         const uint64_t r0 = (uint64_t)cur.x * kBlk;
         const uint32_t m = cur.z;
-        const int wv = r >> 6, lane = r & 63;
-        uint32_t (*cq)[3] = s_cq[wv];
+        const uint32_t *t_qi = s_qi[par], *t_pq = s_pq[par], *t_th = s_th[par], *t_tp = s_tp[par];
+        const float *t_cmin = s_cmin[par];
         uint32_t nq = 0;  // entries in this wave's queue (the same in every lane)
         auto flush = [&]() {
             for (uint32_t e = lane; e < nq; e += 64) {
@@ -957,18 +976,18 @@ __global__ __launch_bounds__(mt::kThreads) void eval_kernel(const uint4 *__restr
                 // most (query, row) pairs miss the k-th key by far: test this
                 // lane's 4 rows at once against the least useful overlap
                 const float mx = fmaxf(fmaxf(acc[a][0][rr], acc[a][1][rr]), fmaxf(acc[a][2][rr], acc[a][3][rr]));
-                const bool act = mx >= s_cmin[i] && i < m;
+                const bool act = mx >= t_cmin[i] && i < m;
                 if (ballot(act) == 0) continue;
-                const uint32_t qk = s_qi[i];
-                const uint32_t pk = s_pq[i];
+                const uint32_t qk = t_qi[i];
+                const uint32_t pk = t_pq[i];
                 const uint32_t wa = weight_a(pk), wb = weight_b(pk);
-                const uint32_t tk = s_th[i];
+                const uint32_t tk = t_th[i];
 #pragma unroll
                 for (int bb = 0; bb < 4; bb++) {
                     const int bi = mt::acc_brow(bb);
                     const uint64_t rw = r0 + bi;
                     const uint32_t C = mt::count(acc[a][bb][rr]);
-                    const uint32_t K = (pk - C) * wb + (s_tp[bi] - C) * wa;
+                    const uint32_t K = (pk - C) * wb + (t_tp[bi] - C) * wa;
                     const bool pass = act && rw < n && K <= tk;
                     const u64 pm = ballot(pass);
                     if (pass) {
@@ -982,10 +1001,22 @@ __global__ __launch_bounds__(mt::kThreads) void eval_kernel(const uint4 *__restr
                 if (nq > kQueue - 256) flush();  // the next group adds at most 4 x 64
             }
         }
-        flush();
-        __syncthreads();  // the metadata is rewritten next
-        if (!more) break;
-        publish(ncmin);
+        if (nq > 64) {
+            flush();
+        } else {  // claim the slots now, write them during the next tile
+            if ((uint32_t)lane < nq) {
+                dpos = atomicAdd(&ccnt[cq[lane][0]], 1u);
+                dperm = perm[cq[lane][2]];
+            }
+            dn = nq;
+            nq = 0;
+        }
+        if (!more) {
+            store_claimed();
+            break;
+        }
+        par ^= 1;
+        publish(ncmin, par);  // the other copy: this tile's may still be read
         cur = info;
         row = nrow;
         cur_ok = nok;
