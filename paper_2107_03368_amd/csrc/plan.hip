@@ -322,9 +322,10 @@ extern "C" int qd_autotune(qd_tree_t t, const uint64_t *d_db, uint64_t n, const 
     std::vector<qd_tuning> cand;
     if (t) {
         for (int order : {QD_ORDER_BEST_FIRST, QD_ORDER_DEPTH_FIRST})
-            for (uint32_t wpc : {4u, 8u, 16u, 32u}) {
+            for (uint32_t wpc : {4u, 8u, 12u, 16u, 32u}) {
                 if (!(mask & (1u << order))) continue;
-                if (order == QD_ORDER_BEST_FIRST && wpc > 8) continue;  // LDS holds 8 best-first waves per CU
+                // best-first: registers hold 12 waves per CU; depth-first: 16
+                if (order == QD_ORDER_BEST_FIRST ? wpc > 12 : wpc == 12) continue;
                 cand.push_back({1, (qd_order)order, wpc, 0, 0.f, 0, 0, 0, 0});
             }
         // the blocked order's round schedule around its default (16 blocks in

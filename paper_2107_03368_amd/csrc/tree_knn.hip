@@ -17,13 +17,14 @@
 // Frontier orders:
 //  best-first (the paper's priority queue): a bucket queue on
 //    floor(Kb / 2wB) (2 levels of A_lb per bucket for the sum-image bound
-//    alone: the buckets' state then takes half the LDS, so 12 waves fit on a
-//    CU instead of 8); the search stops once the popped bucket's lower end
-//    exceeds the k-th key, and a popped node above the key is skipped, so the
-//    result stays exact.  Each bucket is a stack of 16-entry chunks in the
-//    wave's global workspace, its (chunk, fill) word in LDS, and a 2048-bit
-//    occupancy map spread over the 64 lanes finds the lowest non-empty bucket
-//    with one ballot.  Only lane 0 touches the chunk memory.
+//    alone: the buckets' state then takes half the LDS, so 16 waves fit on a
+//    CU instead of 8; registers hold 12); the search stops once the popped
+//    bucket's lower end exceeds the k-th key, and a popped node above the key
+//    is skipped, so the result stays exact.  Each bucket is a stack of
+//    16-entry chunks in the wave's global workspace, its (chunk, fill) word in
+//    LDS, and a 2048-bit occupancy map spread over the 64 lanes finds the
+//    lowest non-empty bucket with one ballot.  Lane 0 writes the chunks; a
+//    chunk is read back whole, one lane per entry.
 //  depth-first: a stack in LDS; at every expansion the preferred child is
 //    visited first (lower bound, or higher learned score where scores are
 //    given); popped nodes are re-checked against the k-th key and skipped
@@ -47,8 +48,10 @@ constexpr int kMaxStack = 256;
 // Best-first: entries of the bucket being popped live in a small LDS stack of
 // the wave ("hot" bucket) while it has room; the other buckets' entries live
 // in the wave's chunks in global memory.  A child's bound is never below its
-// parent's, so pushes never go below the bucket being popped, and most pops
-// take an entry from LDS instead of waiting for global memory.
+// parent's, so pushes never go below the bucket being popped.  When a bucket
+// becomes the hot one, its newest chunk moves to the LDS stack in one load,
+// so every pop takes an entry from LDS and a chunk costs one wait for global
+// memory instead of one per entry.
 constexpr uint32_t kHot = 32;
 
 struct TreeView {
@@ -249,45 +252,38 @@ __global__ __launch_bounds__(kBlock) void tree_knn_kernel(TreeView T, const uint
                 const int L = __builtin_ctzll(nz);
                 const uint32_t b = 64u * (uint32_t)L + (uint32_t)__builtin_ctzll(readlane64(occ, L));
                 floor_kb = b * kBucketLevels * wb;
-                if (b == hot_b && readfirst((uint32_t)sp) > 0) {
-                    // the hot bucket's newest entry, from LDS
-                    sp = (int)readfirst((uint32_t)sp - 1);
-                    e = readlane64(lane == 0 ? stack[sp] : 0ull, 0);
-                    ninfo = readlane64(lane == 0 ? sinfo[sp] : 0ull, 0);
-                    // once the stack is empty, the bucket is empty unless its chunks still hold entries
-                    const bool tb = (readlane64(touched, (int)(b >> 6)) >> (b & 63)) & 1ull;
-                    const uint32_t fill = readfirst(sp != 0 ? 1u : (tb && lane == 0 ? bstate[b] & 31u : 0u));
-                    occ &= fill == 0 && lane == L ? ~(1ull << (b & 63)) : ~0ull;
-                } else {
+                if (!(b == hot_b && readfirst((uint32_t)sp) > 0)) {
                     // the bucket's entries are in its chunks; it becomes the hot
-                    // bucket (the LDS stack is empty: buckets below hot_b are empty)
+                    // bucket (the LDS stack is empty: buckets below hot_b are
+                    // empty), and its newest chunk moves to the LDS stack at
+                    // once, one lane per entry: one wait for up to kChunk pops
                     hot_b = b;
-                    u64 got = 0, gin = 0;
-                    uint32_t emptied = 0, freed = kNone;
+                    const uint32_t st = readfirst(bstate[b]);
+                    const uint32_t c = st >> 5, f = st & 31u;  // f >= 1: the bucket is not empty
+                    const uint32_t pc = readfirst(myprev[c]);
+                    if ((uint32_t)lane < f) {
+                        stack[lane] = mypool[(uint64_t)c * kChunk + lane];
+                        sinfo[lane] = myinfo[(uint64_t)c * kChunk + lane];
+                    }
                     if (lane == 0) {
-                        const uint32_t st = bstate[b];
-                        const uint32_t c = st >> 5, f = (st & 31u) - 1;
-                        got = mypool[(uint64_t)c * kChunk + f];
-                        gin = myinfo[(uint64_t)c * kChunk + f];
-                        if (f == 0) {
-                            const uint32_t pc = myprev[c];
-                            if (pc == kNone) {
-                                bstate[b] = c << 5;  // keep the emptied chunk for this bucket
-                                emptied = 1;
-                            } else {
-                                bstate[b] = (pc << 5) | kChunk;
-                                myfree[nfree] = c;
-                                freed = c;
-                            }
+                        if (pc == kNone) {
+                            bstate[b] = c << 5;  // keep the emptied chunk for this bucket
                         } else {
-                            bstate[b] = (c << 5) | f;
+                            bstate[b] = (pc << 5) | kChunk;
+                            myfree[nfree] = c;
                         }
                     }
-                    e = readlane64(got, 0);
-                    ninfo = readlane64(gin, 0);
-                    if (readfirst(freed) != kNone) nfree++;
-                    occ &= readfirst(emptied) && lane == L ? ~(1ull << (b & 63)) : ~0ull;
+                    if (pc != kNone) nfree++;
+                    sp = (int)f;
                 }
+                // the hot bucket's newest entry, from LDS
+                sp = (int)readfirst((uint32_t)sp - 1);
+                e = readlane64(lane == 0 ? stack[sp] : 0ull, 0);
+                ninfo = readlane64(lane == 0 ? sinfo[sp] : 0ull, 0);
+                // once the stack is empty, the bucket is empty unless its chunks still hold entries
+                const bool tb = (readlane64(touched, (int)(b >> 6)) >> (b & 63)) & 1ull;
+                const uint32_t fill = readfirst(sp != 0 ? 1u : (tb && lane == 0 ? bstate[b] & 31u : 0u));
+                occ &= fill == 0 && lane == L ? ~(1ull << (b & 63)) : ~0ull;
             } else {
                 if (readfirst((uint32_t)sp) == 0) break;
                 sp = (int)readfirst((uint32_t)sp - 1);

@@ -36,6 +36,12 @@ def _same(res, ref, rows=None):
     assert np.array_equal(extra, ref.extra)
     assert np.array_equal(dist, ref.dist)
 
+def _sample(fixed, nq, seed, extra=59):
+    """Query rows the oracle checks: the given ones and `extra` more at random."""
+    rng = np.random.default_rng(seed)
+    return np.unique(np.concatenate([np.array(fixed), rng.choice(nq, extra, replace=False)]))
+
+
 
 @pytest.mark.parametrize("k", [1, 10])
 def test_small_workload_matches_oracle(qd, small_db, small_queries, k):
@@ -100,7 +106,7 @@ def test_1m_workload_sampled_queries(qd, db_1m, k):
     # benchmark uses; the oracle scores a sample of the queries
     q, _ = synth.gen_queries(db_1m, 4096, 2001, 0.1, 0.6)
     res = qd.knn_bruteforce(_t(db_1m), _t(q), k)
-    rows = np.array([0, 1, 777, 2048, 4095])
+    rows = _sample([0, 1, 777, 2048, 4095], 4096, 31)
     ref = oracle.knn_brute(db_1m, q[rows], k)
     _same(res, ref, rows)
 

@@ -34,6 +34,12 @@ def _same(res, ref, rows=None):
     assert np.array_equal(extra, ref.extra)
     assert np.array_equal(dist, ref.dist)
 
+def _sample(fixed, nq, seed, extra=59):
+    """Query rows the oracle checks: the given ones and `extra` more at random."""
+    rng = np.random.default_rng(seed)
+    return np.unique(np.concatenate([np.array(fixed), rng.choice(nq, extra, replace=False)]))
+
+
 
 def _same_tree(gt, ot):
     assert gt["child"].shape[0] == ot.n_nodes
@@ -163,7 +169,7 @@ def test_build_1m_sampled_nodes(tree_1m):
 def test_search_1m_sampled_queries(qd, tree_1m, k):
     db, tree = tree_1m
     q, _ = synth.gen_queries(db, 4096, 2001, 0.1, 0.6)
-    rows = np.array([0, 5, 1000, 3333, 4095])
+    rows = _sample([0, 5, 1000, 3333, 4095], 4096, 32)
     ref = oracle.knn_brute(db, q[rows], k)
     best = qd.knn_tree(tree, _t(q), k, totals=True)
     _same(best, ref, rows)

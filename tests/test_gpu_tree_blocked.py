@@ -40,6 +40,12 @@ def _same(res, ref, rows=None):
     assert np.array_equal(extra, ref.extra)
     assert np.array_equal(dist, ref.dist)
 
+def _sample(fixed, nq, seed, extra=59):
+    """Query rows the oracle checks: the given ones and `extra` more at random."""
+    rng = np.random.default_rng(seed)
+    return np.unique(np.concatenate([np.array(fixed), rng.choice(nq, extra, replace=False)]))
+
+
 
 @pytest.mark.parametrize("k", [1, 10, 50])
 def test_blocked_matches_oracle_10k(qd, small_db, small_queries, k):
@@ -171,7 +177,7 @@ def test_blocked_several_batches(qd):
     ref_gpu = qd.knn_bruteforce(_t(db), _t(q), 10)
     for a, b in zip(_np(res), _np(ref_gpu)):
         assert np.array_equal(a, b)
-    rows = np.array([0, 1, 16_383, 16_384, 16_499])
+    rows = _sample([0, 1, 16_383, 16_384, 16_499], 16_500, 33)
     _same(res, oracle.knn_brute(db, q[rows], 10), rows)
 
 
@@ -189,7 +195,7 @@ def test_blocked_1m(qd, tree_1m, k):
     best = qd.knn_tree(tree, _t(q), k)
     for a, b in zip(_np(res), _np(best)):
         assert np.array_equal(a, b)
-    rows = np.array([0, 7, 2048, 4095])
+    rows = _sample([0, 7, 2048, 4095], 4096, 34)
     _same(res, oracle.knn_brute(db, q[rows], k), rows)
 
 
