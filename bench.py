@@ -54,14 +54,14 @@ ROW_BYTES = 512
 TRAIN_QUERIES, TRAIN_BATCH, TRAIN_EPOCHS, TRAIN_LR, N_SCORED = 4096, 32, 8, 2e-3, 2047
 # HBM bytes per launch of the matrix-core kernels at the 10M x 8,192 workload,
 # from the FETCH_SIZE / WRITE_SIZE counters (KiB) scaled by what they read for a
-# 1 GiB device copy (FETCH 524,315 KiB, WRITE 1,048,576 KiB); drop an entry
+# 1 GiB device copy (FETCH 524,316 KiB, WRITE 1,048,576 KiB); drop an entry
 # when its kernel changes
 TRAFFIC_DETAIL = {
     # scan_mfma_kernel at 10M x 8,192: the main launch (not the threshold sample's)
-    "scan_mfma_kernel": {"read_bytes": 20_080_518 * 2 * 1024, "write_bytes": 543_207 * 1024,
+    "scan_mfma_kernel": {"read_bytes": 20_080_518 * 2 * 1024, "write_bytes": 543_240 * 1024,
                          "algorithmic_read_bytes": 5.124e9, "counter_scale": {"FETCH_SIZE": 2.0, "WRITE_SIZE": 1.0}},
     # eval_kernel at 10M x 8,192, k = 10: the average of the 4 launches of one search
-    "eval_kernel": {"read_bytes": 2_322_708 * 2 * 1024, "write_bytes": 126_892 * 1024,
+    "eval_kernel": {"read_bytes": 2_324_874 * 2 * 1024, "write_bytes": 128_475 * 1024,
                     "counter_scale": {"FETCH_SIZE": 2.0, "WRITE_SIZE": 1.0}},
 }
 TRAFFIC = {kname: d["read_bytes"] + d["write_bytes"] for kname, d in TRAFFIC_DETAIL.items()}
