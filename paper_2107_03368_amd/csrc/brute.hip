@@ -138,16 +138,19 @@ __global__ __launch_bounds__(kBlock) void scan_small_mfma_kernel(const uint4 *__
                                                                  uint64_t rows_per_part, u64 *__restrict__ part,
                                                                  const uint32_t *__restrict__ nq_dev) {
     extern __shared__ u64 lists_lds[];  // kWavesPerBlock x kSmallQ x k keys
-    if (nq_dev) {
-        nq = *nq_dev;  // size given on the device (captured graphs)
-        if ((blockIdx.x % n_qtiles) * kSmallQ >= nq) return;  // whole block
-    }
     const int lane = lane_id();
     const int li = lane & 15, lg = lane >> 4;
-    const uint32_t qtile = blockIdx.x % n_qtiles;
+    // wave w serves query tile w % n_qtiles over row slice w / n_qtiles, so
+    // the waves of a workgroup share their rows when there are several tiles
     const uint32_t wv = threadIdx.x >> 6;
-    const uint32_t p = readfirst((blockIdx.x / n_qtiles) * kWavesPerBlock + wv);
+    const uint64_t w = (uint64_t)blockIdx.x * kWavesPerBlock + wv;
+    const uint32_t qtile = readfirst((uint32_t)(w % n_qtiles));
+    const uint32_t p = readfirst((uint32_t)(w / n_qtiles));
     if (p >= n_parts) return;  // whole wave
+    if (nq_dev) {
+        nq = *nq_dev;  // size given on the device (captured graphs)
+        if (qtile * kSmallQ >= nq) return;  // whole wave
+    }
     const uint64_t r0 = (uint64_t)p * rows_per_part;
     const uint64_t r1 = r0 + rows_per_part < n ? r0 + rows_per_part : n;
     u64 *wl = lists_lds + (size_t)wv * kSmallQ * k;
@@ -398,7 +401,8 @@ BruteLaunch brute_launch_shape(uint64_t n, uint32_t nq, uint32_t k, uint32_t qt_
     rpp = (rpp + step - 1) / step * step;
     sh.rows_per_part = rpp;
     sh.n_parts = (uint32_t)((n + rpp - 1) / rpp);
-    sh.blocks = (uint64_t)((sh.n_parts + kWavesPerBlock - 1) / kWavesPerBlock) * sh.n_qtiles;
+    sh.blocks = matrix ? ((uint64_t)sh.n_parts * sh.n_qtiles + kWavesPerBlock - 1) / kWavesPerBlock
+                       : (uint64_t)((sh.n_parts + kWavesPerBlock - 1) / kWavesPerBlock) * sh.n_qtiles;
     sh.part_bytes = (size_t)(nq ? nq : 1) * sh.n_parts * k * sizeof(u64);
     return sh;
 }
