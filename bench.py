@@ -626,9 +626,16 @@ def smallbatch_main(args, w, dev):
                 ms, cnt = qd.profile_read("planes_scan")
                 res["planes_scan_ms"] = ms / max(cnt, 1)
             else:
+                # the kernel that passes over all rows: the register-tiled scan, the
+                # 16-query matrix tiles, or (from 160 queries) the 256 x 256 tiles,
+                # whose call also scans a sample of the rows first
+                (ms_b, cnt_b) = qd.profile_read("wh_scan_mfma")
                 (ms_v, cnt_v), (ms_m, cnt_m) = qd.profile_read("wh_scan_topk"), qd.profile_read("wh_scan_small_mfma")
-                res["rows_scan_kernel"] = "scan_small_mfma_kernel" if cnt_m else "scan_topk_kernel"
-                res["rows_scan_ms"] = (ms_v + ms_m) / max(cnt_v + cnt_m, 1)
+                if cnt_b:
+                    res["rows_scan_kernel"], res["rows_scan_ms"] = "scan_mfma_kernel", ms_b / cnt_b
+                else:
+                    res["rows_scan_kernel"] = "scan_small_mfma_kernel" if cnt_m else "scan_topk_kernel"
+                    res["rows_scan_ms"] = (ms_v + ms_m) / max(cnt_v + cnt_m, 1)
                 res["rows_scan_gbs"] = n * ROW_BYTES / (res["rows_scan_ms"] * 1e-3) / 1e9
             qd.profile_enable(False)
             res[name + "_ms"] = dt * 1e3

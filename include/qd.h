@@ -470,7 +470,7 @@ int qd_model_train(qd_model_t m, qd_tree_t t, const uint64_t *d_q, uint32_t nq, 
  * batch (max_qdesc descriptors in max_qobj query objects).  params picks the
  * tree's order (best-first, depth-first or blocked, with occupancy or round
  * schedule; no model, scores or traces); query_tile picks the sequential
- * scan: 0 = the matrix cores when max_qdesc >= 512 over >= 65,536 rows (as
+ * scan: 0 = the matrix cores when max_qdesc >= 160 over >= 65,536 rows (as
  * qd_knn_bruteforce decides for a batch of max_qdesc), else the row scan with
  * that query tile (as in qd_knn_bruteforce_shaped; 0 = the one
  * qd_knn_bruteforce picks for max_qdesc queries).  It allocates all its device memory at

@@ -57,8 +57,11 @@ int brute_launch(const BruteLaunch &L, u64 *part, const uint64_t *d_db, uint64_t
 // The matrix-core sequential search on a workspace the caller owns.  Level
 // l searches the first rows[l] rows; every level but the last is a
 // matrix-core pass whose candidate bounds come from the next level (a
-// sample), the last level is the register-tiled scan.
-constexpr uint32_t kMfmaMinQueries = 512;  // smaller batches take the register-tiled scan
+// sample), the last level is the row scan.  Smaller batches take the row
+// scan alone: its 16-query matrix tiles make one pass over the rows per tile,
+// while the 256 x 256 tiles here cost the same for 1 to 256 queries; the two
+// break even at about 160 queries.
+constexpr uint32_t kMfmaMinQueries = 160;
 constexpr uint64_t kMfmaMinRows = 1u << 16;
 constexpr int kMaxLevels = 4;
 struct MfmaLayout {

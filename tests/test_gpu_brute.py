@@ -121,18 +121,19 @@ def _degenerate_rows(n, seed):
     return dense
 
 
-def test_matrix_core_path_equals_register_scan_and_oracle(qd):
-    # >= 512 queries over >= 65,536 rows take the FP4 matrix-core path by
+@pytest.mark.parametrize("nq", [600, 161])
+def test_matrix_core_path_equals_register_scan_and_oracle(qd, nq):
+    # >= 160 queries over >= 65,536 rows take the FP4 matrix-core path by
     # default; the register-tiled scan (an explicit query tile) must agree bit
     # for bit, and the oracle on every query.  Among them: all-zero and all-one
     # queries (|q| = 0 and 4096, the ends of the weights) and all-zero,
     # all-one and dense rows (overlap counts up to 4096)
     db = synth.gen_db(100_003, 1011)  # ragged against the 256-row tile
     db[5000:5030] = _degenerate_rows(30, 1013)
-    q, _ = synth.gen_queries(db, 600, 2011, 0.1, 0.6)  # ragged against the 256-query tile
+    q, _ = synth.gen_queries(db, nq, 2011, 0.1, 0.6)  # ragged against the 256-query tile
     q[100:120] = 0
-    q[300:320] = np.uint64(0xFFFFFFFFFFFFFFFF)
-    q[590:596] = _degenerate_rows(6, 1014)
+    q[130:150] = np.uint64(0xFFFFFFFFFFFFFFFF)
+    q[nq - 10:nq - 4] = _degenerate_rows(6, 1014)
     for k in (1, 10, 50):
         a = qd.knn_bruteforce(_t(db), _t(q), k)
         b = qd.knn_bruteforce(_t(db), _t(q), k, query_tile=16)

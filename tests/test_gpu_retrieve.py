@@ -101,12 +101,12 @@ def test_objects_workload_full_scale(qd):
 
 @pytest.mark.parametrize("path", ["best_first", "blocked", "sequential", "matrix_cores"])
 def test_plan_graph_replays_match_direct_retrieval(qd, path):
-    # the matrix-core scan needs >= 65,536 rows and >= 512 descriptors in the
+    # the matrix-core scan needs >= 65,536 rows and >= 160 descriptors in the
     # largest batch; the plan keeps it for the smaller batches too
     import torch
     n_obj = 280 if path == "matrix_cores" else 40
     db, obj, off, q, qobj = _workload(n_obj, 250 if path == "matrix_cores" else 300, 24, 20, 120, 91)
-    assert path != "matrix_cores" or (len(db) >= 65_536 and len(q) >= 512)
+    assert path != "matrix_cores" or (len(db) >= 65_536 and len(q) >= 160)
     use_tree = path in ("best_first", "blocked")
     order = qd.ORDER_BLOCKED if path == "blocked" else qd.ORDER_BEST_FIRST
     tree = qd.tree_build(_t(db)) if use_tree else None
