@@ -163,22 +163,7 @@ def main():
             paths["tree_blocked_descent"] = lambda: qd.knn_tree(tree, qt, k, order=qd.ORDER_BLOCKED,
                                                                 start=qd.START_BOUND_DESCENT)
         if "learned" in wanted:
-            # offline: train the frontier-order model on traces of the exact search over
-            # the 1M-descriptor database (seed 1001) with its own queries
-            t0 = time.time()
-            tdb = synth.gen_db(1_000_000, 1001)
-            tq, _ = synth.gen_queries(tdb, TRAIN_QUERIES, 2001, 0.1, 0.6)
-            ttree = qd.tree_build(torch.from_numpy(tdb.view(np.int64)).to(dev))
-            model = qd.Model(torch.from_numpy(synth.uniform_f32(qd.MLP_NPARAMS, 3003, -0.05, 0.05)).to(dev))
-            nb = (TRAIN_QUERIES + TRAIN_BATCH - 1) // TRAIN_BATCH
-            order = synth.permutation(nb, 3004)
-            losses, npairs = qd.model_train(model, ttree, torch.from_numpy(tq.view(np.int64)).to(dev), k, N_SCORED,
-                                            TRAIN_EPOCHS, TRAIN_BATCH, TRAIN_LR, batch_order=order)
-            train = {"seconds": time.time() - t0, "pairs": npairs, "epochs": TRAIN_EPOCHS,
-                     "loss_first": float(np.nanmean(losses[:nb])), "loss_last": float(np.nanmean(losses[-nb:]))}
-            del ttree, tdb
-            log(f"order model trained on {npairs} traced pairs in {train['seconds']:.1f}s, loss "
-                f"{train['loss_first']:.4f} -> {train['loss_last']:.4f}")
+            model, train = train_order_model(qd, dev, k)
             n_scored = min(N_SCORED, tree.n_nodes)
             # per-query depth-first search in the model's order (the library scores
             # the top n_scored nodes), and the blocked search starting where the
@@ -662,6 +647,29 @@ def smallbatch_main(args, w, dev):
     print(json.dumps(out), flush=True)
 
 
+def train_order_model(qd, dev, k):
+    """Offline: the frontier-order model trained on traces of the exact search
+    over the 1M-descriptor database (seed 1001) with its own queries."""
+    import torch
+    import synth
+
+    t0 = time.time()
+    tdb = synth.gen_db(1_000_000, 1001)
+    tq, _ = synth.gen_queries(tdb, TRAIN_QUERIES, 2001, 0.1, 0.6)
+    ttree = qd.tree_build(torch.from_numpy(tdb.view(np.int64)).to(dev))
+    model = qd.Model(torch.from_numpy(synth.uniform_f32(qd.MLP_NPARAMS, 3003, -0.05, 0.05)).to(dev))
+    nb = (TRAIN_QUERIES + TRAIN_BATCH - 1) // TRAIN_BATCH
+    order = synth.permutation(nb, 3004)
+    losses, npairs = qd.model_train(model, ttree, torch.from_numpy(tq.view(np.int64)).to(dev), k, N_SCORED,
+                                    TRAIN_EPOCHS, TRAIN_BATCH, TRAIN_LR, batch_order=order)
+    train = {"seconds": time.time() - t0, "pairs": npairs, "epochs": TRAIN_EPOCHS,
+             "loss_first": float(np.nanmean(losses[:nb])), "loss_last": float(np.nanmean(losses[-nb:]))}
+    del ttree, tdb
+    log(f"order model trained on {npairs} traced pairs in {train['seconds']:.1f}s, loss "
+        f"{train['loss_first']:.4f} -> {train['loss_last']:.4f}")
+    return model, train
+
+
 def stream_main(args, w, dev):
     """Serving: query objects arrive as a Poisson stream; the server takes all
     waiting objects (whole objects, up to max_batch descriptors) as one batch,
@@ -704,6 +712,11 @@ def stream_main(args, w, dev):
     plan_tree = qd.Plan(objt, w["n_obj"], max_qdesc=max_batch, max_qobj=max_objs, k=k, threshold=10, tree=tree,
                         order=qd.ORDER_BLOCKED, schedule=tuned["schedule"], start=tuned["start"])
     plan_seq = qd.Plan(objt, w["n_obj"], max_qdesc=max_batch, max_qobj=max_objs, k=k, threshold=10, db=dbt)
+    # the learned order: round 1 of each batch's blocked search starts where the
+    # model (trained offline on the 1M database's traces) leads
+    model, train = train_order_model(qd, dev, k)
+    plan_learned = qd.Plan(objt, w["n_obj"], max_qdesc=max_batch, max_qobj=max_objs, k=k, threshold=10, tree=tree,
+                           order=qd.ORDER_BLOCKED, schedule=tuned["schedule"], model=model)
 
     def plan_path(plan):
         def run(o0, o1):
@@ -713,7 +726,8 @@ def stream_main(args, w, dev):
         return run
     paths = {"brute": lambda a, b: qd.knn_bruteforce(dbt, qt[a:b], k),
              "tree_blocked": lambda a, b: qd.knn_tree(tree, qt[a:b], k, order=qd.ORDER_BLOCKED)}
-    plans = {"brute_plan": plan_path(plan_seq), "tree_blocked_plan": plan_path(plan_tree)}
+    plans = {"brute_plan": plan_path(plan_seq), "tree_blocked_plan": plan_path(plan_tree),
+             "tree_blocked_learned_plan": plan_path(plan_learned)}
     # exactness on the first full batch
     ref = [x.cpu() for x in paths["brute"](0, nb0)]
     out = [x.cpu() for x in paths["tree_blocked"](0, nb0)]
@@ -800,6 +814,7 @@ def stream_main(args, w, dev):
                                f"batches of up to {max_batch} descriptors"},
         "tree_build_s": build_s, "paths": result,
         "autotune": {"seconds": tune_s, "sample_descriptors": nb0, "tree": tuned},
+        "order_model_training": train,
     }
     print(json.dumps(out), flush=True)
 

@@ -469,7 +469,9 @@ int qd_model_train(qd_model_t m, qd_tree_t t, const uint64_t *d_q, uint32_t nq, 
  * search over d_db when t is NULL), k, the vote threshold and the largest
  * batch (max_qdesc descriptors in max_qobj query objects).  params picks the
  * tree's order (best-first, depth-first or blocked, with occupancy or round
- * schedule; no model, scores or traces); query_tile picks the sequential
+ * schedule; a model only with the blocked order, where it sets the start of
+ * round 1, its descent running on the plan's memory; no scores or traces);
+ * query_tile picks the sequential
  * scan: 0 = the matrix cores when max_qdesc >= 160 over >= 65,536 rows (as
  * qd_knn_bruteforce decides for a batch of max_qdesc), else the row scan with
  * that query tile (as in qd_knn_bruteforce_shaped; 0 = the one
@@ -485,7 +487,7 @@ int qd_model_train(qd_model_t m, qd_tree_t t, const uint64_t *d_q, uint32_t nq, 
  * inputs into the plan, replays the graph on `stream` and copies the outputs
  * out; it allocates nothing and never waits for the device.  Runs of one
  * plan must not overlap (they share its buffers).  The plan keeps pointers to
- * t, d_db and d_obj_of, which must outlive it.
+ * t, d_db, d_obj_of and params->model, which must outlive it.
  * ------------------------------------------------------------------------- */
 typedef struct qd_plan_s *qd_plan_t;
 

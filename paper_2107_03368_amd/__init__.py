@@ -343,10 +343,11 @@ _sig("qd_retrieve_objects", [_P, _P, _U64, _P, _U32, _P, _U64, _P, _U32, _U32, _
 
 
 def retrieve_objects(qdesc, qoff, obj_of, n_obj, k, threshold=10, tree=None, db=None, order=ORDER_BEST_FIRST,
-                     return_nn=False, schedule=(0, 0, 0)):
+                     return_nn=False, schedule=(0, 0, 0), model=None):
     """Vote histogram (nqo, n_obj), winner (nqo,), descriptors used (nqo,)[, neighbour rows].
 
-    qoff: cuda int64 (nqo+1) CSR offsets into qdesc; obj_of: cuda int16 object id per database row."""
+    qoff: cuda int64 (nqo+1) CSR offsets into qdesc; obj_of: cuda int16 object id per database row.
+    model: the tree search's learned order (depth-first and blocked orders)."""
     _desc(qdesc, "qdesc")
     if tree is None:
         _desc(db, "db")
@@ -357,6 +358,8 @@ def retrieve_objects(qdesc, qoff, obj_of, n_obj, k, threshold=10, tree=None, db=
     used = torch.empty(nqo, dtype=torch.int32, device=dev)
     nn = torch.empty((qdesc.shape[0], k), dtype=torch.int32, device=dev) if return_nn else None
     prm = _SearchParams(order, None, 0, 0, None, 0, *schedule)
+    if model is not None:
+        prm.model = model.handle.value
     rc = _lib.qd_retrieve_objects(tree.handle if tree is not None else None, _ptr(db), 0 if db is None else db.shape[0],
                                   _ptr(obj_of), n_obj, _ptr(qdesc), qdesc.shape[0], _ptr(qoff), nqo, k, threshold,
                                   ctypes.byref(prm), _ptr(votes), _ptr(winner), _ptr(used), _ptr(nn), _stream())
@@ -590,12 +593,16 @@ class Plan:
     recorded in a hipGraph and replayed per run."""
 
     def __init__(self, obj_of, n_obj, max_qdesc, max_qobj, k, threshold=10, tree=None, db=None,
-                 order=ORDER_BEST_FIRST, waves_per_cu=0, query_tile=0, schedule=(0, 0, 0), start=START_LOWEST_BOUND):
+                 order=ORDER_BEST_FIRST, waves_per_cu=0, query_tile=0, schedule=(0, 0, 0), start=START_LOWEST_BOUND,
+                 model=None):
+        """model (blocked order only): round 1 starts where the model leads."""
         if tree is None:
             _desc(db, "db")
-        self._keep = (tree, db, obj_of)  # the plan points into these
+        self._keep = (tree, db, obj_of, model)  # the plan points into these
         prm = _SearchParams(order, None, 0, waves_per_cu, None, 0, *schedule)
         prm.round1_start = start
+        if model is not None:
+            prm.model = model.handle.value
         h = ctypes.c_void_p()
         _check(_lib.qd_plan_create(tree.handle if tree is not None else None, _ptr(db),
                                    0 if db is None else db.shape[0], _ptr(obj_of), n_obj, max_qdesc, max_qobj, k,

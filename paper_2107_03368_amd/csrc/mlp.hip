@@ -574,18 +574,26 @@ extern "C" int qd_model_features(qd_tree_t t, const uint64_t *d_q, const uint32_
 // full gradient goes to d_grads (QD_MLP_NPARAMS) and the mean loss to d_loss;
 // this path needs the pairs as explicit arrays grouped by query (d_qoff).
 // u_pre (nullable): the per-query layer-1 sums u (nq x H), already formed.
+// ws_given (nullable): scratch of mlp_infer_bytes(n_pairs) for an inference
+// with u_pre (no allocation then).
+static size_t mlp_infer_bytes(uint64_t n_pairs) {
+    const uint64_t np = qd::pad64(n_pairs ? n_pairs : 1);
+    return np * qd::H * 4 + np * qd::H * 4 + np * 4 + 64 * 16;
+}
 static int mlp_run(qd_model_t m, const uint64_t *d_q, uint32_t q0, uint32_t nq, qd::PairIdx P,
                    const uint64_t *d_qoff, uint64_t qoff_base, const float *d_feat, uint64_t n_pairs, const float *y,
-                   float *d_scores, float *d_grads, float *d_loss, hipStream_t s, float *u_pre = nullptr) {
+                   float *d_scores, float *d_grads, float *d_loss, hipStream_t s, float *u_pre = nullptr,
+                   char *ws_given = nullptr) {
     using namespace qd;
     const uint64_t np = pad64(n_pairs ? n_pairs : 1);
     const bool train = y != nullptr;
+    if (ws_given && (train || !u_pre)) return fail(QD_ERR_INVALID, "a given scratch serves inference with u only");
     size_t bytes = (u_pre ? 0 : (size_t)nq * H * 4) + np * H * 4 + np * H * 4 + np * 4;
     if (train)
         bytes += np * H * 4 + np * 4 + np * 4 + np * H * 2 + (size_t)H * H * 4 + (size_t)nq * H * 4 +
                  (size_t)kHeadParts * kHeadPartLen * 4 + (size_t)nq * kL1Chunks * kL1PartLen * 4;
-    char *ws = nullptr;
-    QD_HIP_CHECK(hipMallocAsync((void **)&ws, bytes + 64 * 16, s));
+    char *ws = ws_given;
+    if (!ws) QD_HIP_CHECK(hipMallocAsync((void **)&ws, bytes + 64 * 16, s));
     char *c = ws;
     auto take = [&](size_t b) {
         char *r = c;
@@ -634,7 +642,7 @@ static int mlp_run(qd_model_t m, const uint64_t *d_q, uint32_t q0, uint32_t nq, 
                            S.du, d_grads);
         e = hipGetLastError();
     }
-    (void)hipFreeAsync(ws, s);
+    if (!ws_given) (void)hipFreeAsync(ws, s);
     if (e != hipSuccess) return fail(QD_ERR_DEVICE, "mlp kernels: %s", hipGetErrorString(e));
     return QD_OK;
 }
@@ -744,14 +752,22 @@ __global__ void fill_u32_kernel(uint32_t *__restrict__ p, uint32_t n, uint32_t v
 
 }  // namespace
 
+// Scratch of one descent: the per-query layer-1 sums, the level's (query,
+// node) pairs, their features and scores, then the MLP's own scratch.
+static size_t descend_own_bytes(uint32_t nq) {
+    const uint64_t np = 2ull * nq;
+    return (size_t)nq * H * 4 + np * 8 + np * NF * 4 + np * 4 + 5 * 256;
+}
+
+size_t model_descend_bytes(uint32_t nq) { return descend_own_bytes(nq) + mlp_infer_bytes(2ull * nq) + 256; }
+
 int model_descend(qd_model_t m, qd_tree_t t, const uint64_t *d_q, uint32_t nq, uint32_t max_rows, uint32_t *d_node,
-                  hipStream_t s) {
+                  char *ws_given, hipStream_t s) {
     if (check_model(m) != QD_OK || !t) return fail(QD_ERR_INVALID, "null model or tree");
     if (nq == 0) return QD_OK;
     const uint64_t np = 2ull * nq;
-    char *ws = nullptr;
-    const size_t bytes = (size_t)nq * H * 4 + np * 8 + np * NF * 4 + np * 4 + 4 * 256;
-    QD_HIP_CHECK(hipMallocAsync((void **)&ws, bytes, s));
+    char *ws = ws_given;
+    if (!ws) QD_HIP_CHECK(hipMallocAsync((void **)&ws, model_descend_bytes(nq), s));
     char *c = ws;
     auto take = [&](size_t b) {
         char *r = c;
@@ -777,11 +793,11 @@ int model_descend(qd_model_t m, qd_tree_t t, const uint64_t *d_q, uint32_t nq, u
         }
         if (rc == QD_OK)
             rc = mlp_run(m, d_q, 0, nq, PairIdx{pq, pn, 0, 1}, nullptr, 0, feat, np, nullptr, sc, nullptr, nullptr, s,
-                         u);
+                         u, ws + (descend_own_bytes(nq) + 255) / 256 * 256);
         hipLaunchKernelGGL(descend_pick_kernel, g, dim3(256), 0, s, d_node, nq, t->d_child, t->d_count, max_rows, sc);
     }
     if (rc == QD_OK && hipGetLastError() != hipSuccess) rc = fail(QD_ERR_DEVICE, "model descent: launch failed");
-    (void)hipFreeAsync(ws, s);
+    if (!ws_given) (void)hipFreeAsync(ws, s);
     return rc;
 }
 

@@ -93,8 +93,11 @@ extern "C" int qd_plan_create(qd_tree_t t, const uint64_t *d_db, uint64_t n, con
     const int order = params ? (int)params->order : QD_ORDER_BEST_FIRST;
     if (t && order != QD_ORDER_BEST_FIRST && order != QD_ORDER_DEPTH_FIRST && order != QD_ORDER_BLOCKED)
         return fail(QD_ERR_INVALID, "unknown frontier order");
-    if (params && params->model)
-        return fail(QD_ERR_UNSUPPORTED, "a plan takes no model (scoring allocates per call)");
+    // a model sets where the blocked order's first round starts (its descent
+    // runs on the plan's workspace); the depth-first order's scoring
+    // allocates per call
+    if (params && params->model && !(t && order == QD_ORDER_BLOCKED))
+        return fail(QD_ERR_UNSUPPORTED, "a plan takes a model for the blocked order only");
     if (query_tile != 0 && query_tile != 1 && query_tile != 2 && query_tile != 4 && query_tile != 8 &&
         query_tile != 16 && query_tile != QD_QUERY_TILE_MATRIX)
         return fail(QD_ERR_INVALID, "query tile %u not in {0,1,2,4,8,16,QD_QUERY_TILE_MATRIX}", query_tile);
@@ -126,7 +129,7 @@ extern "C" int qd_plan_create(qd_tree_t t, const uint64_t *d_db, uint64_t n, con
     // (0: chosen for the largest batch as qd_knn_bruteforce would)
     const bool mfma = !t && query_tile == 0 && mfma_eligible(n, nqmax, k);
     if (blocked) {
-        KL = blocked_layout(t, nqmax, k);
+        KL = blocked_layout(t, nqmax, k, params && params->model);
         n_batches = (uint32_t)((nqmax + KL.qb - 1) / KL.qb);
         ws_bytes = KL.bytes;
     } else if (mfma) {

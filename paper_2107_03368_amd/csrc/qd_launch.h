@@ -28,12 +28,13 @@ struct BlockedLayout {
     uint32_t qb = 0;
     size_t qpop = 0, lbq = 0, lbb = 0, list = 0, cuts = 0, r1 = 0, rec = 0, thr = 0, ntop = 0, top = 0, ccnt = 0,
            cand = 0, cnt = 0, qr = 0, act = 0, off = 0, voff = 0, ctr = 0, done = 0, fr = 0, tinfo = 0, redo = 0,
-           qst = 0, lnode = 0, gst = 0, fbq = 0, fbr = 0, fbws = 0, bytes = 0;
-    TreeLaunch fb;  // the per-query fallback's launch
+           qst = 0, lnode = 0, gst = 0, fbq = 0, fbr = 0, fbws = 0, mdesc = 0, bytes = 0;
+    bool model = false;  // the layout holds a learned start's descent workspace (at mdesc)
+    TreeLaunch fb;       // the per-query fallback's launch
     int fb_order = QD_ORDER_DEPTH_FIRST;
 };
 int blocked_check(qd_tree_t t, const qd_search_params *p);
-BlockedLayout blocked_layout(qd_tree_t t, uint32_t nq_max, uint32_t k);
+BlockedLayout blocked_layout(qd_tree_t t, uint32_t nq_max, uint32_t k, bool model = false);
 // One batch of nqb queries (at most L.qb); nq_dev (nullable): the batch's
 // size on the device.  graph: no host synchronisation (capturable).
 int blocked_batch(qd_tree_t t, const BlockedLayout &L, char *ws, const uint64_t *d_q, uint32_t nqb,

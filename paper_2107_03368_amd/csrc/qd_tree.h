@@ -43,8 +43,12 @@ void tree_release(qd_tree_s *t);
 // Learned start of the blocked search: d_node[i] = the node reached from the
 // root by entering, at every inner node holding more than max_rows rows, the
 // child the model scores higher for query i (ties: the similar child).
+// ws (nullable): a workspace of model_descend_bytes(nq) the caller owns
+// (nothing is allocated then, so the launches can be captured); without it
+// the call allocates one.
+size_t model_descend_bytes(uint32_t nq);
 int model_descend(qd_model_t m, qd_tree_t t, const uint64_t *d_q, uint32_t nq, uint32_t max_rows, uint32_t *d_node,
-                  hipStream_t s);
+                  char *ws, hipStream_t s);
 int tree_finish(qd_tree_s *t, const std::vector<int32_t> &child, const std::vector<uint32_t> &begin,
                 const std::vector<uint32_t> &count, bool want_pop, hipStream_t s);
 // Block images for the batched search (tree_blocked.hip).

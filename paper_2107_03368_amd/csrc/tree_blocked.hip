@@ -1268,7 +1268,7 @@ int tree_block_images(qd_tree_s *t, hipStream_t s) {
 }
 
 // Workspace of one batch of up to qb queries (offsets into one allocation).
-BlockedLayout blocked_layout(qd_tree_t t, uint32_t nq, uint32_t k) {
+BlockedLayout blocked_layout(qd_tree_t t, uint32_t nq, uint32_t k, bool model) {
     BlockedLayout L;
     const uint64_t nblk = t->n_blk;
     // batch: up to kMaxBatch queries, bound and list matrices within about 12 GiB
@@ -1320,6 +1320,8 @@ BlockedLayout blocked_layout(qd_tree_t t, uint32_t nq, uint32_t k) {
     L.fbq = take(P * 512);
     L.fbr = take(P * k * 16);
     L.fbws = take(L.fb.total());
+    L.model = model;
+    if (model) L.mdesc = take(model_descend_bytes(qb));  // the learned start's descent
     L.bytes = o;
     return L;
 }
@@ -1380,7 +1382,7 @@ int blocked_batch(qd_tree_t t, const BlockedLayout &L, char *ws, const uint64_t 
     // model's (learned order) or the bound's
     const bool descend = model || (p && p->round1_start == QD_START_BOUND_DESCENT);
     if (model) {
-        rc = model_descend(model, t, qq, nqb, n1 * kBlk, lnode, s);
+        rc = model_descend(model, t, qq, nqb, n1 * kBlk, lnode, L.model ? ws + L.mdesc : nullptr, s);
         if (rc != QD_OK) return rc;
     } else if (descend) {
         KernelTimer timer("tree_block_descend", s);
@@ -1480,7 +1482,7 @@ int knn_tree_blocked(qd_tree_t t, const uint64_t *d_q, uint32_t nq, uint32_t k, 
     int rc = blocked_check(t, p);
     if (rc != QD_OK) return rc;
     if (h_stats) *h_stats = qd_stats{0, 0, 0, 0};
-    const BlockedLayout L = blocked_layout(t, nq, k);
+    const BlockedLayout L = blocked_layout(t, nq, k, p && p->model);
     char *ws = nullptr;
     QD_HIP_CHECK(hipMallocAsync((void **)&ws, L.bytes, s));
     unsigned long long *gst = h_stats ? (unsigned long long *)(ws + L.gst) : nullptr;

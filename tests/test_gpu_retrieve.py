@@ -99,26 +99,32 @@ def test_objects_workload_full_scale(qd):
     assert (rw == qobj).mean() >= 0.95  # the workload is retrievable
 
 
-@pytest.mark.parametrize("path", ["best_first", "blocked", "sequential", "matrix_cores"])
+@pytest.mark.parametrize("path", ["best_first", "blocked", "blocked_learned", "sequential", "matrix_cores"])
 def test_plan_graph_replays_match_direct_retrieval(qd, path):
     # the matrix-core scan needs >= 65,536 rows and >= 160 descriptors in the
-    # largest batch; the plan keeps it for the smaller batches too
+    # largest batch; the plan keeps it for the smaller batches too.  With a
+    # model (an untrained one: any model gives exact results), the blocked
+    # order's first round starts where the model leads, its descent recorded
+    # in the graph on the plan's memory
     import torch
     n_obj = 280 if path == "matrix_cores" else 40
     db, obj, off, q, qobj = _workload(n_obj, 250 if path == "matrix_cores" else 300, 24, 20, 120, 91)
     assert path != "matrix_cores" or (len(db) >= 65_536 and len(q) >= 160)
-    use_tree = path in ("best_first", "blocked")
-    order = qd.ORDER_BLOCKED if path == "blocked" else qd.ORDER_BEST_FIRST
+    use_tree = path in ("best_first", "blocked", "blocked_learned")
+    order = qd.ORDER_BLOCKED if path.startswith("blocked") else qd.ORDER_BEST_FIRST
+    model = None
+    if path == "blocked_learned":
+        model = qd.Model(torch.from_numpy(synth.uniform_f32(qd.MLP_NPARAMS, 3101, -0.05, 0.05)).to("cuda:0"))
     tree = qd.tree_build(_t(db)) if use_tree else None
     dbt = None if use_tree else _t(db)
     plan = qd.Plan(_t(obj), n_obj, max_qdesc=len(q), max_qobj=24, k=5, threshold=10, tree=tree, db=dbt, order=order,
-                   query_tile=16 if path == "sequential" else 0)
+                   query_tile=16 if path == "sequential" else 0, model=model)
     # batches of different sizes, with eager library work between the replays
     for lo, hi in ((0, 24), (3, 10), (0, 1), (5, 24)):
         sub = np.asarray(off[lo:hi + 1], np.uint64) - off[lo]
         qs = q[int(off[lo]):int(off[hi])]
         got = plan.run(_t(qs), _t(sub))
-        ref = qd.retrieve_objects(_t(qs), _t(sub), _t(obj), n_obj, 5, 10, tree=tree, db=dbt, order=order)
+        ref = qd.retrieve_objects(_t(qs), _t(sub), _t(obj), n_obj, 5, 10, tree=tree, db=dbt, order=order, model=model)
         torch.cuda.synchronize()
         for a, b in zip(got, ref):
             assert torch.equal(a, b)
@@ -128,24 +134,29 @@ def test_plan_graph_replays_match_direct_retrieval(qd, path):
         assert np.array_equal(got[2].cpu().numpy().view(np.uint32), ru)
 
 
-@pytest.mark.parametrize("start", [0, 1])
+@pytest.mark.parametrize("start", [0, 1, "model"])
 def test_blocked_plan_with_several_batches(qd, start):
     # more descriptors than one blocked batch holds (16,384): the plan records
     # two batches, each reading its size from the device; replays of shrinking
-    # batches (the second batch empty, then a tiny one) with eager work between
+    # batches (the second batch empty, then a tiny one) with eager work between;
+    # round 1 at the lowest bounds, at the bound's descent, or where a model leads
     import torch
     n_obj, per = 25, 200
     db = synth.gen_db(n_obj * per, 97)
     obj = (np.arange(n_obj * per) // per).astype(np.uint16)
     q, _ = synth.gen_queries(db, 20_000, 98, 0.1, 0.6)
     tree = qd.tree_build(_t(db))
+    model = None
+    if start == "model":
+        model = qd.Model(torch.from_numpy(synth.uniform_f32(qd.MLP_NPARAMS, 3102, -0.05, 0.05)).to("cuda:0"))
+        start = 0
     plan = qd.Plan(_t(obj), n_obj, max_qdesc=20_000, max_qobj=4, k=10, threshold=10, tree=tree,
-                   order=qd.ORDER_BLOCKED, start=start)
+                   order=qd.ORDER_BLOCKED, start=start, model=model)
     for nd in (20_000, 16_384, 9, 17_001):
         off = np.array([0, nd // 3, nd // 2, nd], np.uint64)
         got = plan.run(_t(q[:nd]), _t(off))
         ref = qd.retrieve_objects(_t(q[:nd]), _t(off), _t(obj), n_obj, 10, 10, tree=tree, order=qd.ORDER_BLOCKED,
-                                  return_nn=True)
+                                  return_nn=True, model=model)
         torch.cuda.synchronize()
         for a, b in zip(got, ref[:3]):
             assert torch.equal(a, b)
