@@ -78,6 +78,29 @@ def test_query_tile_values_are_checked_before_device_work():
     assert b"query tile" in lib.qd_last_error() and not h.value
 
 
+class _Params(ctypes.Structure):  # qd_search_params, as declared in include/qd.h
+    _fields_ = [("order", ctypes.c_int), ("d_scores", ctypes.c_void_p), ("n_scored", ctypes.c_uint32),
+                ("waves_per_cu", ctypes.c_uint32), ("d_visited", ctypes.c_void_p), ("n_traced", ctypes.c_uint32),
+                ("round1_blocks", ctypes.c_uint32), ("round2_blocks", ctypes.c_uint32),
+                ("round_growth", ctypes.c_uint32), ("model", ctypes.c_void_p), ("round1_start", ctypes.c_uint32)]
+
+
+def test_plan_takes_a_model_for_the_blocked_order_only():
+    # a sequential plan (no tree) given a model is refused before any device
+    # work; the model handle is never dereferenced
+    lib = ctypes.CDLL(LIB)
+    lib.qd_last_error.restype = ctypes.c_char_p
+    P, U64, U32 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32
+    g = lib.qd_plan_create
+    g.argtypes = [P, P, U64, P, U32, U64, U32, U32, U32, ctypes.POINTER(_Params), U32, ctypes.POINTER(P)]
+    a = P(0x10000)
+    prm = _Params()
+    prm.model = 0x20000
+    h = P()
+    assert g(None, a, 100, a, 4, 64, 4, 10, 0, ctypes.byref(prm), 0, ctypes.byref(h)) == -4  # QD_ERR_UNSUPPORTED
+    assert b"blocked order only" in lib.qd_last_error() and not h.value
+
+
 def test_object_score_argument_errors_without_device_work():
     lib = ctypes.CDLL(LIB)
     lib.qd_last_error.restype = ctypes.c_char_p
