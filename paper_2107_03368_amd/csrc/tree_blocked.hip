@@ -680,69 +680,114 @@ __device__ __forceinline__ uint32_t mfma_tiles(uint32_t c) { return (c - short_p
 
 // Exclusive prefixes over the blocks of the matrix-core tiles (off) and of
 // the short-list pairs (voff); off[nblk], voff[nblk], total[0] and total[1]
-// receive the sums; tinfo[x] = (block, offset of the tile's first query in
-// the block's list, queries in the tile, the block's smallest popcount).
+// receive the sums.  One workgroup: each of its 16 waves takes a contiguous
+// segment of the blocks, 64 consecutive blocks at a time (one per lane, so
+// the loads and stores are coalesced), sums it, and after one exchange of the
+// segment sums writes the prefixes with a scan across its lanes.
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
+    const int lane = lane_id();
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t t = (uint32_t)__shfl_up((int)v, d);
+        v += lane >= d ? t : 0u;
+    }
+    return v;
+}
+
 __global__ __launch_bounds__(1024) void tile_scan_kernel(const uint32_t *__restrict__ cnt, uint64_t nblk,
-                                                         const uint16_t *__restrict__ bpop,
                                                          uint32_t *__restrict__ off, uint32_t *__restrict__ voff,
-                                                         uint4 *__restrict__ tinfo,
                                                          uint32_t *__restrict__ total) {
-    __shared__ uint32_t part[1024], vpart[1024];
-    const uint32_t tid = threadIdx.x;
-    const uint64_t chunk = (nblk + 1023) / 1024;
-    const uint64_t c0 = (uint64_t)tid * chunk, c1 = c0 + chunk < nblk ? c0 + chunk : nblk;
-    // a thread's blocks eight at a time, so their loads are in flight together
-    uint32_t s = 0, vs = 0;
-    for (uint64_t b0 = c0; b0 < c1; b0 += 8) {
-        uint32_t cv[8];
+    constexpr int kW = 16;  // waves
+    __shared__ uint32_t wsum[kW], wvsum[kW];
+    const int lane = lane_id(), w = (int)(threadIdx.x >> 6);
+    const uint64_t seg = ((nblk + kW - 1) / kW + 63) / 64 * 64;  // blocks per wave, whole rounds of 64
+    const uint64_t s0 = (uint64_t)w * seg;
+    const uint64_t s1 = s0 + seg < nblk ? s0 + seg : nblk;
+    // eight rounds' loads in flight at a time
+    constexpr int kU = 8;
+    uint32_t st = 0, sv = 0;
+    for (uint64_t r0 = s0; r0 < s1; r0 += 64 * kU) {
+        uint32_t cv[kU];
 #pragma unroll
-        for (int i = 0; i < 8; i++) cv[i] = b0 + i < c1 ? cnt[b0 + i] : 0;  // 0: no tiles, no pairs
+        for (int u = 0; u < kU; u++) {
+            const uint64_t b = r0 + 64 * u + (uint32_t)lane;
+            cv[u] = b < s1 ? cnt[b] : 0;  // 0: no tiles, no pairs
+        }
 #pragma unroll
-        for (int i = 0; i < 8; i++) {
-            s += mfma_tiles(cv[i]);
-            vs += short_pairs(cv[i]);
+        for (int u = 0; u < kU; u++) {
+            st += mfma_tiles(cv[u]);
+            sv += short_pairs(cv[u]);
         }
     }
-    part[tid] = s;
-    vpart[tid] = vs;
+    st = readlane(wave_incl_scan(st), 63);
+    sv = readlane(wave_incl_scan(sv), 63);
+    if (lane == 0) {
+        wsum[w] = st;
+        wvsum[w] = sv;
+    }
     __syncthreads();
-    for (uint32_t d = 1; d < 1024; d <<= 1) {
-        const uint32_t v = tid >= d ? part[tid - d] : 0;
-        const uint32_t vv = tid >= d ? vpart[tid - d] : 0;
-        __syncthreads();
-        part[tid] += v;
-        vpart[tid] += vv;
-        __syncthreads();
+    uint32_t run = 0, vrun = 0, all = 0, vall = 0;  // this segment's start; the totals
+    for (int i = 0; i < kW; i++) {
+        run += i < w ? wsum[i] : 0u;
+        vrun += i < w ? wvsum[i] : 0u;
+        all += wsum[i];
+        vall += wvsum[i];
     }
-    uint32_t run = part[tid] - s, vrun = vpart[tid] - vs;
-    for (uint64_t b0 = c0; b0 < c1; b0 += 8) {
-        uint32_t cv[8], bv[8];
+    for (uint64_t r0 = s0; r0 < s1; r0 += 64 * kU) {
+        uint32_t cv[kU];
 #pragma unroll
-        for (int i = 0; i < 8; i++) {
-            cv[i] = b0 + i < c1 ? cnt[b0 + i] : 0;
-            bv[i] = bpop && b0 + i < c1 ? bpop[2 * (b0 + i)] : 0;
+        for (int u = 0; u < kU; u++) {
+            const uint64_t b = r0 + 64 * u + (uint32_t)lane;
+            cv[u] = b < s1 ? cnt[b] : 0;
         }
 #pragma unroll
-        for (int i = 0; i < 8; i++) {
-            const uint64_t b = b0 + i;
-            if (b >= c1) break;
-            off[b] = run;
-            voff[b] = vrun;
-            const uint32_t nt = mfma_tiles(cv[i]);
-            const uint32_t listed = cv[i] - short_pairs(cv[i]);  // the list's short rest is not in a tile
-            for (uint32_t t = 0; t < nt; t++) {
-                const uint32_t t0 = t * mt::MA, m = listed - t0 < (uint32_t)mt::MA ? listed - t0 : (uint32_t)mt::MA;
-                tinfo[run + t] = make_uint4((uint32_t)b, t0, m, bv[i]);
+        for (int u = 0; u < kU; u++) {
+            const uint64_t b = r0 + 64 * u + (uint32_t)lane;
+            const uint32_t t = mfma_tiles(cv[u]), v = short_pairs(cv[u]);
+            const uint32_t it = wave_incl_scan(t), iv = wave_incl_scan(v);
+            if (b < s1) {
+                off[b] = run + it - t;
+                voff[b] = vrun + iv - v;
             }
-            run += nt;
-            vrun += short_pairs(cv[i]);
+            run += readlane(it, 63);
+            vrun += readlane(iv, 63);
         }
     }
-    if (tid == 1023) {
-        off[nblk] = part[1023];
-        voff[nblk] = vpart[1023];
-        total[0] = part[1023];
-        total[1] = vpart[1023];
+    if (threadIdx.x == 0) {
+        off[nblk] = all;
+        voff[nblk] = vall;
+        total[0] = all;
+        total[1] = vall;
+    }
+}
+
+// The tile records, one thread per tile: tile x lies in the block b with
+// off[b] <= x < off[b + 1] (the last block whose prefix is at most x: a
+// block without tiles has the same prefix as the next one), found by
+// bisection; tinfo[x] = (block, offset of the tile's first query in the
+// block's list, queries in the tile, the block's smallest popcount).  The
+// grid strides over the tiles the prefix counted.
+__global__ __launch_bounds__(256) void tile_info_kernel(const uint32_t *__restrict__ cnt,
+                                                        const uint32_t *__restrict__ off, uint64_t nblk,
+                                                        const uint16_t *__restrict__ bpop,
+                                                        const uint32_t *__restrict__ ntiles,
+                                                        uint4 *__restrict__ tinfo) {
+    const uint32_t total = *ntiles;
+    for (uint64_t x = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; x < total;
+         x += (uint64_t)gridDim.x * blockDim.x) {
+        uint64_t lo = 0, hi = nblk;  // off[lo] <= x < off[hi] (off[0] = 0, off[nblk] = total)
+        while (hi - lo > 1) {
+            const uint64_t mid = (lo + hi) / 2;
+            if (off[mid] <= x)
+                lo = mid;
+            else
+                hi = mid;
+        }
+        const uint32_t c = cnt[lo];
+        const uint32_t listed = c - short_pairs(c);  // the list's short rest is not in a tile
+        const uint32_t t0 = ((uint32_t)x - off[lo]) * mt::MA;
+        const uint32_t m = listed - t0 < (uint32_t)mt::MA ? listed - t0 : (uint32_t)mt::MA;
+        tinfo[x] = make_uint4((uint32_t)lo, t0, m, bpop ? bpop[2 * lo] : 0u);
     }
 }
 
@@ -1404,6 +1449,8 @@ int blocked_batch(qd_tree_t t, const BlockedLayout &L, char *ws, const uint64_t 
     // registers leave room for one), a multiple of the 8 XCDs
     const uint64_t eval_grid = mt::xcd_grid((uint64_t)device_cus());
     const uint64_t short_grid = mt::xcd_grid((uint64_t)device_cus() * 8);
+    // tile records: at most ceil(nqb / 256) tiles per block
+    const uint64_t info_grid = std::min<uint64_t>((nblk * (nqp / mt::MA) + 255) / 256, (uint64_t)device_cus() * 8);
     const int passes = graph ? kGraphPasses : kMaxPasses;
     bool running = true;
     uint32_t h[5] = {0, 0, 0, 1, 1};  // direct calls: running queries, counters (tiles, short pairs at 3, 4)
@@ -1414,8 +1461,9 @@ int blocked_batch(qd_tree_t t, const BlockedLayout &L, char *ws, const uint64_t 
             hipLaunchKernelGGL(active_kernel, dim3(1), dim3(1024), 0, s, rec, nqb, act, nact);
             hipLaunchKernelGGL(list_kernel, dim3((uint32_t)((waves + 3) / 4)), dim3(256), 0, s, lbb, nblk, n, nqb,
                                nqp, act, nact, rec, frange, donebits, list, cnt, want_stats ? qst : nullptr);
-            hipLaunchKernelGGL(tile_scan_kernel, dim3(1), dim3(1024), 0, s, cnt, nblk, t->d_bpop, off, voff, tinfo,
-                               ctr + 2);
+            hipLaunchKernelGGL(tile_scan_kernel, dim3(1), dim3(1024), 0, s, cnt, nblk, off, voff, ctr + 2);
+            hipLaunchKernelGGL(tile_info_kernel, dim3((uint32_t)info_grid), dim3(256), 0, s, cnt, off, nblk,
+                               t->d_bpop, ctr + 2, tinfo);
         }
         if (!graph) {
             // the host decides whether another pass is needed
