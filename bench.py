@@ -52,19 +52,23 @@ ROW_BYTES = 512
 # frontier-order model: trained on the 1M database's traces, scores the top
 # N_SCORED nodes (depth <= 10) of the searched tree
 TRAIN_QUERIES, TRAIN_BATCH, TRAIN_EPOCHS, TRAIN_LR, N_SCORED = 4096, 32, 8, 2e-3, 2047
-# HBM bytes per launch of the matrix-core kernels at the 10M x 8,192 workload,
-# from the FETCH_SIZE / WRITE_SIZE counters (KiB) scaled by what they read for a
-# 1 GiB device copy (FETCH 524,316 KiB, WRITE 1,048,576 KiB); drop an entry
-# when its kernel changes
+# HBM bytes of the matrix-core kernels at the 10M x 8,192 workload (per launch,
+# or per search), from the FETCH_SIZE / WRITE_SIZE counters (KiB) scaled by
+# what they read for a 1 GiB device copy (FETCH 524,316 KiB, WRITE 1,048,576
+# KiB); drop an entry when its kernel changes
 TRAFFIC_DETAIL = {
     # scan_mfma_kernel at 10M x 8,192: the main launch (not the threshold sample's)
     "scan_mfma_kernel": {"read_bytes": 20_080_518 * 2 * 1024, "write_bytes": 543_240 * 1024,
                          "algorithmic_read_bytes": 5.124e9, "counter_scale": {"FETCH_SIZE": 2.0, "WRITE_SIZE": 1.0}},
-    # eval_kernel at 10M x 8,192, k = 10: the average of the 4 launches of one search
-    "eval_kernel": {"read_bytes": 2_324_874 * 2 * 1024, "write_bytes": 128_475 * 1024,
+    # eval_kernel at 10M x 8,192, k = 10: one search's launches together (a
+    # direct search launches it once per pass, passes without tiles included),
+    # divided below by the launches per search, as the achieved rate is
+    "eval_kernel": {"read_bytes_per_search": 9_299_494 * 2 * 1024, "write_bytes_per_search": 513_898 * 1024,
                     "counter_scale": {"FETCH_SIZE": 2.0, "WRITE_SIZE": 1.0}},
 }
-TRAFFIC = {kname: d["read_bytes"] + d["write_bytes"] for kname, d in TRAFFIC_DETAIL.items()}
+TRAFFIC = {kname: d["read_bytes"] + d["write_bytes"] for kname, d in TRAFFIC_DETAIL.items() if "read_bytes" in d}
+TRAFFIC_PER_SEARCH = {kname: d["read_bytes_per_search"] + d["write_bytes_per_search"]
+                      for kname, d in TRAFFIC_DETAIL.items() if "read_bytes_per_search" in d}
 
 
 def log(*a):
@@ -334,7 +338,7 @@ def main():
         tiles = pb["per_call"]["tree_block_tiles"]
         fill = pairs / (tiles * 256 * 256) if tiles else None
         achieved = ops_per_launch / (ev["avg_ms"] * 1e-3) / 1e12
-        tr = TRAFFIC.get("eval_kernel") if TRAFFIC else None
+        tr = TRAFFIC_PER_SEARCH["eval_kernel"] / launches_per_call if "eval_kernel" in TRAFFIC_PER_SEARCH else None
         return {"kernel": "eval_kernel", "bound": "mfma", "achieved": achieved, "peak": FP4_PEAK_TFLOPS,
                 "unit": "TFLOP/s (fp4 MFMA)", "frac": achieved / FP4_PEAK_TFLOPS, "traffic": tr,
                 "avg_ms": ev["avg_ms"], "ops_per_launch": ops_per_launch,

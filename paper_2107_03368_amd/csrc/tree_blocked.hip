@@ -1371,13 +1371,26 @@ BlockedLayout blocked_layout(qd_tree_t t, uint32_t nq, uint32_t k, bool model) {
     return L;
 }
 
+// Five counts of a direct call's blocked search, in pinned host memory: one
+// small buffer per host thread, allocated on its first use and kept until the
+// process ends (a thread runs one call at a time).
+static uint32_t *pinned_counts() {
+    static thread_local uint32_t *p = nullptr;
+    if (!p && hipHostMalloc((void **)&p, 64, hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        p = nullptr;
+    }
+    return p;
+}
+
 // One batch of nqb queries (nqb <= L.qb) at qq; nq_dev (nullable): the
 // batch's size on the device, at most nqb.  With graph, nothing waits for
 // the host: the rounds run as kGraphPasses fixed passes whose kernels read
 // their work from device memory (a pass with no running query does nothing),
 // queries still running after them take the fallback, and the launches can
-// be captured.  Otherwise the host checks after each pass whether any query
-// still runs.  gst (nullable): totals of the per-query stats.
+// be captured.  Otherwise the same passes run until the host, one pass late,
+// sees that no query runs any more.  gst (nullable): totals of the per-query
+// stats.
 int blocked_batch(qd_tree_t t, const BlockedLayout &L, char *ws, const uint64_t *qq, uint32_t nqb,
                   const uint32_t *nq_dev, uint32_t k, const qd_search_params *p, uint32_t *oi, int32_t *om,
                   int32_t *ox, float *od, uint32_t *d_qstats, unsigned long long *gst, bool graph, hipStream_t s) {
@@ -1453,8 +1466,34 @@ int blocked_batch(qd_tree_t t, const BlockedLayout &L, char *ws, const uint64_t 
     const uint64_t info_grid = std::min<uint64_t>((nblk * (nqp / mt::MA) + 255) / 256, (uint64_t)device_cus() * 8);
     const int passes = graph ? kGraphPasses : kMaxPasses;
     bool running = true;
-    uint32_t h[5] = {0, 0, 0, 1, 1};  // direct calls: running queries, counters (tiles, short pairs at 3, 4)
+    // Direct calls: the host learns whether any query still runs one pass
+    // late.  Every pass's kernels read their work from device memory (as in
+    // a graph), the counts after each pass's lists are copied to pinned host
+    // memory, and the host waits for that copy only while the pass's
+    // evaluation runs, so the device never idles waiting for the host; once
+    // a pass listed no running query the loop stops (that pass's launches
+    // found no work).
+    uint32_t *hb = nullptr;  // running queries, counters (tiles, short pairs at 3, 4)
+    hipEvent_t ev = nullptr;
+    if (!graph) {
+        hb = pinned_counts();
+        if (!hb) return fail(QD_ERR_OOM, "blocked search: pinned host memory");
+        QD_HIP_CHECK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    }
     for (int pass = 0; pass < passes; pass++) {
+        if (!graph && pass > 0) {
+            const hipError_t e = hipEventSynchronize(ev);
+            if (e != hipSuccess) {
+                (void)hipEventDestroy(ev);
+                return fail(QD_ERR_DEVICE, "blocked search: %s", hipGetErrorString(e));
+            }
+            if (hb[0] == 0) {
+                running = false;
+                break;  // no query ran in the previous pass
+            }
+            profile_count("tree_block_tiles", hb[3]);
+            profile_count("tree_block_short_pairs", hb[4]);
+        }
         {
             KernelTimer timer("tree_block_lists", s);
             const uint64_t waves = (nblk + kGroup - 1) / kGroup;
@@ -1466,25 +1505,21 @@ int blocked_batch(qd_tree_t t, const BlockedLayout &L, char *ws, const uint64_t 
                                t->d_bpop, ctr + 2, tinfo);
         }
         if (!graph) {
-            // the host decides whether another pass is needed
-            hipError_t e = hipMemcpyAsync(h, nact, 4, hipMemcpyDeviceToHost, s);
-            if (e == hipSuccess) e = hipMemcpyAsync(h + 1, ctr, 16, hipMemcpyDeviceToHost, s);
-            if (e == hipSuccess) e = hipStreamSynchronize(s);
-            if (e != hipSuccess) return fail(QD_ERR_DEVICE, "blocked search: %s", hipGetErrorString(e));
-            if (h[0] == 0) {
-                running = false;
-                break;  // no query runs any more
+            hipError_t e = hipMemcpyAsync(hb, nact, 4, hipMemcpyDeviceToHost, s);
+            if (e == hipSuccess) e = hipMemcpyAsync(hb + 1, ctr, 16, hipMemcpyDeviceToHost, s);
+            if (e == hipSuccess) e = hipEventRecord(ev, s);
+            if (e != hipSuccess) {
+                (void)hipEventDestroy(ev);
+                return fail(QD_ERR_DEVICE, "blocked search: %s", hipGetErrorString(e));
             }
-            profile_count("tree_block_tiles", h[3]);
-            profile_count("tree_block_short_pairs", h[4]);
         }
-        if (h[3] > 0) {  // a direct call skips a launch it knows has no tiles
+        {
             KernelTimer timer("tree_block_eval", s);
             hipLaunchKernelGGL(eval_kernel, dim3((uint32_t)eval_grid), dim3(mt::kThreads), 0, s, q4,
                                reinterpret_cast<const uint4 *>(t->d_sorted), n, nqp, ctr + 2, list, tinfo, t->d_pop,
                                t->d_perm, qpop, thr, ccnt, cand);
         }
-        if (h[4] > 0) {
+        {
             KernelTimer timer("tree_block_eval_short", s);
             hipLaunchKernelGGL(eval_short_kernel, dim3((uint32_t)short_grid), dim3(256), 0, s, q4,
                                reinterpret_cast<const uint4 *>(t->d_sorted), n, nblk, nqp, list, cnt, voff, t->d_pop,
@@ -1498,6 +1533,7 @@ int blocked_batch(qd_tree_t t, const BlockedLayout &L, char *ws, const uint64_t 
         }
         if (hipGetLastError() != hipSuccess) return fail(QD_ERR_DEVICE, "blocked search: launch failed");
     }
+    if (ev) (void)hipEventDestroy(ev);
     // queries still running after the last pass join the fallback
     if (running)
         hipLaunchKernelGGL(leftover_kernel, dim3((nqb + 255) / 256), dim3(256), 0, s, nqb, rec, ctr, redo);
