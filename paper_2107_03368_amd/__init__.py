@@ -17,7 +17,7 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libqd.so")
 
 if not os.path.exists(LIB_PATH):
-    raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() (hipcc for gfx950)")
+    raise ImportError(f"{LIB_PATH} is not built; build it with python paper_2107_03368_amd/build.py (hipcc for gfx950)")
 
 _lib = ctypes.CDLL(LIB_PATH)
 
