@@ -94,7 +94,7 @@ def main():
                     help="--pmc-run: brute, small1, small8, small16, blocked, best_first, depth_first")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build measures one GPU; --gpus must be 1"}))
+        print(json.dumps({"error": "the search runs on one GPU (a multi-GPU split is a design only); --gpus must be 1"}))
         sys.exit(2)
 
     import torch

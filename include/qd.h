@@ -57,7 +57,7 @@ typedef enum {
     QD_ERR_INVALID = -1,     /* bad argument: null, misaligned, out of range */
     QD_ERR_OOM = -2,         /* device allocation failed */
     QD_ERR_DEVICE = -3,      /* HIP runtime or kernel launch failure */
-    QD_ERR_UNSUPPORTED = -4, /* valid request this build does not serve */
+    QD_ERR_UNSUPPORTED = -4, /* valid request the library does not serve */
     QD_ERR_ABORTED = -5,     /* stopped through an abort flag */
     QD_ERR_FORMAT = -6,      /* malformed serialized data */
     QD_ERR_IO = -7           /* a file could not be opened, read or written */
