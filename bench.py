@@ -88,6 +88,7 @@ def main():
     ap.add_argument("--paths", default="brute,tree,learned",
                     help="brute, tree (best-first, depth-first, blocked), blocked (blocked only), learned")
     ap.add_argument("--max-batch", type=int, default=0, help="stream50m: descriptors per batch (0 = workload's)")
+    ap.add_argument("--k", type=int, default=0, help="neighbours per query (0 = the workload's)")
     ap.add_argument("--pmc-run", action="store_true",
                     help="only a 1 GiB device copy (counter calibration) and one batch of each --pmc-paths path")
     ap.add_argument("--pmc-paths", default="brute,blocked",
@@ -101,7 +102,9 @@ def main():
     import synth
     import paper_2107_03368_amd as qd
 
-    w = WORKLOADS[args.workload]
+    w = dict(WORKLOADS[args.workload])
+    if args.k:
+        w["k"] = args.k
     dev = torch.device("cuda:0")
     if args.workload == "stream50m":
         return stream_main(args, w, dev)
