@@ -146,14 +146,16 @@ __device__ __forceinline__ void stream_begin(const uint4 *row, bool zero, Smem &
 // Multiply the stream's current tile (rows `row`) while staging the first two
 // windows of the next one (rows `next`, read when windows 6 and 7 load them,
 // so the hook may still set them; the current rows again after the last
-// tile: in bounds, never used).  hook(win) runs after window win's barrier,
+// tile: in bounds, never used).  idle (the same in a whole wave): the wave
+// stages its rows as always but multiplies nothing, its accumulators stay
+// zero (a wave whose A rows hold no listed query).  hook(win) runs after window win's barrier,
 // win = 0..7, for the kernel's own work on the next tile (such as a chain of
 // dependent metadata loads, one link per window, which then never stalls a
 // wave: a whole window passes between a load and its use).
 template <class Hook>
 __device__ __forceinline__ void stream_tile(const uint4 *row, bool zero, const uint4 *const &next,
                                             const bool &next_zero, Smem &sm, Stream &st, v4f (&acc)[8][4],
-                                            Hook &&hook) {
+                                            Hook &&hook, bool idle = false) {
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int wq = w >> 2, wr = w & 3;  // 2 x 4 waves, each 128 A rows x 64 B rows
     const int li = lane & 15, lg = lane >> 4;
@@ -221,7 +223,7 @@ __device__ __forceinline__ void stream_tile(const uint4 *row, bool zero, const u
             for (int f = 0; f < 12; f++) r[(s + 1) & 1][f] = *reinterpret_cast<const uint32_t *>(from + roff[f]);
             // one step at a time: the next step's reads go out before this step's work
             __builtin_amdgcn_sched_barrier(0);
-            step(r[s & 1]);
+            if (!idle) step(r[s & 1]);
             __builtin_amdgcn_sched_barrier(0);
         }
         // the buffer of window win - 1: every wave finished reading it before

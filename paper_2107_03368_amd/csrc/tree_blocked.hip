@@ -983,6 +983,9 @@ __global__ __launch_bounds__(mt::kThreads) void eval_kernel(const uint4 *__restr
         // after window w: take what window w - 1 loaded (the window's own store
         // waited for every earlier load), then issue the next loads
         bool nzero = true;
+        // the waves of A rows 128..255 have nothing to multiply when the tile
+        // lists at most 128 queries
+        const bool idle = (r >> 8) == 1 && cur.z <= (uint32_t)(mt::MA / 2);
         mt::stream_tile(row, !cur_ok, nrow, nzero, sm, st, acc, [&](int win) {
             if (win == 0) store_claimed();
             if (win == 1) info = pa;
@@ -997,7 +1000,7 @@ __global__ __launch_bounds__(mt::kThreads) void eval_kernel(const uint4 *__restr
             pa = tinfo[xn + vz];
             issue_b(info);
             issue_c();
-        });
+        }, idle);
         const uint64_t r0 = (uint64_t)cur.x * kBlk;
         const uint32_t m = cur.z;
         const uint32_t *t_qi = s_qi[par], *t_pq = s_pq[par], *t_th = s_th[par], *t_tp = s_tp[par];
