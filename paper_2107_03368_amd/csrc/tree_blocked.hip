@@ -1534,7 +1534,10 @@ int blocked_batch(qd_tree_t t, const BlockedLayout &L, char *ws, const uint64_t 
                                top, ntop, thr, ctr, redo, want_stats ? qst : nullptr, lbq, nblk, donebits, dw, nqp,
                                frange, r1list, descend ? n1 : 0u);
         }
-        if (hipGetLastError() != hipSuccess) return fail(QD_ERR_DEVICE, "blocked search: launch failed");
+        if (hipGetLastError() != hipSuccess) {
+            if (ev) (void)hipEventDestroy(ev);
+            return fail(QD_ERR_DEVICE, "blocked search: launch failed");
+        }
     }
     if (ev) (void)hipEventDestroy(ev);
     // queries still running after the last pass join the fallback
