@@ -153,6 +153,7 @@ def main():
     paths["brute"] = lambda: qd.knn_bruteforce(dbt, qt, k)
     tree = None
     train = None
+    tuning = None
     model = None
     build_s = None
     if ("tree" in wanted or "learned" in wanted or "blocked" in wanted) and hasattr(qd, "tree_build"):
@@ -169,6 +170,17 @@ def main():
             # round 1 at the consecutive blocks the bound's descent reaches
             paths["tree_blocked_descent"] = lambda: qd.knn_tree(tree, qt, k, order=qd.ORDER_BLOCKED,
                                                                 start=qd.START_BOUND_DESCENT)
+            # the round schedule the autotuner picks on another batch of the
+            # same size (other queries of the same distribution)
+            tq_tune, _ = synth.gen_queries(db, nq, w["seed_q"] + 100, w["pmin"], w["pmax"])
+            t0 = time.perf_counter()
+            tuned, tuned_all = qd.autotune(torch.from_numpy(tq_tune.view(np.int64)).to(dev), k, tree=tree, reps=2,
+                                           orders=(qd.ORDER_BLOCKED,))
+            tuning = {"seconds": time.perf_counter() - t0, "picked": tuned,
+                      "candidates": [{"schedule": c["schedule"], "start": c["start"], "ms": c["ms"]} for c in tuned_all]}
+            log(f"autotuned blocked schedule {tuned['schedule']} start {tuned['start']} in {tuning['seconds']:.1f}s")
+            paths["tree_blocked_tuned"] = lambda: qd.knn_tree(tree, qt, k, order=qd.ORDER_BLOCKED,
+                                                              schedule=tuned["schedule"], start=tuned["start"])
         if "learned" in wanted:
             model, train = train_order_model(qd, dev, k)
             n_scored = min(N_SCORED, tree.n_nodes)
@@ -218,6 +230,8 @@ def main():
             kw = {"tree": {}, "tree_dfs": dict(order=qd.ORDER_DEPTH_FIRST),
                   "tree_blocked": dict(order=qd.ORDER_BLOCKED),
                   "tree_blocked_descent": dict(order=qd.ORDER_BLOCKED, start=qd.START_BOUND_DESCENT),
+                  "tree_blocked_tuned": dict(order=qd.ORDER_BLOCKED, schedule=tuned["schedule"] if tuning else None,
+                                             start=tuned["start"] if tuning else 0),
                   "tree_learned": dict(order=qd.ORDER_DEPTH_FIRST, model=model, n_scored=N_SCORED),
                   "tree_blocked_learned": dict(order=qd.ORDER_BLOCKED, model=model)}[name]
             res = qd.knn_tree(tree, qt, k, totals=True, query_stats=True, **kw)
@@ -350,7 +364,10 @@ def main():
     roofline_scan = scan_roofline()
     roofline = blocked_roofline(best) if best.startswith("tree_blocked") else roofline_scan
     if TRAFFIC_DETAIL:
-        roofline["traffic_detail"] = TRAFFIC_DETAIL.get(roofline["kernel"])
+        roofline["traffic_detail"] = dict(TRAFFIC_DETAIL.get(roofline["kernel"]) or {})
+        if roofline["kernel"] == "eval_kernel":
+            # the counter runs search with the default round schedule
+            roofline["traffic_detail"]["measured_on"] = "tree_blocked (default schedule)"
 
     cpu = None
     if args.cpu_sample > 0:
@@ -369,6 +386,7 @@ def main():
         "paths": per_path,
         "tree_build_s": build_s,
         "order_model_training": train,
+        "blocked_autotune": tuning,
         "learned_start_k1": learned_k1,
         "brute_small_batch_hbm": hbm,
         "brute_register_tiled_valu": valu,
