@@ -63,7 +63,7 @@ TRAFFIC_DETAIL = {
     # eval_kernel at 10M x 8,192, k = 10: one search's launches together (a
     # direct search launches it once per pass, passes without tiles included),
     # divided below by the launches per search, as the achieved rate is
-    "eval_kernel": {"read_bytes_per_search": 9_300_646 * 2 * 1024, "write_bytes_per_search": 513_885 * 1024,
+    "eval_kernel": {"read_bytes_per_search": 12_134_001 * 2 * 1024, "write_bytes_per_search": 526_685 * 1024,
                     "counter_scale": {"FETCH_SIZE": 2.0, "WRITE_SIZE": 1.0}},
 }
 TRAFFIC = {kname: d["read_bytes"] + d["write_bytes"] for kname, d in TRAFFIC_DETAIL.items() if "read_bytes" in d}
