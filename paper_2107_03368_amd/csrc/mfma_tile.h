@@ -53,17 +53,19 @@ struct Smem {
 
 // 32 bits -> the 32 e2m1 elements of one lane's operand: element 8j + i
 // (nibble i of word j) comes from bit 4i + j.  The A side keeps bits 0..2 of
-// each nibble where they are (values 0.5, 1 and 2) and moves bit 3, the e2m1
-// sign bit, to bit 2 (value 2); the B side gives the same bits the reciprocal
-// values (2, 1, 0.5 and 0.5), so the product of two set bits is exactly 1
-// and three of the A side's four words need no shift.
+// each nibble where they are (values 0.5, 1 and 2); the B side gives the same
+// bits the reciprocal values (2, 1 and 0.5).  Bit 3, the e2m1 sign bit, moves
+// to bit 1 (value 1) on both sides, so the product of two set bits is exactly
+// 1, three of the A side's four words need no shift, and the B side's last
+// two words come from one shift right by 2.
 __device__ __forceinline__ v8i expand_a(uint32_t w) {
     constexpr uint32_t M = 0x11111111u;
-    return v8i{(int)(w & M), (int)(w & (M << 1)), (int)(w & (M << 2)), (int)((w >> 1) & (M << 2)), 0, 0, 0, 0};
+    return v8i{(int)(w & M), (int)(w & (M << 1)), (int)(w & (M << 2)), (int)((w >> 2) & (M << 1)), 0, 0, 0, 0};
 }
 __device__ __forceinline__ v8i expand_b(uint32_t w) {
     constexpr uint32_t M = 0x11111111u;
-    return v8i{(int)((w << 2) & (M << 2)), (int)(w & (M << 1)), (int)((w >> 2) & M), (int)((w >> 3) & M), 0, 0, 0, 0};
+    const uint32_t r2 = w >> 2;
+    return v8i{(int)((w << 2) & (M << 2)), (int)(w & (M << 1)), (int)(r2 & M), (int)(r2 & (M << 1)), 0, 0, 0, 0};
 }
 
 // The same expansions for two words at once: their shifts run as one 64-bit
@@ -71,14 +73,9 @@ __device__ __forceinline__ v8i expand_b(uint32_t w) {
 // shift; the bits that cross between the two words fall outside the masks).
 // Written as instructions because the compiler splits a 64-bit shift whose
 // halves are masked back into two 32-bit shifts.
-__device__ __forceinline__ uint64_t shr64(uint64_t w, int by) {
+__device__ __forceinline__ uint64_t shr64_2(uint64_t w) {
     uint64_t r;
-    if (by == 1)
-        asm("v_lshrrev_b64 %0, 1, %1" : "=v"(r) : "v"(w));
-    else if (by == 2)
-        asm("v_lshrrev_b64 %0, 2, %1" : "=v"(r) : "v"(w));
-    else
-        asm("v_lshrrev_b64 %0, 3, %1" : "=v"(r) : "v"(w));
+    asm("v_lshrrev_b64 %0, 2, %1" : "=v"(r) : "v"(w));
     return r;
 }
 __device__ __forceinline__ uint64_t shl64_2(uint64_t w) {
@@ -88,19 +85,20 @@ __device__ __forceinline__ uint64_t shl64_2(uint64_t w) {
 }
 __device__ __forceinline__ void expand_a2(uint32_t w0, uint32_t w1, v8i &o0, v8i &o1) {
     constexpr uint32_t M = 0x11111111u;
-    const uint64_t s1 = shr64(((uint64_t)w1 << 32) | w0, 1);
-    o0 = v8i{(int)(w0 & M), (int)(w0 & (M << 1)), (int)(w0 & (M << 2)), (int)((uint32_t)s1 & (M << 2)), 0, 0, 0, 0};
-    o1 = v8i{(int)(w1 & M), (int)(w1 & (M << 1)), (int)(w1 & (M << 2)), (int)((uint32_t)(s1 >> 32) & (M << 2)),
+    const uint64_t r2 = shr64_2(((uint64_t)w1 << 32) | w0);
+    o0 = v8i{(int)(w0 & M), (int)(w0 & (M << 1)), (int)(w0 & (M << 2)), (int)((uint32_t)r2 & (M << 1)), 0, 0, 0, 0};
+    o1 = v8i{(int)(w1 & M), (int)(w1 & (M << 1)), (int)(w1 & (M << 2)), (int)((uint32_t)(r2 >> 32) & (M << 1)),
              0, 0, 0, 0};
 }
 __device__ __forceinline__ void expand_b2(uint32_t w0, uint32_t w1, v8i &o0, v8i &o1) {
     constexpr uint32_t M = 0x11111111u;
     const uint64_t w = ((uint64_t)w1 << 32) | w0;
-    const uint64_t l2 = shl64_2(w), r2 = shr64(w, 2), r3 = shr64(w, 3);
-    o0 = v8i{(int)((uint32_t)l2 & (M << 2)), (int)(w0 & (M << 1)), (int)((uint32_t)r2 & M), (int)((uint32_t)r3 & M),
+    const uint64_t l2 = shl64_2(w), r2 = shr64_2(w);
+    const uint32_t r2lo = (uint32_t)r2, r2hi = (uint32_t)(r2 >> 32);
+    o0 = v8i{(int)((uint32_t)l2 & (M << 2)), (int)(w0 & (M << 1)), (int)(r2lo & M), (int)(r2lo & (M << 1)), 0, 0,
+             0, 0};
+    o1 = v8i{(int)((uint32_t)(l2 >> 32) & (M << 2)), (int)(w1 & (M << 1)), (int)(r2hi & M), (int)(r2hi & (M << 1)),
              0, 0, 0, 0};
-    o1 = v8i{(int)((uint32_t)(l2 >> 32) & (M << 2)), (int)(w1 & (M << 1)), (int)((uint32_t)(r2 >> 32) & M),
-             (int)((uint32_t)(r3 >> 32) & M), 0, 0, 0, 0};
 }
 
 // Workgroups are dispatched to the 8 XCDs round-robin (workgroup x runs on
