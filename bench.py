@@ -214,7 +214,8 @@ def main():
         dt = (time.perf_counter() - t0) / args.steps
         kernels = {}
         for kname in ("wh_scan_mfma", "wh_scan_mfma_sample", "wh_scan_topk", "topk_merge", "topk_select",
-                      "topk_select_sample", "tree_knn", "mlp_features", "mlp_forward", "tree_block_descend",
+                      "topk_select_sample", "tree_knn", "tree_merge", "mlp_features", "mlp_forward",
+                      "tree_block_descend",
                       "tree_block_bounds",
                       "tree_block_plan", "tree_block_round1", "tree_block_lists", "tree_block_eval", "tree_block_eval_short",
                       "tree_block_select"):
@@ -253,6 +254,22 @@ def main():
                 sc_ms = sum(v["avg_ms"] * v["launches"] for kk, v in kernels.items() if kk.startswith("mlp"))
                 per_path[name]["score_time_fraction"] = sc_ms / args.steps / (dt * 1e3)
         log(f"{name}: {dt * 1e3:.2f} ms/batch, {nq / dt:.0f} q/s, kernels {kernels}")
+
+    # the per-query orders with one wave per query (the traversal as listed,
+    # no subtree searches): one timed batch each, for comparison
+    unsplit = {}
+    for name, order in (("tree", qd.ORDER_BEST_FIRST), ("tree_dfs", qd.ORDER_DEPTH_FIRST)):
+        if name not in per_path:
+            continue
+        qd.knn_tree(tree, qt, k, order=order, split=1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        qd.knn_tree(tree, qt, k, order=order, split=1)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        st = qd.knn_tree(tree, qt, k, order=order, split=1, totals=True)[-1]
+        unsplit[name] = {"ms": dt * 1e3, "queries_per_s": nq / dt, "nodes_visited_per_query": st["nodes_visited"] / nq}
+        log(f"{name} with one wave per query: {dt * 1e3:.1f} ms/batch, {st['nodes_visited'] / nq:.0f} nodes/query")
 
     # the learned start where an order can save blocks: at k = 1 the bound order
     # evaluates more than the fewest blocks any exact order must (at k = 10 it is
@@ -388,6 +405,7 @@ def main():
         "order_model_training": train,
         "blocked_autotune": tuning,
         "learned_start_k1": learned_k1,
+        "per_query_one_wave": unsplit,
         "brute_small_batch_hbm": hbm,
         "brute_register_tiled_valu": valu,
         "recall_source_row_at_1": recall,

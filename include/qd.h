@@ -307,6 +307,17 @@ typedef struct {
        bound (ties: the similar child); the other blocks follow in the
        bound-ordered rounds, as with a model.  Results are identical. */
     uint32_t round1_start;
+    /* QD_ORDER_BEST_FIRST / QD_ORDER_DEPTH_FIRST: concurrent searches per
+       query (0 = default 16; 1 = one wave searches the whole tree; else a
+       power of two up to 16).  With n > 1 the tree is cut log2(n) levels
+       below the root, each subtree is searched in the same order by its own
+       wave, the searches of a query prune with the least k-th key any of them
+       has reached (shared through device memory), and their k-lists are
+       merged.  Results are identical for every n; the statistics count the
+       work of all of a query's searches, which depends on their timing.  A
+       traced search (d_visited) runs unsplit.  A batch of nq queries runs
+       nq x n searches, at most 2^31. */
+    uint32_t query_split;
 } qd_search_params;
 enum { QD_START_LOWEST_BOUND = 0, QD_START_BOUND_DESCENT = 1 };
 

@@ -171,7 +171,8 @@ class _SearchParams(ctypes.Structure):
     _fields_ = [("order", ctypes.c_int), ("d_scores", ctypes.c_void_p), ("n_scored", ctypes.c_uint32),
                 ("waves_per_cu", ctypes.c_uint32), ("d_visited", ctypes.c_void_p), ("n_traced", ctypes.c_uint32),
                 ("round1_blocks", ctypes.c_uint32), ("round2_blocks", ctypes.c_uint32),
-                ("round_growth", ctypes.c_uint32), ("model", ctypes.c_void_p), ("round1_start", ctypes.c_uint32)]
+                ("round_growth", ctypes.c_uint32), ("model", ctypes.c_void_p), ("round1_start", ctypes.c_uint32),
+                ("query_split", ctypes.c_uint32)]
 
 
 class Stats(ctypes.Structure):
@@ -266,9 +267,10 @@ START_BOUND_DESCENT = 1
 
 
 def knn_tree(tree, q, k, order=ORDER_BEST_FIRST, scores=None, query_stats=False, totals=False, waves_per_cu=0,
-             schedule=(0, 0, 0), model=None, n_scored=0, start=START_LOWEST_BOUND):
+             schedule=(0, 0, 0), model=None, n_scored=0, start=START_LOWEST_BOUND, split=0):
     """Exact k-NN through the tree.  Returns (idx, missed, extra, dist[, qstats][, totals]).
     schedule: (round-1 blocks, round-2 blocks, growth) of the blocked order, 0 = default.
+    split: concurrent subtree searches per query of the per-query orders (0 = default, 1 = none).
     model: a Model that orders the depth-first search (scoring nodes below n_scored,
     0 = default) or picks where the blocked search starts."""
     _desc(q, "q")
@@ -277,6 +279,7 @@ def knn_tree(tree, q, k, order=ORDER_BEST_FIRST, scores=None, query_stats=False,
     qs = torch.empty((nq, 4), dtype=torch.int32, device=q.device) if query_stats else None
     prm = _SearchParams(order, None, n_scored, waves_per_cu, None, 0, *schedule)
     prm.round1_start = start
+    prm.query_split = split
     if model is not None:
         prm.model = model.handle.value
     if scores is not None:
@@ -343,7 +346,7 @@ _sig("qd_retrieve_objects", [_P, _P, _U64, _P, _U32, _P, _U64, _P, _U32, _U32, _
 
 
 def retrieve_objects(qdesc, qoff, obj_of, n_obj, k, threshold=10, tree=None, db=None, order=ORDER_BEST_FIRST,
-                     return_nn=False, schedule=(0, 0, 0), model=None):
+                     return_nn=False, schedule=(0, 0, 0), model=None, split=0):
     """Vote histogram (nqo, n_obj), winner (nqo,), descriptors used (nqo,)[, neighbour rows].
 
     qoff: cuda int64 (nqo+1) CSR offsets into qdesc; obj_of: cuda int16 object id per database row.
@@ -358,6 +361,7 @@ def retrieve_objects(qdesc, qoff, obj_of, n_obj, k, threshold=10, tree=None, db=
     used = torch.empty(nqo, dtype=torch.int32, device=dev)
     nn = torch.empty((qdesc.shape[0], k), dtype=torch.int32, device=dev) if return_nn else None
     prm = _SearchParams(order, None, 0, 0, None, 0, *schedule)
+    prm.query_split = split
     if model is not None:
         prm.model = model.handle.value
     rc = _lib.qd_retrieve_objects(tree.handle if tree is not None else None, _ptr(db), 0 if db is None else db.shape[0],
@@ -594,13 +598,15 @@ class Plan:
 
     def __init__(self, obj_of, n_obj, max_qdesc, max_qobj, k, threshold=10, tree=None, db=None,
                  order=ORDER_BEST_FIRST, waves_per_cu=0, query_tile=0, schedule=(0, 0, 0), start=START_LOWEST_BOUND,
-                 model=None):
-        """model (blocked order only): round 1 starts where the model leads."""
+                 model=None, split=0):
+        """model (blocked order only): round 1 starts where the model leads.
+        split: concurrent subtree searches per query of the per-query orders."""
         if tree is None:
             _desc(db, "db")
         self._keep = (tree, db, obj_of, model)  # the plan points into these
         prm = _SearchParams(order, None, 0, waves_per_cu, None, 0, *schedule)
         prm.round1_start = start
+        prm.query_split = split
         if model is not None:
             prm.model = model.handle.value
         h = ctypes.c_void_p()

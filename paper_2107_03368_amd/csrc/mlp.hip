@@ -926,7 +926,7 @@ namespace qd {
 int knn_tree_impl(qd_tree_t t, const uint64_t *d_q, uint32_t nq, uint32_t k, int order, const float *d_scores,
                   uint32_t n_scored, uint32_t *d_idx, int32_t *d_missed, int32_t *d_extra, float *d_dist,
                   uint32_t *d_qstats, qd_stats *h_stats, void *stream, uint32_t waves_per_cu, uint32_t *d_trace,
-                  uint32_t n_traced);
+                  uint32_t n_traced, uint32_t split);
 }
 
 // Traces the exact best-first search of the training queries, forms the
@@ -964,7 +964,7 @@ extern "C" int qd_model_train(qd_model_t m, qd_tree_t t, const uint64_t *d_q, ui
     di = (float *)B.p[3];
     vis = (uint32_t *)B.p[4];
     int rc = knn_tree_impl(t, d_q, nq, k, QD_ORDER_BEST_FIRST, nullptr, 0, idx, mi, ex, di, nullptr, nullptr, stream, 0,
-                           vis, n_traced);
+                           vis, n_traced, 1);
     if (rc != QD_OK) return rc;
     uint64_t np = 0;
     QD_HIP_CHECK(hipMalloc(&B.p[5], (size_t)(nq + 1) * 8));

@@ -106,6 +106,8 @@ extern "C" int qd_plan_create(qd_tree_t t, const uint64_t *d_db, uint64_t n, con
         const int rc = blocked_check(t, params);
         if (rc != QD_OK) return rc;
     }
+    if (params && !split_ok(params->query_split))
+        return fail(QD_ERR_INVALID, "query_split %u: 0 or a power of two up to 16", params->query_split);
     qd_plan_s *p = new qd_plan_s();
     p->tree = t;
     p->db = d_db;
@@ -136,7 +138,7 @@ extern "C" int qd_plan_create(qd_tree_t t, const uint64_t *d_db, uint64_t n, con
         ML = mfma_layout(n, nqmax, k);
         ws_bytes = ML.bytes;
     } else if (t) {
-        TL = tree_launch_shape(t, nqmax, order, params ? params->waves_per_cu : 0);
+        TL = tree_launch_shape(t, nqmax, k, order, params ? params->waves_per_cu : 0, params ? params->query_split : 0);
         ws_bytes = TL.total();
     } else {
         BL = brute_launch_shape(n, nqmax, k, query_tile, 0);
@@ -251,10 +253,6 @@ namespace qd {
 int knn_bruteforce_impl(const uint64_t *d_db, uint64_t n, const uint64_t *d_q, uint32_t nq, uint32_t k,
                         uint32_t *d_idx, int32_t *d_missed, int32_t *d_extra, float *d_dist, void *stream,
                         uint32_t qt_force, uint32_t parts_force);
-int knn_tree_impl(qd_tree_t t, const uint64_t *d_q, uint32_t nq, uint32_t k, int order, const float *d_scores,
-                  uint32_t n_scored, uint32_t *d_idx, int32_t *d_missed, int32_t *d_extra, float *d_dist,
-                  uint32_t *d_qstats, qd_stats *h_stats, void *stream, uint32_t waves_per_cu, uint32_t *d_trace,
-                  uint32_t n_traced);
 
 namespace {
 using TuneKey = std::tuple<int, uint64_t, uint64_t, uint32_t, uint32_t, uint32_t>;  // device, n, nodes, nq, k, mask

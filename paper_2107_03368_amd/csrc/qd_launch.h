@@ -11,10 +11,22 @@ namespace qd {
 
 struct TreeLaunch {
     uint64_t blocks = 0, slots = 0, pool_chunks = 0;
+    uint32_t split = 1;  // concurrent subtree searches per query
     size_t head = 0, prev_bytes = 0, pool_bytes = 0;
-    size_t total() const { return head + prev_bytes + pool_bytes; }
+    size_t split_bytes = 0;  // after the pool: the searches' lists and statistics, merged into the results
+    size_t total() const { return head + prev_bytes + pool_bytes + split_bytes; }
 };
-TreeLaunch tree_launch_shape(qd_tree_t t, uint32_t nq_max, int order, uint32_t waves_per_cu);
+// Per-query orders on up to nq_max queries with k neighbours; split = 0
+// picks the default number of subtree searches per query (1: none).
+TreeLaunch tree_launch_shape(qd_tree_t t, uint32_t nq_max, uint32_t k, int order, uint32_t waves_per_cu,
+                             uint32_t split);
+bool split_ok(uint32_t split);  // 0 or a power of two up to 16
+// The per-query and blocked orders behind qd_knn_tree (split: as in
+// tree_launch_shape; a traced search runs unsplit).
+int knn_tree_impl(qd_tree_t t, const uint64_t *d_q, uint32_t nq, uint32_t k, int order, const float *d_scores,
+                  uint32_t n_scored, uint32_t *d_idx, int32_t *d_missed, int32_t *d_extra, float *d_dist,
+                  uint32_t *d_qstats, qd_stats *h_stats, void *stream, uint32_t waves_per_cu, uint32_t *d_trace,
+                  uint32_t n_traced, uint32_t split = 0);
 // The depth-first order's LDS stack holds the tree's depth.
 bool depth_first_fits(qd_tree_t t);
 int tree_launch(qd_tree_t t, const TreeLaunch &L, char *ws, const uint64_t *d_q, uint32_t nq,

@@ -25,10 +25,6 @@ namespace qd {
 int knn_bruteforce_impl(const uint64_t *d_db, uint64_t n, const uint64_t *d_q, uint32_t nq, uint32_t k,
                         uint32_t *d_idx, int32_t *d_missed, int32_t *d_extra, float *d_dist, void *stream,
                         uint32_t qt_force, uint32_t parts_force);
-int knn_tree_impl(qd_tree_t t, const uint64_t *d_q, uint32_t nq, uint32_t k, int order, const float *d_scores,
-                  uint32_t n_scored, uint32_t *d_idx, int32_t *d_missed, int32_t *d_extra, float *d_dist,
-                  uint32_t *d_qstats, qd_stats *h_stats, void *stream, uint32_t waves_per_cu, uint32_t *d_trace,
-                  uint32_t n_traced);
 
 namespace {
 
@@ -160,7 +156,7 @@ extern "C" int qd_retrieve_objects(qd_tree_t t, const uint64_t *d_db, uint64_t n
         if (t)
             rc = knn_tree_impl(t, d_qdesc, (uint32_t)n_qdesc, k, params ? (int)params->order : QD_ORDER_BEST_FIRST,
                                nullptr, 0, nn, missed, extra, dist, nullptr, nullptr, stream,
-                               params ? params->waves_per_cu : 0, nullptr, 0);
+                               params ? params->waves_per_cu : 0, nullptr, 0, params ? params->query_split : 0);
         else
             rc = knn_bruteforce_impl(d_db, n, d_qdesc, (uint32_t)n_qdesc, k, nn, missed, extra, dist, stream, 0, 0);
         if (rc != QD_OK) {
@@ -278,7 +274,8 @@ extern "C" int qd_retrieve_objects_early(qd_tree_t t, const uint64_t *d_db, uint
         int rc;
         if (t)
             rc = knn_tree_impl(t, gq64, m, k, params ? (int)params->order : QD_ORDER_BEST_FIRST, nullptr, 0, oi, om,
-                               ox, od, nullptr, nullptr, stream, params ? params->waves_per_cu : 0, nullptr, 0);
+                               ox, od, nullptr, nullptr, stream, params ? params->waves_per_cu : 0, nullptr, 0,
+                               params ? params->query_split : 0);
         else
             rc = knn_bruteforce_impl(d_db, n, gq64, m, k, oi, om, ox, od, stream, 0, 0);
         if (rc != QD_OK) return done(rc);

@@ -54,10 +54,6 @@
 namespace qd {
 
 int popcount_rows_launch(const uint64_t *d_db, uint64_t n, uint16_t *d_pop, hipStream_t s);
-int knn_tree_impl(qd_tree_t t, const uint64_t *d_q, uint32_t nq, uint32_t k, int order, const float *d_scores,
-                  uint32_t n_scored, uint32_t *d_idx, int32_t *d_missed, int32_t *d_extra, float *d_dist,
-                  uint32_t *d_qstats, qd_stats *h_stats, void *stream, uint32_t waves_per_cu, uint32_t *d_trace,
-                  uint32_t n_traced);
 
 namespace {
 
@@ -1364,7 +1360,7 @@ BlockedLayout blocked_layout(qd_tree_t t, uint32_t nq, uint32_t k, bool model) {
     // best-first one at one wave per CU for a tree deeper than the
     // depth-first stack: its bucket pools are large, and the fallback is rare)
     L.fb_order = depth_first_fits(t) ? QD_ORDER_DEPTH_FIRST : QD_ORDER_BEST_FIRST;
-    L.fb = tree_launch_shape(t, qb, L.fb_order, L.fb_order == QD_ORDER_DEPTH_FIRST ? 0 : 1);
+    L.fb = tree_launch_shape(t, qb, k, L.fb_order, L.fb_order == QD_ORDER_DEPTH_FIRST ? 0 : 1, 1);
     L.fbq = take(P * 512);
     L.fbr = take(P * k * 16);
     L.fbws = take(L.fb.total());

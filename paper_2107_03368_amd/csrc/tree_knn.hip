@@ -30,6 +30,18 @@
 //    given); popped nodes are re-checked against the k-th key and skipped
 //    when they cannot improve the result; the search ends with an empty stack.
 // Both orders return exactly the sequential-search result.
+//
+// Intra-query split: one query's search can run as n concurrent tasks (n a
+// power of two up to 16), each searching one subtree of the tree cut at
+// depth log2(n) (a leaf above that depth is one task's whole subtree) in the
+// same order.  The subtrees partition the rows, so the query's k nearest are
+// the k smallest of the tasks' k-lists (merge_kernel).  Every task prunes
+// with the least k-th key any task of its query has published: a device word
+// per query, lowered with an atomic minimum after each leaf (the atomic also
+// returns the word, taken in at the next leaf, by when it has long
+// returned).  A task's k-th key is never below the query's final one, so the
+// pruning stays exact.  With n tasks a query's search is spread over n waves,
+// so a batch no longer waits for its last few long searches.
 #include "qd_device.h"
 #include "qd_internal.h"
 #include "qd_launch.h"
@@ -72,17 +84,37 @@ struct Scores {
     uint32_t n_scored;    // nodes 0 .. n_scored-1 carry a score
 };
 
+constexpr uint32_t kMaxSplit = 16;
+constexpr uint32_t kDefaultSplit = 16;
+// The tasks' area, one allocation for nq_max queries of n tasks each:
+// subtree roots (n int32, -1: an empty task) | per query, the least k-th key
+// its tasks have published | per task, its k-list (k keys) | their payloads
+// (A | B << 16) | its statistics (nodes visited, leaves, bounds, distances,
+// |q|; 8 words).  Byte offsets from the area's start; the kernels take the
+// start alone and compute the rest, so few pointers stay in registers.
+struct SplitLayout {
+    uint64_t kshared, key, pay, stat, bytes;
+};
+__host__ __device__ inline SplitLayout split_layout(uint64_t nq_max, uint32_t n, uint32_t k) {
+    const uint64_t nt = nq_max * n;
+    SplitLayout L;
+    L.kshared = 256;
+    L.key = L.kshared + (nq_max * 4 + 255) / 256 * 256;
+    L.pay = L.key + nt * k * 8;
+    L.stat = L.pay + (nt * k * 4 + 255) / 256 * 256;
+    L.bytes = L.stat + nt * 32;
+    return L;
+}
+
 __device__ __forceinline__ uint32_t sum32(uint32_t v) { return sum32_half(v); }
 
 template <bool kBest>
-__global__ __launch_bounds__(kBlock) void tree_knn_kernel(TreeView T, const uint4 *__restrict__ q, uint32_t nq,
-                                                          uint32_t k, uint32_t *__restrict__ next_query,
+__global__ __launch_bounds__(kBlock, kBest ? 3 : 4) void tree_knn_kernel(TreeView T, const uint4 *__restrict__ q, uint32_t nq,
+                                                          uint32_t k, uint32_t *__restrict__ next_task,
                                                           u64 *__restrict__ pool, uint32_t *__restrict__ chunk_prev,
-                                                          uint64_t pool_chunks, Scores S, uint32_t *idx,
-                                                          int32_t *missed, int32_t *extra, float *dist,
-                                                          uint32_t *qstats, unsigned long long *gstats,
-                                                          uint32_t *trace, uint32_t n_traced,
-                                                          const uint32_t *__restrict__ nq_dev) {
+                                                          uint64_t pool_chunks, Scores S, uint32_t *trace,
+                                                          uint32_t n_traced, const uint32_t *__restrict__ nq_dev,
+                                                          char *__restrict__ sw, uint32_t nsplit) {
     __shared__ uint32_t bstate_all[kBest ? kWaves * kBuckets : 1];
     __shared__ u64 stack_all[kBest ? kWaves * kHot : kWaves * kMaxStack];  // best-first: the hot bucket's entries
     __shared__ u64 sinfo_all[kBest ? kWaves * kHot : kWaves * kMaxStack];  // the entries' node info
@@ -99,15 +131,43 @@ __global__ __launch_bounds__(kBlock) void tree_knn_kernel(TreeView T, const uint
     u64 *stack = stack_all + wave * (kBest ? kHot : kMaxStack);
     u64 *sinfo = sinfo_all + wave * (kBest ? kHot : kMaxStack);
     const bool has_and = T.andimg != nullptr;
+    const uint32_t nq_max = nq;  // the tasks' area is laid out for nq queries
     if (nq_dev) nq = readfirst(*nq_dev);  // size given on the device (captured graphs)
+    const uint32_t tsh = (uint32_t)__builtin_ctz(nsplit);  // tasks per query = 1 << tsh
+    const uint64_t ntasks = (uint64_t)nq << tsh;
+    uint32_t *const kshared = reinterpret_cast<uint32_t *>(sw + 256);  // the layout's first offset
 
     for (;;) {
         // every lane takes part in the atomic (lane 0 adds 1, the others 0) so
         // that no lane-dependent branch guards the loop head; control values
         // below are passed through readfirstlane so the compiler keeps the
-        // whole traversal wave-uniform
-        const uint32_t qi = readfirst(atomicAdd(next_query, lane == 0 ? 1u : 0u));
-        if (qi >= nq) break;
+        // whole traversal wave-uniform.  A query's tasks are consecutive.
+        const uint32_t task = readfirst(atomicAdd(next_task, lane == 0 ? 1u : 0u));
+        if (task >= ntasks) break;
+        const uint32_t qi = task >> tsh;
+        const int32_t root =
+            nsplit == 1 ? 0 : (int32_t)readfirst((uint32_t) reinterpret_cast<const int32_t *>(sw)[task & (nsplit - 1)]);
+        // this task's list and statistics, for merge_kernel
+        auto put = [&](u64 key, uint32_t pay, uint32_t visited, uint32_t leaves, uint32_t bounds, uint32_t dists,
+                       uint32_t pq) {
+            const SplitLayout SL = split_layout(nq_max, nsplit, k);
+            if (lane < (int)k) {
+                reinterpret_cast<u64 *>(sw + SL.key)[(uint64_t)task * k + lane] = key;
+                reinterpret_cast<uint32_t *>(sw + SL.pay)[(uint64_t)task * k + lane] = pay;
+            }
+            if (lane == 0) {
+                uint32_t *st = reinterpret_cast<uint32_t *>(sw + SL.stat) + (uint64_t)task * 8;
+                st[0] = visited;
+                st[1] = leaves;
+                st[2] = bounds;
+                st[3] = dists;
+                st[4] = pq;
+            }
+        };
+        if (root < 0) {  // no subtree at this position: an empty list
+            put(KEY_NONE, 0, 0, 0, 0, 0, 0);
+            continue;
+        }
 
         // query in two layouts: row slices (chunks j, j+8, j+16, j+24) for the
         // leaf scan, and chunk (lane & 31) for bounding two children at once
@@ -128,6 +188,11 @@ __global__ __launch_bounds__(kBlock) void tree_knn_kernel(TreeView T, const uint
         u64 list = KEY_NONE;      // k best (K << 32 | row), lane r = r-th best
         uint32_t payload = 0;     // A | B << 16 of the entry in `list`
         uint32_t kworst = kNone;  // K of the k-th entry (kNone until k entries)
+        // split: the least k-th key of the query's tasks known here, and the
+        // value the last publishing atomic returned (lane 0; taken in at the
+        // next leaf)
+        uint32_t ucut = nsplit == 1 ? kNone : readfirst(lane == 0 ? atomicMin(&kshared[qi], kNone) : 0u);
+        uint32_t uret = kNone;
         uint32_t visited = 0, leaves = 0, bounds = 0, dists = 0;
 
         // frontier
@@ -233,14 +298,14 @@ __global__ __launch_bounds__(kBlock) void tree_knn_kernel(TreeView T, const uint
             }
         };
 
-        // root
+        // the task's subtree root (the tree's root without a split)
         {
-            const uint32_t kb = readlane(node_bound(0), 0);
-            const u64 in = readlane64(info_of(0), 0);
+            const uint32_t kb = readlane(node_bound(root), 0);
+            const u64 in = readlane64(info_of(root), 0);
             bounds++;
             if (kBest) hot_b = readfirst(kb / (kBucketLevels * wb) < (uint32_t)kBuckets ? kb / (kBucketLevels * wb)
                                                                                           : kBuckets - 1);
-            push(kb, 0, in);
+            push(kb, (uint32_t)root, in);
         }
 
         for (;;) {
@@ -291,10 +356,11 @@ __global__ __launch_bounds__(kBlock) void tree_knn_kernel(TreeView T, const uint
                 ninfo = readlane64(lane == 0 ? sinfo[sp] : 0ull, 0);
             }
             const uint32_t kb = readfirst((uint32_t)(e >> 32)), node = readfirst((uint32_t)e);
-            if (kworst != kNone && kb > kworst) {
+            const uint32_t kcut = kworst < ucut ? kworst : ucut;  // kNone: no k-th key yet
+            if (kcut != kNone && kb > kcut) {
                 // best-first: once the bucket's lower end is past the k-th key,
                 // every open node is; a node of a lower bucket is only skipped
-                if (kBest && floor_kb > kworst) break;
+                if (kBest && floor_kb > kcut) break;
                 continue;  // this entry cannot improve the result
             }
             visited++;
@@ -354,14 +420,21 @@ __global__ __launch_bounds__(kBlock) void tree_knn_kernel(TreeView T, const uint
                     kworst = readfirst(readlane((uint32_t)(readlane64(list, (int)k - 1) >> 32), 0));
                     }
                 }
+                if (nsplit > 1) {
+                    // take in what the previous leaf's atomic returned (the
+                    // loads since then were waited for, so it has returned),
+                    // then publish this task's k-th key and read the word again
+                    ucut = min(ucut, readfirst(uret));
+                    uret = lane == 0 ? atomicMin(&kshared[qi], kworst) : 0u;
+                }
             } else {
                 const int32_t c0 = (int32_t)readfirst((uint32_t)ninfo), c1 = (int32_t)readfirst((uint32_t)(ninfo >> 32));
                 uint32_t kb0, kb1;
                 u64 in0, in1;
                 bound_pair(c0, c1, kb0, kb1, in0, in1);
                 bounds += 2;
-                const bool ok0 = kworst == kNone || kb0 <= kworst;
-                const bool ok1 = kworst == kNone || kb1 <= kworst;
+                const bool ok0 = kcut == kNone || kb0 <= kcut;
+                const bool ok1 = kcut == kNone || kb1 <= kcut;
                 if (kBest) {
                     if (ok0) push(kb0, (uint32_t)c0, in0);
                     if (ok1) push(kb1, (uint32_t)c1, in1);
@@ -380,36 +453,142 @@ __global__ __launch_bounds__(kBlock) void tree_knn_kernel(TreeView T, const uint
             }
         }
 
-        // results
-        if (lane < (int)k) {
-            const uint64_t o = (uint64_t)qi * k + lane;
-            if (list == KEY_NONE) {
-                idx[o] = QD_PAD_IDX;
-                missed[o] = -1;
-                extra[o] = -1;
-                dist[o] = __builtin_inff();
-            } else {
-                const uint32_t A = payload & 0xFFFF, B = payload >> 16;
-                idx[o] = (uint32_t)list;
-                missed[o] = (int32_t)A;
-                extra[o] = (int32_t)B;
-                dist[o] = (float)((double)(list >> 32) / ((double)wa * (double)wb));
-            }
-        }
+        put(list, payload, visited, leaves, bounds, dists, pq);
         if (lane == 0) {
-            if (qstats) {
-                qstats[(uint64_t)qi * 4 + 0] = visited;
-                qstats[(uint64_t)qi * 4 + 1] = leaves;
-                qstats[(uint64_t)qi * 4 + 2] = bounds;
-                qstats[(uint64_t)qi * 4 + 3] = dists;
-            }
-            if (gstats) {
-                atomicAdd(&gstats[0], (unsigned long long)visited);
-                atomicAdd(&gstats[1], (unsigned long long)leaves);
-                atomicAdd(&gstats[2], (unsigned long long)bounds);
-                atomicAdd(&gstats[3], (unsigned long long)dists);
-            }
+            // totals: after the task counter in the workspace head
+            unsigned long long *gstats = reinterpret_cast<unsigned long long *>(next_task + 16);
+            atomicAdd(&gstats[0], (unsigned long long)visited);
+            atomicAdd(&gstats[1], (unsigned long long)leaves);
+            atomicAdd(&gstats[2], (unsigned long long)bounds);
+            atomicAdd(&gstats[3], (unsigned long long)dists);
         }
+    }
+}
+
+// The n subtree roots of a split: position p (bits from the most
+// significant, 0 = first child) is the node reached from the root by
+// following p's log2(n) bits; a leaf met on the way is the subtree of the
+// first position below it, and the others below it are empty (-1).  One
+// thread per position.
+__global__ void roots_kernel(const int32_t *__restrict__ child, uint32_t n, int32_t *__restrict__ roots) {
+    const uint32_t p = threadIdx.x;
+    if (p >= n) return;
+    const uint32_t d = (uint32_t)__builtin_ctz(n);
+    int32_t c = 0;
+    for (uint32_t l = 0; l < d; l++) {
+        const int32_t a = child[2 * (uint64_t)c], b = child[2 * (uint64_t)c + 1];
+        if (a < 0) {
+            if ((p & ((1u << (d - l)) - 1u)) != 0) c = -1;
+            break;
+        }
+        c = (p >> (d - 1 - l)) & 1u ? b : a;
+    }
+    roots[p] = c;
+}
+
+__global__ void fill_words_kernel(uint32_t *p, uint64_t n, uint32_t v) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+__device__ __forceinline__ u64 shfl_xor64(u64 v, int m) {
+    const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)v, m), hi = (uint32_t)__shfl_xor((int)(uint32_t)(v >> 32), m);
+    return (u64)lo | ((u64)hi << 32);
+}
+
+// A query's n task lists -> its k nearest, and its statistics summed over
+// the tasks (n = 1: a copy).  One wave per query: the lists go to LDS, then
+// k steps each take the least head among the lists (the keys are distinct:
+// the subtrees partition the rows).
+constexpr int kMergeWaves = 4;
+__global__ __launch_bounds__(64 * kMergeWaves) void merge_kernel(uint32_t nq, const uint32_t *__restrict__ nq_dev,
+                                                                 uint32_t k, uint32_t n, const char *__restrict__ sw,
+                                                                 uint32_t *idx, int32_t *missed, int32_t *extra,
+                                                                 float *dist, uint32_t *qstats) {
+    __shared__ u64 s_key[kMergeWaves][kMaxSplit * QD_MAX_K];
+    __shared__ uint32_t s_pay[kMergeWaves][kMaxSplit * QD_MAX_K];
+    const int lane = lane_id(), w = (int)(threadIdx.x >> 6);
+    const SplitLayout SL = split_layout(nq, n, k);  // laid out for nq queries
+    const u64 *key = reinterpret_cast<const u64 *>(sw + SL.key);
+    const uint32_t *pay = reinterpret_cast<const uint32_t *>(sw + SL.pay);
+    const uint32_t *stat = reinterpret_cast<const uint32_t *>(sw + SL.stat);
+    if (nq_dev) nq = min(nq, *nq_dev);
+    const uint32_t qi = blockIdx.x * kMergeWaves + w;
+    if (qi >= nq) return;  // the whole wave; nothing below waits for other waves
+    const uint32_t nk = n * k;
+    const uint64_t base = (uint64_t)qi * nk;
+    u64 *sk = s_key[w];
+    uint32_t *sp = s_pay[w];
+    for (uint32_t e = (uint32_t)lane; e < nk; e += 64) {
+        sk[e] = key[base + e];
+        sp[e] = pay[base + e];
+    }
+    // statistics: lane t < n holds task t's
+    uint32_t v0 = 0, v1 = 0, v2 = 0, v3 = 0, pq = 0;
+    if ((uint32_t)lane < n) {
+        const uint32_t *st = stat + ((uint64_t)qi * n + lane) * 8;
+        v0 = st[0];
+        v1 = st[1];
+        v2 = st[2];
+        v3 = st[3];
+        pq = st[4];
+    }
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) {
+        v0 += (uint32_t)__shfl_xor((int)v0, m);
+        v1 += (uint32_t)__shfl_xor((int)v1, m);
+        v2 += (uint32_t)__shfl_xor((int)v2, m);
+        v3 += (uint32_t)__shfl_xor((int)v3, m);
+        pq = max(pq, (uint32_t)__shfl_xor((int)pq, m));  // an empty task reports 0
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    uint32_t h = 0;  // lane t < n: entries of list t taken
+    u64 head = (uint32_t)lane < n ? sk[lane * k] : KEY_NONE;
+    u64 mine = KEY_NONE;  // lane r < k: the r-th nearest
+    uint32_t mpay = 0;
+    for (uint32_t r = 0; r < k; r++) {
+        u64 m = head;
+#pragma unroll
+        for (int s = 32; s >= 1; s >>= 1) {
+            const u64 o = shfl_xor64(m, s);
+            m = o < m ? o : m;
+        }
+        if (m == KEY_NONE) break;  // every list is exhausted
+        const int L = __builtin_ctzll(ballot(head == m));
+        const uint32_t hl = readlane(h, L);
+        const uint32_t pl = sp[(uint32_t)L * k + hl];
+        if ((uint32_t)lane == r) {
+            mine = m;
+            mpay = pl;
+        }
+        if (lane == L) {
+            h++;
+            head = h < k ? sk[lane * k + h] : KEY_NONE;
+        }
+    }
+    if ((uint32_t)lane < k) {
+        const uint64_t o = (uint64_t)qi * k + lane;
+        if (mine == KEY_NONE) {
+            idx[o] = QD_PAD_IDX;
+            missed[o] = -1;
+            extra[o] = -1;
+            dist[o] = __builtin_inff();
+        } else {
+            const uint32_t wa = pq > 1 ? pq : 1;
+            const uint32_t wb = (QD_BITS - pq) > 1 ? QD_BITS - pq : 1;
+            idx[o] = (uint32_t)mine;
+            missed[o] = (int32_t)(mpay & 0xFFFF);
+            extra[o] = (int32_t)(mpay >> 16);
+            dist[o] = (float)((double)(mine >> 32) / ((double)wa * (double)wb));
+        }
+    }
+    if (qstats && lane == 0) {
+        qstats[(uint64_t)qi * 4 + 0] = v0;
+        qstats[(uint64_t)qi * 4 + 1] = v1;
+        qstats[(uint64_t)qi * 4 + 2] = v2;
+        qstats[(uint64_t)qi * 4 + 3] = v3;
     }
 }
 
@@ -421,12 +600,15 @@ __global__ void zero_words_kernel(uint32_t *p, uint32_t n) {
 
 bool depth_first_fits(qd_tree_t t) { return t->depth + 2 <= (uint32_t)kMaxStack; }
 
-TreeLaunch tree_launch_shape(qd_tree_t t, uint32_t nq_max, int order, uint32_t waves_per_cu) {
+TreeLaunch tree_launch_shape(qd_tree_t t, uint32_t nq_max, uint32_t k, int order, uint32_t waves_per_cu,
+                             uint32_t split) {
     TreeLaunch L;
     const int cus = device_cus();
     if (waves_per_cu == 0) waves_per_cu = order == QD_ORDER_BEST_FIRST ? 12 : 16;
+    if (split == 0) split = kDefaultSplit;
+    L.split = split;
     uint64_t blocks = ((uint64_t)cus * waves_per_cu + kWaves - 1) / kWaves;
-    const uint64_t need = ((uint64_t)(nq_max ? nq_max : 1) + kWaves - 1) / kWaves;
+    const uint64_t need = ((uint64_t)(nq_max ? nq_max : 1) * split + kWaves - 1) / kWaves;
     if (blocks > need) blocks = need;
     L.blocks = blocks;
     L.slots = blocks * kWaves;
@@ -438,8 +620,11 @@ TreeLaunch tree_launch_shape(qd_tree_t t, uint32_t nq_max, int order, uint32_t w
     L.head = 256;  // [counter | pad | stats x4 | pad]
     L.prev_bytes = (size_t)(L.slots * L.pool_chunks * 8 + 255) / 256 * 256;  // prev + free list
     L.pool_bytes = (size_t)L.slots * L.pool_chunks * kChunk * 16;  // entries, then their node info
+    L.split_bytes = split_layout(nq_max ? nq_max : 1, split, k).bytes;  // the tasks' lists, also unsplit
     return L;
 }
+
+bool split_ok(uint32_t split) { return split == 0 || (split <= kMaxSplit && (split & (split - 1)) == 0); }
 
 int tree_launch(qd_tree_t t, const TreeLaunch &L, char *ws, const uint64_t *d_q, uint32_t nq,
                 const uint32_t *nq_dev, uint32_t k, int order, const float *d_scores, uint32_t n_scored,
@@ -447,23 +632,39 @@ int tree_launch(qd_tree_t t, const TreeLaunch &L, char *ws, const uint64_t *d_q,
                 uint32_t *d_trace, uint32_t n_traced, hipStream_t s) {
     hipLaunchKernelGGL(zero_words_kernel, dim3(1), dim3(64), 0, s, reinterpret_cast<uint32_t *>(ws),
                        (uint32_t)(L.head / 4));
-    uint32_t *counter = reinterpret_cast<uint32_t *>(ws);
-    unsigned long long *gstats = reinterpret_cast<unsigned long long *>(ws + 64);
+    uint32_t *counter = reinterpret_cast<uint32_t *>(ws);  // the kernel adds its totals at ws + 64
     uint32_t *chunk_prev = reinterpret_cast<uint32_t *>(ws + L.head);
     u64 *pool = reinterpret_cast<u64 *>(ws + L.head + L.prev_bytes);
     TreeView T{reinterpret_cast<const uint4 *>(t->d_sorted), t->d_perm, reinterpret_cast<const uint4 *>(t->d_or),
                reinterpret_cast<const uint4 *>(t->d_and), t->d_child, t->d_begin, t->d_count, t->d_pop,
                t->d_pmin, t->d_pmax};
     Scores S{d_scores, d_scores ? n_scored : 0};
-    KernelTimer timer("tree_knn", s);
-    if (order == QD_ORDER_BEST_FIRST)
-        hipLaunchKernelGGL(tree_knn_kernel<true>, dim3((uint32_t)L.blocks), dim3(kBlock), 0, s, T,
-                           reinterpret_cast<const uint4 *>(d_q), nq, k, counter, pool, chunk_prev, L.pool_chunks, S,
-                           d_idx, d_missed, d_extra, d_dist, d_qstats, gstats, d_trace, n_traced, nq_dev);
-    else
-        hipLaunchKernelGGL(tree_knn_kernel<false>, dim3((uint32_t)L.blocks), dim3(kBlock), 0, s, T,
-                           reinterpret_cast<const uint4 *>(d_q), nq, k, counter, pool, chunk_prev, L.pool_chunks, S,
-                           d_idx, d_missed, d_extra, d_dist, d_qstats, gstats, d_trace, n_traced, nq_dev);
+    if (L.split > 1 && d_trace) return fail(QD_ERR_INVALID, "a traced search runs unsplit");
+    char *sw = ws + L.head + L.prev_bytes + L.pool_bytes;  // the tasks' area
+    if (L.split > 1) {
+        hipLaunchKernelGGL(roots_kernel, dim3(1), dim3(64), 0, s, t->d_child, L.split, reinterpret_cast<int32_t *>(sw));
+        const uint32_t fg = (nq + 255) / 256;
+        hipLaunchKernelGGL(fill_words_kernel, dim3(fg < 1 ? 1 : fg < 1024 ? fg : 1024), dim3(256), 0, s,
+                           reinterpret_cast<uint32_t *>(sw + split_layout(nq, L.split, k).kshared), (uint64_t)nq,
+                           kNone);
+    }
+    {
+        KernelTimer timer("tree_knn", s);
+        if (order == QD_ORDER_BEST_FIRST)
+            hipLaunchKernelGGL(tree_knn_kernel<true>, dim3((uint32_t)L.blocks), dim3(kBlock), 0, s, T,
+                               reinterpret_cast<const uint4 *>(d_q), nq, k, counter, pool, chunk_prev, L.pool_chunks,
+                               S, d_trace, n_traced, nq_dev, sw, L.split);
+        else
+            hipLaunchKernelGGL(tree_knn_kernel<false>, dim3((uint32_t)L.blocks), dim3(kBlock), 0, s, T,
+                               reinterpret_cast<const uint4 *>(d_q), nq, k, counter, pool, chunk_prev, L.pool_chunks,
+                               S, d_trace, n_traced, nq_dev, sw, L.split);
+    }
+    QD_HIP_CHECK(hipGetLastError());
+    {
+        KernelTimer timer("tree_merge", s);
+        hipLaunchKernelGGL(merge_kernel, dim3((nq + kMergeWaves - 1) / kMergeWaves), dim3(64 * kMergeWaves), 0, s,
+                           nq, nq_dev, k, L.split, sw, d_idx, d_missed, d_extra, d_dist, d_qstats);
+    }
     QD_HIP_CHECK(hipGetLastError());
     return QD_OK;
 }
@@ -471,8 +672,9 @@ int tree_launch(qd_tree_t t, const TreeLaunch &L, char *ws, const uint64_t *d_q,
 int knn_tree_impl(qd_tree_t t, const uint64_t *d_q, uint32_t nq, uint32_t k, int order, const float *d_scores,
                   uint32_t n_scored, uint32_t *d_idx, int32_t *d_missed, int32_t *d_extra, float *d_dist,
                   uint32_t *d_qstats, qd_stats *h_stats, void *stream, uint32_t waves_per_cu, uint32_t *d_trace,
-                  uint32_t n_traced) {
+                  uint32_t n_traced, uint32_t split) {
     if (!t) return fail(QD_ERR_INVALID, "null tree");
+    if (!split_ok(split)) return fail(QD_ERR_INVALID, "query_split %u: 0 or a power of two up to %u", split, kMaxSplit);
     if (k < 1 || k > QD_MAX_K) return fail(QD_ERR_INVALID, "k=%u outside 1..%d", k, QD_MAX_K);
     if (order != QD_ORDER_BEST_FIRST && order != QD_ORDER_DEPTH_FIRST && order != QD_ORDER_BLOCKED)
         return fail(QD_ERR_INVALID, "unknown frontier order %d", order);
@@ -488,8 +690,11 @@ int knn_tree_impl(qd_tree_t t, const uint64_t *d_q, uint32_t nq, uint32_t k, int
     if (order == QD_ORDER_DEPTH_FIRST && !depth_first_fits(t))
         return fail(QD_ERR_UNSUPPORTED, "tree depth %u exceeds the depth-first stack (%d)", t->depth, kMaxStack);
     if (n_traced > t->n_nodes) return fail(QD_ERR_INVALID, "n_traced above the node count");
+    if (d_trace && n_traced) split = 1;  // traces follow the one-wave traversal
+    if ((uint64_t)nq * (split ? split : kDefaultSplit) > 0x7FFFFFFFull)
+        return fail(QD_ERR_INVALID, "%u queries x %u subtree searches: too many tasks", nq, split ? split : kDefaultSplit);
     hipStream_t s = (hipStream_t)stream;
-    const TreeLaunch L = tree_launch_shape(t, nq, order, waves_per_cu);
+    const TreeLaunch L = tree_launch_shape(t, nq, k, order, waves_per_cu, split);
     char *ws = nullptr;
     QD_HIP_CHECK(hipMallocAsync((void **)&ws, L.total(), s));
     if (d_trace && n_traced)
@@ -537,7 +742,7 @@ extern "C" int qd_knn_tree(qd_tree_t t, const uint64_t *d_q, uint32_t nq, uint32
         int rc = qd_model_score_tree(model, t, d_q, nq, ns, scores, stream);
         if (rc == QD_OK)
             rc = qd::knn_tree_impl(t, d_q, nq, k, order, scores, ns, d_idx, d_missed, d_extra, d_dist, d_query_stats,
-                                   h_stats, stream, wpc, p->d_visited, p->n_traced);
+                                   h_stats, stream, wpc, p->d_visited, p->n_traced, p->query_split);
         (void)hipFreeAsync(scores, s);
         return rc;
     }
@@ -550,5 +755,5 @@ extern "C" int qd_knn_tree(qd_tree_t t, const uint64_t *d_q, uint32_t nq, uint32
                                     (hipStream_t)stream);
     }
     return qd::knn_tree_impl(t, d_q, nq, k, order, sc, ns, d_idx, d_missed, d_extra, d_dist, d_query_stats, h_stats,
-                             stream, wpc, p ? p->d_visited : nullptr, p ? p->n_traced : 0);
+                             stream, wpc, p ? p->d_visited : nullptr, p ? p->n_traced : 0, p ? p->query_split : 0);
 }

@@ -82,7 +82,8 @@ class _Params(ctypes.Structure):  # qd_search_params, as declared in include/qd.
     _fields_ = [("order", ctypes.c_int), ("d_scores", ctypes.c_void_p), ("n_scored", ctypes.c_uint32),
                 ("waves_per_cu", ctypes.c_uint32), ("d_visited", ctypes.c_void_p), ("n_traced", ctypes.c_uint32),
                 ("round1_blocks", ctypes.c_uint32), ("round2_blocks", ctypes.c_uint32),
-                ("round_growth", ctypes.c_uint32), ("model", ctypes.c_void_p), ("round1_start", ctypes.c_uint32)]
+                ("round_growth", ctypes.c_uint32), ("model", ctypes.c_void_p), ("round1_start", ctypes.c_uint32),
+                ("query_split", ctypes.c_uint32)]
 
 
 def test_plan_takes_a_model_for_the_blocked_order_only():
@@ -99,6 +100,30 @@ def test_plan_takes_a_model_for_the_blocked_order_only():
     h = P()
     assert g(None, a, 100, a, 4, 64, 4, 10, 0, ctypes.byref(prm), 0, ctypes.byref(h)) == -4  # QD_ERR_UNSUPPORTED
     assert b"blocked order only" in lib.qd_last_error() and not h.value
+
+
+def test_query_split_is_checked_before_device_work():
+    # a split that is not 0 or a power of two up to 16 is refused by the
+    # search and by a plan before the tree handle is dereferenced
+    lib = ctypes.CDLL(LIB)
+    lib.qd_last_error.restype = ctypes.c_char_p
+    P, U32 = ctypes.c_void_p, ctypes.c_uint32
+    f = lib.qd_knn_tree
+    f.argtypes = [P, P, U32, U32, ctypes.POINTER(_Params), P, P, P, P, P, P, P]
+    a = P(0x10000)
+    for bad in (3, 6, 32):
+        prm = _Params()
+        prm.query_split = bad
+        assert f(a, a, 8, 10, ctypes.byref(prm), a, a, a, a, None, None, None) == -1
+        assert b"query_split" in lib.qd_last_error()
+    U64 = ctypes.c_uint64
+    g = lib.qd_plan_create
+    g.argtypes = [P, P, U64, P, U32, U64, U32, U32, U32, ctypes.POINTER(_Params), U32, ctypes.POINTER(P)]
+    prm = _Params()
+    prm.query_split = 5
+    h = P()
+    assert g(a, None, 0, a, 4, 64, 4, 10, 0, ctypes.byref(prm), 0, ctypes.byref(h)) == -1
+    assert b"query_split" in lib.qd_last_error() and not h.value
 
 
 def test_object_score_argument_errors_without_device_work():

@@ -171,10 +171,11 @@ def test_trained_order_gain_over_bound_order(qd):
     q, _ = synth.gen_queries(db, 1024, 2005, 0.1, 0.6)
     tree = qd.tree_build(_t(db))
     qt = _t(q)
-    plain = qd.knn_tree(tree, qt, 10, order=qd.ORDER_DEPTH_FIRST, totals=True)
+    # one wave per query, so the node counts do not depend on timing
+    plain = qd.knn_tree(tree, qt, 10, order=qd.ORDER_DEPTH_FIRST, totals=True, split=1)
     scores = qd.model_score_tree(model, tree, qt, 2047)
-    learned = qd.knn_tree(tree, qt, 10, order=qd.ORDER_DEPTH_FIRST, scores=scores, totals=True)
-    best = qd.knn_tree(tree, qt, 10, totals=True)
+    learned = qd.knn_tree(tree, qt, 10, order=qd.ORDER_DEPTH_FIRST, scores=scores, totals=True, split=1)
+    best = qd.knn_tree(tree, qt, 10, totals=True, split=1)
     for a, b in zip(plain[:4], learned[:4]):
         assert torch.equal(a, b)
     n_plain, n_learned, n_best = (r[-1]["nodes_visited"] / len(q) for r in (plain, learned, best))
@@ -190,8 +191,8 @@ def test_model_handle_orders_depth_first_as_explicit_scores(qd, setup):
     model = qd.Model(_t(_params(13)))
     n = min(511, tree.n_nodes)
     sc = qd.model_score_tree(model, tree, _t(q), n)
-    a = qd.knn_tree(tree, _t(q), 10, order=qd.ORDER_DEPTH_FIRST, scores=sc, query_stats=True)
-    b = qd.knn_tree(tree, _t(q), 10, order=qd.ORDER_DEPTH_FIRST, model=model, n_scored=n, query_stats=True)
+    a = qd.knn_tree(tree, _t(q), 10, order=qd.ORDER_DEPTH_FIRST, scores=sc, query_stats=True, split=1)
+    b = qd.knn_tree(tree, _t(q), 10, order=qd.ORDER_DEPTH_FIRST, model=model, n_scored=n, query_stats=True, split=1)
     for x, y in zip(a, b):
         assert np.array_equal(x.cpu().numpy(), y.cpu().numpy())
     with pytest.raises(qd.QDError):

@@ -99,7 +99,8 @@ def test_objects_workload_full_scale(qd):
     assert (rw == qobj).mean() >= 0.95  # the workload is retrievable
 
 
-@pytest.mark.parametrize("path", ["best_first", "blocked", "blocked_learned", "sequential", "matrix_cores"])
+@pytest.mark.parametrize("path", ["best_first", "best_first_unsplit", "depth_first_split16", "blocked",
+                                  "blocked_learned", "sequential", "matrix_cores"])
 def test_plan_graph_replays_match_direct_retrieval(qd, path):
     # the matrix-core scan needs >= 65,536 rows and >= 160 descriptors in the
     # largest batch; the plan keeps it for the smaller batches too.  With a
@@ -110,21 +111,25 @@ def test_plan_graph_replays_match_direct_retrieval(qd, path):
     n_obj = 280 if path == "matrix_cores" else 40
     db, obj, off, q, qobj = _workload(n_obj, 250 if path == "matrix_cores" else 300, 24, 20, 120, 91)
     assert path != "matrix_cores" or (len(db) >= 65_536 and len(q) >= 160)
-    use_tree = path in ("best_first", "blocked", "blocked_learned")
-    order = qd.ORDER_BLOCKED if path.startswith("blocked") else qd.ORDER_BEST_FIRST
+    use_tree = path not in ("sequential", "matrix_cores")
+    order = (qd.ORDER_BLOCKED if path.startswith("blocked") else
+             qd.ORDER_DEPTH_FIRST if path.startswith("depth_first") else qd.ORDER_BEST_FIRST)
+    # per-query orders: the default split, one wave per query, or 16 subtree searches
+    split = {"best_first_unsplit": 1, "depth_first_split16": 16}.get(path, 0)
     model = None
     if path == "blocked_learned":
         model = qd.Model(torch.from_numpy(synth.uniform_f32(qd.MLP_NPARAMS, 3101, -0.05, 0.05)).to("cuda:0"))
     tree = qd.tree_build(_t(db)) if use_tree else None
     dbt = None if use_tree else _t(db)
     plan = qd.Plan(_t(obj), n_obj, max_qdesc=len(q), max_qobj=24, k=5, threshold=10, tree=tree, db=dbt, order=order,
-                   query_tile=16 if path == "sequential" else 0, model=model)
+                   query_tile=16 if path == "sequential" else 0, model=model, split=split)
     # batches of different sizes, with eager library work between the replays
     for lo, hi in ((0, 24), (3, 10), (0, 1), (5, 24)):
         sub = np.asarray(off[lo:hi + 1], np.uint64) - off[lo]
         qs = q[int(off[lo]):int(off[hi])]
         got = plan.run(_t(qs), _t(sub))
-        ref = qd.retrieve_objects(_t(qs), _t(sub), _t(obj), n_obj, 5, 10, tree=tree, db=dbt, order=order, model=model)
+        ref = qd.retrieve_objects(_t(qs), _t(sub), _t(obj), n_obj, 5, 10, tree=tree, db=dbt, order=order, model=model,
+                                  split=split)
         torch.cuda.synchronize()
         for a, b in zip(got, ref):
             assert torch.equal(a, b)

@@ -81,11 +81,13 @@ def test_search_matches_oracle_10k(qd, small_db, small_queries, k):
     q, _ = small_queries
     tree = qd.tree_build(_t(small_db))
     ref = oracle.knn_brute(small_db, q, k)
-    best = qd.knn_tree(tree, _t(q), k, query_stats=True)
-    _same(best, ref)
+    _same(qd.knn_tree(tree, _t(q), k), ref)
     _same(qd.knn_tree(tree, _t(q), k, order=qd.ORDER_DEPTH_FIRST), ref)
-    # traversal statistics follow the oracle's best-first search with the same
-    # bound (ties may pop in another order, so allow a small difference)
+    best = qd.knn_tree(tree, _t(q), k, query_stats=True, split=1)
+    _same(best, ref)
+    # one wave per query: traversal statistics follow the oracle's best-first
+    # search with the same bound (ties may pop in another order, so allow a
+    # small difference)
     ot = oracle.tree_build(small_db)
     ostats = oracle.tree_knn(small_db, ot, q, k, use_pop=True).stats
     g = best[4].cpu().numpy()
@@ -94,7 +96,7 @@ def test_search_matches_oracle_10k(qd, small_db, small_queries, k):
     # the paper's plain image bound: same results, the oracle's plain node counts
     plain = qd.tree_build(_t(small_db), plain_bound=True)
     assert tree.has_pop_range and not plain.has_pop_range
-    pres = qd.knn_tree(plain, _t(q), k, query_stats=True)
+    pres = qd.knn_tree(plain, _t(q), k, query_stats=True, split=1)
     _same(pres, ref)
     _same(qd.knn_tree(plain, _t(q), k, order=qd.ORDER_DEPTH_FIRST), ref)
     pstats = oracle.tree_knn(small_db, ot, q, k).stats
@@ -131,6 +133,48 @@ def test_search_edge_cases(qd):
     t3 = qd.tree_build(_t(small))
     ref = oracle.knn_brute(small, q, 5)
     _same(qd.knn_tree(t3, _t(q), 5), ref)
+
+
+@pytest.mark.parametrize("split", [1, 2, 4, 8, 16])
+def test_split_searches_match_oracle(qd, small_db, small_queries, split):
+    # a query's subtree searches share its k-th key and merge their lists:
+    # the same neighbours for every split, order and k; the statistics add
+    # up the subtree searches' work
+    q, _ = small_queries
+    tree = qd.tree_build(_t(small_db))
+    for k in (1, 10, 64):
+        ref = oracle.knn_brute(small_db, q, k)
+        for order in (qd.ORDER_BEST_FIRST, qd.ORDER_DEPTH_FIRST):
+            res = qd.knn_tree(tree, _t(q), k, order=order, split=split, query_stats=True, totals=True)
+            _same(res, ref)
+            st, tot = res[4].cpu().numpy().astype(np.int64), res[5]
+            assert st[:, 0].sum() == tot["nodes_visited"] and st[:, 3].sum() == tot["dists_evaluated"]
+            assert (st[:, 0] >= 1).all() and (st[:, 3] >= min(k, len(small_db))).all()
+            assert (st[:, 1] <= st[:, 0]).all()
+
+
+def test_split_on_shallow_trees_and_single_queries(qd):
+    # trees with leaves above the cut depth (empty subtree searches), fewer
+    # rows than k, one query, and duplicate rows tying at the k-th key
+    base = synth.gen_db(40, 75)
+    q = np.concatenate([base[:3], synth.gen_queries(base, 5, 76, 0.2, 0.6)[0], np.zeros((1, 64), np.uint64)])
+    for db in (synth.gen_db(3, 77), base, np.concatenate([base, base, base[:7]])):
+        tree = qd.tree_build(_t(db))
+        for k in (1, 5, 64):
+            ref = oracle.knn_brute(db, q, k)
+            for split in (2, 16):
+                for order in (qd.ORDER_BEST_FIRST, qd.ORDER_DEPTH_FIRST):
+                    _same(qd.knn_tree(tree, _t(q), k, order=order, split=split), ref)
+                    one = qd.knn_tree(tree, _t(q[4:5]), k, order=order, split=split)
+                    _same(one, oracle.knn_brute(db, q[4:5], k))
+
+
+def test_split_argument_errors(qd, small_db, small_queries):
+    q, _ = small_queries
+    tree = qd.tree_build(_t(small_db))
+    for bad in (3, 12, 32):
+        with pytest.raises(qd.QDError):
+            qd.knn_tree(tree, _t(q[:4]), 5, split=bad)
 
 
 @pytest.fixture(scope="module")
@@ -171,12 +215,14 @@ def test_search_1m_sampled_queries(qd, tree_1m, k):
     q, _ = synth.gen_queries(db, 4096, 2001, 0.1, 0.6)
     rows = _sample([0, 5, 1000, 3333, 4095], 4096, 32)
     ref = oracle.knn_brute(db, q[rows], k)
-    best = qd.knn_tree(tree, _t(q), k, totals=True)
-    _same(best, ref, rows)
+    _same(qd.knn_tree(tree, _t(q), k), ref, rows)
     _same(qd.knn_tree(tree, _t(q), k, order=qd.ORDER_DEPTH_FIRST), ref, rows)
-    # the plain image bound gives the same neighbours for every query, with more nodes
+    best = qd.knn_tree(tree, _t(q), k, totals=True, split=1)
+    _same(best, ref, rows)
+    # the plain image bound gives the same neighbours for every query, with
+    # more nodes (one wave per query: node counts that do not depend on timing)
     plain = qd.tree_build(_t(db), plain_bound=True)
-    pres = qd.knn_tree(plain, _t(q), k, totals=True)
+    pres = qd.knn_tree(plain, _t(q), k, totals=True, split=1)
     for a, b in zip(best[:4], pres[:4]):
         assert np.array_equal(a.cpu().numpy(), b.cpu().numpy())
     print(f"k={k}: nodes visited per query {best[-1]['nodes_visited'] / len(q):.0f} with popcount ranges, "
