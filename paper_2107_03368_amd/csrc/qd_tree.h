@@ -30,6 +30,11 @@ struct qd_tree_s {
     uint64_t *d_blk = nullptr;     // n_blk x 64 words: OR image of each block's rows
     uint16_t *d_bpop = nullptr;    // n_blk x 2: smallest, largest row popcount of each block (null: plain)
     std::vector<uint32_t> level_max;  // host: most rows of any node of each level (root level 0)
+    // The per-query search split into n = 2^e subtree searches (e = 0..4):
+    // d_split_roots[n - 1 .. 2n - 2] are the n subtree roots (-1: none) and
+    // split_nodes[e] the most nodes any of them holds.
+    int32_t *d_split_roots = nullptr;  // 31 entries
+    uint64_t split_nodes[5] = {};
 };
 
 namespace qd {

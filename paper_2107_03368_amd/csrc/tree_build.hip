@@ -507,7 +507,7 @@ void tree_release(qd_tree_s *t) {
     if (!t) return;
     void *ptrs[] = {t->d_sorted, t->d_perm,  t->d_or,     t->d_and,   t->d_child, t->d_begin, t->d_count,
                     t->d_pop,    t->d_parent, t->d_depth, t->d_iperm, t->d_blk,   t->d_pmin,  t->d_pmax,
-                    t->d_bpop};
+                    t->d_bpop,   t->d_split_roots};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     delete t;
@@ -733,7 +733,40 @@ int tree_finish(qd_tree_s *t, const std::vector<int32_t> &child, const std::vect
         depth[i] = (uint8_t)std::min<uint32_t>(255, level[i]);
         t->level_max[level[i]] = std::max(t->level_max[level[i]], count[i]);
     }
-    if (hipMemcpyAsync(t->d_parent, parent.data(), nn * 4, hipMemcpyHostToDevice, s) != hipSuccess ||
+    // The per-query search split into n subtree searches: position p (its
+    // log2(n) bits from the most significant, 0 = the similar child) is the
+    // node reached from the root along p's bits; a leaf met on the way is the
+    // subtree of the first position below it, the other positions below it
+    // are empty.  With the nodes under each node (children come after their
+    // parents), the most nodes of any subtree bounds one search's queue.
+    std::vector<int32_t> split_roots(31, -1);
+    {
+        std::vector<uint32_t> under(nn, 1);
+        for (uint64_t i = nn; i-- > 0;)
+            if (child[2 * i] >= 0) under[i] = 1 + under[child[2 * i]] + under[child[2 * i + 1]];
+        for (uint32_t e = 0; e < 5; e++) {
+            const uint32_t ns = 1u << e;
+            uint64_t most = 0;
+            for (uint32_t p = 0; p < ns; p++) {
+                int32_t c = 0;
+                for (uint32_t l = 0; l < e; l++) {
+                    const int32_t a = child[2 * (uint64_t)c], b = child[2 * (uint64_t)c + 1];
+                    if (a < 0) {
+                        if ((p & ((1u << (e - l)) - 1u)) != 0) c = -1;
+                        break;
+                    }
+                    c = (p >> (e - 1 - l)) & 1u ? b : a;
+                }
+                split_roots[ns - 1 + p] = c;
+                if (c >= 0) most = std::max<uint64_t>(most, under[c]);
+            }
+            t->split_nodes[e] = most;
+        }
+    }
+    if (hipMalloc((void **)&t->d_split_roots, 31 * 4) != hipSuccess)
+        return cleanup(fail(QD_ERR_OOM, "tree allocation failed"));
+    if (hipMemcpyAsync(t->d_split_roots, split_roots.data(), 31 * 4, hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(t->d_parent, parent.data(), nn * 4, hipMemcpyHostToDevice, s) != hipSuccess ||
         hipMemcpyAsync(t->d_depth, depth.data(), nn, hipMemcpyHostToDevice, s) != hipSuccess ||
         hipMemcpyAsync(t->d_child, child.data(), nn * 8, hipMemcpyHostToDevice, s) != hipSuccess ||
         hipMemcpyAsync(t->d_begin, begin.data(), nn * 4, hipMemcpyHostToDevice, s) != hipSuccess ||

@@ -122,9 +122,8 @@ __global__ __launch_bounds__(kBlock, kBest ? 3 : 4) void tree_knn_kernel(TreeVie
     const int wave = threadIdx.x >> 6;
     const int g = lane >> 3, j = lane & 7;
     const uint64_t slot = (uint64_t)blockIdx.x * kWaves + wave;
-    u64 *mypool = pool + slot * pool_chunks * kChunk;
-    // the entries' node info, in a second pool of the same shape
-    u64 *myinfo = pool + ((uint64_t)gridDim.x * kWaves + slot) * pool_chunks * kChunk;
+    // this wave's chunks: each entry is one 16-byte record (the entry, then its node info)
+    ulonglong2 *mypool = reinterpret_cast<ulonglong2 *>(pool) + slot * pool_chunks * kChunk;
     uint32_t *myprev = chunk_prev + slot * pool_chunks * 2;
     uint32_t *myfree = myprev + pool_chunks;
     uint32_t *bstate = bstate_all + (kBest ? wave * kBuckets : 0);
@@ -256,8 +255,7 @@ __global__ __launch_bounds__(kBlock, kBest ? 3 : 4) void tree_knn_kernel(TreeVie
                         const uint32_t c = take_chunk();
                         took = 1;
                         myprev[c] = kNone;
-                        mypool[(uint64_t)c * kChunk] = e;
-                        myinfo[(uint64_t)c * kChunk] = info;
+                        mypool[(uint64_t)c * kChunk] = make_ulonglong2(e, info);
                         bstate[b] = (c << 5) | 1u;
                     } else {
                         const uint32_t st = bstate[b];
@@ -266,12 +264,10 @@ __global__ __launch_bounds__(kBlock, kBest ? 3 : 4) void tree_knn_kernel(TreeVie
                             const uint32_t c2 = take_chunk();
                             took = 1;
                             myprev[c2] = c;
-                            mypool[(uint64_t)c2 * kChunk] = e;
-                            myinfo[(uint64_t)c2 * kChunk] = info;
+                            mypool[(uint64_t)c2 * kChunk] = make_ulonglong2(e, info);
                             bstate[b] = (c2 << 5) | 1u;
                         } else {
-                            mypool[(uint64_t)c * kChunk + f] = e;
-                            myinfo[(uint64_t)c * kChunk + f] = info;
+                            mypool[(uint64_t)c * kChunk + f] = make_ulonglong2(e, info);
                             bstate[b] = (c << 5) | (f + 1);
                         }
                     }
@@ -327,8 +323,9 @@ __global__ __launch_bounds__(kBlock, kBest ? 3 : 4) void tree_knn_kernel(TreeVie
                     const uint32_t c = st >> 5, f = st & 31u;  // f >= 1: the bucket is not empty
                     const uint32_t pc = readfirst(myprev[c]);
                     if ((uint32_t)lane < f) {
-                        stack[lane] = mypool[(uint64_t)c * kChunk + lane];
-                        sinfo[lane] = myinfo[(uint64_t)c * kChunk + lane];
+                        const ulonglong2 ent = mypool[(uint64_t)c * kChunk + lane];
+                        stack[lane] = ent.x;
+                        sinfo[lane] = ent.y;
                     }
                     if (lane == 0) {
                         if (pc == kNone) {
@@ -465,25 +462,10 @@ __global__ __launch_bounds__(kBlock, kBest ? 3 : 4) void tree_knn_kernel(TreeVie
     }
 }
 
-// The n subtree roots of a split: position p (bits from the most
-// significant, 0 = first child) is the node reached from the root by
-// following p's log2(n) bits; a leaf met on the way is the subtree of the
-// first position below it, and the others below it are empty (-1).  One
-// thread per position.
-__global__ void roots_kernel(const int32_t *__restrict__ child, uint32_t n, int32_t *__restrict__ roots) {
-    const uint32_t p = threadIdx.x;
-    if (p >= n) return;
-    const uint32_t d = (uint32_t)__builtin_ctz(n);
-    int32_t c = 0;
-    for (uint32_t l = 0; l < d; l++) {
-        const int32_t a = child[2 * (uint64_t)c], b = child[2 * (uint64_t)c + 1];
-        if (a < 0) {
-            if ((p & ((1u << (d - l)) - 1u)) != 0) c = -1;
-            break;
-        }
-        c = (p >> (d - 1 - l)) & 1u ? b : a;
-    }
-    roots[p] = c;
+// The n subtree roots of a split, from the tree's table (positions n - 1 ..
+// 2n - 2), into the tasks' area.
+__global__ void roots_kernel(const int32_t *__restrict__ table, uint32_t n, int32_t *__restrict__ roots) {
+    if (threadIdx.x < n) roots[threadIdx.x] = table[n - 1 + threadIdx.x];
 }
 
 __global__ void fill_words_kernel(uint32_t *p, uint64_t n, uint32_t v) {
@@ -604,7 +586,7 @@ TreeLaunch tree_launch_shape(qd_tree_t t, uint32_t nq_max, uint32_t k, int order
                              uint32_t split) {
     TreeLaunch L;
     const int cus = device_cus();
-    if (waves_per_cu == 0) waves_per_cu = order == QD_ORDER_BEST_FIRST ? 12 : 16;
+    if (waves_per_cu == 0) waves_per_cu = order == QD_ORDER_BEST_FIRST ? 12 : 16;  // as many as registers hold
     if (split == 0) split = kDefaultSplit;
     L.split = split;
     uint64_t blocks = ((uint64_t)cus * waves_per_cu + kWaves - 1) / kWaves;
@@ -612,14 +594,15 @@ TreeLaunch tree_launch_shape(qd_tree_t t, uint32_t nq_max, uint32_t k, int order
     if (blocks > need) blocks = need;
     L.blocks = blocks;
     L.slots = blocks * kWaves;
-    // Each node is queued at most once.  Live chunks: a bucket holds at most
-    // one partly filled chunk (or one kept empty chunk) besides full ones, and
-    // emptied chunks go to a free list, so n_nodes/kChunk + 2 per bucket
-    // chunks never run out.
-    L.pool_chunks = order == QD_ORDER_BEST_FIRST ? t->n_nodes / kChunk + 2 * kBuckets + 2 : 1;
+    // A search queues each node of its subtree at most once.  Live chunks: a
+    // bucket holds at most one partly filled chunk (or one kept empty chunk)
+    // besides full ones, and emptied chunks go to a free list, so (the
+    // subtree's nodes)/kChunk + 2 per bucket chunks never run out.
+    const uint64_t sub = t->split_nodes[__builtin_ctz(split)];
+    L.pool_chunks = order == QD_ORDER_BEST_FIRST ? sub / kChunk + 2 * kBuckets + 2 : 1;
     L.head = 256;  // [counter | pad | stats x4 | pad]
     L.prev_bytes = (size_t)(L.slots * L.pool_chunks * 8 + 255) / 256 * 256;  // prev + free list
-    L.pool_bytes = (size_t)L.slots * L.pool_chunks * kChunk * 16;  // entries, then their node info
+    L.pool_bytes = (size_t)L.slots * L.pool_chunks * kChunk * 16;  // 16-byte records: entry, node info
     L.split_bytes = split_layout(nq_max ? nq_max : 1, split, k).bytes;  // the tasks' lists, also unsplit
     return L;
 }
@@ -642,7 +625,8 @@ int tree_launch(qd_tree_t t, const TreeLaunch &L, char *ws, const uint64_t *d_q,
     if (L.split > 1 && d_trace) return fail(QD_ERR_INVALID, "a traced search runs unsplit");
     char *sw = ws + L.head + L.prev_bytes + L.pool_bytes;  // the tasks' area
     if (L.split > 1) {
-        hipLaunchKernelGGL(roots_kernel, dim3(1), dim3(64), 0, s, t->d_child, L.split, reinterpret_cast<int32_t *>(sw));
+        hipLaunchKernelGGL(roots_kernel, dim3(1), dim3(64), 0, s, t->d_split_roots, L.split,
+                           reinterpret_cast<int32_t *>(sw));
         const uint32_t fg = (nq + 255) / 256;
         hipLaunchKernelGGL(fill_words_kernel, dim3(fg < 1 ? 1 : fg < 1024 ? fg : 1024), dim3(256), 0, s,
                            reinterpret_cast<uint32_t *>(sw + split_layout(nq, L.split, k).kshared), (uint64_t)nq,
