@@ -191,7 +191,8 @@ __global__ __launch_bounds__(mt::kThreads) void scan_mfma_kernel(const uint4 *__
                 // test this lane's 4 rows of the query at once (most miss by far)
                 const float mx = fmaxf(fmaxf(acc[a][0][rr], acc[a][1][rr]), fmaxf(acc[a][2][rr], acc[a][3][rr]));
                 const uint32_t qi = q0 + ai;
-                const bool act = mx >= s_cmin[h][ai] && qi < nq;
+                // (a slot past the last query has least overlap 1e30)
+                const bool act = mx >= s_cmin[h][ai];
                 if (ballot(act) == 0) continue;
                 const uint32_t pq = s_p[h][ai];
                 const uint32_t wa = pq > 1 ? pq : 1, wb = (QD_BITS - pq) > 1 ? QD_BITS - pq : 1;

@@ -998,7 +998,6 @@ __global__ __launch_bounds__(mt::kThreads) void eval_kernel(const uint4 *__restr
             issue_c();
         }, idle);
         const uint64_t r0 = (uint64_t)cur.x * kBlk;
-        const uint32_t m = cur.z;
         const uint32_t *t_qi = s_qi[par], *t_pq = s_pq[par], *t_th = s_th[par], *t_tp = s_tp[par];
         const float *t_cmin = s_cmin[par];
         uint32_t nq = 0;  // entries in this wave's queue (the same in every lane)
@@ -1020,7 +1019,8 @@ __global__ __launch_bounds__(mt::kThreads) void eval_kernel(const uint4 *__restr
                 // most (query, row) pairs miss the k-th key by far: test this
                 // lane's 4 rows at once against the least useful overlap
                 const float mx = fmaxf(fmaxf(acc[a][0][rr], acc[a][1][rr]), fmaxf(acc[a][2][rr], acc[a][3][rr]));
-                const bool act = mx >= t_cmin[i] && i < m;
+                // (a slot past the tile's queries has least overlap 1e30)
+                const bool act = mx >= t_cmin[i];
                 if (ballot(act) == 0) continue;
                 const uint32_t qk = t_qi[i];
                 const uint32_t pk = t_pq[i];
