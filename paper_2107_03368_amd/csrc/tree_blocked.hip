@@ -551,7 +551,9 @@ __global__ __launch_bounds__(1024) void active_kernel(const u64 *__restrict__ re
 
 // Per-block query lists for one round: wave w of block x handles the
 // kGroup blocks starting at (4x + w) * kGroup and walks the running queries
-// (act, in query order).
+// (act, in query order), 256 at a time: each thread of the workgroup fetches
+// one query's record, fill range and done word into LDS for all four waves
+// (the next 256 are fetched while these are walked).
 // A query is listed for a block whose key lies in its range of this round,
 // unless an earlier round already evaluated the pair (done bit).  The same
 // walk collects, per block, up to 255 queries whose next round covers the
@@ -559,6 +561,7 @@ __global__ __launch_bounds__(1024) void active_kernel(const u64 *__restrict__ re
 // block's last tile and are marked done, so the next round skips them.
 // Filling uses the tile the round runs anyway; such a pair is evaluated once,
 // against a k-th key at least as large as the next round's, so no row is lost.
+static_assert(4 * kGroup == 32, "a workgroup's blocks share one word of done bits");
 __global__ __launch_bounds__(256) void list_kernel(const uint16_t *__restrict__ lbb, uint64_t nblk, uint64_t n,
                                                    uint32_t nqb, uint32_t nqp, const uint32_t *__restrict__ act,
                                                    const uint32_t *__restrict__ nact, const u64 *__restrict__ rec,
@@ -566,89 +569,96 @@ __global__ __launch_bounds__(256) void list_kernel(const uint16_t *__restrict__ 
                                                    uint16_t *__restrict__ list,
                                                    uint32_t *__restrict__ cnt, uint32_t *__restrict__ qst) {
     __shared__ uint16_t s_fill[4][kGroup][mt::MA - 1];  // per wave and block: fill candidates
-    const int lane = lane_id();
-    uint16_t(*fillq)[mt::MA - 1] = s_fill[threadIdx.x >> 6];
-    const uint64_t b0 = ((uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * kGroup;
-    if (b0 >= nblk) return;
-    const uint32_t nb = readfirst((uint32_t)(nblk - b0 < (uint64_t)kGroup ? nblk - b0 : kGroup));
-    const uint64_t dword = b0 / 32;  // the group's done bits share one word
+    __shared__ u64 s_r[2][4][256];                       // per query: round range lo, hi; fill range lo, hi
+    __shared__ uint32_t s_q[2][256], s_d[2][256];        // per query: its id, its done word
+    const int lane = lane_id(), t = (int)threadIdx.x;
+    uint16_t(*fillq)[mt::MA - 1] = s_fill[t >> 6];
+    const uint64_t b0 = ((uint64_t)blockIdx.x * 4 + (t >> 6)) * kGroup;
+    const bool have = b0 < nblk;  // the same in a whole wave; every wave takes part in the staging
+    const uint32_t nb = have ? readfirst((uint32_t)(nblk - b0 < (uint64_t)kGroup ? nblk - b0 : kGroup)) : 0;
+    const uint64_t dword = blockIdx.x;  // the workgroup's 32 blocks share one word of done bits
     const uint32_t dshift = (uint32_t)(b0 % 32);
     uint32_t c[kGroup], f[kGroup];
 #pragma unroll
     for (int jj = 0; jj < kGroup; jj++) c[jj] = f[jj] = 0;
-    // kChunks chunks of 64 queries at a time: all their loads are issued first
-    // (unconditionally, in bounds), so the walk waits for memory once per
-    // kChunks chunks instead of twice per chunk
-    constexpr int kChunks = 2;
     const uint32_t na = readfirst(*nact);
-    // when every query runs the list is the identity and is not read; else the
-    // next batch's query ids are loaded while this batch is walked
+    // when every query runs the list is the identity and is not read
     const bool all = na == nqb;
-    auto qid = [&](uint32_t ia) { return all ? (ia < na ? ia : na - 1) : act[ia < na ? ia : na - 1]; };
-    uint32_t nq_next[kChunks];
+    uint32_t fq = 0, fd = 0;  // this thread's fetch for the next 256: query, done word, ranges
+    u64 fr[4] = {0, 0, 0, 0};
+    auto fetch = [&](uint32_t i0) {  // unconditional and in bounds (na >= 1)
+        const uint32_t ia = i0 + (uint32_t)t < na ? i0 + (uint32_t)t : na - 1;
+        fq = all ? ia : act[ia];
+        fr[0] = rec[2 * (uint64_t)fq];
+        fr[1] = rec[2 * (uint64_t)fq + 1];
+        fr[2] = frange[2 * (uint64_t)fq];
+        fr[3] = frange[2 * (uint64_t)fq + 1];
+        fd = done[dword * nqp + fq];
+    };
+    if (na) fetch(0);
+    int sb = 0;
+    for (uint32_t i00 = 0; i00 < na; i00 += 256) {
+        s_q[sb][t] = fq;
+        s_d[sb][t] = fd;
 #pragma unroll
-    for (int u = 0; u < kChunks; u++) nq_next[u] = na ? qid(64 * u + (uint32_t)lane) : 0;
-    for (uint32_t i00 = 0; i00 < na; i00 += 64 * kChunks) {
-        u64 rlo[kChunks], rhi[kChunks], rflo[kChunks], rfhi[kChunks];
-        uint32_t rdone[kChunks], rq[kChunks];
-        uint16_t rlv[kChunks][kGroup];
+        for (int x = 0; x < 4; x++) s_r[sb][x][t] = fr[x];
+        // also: every wave finished reading this buffer two batches ago
+        __syncthreads();
+        if (i00 + 256 < na) fetch(i00 + 256);
+        // two groups of 64 queries at a time: their bounds are loaded before any is used
+        for (int h = 0; have && h < 2; h++) {
+            uint16_t rlv[2][kGroup];
 #pragma unroll
-        for (int u = 0; u < kChunks; u++) {
-            rq[u] = nq_next[u];
-            nq_next[u] = qid(i00 + 64 * (kChunks + u) + (uint32_t)lane);
-        }
+            for (int u = 0; u < 2; u++) {
+                const uint32_t qc = s_q[sb][128 * h + 64 * u + lane];
 #pragma unroll
-        for (int u = 0; u < kChunks; u++) {
-            const uint32_t qc = rq[u];
-            rlo[u] = rec[2 * qc];
-            rhi[u] = rec[2 * qc + 1];
-            rflo[u] = frange[2 * qc];
-            rfhi[u] = frange[2 * qc + 1];
-            rdone[u] = done[(uint64_t)dword * nqp + qc];
+                for (int jj = 0; jj < kGroup; jj++)
+                    rlv[u][jj] = lbb[(b0 + ((uint32_t)jj < nb ? jj : 0)) * nqp + qc];
+            }
 #pragma unroll
-            for (int jj = 0; jj < kGroup; jj++)
-                rlv[u][jj] = lbb[(b0 + ((uint32_t)jj < nb ? jj : 0)) * nqp + qc];
-        }
+            for (int u = 0; u < 2; u++) {
+                const int e = 128 * h + 64 * u + lane;
+                const uint32_t qi = s_q[sb][e];
+                const bool in = i00 + (uint32_t)e < na;
+                const u64 lo = in ? s_r[sb][0][e] : 0, hi = in ? s_r[sb][1][e] : 0;
+                const bool run = hi > lo;  // only a query running this round has its candidates merged
+                const u64 flo = run ? s_r[sb][2][e] : 0, fhi = run ? s_r[sb][3][e] : 0;
+                if (ballot(run) == 0) continue;
+                const uint32_t dbits = run ? s_d[sb][e] >> dshift : 0;
+                uint32_t mb = 0, mr = 0;
 #pragma unroll
-        for (int u = 0; u < kChunks; u++) {
-            const uint32_t qi = rq[u];
-            const bool in = i00 + 64 * u + (uint32_t)lane < na;
-            const u64 lo = in ? rlo[u] : 0, hi = in ? rhi[u] : 0;
-            const bool run = hi > lo;  // only a query running this round has its candidates merged
-            const u64 flo = run ? rflo[u] : 0, fhi = run ? rfhi[u] : 0;
-            if (ballot(run) == 0) continue;
-            const uint32_t dbits = run ? rdone[u] >> dshift : 0;
-            uint32_t mb = 0, mr = 0;
-#pragma unroll
-            for (int jj = 0; jj < kGroup; jj++) {
-                if ((uint32_t)jj < nb) {
-                    const uint64_t b = b0 + jj;
-                    const u64 key = range_key(rlv[u][jj], (uint32_t)b);
-                    const bool d = (dbits >> jj) & 1u;
-                    const bool m = key > lo && key <= hi && !d;
-                    const u64 mask = ballot(m);
-                    if (m) list[b * nqp + c[jj] + lanes_below(mask)] = (uint16_t)qi;
-                    c[jj] += (uint32_t)__popcll(mask);
-                    if (m) {
-                        mb++;
-                        mr += b + 1 < nblk ? (uint32_t)kBlk : (uint32_t)(n - b * kBlk);
-                    }
-                    if (f[jj] < mt::MA - 1) {  // fill candidates, in query order
-                        const bool mf = key > flo && key <= fhi && !d;
-                        const u64 fmask = ballot(mf);
-                        const uint32_t at = f[jj] + lanes_below(fmask);
-                        if (mf && at < mt::MA - 1) fillq[jj][at] = (uint16_t)qi;
-                        const uint32_t t = f[jj] + (uint32_t)__popcll(fmask);
-                        f[jj] = t < mt::MA - 1 ? t : mt::MA - 1;
+                for (int jj = 0; jj < kGroup; jj++) {
+                    if ((uint32_t)jj < nb) {
+                        const uint64_t b = b0 + jj;
+                        const u64 key = range_key(rlv[u][jj], (uint32_t)b);
+                        const bool d = (dbits >> jj) & 1u;
+                        const bool m = key > lo && key <= hi && !d;
+                        const u64 mask = ballot(m);
+                        if (m) list[b * nqp + c[jj] + lanes_below(mask)] = (uint16_t)qi;
+                        c[jj] += (uint32_t)__popcll(mask);
+                        if (m) {
+                            mb++;
+                            mr += b + 1 < nblk ? (uint32_t)kBlk : (uint32_t)(n - b * kBlk);
+                        }
+                        if (f[jj] < mt::MA - 1) {  // fill candidates, in query order
+                            const bool mf = key > flo && key <= fhi && !d;
+                            const u64 fmask = ballot(mf);
+                            const uint32_t at = f[jj] + lanes_below(fmask);
+                            if (mf && at < mt::MA - 1) fillq[jj][at] = (uint16_t)qi;
+                            const uint32_t t2 = f[jj] + (uint32_t)__popcll(fmask);
+                            f[jj] = t2 < mt::MA - 1 ? t2 : mt::MA - 1;
+                        }
                     }
                 }
-            }
-            if (qst && mb) {
-                atomicAdd(&qst[(uint64_t)qi * 4 + 0], mb);
-                atomicAdd(&qst[(uint64_t)qi * 4 + 3], mr);
+                if (qst && mb) {
+                    atomicAdd(&qst[(uint64_t)qi * 4 + 0], mb);
+                    atomicAdd(&qst[(uint64_t)qi * 4 + 3], mr);
+                }
             }
         }
+        sb ^= 1;
     }
+    if (!have) return;
     // the first candidates fill the last tile's free slots
     for (uint32_t jj = 0; jj < nb; jj++) {
         const uint64_t b = b0 + jj;
@@ -657,7 +667,7 @@ __global__ __launch_bounds__(256) void list_kernel(const uint16_t *__restrict__ 
         for (uint32_t i = (uint32_t)lane; i < take; i += 64) {
             const uint32_t qi = fillq[jj][i];  // written by this wave above (LDS keeps its order)
             list[b * nqp + c[jj] + i] = (uint16_t)qi;
-            atomicOr(&done[(uint64_t)dword * nqp + qi], 1u << (dshift + jj));
+            atomicOr(&done[dword * nqp + qi], 1u << (dshift + jj));
             if (qst) {
                 atomicAdd(&qst[(uint64_t)qi * 4 + 0], 1u);
                 atomicAdd(&qst[(uint64_t)qi * 4 + 3], b + 1 < nblk ? (uint32_t)kBlk : (uint32_t)(n - b * kBlk));
