@@ -258,16 +258,18 @@ def main():
     # the per-query orders with one wave per query (the traversal as listed,
     # no subtree searches): one timed batch each, for comparison
     unsplit = {}
-    for name, order in (("tree", qd.ORDER_BEST_FIRST), ("tree_dfs", qd.ORDER_DEPTH_FIRST)):
+    for name, order in (("tree", qd.ORDER_BEST_FIRST), ("tree_dfs", qd.ORDER_DEPTH_FIRST),
+                        ("tree_learned", qd.ORDER_DEPTH_FIRST)):
         if name not in per_path:
             continue
-        qd.knn_tree(tree, qt, k, order=order, split=1)
+        kw = dict(model=model, n_scored=N_SCORED) if name == "tree_learned" else {}
+        qd.knn_tree(tree, qt, k, order=order, split=1, **kw)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        qd.knn_tree(tree, qt, k, order=order, split=1)
+        qd.knn_tree(tree, qt, k, order=order, split=1, **kw)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
-        st = qd.knn_tree(tree, qt, k, order=order, split=1, totals=True)[-1]
+        st = qd.knn_tree(tree, qt, k, order=order, split=1, totals=True, **kw)[-1]
         unsplit[name] = {"ms": dt * 1e3, "queries_per_s": nq / dt, "nodes_visited_per_query": st["nodes_visited"] / nq}
         log(f"{name} with one wave per query: {dt * 1e3:.1f} ms/batch, {st['nodes_visited'] / nq:.0f} nodes/query")
 
