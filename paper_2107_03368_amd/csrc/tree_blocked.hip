@@ -74,9 +74,9 @@ constexpr uint32_t kMaxBatch = 16384;      // queries per batch (list entries ar
 // A block list (or the rest of one past its full 256-query tiles) shorter
 // than this is evaluated on the vector ALUs, one wave per (query, block)
 // pair, instead of in a matrix-core tile that costs the same for 1 or 256
-// listed queries (measured at 10M rows: 16, 24 and 32 within 1%, 48 2% and
-// 96 7% slower).
-constexpr uint32_t kShortList = 24;
+// listed queries (measured at 10M rows x 8,192 queries: 12 and 16 fastest,
+// 24 0.4%, 32 0.9% and 48 2% slower).
+constexpr uint32_t kShortList = 16;
 
 // Position of block b of bound level L in the per-query block order; a round
 // covers the keys in (lo, hi].  Key 0 is below every block.

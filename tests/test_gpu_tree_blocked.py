@@ -128,7 +128,7 @@ def test_blocked_edge_cases(qd):
 
 @pytest.mark.parametrize("plain_bound", [False, True])
 def test_blocked_degenerate_queries_on_the_matrix_cores(qd, plain_bound):
-    # block lists long enough (>= 24 queries) for the matrix-core tiles, made
+    # block lists long enough (>= 24 queries, above the short-list cutoff) for the matrix-core tiles, made
     # of degenerate queries only: all zero (|q| = 0: every block's bound is 0,
     # the key is the row's popcount), all one (|q| = 4096), one set bit, and
     # all but one bit; the rows include all-zero, all-one and dense rows
