@@ -65,7 +65,7 @@ __global__ __launch_bounds__(mt::kThreads) void scan_mfma_kernel(const uint4 *__
     // sets: the current tile's, and the next tile's, written during the current tile.
     __shared__ uint32_t s_p[2][MQ + MR];
     __shared__ u64 s_th[2][MQ + MR];
-    __shared__ float s_cmin[2][MQ + MR];
+    __shared__ __align__(16) float s_cmin[2][MQ + MR];
     // per wave: the tile's passing (query, key, row) entries, appended in order
     // and written out together, so the candidate slots' atomics overlap
     // instead of waiting one after another
@@ -181,10 +181,24 @@ __global__ __launch_bounds__(mt::kThreads) void scan_mfma_kernel(const uint4 *__
             }
             nqe = 0;
         };
+        // this lane's four rows: their popcounts and whether they exist, the
+        // same for every query group of the tile
+        uint32_t tpv[4];
+        bool rv[4];
+#pragma unroll
+        for (int b = 0; b < 4; b++) {
+            tpv[b] = s_p[h][MQ + mt::acc_brow(b)];
+            rv[b] = t0 + (uint64_t)mt::acc_brow(b) < n;
+        }
+        // a group's four query slots are consecutive: their least overlaps
+        // are one 16-byte read, issued a group ahead of the test
+        float4 cm_next = *reinterpret_cast<const float4 *>(&s_cmin[h][mt::acc_arow(0, 0)]);
 #pragma unroll
         for (int a = 0; a < 8; a++) {
             // one group of queries at a time, so their metadata loads stay next to their use
             __builtin_amdgcn_sched_barrier(0);
+            const float4 cm = cm_next;
+            if (a < 7) cm_next = *reinterpret_cast<const float4 *>(&s_cmin[h][mt::acc_arow(a + 1, 0)]);
 #pragma unroll
             for (int rr = 0; rr < 4; rr++) {
                 const int ai = mt::acc_arow(a, rr);
@@ -192,19 +206,19 @@ __global__ __launch_bounds__(mt::kThreads) void scan_mfma_kernel(const uint4 *__
                 const float mx = fmaxf(fmaxf(acc[a][0][rr], acc[a][1][rr]), fmaxf(acc[a][2][rr], acc[a][3][rr]));
                 const uint32_t qi = q0 + ai;
                 // (a slot past the last query has least overlap 1e30)
-                const bool act = mx >= s_cmin[h][ai];
+                const bool act = mx >= (rr == 0 ? cm.x : rr == 1 ? cm.y : rr == 2 ? cm.z : cm.w);
                 if (ballot(act) == 0) continue;
                 const uint32_t pq = s_p[h][ai];
                 const uint32_t wa = pq > 1 ? pq : 1, wb = (QD_BITS - pq) > 1 ? QD_BITS - pq : 1;
                 const u64 th = s_th[h][ai];
 #pragma unroll
                 for (int b = 0; b < 4; b++) {
-                    const int bi = mt::acc_brow(b);
-                    const uint64_t t = t0 + bi;
+                    const uint64_t t = t0 + mt::acc_brow(b);
                     const uint32_t C = mt::count(acc[a][b][rr]);
-                    const uint32_t K = (pq - C) * wb + (s_p[h][MQ + bi] - C) * wa;
+                    // every term is below 2^13: exact in 24-bit multiplies
+                    const uint32_t K = __umul24(pq - C, wb) + __umul24(tpv[b] - C, wa);
                     const u64 key = ((u64)K << 32) | (uint32_t)t;
-                    const bool pass = act && t < n && key <= th;
+                    const bool pass = act && rv[b] && key <= th;
                     const u64 pm = ballot(pass);
                     if (pass) {
                         const uint32_t e = nqe + lanes_below(pm);

@@ -883,7 +883,7 @@ __global__ __launch_bounds__(mt::kThreads) void eval_kernel(const uint4 *__restr
     __shared__ mt::Smem sm;
     // two copies (tiles alternate): query slot's query, |q|, k-th key; row's |t|
     __shared__ uint32_t s_qi[2][mt::MA], s_pq[2][mt::MA], s_th[2][mt::MA], s_tp[2][mt::MB];
-    __shared__ float s_cmin[2][mt::MA];  // per query slot: the least overlap that can reach its k-th key
+    __shared__ __align__(16) float s_cmin[2][mt::MA];  // per query slot: the least overlap that can reach its k-th key
     // per wave: the tile's passing (query, key, row) entries, appended in order
     // and written out together, so the candidate slots' atomics overlap
     // instead of waiting one after another
@@ -1010,6 +1010,18 @@ __global__ __launch_bounds__(mt::kThreads) void eval_kernel(const uint4 *__restr
         const uint64_t r0 = (uint64_t)cur.x * kBlk;
         const uint32_t *t_qi = s_qi[par], *t_pq = s_pq[par], *t_th = s_th[par], *t_tp = s_tp[par];
         const float *t_cmin = s_cmin[par];
+        // this lane's four rows: their popcounts and whether they exist, the
+        // same for every query group of the tile
+        uint32_t tpv[4];
+        bool rv[4];
+#pragma unroll
+        for (int bb = 0; bb < 4; bb++) {
+            tpv[bb] = t_tp[mt::acc_brow(bb)];
+            rv[bb] = r0 + (uint64_t)mt::acc_brow(bb) < n;
+        }
+        // a group's four query slots are consecutive: their least overlaps
+        // are one 16-byte read, issued a group ahead of the test
+        float4 cm_next = *reinterpret_cast<const float4 *>(t_cmin + mt::acc_arow(0, 0));
         uint32_t nq = 0;  // entries in this wave's queue (the same in every lane)
         auto flush = [&]() {
             for (uint32_t e = lane; e < nq; e += 64) {
@@ -1023,6 +1035,8 @@ __global__ __launch_bounds__(mt::kThreads) void eval_kernel(const uint4 *__restr
         for (int a = 0; a < 8; a++) {
             // one group of queries at a time, so their metadata loads stay next to their use
             __builtin_amdgcn_sched_barrier(0);
+            const float4 cm = cm_next;
+            if (a < 7) cm_next = *reinterpret_cast<const float4 *>(t_cmin + mt::acc_arow(a + 1, 0));
 #pragma unroll
             for (int rr = 0; rr < 4; rr++) {
                 const uint32_t i = (uint32_t)mt::acc_arow(a, rr);
@@ -1030,7 +1044,7 @@ __global__ __launch_bounds__(mt::kThreads) void eval_kernel(const uint4 *__restr
                 // lane's 4 rows at once against the least useful overlap
                 const float mx = fmaxf(fmaxf(acc[a][0][rr], acc[a][1][rr]), fmaxf(acc[a][2][rr], acc[a][3][rr]));
                 // (a slot past the tile's queries has least overlap 1e30)
-                const bool act = mx >= t_cmin[i];
+                const bool act = mx >= (rr == 0 ? cm.x : rr == 1 ? cm.y : rr == 2 ? cm.z : cm.w);
                 if (ballot(act) == 0) continue;
                 const uint32_t qk = t_qi[i];
                 const uint32_t pk = t_pq[i];
@@ -1038,11 +1052,11 @@ __global__ __launch_bounds__(mt::kThreads) void eval_kernel(const uint4 *__restr
                 const uint32_t tk = t_th[i];
 #pragma unroll
                 for (int bb = 0; bb < 4; bb++) {
-                    const int bi = mt::acc_brow(bb);
-                    const uint64_t rw = r0 + bi;
+                    const uint64_t rw = r0 + mt::acc_brow(bb);
                     const uint32_t C = mt::count(acc[a][bb][rr]);
-                    const uint32_t K = (pk - C) * wb + (t_tp[bi] - C) * wa;
-                    const bool pass = act && rw < n && K <= tk;
+                    // every term is below 2^13: exact in 24-bit multiplies
+                    const uint32_t K = __umul24(pk - C, wb) + __umul24(tpv[bb] - C, wa);
+                    const bool pass = act && rv[bb] && K <= tk;
                     const u64 pm = ballot(pass);
                     if (pass) {
                         const uint32_t e = nq + lanes_below(pm);
