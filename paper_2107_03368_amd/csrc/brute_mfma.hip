@@ -211,14 +211,21 @@ __global__ __launch_bounds__(mt::kThreads) void scan_mfma_kernel(const uint4 *__
                 const uint32_t pq = s_p[h][ai];
                 const uint32_t wa = pq > 1 ? pq : 1, wb = (QD_BITS - pq) > 1 ? QD_BITS - pq : 1;
                 const u64 th = s_th[h][ai];
+                // K = |q|*wB + |t|*wA - C*(wA + wB): the first two terms per
+                // row once per group, then one 24-bit multiply-add per pair
+                // (C <= 4096 and wA + wB <= 4097; every term below 2^26)
+                const uint32_t P = __umul24(pq, wb);
+                const int nsw = -(int)(wa + wb);
+                uint32_t PT[4];
+#pragma unroll
+                for (int b = 0; b < 4; b++) PT[b] = P + __umul24(tpv[b], wa);
 #pragma unroll
                 for (int b = 0; b < 4; b++) {
                     const uint64_t t = t0 + mt::acc_brow(b);
                     const uint32_t C = mt::count(acc[a][b][rr]);
-                    // every term is below 2^13: exact in 24-bit multiplies
-                    const uint32_t K = __umul24(pq - C, wb) + __umul24(tpv[b] - C, wa);
+                    const uint32_t K = (uint32_t)((int)PT[b] + __mul24((int)C, nsw));
                     const u64 key = ((u64)K << 32) | (uint32_t)t;
-                    const bool pass = act && rv[b] && key <= th;
+                    const bool pass = act & rv[b] & (key <= th);  // no short-circuit: no branch per test
                     const u64 pm = ballot(pass);
                     if (pass) {
                         const uint32_t e = nqe + lanes_below(pm);

@@ -1050,13 +1050,20 @@ __global__ __launch_bounds__(mt::kThreads) void eval_kernel(const uint4 *__restr
                 const uint32_t pk = t_pq[i];
                 const uint32_t wa = weight_a(pk), wb = weight_b(pk);
                 const uint32_t tk = t_th[i];
+                // K = |q|*wB + |t|*wA - C*(wA + wB): the first two terms per
+                // row once per group, then one 24-bit multiply-add per pair
+                // (C <= 4096 and wA + wB <= 4097; every term below 2^26)
+                const uint32_t P = __umul24(pk, wb);
+                const int nsw = -(int)(wa + wb);
+                uint32_t PT[4];
+#pragma unroll
+                for (int bb = 0; bb < 4; bb++) PT[bb] = P + __umul24(tpv[bb], wa);
 #pragma unroll
                 for (int bb = 0; bb < 4; bb++) {
                     const uint64_t rw = r0 + mt::acc_brow(bb);
                     const uint32_t C = mt::count(acc[a][bb][rr]);
-                    // every term is below 2^13: exact in 24-bit multiplies
-                    const uint32_t K = __umul24(pk - C, wb) + __umul24(tpv[bb] - C, wa);
-                    const bool pass = act && rv[bb] && K <= tk;
+                    const uint32_t K = (uint32_t)((int)PT[bb] + __mul24((int)C, nsw));
+                    const bool pass = act & rv[bb] & (K <= tk);  // no short-circuit: no branch per test
                     const u64 pm = ballot(pass);
                     if (pass) {
                         const uint32_t e = nq + lanes_below(pm);
