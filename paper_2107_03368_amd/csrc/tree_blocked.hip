@@ -144,7 +144,7 @@ __global__ __launch_bounds__(mt::kThreads) void bound_kernel(const uint4 *__rest
                                                              uint16_t *__restrict__ lbq, uint16_t *__restrict__ lbb,
                                                              const uint32_t *__restrict__ nq_dev) {
     __shared__ mt::Smem sm;
-    __shared__ uint32_t s_pq[mt::MA], s_pmin[mt::MB], s_pmax[mt::MB];
+    __shared__ uint32_t s_pq[mt::MA], s_dm[mt::MA], s_pmin[mt::MB], s_pmax[mt::MB];
     if (nq_dev) nqb = min(nqb, *nq_dev);  // the batch's size on the device (captured graphs)
     const uint64_t n_tiles = (uint64_t)n_qtiles * ((nblk + mt::MB - 1) / mt::MB);
     for (uint64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
@@ -157,7 +157,14 @@ __global__ __launch_bounds__(mt::kThreads) void bound_kernel(const uint4 *__rest
         if (own < mt::MA) {
             ok = q0 + own < nqb;
             row = ok ? q + (uint64_t)(q0 + own) * 32 : q;
-            s_pq[own] = ok ? qpop[q0 + own] : 0;
+            const uint32_t pq = ok ? qpop[q0 + own] : 0;
+            s_pq[own] = pq;
+            // floor(x / wB) for every x < 2^25 as (x * m) >> (25 + l), with
+            // l = ceil(log2 wB) and m = ceil(2^(25 + l) / wB) < 2^26
+            // (division by an invariant integer; checked for every wB and
+            // at both sides of every multiple of it); m | l << 26
+            const uint32_t wb = weight_b(pq), l = 32u - (uint32_t)__builtin_clz(wb | 1u) - ((wb & (wb - 1)) == 0);
+            s_dm[own] = (uint32_t)((((uint64_t)1 << (25 + l)) + wb - 1) / wb) | (l << 26);
         } else {
             ok = b0 + (own - mt::MA) < nblk;
             row = ok ? img + (b0 + (own - mt::MA)) * 32 : img;
@@ -183,10 +190,12 @@ __global__ __launch_bounds__(mt::kThreads) void bound_kernel(const uint4 *__rest
                     const uint32_t qi = qa + r;
                     uint32_t v = 0xFFFFu;
                     if (qi < nqb) {
-                        const uint32_t pq = s_pq[qi - q0], ov = mt::count(acc[a][bb][r]);
+                        const uint32_t pq = s_pq[qi - q0], dm = s_dm[qi - q0], ov = mt::count(acc[a][bb][r]);
                         const uint32_t al = pq - (ov < pmax ? ov : pmax);
                         const uint32_t bl = pmin > ov ? pmin - ov : 0;
-                        v = bl ? al + bl * weight_a(pq) / weight_b(pq) : al;  // bl * wA < 2^24
+                        // floor(bl * wA / wB); bl * wA <= 2^24
+                        const uint32_t x = __umul24(bl, weight_a(pq));
+                        v = al + (uint32_t)(((uint64_t)x * (dm & 0x3FFFFFFu)) >> (25 + (dm >> 26)));
                         v = v < QD_BITS ? v : QD_BITS;
                         lbq[(uint64_t)qi * nblk + blk] = (uint16_t)v;
                     }
